@@ -1,0 +1,477 @@
+"""FP64 CPU oracle for the HDCR hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+(``paper_1611_06944_amd``) and never imports it.
+
+Arrays are numpy complex128 in the canonical site-major layout
+``psi[t, z, y, x, s, spin, colour]`` / ``U[t, z, y, x, mu, row, col]``.
+Coarse vectors are ``v[site_c, k]`` and the little Dirac operator is
+``A[site_c, d, j, k]`` with d in D9 = (0, +x, +y, +z, +t, -x, -y, -z, -t).
+
+The operator-level routines (H, the hop-class split of H, the block basis,
+restriction, prolongation, the little Dirac operator and the coarse apply)
+are plain C++ loops in ``hdcr_oracle.cpp``.  This module adds, in numpy:
+
+* conjugate residual for Hermitian indefinite H (Sec. 3),
+* Chebyshev interpolation of 1/y and the smoother S = p(H^2) H (Sec. 4,
+  order-10 smoother on [1, 64]),
+* the high-order Chebyshev low-pass filter used to generate the subspace
+  (Sec. 4 and the Fig. 1 caption),
+* the coarse Krylov solve Q = P A^-1 P^dag (Sec. 4, coarse-inverse display),
+* the symmetric two-level cycle (Sec. 4, the M_outer display) and the
+  flexible (variable-preconditioned) GCR outer iteration (Sec. 4).
+
+Each function names the passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hdcr_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ERANK = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the C++ half of the oracle (g++ -O3 -fopenmp)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["g++", "-O3", "-march=x86-64-v2", "-fopenmp", "-std=c++17", "-shared", "-fPIC",
+               _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+@dataclass
+class Params:
+    """Fine-lattice parameters: L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc per direction."""
+    L: tuple
+    Ls: int
+    M5: float = 1.8
+    mf: float = 0.01
+    bc: tuple = (1, 1, 1, -1)
+
+    @property
+    def dims(self):
+        return (ctypes.c_int * 5)(*[int(v) for v in self.L], int(self.Ls))
+
+    @property
+    def cbc(self):
+        return (ctypes.c_int * 4)(*[int(v) for v in self.bc])
+
+    @property
+    def fshape(self):
+        Lx, Ly, Lz, Lt = self.L
+        return (Lt, Lz, Ly, Lx, self.Ls, 4, 3)
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.complex128 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def gamma(mu: int) -> np.ndarray:
+    """The oracle's gamma matrix (mu = 0..3 for x, y, z, t; 4 for gamma5)."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    lib().or_gamma(ctypes.c_int(mu), _dp(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Fine operator (Sec. 3): D_dwf and H = Gamma5 D_dwf
+# ----------------------------------------------------------------------------
+
+def apply_dw(U, psi, p: Params) -> np.ndarray:
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    lib().or_apply_dw(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi), _dp(out))
+    return out
+
+
+def apply_h(U, psi, p: Params) -> np.ndarray:
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    lib().or_apply_h(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi), _dp(out))
+    return out
+
+
+def apply_h_classes(U, psi, p: Params, block) -> np.ndarray:
+    """H split by hop class relative to the blocks (9 fields, D9 order)."""
+    U, psi = _c(U), _c(psi)
+    out = np.empty((9,) + psi.shape, dtype=np.complex128)
+    blk = (ctypes.c_int * 4)(*[int(b) for b in block])
+    lib().or_apply_h_classes(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), blk,
+                             _dp(U), _dp(psi), _dp(out))
+    return out
+
+
+def apply_gamma5_field(psi) -> np.ndarray:
+    """Gamma5 = gamma5 R5 on a fine field: (Gamma5 psi)(x,s) = gamma5 psi(x, Ls-1-s)."""
+    g5 = gamma(4)
+    return np.einsum("ab,...sbc->...sac", g5, psi[..., ::-1, :, :])
+
+
+# ----------------------------------------------------------------------------
+# Coarse space (Sec. 4)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Coarse:
+    p: Params
+    block: tuple          # block extents (x, y, z, t); blocks span all of Ls
+    nvec: int
+
+    @property
+    def nb(self):
+        return 2 * self.nvec
+
+    @property
+    def cdims(self):
+        return tuple(int(l) // int(b) for l, b in zip(self.p.L, self.block))
+
+    @property
+    def nc(self):
+        c = self.cdims
+        return c[0] * c[1] * c[2] * c[3]
+
+    @property
+    def cblock(self):
+        return (ctypes.c_int * 4)(*[int(b) for b in self.block])
+
+
+def block_basis(vecs, cs: Coarse, mode: int = 0):
+    """Chirally split, block-orthonormal basis phi^b_k (Sec. 4).
+
+    Returns (basis[Nb, ...fine field...], status); status 4 = rank deficient.
+    """
+    vecs = _c(np.stack(vecs) if isinstance(vecs, (list, tuple)) else vecs)
+    assert vecs.shape[0] == cs.nvec
+    basis = np.empty((cs.nb,) + vecs.shape[1:], dtype=np.complex128)
+    st = lib().or_block_basis(cs.p.dims, cs.cblock, ctypes.c_int(cs.nvec), ctypes.c_int(mode), _dp(vecs), _dp(basis))
+    return basis, int(st)
+
+
+def restrict(basis, psi, cs: Coarse) -> np.ndarray:
+    basis, psi = _c(basis), _c(psi)
+    v = np.empty((cs.nc, cs.nb), dtype=np.complex128)
+    lib().or_restrict(cs.p.dims, cs.cblock, ctypes.c_int(cs.nb), _dp(basis), _dp(psi), _dp(v))
+    return v
+
+
+def prolong(basis, v, cs: Coarse) -> np.ndarray:
+    basis, v = _c(basis), _c(v)
+    psi = np.empty(basis.shape[1:], dtype=np.complex128)
+    lib().or_prolong(cs.p.dims, cs.cblock, ctypes.c_int(cs.nb), _dp(basis), _dp(v), _dp(psi))
+    return psi
+
+
+def coarse_build(U, basis, cs: Coarse) -> np.ndarray:
+    """Little Dirac operator A[a, d, j, k] = <phi^a_j | H^(d) | phi^(a+d)_k> (Sec. 4)."""
+    U, basis = _c(U), _c(basis)
+    A = np.empty((cs.nc, 9, cs.nb, cs.nb), dtype=np.complex128)
+    p = cs.p
+    lib().or_coarse_build(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), cs.cblock,
+                          ctypes.c_int(cs.nb), _dp(U), _dp(basis), _dp(A))
+    return A
+
+
+def coarse_columns(U, basis, cs: Coarse, kcols) -> np.ndarray:
+    """Columns k of A: out[c, a, d, j] = A[a, d, j, kcols[c]]."""
+    U, basis = _c(U), _c(basis)
+    kc = (ctypes.c_int * len(kcols))(*[int(k) for k in kcols])
+    out = np.empty((len(kcols), cs.nc, 9, cs.nb), dtype=np.complex128)
+    p = cs.p
+    lib().or_coarse_columns(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), cs.cblock,
+                            ctypes.c_int(cs.nb), _dp(U), _dp(basis), ctypes.c_int(len(kcols)), kc, _dp(out))
+    return out
+
+
+def coarse_apply(A, v, cdims) -> np.ndarray:
+    """(A v)(a) = sum_d A[a, d] v(a + d), coarse-periodic. v: [nc, nb] or [nrhs, nc, nb]."""
+    A, v = _c(A), _c(v)
+    nb = A.shape[-1]
+    nrhs = 1 if v.ndim == 2 else v.shape[0]
+    out = np.empty_like(v)
+    cd = (ctypes.c_int * 4)(*[int(c) for c in cdims])
+    lib().or_coarse_apply(cd, ctypes.c_int(nb), ctypes.c_int(nrhs), _dp(A), _dp(v), _dp(out))
+    return out
+
+
+def coarse_dense(A, cdims) -> np.ndarray:
+    """The coarse operator as a dense (nc*nb) x (nc*nb) matrix (small lattices only)."""
+    nc, _, nb, _ = A.shape
+    Cx, Cy, Cz, Ct = cdims
+    M = np.zeros((nc * nb, nc * nb), dtype=np.complex128)
+    for a in range(nc):
+        c = [a % Cx, (a // Cx) % Cy, (a // (Cx * Cy)) % Cz, a // (Cx * Cy * Cz)]
+        for d in range(9):
+            cc = list(c)
+            if d > 0:
+                mu = (d - 1) % 4
+                cc[mu] = (cc[mu] + (1 if d <= 4 else -1)) % cdims[mu]
+            b = ((cc[3] * Cz + cc[2]) * Cy + cc[1]) * Cx + cc[0]
+            M[a * nb:(a + 1) * nb, b * nb:(b + 1) * nb] += A[a, d]
+    return M
+
+
+# ----------------------------------------------------------------------------
+# Krylov solvers and polynomials
+# ----------------------------------------------------------------------------
+
+def vdot(a, b) -> complex:
+    """<a, b> = sum conj(a) b."""
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def norm(a) -> float:
+    return float(np.sqrt(np.vdot(a.ravel(), a.ravel()).real))
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    status: int               # 0 converged, 1 not converged, 2 breakdown
+    history: list = field(default_factory=list)   # |r| after each iteration (updated residual)
+    applies: int = 0
+    true_rel: float = float("nan")
+
+
+def cr(apply, b, tol=1e-8, maxiter=10000, x0=None, breakdown_tol=1e-13, check_true=True) -> SolveResult:
+    """Conjugate residual for a Hermitian (indefinite) operator (Sec. 3).
+
+    r = b - H x;  p = r;  Ar = H r;  Ap = Ar
+    repeat:  alpha = Re<r,Ar>/|Ap|^2;  x += alpha p;  r -= alpha Ap
+             Ar = H r;  beta = Re<r',Ar'>/Re<r,Ar>;  p = r + beta p;  Ap = Ar + beta Ap
+    Stops when the updated |r| <= tol |b|; the true residual is then recomputed and
+    the iteration restarted from it if it is not met.  Status 2 on breakdown
+    (|<r,Ar>| below rounding level), 1 if maxiter is reached.
+    """
+    bn = norm(b)
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    napp = 0
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - apply(x)
+        napp += 1
+    hist = []
+    if bn == 0.0:
+        return SolveResult(x, 0, 0, hist, napp, 0.0)
+    it = 0
+    status = 1
+    while it < maxiter:
+        Ar = apply(r)
+        napp += 1
+        p = r.copy()
+        Ap = Ar.copy()
+        rAr = vdot(r, Ar).real
+        restart = False
+        while it < maxiter:
+            if abs(rAr) < breakdown_tol * norm(r) * norm(Ar):
+                return SolveResult(x, it, 2, hist, napp, norm(b - apply(x)) / bn)
+            alpha = rAr / vdot(Ap, Ap).real
+            x += alpha * p
+            r -= alpha * Ap
+            it += 1
+            rn = norm(r)
+            hist.append(rn)
+            if rn <= tol * bn:
+                if not check_true:
+                    return SolveResult(x, it, 0, hist, napp, float("nan"))
+                r = b - apply(x)
+                napp += 1
+                if norm(r) <= tol * bn:
+                    return SolveResult(x, it, 0, hist, napp, norm(r) / bn)
+                restart = True
+                break
+            Ar = apply(r)
+            napp += 1
+            rAr_new = vdot(r, Ar).real
+            beta = rAr_new / rAr
+            rAr = rAr_new
+            p = r + beta * p
+            Ap = Ar + beta * Ap
+        if not restart:
+            break
+    r = b - apply(x)
+    return SolveResult(x, it, status, hist, napp + 1, norm(r) / bn)
+
+
+def cheby_coeffs(n: int, lo: float, hi: float, f=lambda y: 1.0 / y) -> np.ndarray:
+    """Chebyshev interpolation coefficients of f on [lo, hi] with n terms (Sec. 4 smoother).
+
+    c_j = (2/n) sum_{k<n} f(y_k) cos(pi j (k+1/2)/n),
+    y_k = (hi+lo)/2 + (hi-lo)/2 cos(pi (k+1/2)/n);
+    p(y) = sum_{j<n} c_j T_j(yhat) - c_0/2 with yhat = (2y - hi - lo)/(hi - lo).
+    "Order 10" is read as n = 10 terms (degree 9).
+    """
+    k = np.arange(n)
+    th = np.pi * (k + 0.5) / n
+    yk = 0.5 * (hi + lo) + 0.5 * (hi - lo) * np.cos(th)
+    fk = np.array([f(y) for y in yk])
+    return np.array([2.0 / n * np.sum(fk * np.cos(j * th)) for j in range(n)])
+
+
+def cheby_eval(c, lo, hi, y):
+    """p(y) = sum c_j T_j(yhat) - c_0/2 (scalar or array y)."""
+    yh = (2.0 * np.asarray(y, dtype=float) - hi - lo) / (hi - lo)
+    t0 = np.ones_like(yh)
+    t1 = yh
+    out = c[0] * t0 - 0.5 * c[0]
+    if len(c) > 1:
+        out = out + c[1] * t1
+    for j in range(2, len(c)):
+        t0, t1 = t1, 2 * yh * t1 - t0
+        out = out + c[j] * t1
+    return out
+
+
+def smoother(apply, r, order=10, lo=1.0, hi=64.0):
+    """S r = p(H^2) H r with p the Chebyshev interpolant of 1/y on [lo, hi] (Sec. 4).
+
+    p(H^2) is evaluated by the three-term recurrence T_{j+1} = 2 yhat T_j - T_{j-1}
+    with yhat = (2 H^2 - hi - lo)/(hi - lo); 1 + 2 (order - 1) H applications.
+    """
+    c = cheby_coeffs(order, lo, hi)
+
+    def yhat(v):
+        return (2.0 * apply(apply(v)) - (hi + lo) * v) / (hi - lo)
+
+    u = apply(r)
+    t0 = u
+    out = 0.5 * c[0] * t0
+    if order > 1:
+        t1 = yhat(u)
+        out = out + c[1] * t1
+        for j in range(2, order):
+            t2 = 2.0 * yhat(t1) - t0
+            out = out + c[j] * t2
+            t0, t1 = t1, t2
+    return out
+
+
+def cheby_filter(apply, eta, degree: int, lo: float, hi: float, normalise=True):
+    """Chebyshev low-pass filter T_d(yhat) eta, yhat = (2 H^2 - hi - lo)/(hi - lo) (Sec. 4).
+
+    [lo, hi] = [lambda_cut^2, lambda_max^2]: modes with H^2 inside the interval
+    are bounded by 1, modes below lambda_cut^2 grow like cosh(d acosh|yhat|).
+    The result is normalised to unit norm.
+    """
+    def yhat(v):
+        return (2.0 * apply(apply(v)) - (hi + lo) * v) / (hi - lo)
+
+    t0 = eta.copy()
+    if degree == 0:
+        out = t0
+    else:
+        t1 = yhat(t0)
+        for _ in range(2, degree + 1):
+            t0, t1 = t1, 2.0 * yhat(t1) - t0
+        out = t1
+    if normalise:
+        out = out / norm(out)
+    return out
+
+
+def power_max(apply, v0, iters=30):
+    """Rayleigh-quotient estimate of the largest eigenvalue of H^2 by power iteration."""
+    v = v0 / norm(v0)
+    lam = 0.0
+    for _ in range(iters):
+        w = apply(apply(v))
+        lam = vdot(v, w).real
+        v = w / norm(w)
+    return lam
+
+
+def coarse_cr(A, v, cdims, tol=1e-2, maxiter=500):
+    """Coarse solve A c = v by CR from c = 0 (Sec. 4: the subspace inverse by a Krylov method).
+
+    tol = 0 runs exactly maxiter iterations (fixed-work mode used for parity).
+    """
+    return cr(lambda u: coarse_apply(A, u, cdims), v, tol=tol, maxiter=maxiter, check_true=False)
+
+
+def vcycle(apply, A, basis, cs: Coarse, r, order=10, lo=1.0, hi=64.0, ctol=1e-2, cmaxiter=500,
+           coarse_solve=None):
+    """Two-level cycle B r (Sec. 4, the M_outer display), symmetric form:
+
+    e1 = S r;  e2 = e1 + Q (r - H e1);  e3 = e2 + S (r - H e2),  Q = P A^-1 P^dag.
+    Expanding gives S P_L + P_R S + Q - S P_L H S with P_L = 1 - HQ, P_R = 1 - QH.
+    The coarse inverse is CR on A (``coarse_cr``) unless ``coarse_solve(v, cdims)``
+    is given (the tests pass an exact dense solve there).
+    """
+    e1 = smoother(apply, r, order, lo, hi)
+    t = r - apply(e1)
+    vc = restrict(basis, t, cs)
+    if coarse_solve is None:
+        c = coarse_cr(A, vc, cs.cdims, tol=ctol, maxiter=cmaxiter).x
+    else:
+        c = coarse_solve(vc, cs.cdims)
+    e2 = e1 + prolong(basis, c, cs)
+    t = r - apply(e2)
+    return e2 + smoother(apply, t, order, lo, hi)
+
+
+def fgcr(apply, precond, b, tol=1e-8, maxiter=200, restart=8, x0=None) -> SolveResult:
+    """Flexible (variable-preconditioned) GCR (Sec. 4, outer iteration).
+
+    For i < restart:  z = B r;  w = H z;  orthogonalise w against the stored w_j by
+    modified Gram-Schmidt, applying the same combination to z;  normalise;
+    alpha = <w, r>;  x += alpha z;  r -= alpha w.  The true residual is recomputed
+    at every restart.
+    """
+    bn = norm(b)
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply(x) if x0 is not None else b.copy()
+    hist = []
+    it = 0
+    while it < maxiter:
+        Z, W = [], []
+        for _ in range(restart):
+            z = precond(r)
+            w = apply(z)
+            for zj, wj in zip(Z, W):
+                beta = vdot(wj, w)
+                w = w - beta * wj
+                z = z - beta * zj
+            nw = norm(w)
+            w = w / nw
+            z = z / nw
+            alpha = vdot(w, r)
+            x = x + alpha * z
+            r = r - alpha * w
+            Z.append(z)
+            W.append(w)
+            it += 1
+            hist.append(norm(r))
+            if hist[-1] <= tol * bn or it >= maxiter:
+                break
+        r = b - apply(x)
+        if norm(r) <= tol * bn:
+            return SolveResult(x, it, 0, hist, 0, norm(r) / bn)
+    return SolveResult(x, it, 1, hist, 0, norm(b - apply(x)) / bn)
