@@ -1,0 +1,173 @@
+/*
+ * hdcr.h -- C ABI of the MI355X (gfx950) hot path of the Hierarchically
+ * Deflated Conjugate Residual solver (Yamaguchi & Boyle, Lattice 2016).
+ *
+ * The library solves H x = b for the Hermitian indefinite 5d domain wall
+ * operator H = Gamma5 D_dwf = gamma5 R5 D_dwf (Sec. 3), either by plain
+ * conjugate residual (Sec. 3) or by flexible GCR preconditioned with a
+ * two-level cycle built on a chirally split, block-local coarse space whose
+ * little Dirac operator is a 9-point nearest-neighbour stencil of dense
+ * Nb x Nb blocks (Sec. 4).  To solve D_dwf psi = eta, pass b = Gamma5 eta.
+ *
+ * Conventions (fixed; the paper leaves them open):
+ *   D_dwf (Shamir form, Cayley b = 1, c = 0):
+ *     (D psi)(x,s) = (5 - M5) psi(x,s)
+ *        - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu,s)]
+ *        - P- psi(x,s+1) - P+ psi(x,s-1),
+ *     walls: -P- psi(x,Ls) -> +mf P- psi(x,0), -P+ psi(x,-1) -> +mf P+ psi(x,Ls-1);
+ *     a 4d hop that crosses the lattice boundary in direction mu picks up bc[mu].
+ *   (H psi)(x,s) = g5 (D psi)(x, Ls-1-s).
+ *   Gamma matrices: chiral basis, g_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = x, y, z),
+ *     g_t = [[0, 1], [1, 0]], g5 = diag(1, 1, -1, -1), P+- = (1 +- g5)/2.
+ *   Sites: site4 = ((t*Lz + z)*Ly + y)*Lx + x.
+ *
+ * Memory layouts of caller buffers (device memory unless stated):
+ *   fine field  psi[c][site4][s], c = spin*3 + colour (12), complex interleaved (re, im);
+ *               C128 = 2 x double, C64 = 2 x float per complex entry.
+ *   gauge field U[mu][row][col][site4], complex interleaved, same precision as the field.
+ *   coarse vector v[rhs][site_c][k], k < Nb = 2*nvec, site_c ordered like site4 over the
+ *               coarse lattice (extent L[mu]/block[mu]); C128 or C64.
+ *   basis, A:   opaque device buffers of hdcr_basis_bytes() / hdcr_coarse_bytes() bytes;
+ *               read them through hdcr_export_basis() / hdcr_export_coarse().
+ *
+ * Ownership: the caller owns every buffer.  The library never allocates or
+ * frees device memory; scratch space comes in through (work, work_bytes),
+ * sized by hdcr_workspace_bytes().  Every call except hdcr_solve,
+ * hdcr_make_subspace, hdcr_power_max and hdcr_vec_dot is stream-ordered and
+ * returns before the work is done; those four return after it has completed.
+ * In and out buffers of one call must not overlap.
+ *
+ * Errors: 0 = success.  Negative codes are caller errors found before any
+ * launch (HDCR_EINVAL), runtime failures (HDCR_EHIP) or a workspace that is
+ * too small (HDCR_ENOMEM).  Positive codes are numerical outcomes of a solve.
+ * hdcr_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef HDCR_H
+#define HDCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HDCR_OK 0
+#define HDCR_EINVAL (-1)
+#define HDCR_EHIP (-2)
+#define HDCR_ENOMEM (-3)
+#define HDCR_ENOTCONV 1    /* maxiter reached; x holds the last iterate */
+#define HDCR_EBREAKDOWN 2  /* |<r,Hr>| or |w| fell to rounding level */
+#define HDCR_ENAN 3        /* a NaN or Inf appeared in a residual */
+#define HDCR_ERANK 4       /* block basis numerically rank deficient */
+
+typedef enum {
+    HDCR_C128 = 0,  /* complex double */
+    HDCR_C64 = 1,   /* complex float */
+    HDCR_BF16C = 2  /* (bf16 re, bf16 im): little Dirac operator storage only */
+} hdcr_dtype;
+
+/* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1
+ * antiperiodic), domain wall height M5 and quark mass mf. */
+typedef struct hdcr_fine_desc {
+    int32_t L[4];
+    int32_t Ls;
+    int32_t bc[4];
+    int32_t reserved;
+    double M5;
+    double mf;
+} hdcr_fine_desc;
+
+/* Coarse space: blocks of block[mu] sites in 4d covering the whole fifth
+ * dimension (Sec. 4), nvec subspace vectors, Nb = 2*nvec after the chiral
+ * split.  Requires L[mu] % block[mu] == 0 and Ls even. */
+typedef struct hdcr_coarse_desc {
+    hdcr_fine_desc fine;
+    int32_t block[4];
+    int32_t nvec;
+    int32_t reserved;
+} hdcr_coarse_desc;
+
+typedef enum { HDCR_PRECOND_NONE = 0, HDCR_PRECOND_TWO_LEVEL = 1 } hdcr_precond;
+
+/* Solver parameters.  precond NONE: plain conjugate residual in FP64 (Sec. 3).
+ * TWO_LEVEL: FP64 flexible GCR(restart) whose preconditioner is the symmetric
+ * two-level cycle (Sec. 4, M_outer) in inner_dtype: Chebyshev smoother of
+ * cheb_order terms approximating 1/y on [cheb_lo, cheb_hi] applied as
+ * p(H^2) H, and a coarse CR solve on A (coarse_dtype storage) to relative
+ * tolerance coarse_tol or coarse_maxiter iterations. */
+typedef struct hdcr_solve_params {
+    double tol;             /* relative true residual |b - Hx|/|b| */
+    int32_t maxiter;        /* outer iterations */
+    int32_t restart;        /* FGCR window (TWO_LEVEL) */
+    int32_t precond;        /* hdcr_precond */
+    int32_t cheb_order;     /* number of Chebyshev terms, 10 in the paper */
+    double cheb_lo;         /* 1.0 in the paper */
+    double cheb_hi;         /* 64.0 in the paper */
+    double coarse_tol;
+    int32_t coarse_maxiter;
+    int32_t inner_dtype;    /* HDCR_C64 or HDCR_C128: smoother, restriction, prolongation */
+    int32_t coarse_dtype;   /* storage of A passed to hdcr_solve: C128, C64 or BF16C */
+    int32_t verbose;
+} hdcr_solve_params;
+
+/* Statistics of one solve (the columns of the paper's Table 1 and more). */
+typedef struct hdcr_solve_stats {
+    int32_t status;
+    int32_t outer_iters;
+    int64_t coarse_iters;       /* total coarse CR iterations */
+    int64_t fine_applies_f64;   /* H applications in FP64 */
+    int64_t fine_applies_inner; /* H applications in the inner precision */
+    int64_t coarse_applies;
+    double true_rel_residual;
+    double seconds_total;
+    double seconds_fine;        /* smoother + inner residuals (event-timed) */
+    double seconds_coarse;      /* restriction + coarse solve + prolongation */
+    double seconds_outer;       /* FP64 apply + orthogonalisation + updates */
+    int32_t history_len;        /* entries written to the caller's history array */
+    int32_t reserved;
+} hdcr_solve_stats;
+
+const char* hdcr_strerror(int code);
+const char* hdcr_last_error(void);
+
+/* out = H psi with H = Gamma5 D_dwf (Sec. 3).  dtype C128 or C64; U, psi and
+ * out in that precision.  One kernel launch on `stream`. */
+int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
+                    hipStream_t stream);
+
+/* <x, y> = sum conj(x_i) y_i over n complex entries (C128 or C64 data, FP64
+ * accumulation, fixed reduction order), written to out[0] (re), out[1] (im) on
+ * the host.  work: device scratch of at least HDCR_DOT_WORK_BYTES bytes.
+ * Synchronises `stream`. */
+#define HDCR_DOT_WORK_BYTES 32768
+int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work,
+                 size_t work_bytes, hipStream_t stream);
+
+/* Scratch bytes needed by the calls below: which = HDCR_WS_SOLVE (hdcr_solve
+ * with the given params), HDCR_WS_BUILD (hdcr_build_coarse), HDCR_WS_SUBSPACE
+ * (hdcr_make_subspace / hdcr_power_max), HDCR_WS_SMOOTH (hdcr_smooth),
+ * HDCR_WS_VCYCLE (hdcr_vcycle with the given params). */
+#define HDCR_WS_SOLVE 0
+#define HDCR_WS_BUILD 1
+#define HDCR_WS_SUBSPACE 2
+#define HDCR_WS_SMOOTH 3
+#define HDCR_WS_VCYCLE 4
+size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
+
+/* Solve H x = b to |b - H x| <= tol |b| (x: initial guess in, solution out;
+ * C128 fields; U in C128).  precond NONE ignores basis and A (may be NULL).
+ * TWO_LEVEL needs the basis and A of hdcr_build_coarse (A in
+ * params->coarse_dtype).  history (host, may be NULL) receives up to
+ * history_cap relative residual norms, one per outer iteration.  Returns 0 or
+ * a positive status (stats->status holds the same).  Synchronous. */
+int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
+               const void* A, const void* b, void* x, hdcr_solve_stats* stats, double* history, int32_t history_cap,
+               void* work, size_t work_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDCR_H */

@@ -118,6 +118,16 @@ def apply_h(U, psi, p: Params) -> np.ndarray:
     return out
 
 
+def apply_h_sites(U, psi, p: Params, sel) -> np.ndarray:
+    """(H psi) at the selected output sites sel = site4 * Ls + s; returns [len(sel), 4, 3]."""
+    U, psi = _c(U), _c(psi)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    out = np.empty((len(sel), 4, 3), dtype=np.complex128)
+    lib().or_apply_h_sites(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi),
+                           ctypes.c_long(len(sel)), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))
+    return out
+
+
 def apply_h_classes(U, psi, p: Params, block) -> np.ndarray:
     """H split by hop class relative to the blocks (9 fields, D9 order)."""
     U, psi = _c(U), _c(psi)

@@ -305,6 +305,26 @@ void or_apply_h(const int* dims, const int* bc, double M5, double mf, const doub
         }
 }
 
+// (H in) at nsel selected 5d output sites: sel[i] = site4 * Ls + s; out_sel[i][12].
+// Used for spot checks on lattices too large to apply H to in full.
+void or_apply_h_sites(const int* dims, const int* bc, double M5, double mf, const double* U_, const double* in_,
+                      long nsel, const long* sel, double* out_) {
+    Geom g(dims);
+    const cd* U = reinterpret_cast<const cd*>(U_);
+    const cd* in = reinterpret_cast<const cd*>(in_);
+    cd* out = reinterpret_cast<cd*>(out_);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nsel; ++i) {
+        const long x4 = sel[i] / g.Ls;
+        const int s_out = (int)(sel[i] % g.Ls);
+        cd acc[9][12];
+        for (int k = 0; k < 9; ++k)
+            for (int c = 0; c < 12; ++c) acc[k][c] = 0;
+        dwf_site(g, bc, M5, mf, nullptr, U, in, x4, g.Ls - 1 - s_out, acc);
+        g5_mul(out + i * 12, acc[0]);
+    }
+}
+
 // out9[cls] = H^(cls) in: H split by hop class relative to blocks of extent `block`
 // (nine full fields, D9 order). Summing the nine gives H in.
 void or_apply_h_classes(const int* dims, const int* bc, double M5, double mf, const int* block,

@@ -1,0 +1,214 @@
+"""MI355X (gfx950) hot path of the Hierarchically Deflated Conjugate Residual
+solver (Yamaguchi & Boyle, Lattice 2016): thin Python binding over the HIP
+C-ABI library ``libhdcr.so`` (declared in ``include/hdcr.h``).
+
+Every function here only marshals arguments: torch device tensors supply the
+pointers and the HIP stream, the work runs in the library's kernels.  There
+is no CPU fallback: without the built library every call raises.
+
+Device layouts (see ``include/hdcr.h``):
+  fine field   [12, V4, Ls]  complex128 / complex64   (component c = spin*3 + colour)
+  gauge field  [4, 3, 3, V4] complex128 / complex64
+  coarse vec   [nrhs, Nc, Nb] or [Nc, Nb]
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import (BF16C, C64, C128, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL, CoarseDesc, FineDesc,  # noqa: F401
+                   SolveParams, SolveStats)
+
+__all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
+           "load", "HDCRError"]
+
+load = _abi.load
+
+
+@dataclass(frozen=True)
+class Lattice:
+    """Fine lattice L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc; optional coarse blocking."""
+    L: tuple
+    Ls: int
+    M5: float = 1.8
+    mf: float = 0.01
+    bc: tuple = (1, 1, 1, -1)
+    block: tuple = (1, 1, 1, 1)
+    nvec: int = 0
+
+    @property
+    def V4(self):
+        return int(np.prod(self.L))
+
+    @property
+    def N5(self):
+        return self.V4 * self.Ls
+
+    @property
+    def fshape(self):
+        return (12, self.V4, self.Ls)
+
+    @property
+    def cdims(self):
+        return tuple(int(l) // int(b) for l, b in zip(self.L, self.block))
+
+    @property
+    def nc(self):
+        return int(np.prod(self.cdims))
+
+    @property
+    def nb(self):
+        return 2 * self.nvec
+
+    def fine_desc(self) -> FineDesc:
+        d = FineDesc()
+        d.L[:] = [int(v) for v in self.L]
+        d.Ls = int(self.Ls)
+        d.bc[:] = [int(v) for v in self.bc]
+        d.M5 = float(self.M5)
+        d.mf = float(self.mf)
+        return d
+
+    def coarse_desc(self) -> CoarseDesc:
+        c = CoarseDesc()
+        c.fine = self.fine_desc()
+        c.block[:] = [int(v) for v in self.block]
+        c.nvec = int(self.nvec)
+        return c
+
+
+# ----------------------------------------------------------------------------
+# layout conversion (host, numpy): canonical site-major <-> device SoA
+# ----------------------------------------------------------------------------
+
+def pack_fermion(psi_aos: np.ndarray) -> np.ndarray:
+    """[t, z, y, x, s, spin, col] -> [12, V4, Ls]."""
+    sh = psi_aos.shape
+    V4 = sh[0] * sh[1] * sh[2] * sh[3]
+    return np.ascontiguousarray(psi_aos.reshape(V4, sh[4], 12).transpose(2, 0, 1))
+
+
+def unpack_fermion(psi_soa: np.ndarray, L, Ls: int) -> np.ndarray:
+    """[12, V4, Ls] -> [t, z, y, x, s, spin, col]."""
+    Lx, Ly, Lz, Lt = L
+    return np.ascontiguousarray(np.asarray(psi_soa).transpose(1, 2, 0)).reshape(Lt, Lz, Ly, Lx, Ls, 4, 3)
+
+
+def pack_gauge(U_aos: np.ndarray) -> np.ndarray:
+    """[t, z, y, x, mu, row, col] -> [mu, row, col, V4]."""
+    sh = U_aos.shape
+    V4 = sh[0] * sh[1] * sh[2] * sh[3]
+    return np.ascontiguousarray(U_aos.reshape(V4, 4, 3, 3).transpose(1, 2, 3, 0))
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.complex64:
+        return C64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ----------------------------------------------------------------------------
+# entry points
+# ----------------------------------------------------------------------------
+
+def apply_fine(lat: Lattice, U, psi, out=None, stream=None):
+    """out = H psi, H = Gamma5 D_dwf (one HIP kernel launch)."""
+    torch = _torch()
+    lib = load()
+    if out is None:
+        out = torch.empty_like(psi)
+    d = lat.fine_desc()
+    _abi.check(lib.hdcr_apply_fine(ctypes.byref(d), _dtype_code(psi), _ptr(U), _ptr(psi), _ptr(out), _stream(stream)),
+               "hdcr_apply_fine")
+    return out
+
+
+def vec_dot(x, y, stream=None, work=None) -> complex:
+    """<x, y> with FP64 accumulation (synchronous)."""
+    lib = load()
+    if work is None:
+        work = _workspace(_abi.DOT_WORK_BYTES, x.device)
+    out = (ctypes.c_double * 2)()
+    _abi.check(lib.hdcr_vec_dot(_dtype_code(x), x.numel(), _ptr(x), _ptr(y), out, _ptr(work), work.numel(),
+                                _stream(stream)), "hdcr_vec_dot")
+    return complex(out[0], out[1])
+
+
+def default_params(**kw) -> SolveParams:
+    p = SolveParams()
+    p.tol = 1e-8
+    p.maxiter = 100000
+    p.restart = 8
+    p.precond = PRECOND_NONE
+    p.cheb_order = 10
+    p.cheb_lo = 1.0
+    p.cheb_hi = 64.0
+    p.coarse_tol = 1e-2
+    p.coarse_maxiter = 500
+    p.inner_dtype = C64
+    p.coarse_dtype = C64
+    p.verbose = 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(which: int, lat: Lattice, params: SolveParams | None = None) -> int:
+    lib = load()
+    cd = lat.coarse_desc()
+    return int(lib.hdcr_workspace_bytes(which, ctypes.byref(cd), ctypes.byref(params) if params is not None else None))
+
+
+def solve(lat: Lattice, U, b, x=None, params: SolveParams | None = None, basis=None, A=None, work=None,
+          history_cap: int = 100000, stream=None):
+    """Solve H x = b (synchronous).  Returns (x, stats dict, relative-residual history)."""
+    torch = _torch()
+    lib = load()
+    params = params or default_params()
+    if x is None:
+        x = torch.zeros_like(b)
+    cd = lat.coarse_desc()
+    if work is None:
+        work = _workspace(workspace_bytes(_abi.WS_SOLVE, lat, params), b.device)
+    st = SolveStats()
+    hist = (ctypes.c_double * max(1, history_cap))()
+    code = lib.hdcr_solve(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A), _ptr(b), _ptr(x),
+                          ctypes.byref(st), hist, history_cap, _ptr(work), work.numel(), _stream(stream))
+    _abi.check(code, "hdcr_solve")
+    return x, st.as_dict(), list(hist[:st.history_len])

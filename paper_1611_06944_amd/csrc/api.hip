@@ -1,0 +1,174 @@
+// C-ABI entry points: argument validation, workspace sizing and dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "solver.h"
+
+namespace hdcr {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+FineGeom make_geom(const hdcr_fine_desc* d) {
+    FineGeom g;
+    for (int i = 0; i < 4; ++i) {
+        g.L[i] = d->L[i];
+        g.bc[i] = d->bc[i];
+    }
+    g.Ls = d->Ls;
+    g.V4 = d->L[0] * d->L[1] * d->L[2] * d->L[3];
+    g.N5 = g.V4 * g.Ls;
+    int st = 1;
+    for (int i = 0; i < 4; ++i) {
+        g.stride[i] = st;
+        g.wrap[i] = (d->L[i] - 1) * st;
+        st *= d->L[i];
+    }
+    g.diag = 5.0 - d->M5;
+    g.mf = d->mf;
+    return g;
+}
+
+int check_fine_desc(const hdcr_fine_desc* d) {
+    if (!d) return fail(HDCR_EINVAL, "null fine descriptor");
+    int64_t v = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (d->L[i] < 1) return fail(HDCR_EINVAL, "lattice extent L[" + std::to_string(i) + "] must be >= 1");
+        if (d->bc[i] != 1 && d->bc[i] != -1)
+            return fail(HDCR_EINVAL, "bc[" + std::to_string(i) + "] must be +1 or -1");
+        v *= d->L[i];
+    }
+    if (d->Ls < 1) return fail(HDCR_EINVAL, "Ls must be >= 1");
+    // kernels address a whole FP64 field with 32-bit byte offsets
+    if (v * d->Ls * 12 * 16 >= (int64_t(1) << 32))
+        return fail(HDCR_EINVAL, "lattice too large (an FP64 fine field must stay below 4 GiB)");
+    if (!std::isfinite(d->M5) || !std::isfinite(d->mf)) return fail(HDCR_EINVAL, "M5 and mf must be finite");
+    return HDCR_OK;
+}
+
+int check_ptr(const void* p, size_t align, const char* name) {
+    if (!p) return fail(HDCR_EINVAL, std::string("null pointer: ") + name);
+    if (reinterpret_cast<uintptr_t>(p) % align)
+        return fail(HDCR_EINVAL, std::string("misaligned pointer: ") + name);
+    return HDCR_OK;
+}
+
+static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4; }
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace hdcr
+
+using namespace hdcr;
+
+extern "C" {
+
+const char* hdcr_strerror(int code) {
+    switch (code) {
+        case HDCR_OK: return "success";
+        case HDCR_EINVAL: return "invalid argument";
+        case HDCR_EHIP: return "HIP runtime error";
+        case HDCR_ENOMEM: return "workspace too small";
+        case HDCR_ENOTCONV: return "not converged within maxiter";
+        case HDCR_EBREAKDOWN: return "Krylov breakdown";
+        case HDCR_ENAN: return "NaN or Inf in the residual";
+        case HDCR_ERANK: return "block basis rank deficient";
+        default: return "unknown status";
+    }
+}
+
+const char* hdcr_last_error(void) { return hdcr::last_error_cstr(); }
+
+int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
+                    hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_apply_fine: dtype must be C128 or C64");
+    const size_t cs = csize(dtype);
+    if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(psi, cs, "psi")) || (e = check_ptr(out, cs, "out"))) return e;
+    const FineGeom g = make_geom(desc);
+    const size_t fbytes = (size_t)12 * g.N5 * cs;
+    if (overlap(psi, fbytes, out, fbytes)) return fail(HDCR_EINVAL, "hdcr_apply_fine: psi and out overlap");
+    if (dtype == HDCR_C128)
+        launch_dslash<double>(g, (const double2*)U, (const double2*)psi, (double2*)out, stream);
+    else
+        launch_dslash<float>(g, (const float2*)U, (const float2*)psi, (float2*)out, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work, size_t work_bytes,
+                 hipStream_t stream) {
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_vec_dot: dtype must be C128 or C64");
+    if (n < 0) return fail(HDCR_EINVAL, "hdcr_vec_dot: n < 0");
+    if (!out) return fail(HDCR_EINVAL, "hdcr_vec_dot: null out");
+    int e;
+    if (n > 0 && ((e = check_ptr(x, csize(dtype), "x")) || (e = check_ptr(y, csize(dtype), "y")))) return e;
+    if ((e = check_ptr(work, 256, "work"))) return e;
+    if (work_bytes < HDCR_DOT_WORK_BYTES) return fail(HDCR_ENOMEM, "hdcr_vec_dot: work smaller than HDCR_DOT_WORK_BYTES");
+    double2* scratch = static_cast<double2*>(work);
+    if (dtype == HDCR_C128)
+        launch_dot<double>(n, (const double2*)x, (const double2*)y, scratch, scratch + REDUCE_BLOCKS, stream);
+    else
+        launch_dot<float>(n, (const float2*)x, (const float2*)y, scratch, scratch + REDUCE_BLOCKS, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    double2 h;
+    HDCR_HIP_CHECK(hipMemcpyAsync(&h, scratch + REDUCE_BLOCKS, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+    out[0] = h.x;
+    out[1] = h.y;
+    return HDCR_OK;
+}
+
+size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params) {
+    if (!desc || check_fine_desc(&desc->fine)) return 0;
+    const FineGeom g = make_geom(&desc->fine);
+    switch (which) {
+        case HDCR_WS_SOLVE:
+            if (!params) return 0;
+            if (params->precond == HDCR_PRECOND_NONE) return cr_workspace_bytes(g);
+            return 0;
+        default:
+            return 0;
+    }
+}
+
+int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
+               const void* A, const void* b, void* x, hdcr_solve_stats* stats, double* history, int32_t history_cap,
+               void* work, size_t work_bytes, hipStream_t stream) {
+    if (!desc || !params) return fail(HDCR_EINVAL, "hdcr_solve: null descriptor or params");
+    int e = check_fine_desc(&desc->fine);
+    if (e) return e;
+    if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(b, 16, "b")) || (e = check_ptr(x, 16, "x")) ||
+        (e = check_ptr(work, 256, "work")))
+        return e;
+    if (!(params->tol > 0) || params->maxiter < 0) return fail(HDCR_EINVAL, "hdcr_solve: tol must be > 0, maxiter >= 0");
+    if (history_cap < 0 || (history_cap > 0 && !history)) return fail(HDCR_EINVAL, "hdcr_solve: bad history buffer");
+    const FineGeom g = make_geom(&desc->fine);
+    const size_t fbytes = (size_t)12 * g.N5 * 16;
+    if (overlap(b, fbytes, x, fbytes)) return fail(HDCR_EINVAL, "hdcr_solve: b and x overlap");
+    if (params->precond == HDCR_PRECOND_NONE) {
+        if (work_bytes < cr_workspace_bytes(g)) return fail(HDCR_ENOMEM, "hdcr_solve: workspace too small");
+        return cr_solve(g, params, (const double2*)U, (const double2*)b, (double2*)x, stats, history, history_cap,
+                        work, work_bytes, stream);
+    }
+    (void)basis;
+    (void)A;
+    return fail(HDCR_EINVAL, "hdcr_solve: unknown precond");
+}
+
+}  // extern "C"

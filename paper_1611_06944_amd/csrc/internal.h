@@ -1,0 +1,164 @@
+// Internal declarations shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hdcr.h"
+
+namespace hdcr {
+
+// ---------------------------------------------------------------------------
+// complex helpers on HIP vector types (re = .x, im = .y)
+// ---------------------------------------------------------------------------
+template <typename T> struct C2t;
+template <> struct C2t<double> { typedef double2 type; };
+template <> struct C2t<float> { typedef float2 type; };
+template <typename T> using C2 = typename C2t<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ C2<T> mk(T re, T im) {
+    C2<T> r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+template <typename T> __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ C2<T> cscale(T s, C2<T> a) { return mk<T>(s * a.x, s * a.y); }
+// a * b
+template <typename T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ C2<T> cjmul(C2<T> a, C2<T> b) {
+    return mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// acc + a * b
+template <typename T> __device__ __forceinline__ C2<T> cfma(C2<T> a, C2<T> b, C2<T> acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename T> __device__ __forceinline__ C2<T> cjfma(C2<T> a, C2<T> b, C2<T> acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+// i * a, -i * a
+template <typename T> __device__ __forceinline__ C2<T> cmuli(C2<T> a) { return mk<T>(-a.y, a.x); }
+template <typename T> __device__ __forceinline__ C2<T> cmulmi(C2<T> a) { return mk<T>(a.y, -a.x); }
+template <typename T> __device__ __forceinline__ C2<T> cneg(C2<T> a) { return mk<T>(-a.x, -a.y); }
+
+// ---------------------------------------------------------------------------
+// buffer addressing: a scalar resource descriptor plus a 32-bit per-lane byte
+// offset and a uniform (scalar) byte offset.  Every field kernel addresses its
+// arrays this way so that the many component loads of a site share one vector
+// address register.  Loads past the descriptor's byte range return zero.
+// ---------------------------------------------------------------------------
+constexpr int BUF_FLAGS = 0x00020000;  // gfx9 raw-buffer descriptor word 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, BUF_FLAGS);
+}
+
+template <typename T> struct Buf;
+template <> struct Buf<double> {
+    static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                               voff, soff, 0);
+    }
+};
+template <> struct Buf<float> {
+    static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                              voff, soff, 0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// geometry passed to kernels by value
+// ---------------------------------------------------------------------------
+struct FineGeom {
+    int L[4];
+    int Ls;
+    int V4;
+    int N5;       // V4 * Ls
+    int bc[4];
+    int stride[4];  // 4d site-index stride of direction mu
+    int wrap[4];    // (L[mu] - 1) * stride[mu]
+    double diag;    // 5 - M5
+    double mf;
+};
+
+FineGeom make_geom(const hdcr_fine_desc* d);
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+int fail(int code, const std::string& msg);
+
+#define HDCR_HIP_CHECK(expr)                                                              \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return ::hdcr::fail(HDCR_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+int check_fine_desc(const hdcr_fine_desc* d);
+int check_ptr(const void* p, size_t align, const char* name);
+
+// ---------------------------------------------------------------------------
+// kernels launched from host code (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+// out = H in  (fine operator), precision T
+template <typename T>
+void launch_dslash(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s);
+
+// Reductions: every reduction writes REDUCE_BLOCKS partial sums (as double2)
+// into `partials` and a finalize step sums them in fixed order into `result`.
+constexpr int REDUCE_BLOCKS = 1024;
+constexpr int REDUCE_THREADS = 256;
+static_assert((REDUCE_BLOCKS + 1) * 16 <= HDCR_DOT_WORK_BYTES, "dot scratch");
+
+// Workgroup tree reduction of NQ double values per thread; thread 0 of the
+// workgroup returns the sums.  Uses LDS, REDUCE_THREADS threads.
+template <int NQ>
+__device__ __forceinline__ void block_reduce(double (&v)[NQ]) {
+    __shared__ double sh[NQ][REDUCE_THREADS];
+    const int t = threadIdx.x;
+    __syncthreads();  // a previous reduction in the same kernel may still be reading sh
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int w = REDUCE_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sh[q][t] += sh[q][t + w];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = sh[q][0];
+}
+
+template <typename T>
+void launch_dot(int64_t n, const C2<T>* x, const C2<T>* y, double2* partials, double2* result, hipStream_t s);
+void launch_finalize(const double2* partials, int np, double2* result, hipStream_t s);
+
+}  // namespace hdcr

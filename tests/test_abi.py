@@ -1,0 +1,110 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+function declared in include/hdcr.h, its structs match the ctypes mirror, and
+argument validation rejects bad calls before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hdcr.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hdcr_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1611_06944_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1611_06944_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert "hdcr_apply_fine" in names and "hdcr_solve" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(ROOT, "paper_1611_06944_amd", "libhdcr.so")],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    for n in names:
+        getattr(lib, n)
+
+
+def test_ctypes_mirror_matches_c_layout(tmp_path):
+    from paper_1611_06944_amd import _abi
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "hdcr.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(hdcr_fine_desc), sizeof(hdcr_coarse_desc), sizeof(hdcr_solve_params),
+         sizeof(hdcr_solve_stats));
+  printf("%zu %zu %zu\n", offsetof(hdcr_fine_desc, M5), offsetof(hdcr_coarse_desc, nvec),
+         offsetof(hdcr_solve_params, coarse_maxiter));
+  printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+                    "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    py = [ctypes.sizeof(_abi.FineDesc), ctypes.sizeof(_abi.CoarseDesc), ctypes.sizeof(_abi.SolveParams),
+          ctypes.sizeof(_abi.SolveStats), _abi.FineDesc.M5.offset, _abi.CoarseDesc.nvec.offset,
+          _abi.SolveParams.coarse_maxiter.offset, _abi.SolveStats.true_rel_residual.offset,
+          _abi.SolveStats.history_len.offset]
+    assert vals == py
+
+
+def test_argument_validation_before_launch(lib):
+    from paper_1611_06944_amd import Lattice, _abi
+    lat = Lattice((4, 4, 4, 4), 8)
+    d = lat.fine_desc()
+    fake = ctypes.c_void_p(4096)
+    # null descriptor
+    assert lib.hdcr_apply_fine(None, 0, fake, fake, ctypes.c_void_p(8192), None) == _abi.HDCR_EINVAL
+    # bad dtype
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 2, fake, fake, ctypes.c_void_p(8192), None) == _abi.HDCR_EINVAL
+    # null pointer
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, None, fake, ctypes.c_void_p(8192), None) == _abi.HDCR_EINVAL
+    assert b"U" in lib.hdcr_last_error()
+    # misaligned pointer
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, ctypes.c_void_p(4100), fake, ctypes.c_void_p(1 << 30),
+                               None) == _abi.HDCR_EINVAL
+    # aliased in/out
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, fake, fake, fake, None) == _abi.HDCR_EINVAL
+    assert b"overlap" in lib.hdcr_last_error()
+    # bad boundary condition and extent
+    d.bc[3] = 0
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, fake, fake, ctypes.c_void_p(1 << 30), None) == _abi.HDCR_EINVAL
+    d.bc[3] = -1
+    d.L[0] = 0
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, fake, fake, ctypes.c_void_p(1 << 30), None) == _abi.HDCR_EINVAL
+    assert lib.hdcr_strerror(_abi.HDCR_ENOTCONV) == b"not converged within maxiter"
+
+
+def test_layout_roundtrip():
+    import hdcr_inputs as hi
+    from paper_1611_06944_amd import pack_fermion, pack_gauge, unpack_fermion
+    L, Ls = (2, 3, 4, 5), 6
+    psi = hi.gaussian_fermion(L, Ls, seed=1)
+    soa = pack_fermion(psi)
+    assert soa.shape == (12, 120, 6)
+    # component c = spin*3 + col of site4 ((t*Lz+z)*Ly+y)*Lx+x, fifth coordinate s
+    t, z, y, x, s, sp, col = 4, 3, 2, 1, 5, 2, 1
+    assert soa[sp * 3 + col, ((t * 4 + z) * 3 + y) * 2 + x, s] == psi[t, z, y, x, s, sp, col]
+    np.testing.assert_array_equal(unpack_fermion(soa, L, Ls), psi)
+    U = hi.gauge_field(L, seed=2)
+    g = pack_gauge(U)
+    assert g[3, 1, 2, ((t * 4 + z) * 3 + y) * 2 + x] == U[t, z, y, x, 3, 1, 2]

@@ -127,3 +127,14 @@ def test_hop_classes_sum_to_h():
     # extent-1 blocks in z: every z hop crosses a face; extent = L in t: the t hops that
     # wrap the lattice cross the (only) block's face
     assert np.abs(cls[3]).max() > 0 and np.abs(cls[7]).max() > 0
+
+
+def test_apply_h_sites_matches_full_apply():
+    L, Ls = (4, 2, 6, 4), 6
+    p = oracle.Params(L, Ls)
+    U = hi.gauge_field(L)
+    psi = hi.gaussian_fermion(L, Ls, seed=2)
+    full = oracle.apply_h(U, psi, p).reshape(-1, Ls, 4, 3)
+    sel = np.array([0, 5, 17, 191, 4 * 2 * 6 * 4 * 6 - 1])
+    got = oracle.apply_h_sites(U, psi, p, sel)
+    np.testing.assert_array_equal(got, full.reshape(-1, 4, 3)[sel])
