@@ -1,5 +1,6 @@
 // C-ABI entry points: argument validation, workspace sizing and dispatch.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -36,7 +37,27 @@ FineGeom make_geom(const hdcr_fine_desc* d) {
     }
     g.diag = 5.0 - d->M5;
     g.mf = d->mf;
+    choose_traversal(g, 0, 0);
     return g;
+}
+
+void choose_traversal(FineGeom& g, int tslab, int ysplit) {
+    const int Lt = g.L[3], Ly = g.L[1];
+    // tuning overrides (benchmark sweeps only)
+    if (const char* e = std::getenv("HDCR_TSLAB")) tslab = std::atoi(e);
+    if (const char* e = std::getenv("HDCR_YSPLIT")) ysplit = std::atoi(e);
+    if (tslab <= 0) {
+        // one slab per XCD when Lt allows it, else the whole t extent
+        tslab = (Lt % NUM_XCD == 0) ? Lt / NUM_XCD : Lt;
+        if (tslab < 1) tslab = 1;
+    }
+    if (Lt % tslab != 0) tslab = Lt;
+    if (ysplit <= 0) ysplit = 1;
+    if (Ly % ysplit != 0) ysplit = 1;
+    g.tslab = tslab;
+    g.ysplit = ysplit;
+    g.variant = 0;
+    if (const char* e = std::getenv("HDCR_DSLASH_VARIANT")) g.variant = std::atoi(e);
 }
 
 int check_fine_desc(const hdcr_fine_desc* d) {

@@ -102,7 +102,22 @@ struct FineGeom {
     int wrap[4];    // (L[mu] - 1) * stride[mu]
     double diag;    // 5 - M5
     double mf;
+    // traversal order of the stencil kernels (see Traversal in fine.hip):
+    // t is cut into slabs of tslab slices and y into ysplit parts; inside a
+    // slab the order is x, y-part, t, z, so t and z neighbours are a few
+    // rows apart; workgroups are remapped so each XCD sweeps one contiguous
+    // range of that order.
+    int tslab;
+    int ysplit;
+    int variant;  // fine-stencil kernel variant (0 = default choice)
 };
+
+// number of XCDs (separate L2 caches) that hardware workgroup dispatch
+// round-robins over on gfx950
+constexpr int NUM_XCD = 8;
+
+// choose the traversal parameters for a lattice (host)
+void choose_traversal(FineGeom& g, int tslab, int ysplit);
 
 FineGeom make_geom(const hdcr_fine_desc* d);
 
