@@ -156,6 +156,53 @@ int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, doub
 #define HDCR_WS_VCYCLE 4
 size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
 
+/* Bytes of the opaque basis buffer (FP64 and FP32 copies of the chirally
+ * compressed block basis) and of the little Dirac operator in `dtype`. */
+size_t hdcr_basis_bytes(const hdcr_coarse_desc* desc);
+size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype);
+
+/* Coarse space (Sec. 4).  vecs: nvec fine fields (C128, [k][12][V4][Ls]), the
+ * subspace vectors phi_k.  Each is split into its two Gamma5 = gamma5 R5
+ * chiralities, restricted to the blocks (block[mu] sites x all of Ls) and, per
+ * block and chirality, orthonormalised in index order (Q of a thin QR with a
+ * positive real R diagonal): basis vector j < nvec of block a is phi^{a,+}_j,
+ * j >= nvec is phi^{a,-}_{j-nvec}.  Then the little Dirac operator
+ *   A[a][d][j][k] = <phi^a_j | H^(d) | phi^{a+d}_k>,  d in D9 = (0,+x,+y,+z,+t,-x,-y,-z,-t),
+ * where H^(d), d != 0, holds the hops from block a+d into block a across the
+ * face d and H^(0) everything else (diagonal, fifth dimension, hops inside a);
+ * summing the nine blocks over equal a+d gives <phi^a_j|H|phi^b_k>.  Built in
+ * FP64 and stored in A_dtype.  U in C128.  work: hdcr_workspace_bytes(
+ * HDCR_WS_BUILD).  Synchronous; returns HDCR_ERANK if a block's vectors are
+ * dependent (remaining norm below 1e-12 of the chiral projection's). */
+int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* vecs, void* basis, void* A,
+                      hdcr_dtype A_dtype, void* work, size_t work_bytes, hipStream_t stream);
+
+/* A in C128 storage -> A in C64 or BF16C storage (round to nearest). */
+int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* A_dst,
+                        hipStream_t stream);
+
+/* Read back the opaque buffers: A (any storage) as logical A[a][d][j][k]
+ * complex double; the basis as Nb full fine fields (C128, [j][12][V4][Ls]),
+ * field j holding phi^a_j on every block a. */
+int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, void* A_c128,
+                       hipStream_t stream);
+int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields_c128, hipStream_t stream);
+
+/* Restriction v[a][j] = <phi^a_j, psi> (P^dag) and prolongation
+ * psi(x) = sum_j phi^{b(x)}_j(x) v[b(x)][j] (P), in C128 or C64 (the basis copy
+ * of that precision is used). */
+int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* psi, void* v,
+                  hipStream_t stream);
+int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,
+                 hipStream_t stream);
+
+/* Coarse 9-point apply out[r][a] = sum_d A[a][d] v[r][a+d] (coarse-periodic;
+ * the fine antiperiodic sign is inside A) for nrhs right-hand sides.  dtype is
+ * A's storage; vectors are C128 for C128 storage, C64 otherwise (BF16C storage
+ * accumulates in FP32). */
+int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, const void* v, void* out,
+                      int32_t nrhs, hipStream_t stream);
+
 /* Solve H x = b to |b - H x| <= tol |b| (x: initial guess in, solution out;
  * C128 fields; U in C128).  precond NONE ignores basis and A (may be NULL).
  * TWO_LEVEL needs the basis and A of hdcr_build_coarse (A in

@@ -23,6 +23,7 @@ from ._abi import (BF16C, C64, C128, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL,
                    SolveParams, SolveStats)
 
 __all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
+           "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "load", "HDCRError"]
 
 load = _abi.load
@@ -212,3 +213,117 @@ def solve(lat: Lattice, U, b, x=None, params: SolveParams | None = None, basis=N
                           ctypes.byref(st), hist, history_cap, _ptr(work), work.numel(), _stream(stream))
     _abi.check(code, "hdcr_solve")
     return x, st.as_dict(), list(hist[:st.history_len])
+
+
+# ----------------------------------------------------------------------------
+# coarse space
+# ----------------------------------------------------------------------------
+
+def basis_bytes(lat: Lattice) -> int:
+    cd = lat.coarse_desc()
+    n = int(load().hdcr_basis_bytes(ctypes.byref(cd)))
+    if n == 0:
+        raise ValueError(f"invalid coarse description {lat}")
+    return n
+
+
+def coarse_bytes(lat: Lattice, dtype: int) -> int:
+    cd = lat.coarse_desc()
+    n = int(load().hdcr_coarse_bytes(ctypes.byref(cd), int(dtype)))
+    if n == 0:
+        raise ValueError(f"invalid coarse description {lat}")
+    return n
+
+
+def build_coarse(lat: Lattice, U, vecs, A_dtype: int = C128, work=None, stream=None):
+    """Chirally split block-orthonormal basis and little Dirac operator (synchronous).
+
+    vecs: complex128 tensor [nvec, 12, V4, Ls].  Returns (basis, A) opaque uint8 tensors.
+    """
+    torch = _torch()
+    lib = load()
+    dev = U.device
+    basis = torch.empty(basis_bytes(lat), dtype=torch.uint8, device=dev)
+    A = torch.empty(coarse_bytes(lat, A_dtype), dtype=torch.uint8, device=dev)
+    if work is None:
+        work = _workspace(workspace_bytes(_abi.WS_BUILD, lat), dev)
+    cd = lat.coarse_desc()
+    _abi.check(lib.hdcr_build_coarse(ctypes.byref(cd), _ptr(U), _ptr(vecs), _ptr(basis), _ptr(A), int(A_dtype),
+                                     _ptr(work), work.numel(), _stream(stream)), "hdcr_build_coarse")
+    return basis, A
+
+
+def build_coarse_status(lat: Lattice, U, vecs, A_dtype: int = C128):
+    """As build_coarse but returns the status code instead of raising on rank deficiency."""
+    torch = _torch()
+    lib = load()
+    dev = U.device
+    basis = torch.empty(basis_bytes(lat), dtype=torch.uint8, device=dev)
+    A = torch.empty(coarse_bytes(lat, A_dtype), dtype=torch.uint8, device=dev)
+    work = _workspace(workspace_bytes(_abi.WS_BUILD, lat), dev)
+    cd = lat.coarse_desc()
+    code = lib.hdcr_build_coarse(ctypes.byref(cd), _ptr(U), _ptr(vecs), _ptr(basis), _ptr(A), int(A_dtype),
+                                 _ptr(work), work.numel(), _stream(None))
+    _abi.check(code, "hdcr_build_coarse")
+    return code
+
+
+def convert_coarse(lat: Lattice, A128, dtype: int, stream=None):
+    torch = _torch()
+    out = torch.empty(coarse_bytes(lat, dtype), dtype=torch.uint8, device=A128.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_convert_coarse(ctypes.byref(cd), _ptr(A128), int(dtype), _ptr(out), _stream(stream)),
+               "hdcr_convert_coarse")
+    return out
+
+
+def export_coarse(lat: Lattice, A, dtype: int, stream=None):
+    """Logical A[a, d, j, k] (complex128) from any storage."""
+    torch = _torch()
+    out = torch.empty((lat.nc, 9, lat.nb, lat.nb), dtype=torch.complex128, device=A.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_export_coarse(ctypes.byref(cd), int(dtype), _ptr(A), _ptr(out), _stream(stream)),
+               "hdcr_export_coarse")
+    return out
+
+
+def export_basis(lat: Lattice, basis, stream=None):
+    """The basis as Nb full fine fields [Nb, 12, V4, Ls] (complex128)."""
+    torch = _torch()
+    out = torch.empty((lat.nb, 12, lat.V4, lat.Ls), dtype=torch.complex128, device=basis.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_export_basis(ctypes.byref(cd), _ptr(basis), _ptr(out), _stream(stream)),
+               "hdcr_export_basis")
+    return out
+
+
+def restrict(lat: Lattice, basis, psi, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty((lat.nc, lat.nb), dtype=psi.dtype, device=psi.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_restrict(ctypes.byref(cd), _dtype_code(psi), _ptr(basis), _ptr(psi), _ptr(out),
+                                    _stream(stream)), "hdcr_restrict")
+    return out
+
+
+def prolong(lat: Lattice, basis, v, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(lat.fshape, dtype=v.dtype, device=v.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_prolong(ctypes.byref(cd), _dtype_code(v), _ptr(basis), _ptr(v), _ptr(out),
+                                   _stream(stream)), "hdcr_prolong")
+    return out
+
+
+def apply_coarse(lat: Lattice, A, A_dtype: int, v, out=None, stream=None):
+    """out[r] = A v[r]; v: [nrhs, Nc, Nb] or [Nc, Nb] (complex128 for C128 storage, complex64 otherwise)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(v)
+    nrhs = 1 if v.dim() == 2 else v.shape[0]
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_apply_coarse(ctypes.byref(cd), int(A_dtype), _ptr(A), _ptr(v), _ptr(out), nrhs,
+                                        _stream(stream)), "hdcr_apply_coarse")
+    return out

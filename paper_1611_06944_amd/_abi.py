@@ -66,6 +66,15 @@ PROTOTYPES = {
     "hdcr_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams)]),
     "hdcr_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp, _vp, _vp,
                                   ctypes.POINTER(SolveStats), _dbl_p, _i32, _vp, _sz, _vp]),
+    "hdcr_basis_bytes": (_sz, [ctypes.POINTER(CoarseDesc)]),
+    "hdcr_coarse_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32]),
+    "hdcr_build_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
+    "hdcr_convert_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _i32, _vp, _vp]),
+    "hdcr_export_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp]),
+    "hdcr_export_basis": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp]),
+    "hdcr_restrict": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
+    "hdcr_prolong": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
+    "hdcr_apply_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _i32, _vp]),
 }
 
 _lib = None

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <string>
 
+#include "coarse.h"
 #include "solver.h"
 
 namespace hdcr {
@@ -163,6 +164,9 @@ size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_
             if (!params) return 0;
             if (params->precond == HDCR_PRECOND_NONE) return cr_workspace_bytes(g);
             return 0;
+        case HDCR_WS_BUILD:
+            if (check_coarse_desc(desc)) return 0;
+            return build_workspace_bytes(make_coarse_geom(desc));
         default:
             return 0;
     }

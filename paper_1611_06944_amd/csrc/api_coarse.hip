@@ -1,0 +1,227 @@
+// C-ABI entry points of the coarse space: basis and little Dirac operator
+// build, restriction, prolongation, coarse apply, export.
+#include <string>
+
+#include "coarse.h"
+#include "solver.h"
+
+namespace hdcr {
+
+int check_coarse_desc(const hdcr_coarse_desc* d) {
+    if (!d) return fail(HDCR_EINVAL, "null coarse descriptor");
+    int e = check_fine_desc(&d->fine);
+    if (e) return e;
+    if (d->fine.Ls % 2 != 0) return fail(HDCR_EINVAL, "the coarse space needs an even Ls (chiral halves of Gamma5)");
+    int64_t bvol = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (d->block[mu] < 1 || d->fine.L[mu] % d->block[mu] != 0)
+            return fail(HDCR_EINVAL, "block[" + std::to_string(mu) + "] must divide L[" + std::to_string(mu) + "]");
+        bvol *= d->block[mu];
+    }
+    const int64_t nhalf = bvol * (d->fine.Ls / 2) * 12;
+    if (d->nvec < 1 || d->nvec > nhalf)
+        return fail(HDCR_EINVAL, "nvec must be in [1, block dof / 2] (the dimension of one chirality half)");
+    if (2 * d->nvec > 128) return fail(HDCR_EINVAL, "Nb = 2*nvec must be <= 128");
+    return HDCR_OK;
+}
+
+CoarseGeom make_coarse_geom(const hdcr_coarse_desc* d) {
+    CoarseGeom c;
+    c.f = make_geom(&d->fine);
+    c.bvol = 1;
+    c.Nc = 1;
+    int st = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        c.B[mu] = d->block[mu];
+        c.C[mu] = d->fine.L[mu] / d->block[mu];
+        c.bvol *= c.B[mu];
+        c.Nc *= c.C[mu];
+        c.cstride[mu] = st;
+        st *= c.C[mu];
+    }
+    c.nvec = d->nvec;
+    c.Nb = 2 * d->nvec;
+    c.Lh = d->fine.Ls / 2;
+    c.nhalf = c.bvol * c.Lh * 12;
+    return c;
+}
+
+// columns of A built per pass of the class-split stencil
+static int build_chunk(const CoarseGeom& c) { return c.Nb < 4 ? c.Nb : 4; }
+
+size_t build_workspace_bytes(const CoarseGeom& c) {
+    Carver w(nullptr, 0);
+    const size_t fsz = (size_t)12 * c.f.N5;
+    const int kc = build_chunk(c);
+    w.take<double2>(fsz * kc);          // expanded basis fields
+    w.take<double2>(fsz * kc * 9);      // class-split images
+    w.take<double2>(coarse_elems(c));   // A in FP64
+    w.take<int>(64);                    // rank flag
+    return w.used();
+}
+
+static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4; }
+
+}  // namespace hdcr
+
+using namespace hdcr;
+
+extern "C" {
+
+size_t hdcr_basis_bytes(const hdcr_coarse_desc* desc) {
+    if (check_coarse_desc(desc)) return 0;
+    return basis_bytes(make_coarse_geom(desc));
+}
+
+size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype) {
+    if (check_coarse_desc(desc)) return 0;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_BF16C) return 0;
+    return coarse_bytes(make_coarse_geom(desc), dtype);
+}
+
+int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* vecs, void* basis, void* A,
+                      hdcr_dtype A_dtype, void* work, size_t work_bytes, hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (A_dtype != HDCR_C128 && A_dtype != HDCR_C64 && A_dtype != HDCR_BF16C)
+        return fail(HDCR_EINVAL, "hdcr_build_coarse: bad A dtype");
+    if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(vecs, 16, "vecs")) || (e = check_ptr(basis, 16, "basis")) ||
+        (e = check_ptr(A, 16, "A")) || (e = check_ptr(work, 256, "work")))
+        return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (work_bytes < build_workspace_bytes(c)) return fail(HDCR_ENOMEM, "hdcr_build_coarse: workspace too small");
+    const size_t fsz = (size_t)12 * c.f.N5;
+    const int kc = build_chunk(c);
+    Carver w(work, work_bytes);
+    double2* X = w.take<double2>(fsz * kc);
+    double2* Y = w.take<double2>(fsz * kc * 9);
+    double2* A64 = w.take<double2>(coarse_elems(c));
+    int* flag = w.take<int>(64);
+    double2* b64 = basis64(basis);
+    // chiral split and block orthonormalisation
+    HDCR_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), stream));
+    launch_basis_fold(c, static_cast<const double2*>(vecs), b64, stream);
+    launch_block_orth(c, b64, flag, stream);
+    launch_basis_to_f32(c, b64, basis32(c, basis), stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    // A = P^dag H P, kc columns at a time
+    double2* Adst = (A_dtype == HDCR_C128) ? static_cast<double2*>(A) : A64;
+    const double2* U64 = static_cast<const double2*>(U);
+    for (int k0 = 0; k0 < c.Nb; k0 += kc) {
+        const int nk = (c.Nb - k0 < kc) ? c.Nb - k0 : kc;
+        launch_basis_expand(c, b64, k0, nk, X, stream);
+        for (int kk = 0; kk < nk; ++kk)
+            for (int d = 0; d < 9; ++d) launch_dslash_class(c, U64, X + kk * fsz, Y + (kk * 9 + d) * fsz, d, stream);
+        launch_coarse_project(c, b64, Y, k0, nk, Adst, stream);
+        HDCR_HIP_CHECK(hipGetLastError());
+    }
+    if (A_dtype != HDCR_C128) launch_coarse_convert(c, A64, A_dtype, A, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    int hflag = 0;
+    HDCR_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+    if (hflag) return fail(HDCR_ERANK, "hdcr_build_coarse: a block's subspace vectors are numerically dependent");
+    return HDCR_OK;
+}
+
+int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* Adst,
+                        hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C64 && dtype != HDCR_BF16C) return fail(HDCR_EINVAL, "hdcr_convert_coarse: dtype C64 or BF16C");
+    if ((e = check_ptr(A128, 16, "A128")) || (e = check_ptr(Adst, 4, "Adst"))) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    launch_coarse_convert(c, static_cast<const double2*>(A128), dtype, Adst, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, void* out, hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_BF16C)
+        return fail(HDCR_EINVAL, "hdcr_export_coarse: bad dtype");
+    if ((e = check_ptr(A, 4, "A")) || (e = check_ptr(out, 16, "out"))) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    launch_coarse_export(c, dtype, A, static_cast<double2*>(out), stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields, hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(fields, 16, "fields"))) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    launch_basis_expand(c, basis64(basis), 0, c.Nb, static_cast<double2*>(fields), stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* psi, void* v,
+                  hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_restrict: dtype C128 or C64");
+    if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(psi, csize(dtype), "psi")) ||
+        (e = check_ptr(v, csize(dtype), "v")))
+        return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (dtype == HDCR_C128)
+        launch_restrict<double>(c, basis64(basis), static_cast<const double2*>(psi), nullptr, static_cast<double2*>(v),
+                                stream);
+    else
+        launch_restrict<float>(c, basis32(c, basis), static_cast<const float2*>(psi), nullptr, static_cast<float2*>(v),
+                               stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,
+                 hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_prolong: dtype C128 or C64");
+    if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(psi, csize(dtype), "psi")) ||
+        (e = check_ptr(v, csize(dtype), "v")))
+        return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (dtype == HDCR_C128)
+        launch_prolong<double>(c, basis64(basis), static_cast<const double2*>(v), nullptr, static_cast<double2*>(psi),
+                               stream);
+    else
+        launch_prolong<float>(c, basis32(c, basis), static_cast<const float2*>(v), nullptr, static_cast<float2*>(psi),
+                              stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, const void* v, void* out,
+                      int32_t nrhs, hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_BF16C)
+        return fail(HDCR_EINVAL, "hdcr_apply_coarse: bad dtype");
+    if (nrhs < 1 || nrhs > 65535) return fail(HDCR_EINVAL, "hdcr_apply_coarse: nrhs in [1, 65535]");
+    const hdcr_dtype vdt = (dtype == HDCR_C128) ? HDCR_C128 : HDCR_C64;
+    if ((e = check_ptr(A, 4, "A")) || (e = check_ptr(v, csize(vdt), "v")) || (e = check_ptr(out, csize(vdt), "out")))
+        return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    const size_t vb = (size_t)nrhs * c.Nc * c.Nb * csize(vdt);
+    const char* pv = static_cast<const char*>(v);
+    const char* po = static_cast<const char*>(out);
+    if (pv < po + vb && po < pv + vb) return fail(HDCR_EINVAL, "hdcr_apply_coarse: v and out overlap");
+    if (dtype == HDCR_C128)
+        launch_coarse_apply<double>(c, static_cast<const double2*>(A), static_cast<const double2*>(v),
+                                    static_cast<double2*>(out), nrhs, stream);
+    else if (dtype == HDCR_C64)
+        launch_coarse_apply<float>(c, static_cast<const float2*>(A), static_cast<const float2*>(v),
+                                   static_cast<float2*>(out), nrhs, stream);
+    else
+        launch_coarse_apply_bf16(c, static_cast<const uint16_t*>(A), static_cast<const float2*>(v),
+                                 static_cast<float2*>(out), nrhs, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Coarse-space geometry and the kernels of the block-projected subspace.
+#pragma once
+
+#include "internal.h"
+
+namespace hdcr {
+
+// Blocks of B[mu] 4d sites spanning all of Ls (Sec. 4).  The basis of a block
+// is chirally split: phi^{a,+}_k and phi^{a,-}_k lie in the +1 and -1
+// eigenspaces of Gamma5 = gamma5 R5, which is block-local.  Such a vector is
+// fixed by its values on s < Ls/2:  phi(x, Ls-1-s, spin) = sigma g(spin) phi(x, s, spin)
+// with sigma = +-1 the chirality and g = gamma5's diagonal (+1 upper, -1 lower
+// spins).  The library stores sqrt(2) * phi on s < Ls/2 only ("compressed"),
+// which makes the compressed vectors orthonormal in C^{nhalf} and halves the
+// basis memory and traffic.
+//
+// Compressed index inside a block: i = (comp * bvol + sl) * Lh + s, comp =
+// spin*3 + colour, sl = lexicographic site inside the block, s < Lh = Ls/2.
+// Basis buffer: [FP64 part][FP32 part], each [a][h][k][i] (h = 0: +, 1: -).
+struct CoarseGeom {
+    FineGeom f;
+    int B[4];    // block extents
+    int C[4];    // coarse extents
+    int Nc;      // coarse sites
+    int bvol;    // 4d sites per block
+    int nvec;    // vectors per chirality
+    int Nb;      // 2 * nvec
+    int Lh;      // Ls / 2
+    int nhalf;   // bvol * Lh * 12
+    int cstride[4];  // coarse site-index strides
+};
+
+CoarseGeom make_coarse_geom(const hdcr_coarse_desc* d);
+int check_coarse_desc(const hdcr_coarse_desc* d);
+size_t build_workspace_bytes(const CoarseGeom& c);
+
+inline size_t basis_elems(const CoarseGeom& c) { return (size_t)c.Nc * 2 * c.nvec * c.nhalf; }
+inline size_t basis_bytes(const CoarseGeom& c) { return basis_elems(c) * (16 + 8); }
+inline const double2* basis64(const void* b) { return static_cast<const double2*>(b); }
+inline double2* basis64(void* b) { return static_cast<double2*>(b); }
+inline const float2* basis32(const CoarseGeom& c, const void* b) {
+    return reinterpret_cast<const float2*>(static_cast<const char*>(b) + basis_elems(c) * 16);
+}
+inline float2* basis32(const CoarseGeom& c, void* b) {
+    return reinterpret_cast<float2*>(static_cast<char*>(b) + basis_elems(c) * 16);
+}
+
+// little Dirac operator storage (opaque): [a][d][k][j], column-major Nb x Nb
+// blocks (a wavefront lane owns a row j); BF16C packs (bf16 re, bf16 im) in 32 bits
+__host__ __device__ inline size_t coarse_elems(const CoarseGeom& c) { return (size_t)c.Nc * 9 * c.Nb * c.Nb; }
+size_t coarse_bytes(const CoarseGeom& c, hdcr_dtype dt);
+
+// --- kernels (coarse.hip) ---
+// raw chiral folds of the subspace vectors into the FP64 basis region
+void launch_basis_fold(const CoarseGeom& c, const double2* vecs, double2* b64, hipStream_t s);
+// per block and chirality: classical Gram-Schmidt applied twice, in index
+// order; rank_flag[0] is set to 1 if a vector is dependent (|w| <= 1e-12 |w0|)
+void launch_block_orth(const CoarseGeom& c, double2* b64, int* rank_flag, hipStream_t s);
+void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, hipStream_t s);
+// full fine fields of basis vectors k0 .. k0+nk-1 (k < nvec: + half, else - half), FP64
+void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk, double2* fields, hipStream_t s);
+
+// v[a][j] = <phi^a_j, psi - psi2>   (psi2 may be null)
+template <typename T>
+void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
+                     hipStream_t s);
+// psi = y + P v   (y may be null: psi = P v)
+template <typename T>
+void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
+                    hipStream_t s);
+
+// out[r][a] = sum_d A[a][d] v[r][a+d]  (C128 / C64 storage, column-major blocks)
+template <typename T>
+void launch_coarse_apply(const CoarseGeom& c, const C2<T>* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s);
+// BF16 storage with FP32 accumulation
+void launch_coarse_apply_bf16(const CoarseGeom& c, const uint16_t* A, const float2* v, float2* out, int nrhs,
+                              hipStream_t s);
+
+// little Dirac operator build: A64[a][d][k][j] for basis vectors in [k0, k0+nk)
+// given the class-split fine fields Y[(kk*9 + d)] = H^(d) Phi_{k0+kk}
+void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,
+                           hipStream_t s);
+// out = H^(cls) in: the terms of H whose hop class is cls (0 = diagonal, fifth
+// dimension and hops inside a block; 1+mu / 5+mu = forward / backward mu hops
+// that cross the block face)
+void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
+                         hipStream_t s);
+// A64 (column-major) -> other storage
+void launch_coarse_convert(const CoarseGeom& c, const double2* A64, hdcr_dtype dt, void* dst, hipStream_t s);
+// any storage -> logical A[a][d][j][k] complex double
+void launch_coarse_export(const CoarseGeom& c, hdcr_dtype dt, const void* A, double2* out, hipStream_t s);
+
+}  // namespace hdcr

@@ -1,0 +1,553 @@
+// Coarse space of the two-level method (Sec. 4) on gfx950: chiral split and
+// block orthonormalisation of the subspace vectors, restriction P^dag and
+// prolongation P, the little Dirac operator A = P^dag H P and its 9-point
+// coarse apply.  Layouts are described in coarse.h.
+#include <cmath>
+
+#include "coarse.h"
+
+namespace hdcr {
+
+namespace {
+
+constexpr int CWG = 256;
+constexpr double RSQRT2 = 0.70710678118654752440;
+
+// block-local site sl of coarse site a -> lexicographic 4d site index
+__device__ __forceinline__ int block_site(const CoarseGeom& c, int a, int sl) {
+    int x[4];
+    int r = sl;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        x[mu] = r % c.B[mu];
+        r /= c.B[mu];
+    }
+    x[3] = r;
+    int ca = a;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        x[mu] += (ca % c.C[mu]) * c.B[mu];
+        ca /= c.C[mu];
+    }
+    x[3] += ca * c.B[3];
+    return ((x[3] * c.f.L[2] + x[2]) * c.f.L[1] + x[1]) * c.f.L[0] + x[0];
+}
+
+// coarse neighbour a + d (coarse-periodic), d in D9 = (0,+x,+y,+z,+t,-x,-y,-z,-t)
+__device__ __forceinline__ int coarse_nbr(const CoarseGeom& c, int a, int d) {
+    if (d == 0) return a;
+    const int mu = (d - 1) & 3;
+    const int xm = (a / c.cstride[mu]) % c.C[mu];
+    if (d <= 4) return (xm == c.C[mu] - 1) ? a - (c.C[mu] - 1) * c.cstride[mu] : a + c.cstride[mu];
+    return (xm == 0) ? a + (c.C[mu] - 1) * c.cstride[mu] : a - c.cstride[mu];
+}
+
+template <typename T> __device__ __forceinline__ C2<T> shfl_xor_c(C2<T> v, int m) {
+    return mk<T>(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+
+// sum of v over the 256 work-items; every work-item gets the result.
+// sh must hold 4 * N entries.
+template <typename T, int N>
+__device__ __forceinline__ void wg_sum(C2<T> (&v)[N], C2<T>* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v[q] = cadd<T>(v[q], shfl_xor_c<T>(v[q], m));
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) sh[wave * N + q] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = cadd<T>(cadd<T>(sh[q], sh[N + q]), cadd<T>(sh[2 * N + q], sh[3 * N + q]));
+}
+
+// ---------------------------------------------------------------------------
+// basis construction
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(CWG) basis_fold_kernel(CoarseGeom c, const double2* __restrict__ vecs,
+                                                         double2* __restrict__ b64) {
+    const size_t total = (size_t)c.nvec * c.Nc * c.nhalf;
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < total; e += (size_t)gridDim.x * CWG) {
+        const int i = (int)(e % c.nhalf);
+        const size_t rest = e / c.nhalf;
+        const int a = (int)(rest % c.Nc);
+        const int k = (int)(rest / c.Nc);
+        const int s = i % c.Lh;
+        const int sl = (i / c.Lh) % c.bvol;
+        const int comp = i / (c.Lh * c.bvol);
+        const int site = block_site(c, a, sl);
+        const size_t fb = (((size_t)k * 12 + comp) * c.f.V4 + site) * c.f.Ls;
+        const double2 v1 = vecs[fb + s];
+        const double2 v2 = vecs[fb + c.f.Ls - 1 - s];
+        const double g = (comp < 6) ? 1.0 : -1.0;
+        // compressed sqrt(2) * (v +- Gamma5 v)/2 on s < Ls/2
+        const double2 wp = make_double2((v1.x + g * v2.x) * RSQRT2, (v1.y + g * v2.y) * RSQRT2);
+        const double2 wm = make_double2((v1.x - g * v2.x) * RSQRT2, (v1.y - g * v2.y) * RSQRT2);
+        b64[(((size_t)a * 2 + 0) * c.nvec + k) * c.nhalf + i] = wp;
+        b64[(((size_t)a * 2 + 1) * c.nvec + k) * c.nhalf + i] = wm;
+    }
+}
+
+// One workgroup per (block, chirality): the vectors are orthonormalised in
+// index order; each is projected against the previous ones in chunks of 8
+// (classical Gram-Schmidt inside a chunk), the projection is applied twice,
+// then the vector is normalised.  Every work-item owns the same indices i of
+// all vectors, so only the reductions cross work-items.
+constexpr int ORTH_CHUNK = 8;
+
+__global__ void __launch_bounds__(CWG) block_orth_kernel(CoarseGeom c, double2* __restrict__ b64,
+                                                         int* __restrict__ rank_flag) {
+    __shared__ double2 sh[4 * ORTH_CHUNK];
+    double2* base = b64 + (size_t)blockIdx.x * c.nvec * c.nhalf;
+    const int n = c.nhalf;
+    for (int k = 0; k < c.nvec; ++k) {
+        double2* w = base + (size_t)k * n;
+        double2 nn[1] = {make_double2(0, 0)};
+        for (int i = threadIdx.x; i < n; i += CWG) nn[0].x += w[i].x * w[i].x + w[i].y * w[i].y;
+        wg_sum<double, 1>(nn, sh);
+        const double n0 = nn[0].x;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j0 = 0; j0 < k; j0 += ORTH_CHUNK) {
+                const int jn = min(ORTH_CHUNK, k - j0);
+                double2 r[ORTH_CHUNK];
+#pragma unroll
+                for (int q = 0; q < ORTH_CHUNK; ++q) r[q] = make_double2(0, 0);
+                for (int i = threadIdx.x; i < n; i += CWG) {
+                    const double2 wi = w[i];
+#pragma unroll
+                    for (int q = 0; q < ORTH_CHUNK; ++q)
+                        if (q < jn) r[q] = cjfma<double>(base[(size_t)(j0 + q) * n + i], wi, r[q]);
+                }
+                wg_sum<double, ORTH_CHUNK>(r, sh);
+                for (int i = threadIdx.x; i < n; i += CWG) {
+                    double2 wi = w[i];
+#pragma unroll
+                    for (int q = 0; q < ORTH_CHUNK; ++q)
+                        if (q < jn) wi = cfma<double>(cneg<double>(r[q]), base[(size_t)(j0 + q) * n + i], wi);
+                    w[i] = wi;
+                }
+            }
+        }
+        nn[0] = make_double2(0, 0);
+        for (int i = threadIdx.x; i < n; i += CWG) nn[0].x += w[i].x * w[i].x + w[i].y * w[i].y;
+        wg_sum<double, 1>(nn, sh);
+        double nr = nn[0].x;
+        if (!(nr > 1e-24 * n0)) {
+            if (threadIdx.x == 0) rank_flag[0] = 1;
+            nr = 1.0;
+        }
+        const double inv = 1.0 / sqrt(nr);
+        for (int i = threadIdx.x; i < n; i += CWG) w[i] = make_double2(w[i].x * inv, w[i].y * inv);
+    }
+}
+
+__global__ void __launch_bounds__(CWG) basis_to_f32_kernel(size_t n, const double2* __restrict__ a,
+                                                           float2* __restrict__ b) {
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < n; e += (size_t)gridDim.x * CWG)
+        b[e] = make_float2((float)a[e].x, (float)a[e].y);
+}
+
+// fields[kk][comp][site][s] = basis vector k0+kk as a full fine field
+__global__ void __launch_bounds__(CWG) basis_expand_kernel(CoarseGeom c, const double2* __restrict__ b64, int k0,
+                                                           int nk, double2* __restrict__ fields) {
+    const size_t per = (size_t)12 * c.f.N5;
+    const size_t total = per * nk;
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < total; e += (size_t)gridDim.x * CWG) {
+        const int kk = (int)(e / per);
+        size_t r = e % per;
+        const int s = (int)(r % c.f.Ls);
+        r /= c.f.Ls;
+        const int site = (int)(r % c.f.V4);
+        const int comp = (int)(r / c.f.V4);
+        // coordinates -> block and block-local site
+        int x[4], t = site;
+        x[0] = t % c.f.L[0];
+        t /= c.f.L[0];
+        x[1] = t % c.f.L[1];
+        t /= c.f.L[1];
+        x[2] = t % c.f.L[2];
+        x[3] = t / c.f.L[2];
+        int a = 0, sl = 0;
+#pragma unroll
+        for (int mu = 3; mu >= 0; --mu) {
+            a = a * c.C[mu] + x[mu] / c.B[mu];
+            sl = sl * c.B[mu] + x[mu] % c.B[mu];
+        }
+        const int k = k0 + kk;
+        const int h = (k < c.nvec) ? 0 : 1;
+        const int kh = k - h * c.nvec;
+        const bool upper_s = s < c.Lh;
+        const int sc = upper_s ? s : c.f.Ls - 1 - s;
+        const int i = (comp * c.bvol + sl) * c.Lh + sc;
+        double2 v = b64[(((size_t)a * 2 + h) * c.nvec + kh) * c.nhalf + i];
+        double f = RSQRT2;
+        if (!upper_s) f *= (h == 0 ? 1.0 : -1.0) * (comp < 6 ? 1.0 : -1.0);
+        fields[e] = make_double2(v.x * f, v.y * f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// restriction and prolongation
+// ---------------------------------------------------------------------------
+
+template <typename T> struct RestrictChunk { static constexpr int KC = 16; };
+template <> struct RestrictChunk<double> { static constexpr int KC = 8; };
+
+// one workgroup per coarse site; each work-item strides over the compressed
+// indices and accumulates KC inner products per chirality, chunk by chunk
+template <typename T>
+__global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>* __restrict__ basis,
+                                                       const C2<T>* __restrict__ psi, const C2<T>* __restrict__ psi2,
+                                                       C2<T>* __restrict__ v) {
+    constexpr int KC = RestrictChunk<T>::KC;
+    __shared__ C2<T> sh[4 * 2 * KC];
+    const int a = blockIdx.x;
+    const C2<T>* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
+    const C2<T>* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
+    const T r2 = (T)RSQRT2;
+    for (int k0 = 0; k0 < c.nvec; k0 += KC) {
+        const int kn = min(KC, c.nvec - k0);
+        C2<T> acc[2 * KC];
+#pragma unroll
+        for (int q = 0; q < 2 * KC; ++q) acc[q] = mk<T>(0, 0);
+        for (int i = threadIdx.x; i < c.nhalf; i += CWG) {
+            const int s = i % c.Lh;
+            const int sl = (i / c.Lh) % c.bvol;
+            const int comp = i / (c.Lh * c.bvol);
+            const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
+            C2<T> p1 = psi[fb + s], p2 = psi[fb + c.f.Ls - 1 - s];
+            if (psi2) {
+                p1 = csub<T>(p1, psi2[fb + s]);
+                p2 = csub<T>(p2, psi2[fb + c.f.Ls - 1 - s]);
+            }
+            const T g = (comp < 6) ? (T)1 : (T)-1;
+            const C2<T> fp = mk<T>((p1.x + g * p2.x) * r2, (p1.y + g * p2.y) * r2);
+            const C2<T> fm = mk<T>((p1.x - g * p2.x) * r2, (p1.y - g * p2.y) * r2);
+#pragma unroll
+            for (int q = 0; q < KC; ++q) {
+                if (q < kn) {
+                    acc[q] = cjfma<T>(bp[(size_t)(k0 + q) * c.nhalf + i], fp, acc[q]);
+                    acc[KC + q] = cjfma<T>(bm[(size_t)(k0 + q) * c.nhalf + i], fm, acc[KC + q]);
+                }
+            }
+        }
+        wg_sum<T, 2 * KC>(acc, sh);
+        // static register indices (a runtime index would move acc to scratch)
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            if (threadIdx.x == q && q < kn) {
+                v[(size_t)a * c.Nb + k0 + q] = acc[q];
+                v[(size_t)a * c.Nb + c.nvec + k0 + q] = acc[KC + q];
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const C2<T>* __restrict__ basis,
+                                                      const C2<T>* __restrict__ v, const C2<T>* __restrict__ y,
+                                                      C2<T>* __restrict__ psi) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);
+    const int a = blockIdx.x;
+    for (int j = threadIdx.x; j < c.Nb; j += CWG) vs[j] = v[(size_t)a * c.Nb + j];
+    __syncthreads();
+    const C2<T>* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
+    const C2<T>* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
+    const T r2 = (T)RSQRT2;
+    for (int i = threadIdx.x; i < c.nhalf; i += CWG) {
+        C2<T> tp = mk<T>(0, 0), tm = mk<T>(0, 0);
+        for (int k = 0; k < c.nvec; ++k) {
+            tp = cfma<T>(bp[(size_t)k * c.nhalf + i], vs[k], tp);
+            tm = cfma<T>(bm[(size_t)k * c.nhalf + i], vs[c.nvec + k], tm);
+        }
+        const int s = i % c.Lh;
+        const int sl = (i / c.Lh) % c.bvol;
+        const int comp = i / (c.Lh * c.bvol);
+        const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
+        const T g = (comp < 6) ? (T)1 : (T)-1;
+        C2<T> o1 = mk<T>((tp.x + tm.x) * r2, (tp.y + tm.y) * r2);
+        C2<T> o2 = mk<T>(g * (tp.x - tm.x) * r2, g * (tp.y - tm.y) * r2);
+        if (y) {
+            o1 = cadd<T>(o1, y[fb + s]);
+            o2 = cadd<T>(o2, y[fb + c.f.Ls - 1 - s]);
+        }
+        psi[fb + s] = o1;
+        psi[fb + c.f.Ls - 1 - s] = o2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse apply (column-major blocks: A[a][d][k][j], a lane owns row j)
+// ---------------------------------------------------------------------------
+
+template <typename T, typename S> __device__ __forceinline__ C2<T> ldA(const S* A, size_t idx);
+template <> __device__ __forceinline__ double2 ldA<double, double2>(const double2* A, size_t idx) { return A[idx]; }
+template <> __device__ __forceinline__ float2 ldA<float, float2>(const float2* A, size_t idx) { return A[idx]; }
+template <> __device__ __forceinline__ float2 ldA<float, uint32_t>(const uint32_t* A, size_t idx) {
+    const uint32_t w = A[idx];  // (bf16 re, bf16 im)
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
+// one workgroup per (coarse site, right-hand side); wave w handles the
+// directions d = w, w+4, w+8; the neighbour vectors are staged in LDS
+template <typename T, typename S>
+__global__ void __launch_bounds__(CWG) coarse_apply_kernel(CoarseGeom c, const S* __restrict__ A,
+                                                           const C2<T>* __restrict__ v, C2<T>* __restrict__ out) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
+    C2<T>* part = vs + 9 * c.Nb;                       // [4][Nb]
+    const int a = blockIdx.x;
+    const int rhs = blockIdx.y;
+    const C2<T>* vr = v + (size_t)rhs * c.Nc * c.Nb;
+    for (int e = threadIdx.x; e < 9 * c.Nb; e += CWG) {
+        const int d = e / c.Nb, k = e - d * c.Nb;
+        vs[e] = vr[(size_t)coarse_nbr(c, a, d) * c.Nb + k];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < c.Nb; j0 += 64) {
+        const int j = j0 + lane;
+        C2<T> acc = mk<T>(0, 0);
+        if (j < c.Nb) {
+            for (int d = wave; d < 9; d += 4) {
+                const size_t base = ((size_t)a * 9 + d) * c.Nb * c.Nb + j;
+                const C2<T>* vd = vs + d * c.Nb;
+                for (int k = 0; k < c.Nb; ++k) acc = cfma<T>(ldA<T, S>(A, base + (size_t)k * c.Nb), vd[k], acc);
+            }
+            part[wave * c.Nb + j] = acc;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < c.Nb; j += CWG) {
+        const C2<T> r = cadd<T>(cadd<T>(part[j], part[c.Nb + j]), cadd<T>(part[2 * c.Nb + j], part[3 * c.Nb + j]));
+        out[((size_t)rhs * c.Nc + a) * c.Nb + j] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse build: projection of the class-split fields onto the block basis
+// ---------------------------------------------------------------------------
+
+// site sl of block-face class d: d = 0 -> all bvol sites; d = 1+mu -> local
+// x_mu = B_mu - 1; d = 5+mu -> local x_mu = 0 (f enumerates the face)
+__device__ __forceinline__ int class_site(const CoarseGeom& c, int d, int f) {
+    if (d == 0) return f;
+    const int mu = (d - 1) & 3;
+    const int fixed = (d <= 4) ? c.B[mu] - 1 : 0;
+    int x[4], r = f;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) {
+            x[nu] = fixed;
+        } else {
+            x[nu] = r % c.B[nu];
+            r /= c.B[nu];
+        }
+    }
+    return ((x[3] * c.B[2] + x[2]) * c.B[1] + x[1]) * c.B[0] + x[0];
+}
+
+constexpr int PROJ_NK = 8;     // basis vectors (columns) per launch
+constexpr int PROJ_CHUNK = 32; // compressed indices staged per step
+
+// grid (Nc, 9): the workgroup computes A64[a][d][k0+kk][j] for all j < Nb, kk < nk,
+// summing conj(phi^a_j) . (H^(d) Phi_k) over the sites of class d in block a
+__global__ void __launch_bounds__(CWG) coarse_project_kernel(CoarseGeom c, const double2* __restrict__ b64,
+                                                             const double2* __restrict__ Y, int k0, int nk,
+                                                             double2* __restrict__ A64) {
+    __shared__ double2 F[2][PROJ_NK][PROJ_CHUNK];  // chiral folds of the fields
+    const int a = blockIdx.x, d = blockIdx.y;
+    const int nsites = (d == 0) ? c.bvol : c.bvol / c.B[(d - 1) & 3];
+    const int nidx = 12 * nsites * c.Lh;
+    const size_t fsz = (size_t)12 * c.f.N5;
+    // work-item -> (row j, column group): 64 rows x 4 groups
+    const int jl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    double2 acc[2][PROJ_NK / 4];
+    for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < PROJ_NK / 4; ++q) acc[r][q] = make_double2(0, 0);
+    for (int i0 = 0; i0 < nidx; i0 += PROJ_CHUNK) {
+        // stage the folds of the chunk
+        for (int e = threadIdx.x; e < nk * PROJ_CHUNK; e += CWG) {
+            const int kk = e / PROJ_CHUNK, ii = e % PROJ_CHUNK;
+            const int idx = i0 + ii;
+            double2 fp = make_double2(0, 0), fm = make_double2(0, 0);
+            if (idx < nidx) {
+                const int s = idx % c.Lh;
+                const int f = (idx / c.Lh) % nsites;
+                const int comp = idx / (c.Lh * nsites);
+                const int site = block_site(c, a, class_site(c, d, f));
+                const size_t fb = (((size_t)kk * 9 + d) * fsz) + ((size_t)comp * c.f.V4 + site) * c.f.Ls;
+                const double2 p1 = Y[fb + s], p2 = Y[fb + c.f.Ls - 1 - s];
+                const double g = (comp < 6) ? 1.0 : -1.0;
+                fp = make_double2((p1.x + g * p2.x) * RSQRT2, (p1.y + g * p2.y) * RSQRT2);
+                fm = make_double2((p1.x - g * p2.x) * RSQRT2, (p1.y - g * p2.y) * RSQRT2);
+            }
+            F[0][kk][ii] = fp;
+            F[1][kk][ii] = fm;
+        }
+        __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            const int j = jl + 64 * r;
+            if (j < c.Nb) {
+                const int h = (j < c.nvec) ? 0 : 1;
+                const double2* bj = b64 + (((size_t)a * 2 + h) * c.nvec + (j - h * c.nvec)) * c.nhalf;
+                const int iend = min(PROJ_CHUNK, nidx - i0);
+                for (int ii = 0; ii < iend; ++ii) {
+                    const int idx = i0 + ii;
+                    const int s = idx % c.Lh;
+                    const int f = (idx / c.Lh) % nsites;
+                    const int comp = idx / (c.Lh * nsites);
+                    const double2 bv = bj[(comp * c.bvol + class_site(c, d, f)) * c.Lh + s];
+#pragma unroll
+                    for (int q = 0; q < PROJ_NK / 4; ++q) {
+                        const int kk = grp + 4 * q;
+                        if (kk < nk) acc[r][q] = cjfma<double>(bv, F[h][kk][ii], acc[r][q]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int r = 0; r < 2; ++r) {
+        const int j = jl + 64 * r;
+        if (j >= c.Nb) continue;
+#pragma unroll
+        for (int q = 0; q < PROJ_NK / 4; ++q) {
+            const int kk = grp + 4 * q;
+            if (kk < nk) A64[(((size_t)a * 9 + d) * c.Nb + (k0 + kk)) * c.Nb + j] = acc[r][q];
+        }
+    }
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void __launch_bounds__(CWG) coarse_convert_kernel(size_t n, const double2* __restrict__ A64, int dt,
+                                                             void* __restrict__ dst) {
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < n; e += (size_t)gridDim.x * CWG) {
+        const double2 v = A64[e];
+        if (dt == HDCR_C64) {
+            static_cast<float2*>(dst)[e] = make_float2((float)v.x, (float)v.y);
+        } else {
+            const uint32_t re = f32_to_bf16_rne((float)v.x), im = f32_to_bf16_rne((float)v.y);
+            static_cast<uint32_t*>(dst)[e] = re | (im << 16);
+        }
+    }
+}
+
+// logical out[a][d][j][k] from column-major storage [a][d][k][j]
+__global__ void __launch_bounds__(CWG) coarse_export_kernel(CoarseGeom c, int dt, const void* __restrict__ A,
+                                                            double2* __restrict__ out) {
+    const size_t n = coarse_elems(c);
+    const size_t nb2 = (size_t)c.Nb * c.Nb;
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < n; e += (size_t)gridDim.x * CWG) {
+        const size_t blk = e / nb2;
+        const int r = (int)(e % nb2);
+        const int j = r / c.Nb, k = r % c.Nb;
+        const size_t src = blk * nb2 + (size_t)k * c.Nb + j;
+        double2 v;
+        if (dt == HDCR_C128) {
+            v = static_cast<const double2*>(A)[src];
+        } else if (dt == HDCR_C64) {
+            const float2 f = static_cast<const float2*>(A)[src];
+            v = make_double2(f.x, f.y);
+        } else {
+            const float2 f = ldA<float, uint32_t>(static_cast<const uint32_t*>(A), src);
+            v = make_double2(f.x, f.y);
+        }
+        out[e] = v;
+    }
+}
+
+int grid_for(size_t n) {
+    size_t b = (n + CWG - 1) / CWG;
+    return (int)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
+}
+
+}  // namespace
+
+size_t coarse_bytes(const CoarseGeom& c, hdcr_dtype dt) {
+    return coarse_elems(c) * (dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4);
+}
+
+void launch_basis_fold(const CoarseGeom& c, const double2* vecs, double2* b64, hipStream_t s) {
+    const size_t total = (size_t)c.nvec * c.Nc * c.nhalf;
+    hipLaunchKernelGGL(basis_fold_kernel, dim3(grid_for(total)), dim3(CWG), 0, s, c, vecs, b64);
+}
+
+void launch_block_orth(const CoarseGeom& c, double2* b64, int* rank_flag, hipStream_t s) {
+    hipLaunchKernelGGL(block_orth_kernel, dim3(c.Nc * 2), dim3(CWG), 0, s, c, b64, rank_flag);
+}
+
+void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, hipStream_t s) {
+    const size_t n = basis_elems(c);
+    hipLaunchKernelGGL(basis_to_f32_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, n, b64, b32);
+}
+
+void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk, double2* fields, hipStream_t s) {
+    const size_t n = (size_t)12 * c.f.N5 * nk;
+    hipLaunchKernelGGL(basis_expand_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, c, b64, k0, nk, fields);
+}
+
+template <typename T>
+void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(c.Nc), dim3(CWG), 0, s, c, basis, psi, psi2, v);
+}
+
+template <typename T>
+void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(prolong_kernel<T>, dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v, y, psi);
+}
+
+template <typename T>
+void launch_coarse_apply(const CoarseGeom& c, const C2<T>* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL((coarse_apply_kernel<T, C2<T>>), dim3(c.Nc, nrhs), dim3(CWG), 13 * c.Nb * sizeof(C2<T>), s, c,
+                       A, v, out);
+}
+
+void launch_coarse_apply_bf16(const CoarseGeom& c, const uint16_t* A, const float2* v, float2* out, int nrhs,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((coarse_apply_kernel<float, uint32_t>), dim3(c.Nc, nrhs), dim3(CWG), 13 * c.Nb * sizeof(float2),
+                       s, c, reinterpret_cast<const uint32_t*>(A), v, out);
+}
+
+void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(coarse_project_kernel, dim3(c.Nc, 9), dim3(CWG), 0, s, c, b64, Y, k0, nk, A64);
+}
+
+void launch_coarse_convert(const CoarseGeom& c, const double2* A64, hdcr_dtype dt, void* dst, hipStream_t s) {
+    const size_t n = coarse_elems(c);
+    hipLaunchKernelGGL(coarse_convert_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, n, A64, (int)dt, dst);
+}
+
+void launch_coarse_export(const CoarseGeom& c, hdcr_dtype dt, const void* A, double2* out, hipStream_t s) {
+    hipLaunchKernelGGL(coarse_export_kernel, dim3(grid_for(coarse_elems(c))), dim3(CWG), 0, s, c, (int)dt, A, out);
+}
+
+template void launch_restrict<double>(const CoarseGeom&, const double2*, const double2*, const double2*, double2*,
+                                      hipStream_t);
+template void launch_restrict<float>(const CoarseGeom&, const float2*, const float2*, const float2*, float2*,
+                                     hipStream_t);
+template void launch_prolong<double>(const CoarseGeom&, const double2*, const double2*, const double2*, double2*,
+                                     hipStream_t);
+template void launch_prolong<float>(const CoarseGeom&, const float2*, const float2*, const float2*, float2*,
+                                    hipStream_t);
+template void launch_coarse_apply<double>(const CoarseGeom&, const double2*, const double2*, double2*, int,
+                                          hipStream_t);
+template void launch_coarse_apply<float>(const CoarseGeom&, const float2*, const float2*, float2*, int, hipStream_t);
+
+}  // namespace hdcr

@@ -28,7 +28,7 @@
 // so each hop multiplies a half spinor (2 spins x 3 colours) by the link.
 // The output is written at (x, Ls-1-s) with the lower spins negated:
 // H = gamma5 R5 D.
-#include "internal.h"
+#include "coarse.h"
 
 namespace hdcr {
 
@@ -38,6 +38,15 @@ constexpr int WG = 256;
 constexpr int MIN_SLOTS = 8;                 // work-items per site required by the LDS-link variant
 constexpr int MAX_WG_SITES = WG / MIN_SLOTS + 1;
 constexpr int LINK_STRIDE = 8 * 9 + 1;       // complex entries per staged site (padded against bank conflicts)
+
+// Hop-class selection used by the little-Dirac-operator build: cls = -1 keeps
+// every term; cls = 0 keeps the diagonal, the fifth-dimension hops and the 4d
+// hops that stay inside a block of extent B; cls = 1+mu (5+mu) keeps only the
+// forward (backward) mu hops that cross the block face.
+struct ClassSel {
+    int B[4];
+    int cls;
+};
 
 struct FieldRefs {
     __amdgpu_buffer_rsrc_t in, U, out;
@@ -199,9 +208,9 @@ __device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
     return tr;
 }
 
-template <typename T, int SPT, bool LDSL, int MU>
+template <typename T, int SPT, bool LDSL, bool CLS, int MU>
 __device__ __forceinline__ void hop_pair(const FineGeom& g, const FieldRefs& f, const Site& st, int s0,
-                                         const C2<T>* lnk, C2<T> (&acc)[SPT][12]) {
+                                         const C2<T>* lnk, const ClassSel& cs, C2<T> (&acc)[SPT][12]) {
     constexpr uint32_t CB = sizeof(C2<T>);
     const int site = st.site;
     const int xmu = st.x[MU];
@@ -211,8 +220,17 @@ __device__ __forceinline__ void hop_pair(const FineGeom& g, const FieldRefs& f, 
     const int sf = site + (wrap_f ? -g.wrap[MU] : g.stride[MU]);
     const int sb = site + (wrap_b ? g.wrap[MU] : -g.stride[MU]);
     const T half = (T)(-0.5);
-    const T cf = wrap_f ? half * (T)g.bc[MU] : half;
-    const T cb = wrap_b ? half * (T)g.bc[MU] : half;
+    T cf = wrap_f ? half * (T)g.bc[MU] : half;
+    T cb = wrap_b ? half * (T)g.bc[MU] : half;
+    if constexpr (CLS) {
+        // keep a hop only if its class is the selected one
+        const int lx = xmu % cs.B[MU];
+        const bool cross_f = (lx == cs.B[MU] - 1), cross_b = (lx == 0);
+        const bool keep_f = cross_f ? (cs.cls == 1 + MU) : (cs.cls == 0);
+        const bool keep_b = cross_b ? (cs.cls == 5 + MU) : (cs.cls == 0);
+        cf = keep_f ? cf : (T)0;
+        cb = keep_b ? cb : (T)0;
+    }
     C2<T> u[9];
     // forward: -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
     if constexpr (LDSL) {
@@ -236,8 +254,9 @@ __device__ __forceinline__ void hop_pair(const FineGeom& g, const FieldRefs& f, 
 
 // SPT: fifth-dimension slots per work-item; LDSL: links staged in LDS
 // (requires Ls / SPT >= MIN_SLOTS).
-template <typename T, int SPT, bool LDSL>
-__global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out) {
+template <typename T, int SPT, bool LDSL, bool CLS>
+__global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out,
+                                                        ClassSel cs) {
     constexpr uint32_t CB = sizeof(C2<T>);
     const int lb = logical_block(blockIdx.x, gridDim.x);
     const int slots = g.Ls / SPT;  // work-items per 4d site
@@ -280,12 +299,14 @@ __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>*
     // diagonal (5 - M5) and the fifth-dimension hops: -P+ psi(s-1) on the upper
     // spins, -P- psi(s+1) on the lower spins, +mf on the walls
     {
-        const T diag = (T)g.diag;
-        const T mf = (T)g.mf;
+        // the diagonal and fifth-dimension terms belong to hop class 0
+        const T keep = (!CLS || cs.cls == 0) ? (T)1 : (T)0;
+        const T diag = keep * (T)g.diag;
+        const T mf = keep * (T)g.mf;
         const int sm = (s0 == 0) ? Ls - 1 : s0 - 1;           // below the first slot
         const int sp = (s0 + SPT == Ls) ? 0 : s0 + SPT;        // above the last slot
-        const T cm = (s0 == 0) ? mf : (T)(-1);
-        const T cp = (s0 + SPT == Ls) ? mf : (T)(-1);
+        const T cm = (s0 == 0) ? mf : -keep;
+        const T cp = (s0 + SPT == Ls) ? mf : -keep;
         const uint32_t o0 = (uint32_t)(site * Ls + s0) * CB;
         const uint32_t om = (uint32_t)(site * Ls + sm) * CB;
         const uint32_t op = (uint32_t)(site * Ls + sp) * CB;
@@ -301,19 +322,19 @@ __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>*
                 T cw;
                 if (c < 6) {
                     nb = (k == 0) ? w : v[k > 0 ? k - 1 : 0];
-                    cw = (k == 0) ? cm : (T)(-1);
+                    cw = (k == 0) ? cm : -keep;
                 } else {
                     nb = (k == SPT - 1) ? w : v[k + 1 < SPT ? k + 1 : k];
-                    cw = (k == SPT - 1) ? cp : (T)(-1);
+                    cw = (k == SPT - 1) ? cp : -keep;
                 }
                 acc[k][c] = mk<T>(diag * v[k].x + cw * nb.x, diag * v[k].y + cw * nb.y);
             }
         }
     }
-    hop_pair<T, SPT, LDSL, 0>(g, f, st, s0, lnk, acc);
-    hop_pair<T, SPT, LDSL, 1>(g, f, st, s0, lnk, acc);
-    hop_pair<T, SPT, LDSL, 2>(g, f, st, s0, lnk, acc);
-    hop_pair<T, SPT, LDSL, 3>(g, f, st, s0, lnk, acc);
+    hop_pair<T, SPT, LDSL, CLS, 0>(g, f, st, s0, lnk, cs, acc);
+    hop_pair<T, SPT, LDSL, CLS, 1>(g, f, st, s0, lnk, cs, acc);
+    hop_pair<T, SPT, LDSL, CLS, 2>(g, f, st, s0, lnk, cs, acc);
+    hop_pair<T, SPT, LDSL, CLS, 3>(g, f, st, s0, lnk, cs, acc);
 
     // slot k (s = s0 + k) goes to s' = Ls - 1 - s0 - k: the SPT outputs are
     // consecutive, in reverse order, starting at Ls - s0 - SPT
@@ -327,11 +348,12 @@ __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>*
     }
 }
 
-template <typename T, int SPT, bool LDSL>
-void launch_variant(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+template <typename T, int SPT, bool LDSL, bool CLS = false>
+void launch_variant(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s,
+                    ClassSel cs = ClassSel{{1, 1, 1, 1}, -1}) {
     const int items = g.V4 * (g.Ls / SPT);
     const int blocks = (items + WG - 1) / WG;
-    hipLaunchKernelGGL((dslash_dwf_kernel<T, SPT, LDSL>), dim3(blocks), dim3(WG), 0, s, g, U, in, out);
+    hipLaunchKernelGGL((dslash_dwf_kernel<T, SPT, LDSL, CLS>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs);
 }
 
 }  // namespace
@@ -350,6 +372,14 @@ void launch_dslash(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
     } else {
         launch_variant<T, 1, false>(g, U, in, out, s);
     }
+}
+
+void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
+                         hipStream_t s) {
+    ClassSel cs;
+    for (int mu = 0; mu < 4; ++mu) cs.B[mu] = c.B[mu];
+    cs.cls = cls;
+    launch_variant<double, 1, false, true>(c.f, U, in, out, s, cs);
 }
 
 template void launch_dslash<double>(const FineGeom&, const double2*, const double2*, double2*, hipStream_t);

@@ -1,0 +1,127 @@
+"""GPU parity of the coarse space (Sec. 4) against the FP64 oracle, through the C-ABI:
+chirally split block basis, restriction/prolongation, little Dirac operator and coarse
+apply (FP64 1e-10; FP32 1e-5; BF16 storage 1e-2, its rounding error being 2^-9 per entry)."""
+import numpy as np
+import pytest
+
+import hdcr_inputs as hi
+import oracle
+import paper_1611_06944_amd as hd
+from tests.gpu_util import log, max_rel_elem, rel_err, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # L, Ls, block, nvec
+    ((4, 4, 4, 4), 4, (2, 2, 2, 2), 4),     # coarse 2^4: +mu and -mu blocks coincide
+    ((6, 4, 2, 6), 6, (2, 2, 2, 3), 3),     # coarse 3 x 2 x 1 x 2: extents 1, 2 and 3
+    ((2, 2, 2, 2), 4, (1, 1, 1, 1), 24),    # full rank: P unitary
+    ((8, 8, 8, 8), 8, (4, 4, 4, 4), 6),     # several workgroups, 4^4 blocks
+]
+
+
+def _setup(L, Ls, block, nvec, seed=1):
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.03)
+    cs = oracle.Coarse(p, block, nvec)
+    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.03, block=block, nvec=nvec)
+    U = hi.gauge_field(L, seed=seed)
+    vecs = [hi.gaussian_fermion(L, Ls, seed=100 + k) for k in range(nvec)]
+    return p, cs, lat, U, vecs
+
+
+def _dev_vecs(vecs):
+    return to_dev(np.stack([hd.pack_fermion(v) for v in vecs]))
+
+
+@pytest.mark.parametrize("L,Ls,block,nvec", CASES)
+def test_basis_and_coarse_build_parity(L, Ls, block, nvec):
+    torch = torch_dev()
+    log(f"coarse build L={L} Ls={Ls} block={block} nvec={nvec}")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    basis_ref, st = oracle.block_basis(vecs, cs)
+    assert st == 0
+    A_ref = oracle.coarse_build(U, basis_ref, cs)
+    Ud = to_dev(hd.pack_gauge(U))
+    basis, A = hd.build_coarse(lat, Ud, _dev_vecs(vecs), hd.C128)
+    fields = to_host(hd.export_basis(lat, basis))
+    got = np.stack([hd.unpack_fermion(f, L, Ls) for f in fields])
+    assert max_rel_elem(got, basis_ref) <= 1e-10
+    Ag = to_host(hd.export_coarse(lat, A, hd.C128))
+    assert max_rel_elem(Ag, A_ref) <= 1e-10
+    # reduced-precision storage
+    A64 = hd.convert_coarse(lat, A, hd.C64)
+    assert max_rel_elem(to_host(hd.export_coarse(lat, A64, hd.C64)), A_ref) <= 1e-6
+    Ab = hd.convert_coarse(lat, A, hd.BF16C)
+    assert max_rel_elem(to_host(hd.export_coarse(lat, Ab, hd.BF16C)), A_ref) <= 4e-3
+    # building straight into C64 storage agrees with the conversion
+    _, A2 = hd.build_coarse(lat, Ud, _dev_vecs(vecs), hd.C64)
+    assert torch.equal(A2, A64)
+
+
+@pytest.mark.parametrize("L,Ls,block,nvec", CASES[:2] + CASES[3:])
+def test_restrict_prolong_apply_parity(L, Ls, block, nvec):
+    torch = torch_dev()
+    log(f"restrict/prolong/apply L={L} Ls={Ls} block={block} nvec={nvec}")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    basis_ref, _ = oracle.block_basis(vecs, cs)
+    A_ref = oracle.coarse_build(U, basis_ref, cs)
+    basis, A = hd.build_coarse(lat, to_dev(hd.pack_gauge(U)), _dev_vecs(vecs), hd.C128)
+    psi = hi.gaussian_fermion(L, Ls, seed=7)
+    v = hi.gaussian_coarse(cs.nc, cs.nb, seed=8, nrhs=3)
+    r_ref = oracle.restrict(basis_ref, psi, cs)
+    pr_ref = oracle.prolong(basis_ref, v[0], cs)
+    ap_ref = oracle.coarse_apply(A_ref, v, cs.cdims)
+    for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+        psid = to_dev(hd.pack_fermion(psi), dt)
+        r = to_host(hd.restrict(lat, basis, psid))
+        assert max_rel_elem(r, r_ref) <= tol, dt
+        pr = hd.unpack_fermion(to_host(hd.prolong(lat, basis, to_dev(v[0], dt))), L, Ls)
+        assert max_rel_elem(pr, pr_ref) <= tol, dt
+    # coarse apply: C128, C64 and BF16 storage, three right-hand sides
+    out = to_host(hd.apply_coarse(lat, A, hd.C128, to_dev(v)))
+    assert max_rel_elem(out, ap_ref) <= 1e-10
+    A64 = hd.convert_coarse(lat, A, hd.C64)
+    out = to_host(hd.apply_coarse(lat, A64, hd.C64, to_dev(v, torch.complex64)))
+    assert max_rel_elem(out, ap_ref) <= 1e-5
+    Ab = hd.convert_coarse(lat, A, hd.BF16C)
+    out = to_host(hd.apply_coarse(lat, Ab, hd.BF16C, to_dev(v, torch.complex64)))
+    assert rel_err(out, ap_ref) <= 1e-2
+    # single right-hand side
+    out1 = to_host(hd.apply_coarse(lat, A, hd.C128, to_dev(v[1])))
+    assert max_rel_elem(out1, ap_ref[1]) <= 1e-10
+
+
+def test_rank_deficient_vectors():
+    torch_dev()
+    L, Ls, block, nvec = (2, 2, 2, 2), 4, (2, 2, 2, 2), 3
+    log("coarse build rank deficiency")
+    lat = hd.Lattice(L, Ls, block=block, nvec=nvec)
+    v0 = hi.gaussian_fermion(L, Ls, seed=1)
+    vecs = [v0, hi.gaussian_fermion(L, Ls, seed=2), 2.0 * v0]
+    U = to_dev(hd.pack_gauge(hi.gauge_field(L)))
+    code = hd.build_coarse_status(lat, U, _dev_vecs(vecs))
+    assert code == hd._abi.HDCR_ERANK
+
+
+def test_coarse_build_cfg2_scale():
+    """16^4 x 16, 4^4 blocks, 24 vectors (Nb = 48): the GPU little Dirac operator satisfies
+    the Galerkin identity A v = P^dag H P v (GPU kernels, FP64) and matches the oracle on
+    two full columns (all blocks, directions and rows)."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (16, 16, 16, 16), 16, (4, 4, 4, 4), 24
+    log(f"coarse build at L={L} Ls={Ls} nvec={nvec}")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    Ud = to_dev(hd.pack_gauge(U))
+    basis, A = hd.build_coarse(lat, Ud, _dev_vecs(vecs), hd.C128)
+    v = to_dev(hi.gaussian_coarse(cs.nc, cs.nb, seed=3))
+    Av = hd.apply_coarse(lat, A, hd.C128, v)
+    PHPv = hd.restrict(lat, basis, hd.apply_fine(lat, Ud, hd.prolong(lat, basis, v)))
+    assert rel_err(to_host(Av), to_host(PHPv)) <= 1e-12
+    # oracle columns k = 5 (+ chirality) and 30 (- chirality)
+    basis_ref, st = oracle.block_basis(vecs, cs)
+    assert st == 0
+    del vecs
+    cols = oracle.coarse_columns(U, basis_ref, cs, [5, 30])
+    Ag = to_host(hd.export_coarse(lat, A, hd.C128))
+    for c, k in enumerate([5, 30]):
+        assert max_rel_elem(Ag[:, :, :, k], cols[c]) <= 1e-10
