@@ -53,6 +53,8 @@
 extern "C" {
 #endif
 
+#define HDCR_API __attribute__((visibility("default")))
+
 #define HDCR_OK 0
 #define HDCR_EINVAL (-1)
 #define HDCR_EHIP (-2)
@@ -129,12 +131,12 @@ typedef struct hdcr_solve_stats {
     int32_t reserved;
 } hdcr_solve_stats;
 
-const char* hdcr_strerror(int code);
-const char* hdcr_last_error(void);
+HDCR_API const char* hdcr_strerror(int code);
+HDCR_API const char* hdcr_last_error(void);
 
 /* out = H psi with H = Gamma5 D_dwf (Sec. 3).  dtype C128 or C64; U, psi and
  * out in that precision.  One kernel launch on `stream`. */
-int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
+HDCR_API int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
                     hipStream_t stream);
 
 /* <x, y> = sum conj(x_i) y_i over n complex entries (C128 or C64 data, FP64
@@ -142,7 +144,7 @@ int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U,
  * the host.  work: device scratch of at least HDCR_DOT_WORK_BYTES bytes.
  * Synchronises `stream`. */
 #define HDCR_DOT_WORK_BYTES 32768
-int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work,
+HDCR_API int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work,
                  size_t work_bytes, hipStream_t stream);
 
 /* Scratch bytes needed by the calls below: which = HDCR_WS_SOLVE (hdcr_solve
@@ -154,12 +156,12 @@ int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, doub
 #define HDCR_WS_SUBSPACE 2
 #define HDCR_WS_SMOOTH 3
 #define HDCR_WS_VCYCLE 4
-size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
+HDCR_API size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
 
 /* Bytes of the opaque basis buffer (FP64 and FP32 copies of the chirally
  * compressed block basis) and of the little Dirac operator in `dtype`. */
-size_t hdcr_basis_bytes(const hdcr_coarse_desc* desc);
-size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype);
+HDCR_API size_t hdcr_basis_bytes(const hdcr_coarse_desc* desc);
+HDCR_API size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype);
 
 /* Coarse space (Sec. 4).  vecs: nvec fine fields (C128, [k][12][V4][Ls]), the
  * subspace vectors phi_k.  Each is split into its two Gamma5 = gamma5 R5
@@ -174,34 +176,67 @@ size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype);
  * FP64 and stored in A_dtype.  U in C128.  work: hdcr_workspace_bytes(
  * HDCR_WS_BUILD).  Synchronous; returns HDCR_ERANK if a block's vectors are
  * dependent (remaining norm below 1e-12 of the chiral projection's). */
-int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* vecs, void* basis, void* A,
+HDCR_API int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* vecs, void* basis, void* A,
                       hdcr_dtype A_dtype, void* work, size_t work_bytes, hipStream_t stream);
 
 /* A in C128 storage -> A in C64 or BF16C storage (round to nearest). */
-int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* A_dst,
+HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* A_dst,
                         hipStream_t stream);
 
 /* Read back the opaque buffers: A (any storage) as logical A[a][d][j][k]
  * complex double; the basis as Nb full fine fields (C128, [j][12][V4][Ls]),
  * field j holding phi^a_j on every block a. */
-int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, void* A_c128,
+HDCR_API int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, void* A_c128,
                        hipStream_t stream);
-int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields_c128, hipStream_t stream);
+HDCR_API int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields_c128, hipStream_t stream);
 
 /* Restriction v[a][j] = <phi^a_j, psi> (P^dag) and prolongation
  * psi(x) = sum_j phi^{b(x)}_j(x) v[b(x)][j] (P), in C128 or C64 (the basis copy
  * of that precision is used). */
-int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* psi, void* v,
+HDCR_API int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* psi, void* v,
                   hipStream_t stream);
-int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,
+HDCR_API int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,
                  hipStream_t stream);
 
 /* Coarse 9-point apply out[r][a] = sum_d A[a][d] v[r][a+d] (coarse-periodic;
  * the fine antiperiodic sign is inside A) for nrhs right-hand sides.  dtype is
  * A's storage; vectors are C128 for C128 storage, C64 otherwise (BF16C storage
  * accumulates in FP32). */
-int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, const void* v, void* out,
+HDCR_API int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, const void* v, void* out,
                       int32_t nrhs, hipStream_t stream);
+
+/* Chebyshev smoother (Sec. 4): out = p(H^2) H in, p the Chebyshev interpolant of
+ * 1/y on [lo, hi] with `order` terms (the paper: order 10 on [1, 64]), so that
+ * out ~ H^-1 in on the modes with lo <= lambda^2 <= hi.  dtype C128 or C64 (U, in
+ * and out in that precision).  work: hdcr_workspace_bytes(HDCR_WS_SMOOTH)
+ * (4 fields).  2*order - 1 applications of H. */
+HDCR_API int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int32_t order, double lo, double hi,
+                const void* in, void* out, void* work, size_t work_bytes, hipStream_t stream);
+
+/* One application of the symmetric two-level cycle (Sec. 4, M_outer):
+ *   e1 = S r;  e2 = e1 + Q (r - H e1);  e = e2 + S (r - H e2),  Q = P CR_A(P^dag .)
+ * with the smoother and coarse solve of params (coarse CR from 0 to
+ * coarse_tol, or exactly coarse_maxiter iterations when coarse_tol <= 0).
+ * r, e, U: C128; computed in params->inner_dtype.  work:
+ * hdcr_workspace_bytes(HDCR_WS_VCYCLE). */
+HDCR_API int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
+                const void* A, const void* r, void* e, void* work, size_t work_bytes, hipStream_t stream);
+
+/* Subspace generation (Sec. 4, Fig. 1): vecs[k] = T_degree(yhat) noise[k] / |.|
+ * with yhat = (2 H^2 - hi - lo)/(hi - lo): the Chebyshev low-pass filter that
+ * leaves the modes with lo <= lambda^2 <= hi bounded by 1 and amplifies those
+ * below lo.  noise, vecs: nvec C128 fields; U: C128; computed in dtype (C128 or
+ * C64).  work: hdcr_subspace_workspace_bytes().  Synchronous. */
+HDCR_API size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_dtype dtype);
+HDCR_API int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nvec, int32_t degree, double lo,
+                       double hi, const void* U, const void* noise, void* vecs, void* work, size_t work_bytes,
+                       hipStream_t stream);
+
+/* Power-iteration estimate of the largest eigenvalue of H^2 (Rayleigh quotient
+ * after `iters` steps from v0); C128.  work: hdcr_subspace_workspace_bytes(desc,
+ * HDCR_C128).  Synchronous. */
+HDCR_API int hdcr_power_max(const hdcr_fine_desc* desc, const void* U, const void* v0, int32_t iters, double* lam,
+                   void* work, size_t work_bytes, hipStream_t stream);
 
 /* Solve H x = b to |b - H x| <= tol |b| (x: initial guess in, solution out;
  * C128 fields; U in C128).  precond NONE ignores basis and A (may be NULL).
@@ -209,7 +244,7 @@ int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void
  * params->coarse_dtype).  history (host, may be NULL) receives up to
  * history_cap relative residual norms, one per outer iteration.  Returns 0 or
  * a positive status (stats->status holds the same).  Synchronous. */
-int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
+HDCR_API int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
                const void* A, const void* b, void* x, hdcr_solve_stats* stats, double* history, int32_t history_cap,
                void* work, size_t work_bytes, hipStream_t stream);
 

@@ -24,7 +24,7 @@ from ._abi import (BF16C, C64, C128, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL,
 
 __all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
-           "load", "HDCRError"]
+           "smooth", "vcycle", "make_subspace", "power_max", "load", "HDCRError"]
 
 load = _abi.load
 
@@ -327,3 +327,59 @@ def apply_coarse(lat: Lattice, A, A_dtype: int, v, out=None, stream=None):
     _abi.check(load().hdcr_apply_coarse(ctypes.byref(cd), int(A_dtype), _ptr(A), _ptr(v), _ptr(out), nrhs,
                                         _stream(stream)), "hdcr_apply_coarse")
     return out
+
+
+# ----------------------------------------------------------------------------
+# smoother, two-level cycle, subspace filter
+# ----------------------------------------------------------------------------
+
+def smooth(lat: Lattice, U, x, order=10, lo=1.0, hi=64.0, out=None, work=None, stream=None):
+    """out = p(H^2) H x (Chebyshev smoother); precision of x (U in the same precision)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    if work is None:
+        work = _workspace(workspace_bytes(_abi.WS_SMOOTH, lat), x.device)
+    d = lat.fine_desc()
+    _abi.check(load().hdcr_smooth(ctypes.byref(d), _dtype_code(x), _ptr(U), int(order), float(lo), float(hi), _ptr(x),
+                                  _ptr(out), _ptr(work), work.numel(), _stream(stream)), "hdcr_smooth")
+    return out
+
+
+def vcycle(lat: Lattice, U, basis, A, r, params: SolveParams, out=None, work=None, stream=None):
+    """One application of the two-level cycle to r (complex128)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(r)
+    if work is None:
+        work = _workspace(workspace_bytes(_abi.WS_VCYCLE, lat, params), r.device)
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_vcycle(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A), _ptr(r),
+                                  _ptr(out), _ptr(work), work.numel(), _stream(stream)), "hdcr_vcycle")
+    return out
+
+
+def make_subspace(lat: Lattice, U, noise, degree, lo, hi, dtype=C64, work=None, stream=None):
+    """Chebyshev-filtered, normalised vectors T_d(yhat) noise[k] (noise: complex128 [nvec, 12, V4, Ls])."""
+    torch = _torch()
+    lib = load()
+    d = lat.fine_desc()
+    out = torch.empty_like(noise)
+    if work is None:
+        work = _workspace(lib.hdcr_subspace_workspace_bytes(ctypes.byref(d), int(dtype)), noise.device)
+    _abi.check(lib.hdcr_make_subspace(ctypes.byref(d), int(dtype), int(noise.shape[0]), int(degree), float(lo),
+                                      float(hi), _ptr(U), _ptr(noise), _ptr(out), _ptr(work), work.numel(),
+                                      _stream(stream)), "hdcr_make_subspace")
+    return out
+
+
+def power_max(lat: Lattice, U, v0, iters=30, work=None, stream=None) -> float:
+    """Rayleigh-quotient estimate of the largest eigenvalue of H^2 by power iteration."""
+    lib = load()
+    d = lat.fine_desc()
+    if work is None:
+        work = _workspace(lib.hdcr_subspace_workspace_bytes(ctypes.byref(d), C128), v0.device)
+    lam = ctypes.c_double(0.0)
+    _abi.check(lib.hdcr_power_max(ctypes.byref(d), _ptr(U), _ptr(v0), int(iters), ctypes.byref(lam), _ptr(work),
+                                  work.numel(), _stream(stream)), "hdcr_power_max")
+    return lam.value

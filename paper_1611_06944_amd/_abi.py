@@ -75,6 +75,14 @@ PROTOTYPES = {
     "hdcr_restrict": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
     "hdcr_prolong": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
     "hdcr_apply_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _i32, _vp]),
+    "hdcr_smooth": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp,
+                                   _vp, _vp, _sz, _vp]),
+    "hdcr_vcycle": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _sz, _vp]),
+    "hdcr_subspace_workspace_bytes": (_sz, [ctypes.POINTER(FineDesc), _i32]),
+    "hdcr_make_subspace": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _i32, _i32, ctypes.c_double,
+                                          ctypes.c_double, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "hdcr_power_max": (ctypes.c_int, [ctypes.POINTER(FineDesc), _vp, _vp, _i32, _dbl_p, _vp, _sz, _vp]),
 }
 
 _lib = None

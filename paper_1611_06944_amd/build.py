@@ -21,7 +21,7 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-munsafe-fp-atomics",
+    "-ffp-contract=fast", "-fvisibility=hidden",
     "-I" + os.path.join(ROOT, "include"),
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]

@@ -4,8 +4,7 @@
 #include <cstring>
 #include <string>
 
-#include "coarse.h"
-#include "solver.h"
+#include "twolevel.h"
 
 namespace hdcr {
 
@@ -163,7 +162,16 @@ size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_
         case HDCR_WS_SOLVE:
             if (!params) return 0;
             if (params->precond == HDCR_PRECOND_NONE) return cr_workspace_bytes(g);
-            return 0;
+            if (check_coarse_desc(desc) || check_two_level_params(params)) return 0;
+            return two_level_workspace_bytes(make_coarse_geom(desc), params);
+        case HDCR_WS_VCYCLE:
+            if (!params || check_coarse_desc(desc) || check_two_level_params(params)) return 0;
+            return vcycle_workspace_bytes(make_coarse_geom(desc), params);
+        case HDCR_WS_SMOOTH:
+            return (size_t)4 * 12 * g.N5 * 16 + 4 * 256;
+        case HDCR_WS_SUBSPACE:
+            return hdcr_subspace_workspace_bytes(&desc->fine, (params && params->inner_dtype == HDCR_C64) ? HDCR_C64
+                                                                                                         : HDCR_C128);
         case HDCR_WS_BUILD:
             if (check_coarse_desc(desc)) return 0;
             return build_workspace_bytes(make_coarse_geom(desc));
@@ -191,9 +199,14 @@ int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, co
         return cr_solve(g, params, (const double2*)U, (const double2*)b, (double2*)x, stats, history, history_cap,
                         work, work_bytes, stream);
     }
-    (void)basis;
-    (void)A;
-    return fail(HDCR_EINVAL, "hdcr_solve: unknown precond");
+    if (params->precond != HDCR_PRECOND_TWO_LEVEL) return fail(HDCR_EINVAL, "hdcr_solve: unknown precond");
+    if ((e = check_coarse_desc(desc))) return e;
+    if ((e = check_two_level_params(params))) return e;
+    if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(A, 4, "A"))) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (work_bytes < two_level_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_solve: workspace too small");
+    return two_level_solve(c, params, (const double2*)U, basis, A, (const double2*)b, (double2*)x, stats, history,
+                           history_cap, work, work_bytes, stream);
 }
 
 }  // extern "C"

@@ -76,6 +76,31 @@ void launch_coarse_apply(const CoarseGeom& c, const C2<T>* A, const C2<T>* v, C2
 void launch_coarse_apply_bf16(const CoarseGeom& c, const uint16_t* A, const float2* v, float2* out, int nrhs,
                               hipStream_t s);
 
+// Coarse conjugate residual (the subspace inverse by a Krylov method, Sec. 4)
+// with device-resident scalars: every kernel reads a done flag and returns at
+// once when it is set, so a batch of iterations can be enqueued without
+// synchronising; reductions finish in the last-arriving workgroup in a fixed
+// order (reproducible).
+template <typename T> struct CoarseCRWork {
+    C2<T>* r;
+    C2<T>* p;
+    C2<T>* Ar;
+    C2<T>* Ap;
+    double* part;   // partial sums, 2 * max(Nc, CCR_BLOCKS) entries
+    double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
+    int* flags;     // 0 done, 1 iterations, 2 arrival counter, 3 maxiter
+};
+constexpr int CCR_BLOCKS = 64;
+// r = b, x = 0, |b|^2; resets the iteration state
+template <typename T>
+void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,
+                     hipStream_t s);
+// one CR iteration (x, r update; Ar = A r; p, Ap update); first = true issues
+// the start-up step (p = r, Ap = A r) instead
+template <typename T>
+void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
+                     bool first, hipStream_t s);
+
 // little Dirac operator build: A64[a][d][k][j] for basis vectors in [k0, k0+nk)
 // given the class-split fine fields Y[(kk*9 + d)] = H^(d) Phi_{k0+kk}
 void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,

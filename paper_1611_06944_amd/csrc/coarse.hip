@@ -332,6 +332,212 @@ __global__ void __launch_bounds__(CWG) coarse_apply_kernel(CoarseGeom c, const S
 }
 
 // ---------------------------------------------------------------------------
+// coarse conjugate residual
+// ---------------------------------------------------------------------------
+
+// After every workgroup has stored its partial sums, true in the workgroup
+// that arrived last (which then reduces them in a fixed order).
+__device__ __forceinline__ bool last_arrival(int* counter) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)(gridDim.x * gridDim.y) - 1);
+    __syncthreads();
+    return is_last != 0;
+}
+
+// fixed-order sum of nq rows of np partials (row q at part + q*np), in the last block
+template <int NQ>
+__device__ __forceinline__ void reduce_partials(const double* part, int np, double (&out)[NQ]) {
+    __threadfence();
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] += __builtin_nontemporal_load(part + (size_t)q * np + i);
+    }
+    block_reduce<NQ>(v);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = v[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __restrict__ b, C2<T>* __restrict__ x,
+                                                       C2<T>* __restrict__ r, double* part, double* cs, int* flags,
+                                                       int maxiter, double tol2) {
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
+        const C2<T> bv = b[i];
+        r[i] = bv;
+        x[i] = mk<T>(0, 0);
+        v[0] += (double)bv.x * bv.x + (double)bv.y * bv.y;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (last_arrival(flags + 2)) {
+        double s[1];
+        reduce_partials<1>(part, gridDim.x, s);
+        if (threadIdx.x == 0) {
+            cs[4] = s[0];
+            cs[3] = s[0];
+            cs[5] = tol2;
+            flags[3] = maxiter;
+            flags[1] = 0;
+            flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0])) ? 1 : 0;
+            flags[2] = 0;
+        }
+    }
+}
+
+// Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar and
+// the sums <r,Ar>, |Ar|^2; else the sum <r,Ar> (the new value)
+template <typename T, typename S, bool FIRST>
+__global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* __restrict__ A,
+                                                        const C2<T>* __restrict__ r, C2<T>* __restrict__ Ar,
+                                                        C2<T>* __restrict__ p, C2<T>* __restrict__ Ap, double* part,
+                                                        double* cs, int* flags) {
+    if (flags[0]) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
+    C2<T>* prt = vs + 9 * c.Nb;                        // [4][Nb]
+    const int a = blockIdx.x;
+    for (int e = threadIdx.x; e < 9 * c.Nb; e += CWG) {
+        const int d = e / c.Nb, k = e - d * c.Nb;
+        vs[e] = r[(size_t)coarse_nbr(c, a, d) * c.Nb + k];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < c.Nb; j0 += 64) {
+        const int j = j0 + lane;
+        C2<T> acc = mk<T>(0, 0);
+        if (j < c.Nb) {
+            for (int d = wave; d < 9; d += 4) {
+                const size_t base = ((size_t)a * 9 + d) * c.Nb * c.Nb + j;
+                const C2<T>* vd = vs + d * c.Nb;
+                for (int k = 0; k < c.Nb; ++k) acc = cfma<T>(ldA<T, S>(A, base + (size_t)k * c.Nb), vd[k], acc);
+            }
+            prt[wave * c.Nb + j] = acc;
+        }
+    }
+    __syncthreads();
+    double sums[2] = {0.0, 0.0};
+    for (int j = threadIdx.x; j < c.Nb; j += CWG) {
+        const C2<T> o = cadd<T>(cadd<T>(prt[j], prt[c.Nb + j]), cadd<T>(prt[2 * c.Nb + j], prt[3 * c.Nb + j]));
+        const size_t idx = (size_t)a * c.Nb + j;
+        Ar[idx] = o;
+        const C2<T> rv = vs[j];  // d = 0 slot holds r(a)
+        if (FIRST) {
+            p[idx] = rv;
+            Ap[idx] = o;
+        }
+        sums[0] += (double)rv.x * o.x + (double)rv.y * o.y;
+        sums[1] += (double)o.x * o.x + (double)o.y * o.y;
+    }
+    block_reduce<2>(sums);
+    if (threadIdx.x == 0) {
+        part[a] = sums[0];
+        part[c.Nc + a] = sums[1];
+    }
+    if (last_arrival(flags + 2)) {
+        double t[2];
+        reduce_partials<2>(part, c.Nc, t);
+        if (threadIdx.x == 0) {
+            if (FIRST) {
+                cs[0] = t[0];
+                cs[2] = t[1];
+            } else {
+                cs[1] = t[0];
+            }
+            if (!(fabs(t[0]) > 0.0) || !isfinite(t[0])) flags[0] = 1;  // breakdown ends the coarse solve
+            flags[2] = 0;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha Ap with alpha = <r,Ar>/|Ap|^2; |r|^2, convergence test
+template <typename T>
+__global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __restrict__ x, C2<T>* __restrict__ r,
+                                                            const C2<T>* __restrict__ p, const C2<T>* __restrict__ Ap,
+                                                            double* part, double* cs, int* flags) {
+    if (flags[0]) return;
+    const T alpha = (T)(cs[0] / cs[2]);
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
+        C2<T> xv = x[i], rv = r[i];
+        const C2<T> pv = p[i], apv = Ap[i];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        rv.x -= alpha * apv.x;
+        rv.y -= alpha * apv.y;
+        x[i] = xv;
+        r[i] = rv;
+        v[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (last_arrival(flags + 2)) {
+        double s[1];
+        reduce_partials<1>(part, gridDim.x, s);
+        if (threadIdx.x == 0) {
+            cs[3] = s[0];
+            const int it = flags[1] + 1;
+            flags[1] = it;
+            if (s[0] <= cs[5] * cs[4] || it >= flags[3] || !isfinite(s[0])) flags[0] = 1;
+            flags[2] = 0;
+        }
+    }
+}
+
+// p = r + beta p; Ap = Ar + beta Ap with beta = <r,Ar>_new/<r,Ar>; |Ap|^2
+template <typename T>
+__global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* __restrict__ r, C2<T>* __restrict__ p,
+                                                           const C2<T>* __restrict__ Ar, C2<T>* __restrict__ Ap,
+                                                           double* part, double* cs, int* flags) {
+    if (flags[0]) return;
+    const T beta = (T)(cs[1] / cs[0]);
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
+        C2<T> pv = p[i], apv = Ap[i];
+        const C2<T> rv = r[i], arv = Ar[i];
+        pv.x = rv.x + beta * pv.x;
+        pv.y = rv.y + beta * pv.y;
+        apv.x = arv.x + beta * apv.x;
+        apv.y = arv.y + beta * apv.y;
+        p[i] = pv;
+        Ap[i] = apv;
+        v[0] += (double)apv.x * apv.x + (double)apv.y * apv.y;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    if (last_arrival(flags + 2)) {
+        double s[1];
+        reduce_partials<1>(part, gridDim.x, s);
+        if (threadIdx.x == 0) {
+            cs[2] = s[0];
+            cs[0] = cs[1];
+            flags[2] = 0;
+        }
+    }
+}
+
+// coarse vectors are FP64 with C128 storage and FP32 with C64 / BF16 storage
+template <typename T, bool FIRST>
+void ccr_apply_dispatch(const CoarseGeom& c, hdcr_dtype dt, const void* A, const CoarseCRWork<T>& w, hipStream_t s) {
+    const size_t lds = 13 * c.Nb * sizeof(C2<T>);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((ccr_apply_kernel<T, double2, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
+                           static_cast<const double2*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+    } else if (dt == HDCR_C64) {
+        hipLaunchKernelGGL((ccr_apply_kernel<T, float2, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
+                           static_cast<const float2*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+    } else {
+        hipLaunchKernelGGL((ccr_apply_kernel<T, uint32_t, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
+                           static_cast<const uint32_t*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // coarse build: projection of the class-split fields onto the block basis
 // ---------------------------------------------------------------------------
 
@@ -476,6 +682,38 @@ int grid_for(size_t n) {
 }
 
 }  // namespace
+
+template <typename T>
+void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,
+                     hipStream_t s) {
+    const double tol2 = tol > 0 ? tol * tol : 0.0;
+    hipLaunchKernelGGL(ccr_init_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, c.Nc * c.Nb, b, x, w.r, w.part, w.cs,
+                       w.flags, maxiter, tol2);
+}
+
+template <typename T>
+void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
+                     bool first, hipStream_t s) {
+    const int n = c.Nc * c.Nb;
+    if (first) {
+        ccr_apply_dispatch<T, true>(c, A_dtype, A, w, s);
+        return;
+    }
+    hipLaunchKernelGGL(ccr_update_xr_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, x, w.r, w.p, w.Ap, w.part, w.cs,
+                       w.flags);
+    ccr_apply_dispatch<T, false>(c, A_dtype, A, w, s);
+    hipLaunchKernelGGL(ccr_update_p_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, w.r, w.p, w.Ar, w.Ap, w.part,
+                       w.cs, w.flags);
+}
+
+template void launch_ccr_init<double>(const CoarseGeom&, const double2*, double2*, const CoarseCRWork<double>&, int,
+                                      double, hipStream_t);
+template void launch_ccr_init<float>(const CoarseGeom&, const float2*, float2*, const CoarseCRWork<float>&, int,
+                                     double, hipStream_t);
+template void launch_ccr_step<double>(const CoarseGeom&, hdcr_dtype, const void*, double2*,
+                                      const CoarseCRWork<double>&, bool, hipStream_t);
+template void launch_ccr_step<float>(const CoarseGeom&, hdcr_dtype, const void*, float2*, const CoarseCRWork<float>&,
+                                     bool, hipStream_t);
 
 size_t coarse_bytes(const CoarseGeom& c, hdcr_dtype dt) {
     return coarse_elems(c) * (dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4);

@@ -1,0 +1,716 @@
+// Two-level HDCR solve (Sec. 4) on gfx950: coarse conjugate residual, the
+// Chebyshev smoother, the symmetric two-level cycle, flexible GCR in FP64,
+// the Chebyshev low-pass subspace filter and a power-iteration estimate of the
+// top of the H^2 spectrum.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "twolevel.h"
+
+namespace hdcr {
+
+// ---------------------------------------------------------------------------
+// phase timer (HIP events on the solve's stream)
+// ---------------------------------------------------------------------------
+hipEvent_t PhaseTimer::get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+        e = pool.back();
+        pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+void PhaseTimer::begin(int phase) {
+    if (!on) return;
+    if (open_phase == phase) return;
+    end();
+    open_ev = get();
+    if (open_ev) (void)hipEventRecord(open_ev, s);
+    open_phase = phase;
+}
+void PhaseTimer::end() {
+    if (!on || open_phase < 0) return;
+    hipEvent_t b = get();
+    if (b && open_ev) {
+        (void)hipEventRecord(b, s);
+        recs.push_back({open_ev, b, open_phase});
+    }
+    open_phase = -1;
+    open_ev = nullptr;
+}
+void PhaseTimer::totals(double out[3]) {
+    out[0] = out[1] = out[2] = 0.0;
+    for (auto& r : recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) out[r.phase] += ms * 1e-3;
+    }
+}
+PhaseTimer::~PhaseTimer() {
+    for (auto& r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    if (open_ev) (void)hipEventDestroy(open_ev);
+}
+
+// ---------------------------------------------------------------------------
+// coarse CR driver
+// ---------------------------------------------------------------------------
+template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeom& c) {
+    const size_t n = (size_t)c.Nc * c.Nb;
+    CoarseCRWork<T> k;
+    k.r = w.take<C2<T>>(n);
+    k.p = w.take<C2<T>>(n);
+    k.Ar = w.take<C2<T>>(n);
+    k.Ap = w.take<C2<T>>(n);
+    k.part = w.take<double>(2 * (size_t)std::max(c.Nc, CCR_BLOCKS));
+    k.cs = w.take<double>(8);
+    k.flags = w.take<int>(8);
+    return k;
+}
+template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
+    Carver w(nullptr, 0);
+    coarse_cr_carve<T>(w, c);
+    return w.used();
+}
+
+template <typename T>
+int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T>* b, C2<T>* x, int maxiter,
+              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters) {
+    launch_ccr_init<T>(c, b, x, w, maxiter, tol, s);
+    launch_ccr_step<T>(c, A_dtype, A, x, w, true, s);
+    if (tol <= 0) {
+        for (int i = 0; i < maxiter; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
+        if (iters) *iters = maxiter;
+        HDCR_HIP_CHECK(hipGetLastError());
+        return HDCR_OK;
+    }
+    // enqueue a batch sized by the previous solve, then check the device flag
+    int enq = 0;
+    int batch = std::max(4, std::min(hint > 0 ? hint + 2 : 16, maxiter));
+    int hf[2] = {0, 0};
+    while (enq < maxiter) {
+        const int nb = std::min(batch, maxiter - enq);
+        for (int i = 0; i < nb; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
+        enq += nb;
+        HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HDCR_HIP_CHECK(hipStreamSynchronize(s));
+        if (hf[0]) break;
+        batch = 8;
+    }
+    if (iters) *iters = hf[1];
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev smoother
+// ---------------------------------------------------------------------------
+void cheby_coeffs(int n, double lo, double hi, double* c) {
+    // interpolant of 1/y at the n Chebyshev points of [lo, hi]:
+    // p(y) = sum_j c_j T_j(yhat) - c_0/2,  yhat = (2y - hi - lo)/(hi - lo)
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double th = pi * (k + 0.5) / n;
+            const double y = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos(th);
+            s += std::cos(j * th) / y;
+        }
+        c[j] = 2.0 * s / n;
+    }
+}
+
+template <typename T>
+void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* acc, C2<T>* const tmp[4], int order,
+                   double lo, double hi, hipStream_t s) {
+    const int64_t n = 12LL * g.N5;
+    std::vector<double> c(order);
+    cheby_coeffs(order, lo, hi, c.data());
+    C2<T>* T0 = tmp[0];
+    C2<T>* T1 = tmp[1];
+    C2<T>* V = tmp[2];
+    C2<T>* W = tmp[3];
+    // u = H in, acc = (c0 / 2) u
+    launch_dslash<T>(g, U, in, T0, s);
+    launch_scale<T>(n, (T)(0.5 * c[0]), T0, acc, s);
+    if (order < 2) return;
+    // T1 = yhat u = (2 H^2 u - (hi + lo) u) / (hi - lo)
+    const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
+    launch_dslash<T>(g, U, T0, V, s);
+    launch_dslash<T>(g, U, V, W, s);
+    launch_axpby<T>(n, (T)b1, T0, (T)a1, W, s);   // W = b1 T0 + a1 W
+    std::swap(T1, W);
+    launch_axpby<T>(n, (T)c[1], T1, (T)1, acc, s);
+    // T_{j+1} = 2 yhat T_j - T_{j-1}
+    const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
+    for (int j = 2; j < order; ++j) {
+        launch_dslash<T>(g, U, T1, V, s);
+        launch_dslash<T>(g, U, V, W, s);
+        launch_cheb_step<T>(n, (T)a2, W, (T)b2, T1, T0, (T)c[j], acc, s);
+        std::swap(T0, T1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// two-level cycle
+// ---------------------------------------------------------------------------
+template <typename T> struct CycleWork {
+    C2<T>* t;
+    C2<T>* d;
+    C2<T>* s2;
+    C2<T>* sm[4];
+    C2<T>* vc;
+    C2<T>* cx;
+    CoarseCRWork<T> ccr;
+};
+template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
+    const size_t n = (size_t)12 * c.f.N5;
+    CycleWork<T> k;
+    k.t = w.take<C2<T>>(n);
+    k.d = w.take<C2<T>>(n);
+    k.s2 = w.take<C2<T>>(n);
+    for (int i = 0; i < 4; ++i) k.sm[i] = w.take<C2<T>>(n);
+    k.vc = w.take<C2<T>>((size_t)c.Nc * c.Nb);
+    k.cx = w.take<C2<T>>((size_t)c.Nc * c.Nb);
+    k.ccr = coarse_cr_carve<T>(w, c);
+    return k;
+}
+
+struct CycleCounts {
+    int64_t fine = 0, coarse_iters = 0, coarse_applies = 0;
+    int last_coarse = 0;
+};
+
+// e = B r:  e1 = S r;  e2 = e1 + Q (r - H e1);  e = e2 + S (r - H e2),  Q = P A^-1 P^dag
+template <typename T>
+int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, const C2<T>* basis, const void* A,
+           const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm, CycleCounts& cnt, hipStream_t s) {
+    const FineGeom& g = c.f;
+    const int64_t n = 12LL * g.N5;
+    const int order = prm->cheb_order;
+    tm.begin(PhaseTimer::FINE);
+    cheb_smoother<T>(g, U, r, e, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    launch_dslash<T>(g, U, e, w.t, s);
+    tm.begin(PhaseTimer::COARSE);
+    launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+    int it = 0;
+    int st = coarse_cr<T>(c, (hdcr_dtype)prm->coarse_dtype, A, w.vc, w.cx, prm->coarse_maxiter, prm->coarse_tol, w.ccr,
+                          cnt.last_coarse, s, &it);
+    if (st) return st;
+    cnt.last_coarse = it;
+    cnt.coarse_iters += it;
+    cnt.coarse_applies += it + 1;
+    launch_prolong<T>(c, basis, w.cx, e, e, s);
+    tm.begin(PhaseTimer::FINE);
+    launch_dslash<T>(g, U, e, w.t, s);
+    launch_sub<T>(n, r, w.t, w.d, s);
+    cheb_smoother<T>(g, U, w.d, w.s2, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    launch_axpby<T>(n, (T)1, w.s2, (T)1, e, s);
+    cnt.fine += 2 * (2 * order - 1) + 2;
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// flexible GCR (FP64 outer iteration) preconditioned with the two-level cycle
+// ---------------------------------------------------------------------------
+template <typename T> struct FgcrWork {
+    double2* Z[MAXV];
+    double2* W[MAXV];
+    double2* r;
+    double2* tmp;
+    double* part;
+    double* S;        // device scalars: D1 [0,17), D2 [17,34), D3 [34,51), rr 51, bb 52
+    C2<T>* U_in;      // inner-precision links (FP32 copy, or null for FP64)
+    C2<T>* r_in;
+    C2<T>* e_in;
+    CycleWork<T> cyc;
+};
+constexpr int SD1 = 0, SD2 = 2 * MAXV + 1, SD3 = 2 * (2 * MAXV + 1), SRR = 3 * (2 * MAXV + 1), SBB = SRR + 1,
+              SCOUNT = SBB + 8;
+
+template <typename T> FgcrWork<T> fgcr_carve(Carver& w, const CoarseGeom& c, int m) {
+    const size_t n = (size_t)12 * c.f.N5;
+    FgcrWork<T> k;
+    for (int i = 0; i < MAXV; ++i) {
+        k.Z[i] = (i < m) ? w.take<double2>(n) : nullptr;
+        k.W[i] = (i < m) ? w.take<double2>(n) : nullptr;
+    }
+    k.r = w.take<double2>(n);
+    k.tmp = w.take<double2>(n);
+    k.part = w.take<double>((size_t)(2 * MAXV + 1) * REDUCE_BLOCKS);
+    k.S = w.take<double>(SCOUNT);
+    if (sizeof(T) == 4) {
+        k.U_in = w.take<C2<T>>((size_t)36 * c.f.V4);
+        k.r_in = w.take<C2<T>>(n);
+        k.e_in = w.take<C2<T>>(n);
+    } else {
+        k.U_in = nullptr;
+        k.r_in = nullptr;
+        k.e_in = nullptr;
+    }
+    k.cyc = cycle_carve<T>(w, c);
+    return k;
+}
+
+template <typename T> size_t fgcr_bytes(const CoarseGeom& c, int m) {
+    Carver w(nullptr, 0);
+    fgcr_carve<T>(w, c, m);
+    return w.used();
+}
+
+template <typename T>
+int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2* U, const void* basis, const void* A,
+               const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap, void* work,
+               size_t work_bytes, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const FineGeom& g = c.f;
+    const int64_t n = 12LL * g.N5;
+    const int m = prm->restart;
+    Carver cw(work, work_bytes);
+    FgcrWork<T> w = fgcr_carve<T>(cw, c, m);
+    if (!cw.ok()) return fail(HDCR_ENOMEM, "hdcr_solve: workspace too small for the two-level solve");
+    PhaseTimer tm;
+    tm.s = s;
+    tm.on = true;
+    CycleCounts cnt;
+    int64_t n64 = 0;  // FP64 fine applications
+
+    const C2<T>* Uin;
+    const C2<T>* bas;
+    if constexpr (sizeof(T) == 4) {
+        launch_convert<double2, float2>(36LL * g.V4, U, w.U_in, s);
+        Uin = w.U_in;
+        bas = basis32(c, basis);
+    } else {
+        Uin = U;
+        bas = basis64(basis);
+    }
+    HDCR_HIP_CHECK(hipMemsetAsync(w.cyc.ccr.flags, 0, 8 * sizeof(int), s));
+
+    double hS[SCOUNT];
+    auto readS = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(hS, w.S, sizeof(hS), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    };
+    // |b|^2 and r = b - H x
+    tm.begin(PhaseTimer::OUTER);
+    launch_norm2<double>(n, b, w.part, w.S, SBB, s);
+    launch_dslash<double>(g, U, x, w.tmp, s);
+    ++n64;
+    launch_sub<double>(n, b, w.tmp, w.r, s);
+    launch_norm2<double>(n, w.r, w.part, w.S, SRR, s);
+    tm.end();
+    HDCR_HIP_CHECK(readS());
+    const double bb = hS[SBB];
+    double rr = hS[SRR];
+    const double tol2 = prm->tol * prm->tol * bb;
+    int status = HDCR_ENOTCONV;
+    int it = 0, hl = 0;
+    if (bb == 0.0) {
+        HDCR_HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double2), s));
+        status = HDCR_OK;
+        rr = 0.0;
+    } else if (!std::isfinite(bb) || !std::isfinite(rr)) {
+        status = HDCR_ENAN;
+    } else if (rr <= tol2) {
+        status = HDCR_OK;
+    }
+    typedef std::complex<double> cd;
+    while (status == HDCR_ENOTCONV && it < prm->maxiter) {
+        // coefficient of the normalised directions zhat_i over the raw Z_j
+        std::vector<std::vector<cd>> coef;
+        std::vector<cd> alpha;
+        int i = 0;
+        bool stop = false;
+        for (; i < m && it < prm->maxiter; ++i) {
+            // z_i = B r
+            int e;
+            if constexpr (sizeof(T) == 4) {
+                tm.begin(PhaseTimer::OUTER);
+                launch_convert<double2, float2>(n, w.r, w.r_in, s);
+                e = vcycle<T>(c, prm, Uin, bas, A, w.r_in, w.e_in, w.cyc, tm, cnt, s);
+                tm.begin(PhaseTimer::OUTER);
+                launch_convert<float2, double2>(n, w.e_in, w.Z[i], s);
+            } else {
+                e = vcycle<T>(c, prm, Uin, bas, A, w.r, w.Z[i], w.cyc, tm, cnt, s);
+            }
+            if (e) return e;
+            tm.begin(PhaseTimer::OUTER);
+            // w_i = H z_i, orthogonalised twice against the previous (normalised) w_j
+            launch_dslash<double>(g, U, w.Z[i], w.W[i], s);
+            ++n64;
+            PtrList Wl{};
+            for (int j = 0; j < i; ++j) Wl.p[j] = w.W[j];
+            if (i > 0) {
+                launch_multidot(n, Wl, i, w.W[i], w.part, w.S + SD1, s);
+                launch_multi_axpy(n, Wl, i, w.S + SD1, w.W[i], s);
+                launch_multidot(n, Wl, i, w.W[i], w.part, w.S + SD2, s);
+                launch_multi_axpy(n, Wl, i, w.S + SD2, w.W[i], s);
+            }
+            // <r, w>, |w|^2; r -= (<w, r>/|w|^2) w; normalise w
+            PtrList Rl{};
+            Rl.p[0] = w.r;
+            launch_multidot(n, Rl, 1, w.W[i], w.part, w.S + SD3, s);
+            launch_r_update(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
+            launch_finalize_real(w.part, 1, w.S, SRR, -1, -1, -1, s);
+            launch_scale_inv_sqrt<double>(n, w.W[i], w.S, SD3 + 2 * MAXV, s);
+            tm.end();
+            HDCR_HIP_CHECK(readS());
+            ++it;
+            rr = hS[SRR];
+            const double ww = hS[SD3 + 2 * MAXV];
+            if (!std::isfinite(rr) || !std::isfinite(ww)) {
+                status = HDCR_ENAN;
+                stop = true;
+                ++i;
+                break;
+            }
+            if (!(ww > 0.0)) {
+                status = HDCR_EBREAKDOWN;
+                stop = true;
+                break;
+            }
+            const double nw = std::sqrt(ww);
+            // zhat_i = (Z_i - sum_j beta_ij zhat_j) / |w_i|
+            std::vector<cd> ci(m, cd(0, 0));
+            ci[i] = cd(1, 0);
+            for (int j = 0; j < i; ++j) {
+                const cd beta = cd(hS[SD1 + 2 * j], hS[SD1 + 2 * j + 1]) + cd(hS[SD2 + 2 * j], hS[SD2 + 2 * j + 1]);
+                for (int q = 0; q < m; ++q) ci[q] -= beta * coef[j][q];
+            }
+            for (auto& v : ci) v /= nw;
+            coef.push_back(ci);
+            // step along zhat_i: <what_i, r> = conj(<r, w_i>) / |w_i|
+            alpha.push_back(std::conj(cd(hS[SD3], hS[SD3 + 1])) / nw);
+            if (history && hl < hcap) history[hl++] = std::sqrt(rr / bb);
+            if (rr <= tol2) {
+                ++i;
+                break;
+            }
+        }
+        // x += sum_i alpha_i zhat_i = sum_q gamma_q Z_q
+        const int nz = (int)coef.size();
+        if (nz > 0) {
+            std::vector<double2> gam(m, make_double2(0, 0));
+            for (int q = 0; q < m; ++q) {
+                cd gq(0, 0);
+                for (int k = 0; k < nz; ++k) gq += alpha[k] * coef[k][q];
+                gam[q] = make_double2(gq.real(), gq.imag());
+            }
+            PtrList Zl{};
+            for (int q = 0; q < m && q < MAXV; ++q) Zl.p[q] = w.Z[q];
+            tm.begin(PhaseTimer::OUTER);
+            launch_multi_update(n, Zl, std::min(m, MAXV), gam.data(), x, s);
+        }
+        if (stop) break;
+        // true residual at every restart
+        tm.begin(PhaseTimer::OUTER);
+        launch_dslash<double>(g, U, x, w.tmp, s);
+        ++n64;
+        launch_sub<double>(n, b, w.tmp, w.r, s);
+        launch_norm2<double>(n, w.r, w.part, w.S, SRR, s);
+        tm.end();
+        HDCR_HIP_CHECK(readS());
+        rr = hS[SRR];
+        if (!std::isfinite(rr)) {
+            status = HDCR_ENAN;
+            break;
+        }
+        if (rr <= tol2) status = HDCR_OK;
+    }
+    // final true residual
+    tm.begin(PhaseTimer::OUTER);
+    launch_dslash<double>(g, U, x, w.tmp, s);
+    ++n64;
+    launch_sub<double>(n, b, w.tmp, w.r, s);
+    launch_norm2<double>(n, w.r, w.part, w.S, SRR, s);
+    tm.end();
+    HDCR_HIP_CHECK(readS());
+    HDCR_HIP_CHECK(hipGetLastError());
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) {
+        double ph[3];
+        tm.totals(ph);
+        st->status = status;
+        st->outer_iters = it;
+        st->coarse_iters = cnt.coarse_iters;
+        st->fine_applies_f64 = n64;
+        st->fine_applies_inner = cnt.fine;
+        st->coarse_applies = cnt.coarse_applies;
+        st->true_rel_residual = bb > 0 ? std::sqrt(hS[SRR] / bb) : 0.0;
+        st->seconds_total = t;
+        st->seconds_fine = ph[PhaseTimer::FINE];
+        st->seconds_coarse = ph[PhaseTimer::COARSE];
+        st->seconds_outer = ph[PhaseTimer::OUTER];
+        st->history_len = hl;
+    }
+    return status;
+}
+
+int check_two_level_params(const hdcr_solve_params* p) {
+    if (p->restart < 1 || p->restart > MAXV)
+        return fail(HDCR_EINVAL, "restart must be in [1, " + std::to_string(MAXV) + "]");
+    if (p->cheb_order < 1 || p->cheb_order > 1000) return fail(HDCR_EINVAL, "cheb_order must be in [1, 1000]");
+    if (!(p->cheb_lo > 0) || !(p->cheb_hi > p->cheb_lo)) return fail(HDCR_EINVAL, "need 0 < cheb_lo < cheb_hi");
+    if (p->coarse_maxiter < 0) return fail(HDCR_EINVAL, "coarse_maxiter must be >= 0");
+    if (p->inner_dtype == HDCR_C128) {
+        if (p->coarse_dtype != HDCR_C128) return fail(HDCR_EINVAL, "inner C128 needs coarse_dtype C128");
+    } else if (p->inner_dtype == HDCR_C64) {
+        if (p->coarse_dtype != HDCR_C64 && p->coarse_dtype != HDCR_BF16C)
+            return fail(HDCR_EINVAL, "inner C64 needs coarse_dtype C64 or BF16C");
+    } else {
+        return fail(HDCR_EINVAL, "inner_dtype must be C128 or C64");
+    }
+    return HDCR_OK;
+}
+
+size_t two_level_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p) {
+    if (p->inner_dtype == HDCR_C64) return fgcr_bytes<float>(c, p->restart);
+    return fgcr_bytes<double>(c, p->restart);
+}
+
+int two_level_solve(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis,
+                    const void* A, const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap,
+                    void* work, size_t work_bytes, hipStream_t s) {
+    if (p->inner_dtype == HDCR_C64)
+        return fgcr_solve<float>(c, p, U, basis, A, b, x, st, history, hcap, work, work_bytes, s);
+    return fgcr_solve<double>(c, p, U, basis, A, b, x, st, history, hcap, work, work_bytes, s);
+}
+
+// one application of the two-level cycle on a C128 vector (inner precision from p)
+size_t vcycle_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p) {
+    Carver w(nullptr, 0);
+    const size_t n = (size_t)12 * c.f.N5;
+    if (p->inner_dtype == HDCR_C64) {
+        w.take<float2>((size_t)36 * c.f.V4);
+        w.take<float2>(n);
+        w.take<float2>(n);
+        cycle_carve<float>(w, c);
+    } else {
+        cycle_carve<double>(w, c);
+    }
+    return w.used();
+}
+
+int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis, const void* A,
+                 const double2* r, double2* e, void* work, size_t work_bytes, hipStream_t s) {
+    Carver w(work, work_bytes);
+    PhaseTimer tm;
+    CycleCounts cnt;
+    const int64_t n = 12LL * c.f.N5;
+    if (p->inner_dtype == HDCR_C64) {
+        float2* U32 = w.take<float2>((size_t)36 * c.f.V4);
+        float2* r32 = w.take<float2>(n);
+        float2* e32 = w.take<float2>(n);
+        CycleWork<float> cw = cycle_carve<float>(w, c);
+        if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
+        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, 8 * sizeof(int), s));
+        launch_convert<double2, float2>(36LL * c.f.V4, U, U32, s);
+        launch_convert<double2, float2>(n, r, r32, s);
+        int st = vcycle<float>(c, p, U32, basis32(c, basis), A, r32, e32, cw, tm, cnt, s);
+        if (st) return st;
+        launch_convert<float2, double2>(n, e32, e, s);
+    } else {
+        CycleWork<double> cw = cycle_carve<double>(w, c);
+        if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
+        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, 8 * sizeof(int), s));
+        int st = vcycle<double>(c, p, U, basis64(basis), A, r, e, cw, tm, cnt, s);
+        if (st) return st;
+    }
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// subspace generation: Chebyshev low-pass filter of Gaussian noise (Sec. 4)
+// ---------------------------------------------------------------------------
+// returns the buffer (one of t0, t1, wv) that holds the result
+template <typename T>
+C2<T>* cheb_filter(const FineGeom& g, const C2<T>* U, int degree, double lo, double hi, C2<T>* t0, C2<T>* t1,
+                   C2<T>* v, C2<T>* wv, double* part, double* S, hipStream_t s) {
+    // T_d(yhat) eta with yhat = (2 H^2 - hi - lo)/(hi - lo); the pair (t0, t1) is
+    // rescaled every 16 steps (the recurrence is linear) so FP32 cannot overflow
+    const int64_t n = 12LL * g.N5;
+    if (degree == 0) return t0;
+    const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
+    launch_dslash<T>(g, U, t0, v, s);
+    launch_dslash<T>(g, U, v, wv, s);
+    launch_axpby<T>(n, (T)b1, t0, (T)a1, wv, s);   // wv = yhat t0
+    std::swap(t1, wv);                              // t1 = T_1
+    const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
+    for (int j = 2; j <= degree; ++j) {
+        launch_dslash<T>(g, U, t1, v, s);
+        launch_dslash<T>(g, U, v, wv, s);
+        launch_cheb_step<T>(n, (T)a2, wv, (T)b2, t1, t0, (T)0, (C2<T>*)nullptr, s);  // t0 = T_j
+        std::swap(t0, t1);
+        if (j % 16 == 0) {
+            launch_norm2<T>(n, t1, part, S, 0, s);
+            launch_scale_inv_sqrt<T>(n, t0, S, 0, s);
+            launch_scale_inv_sqrt<T>(n, t1, S, 0, s);
+        }
+    }
+    return t1;
+}
+
+}  // namespace hdcr
+
+using namespace hdcr;
+
+extern "C" {
+
+int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int32_t order, double lo, double hi,
+                const void* in, void* out, void* work, size_t work_bytes, hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_smooth: dtype C128 or C64");
+    if (order < 1 || order > 1000 || !(lo > 0) || !(hi > lo)) return fail(HDCR_EINVAL, "hdcr_smooth: bad polynomial");
+    const size_t cs = dtype == HDCR_C128 ? 16 : 8;
+    if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(in, cs, "in")) || (e = check_ptr(out, cs, "out")) ||
+        (e = check_ptr(work, 256, "work")))
+        return e;
+    const FineGeom g = make_geom(desc);
+    const size_t n = (size_t)12 * g.N5;
+    if (work_bytes < 4 * n * cs + 4 * 256) return fail(HDCR_ENOMEM, "hdcr_smooth: workspace too small");
+    Carver w(work, work_bytes);
+    if (dtype == HDCR_C128) {
+        double2* tmp[4];
+        for (int i = 0; i < 4; ++i) tmp[i] = w.take<double2>(n);
+        cheb_smoother<double>(g, (const double2*)U, (const double2*)in, (double2*)out, tmp, order, lo, hi, stream);
+    } else {
+        float2* tmp[4];
+        for (int i = 0; i < 4; ++i) tmp[i] = w.take<float2>(n);
+        cheb_smoother<float>(g, (const float2*)U, (const float2*)in, (float2*)out, tmp, order, lo, hi, stream);
+    }
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
+                const void* A, const void* r, void* e, void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_coarse_desc(desc);
+    if (st) return st;
+    if (!params) return fail(HDCR_EINVAL, "hdcr_vcycle: null params");
+    if ((st = check_two_level_params(params))) return st;
+    if ((st = check_ptr(U, 16, "U")) || (st = check_ptr(basis, 16, "basis")) || (st = check_ptr(A, 4, "A")) ||
+        (st = check_ptr(r, 16, "r")) || (st = check_ptr(e, 16, "e")) || (st = check_ptr(work, 256, "work")))
+        return st;
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (work_bytes < vcycle_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
+    return vcycle_apply(c, params, (const double2*)U, basis, A, (const double2*)r, (double2*)e, work, work_bytes,
+                        stream);
+}
+
+size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_dtype dtype) {
+    if (check_fine_desc(desc)) return 0;
+    const FineGeom g = make_geom(desc);
+    Carver w(nullptr, 0);
+    const size_t n = (size_t)12 * g.N5;
+    if (dtype == HDCR_C64) {
+        w.take<float2>((size_t)36 * g.V4);
+        for (int i = 0; i < 4; ++i) w.take<float2>(n);
+    } else {
+        for (int i = 0; i < 4; ++i) w.take<double2>(n);
+    }
+    w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+    w.take<double>(64);
+    return w.used();
+}
+
+int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nvec, int32_t degree, double lo,
+                       double hi, const void* U, const void* noise, void* vecs, void* work, size_t work_bytes,
+                       hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_make_subspace: dtype C128 or C64");
+    if (nvec < 1 || degree < 0 || degree > 100000 || !(hi > lo)) return fail(HDCR_EINVAL, "hdcr_make_subspace: bad args");
+    if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(noise, 16, "noise")) || (e = check_ptr(vecs, 16, "vecs")) ||
+        (e = check_ptr(work, 256, "work")))
+        return e;
+    const FineGeom g = make_geom(desc);
+    if (work_bytes < hdcr_subspace_workspace_bytes(desc, dtype))
+        return fail(HDCR_ENOMEM, "hdcr_make_subspace: workspace too small");
+    const int64_t n = 12LL * g.N5;
+    Carver w(work, work_bytes);
+    const double2* nz = static_cast<const double2*>(noise);
+    double2* out = static_cast<double2*>(vecs);
+    if (dtype == HDCR_C64) {
+        float2* U32 = w.take<float2>((size_t)36 * g.V4);
+        float2* b[4];
+        for (int i = 0; i < 4; ++i) b[i] = w.take<float2>(n);
+        double* part = w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+        double* S = w.take<double>(64);
+        launch_convert<double2, float2>(36LL * g.V4, (const double2*)U, U32, stream);
+        for (int k = 0; k < nvec; ++k) {
+            launch_convert<double2, float2>(n, nz + k * n, b[0], stream);
+            float2* res = cheb_filter<float>(g, U32, degree, lo, hi, b[0], b[1], b[2], b[3], part, S, stream);
+            launch_norm2<float>(n, res, part, S, 1, stream);
+            launch_scale_inv_sqrt<float>(n, res, S, 1, stream);
+            launch_convert<float2, double2>(n, res, out + k * n, stream);
+        }
+    } else {
+        double2* b[4];
+        for (int i = 0; i < 4; ++i) b[i] = w.take<double2>(n);
+        double* part = w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+        double* S = w.take<double>(64);
+        for (int k = 0; k < nvec; ++k) {
+            launch_convert<double2, double2>(n, nz + k * n, b[0], stream);
+            double2* res = cheb_filter<double>(g, (const double2*)U, degree, lo, hi, b[0], b[1], b[2], b[3], part, S,
+                                               stream);
+            launch_norm2<double>(n, res, part, S, 1, stream);
+            launch_scale_inv_sqrt<double>(n, res, S, 1, stream);
+            launch_convert<double2, double2>(n, res, out + k * n, stream);
+        }
+    }
+    HDCR_HIP_CHECK(hipGetLastError());
+    HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+    return HDCR_OK;
+}
+
+int hdcr_power_max(const hdcr_fine_desc* desc, const void* U, const void* v0, int32_t iters, double* lam, void* work,
+                   size_t work_bytes, hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (iters < 1 || !lam) return fail(HDCR_EINVAL, "hdcr_power_max: iters >= 1 and lam required");
+    if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(v0, 16, "v0")) || (e = check_ptr(work, 256, "work"))) return e;
+    const FineGeom g = make_geom(desc);
+    const int64_t n = 12LL * g.N5;
+    if (work_bytes < hdcr_subspace_workspace_bytes(desc, HDCR_C128))
+        return fail(HDCR_ENOMEM, "hdcr_power_max: workspace too small");
+    Carver w(work, work_bytes);
+    double2* v = w.take<double2>(n);
+    double2* t = w.take<double2>(n);
+    double2* u = w.take<double2>(n);
+    w.take<double2>(n);
+    double* part = w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+    double* S = w.take<double>(64);
+    const double2* Ud = static_cast<const double2*>(U);
+    // v = v0/|v0|; repeat: u = H^2 v, lambda = <v, u>, v = u/|u|
+    launch_convert<double2, double2>(n, static_cast<const double2*>(v0), v, stream);
+    launch_norm2<double>(n, v, part, S, 0, stream);
+    launch_scale_inv_sqrt<double>(n, v, S, 0, stream);
+    PtrList Vl{};
+    for (int i = 0; i < iters; ++i) {
+        launch_dslash<double>(g, Ud, v, t, stream);
+        launch_dslash<double>(g, Ud, t, u, stream);
+        Vl.p[0] = v;
+        launch_multidot(n, Vl, 1, u, part, S + 8, stream);  // S[8] = Re<v,u>, S[8+2*MAXV] = |u|^2
+        launch_scale_inv_sqrt<double>(n, u, S, 8 + 2 * MAXV, stream);
+        std::swap(v, u);
+    }
+    double h = 0.0;
+    HDCR_HIP_CHECK(hipMemcpyAsync(&h, S + 8, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+    *lam = h;
+    return HDCR_OK;
+}
+
+}  // extern "C"

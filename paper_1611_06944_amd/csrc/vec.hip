@@ -1,0 +1,265 @@
+// Vector kernels used by the two-level solver: precision conversion, linear
+// combinations with scalars from the host or from device memory, fused
+// Chebyshev recurrence steps, and multi-vector inner products (FP64
+// accumulation, fixed reduction order).
+#include "vec.h"
+#include "solver.h"
+
+namespace hdcr {
+
+namespace {
+
+constexpr int VWG = 256;
+
+int vgrid(int64_t n) {
+    int64_t b = (n + VWG - 1) / VWG;
+    if (b > 8192) b = 8192;
+    return (int)(b < 1 ? 1 : b);
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(VWG) convert_kernel(int64_t n, const A* __restrict__ x, B* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const A v = x[i];
+        B o;
+        o.x = v.x;
+        o.y = v.y;
+        y[i] = o;
+    }
+}
+
+// y = a x + b y (real a, b)
+template <typename T>
+__global__ void __launch_bounds__(VWG) axpby_kernel(int64_t n, T a, const C2<T>* __restrict__ x, T b,
+                                                    C2<T>* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const C2<T> xv = x[i];
+        C2<T> yv = y[i];
+        yv.x = a * xv.x + b * yv.x;
+        yv.y = a * xv.y + b * yv.y;
+        y[i] = yv;
+    }
+}
+
+// out = x - y
+template <typename T>
+__global__ void __launch_bounds__(VWG) sub_kernel(int64_t n, const C2<T>* __restrict__ x, const C2<T>* __restrict__ y,
+                                                  C2<T>* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG)
+        out[i] = csub<T>(x[i], y[i]);
+}
+
+// Chebyshev step: t0 <- a w + b t1 - t0 ;  acc <- acc + c t0 (the new term)
+template <typename T>
+__global__ void __launch_bounds__(VWG) cheb_step_kernel(int64_t n, T a, const C2<T>* __restrict__ w, T b,
+                                                        const C2<T>* __restrict__ t1, C2<T>* __restrict__ t0, T c,
+                                                        C2<T>* __restrict__ acc) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const C2<T> wv = w[i], t1v = t1[i], t0v = t0[i];
+        C2<T> nv;
+        nv.x = a * wv.x + b * t1v.x - t0v.x;
+        nv.y = a * wv.y + b * t1v.y - t0v.y;
+        t0[i] = nv;
+        if (acc) {
+            C2<T> av = acc[i];
+            av.x += c * nv.x;
+            av.y += c * nv.y;
+            acc[i] = av;
+        }
+    }
+}
+
+// out = a x (real a)
+template <typename T>
+__global__ void __launch_bounds__(VWG) scale_kernel(int64_t n, T a, const C2<T>* __restrict__ x,
+                                                    C2<T>* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const C2<T> v = x[i];
+        out[i] = mk<T>(a * v.x, a * v.y);
+    }
+}
+
+// partial sums of <V[j], y> for j < nv (and |y|^2 if want_norm) into part[q * REDUCE_BLOCKS + blk]
+__global__ void __launch_bounds__(REDUCE_THREADS) multidot_kernel(int64_t n, PtrList V,
+                                                                  int nv, const double2* __restrict__ y,
+                                                                  double* __restrict__ part) {
+    double acc[2 * MAXV + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double2 yv = y[i];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+            if (j < nv) {
+                const double2 v = V.p[j][i];
+                acc[2 * j] += v.x * yv.x + v.y * yv.y;
+                acc[2 * j + 1] += v.x * yv.y - v.y * yv.x;
+            }
+        }
+        acc[2 * MAXV] += yv.x * yv.x + yv.y * yv.y;
+    }
+    block_reduce<2 * MAXV + 1>(acc);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 2 * MAXV + 1; ++q) part[(int64_t)q * REDUCE_BLOCKS + blockIdx.x] = acc[q];
+    }
+}
+
+__global__ void __launch_bounds__(REDUCE_THREADS) multidot_finalize_kernel(const double* __restrict__ part, int nq,
+                                                                           double* __restrict__ out) {
+    // one workgroup per quantity
+    const int q = blockIdx.x;
+    if (q >= nq) return;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < REDUCE_BLOCKS; i += blockDim.x) v[0] += part[(int64_t)q * REDUCE_BLOCKS + i];
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) out[q] = v[0];
+}
+
+// y <- y - sum_j coef[j] V[j]   (coef: complex, device memory)
+__global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrList V, int nv,
+                                                         const double* __restrict__ coef, double2* __restrict__ y) {
+    double2 cf[MAXV];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j) cf[j] = (j < nv) ? make_double2(coef[2 * j], coef[2 * j + 1]) : make_double2(0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        double2 yv = y[i];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+            if (j < nv) yv = cfma<double>(cneg<double>(cf[j]), V.p[j][i], yv);
+        y[i] = yv;
+    }
+}
+
+// x <- x + sum_j g[j] Z[j]   (g: complex, kernel arguments)
+struct Coefs {
+    double2 g[MAXV];
+};
+__global__ void __launch_bounds__(VWG) multi_update_kernel(int64_t n, PtrList Z, int nz,
+                                                           Coefs g, double2* __restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        double2 xv = x[i];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+            if (j < nz) xv = cfma<double>(g.g[j], Z.p[j][i], xv);
+        x[i] = xv;
+    }
+}
+
+// r <- r - (conj(c) / nn) w with c = (S[ic], S[ic+1]) = <r, w> and nn = S[inn] = |w|^2
+// (so the step is <w, r>/|w|^2); partial |r|^2
+__global__ void __launch_bounds__(REDUCE_THREADS) r_update_kernel(int64_t n, const double* __restrict__ S, int ic,
+                                                                  int inn, const double2* __restrict__ w,
+                                                                  double2* __restrict__ r, double* __restrict__ part) {
+    const double nn = S[inn];
+    const double2 a = make_double2(S[ic] / nn, -S[ic + 1] / nn);
+    double v[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double2 rv = cfma<double>(cneg<double>(a), w[i], r[i]);
+        r[i] = rv;
+        v[0] += rv.x * rv.x + rv.y * rv.y;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// partial |x|^2 (FP64 accumulation)
+template <typename T>
+__global__ void __launch_bounds__(REDUCE_THREADS) norm2_kernel(int64_t n, const C2<T>* __restrict__ x,
+                                                               double* __restrict__ part) {
+    double v[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const C2<T> a = x[i];
+        v[0] += (double)a.x * a.x + (double)a.y * a.y;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// x <- x / sqrt(S[idx])  (S[idx] > 0)
+template <typename T>
+__global__ void __launch_bounds__(VWG) scale_inv_sqrt_kernel(int64_t n, C2<T>* __restrict__ x,
+                                                             const double* __restrict__ S, int idx) {
+    const T f = (T)(1.0 / sqrt(S[idx]));
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const C2<T> v = x[i];
+        x[i] = mk<T>(f * v.x, f * v.y);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(norm2_kernel<T>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, x, part);
+    launch_finalize_real(part, 1, S, idx, -1, -1, -1, s);
+}
+template <typename T>
+void launch_scale_inv_sqrt(int64_t n, C2<T>* x, const double* S, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(scale_inv_sqrt_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, x, S, idx);
+}
+template void launch_norm2<double>(int64_t, const double2*, double*, double*, int, hipStream_t);
+template void launch_norm2<float>(int64_t, const float2*, double*, double*, int, hipStream_t);
+template void launch_scale_inv_sqrt<double>(int64_t, double2*, const double*, int, hipStream_t);
+template void launch_scale_inv_sqrt<float>(int64_t, float2*, const double*, int, hipStream_t);
+
+template <typename A, typename B>
+void launch_convert(int64_t n, const A* x, B* y, hipStream_t s) {
+    hipLaunchKernelGGL((convert_kernel<A, B>), dim3(vgrid(n)), dim3(VWG), 0, s, n, x, y);
+}
+template void launch_convert<double2, float2>(int64_t, const double2*, float2*, hipStream_t);
+template void launch_convert<float2, double2>(int64_t, const float2*, double2*, hipStream_t);
+template void launch_convert<double2, double2>(int64_t, const double2*, double2*, hipStream_t);
+template void launch_convert<float2, float2>(int64_t, const float2*, float2*, hipStream_t);
+
+template <typename T>
+void launch_axpby(int64_t n, T a, const C2<T>* x, T b, C2<T>* y, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, a, x, b, y);
+}
+template <typename T>
+void launch_sub(int64_t n, const C2<T>* x, const C2<T>* y, C2<T>* out, hipStream_t s) {
+    hipLaunchKernelGGL(sub_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, x, y, out);
+}
+template <typename T>
+void launch_cheb_step(int64_t n, T a, const C2<T>* w, T b, const C2<T>* t1, C2<T>* t0, T c, C2<T>* acc,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, a, w, b, t1, t0, c, acc);
+}
+template <typename T>
+void launch_scale(int64_t n, T a, const C2<T>* x, C2<T>* out, hipStream_t s) {
+    hipLaunchKernelGGL(scale_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, a, x, out);
+}
+#define HDCR_VEC_INST(T)                                                                                      \
+    template void launch_axpby<T>(int64_t, T, const C2<T>*, T, C2<T>*, hipStream_t);                           \
+    template void launch_sub<T>(int64_t, const C2<T>*, const C2<T>*, C2<T>*, hipStream_t);                     \
+    template void launch_cheb_step<T>(int64_t, T, const C2<T>*, T, const C2<T>*, C2<T>*, T, C2<T>*, hipStream_t); \
+    template void launch_scale<T>(int64_t, T, const C2<T>*, C2<T>*, hipStream_t);
+HDCR_VEC_INST(double)
+HDCR_VEC_INST(float)
+#undef HDCR_VEC_INST
+
+void launch_multidot(int64_t n, const PtrList& V, int nv, const double2* y, double* part, double* out,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(multidot_kernel, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, y, part);
+    hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
+                       out);
+}
+
+void launch_multi_axpy(int64_t n, const PtrList& V, int nv, const double* coef, double2* y, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, V, nv, coef, y);
+}
+
+void launch_multi_update(int64_t n, const PtrList& Z, int nz, const double2* g, double2* x, hipStream_t s) {
+    Coefs c;
+    for (int j = 0; j < MAXV; ++j) c.g[j] = (j < nz) ? g[j] : make_double2(0, 0);
+    hipLaunchKernelGGL(multi_update_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, Z, nz, c, x);
+}
+
+void launch_r_update(int64_t n, const double* S, int ic, int inn, const double2* w, double2* r, double* part,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(r_update_kernel, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, S, ic, inn, w, r, part);
+}
+
+}  // namespace hdcr

@@ -108,3 +108,22 @@ def test_layout_roundtrip():
     U = hi.gauge_field(L, seed=2)
     g = pack_gauge(U)
     assert g[3, 1, 2, ((t * 4 + z) * 3 + y) * 2 + x] == U[t, z, y, x, 3, 1, 2]
+
+
+def test_two_level_param_validation(lib):
+    """Invalid two-level parameters are rejected by the workspace query (host only)."""
+    import paper_1611_06944_amd as hd
+    lat = hd.Lattice((4, 4, 4, 4), 4, block=(2, 2, 2, 2), nvec=4)
+    good = hd.default_params(precond=hd.PRECOND_TWO_LEVEL)
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, good) > 0
+    # inner C64 needs C64 or BF16 coarse storage
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
+                                                                       coarse_dtype=hd.C128)) == 0
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
+                                                                       restart=99)) == 0
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
+                                                                       cheb_lo=2.0, cheb_hi=1.0)) == 0
+    # odd Ls or a block that does not divide the lattice: invalid coarse space
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, hd.Lattice((4, 4, 4, 4), 5, block=(2, 2, 2, 2), nvec=4), good) == 0
+    assert hd.workspace_bytes(hd._abi.WS_BUILD, hd.Lattice((4, 4, 4, 4), 4, block=(3, 2, 2, 2), nvec=4)) == 0
+    assert hd.workspace_bytes(hd._abi.WS_BUILD, hd.Lattice((4, 4, 4, 4), 4, block=(2, 2, 2, 2), nvec=4)) > 0

@@ -1,0 +1,147 @@
+"""GPU parity of the two-level method (Sec. 4) against the FP64 oracle, through the
+C-ABI: Chebyshev smoother, subspace filter, power iteration, the symmetric two-level
+cycle (fixed coarse iteration count) and the flexible-GCR HDCR solve."""
+import numpy as np
+import pytest
+
+import hdcr_inputs as hi
+import oracle
+import paper_1611_06944_amd as hd
+from tests.gpu_util import log, max_rel_elem, rel_err, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _lat(L, Ls, block=(2, 2, 2, 2), nvec=4, mf=0.01):
+    p = oracle.Params(L, Ls, M5=1.8, mf=mf)
+    return p, oracle.Coarse(p, block, nvec), hd.Lattice(L, Ls, M5=1.8, mf=mf, block=block, nvec=nvec)
+
+
+@pytest.mark.parametrize("order", [1, 2, 10])
+def test_smoother_parity(order):
+    torch = torch_dev()
+    L, Ls = (4, 4, 4, 6), 8
+    log(f"smoother order={order}")
+    p, _, lat = _lat(L, Ls)
+    U = hi.gauge_field(L)
+    r = hi.gaussian_fermion(L, Ls, seed=4)
+    ref = oracle.smoother(lambda f: oracle.apply_h(U, f, p), r, order=order, lo=1.0, hi=64.0)
+    for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+        out = hd.smooth(lat, to_dev(hd.pack_gauge(U), dt), to_dev(hd.pack_fermion(r), dt), order=order)
+        got = hd.unpack_fermion(to_host(out), L, Ls)
+        assert max_rel_elem(got, ref) <= tol, dt
+
+
+def test_subspace_filter_and_power_parity():
+    torch = torch_dev()
+    L, Ls = (4, 4, 4, 4), 8
+    log("subspace filter and power iteration")
+    p, _, lat = _lat(L, Ls)
+    U = hi.gauge_field(L)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    v0 = hi.gaussian_fermion(L, Ls, seed=99)
+    Ud = to_dev(hd.pack_gauge(U))
+    lam = hd.power_max(lat, Ud, to_dev(hd.pack_fermion(v0)), iters=25)
+    lam_ref = oracle.power_max(ap, v0, iters=25)
+    assert abs(lam - lam_ref) <= 1e-10 * lam_ref
+    noise = hi.subspace_noise(L, Ls, 3)
+    lo, hi_ = 0.05 * lam_ref, 1.1 * lam_ref
+    ref = [oracle.cheby_filter(ap, e, 40, lo, hi_) for e in noise]
+    nd = to_dev(np.stack([hd.pack_fermion(e) for e in noise]))
+    for dt, tol in ((hd.C128, 1e-10), (hd.C64, 1e-5)):
+        out = to_host(hd.make_subspace(lat, Ud, nd, 40, lo, hi_, dtype=dt))
+        for k in range(3):
+            assert max_rel_elem(hd.unpack_fermion(out[k], L, Ls), ref[k]) <= tol, (dt, k)
+
+
+def _coarse(L, Ls, block, nvec, p, cs, U, filtered=True):
+    ap = lambda f: oracle.apply_h(U, f, p)
+    if filtered:
+        lmax = oracle.power_max(ap, hi.gaussian_fermion(L, Ls, seed=99), iters=30) * 1.1
+        vecs = [oracle.cheby_filter(ap, e, 12, 0.05 * lmax, lmax) for e in hi.subspace_noise(L, Ls, nvec)]
+    else:
+        vecs = hi.subspace_noise(L, Ls, nvec)
+    basis_ref, st = oracle.block_basis(vecs, cs)
+    assert st == 0
+    A_ref = oracle.coarse_build(U, basis_ref, cs)
+    return vecs, basis_ref, A_ref
+
+
+@pytest.mark.parametrize("inner", ["c128", "c64"])
+def test_vcycle_parity_fixed_coarse_iterations(inner):
+    """One application of B (the paper's M_outer) with exactly 6 coarse CR iterations."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (4, 4, 4, 4), 8, (2, 2, 2, 2), 4
+    log(f"vcycle parity inner={inner}")
+    p, cs, lat = _lat(L, Ls, block, nvec)
+    U = hi.gauge_field(L)
+    vecs, basis_ref, A_ref = _coarse(L, Ls, block, nvec, p, cs, U)
+    r = hi.gaussian_fermion(L, Ls, seed=5)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    ref = oracle.vcycle(ap, A_ref, basis_ref, cs, r, order=10, lo=1.0, hi=64.0, ctol=0.0, cmaxiter=6)
+    Ud = to_dev(hd.pack_gauge(U))
+    cdt = hd.C128 if inner == "c128" else hd.C64
+    basis, A = hd.build_coarse(lat, Ud, to_dev(np.stack([hd.pack_fermion(v) for v in vecs])), cdt)
+    prm = hd.default_params(inner_dtype=cdt, coarse_dtype=cdt, coarse_tol=0.0, coarse_maxiter=6)
+    e = hd.unpack_fermion(to_host(hd.vcycle(lat, Ud, basis, A, to_dev(hd.pack_fermion(r)), prm)), L, Ls)
+    tol = 1e-10 if inner == "c128" else 1e-5
+    assert max_rel_elem(e, ref) <= tol
+
+
+def test_hdcr_solve_fp64_matches_oracle_iterates():
+    """FP64 inner cycle with 6 coarse iterations: the FGCR residual history follows the
+    oracle's, and the solution reaches |b - Hx| <= 1e-8 |b| under the oracle's H."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (4, 4, 4, 4), 8, (2, 2, 2, 2), 4
+    log("hdcr solve fp64 vs oracle fgcr")
+    p, cs, lat = _lat(L, Ls, block, nvec)
+    U = hi.gauge_field(L)
+    vecs, basis_ref, A_ref = _coarse(L, Ls, block, nvec, p, cs, U)
+    b = hi.gaussian_fermion(L, Ls, seed=0)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    ref = oracle.fgcr(ap, lambda r: oracle.vcycle(ap, A_ref, basis_ref, cs, r, ctol=0.0, cmaxiter=6), b,
+                      tol=1e-8, maxiter=100, restart=8)
+    Ud = to_dev(hd.pack_gauge(U))
+    basis, A = hd.build_coarse(lat, Ud, to_dev(np.stack([hd.pack_fermion(v) for v in vecs])), hd.C128)
+    prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C128, coarse_dtype=hd.C128,
+                            coarse_tol=0.0, coarse_maxiter=6, restart=8, tol=1e-8, maxiter=100)
+    x, st, hist = hd.solve(lat, Ud, to_dev(hd.pack_fermion(b)), params=prm, basis=basis, A=A)
+    assert st["status"] == 0
+    bn = oracle.norm(b)
+    k = min(5, len(hist), len(ref.history))
+    np.testing.assert_allclose(np.array(hist[:k]), np.array(ref.history[:k]) / bn, rtol=1e-6)
+    assert abs(st["outer_iters"] - ref.iters) <= 1
+    xs = hd.unpack_fermion(to_host(x), L, Ls)
+    assert oracle.norm(b - ap(xs)) <= 1e-8 * bn
+
+
+@pytest.mark.parametrize("coarse", ["c64", "bf16"])
+def test_hdcr_solve_mixed_precision(coarse):
+    """FP32 inner cycle, C64 or BF16 coarse storage, coarse CR to 1e-2: converges to the
+    FP64 true residual 1e-8 and to the plain-CR solution."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (8, 8, 8, 8), 8, (4, 4, 4, 4), 8
+    log(f"hdcr solve mixed precision coarse={coarse}")
+    p, cs, lat = _lat(L, Ls, block, nvec)
+    U = hi.gauge_field(L)
+    Ud = to_dev(hd.pack_gauge(U))
+    b = hi.gaussian_fermion(L, Ls, seed=0)
+    bd = to_dev(hd.pack_fermion(b))
+    # subspace on the GPU: power iteration + Chebyshev filter of Gaussian noise
+    lam = hd.power_max(lat, Ud, to_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=99))), iters=30)
+    noise = to_dev(np.stack([hd.pack_fermion(e) for e in hi.subspace_noise(L, Ls, nvec)]))
+    vecs = hd.make_subspace(lat, Ud, noise, 24, 0.02 * 1.1 * lam, 1.1 * lam, dtype=hd.C64)
+    cdt = hd.C64 if coarse == "c64" else hd.BF16C
+    basis, A = hd.build_coarse(lat, Ud, vecs, cdt)
+    prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=cdt, coarse_tol=1e-2,
+                            coarse_maxiter=200, restart=8, tol=1e-8, maxiter=200)
+    x, st, hist = hd.solve(lat, Ud, bd, params=prm, basis=basis, A=A)
+    assert st["status"] == 0, st
+    xs = hd.unpack_fermion(to_host(x), L, Ls)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    assert oracle.norm(b - ap(xs)) <= 1e-8 * oracle.norm(b)
+    assert abs(st["true_rel_residual"] - oracle.norm(b - ap(xs)) / oracle.norm(b)) <= 1e-2 * 1e-8
+    x_cr, st_cr, _ = hd.solve(lat, Ud, bd, params=hd.default_params(tol=1e-10))
+    assert rel_err(to_host(x), to_host(x_cr)) <= 1e-6
+    assert st["outer_iters"] < st_cr["outer_iters"]
+    assert st["coarse_iters"] > 0 and st["fine_applies_inner"] > 0
