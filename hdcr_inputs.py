@@ -127,3 +127,16 @@ def plaquette(U: np.ndarray) -> float:
             tot += np.real(np.trace(p, axis1=-2, axis2=-1)).mean() / 3.0
             n += 1
     return tot / n
+
+
+def gaussian_fermion_device(L, Ls: int, seed: int, device="cuda:0"):
+    """Complex Gaussian fermion field drawn on the device with torch's seeded
+    generator (re, im ~ N(0, 1)), for large subspace-noise draws that would be
+    slow on the host.  Returned in the device layout [12, V4, Ls]."""
+    import torch
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    V4 = Lx * Ly * Lz * Lt
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    ri = torch.randn((12, V4, int(Ls), 2), dtype=torch.float64, device=device, generator=g)
+    return torch.view_as_complex(ri)

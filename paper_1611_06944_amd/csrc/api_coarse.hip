@@ -12,6 +12,7 @@ int check_coarse_desc(const hdcr_coarse_desc* d) {
     int e = check_fine_desc(&d->fine);
     if (e) return e;
     if (d->fine.Ls % 2 != 0) return fail(HDCR_EINVAL, "the coarse space needs an even Ls (chiral halves of Gamma5)");
+    if (d->fine.Ls > 512) return fail(HDCR_EINVAL, "the coarse space supports Ls <= 512");
     int64_t bvol = 1;
     for (int mu = 0; mu < 4; ++mu) {
         if (d->block[mu] < 1 || d->fine.L[mu] % d->block[mu] != 0)

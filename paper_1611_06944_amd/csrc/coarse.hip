@@ -196,57 +196,94 @@ __global__ void __launch_bounds__(CWG) basis_expand_kernel(CoarseGeom c, const d
 // restriction and prolongation
 // ---------------------------------------------------------------------------
 
-template <typename T> struct RestrictChunk { static constexpr int KC = 16; };
-template <> struct RestrictChunk<double> { static constexpr int KC = 8; };
+// two consecutive complex entries (s and s+1 of one component)
+template <typename T> struct Pair {
+    C2<T> a, b;
+};
+template <typename T> __device__ __forceinline__ Pair<T> ld_pair(const C2<T>* p) {
+    Pair<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        r.a = mk<T>(q.x, q.y);
+        r.b = mk<T>(q.z, q.w);
+    } else {
+        r.a = p[0];
+        r.b = p[1];
+    }
+    return r;
+}
 
-// one workgroup per coarse site; each work-item strides over the compressed
-// indices and accumulates KC inner products per chirality, chunk by chunk
-template <typename T>
+constexpr int RKG = 16;  // basis vectors per restriction workgroup
+
+// grid (Nc, 2 chiralities, ceil(nvec / RKG)): v[a][h*nvec + k] = <phi^{a,h}_k, psi - psi2>
+// for the RKG vectors k of the workgroup.  Work-item = (row slot, W consecutive s):
+// a row is (component, block site), so the loads of the compressed basis (index
+// row * Lh + s) and of psi are contiguous; W = 2 (Lh even) makes them 16-byte
+// pairs in FP32.
+template <typename T, bool SUB, int W>
 __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>* __restrict__ basis,
                                                        const C2<T>* __restrict__ psi, const C2<T>* __restrict__ psi2,
                                                        C2<T>* __restrict__ v) {
-    constexpr int KC = RestrictChunk<T>::KC;
-    __shared__ C2<T> sh[4 * 2 * KC];
-    const int a = blockIdx.x;
-    const C2<T>* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
-    const C2<T>* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
+    __shared__ C2<T> sh[4 * RKG];
+    const int a = blockIdx.x, h = blockIdx.y;
+    const int k0 = blockIdx.z * RKG;
+    const int kn = min(RKG, c.nvec - k0);
+    const int nsp = c.Lh / W;                 // s slots per row
+    const int slots = CWG / nsp;              // rows processed per sweep
+    const int sp = threadIdx.x % nsp, q0 = threadIdx.x / nsp;
+    const int s = W * sp;
+    const int nrows = 12 * c.bvol;
+    const C2<T>* bh = basis + (((size_t)a * 2 + h) * c.nvec + k0) * c.nhalf;
     const T r2 = (T)RSQRT2;
-    for (int k0 = 0; k0 < c.nvec; k0 += KC) {
-        const int kn = min(KC, c.nvec - k0);
-        C2<T> acc[2 * KC];
+    C2<T> acc[RKG];
 #pragma unroll
-        for (int q = 0; q < 2 * KC; ++q) acc[q] = mk<T>(0, 0);
-        for (int i = threadIdx.x; i < c.nhalf; i += CWG) {
-            const int s = i % c.Lh;
-            const int sl = (i / c.Lh) % c.bvol;
-            const int comp = i / (c.Lh * c.bvol);
+    for (int q = 0; q < RKG; ++q) acc[q] = mk<T>(0, 0);
+    if (q0 < slots) {
+        for (int row = q0; row < nrows; row += slots) {
+            const int comp = row / c.bvol, sl = row - comp * c.bvol;
             const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
-            C2<T> p1 = psi[fb + s], p2 = psi[fb + c.f.Ls - 1 - s];
-            if (psi2) {
-                p1 = csub<T>(p1, psi2[fb + s]);
-                p2 = csub<T>(p2, psi2[fb + c.f.Ls - 1 - s]);
+            // slot s + w pairs with the mirrored Ls-1-s-w
+            C2<T> p1[W], p2[W];
+            if constexpr (W == 2) {
+                const Pair<T> lo = ld_pair<T>(psi + fb + s), hi = ld_pair<T>(psi + fb + c.f.Ls - 2 - s);
+                p1[0] = lo.a;
+                p1[1] = lo.b;
+                p2[0] = hi.b;
+                p2[1] = hi.a;
+            } else {
+                p1[0] = psi[fb + s];
+                p2[0] = psi[fb + c.f.Ls - 1 - s];
             }
-            const T g = (comp < 6) ? (T)1 : (T)-1;
-            const C2<T> fp = mk<T>((p1.x + g * p2.x) * r2, (p1.y + g * p2.y) * r2);
-            const C2<T> fm = mk<T>((p1.x - g * p2.x) * r2, (p1.y - g * p2.y) * r2);
+            if constexpr (SUB) {
 #pragma unroll
-            for (int q = 0; q < KC; ++q) {
+                for (int w = 0; w < W; ++w) {
+                    p1[w] = csub<T>(p1[w], psi2[fb + s + w]);
+                    p2[w] = csub<T>(p2[w], psi2[fb + c.f.Ls - 1 - s - w]);
+                }
+            }
+            const T sg = ((comp < 6) == (h == 0)) ? (T)1 : (T)-1;
+            C2<T> f[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) f[w] = mk<T>((p1[w].x + sg * p2[w].x) * r2, (p1[w].y + sg * p2[w].y) * r2);
+            const size_t i = (size_t)row * c.Lh + s;
+#pragma unroll
+            for (int q = 0; q < RKG; ++q) {
                 if (q < kn) {
-                    acc[q] = cjfma<T>(bp[(size_t)(k0 + q) * c.nhalf + i], fp, acc[q]);
-                    acc[KC + q] = cjfma<T>(bm[(size_t)(k0 + q) * c.nhalf + i], fm, acc[KC + q]);
+                    if constexpr (W == 2) {
+                        const Pair<T> bv = ld_pair<T>(bh + (size_t)q * c.nhalf + i);
+                        acc[q] = cjfma<T>(bv.a, f[0], acc[q]);
+                        acc[q] = cjfma<T>(bv.b, f[W - 1], acc[q]);
+                    } else {
+                        acc[q] = cjfma<T>(bh[(size_t)q * c.nhalf + i], f[0], acc[q]);
+                    }
                 }
             }
         }
-        wg_sum<T, 2 * KC>(acc, sh);
-        // static register indices (a runtime index would move acc to scratch)
-#pragma unroll
-        for (int q = 0; q < KC; ++q) {
-            if (threadIdx.x == q && q < kn) {
-                v[(size_t)a * c.Nb + k0 + q] = acc[q];
-                v[(size_t)a * c.Nb + c.nvec + k0 + q] = acc[KC + q];
-            }
-        }
     }
+    wg_sum<T, RKG>(acc, sh);
+#pragma unroll
+    for (int q = 0; q < RKG; ++q)
+        if (threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
 template <typename T>
@@ -741,7 +778,21 @@ void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk
 template <typename T>
 void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
                      hipStream_t s) {
-    hipLaunchKernelGGL(restrict_kernel<T>, dim3(c.Nc), dim3(CWG), 0, s, c, basis, psi, psi2, v);
+    const dim3 grid(c.Nc, 2, (c.nvec + RKG - 1) / RKG);
+    // two s slots per work-item when Ls/2 is even and a row fits the workgroup
+    const bool two = (c.Lh % 2 == 0) && (c.Lh / 2 <= CWG);
+    if (c.Lh > CWG) return;  // not reachable: Ls <= 512 is enforced by the descriptor checks
+    if (two) {
+        if (psi2)
+            hipLaunchKernelGGL((restrict_kernel<T, true, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+        else
+            hipLaunchKernelGGL((restrict_kernel<T, false, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+    } else {
+        if (psi2)
+            hipLaunchKernelGGL((restrict_kernel<T, true, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+        else
+            hipLaunchKernelGGL((restrict_kernel<T, false, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+    }
 }
 
 template <typename T>
