@@ -24,7 +24,8 @@
  * Memory layouts of caller buffers (device memory unless stated):
  *   fine field  psi[c][site4][s], c = spin*3 + colour (12), complex interleaved (re, im);
  *               C128 = 2 x double, C64 = 2 x float per complex entry.
- *   gauge field U[mu][row][col][site4], complex interleaved, same precision as the field.
+ *   gauge field U[site4][mu][row][col] (the 36 entries of a site contiguous), complex
+ *               interleaved, same precision as the field.
  *   coarse vector v[rhs][site_c][k], k < Nb = 2*nvec, site_c ordered like site4 over the
  *               coarse lattice (extent L[mu]/block[mu]); C128 or C64.
  *   basis, A:   opaque device buffers of hdcr_basis_bytes() / hdcr_coarse_bytes() bytes;

@@ -99,10 +99,11 @@ def unpack_fermion(psi_soa: np.ndarray, L, Ls: int) -> np.ndarray:
 
 
 def pack_gauge(U_aos: np.ndarray) -> np.ndarray:
-    """[t, z, y, x, mu, row, col] -> [mu, row, col, V4]."""
+    """[t, z, y, x, mu, row, col] -> [V4, mu, row, col] (site-major: the 36
+    link entries of a site are contiguous)."""
     sh = U_aos.shape
     V4 = sh[0] * sh[1] * sh[2] * sh[3]
-    return np.ascontiguousarray(U_aos.reshape(V4, 4, 3, 3).transpose(1, 2, 3, 0))
+    return np.ascontiguousarray(U_aos.reshape(V4, 4, 3, 3))
 
 
 # ----------------------------------------------------------------------------

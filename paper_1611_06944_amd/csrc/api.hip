@@ -52,7 +52,13 @@ void choose_traversal(FineGeom& g, int tslab, int ysplit) {
         if (tslab < 1) tslab = 1;
     }
     if (Lt % tslab != 0) tslab = Lt;
-    if (ysplit <= 0) ysplit = 1;
+    if (ysplit <= 0) {
+        // y parts of about 8 rows: the z-neighbour re-reads of a slab stay
+        // within the XCD's L2 (measured best at 24^4 x 16)
+        ysplit = Ly / 8;
+        if (ysplit < 1) ysplit = 1;
+        while (ysplit > 1 && Ly % ysplit != 0) --ysplit;
+    }
     if (Ly % ysplit != 0) ysplit = 1;
     g.tslab = tslab;
     g.ysplit = ysplit;
@@ -71,8 +77,8 @@ int check_fine_desc(const hdcr_fine_desc* d) {
     }
     if (d->Ls < 1) return fail(HDCR_EINVAL, "Ls must be >= 1");
     // kernels address a whole FP64 field with 32-bit byte offsets
-    if (v * d->Ls * 12 * 16 >= (int64_t(1) << 32))
-        return fail(HDCR_EINVAL, "lattice too large (an FP64 fine field must stay below 4 GiB)");
+    if (v * d->Ls * 12 * 16 >= (int64_t(1) << 32) || v * 36 * 16 >= (int64_t(1) << 32))
+        return fail(HDCR_EINVAL, "lattice too large (an FP64 fine field and gauge field must stay below 4 GiB)");
     if (!std::isfinite(d->M5) || !std::isfinite(d->mf)) return fail(HDCR_EINVAL, "M5 and mf must be finite");
     return HDCR_OK;
 }

@@ -1,15 +1,18 @@
 // Fine operator H = Gamma5 D_dwf (Sec. 3) for gfx950.
 //
-// Work-items own SPT consecutive fifth-dimension coordinates of one 4d site,
-// s fastest, so a 64-wide wavefront covers a few consecutive 4d sites times
-// all of Ls: every component load of the site-major SoA field psi[c][site4][s]
-// is one contiguous run (SPT = 2 turns the FP32 loads into 16-byte ones), and
-// the fifth-dimension neighbours come from the same cache lines as the site.
+// One work-item per 5d site (x, s), s fastest, so a 64-wide wavefront covers
+// 64/Ls whole 4d sites (Ls dividing 64): every component load of the
+// site-major SoA field psi[c][site4][s] is one contiguous run.
 //
-// The SU(3) links of the sites a workgroup touches (forward links at the site,
-// backward links at the site minus mu) are staged once into LDS, so the Ls
-// work-items sharing a link read it from LDS instead of issuing their own
-// vector-memory loads.
+// Data-return traffic of the vector memory path is what limits a gather
+// stencil on this chip, so the tile kernel keeps it to the spinor gathers:
+//  * the 8 SU(3) links a 4d site needs (forward links at the site, backward
+//    links at the site minus mu) are loaded once per site by its Ls
+//    work-items into LDS, instead of once per work-item;
+//  * for Ls = 8 and 16 the fifth-dimension neighbours psi(s -+ 1) are taken
+//    from the neighbouring lanes with DPP moves instead of memory loads.
+// The generic kernel (other Ls, and the hop-class split used by the coarse
+// build) loads links and fifth-dimension neighbours directly.
 //
 // Field loads and stores go through buffer descriptors: the per-lane part of an
 // address is one 32-bit byte offset per neighbouring site, the component offset
@@ -25,9 +28,10 @@
 // w_t = 1),
 //   (1 - g_mu) psi = (h, -w_mu^dag h),  h = u - w_mu d,
 //   (1 + g_mu) psi = (h, +w_mu^dag h),  h = u + w_mu d,
-// so each hop multiplies a half spinor (2 spins x 3 colours) by the link.
-// The output is written at (x, Ls-1-s) with the lower spins negated:
-// H = gamma5 R5 D.
+// so each hop multiplies a half spinor (2 spins x 3 colours) by the link; the
+// hop coefficient (-1/2, times bc[mu] across the boundary) is applied in the
+// accumulating FMAs.  The output is written at (x, Ls-1-s) with the lower
+// spins negated: H = gamma5 R5 D.
 #include "coarse.h"
 
 namespace hdcr {
@@ -35,9 +39,7 @@ namespace hdcr {
 namespace {
 
 constexpr int WG = 256;
-constexpr int MIN_SLOTS = 8;                 // work-items per site required by the LDS-link variant
-constexpr int MAX_WG_SITES = WG / MIN_SLOTS + 1;
-constexpr int LINK_STRIDE = 8 * 9 + 1;       // complex entries per staged site (padded against bank conflicts)
+constexpr int LPAD = 10;  // complex entries per staged link matrix (9 used; keeps FP32 matrices 16-byte aligned)
 
 // Hop-class selection used by the little-Dirac-operator build: cls = -1 keeps
 // every term; cls = 0 keeps the diagonal, the fifth-dimension hops and the 4d
@@ -51,40 +53,6 @@ struct ClassSel {
 struct FieldRefs {
     __amdgpu_buffer_rsrc_t in, U, out;
     uint32_t cstride;  // bytes between field components (N5 complex)
-    uint32_t lstride;  // bytes between link elements (V4 complex)
-};
-
-// SPT consecutive complex entries of one component
-template <typename T, int SPT> struct Vec;
-template <typename T> struct Vec<T, 1> {
-    static __device__ __forceinline__ void ld(const __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, C2<T> (&o)[1]) {
-        o[0] = Buf<T>::ld(r, v, s);
-    }
-    static __device__ __forceinline__ void st(const C2<T> (&a)[1], __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        Buf<T>::st(a[0], r, v, s);
-    }
-};
-template <> struct Vec<float, 2> {
-    typedef __attribute__((ext_vector_type(4))) unsigned u4;
-    static __device__ __forceinline__ void ld(const __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, float2 (&o)[2]) {
-        const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0));
-        o[0] = make_float2(q.x, q.y);
-        o[1] = make_float2(q.z, q.w);
-    }
-    static __device__ __forceinline__ void st(const float2 (&a)[2], __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        const float4 q = make_float4(a[0].x, a[0].y, a[1].x, a[1].y);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, q), r, v, s, 0);
-    }
-};
-template <> struct Vec<double, 2> {
-    static __device__ __forceinline__ void ld(const __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, double2 (&o)[2]) {
-        o[0] = Buf<double>::ld(r, v, s);
-        o[1] = Buf<double>::ld(r, v + 16, s);
-    }
-    static __device__ __forceinline__ void st(const double2 (&a)[2], __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        Buf<double>::st(a[0], r, v, s);
-        Buf<double>::st(a[1], r, v + 16, s);
-    }
 };
 
 // H[r] = sum_c U[r][c] h[c]  (DAG = false)   or   sum_c conj(U[c][r]) h[c]  (DAG = true)
@@ -104,73 +72,65 @@ __device__ __forceinline__ void su3_mul(const C2<T> (&u)[9], const C2<T> (&h)[3]
     }
 }
 
-// One hop in direction MU (0..3 = x, y, z, t), forward (FWD) or backward, for
-// the SPT fifth-dimension slots of a work-item: psi at the neighbouring site
-// (byte offset noff of its first slot), link u, scaled by coef (-1/2 times the
-// boundary sign), added into acc.
-template <typename T, int SPT, int MU, bool FWD>
+// y += a x  and  y += a (i x)
+template <typename T> __device__ __forceinline__ void axpy(T a, C2<T> x, C2<T>& y) {
+    y.x = fma(a, x.x, y.x);
+    y.y = fma(a, x.y, y.y);
+}
+template <typename T> __device__ __forceinline__ void axpy_i(T a, C2<T> x, C2<T>& y) {
+    y.x = fma(-a, x.y, y.x);
+    y.y = fma(a, x.x, y.y);
+}
+
+// One hop in direction MU (0..3 = x, y, z, t), forward (FWD) or backward:
+// psi at the neighbouring 5d site (byte offset noff), link u (U_mu(x) forward,
+// U_mu(x - mu) backward), hop coefficient coef, accumulated into acc.
+template <typename T, int MU, bool FWD>
 __device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<T> (&u)[9], T coef,
-                                    C2<T> (&acc)[SPT][12]) {
-    C2<T> h0[SPT][3], h1[SPT][3];
+                                    C2<T> (&acc)[12]) {
+    C2<T> h0[3], h1[3];
 #pragma unroll
     for (int col = 0; col < 3; ++col) {
-        C2<T> u0[SPT], u1[SPT], d0[SPT], d1[SPT];
-        Vec<T, SPT>::ld(f.in, noff, (uint32_t)(0 * 3 + col) * f.cstride, u0);
-        Vec<T, SPT>::ld(f.in, noff, (uint32_t)(1 * 3 + col) * f.cstride, u1);
-        Vec<T, SPT>::ld(f.in, noff, (uint32_t)(2 * 3 + col) * f.cstride, d0);
-        Vec<T, SPT>::ld(f.in, noff, (uint32_t)(3 * 3 + col) * f.cstride, d1);
-#pragma unroll
-        for (int k = 0; k < SPT; ++k) {
-            // h = u -+ w_mu d  (minus for the forward hop (1 - g), plus for backward (1 + g))
-            C2<T> a, b;
-            if (MU == 0) {        // w_x d = (-i d1, -i d0)
-                a = FWD ? cadd<T>(u0[k], cmuli<T>(d1[k])) : csub<T>(u0[k], cmuli<T>(d1[k]));
-                b = FWD ? cadd<T>(u1[k], cmuli<T>(d0[k])) : csub<T>(u1[k], cmuli<T>(d0[k]));
-            } else if (MU == 1) { // w_y d = (-d1, d0)
-                a = FWD ? cadd<T>(u0[k], d1[k]) : csub<T>(u0[k], d1[k]);
-                b = FWD ? csub<T>(u1[k], d0[k]) : cadd<T>(u1[k], d0[k]);
-            } else if (MU == 2) { // w_z d = (-i d0, i d1)
-                a = FWD ? cadd<T>(u0[k], cmuli<T>(d0[k])) : csub<T>(u0[k], cmuli<T>(d0[k]));
-                b = FWD ? csub<T>(u1[k], cmuli<T>(d1[k])) : cadd<T>(u1[k], cmuli<T>(d1[k]));
-            } else {              // w_t d = (d0, d1)
-                a = FWD ? csub<T>(u0[k], d0[k]) : cadd<T>(u0[k], d0[k]);
-                b = FWD ? csub<T>(u1[k], d1[k]) : cadd<T>(u1[k], d1[k]);
-            }
-            h0[k][col] = cscale<T>(coef, a);
-            h1[k][col] = cscale<T>(coef, b);
+        const C2<T> u0 = Buf<T>::ld(f.in, noff, (uint32_t)(0 * 3 + col) * f.cstride);
+        const C2<T> u1 = Buf<T>::ld(f.in, noff, (uint32_t)(1 * 3 + col) * f.cstride);
+        const C2<T> d0 = Buf<T>::ld(f.in, noff, (uint32_t)(2 * 3 + col) * f.cstride);
+        const C2<T> d1 = Buf<T>::ld(f.in, noff, (uint32_t)(3 * 3 + col) * f.cstride);
+        // h = u -+ w_mu d  (minus for the forward hop (1 - g), plus for backward (1 + g))
+        if (MU == 0) {        // w_x d = (-i d1, -i d0)
+            h0[col] = FWD ? cadd<T>(u0, cmuli<T>(d1)) : csub<T>(u0, cmuli<T>(d1));
+            h1[col] = FWD ? cadd<T>(u1, cmuli<T>(d0)) : csub<T>(u1, cmuli<T>(d0));
+        } else if (MU == 1) { // w_y d = (-d1, d0)
+            h0[col] = FWD ? cadd<T>(u0, d1) : csub<T>(u0, d1);
+            h1[col] = FWD ? csub<T>(u1, d0) : cadd<T>(u1, d0);
+        } else if (MU == 2) { // w_z d = (-i d0, i d1)
+            h0[col] = FWD ? cadd<T>(u0, cmuli<T>(d0)) : csub<T>(u0, cmuli<T>(d0));
+            h1[col] = FWD ? csub<T>(u1, cmuli<T>(d1)) : cadd<T>(u1, cmuli<T>(d1));
+        } else {              // w_t d = (d0, d1)
+            h0[col] = FWD ? csub<T>(u0, d0) : cadd<T>(u0, d0);
+            h1[col] = FWD ? csub<T>(u1, d1) : cadd<T>(u1, d1);
         }
     }
+    C2<T> H0[3], H1[3];
+    su3_mul<T, !FWD>(u, h0, H0);
+    su3_mul<T, !FWD>(u, h1, H1);
+    // upper spins += coef H; lower spins -+= coef w^dag H (minus forward, plus backward)
+    const T sl = FWD ? -coef : coef;
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-        C2<T> H0[3], H1[3];
-        su3_mul<T, !FWD>(u, h0[k], H0);
-        su3_mul<T, !FWD>(u, h1[k], H1);
-#pragma unroll
-        for (int col = 0; col < 3; ++col) {
-            acc[k][0 * 3 + col] = cadd<T>(acc[k][0 * 3 + col], H0[col]);
-            acc[k][1 * 3 + col] = cadd<T>(acc[k][1 * 3 + col], H1[col]);
-            // lower spins: -w^dag H (forward) or +w^dag H (backward)
-            C2<T> l0, l1;
-            if (MU == 0) {        // w_x^dag H = (i H1, i H0)
-                l0 = cmuli<T>(H1[col]);
-                l1 = cmuli<T>(H0[col]);
-            } else if (MU == 1) { // w_y^dag H = (H1, -H0)
-                l0 = H1[col];
-                l1 = cneg<T>(H0[col]);
-            } else if (MU == 2) { // w_z^dag H = (i H0, -i H1)
-                l0 = cmuli<T>(H0[col]);
-                l1 = cmulmi<T>(H1[col]);
-            } else {              // w_t^dag H = (H0, H1)
-                l0 = H0[col];
-                l1 = H1[col];
-            }
-            if (FWD) {
-                acc[k][2 * 3 + col] = csub<T>(acc[k][2 * 3 + col], l0);
-                acc[k][3 * 3 + col] = csub<T>(acc[k][3 * 3 + col], l1);
-            } else {
-                acc[k][2 * 3 + col] = cadd<T>(acc[k][2 * 3 + col], l0);
-                acc[k][3 * 3 + col] = cadd<T>(acc[k][3 * 3 + col], l1);
-            }
+    for (int col = 0; col < 3; ++col) {
+        axpy<T>(coef, H0[col], acc[0 * 3 + col]);
+        axpy<T>(coef, H1[col], acc[1 * 3 + col]);
+        if (MU == 0) {        // w_x^dag H = (i H1, i H0)
+            axpy_i<T>(sl, H1[col], acc[2 * 3 + col]);
+            axpy_i<T>(sl, H0[col], acc[3 * 3 + col]);
+        } else if (MU == 1) { // w_y^dag H = (H1, -H0)
+            axpy<T>(sl, H1[col], acc[2 * 3 + col]);
+            axpy<T>(-sl, H0[col], acc[3 * 3 + col]);
+        } else if (MU == 2) { // w_z^dag H = (i H0, -i H1)
+            axpy_i<T>(sl, H0[col], acc[2 * 3 + col]);
+            axpy_i<T>(-sl, H1[col], acc[3 * 3 + col]);
+        } else {              // w_t^dag H = (H0, H1)
+            axpy<T>(sl, H0[col], acc[2 * 3 + col]);
+            axpy<T>(sl, H1[col], acc[3 * 3 + col]);
         }
     }
 }
@@ -208,170 +168,254 @@ __device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
     return tr;
 }
 
-template <typename T, int SPT, bool LDSL, bool CLS, int MU>
-__device__ __forceinline__ void hop_pair(const FineGeom& g, const FieldRefs& f, const Site& st, int s0,
-                                         const C2<T>* lnk, const ClassSel& cs, C2<T> (&acc)[SPT][12]) {
-    constexpr uint32_t CB = sizeof(C2<T>);
-    const int site = st.site;
-    const int xmu = st.x[MU];
-    // branch-free neighbour indices: the wrap-around is a select between uniform steps
-    const bool wrap_f = (xmu == g.L[MU] - 1);
-    const bool wrap_b = (xmu == 0);
-    const int sf = site + (wrap_f ? -g.wrap[MU] : g.stride[MU]);
-    const int sb = site + (wrap_b ? g.wrap[MU] : -g.stride[MU]);
-    const T half = (T)(-0.5);
-    T cf = wrap_f ? half * (T)g.bc[MU] : half;
-    T cb = wrap_b ? half * (T)g.bc[MU] : half;
-    if constexpr (CLS) {
-        // keep a hop only if its class is the selected one
-        const int lx = xmu % cs.B[MU];
-        const bool cross_f = (lx == cs.B[MU] - 1), cross_b = (lx == 0);
-        const bool keep_f = cross_f ? (cs.cls == 1 + MU) : (cs.cls == 0);
-        const bool keep_b = cross_b ? (cs.cls == 5 + MU) : (cs.cls == 0);
-        cf = keep_f ? cf : (T)0;
-        cb = keep_b ? cb : (T)0;
+// Neighbouring 4d sites of a work-item's site and the hop coefficients
+// (-1/2, times bc[mu] for a hop across the lattice boundary).  The wrap-around
+// is a select between uniform steps, so no branch depends on the lane.
+template <typename T> struct Nbrs {
+    int f[4], b[4];
+    T cf[4], cb[4];
+};
+template <typename T> __device__ __forceinline__ Nbrs<T> neighbours(const FineGeom& g, const Site& st) {
+    Nbrs<T> n;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const bool wf = (st.x[mu] == g.L[mu] - 1), wb = (st.x[mu] == 0);
+        n.f[mu] = st.site + (wf ? -g.wrap[mu] : g.stride[mu]);
+        n.b[mu] = st.site + (wb ? g.wrap[mu] : -g.stride[mu]);
+        const T half = (T)(-0.5);
+        n.cf[mu] = wf ? half * (T)g.bc[mu] : half;
+        n.cb[mu] = wb ? half * (T)g.bc[mu] : half;
     }
-    C2<T> u[9];
-    // forward: -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
-    if constexpr (LDSL) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = lnk[MU * 9 + e];
-    } else {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)site * CB, (uint32_t)(MU * 9 + e) * f.lstride);
-    }
-    hop<T, SPT, MU, true>(f, (uint32_t)(sf * g.Ls + s0) * CB, u, cf, acc);
-    // backward: -1/2 (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
-    if constexpr (LDSL) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = lnk[(4 + MU) * 9 + e];
-    } else {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)sb * CB, (uint32_t)(MU * 9 + e) * f.lstride);
-    }
-    hop<T, SPT, MU, false>(f, (uint32_t)(sb * g.Ls + s0) * CB, u, cb, acc);
+    return n;
 }
 
-// SPT: fifth-dimension slots per work-item; LDSL: links staged in LDS
-// (requires Ls / SPT >= MIN_SLOTS).
-template <typename T, int SPT, bool LDSL, bool CLS>
+// DPP lane moves inside a row of 16 lanes (dpp_ctrl row_shl:n = 0x100 + n,
+// row_shr:n = 0x110 + n, row_ror:n = 0x120 + n).
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_f(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, typename T> __device__ __forceinline__ C2<T> dpp_c(C2<T> v) {
+    return mk<T>(dpp_f<CTRL>(v.x), dpp_f<CTRL>(v.y));
+}
+// value held by the lane of fifth coordinate s - 1 (DOWN) or s + 1, cyclic in
+// groups of LS lanes (LS = 8 or 16, so a group never straddles a DPP row)
+template <typename T, int LS, bool DOWN> __device__ __forceinline__ C2<T> s_neighbour(C2<T> v, int s) {
+    if constexpr (LS == 16) {
+        return DOWN ? dpp_c<0x121, T>(v) : dpp_c<0x12F, T>(v);
+    } else {
+        static_assert(LS == 8, "DPP fifth-dimension exchange needs LS = 8 or 16");
+        if (DOWN) {
+            const C2<T> a = dpp_c<0x111, T>(v), w = dpp_c<0x100 + LS - 1, T>(v);
+            return (s == 0) ? w : a;
+        } else {
+            const C2<T> a = dpp_c<0x101, T>(v), w = dpp_c<0x110 + LS - 1, T>(v);
+            return (s == LS - 1) ? w : a;
+        }
+    }
+}
+
+template <typename T, int MU>
+__device__ __forceinline__ void hop_pair_lds(const FieldRefs& f, const Nbrs<T>& n, int Ls, int s, const C2<T>* lnk,
+                                             C2<T> (&acc)[12]) {
+    constexpr uint32_t CB = sizeof(C2<T>);
+    C2<T> u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = lnk[MU * LPAD + e];
+    hop<T, MU, true>(f, (uint32_t)(n.f[MU] * Ls + s) * CB, u, n.cf[MU], acc);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = lnk[(4 + MU) * LPAD + e];
+    hop<T, MU, false>(f, (uint32_t)(n.b[MU] * Ls + s) * CB, u, n.cb[MU], acc);
+}
+
+// Tile kernel: Ls = LS divides WG; a workgroup holds WG / LS whole 4d sites.
+// NT: stores with the non-temporal hint (streamed past the L2).
+template <typename T, int LS, bool NT>
+__global__ void __launch_bounds__(WG) dslash_tile_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out) {
+    constexpr uint32_t CB = sizeof(C2<T>);
+    constexpr int SITES = WG / LS;
+    constexpr bool DPP = (LS == 8 || LS == 16);
+    __shared__ C2<T> lds[SITES * 8 * LPAD];
+
+    const int lb = logical_block(blockIdx.x, gridDim.x);
+    const int gid = lb * WG + threadIdx.x;
+    const int lsite = gid / LS;
+    const int s = gid % LS;
+    const int j = threadIdx.x / LS;  // site slot inside the workgroup
+    const bool active = lsite < g.V4;
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+
+    const Site st = traverse(g, active ? lsite : 0);
+    const Nbrs<T> n = neighbours<T>(g, st);
+
+    // stage the 8 link matrices of the site: matrix d < 4 is U_d(x), d >= 4 is
+    // U_{d-4}(x - (d-4)); the LS work-items of the site load 9 entries each pass
+    if (active) {
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int src = (d < 4) ? st.site : n.b[d - 4];
+#pragma unroll
+            for (int e0 = 0; e0 < 9; e0 += LS) {
+                const int e = e0 + s;
+                if (e < 9)
+                    lds[(j * 8 + d) * LPAD + e] =
+                        Buf<T>::ld(f.U, (uint32_t)(src * 36 + (d & 3) * 9 + e) * CB, 0u);
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const C2<T>* lnk = lds + j * 8 * LPAD;
+
+    // diagonal (5 - M5) and the fifth-dimension hops: -P+ psi(s-1) on the upper
+    // spins, -P- psi(s+1) on the lower spins, +mf across the walls
+    C2<T> acc[12];
+    {
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (s == 0) ? mf : (T)-1;
+        const T cp = (s == LS - 1) ? mf : (T)-1;
+        const uint32_t o0 = (uint32_t)(st.site * LS + s) * CB;
+        const uint32_t om = (uint32_t)(st.site * LS + (s == 0 ? LS - 1 : s - 1)) * CB;
+        const uint32_t op = (uint32_t)(st.site * LS + (s == LS - 1 ? 0 : s + 1)) * CB;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const C2<T> v = Buf<T>::ld(f.in, o0, (uint32_t)c * f.cstride);
+            C2<T> w;
+            if constexpr (DPP)
+                w = (c < 6) ? s_neighbour<T, LS, true>(v, s) : s_neighbour<T, LS, false>(v, s);
+            else
+                w = Buf<T>::ld(f.in, (c < 6) ? om : op, (uint32_t)c * f.cstride);
+            const T cw = (c < 6) ? cm : cp;
+            acc[c] = mk<T>(fma(diag, v.x, cw * w.x), fma(diag, v.y, cw * w.y));
+        }
+    }
+    hop_pair_lds<T, 0>(f, n, LS, s, lnk, acc);
+    hop_pair_lds<T, 1>(f, n, LS, s, lnk, acc);
+    hop_pair_lds<T, 2>(f, n, LS, s, lnk, acc);
+    hop_pair_lds<T, 3>(f, n, LS, s, lnk, acc);
+
+    const uint32_t oo = (uint32_t)(st.site * LS + (LS - 1 - s)) * CB;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const C2<T> o = (c < 6) ? acc[c] : cneg<T>(acc[c]);
+        if constexpr (NT)
+            Buf<T>::st_nt(o, f.out, oo, (uint32_t)c * f.cstride);
+        else
+            Buf<T>::st(o, f.out, oo, (uint32_t)c * f.cstride);
+    }
+}
+
+// Generic kernel: any Ls, links and fifth-dimension neighbours loaded
+// directly; CLS selects one hop class (coarse-operator build).
+template <typename T, bool CLS>
 __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out,
                                                         ClassSel cs) {
     constexpr uint32_t CB = sizeof(C2<T>);
     const int lb = logical_block(blockIdx.x, gridDim.x);
-    const int slots = g.Ls / SPT;  // work-items per 4d site
+    const int Ls = g.Ls;
     const int gid = lb * WG + threadIdx.x;
-    const bool active = gid < g.V4 * slots;
+    if (gid >= g.N5) return;
     FieldRefs f;
     f.cstride = (uint32_t)g.N5 * CB;
-    f.lstride = (uint32_t)g.V4 * CB;
     f.in = make_rsrc(in, 12u * f.cstride);
     f.out = make_rsrc(out, 12u * f.cstride);
-    f.U = make_rsrc(U, 36u * f.lstride);
-
-    const int lsite = gid / slots;
-    const int s0 = (gid % slots) * SPT;
-
-    __shared__ C2<T> lds_links[LDSL ? MAX_WG_SITES * LINK_STRIDE : 1];
-    const C2<T>* lnk = nullptr;
-    if (LDSL) {
-        // stage the forward links U_mu(x) and backward links U_mu(x - mu) of every site of the workgroup
-        const int first = (lb * WG) / slots;
-        const int last = min((lb * WG + WG - 1) / slots, g.V4 - 1);
-        const int ns = last - first + 1;
-        for (int e = threadIdx.x; e < ns * 72; e += WG) {
-            const int sl = e / 72, r = e - sl * 72;
-            const int d = r / 9, el = r - d * 9;
-            const int mu = d & 3;
-            const Site t = traverse(g, first + sl);
-            const int src = (d < 4) ? t.site : ((t.x[mu] == 0) ? t.site + g.wrap[mu] : t.site - g.stride[mu]);
-            lds_links[sl * LINK_STRIDE + r] = Buf<T>::ld(f.U, (uint32_t)src * CB, (uint32_t)(mu * 9 + el) * f.lstride);
-        }
-        __syncthreads();
-        lnk = lds_links + (lsite - first) * LINK_STRIDE;
-    }
-    if (!active) return;
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    const int lsite = gid / Ls;
+    const int s = gid - lsite * Ls;
     const Site st = traverse(g, lsite);
-    const int site = st.site;
-    const int Ls = g.Ls;
-
-    C2<T> acc[SPT][12];
-    // diagonal (5 - M5) and the fifth-dimension hops: -P+ psi(s-1) on the upper
-    // spins, -P- psi(s+1) on the lower spins, +mf on the walls
+    Nbrs<T> n = neighbours<T>(g, st);
+    if constexpr (CLS) {
+        // keep a hop only if its class is the selected one
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const int lx = st.x[mu] % cs.B[mu];
+            const bool keep_f = (lx == cs.B[mu] - 1) ? (cs.cls == 1 + mu) : (cs.cls == 0);
+            const bool keep_b = (lx == 0) ? (cs.cls == 5 + mu) : (cs.cls == 0);
+            n.cf[mu] = keep_f ? n.cf[mu] : (T)0;
+            n.cb[mu] = keep_b ? n.cb[mu] : (T)0;
+        }
+    }
+    C2<T> acc[12];
     {
         // the diagonal and fifth-dimension terms belong to hop class 0
         const T keep = (!CLS || cs.cls == 0) ? (T)1 : (T)0;
-        const T diag = keep * (T)g.diag;
-        const T mf = keep * (T)g.mf;
-        const int sm = (s0 == 0) ? Ls - 1 : s0 - 1;           // below the first slot
-        const int sp = (s0 + SPT == Ls) ? 0 : s0 + SPT;        // above the last slot
-        const T cm = (s0 == 0) ? mf : -keep;
-        const T cp = (s0 + SPT == Ls) ? mf : -keep;
-        const uint32_t o0 = (uint32_t)(site * Ls + s0) * CB;
-        const uint32_t om = (uint32_t)(site * Ls + sm) * CB;
-        const uint32_t op = (uint32_t)(site * Ls + sp) * CB;
+        const T diag = keep * (T)g.diag, mf = keep * (T)g.mf;
+        const T cm = (s == 0) ? mf : -keep;
+        const T cp = (s == Ls - 1) ? mf : -keep;
+        const uint32_t o0 = (uint32_t)(st.site * Ls + s) * CB;
+        const uint32_t om = (uint32_t)(st.site * Ls + (s == 0 ? Ls - 1 : s - 1)) * CB;
+        const uint32_t op = (uint32_t)(st.site * Ls + (s == Ls - 1 ? 0 : s + 1)) * CB;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            C2<T> v[SPT];
-            Vec<T, SPT>::ld(f.in, o0, (uint32_t)c * f.cstride, v);
+            const C2<T> v = Buf<T>::ld(f.in, o0, (uint32_t)c * f.cstride);
             const C2<T> w = Buf<T>::ld(f.in, (c < 6) ? om : op, (uint32_t)c * f.cstride);
-#pragma unroll
-            for (int k = 0; k < SPT; ++k) {
-                // neighbour in s: upper spins take s-1, lower spins s+1
-                C2<T> nb;
-                T cw;
-                if (c < 6) {
-                    nb = (k == 0) ? w : v[k > 0 ? k - 1 : 0];
-                    cw = (k == 0) ? cm : -keep;
-                } else {
-                    nb = (k == SPT - 1) ? w : v[k + 1 < SPT ? k + 1 : k];
-                    cw = (k == SPT - 1) ? cp : -keep;
-                }
-                acc[k][c] = mk<T>(diag * v[k].x + cw * nb.x, diag * v[k].y + cw * nb.y);
-            }
+            const T cw = (c < 6) ? cm : cp;
+            acc[c] = mk<T>(fma(diag, v.x, cw * w.x), fma(diag, v.y, cw * w.y));
         }
     }
-    hop_pair<T, SPT, LDSL, CLS, 0>(g, f, st, s0, lnk, cs, acc);
-    hop_pair<T, SPT, LDSL, CLS, 1>(g, f, st, s0, lnk, cs, acc);
-    hop_pair<T, SPT, LDSL, CLS, 2>(g, f, st, s0, lnk, cs, acc);
-    hop_pair<T, SPT, LDSL, CLS, 3>(g, f, st, s0, lnk, cs, acc);
-
-    // slot k (s = s0 + k) goes to s' = Ls - 1 - s0 - k: the SPT outputs are
-    // consecutive, in reverse order, starting at Ls - s0 - SPT
-    const uint32_t oo = (uint32_t)(site * Ls + (Ls - s0 - SPT)) * CB;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        C2<T> o[SPT];
-#pragma unroll
-        for (int k = 0; k < SPT; ++k) o[SPT - 1 - k] = (c < 6) ? acc[k][c] : cneg<T>(acc[k][c]);
-        Vec<T, SPT>::st(o, f.out, oo, (uint32_t)c * f.cstride);
+#define HDCR_GENERIC_HOPS(MU)                                                                              \
+    {                                                                                                      \
+        C2<T> u[9];                                                                                        \
+        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)st.site * (36u * CB), (uint32_t)(MU * 9 + e) * CB); \
+        hop<T, MU, true>(f, (uint32_t)(n.f[MU] * Ls + s) * CB, u, n.cf[MU], acc);                          \
+        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)n.b[MU] * (36u * CB), (uint32_t)(MU * 9 + e) * CB); \
+        hop<T, MU, false>(f, (uint32_t)(n.b[MU] * Ls + s) * CB, u, n.cb[MU], acc);                         \
     }
+    HDCR_GENERIC_HOPS(0)
+    HDCR_GENERIC_HOPS(1)
+    HDCR_GENERIC_HOPS(2)
+    HDCR_GENERIC_HOPS(3)
+#undef HDCR_GENERIC_HOPS
+    const uint32_t oo = (uint32_t)(st.site * Ls + (Ls - 1 - s)) * CB;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) Buf<T>::st((c < 6) ? acc[c] : cneg<T>(acc[c]), f.out, oo, (uint32_t)c * f.cstride);
 }
 
-template <typename T, int SPT, bool LDSL, bool CLS = false>
-void launch_variant(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s,
+template <typename T, int LS, bool NT>
+void launch_tile(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+    const int blocks = (g.N5 + WG - 1) / WG;
+    hipLaunchKernelGGL((dslash_tile_kernel<T, LS, NT>), dim3(blocks), dim3(WG), 0, s, g, U, in, out);
+}
+
+template <typename T, bool CLS>
+void launch_generic(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s,
                     ClassSel cs = ClassSel{{1, 1, 1, 1}, -1}) {
-    const int items = g.V4 * (g.Ls / SPT);
-    const int blocks = (items + WG - 1) / WG;
-    hipLaunchKernelGGL((dslash_dwf_kernel<T, SPT, LDSL, CLS>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs);
+    const int blocks = (g.N5 + WG - 1) / WG;
+    hipLaunchKernelGGL((dslash_dwf_kernel<T, CLS>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs);
+}
+
+template <typename T, bool NT>
+bool launch_tile_ls(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+    switch (g.Ls) {
+        case 8: launch_tile<T, 8, NT>(g, U, in, out, s); return true;
+        case 16: launch_tile<T, 16, NT>(g, U, in, out, s); return true;
+        case 32: launch_tile<T, 32, NT>(g, U, in, out, s); return true;
+        case 64: launch_tile<T, 64, NT>(g, U, in, out, s); return true;
+        default: return false;
+    }
 }
 
 }  // namespace
 
 template <typename T>
 void launch_dslash(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
-    // variant 0 (default) and 2: one slot per work-item, links from global
-    // memory (measured fastest at 24^4 x 16).  variant 1: links staged in LDS
-    // (one slot; FP32 with Ls/2 >= MIN_SLOTS takes two slots).  The LDS
-    // variants need Ls / SPT >= MIN_SLOTS and fall back otherwise.
-    if (g.variant == 1 && g.Ls >= MIN_SLOTS) {
-        if (sizeof(T) == 4 && g.Ls % 2 == 0 && g.Ls / 2 >= MIN_SLOTS)
-            launch_variant<T, 2, true>(g, U, in, out, s);
-        else
-            launch_variant<T, 1, true>(g, U, in, out, s);
-    } else {
-        launch_variant<T, 1, false>(g, U, in, out, s);
+    // tile kernel for Ls = 8, 16, 32, 64 with non-temporal output stores (the
+    // output is not re-read by this launch; streaming it keeps the L2 for the
+    // neighbour re-reads); variant 1: cached stores, variant 2: generic kernel
+    if (g.variant != 2) {
+        if (g.variant == 1 ? launch_tile_ls<T, false>(g, U, in, out, s) : launch_tile_ls<T, true>(g, U, in, out, s))
+            return;
     }
+    launch_generic<T, false>(g, U, in, out, s);
 }
 
 void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
@@ -379,7 +423,7 @@ void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* i
     ClassSel cs;
     for (int mu = 0; mu < 4; ++mu) cs.B[mu] = c.B[mu];
     cs.cls = cls;
-    launch_variant<double, 1, false, true>(c.f, U, in, out, s, cs);
+    launch_generic<double, true>(c.f, U, in, out, s, cs);
 }
 
 template void launch_dslash<double>(const FineGeom&, const double2*, const double2*, double2*, hipStream_t);

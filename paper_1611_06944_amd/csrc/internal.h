@@ -64,6 +64,7 @@ template <typename T> __device__ __forceinline__ C2<T> cneg(C2<T> a) { return mk
 // address register.  Loads past the descriptor's byte range return zero.
 // ---------------------------------------------------------------------------
 constexpr int BUF_FLAGS = 0x00020000;  // gfx9 raw-buffer descriptor word 3
+constexpr int CPOL_NT = 2;             // cache-policy operand of buffer stores: non-temporal
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, BUF_FLAGS);
@@ -78,6 +79,11 @@ template <> struct Buf<double> {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
                                                voff, soff, 0);
     }
+    // store with the non-temporal hint (cache policy bit NT)
+    static __device__ __forceinline__ void st_nt(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
+                                               voff, soff, CPOL_NT);
+    }
 };
 template <> struct Buf<float> {
     static __device__ __forceinline__ float2 ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -86,6 +92,10 @@ template <> struct Buf<float> {
     static __device__ __forceinline__ void st(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
                                               voff, soff, 0);
+    }
+    static __device__ __forceinline__ void st_nt(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                              voff, soff, CPOL_NT);
     }
 };
 

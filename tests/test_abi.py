@@ -107,7 +107,8 @@ def test_layout_roundtrip():
     np.testing.assert_array_equal(unpack_fermion(soa, L, Ls), psi)
     U = hi.gauge_field(L, seed=2)
     g = pack_gauge(U)
-    assert g[3, 1, 2, ((t * 4 + z) * 3 + y) * 2 + x] == U[t, z, y, x, 3, 1, 2]
+    assert g.shape == (120, 4, 3, 3)
+    assert g[((t * 4 + z) * 3 + y) * 2 + x, 3, 1, 2] == U[t, z, y, x, 3, 1, 2]
 
 
 def test_two_level_param_validation(lib):
