@@ -233,10 +233,34 @@ __device__ __forceinline__ void hop_pair_lds(const FieldRefs& f, const Nbrs<T>& 
     hop<T, MU, false>(f, (uint32_t)(n.b[MU] * Ls + s) * CB, u, n.cb[MU], acc);
 }
 
+// Writes the 12 components of a work-item's output element (byte offset oo):
+// H = gamma5 R5 D negates the lower spins; with NY > 0 the result is
+// beta (H in) + sum_i g[i] y[i].  NT: non-temporal stores.
+template <typename T, int NY, bool NT>
+__device__ __forceinline__ void store_out(const FieldRefs& f, uint32_t oo, const Epi<T>& ep, const C2<T> (&acc)[12]) {
+    __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
+#pragma unroll
+    for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        C2<T> o = (c < 6) ? acc[c] : cneg<T>(acc[c]);
+        if constexpr (NY > 0) {
+            o = cscale<T>(ep.beta, o);
+#pragma unroll
+            for (int i = 0; i < NY; ++i) axpy<T>(ep.g[i], Buf<T>::ld(yr[i], oo, (uint32_t)c * f.cstride), o);
+        }
+        if constexpr (NT)
+            Buf<T>::st_nt(o, f.out, oo, (uint32_t)c * f.cstride);
+        else
+            Buf<T>::st(o, f.out, oo, (uint32_t)c * f.cstride);
+    }
+}
+
 // Tile kernel: Ls = LS divides WG; a workgroup holds WG / LS whole 4d sites.
-// NT: stores with the non-temporal hint (streamed past the L2).
-template <typename T, int LS, bool NT>
-__global__ void __launch_bounds__(WG) dslash_tile_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out) {
+// NT: stores with the non-temporal hint (streamed past the L2); NY: epilogue terms.
+template <typename T, int LS, bool NT, int NY>
+__global__ void __launch_bounds__(WG) dslash_tile_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out,
+                                                         Epi<T> ep) {
     constexpr uint32_t CB = sizeof(C2<T>);
     constexpr int SITES = WG / LS;
     constexpr bool DPP = (LS == 8 || LS == 16);
@@ -303,22 +327,14 @@ __global__ void __launch_bounds__(WG) dslash_tile_kernel(FineGeom g, const C2<T>
     hop_pair_lds<T, 2>(f, n, LS, s, lnk, acc);
     hop_pair_lds<T, 3>(f, n, LS, s, lnk, acc);
 
-    const uint32_t oo = (uint32_t)(st.site * LS + (LS - 1 - s)) * CB;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const C2<T> o = (c < 6) ? acc[c] : cneg<T>(acc[c]);
-        if constexpr (NT)
-            Buf<T>::st_nt(o, f.out, oo, (uint32_t)c * f.cstride);
-        else
-            Buf<T>::st(o, f.out, oo, (uint32_t)c * f.cstride);
-    }
+    store_out<T, NY, NT>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
 }
 
 // Generic kernel: any Ls, links and fifth-dimension neighbours loaded
 // directly; CLS selects one hop class (coarse-operator build).
-template <typename T, bool CLS>
+template <typename T, bool CLS, int NY>
 __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out,
-                                                        ClassSel cs) {
+                                                        ClassSel cs, Epi<T> ep) {
     constexpr uint32_t CB = sizeof(C2<T>);
     const int lb = logical_block(blockIdx.x, gridDim.x);
     const int Ls = g.Ls;
@@ -375,47 +391,67 @@ __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>*
     HDCR_GENERIC_HOPS(2)
     HDCR_GENERIC_HOPS(3)
 #undef HDCR_GENERIC_HOPS
-    const uint32_t oo = (uint32_t)(st.site * Ls + (Ls - 1 - s)) * CB;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) Buf<T>::st((c < 6) ? acc[c] : cneg<T>(acc[c]), f.out, oo, (uint32_t)c * f.cstride);
+    store_out<T, NY, false>(f, (uint32_t)(st.site * Ls + (Ls - 1 - s)) * CB, ep, acc);
 }
 
-template <typename T, int LS, bool NT>
-void launch_tile(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+template <typename T, int LS, bool NT, int NY>
+void launch_tile(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
     const int blocks = (g.N5 + WG - 1) / WG;
-    hipLaunchKernelGGL((dslash_tile_kernel<T, LS, NT>), dim3(blocks), dim3(WG), 0, s, g, U, in, out);
+    hipLaunchKernelGGL((dslash_tile_kernel<T, LS, NT, NY>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, ep);
 }
 
-template <typename T, bool CLS>
-void launch_generic(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s,
+template <typename T, bool CLS, int NY>
+void launch_generic(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s,
                     ClassSel cs = ClassSel{{1, 1, 1, 1}, -1}) {
     const int blocks = (g.N5 + WG - 1) / WG;
-    hipLaunchKernelGGL((dslash_dwf_kernel<T, CLS>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs);
+    hipLaunchKernelGGL((dslash_dwf_kernel<T, CLS, NY>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs, ep);
 }
 
-template <typename T, bool NT>
-bool launch_tile_ls(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+template <typename T, bool NT, int NY>
+bool launch_tile_ls(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep,
+                    hipStream_t s) {
     switch (g.Ls) {
-        case 8: launch_tile<T, 8, NT>(g, U, in, out, s); return true;
-        case 16: launch_tile<T, 16, NT>(g, U, in, out, s); return true;
-        case 32: launch_tile<T, 32, NT>(g, U, in, out, s); return true;
-        case 64: launch_tile<T, 64, NT>(g, U, in, out, s); return true;
+        case 8: launch_tile<T, 8, NT, NY>(g, U, in, out, ep, s); return true;
+        case 16: launch_tile<T, 16, NT, NY>(g, U, in, out, ep, s); return true;
+        case 32: launch_tile<T, 32, NT, NY>(g, U, in, out, ep, s); return true;
+        case 64: launch_tile<T, 64, NT, NY>(g, U, in, out, ep, s); return true;
         default: return false;
     }
+}
+
+// tile kernel for Ls = 8, 16, 32, 64 with non-temporal output stores (the
+// output is not re-read by this launch; streaming it keeps the L2 for the
+// neighbour re-reads); generic kernel otherwise.  Tuning switch: variant 1
+// uses cached stores for the plain apply, variant 2 the generic kernel.
+template <typename T, int NY>
+void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
+    if (g.variant != 2) {
+        if (NY == 0 && g.variant == 1) {
+            if (launch_tile_ls<T, false, NY>(g, U, in, out, ep, s)) return;
+        } else if (launch_tile_ls<T, true, NY>(g, U, in, out, ep, s)) {
+            return;
+        }
+    }
+    launch_generic<T, false, NY>(g, U, in, out, ep, s);
 }
 
 }  // namespace
 
 template <typename T>
 void launch_dslash(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
-    // tile kernel for Ls = 8, 16, 32, 64 with non-temporal output stores (the
-    // output is not re-read by this launch; streaming it keeps the L2 for the
-    // neighbour re-reads); variant 1: cached stores, variant 2: generic kernel
-    if (g.variant != 2) {
-        if (g.variant == 1 ? launch_tile_ls<T, false>(g, U, in, out, s) : launch_tile_ls<T, true>(g, U, in, out, s))
-            return;
+    launch_ny<T, 0>(g, U, in, out, Epi<T>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, (T)1, 0}, s);
+}
+
+template <typename T>
+void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& e,
+                       hipStream_t s) {
+    switch (e.ny) {
+        case 1: launch_ny<T, 1>(g, U, in, out, e, s); break;
+        case 2: launch_ny<T, 2>(g, U, in, out, e, s); break;
+        case 3: launch_ny<T, 3>(g, U, in, out, e, s); break;
+        case 4: launch_ny<T, 4>(g, U, in, out, e, s); break;
+        default: launch_ny<T, 0>(g, U, in, out, e, s); break;
     }
-    launch_generic<T, false>(g, U, in, out, s);
 }
 
 void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
@@ -423,10 +459,15 @@ void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* i
     ClassSel cs;
     for (int mu = 0; mu < 4; ++mu) cs.B[mu] = c.B[mu];
     cs.cls = cls;
-    launch_generic<double, true>(c.f, U, in, out, s, cs);
+    launch_generic<double, true, 0>(c.f, U, in, out, Epi<double>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0, 0},
+                                    s, cs);
 }
 
 template void launch_dslash<double>(const FineGeom&, const double2*, const double2*, double2*, hipStream_t);
 template void launch_dslash<float>(const FineGeom&, const float2*, const float2*, float2*, hipStream_t);
+template void launch_dslash_epi<double>(const FineGeom&, const double2*, const double2*, double2*, const Epi<double>&,
+                                        hipStream_t);
+template void launch_dslash_epi<float>(const FineGeom&, const float2*, const float2*, float2*, const Epi<float>&,
+                                       hipStream_t);
 
 }  // namespace hdcr

@@ -155,6 +155,19 @@ int check_ptr(const void* p, size_t align, const char* name);
 template <typename T>
 void launch_dslash(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s);
 
+// Fused epilogue of a stencil launch: out = beta (H in) + sum_{i < ny} g[i] y[i]
+// (0 <= ny <= 4).  y[i] is read at the element the work-item writes, before the
+// write, so y[i] may be the output buffer itself; it must not be `in`.
+template <typename T> struct Epi {
+    const C2<T>* y[4];
+    T g[4];
+    T beta;
+    int ny;
+};
+template <typename T>
+void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& e,
+                       hipStream_t s);
+
 // Reductions: every reduction writes REDUCE_BLOCKS partial sums (as double2)
 // into `partials` and a finalize step sums them in fixed order into `result`.
 constexpr int REDUCE_BLOCKS = 1024;

@@ -8,6 +8,9 @@
 #include <complex>
 #include <cstring>
 
+#include <initializer_list>
+#include <utility>
+
 #include "twolevel.h"
 
 namespace hdcr {
@@ -127,35 +130,73 @@ void cheby_coeffs(int n, double lo, double hi, double* c) {
     }
 }
 
+// out = p(H^2) H in   (accumulate: out += p(H^2) H in), with
+// p(y) = sum_{j<n} c'_j T_j(yhat), c'_0 = c_0 / 2, c'_j = c_j, yhat = a1 y + b1,
+// evaluated by Clenshaw's recurrence on u = H in:
+//   b_{n-1} = c'_{n-1} u,  b_k = c'_k u + 2 yhat b_{k+1} - b_{k+2},
+//   result = c'_0 u + yhat b_1 - b_2,
+// where yhat b = a1 H (H b) + b1 b.  Each step's second stencil application
+// carries the combination in its epilogue, so a step costs two stencil passes
+// and no separate vector pass.  tmp: four fields (u, V, and two b_k).
 template <typename T>
-void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* acc, C2<T>* const tmp[4], int order,
-                   double lo, double hi, hipStream_t s) {
+void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, bool accumulate,
+                   C2<T>* const tmp[4], int order, double lo, double hi, hipStream_t s) {
     const int64_t n = 12LL * g.N5;
-    std::vector<double> c(order);
-    cheby_coeffs(order, lo, hi, c.data());
-    C2<T>* T0 = tmp[0];
-    C2<T>* T1 = tmp[1];
-    C2<T>* V = tmp[2];
-    C2<T>* W = tmp[3];
-    // u = H in, acc = (c0 / 2) u
-    launch_dslash<T>(g, U, in, T0, s);
-    launch_scale<T>(n, (T)(0.5 * c[0]), T0, acc, s);
-    if (order < 2) return;
-    // T1 = yhat u = (2 H^2 u - (hi + lo) u) / (hi - lo)
+    const int nc = order;
+    std::vector<double> c(nc);
+    cheby_coeffs(nc, lo, hi, c.data());
+    c[0] *= 0.5;
     const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
-    launch_dslash<T>(g, U, T0, V, s);
-    launch_dslash<T>(g, U, V, W, s);
-    launch_axpby<T>(n, (T)b1, T0, (T)a1, W, s);   // W = b1 T0 + a1 W
-    std::swap(T1, W);
-    launch_axpby<T>(n, (T)c[1], T1, (T)1, acc, s);
-    // T_{j+1} = 2 yhat T_j - T_{j-1}
-    const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
-    for (int j = 2; j < order; ++j) {
-        launch_dslash<T>(g, U, T1, V, s);
-        launch_dslash<T>(g, U, V, W, s);
-        launch_cheb_step<T>(n, (T)a2, W, (T)b2, T1, T0, (T)c[j], acc, s);
-        std::swap(T0, T1);
+    C2<T>* u = tmp[0];
+    C2<T>* V = tmp[1];
+    C2<T>* bk1 = tmp[2];  // b_{k+1}
+    C2<T>* bk2 = tmp[3];  // b_{k+2}, overwritten in place by b_k
+    launch_dslash<T>(g, U, in, u, s);
+    if (nc == 1) {
+        if (accumulate)
+            launch_axpby<T>(n, (T)c[0], u, (T)1, out, s);
+        else
+            launch_scale<T>(n, (T)c[0], u, out, s);
+        return;
     }
+    auto epi = [&](const C2<T>* src, C2<T>* dst, double beta, std::initializer_list<std::pair<const C2<T>*, double>> ys,
+                   bool acc_out) {
+        Epi<T> e{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, (T)beta, 0};
+        for (const auto& y : ys) {
+            e.y[e.ny] = y.first;
+            e.g[e.ny] = (T)y.second;
+            ++e.ny;
+        }
+        if (acc_out) {
+            e.y[e.ny] = out;
+            e.g[e.ny] = (T)1;
+            ++e.ny;
+        }
+        launch_dslash_epi<T>(g, U, src, dst, e, s);
+    };
+    launch_dslash<T>(g, U, u, V, s);
+    if (nc == 2) {
+        // result = c'_0 u + yhat (c'_1 u) = (c'_0 + b1 c'_1) u + a1 c'_1 H H u
+        epi(V, out, a1 * c[1], {{u, c[0] + b1 * c[1]}}, accumulate);
+        return;
+    }
+    // b_{n-2} = (c'_{n-2} + 2 b1 c'_{n-1}) u + 2 a1 c'_{n-1} H H u
+    epi(V, bk1, 2 * a1 * c[nc - 1], {{u, c[nc - 2] + 2 * b1 * c[nc - 1]}}, false);
+    bool implicit2 = true;  // b_{k+2} = b_{n-1} = c'_{n-1} u is not stored
+    for (int k = nc - 3; k >= 1; --k) {
+        launch_dslash<T>(g, U, bk1, V, s);
+        if (implicit2)
+            epi(V, bk2, 2 * a1, {{u, c[k] - c[nc - 1]}, {bk1, 2 * b1}}, false);
+        else
+            epi(V, bk2, 2 * a1, {{u, c[k]}, {bk1, 2 * b1}, {bk2, -1.0}}, false);
+        implicit2 = false;
+        std::swap(bk1, bk2);
+    }
+    launch_dslash<T>(g, U, bk1, V, s);
+    if (implicit2)
+        epi(V, out, a1, {{u, c[0] - c[nc - 1]}, {bk1, b1}}, accumulate);
+    else
+        epi(V, out, a1, {{u, c[0]}, {bk1, b1}, {bk2, -1.0}}, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,7 +205,6 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ac
 template <typename T> struct CycleWork {
     C2<T>* t;
     C2<T>* d;
-    C2<T>* s2;
     C2<T>* sm[4];
     C2<T>* vc;
     C2<T>* cx;
@@ -175,7 +215,6 @@ template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
     CycleWork<T> k;
     k.t = w.take<C2<T>>(n);
     k.d = w.take<C2<T>>(n);
-    k.s2 = w.take<C2<T>>(n);
     for (int i = 0; i < 4; ++i) k.sm[i] = w.take<C2<T>>(n);
     k.vc = w.take<C2<T>>((size_t)c.Nc * c.Nb);
     k.cx = w.take<C2<T>>((size_t)c.Nc * c.Nb);
@@ -193,10 +232,9 @@ template <typename T>
 int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, const C2<T>* basis, const void* A,
            const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm, CycleCounts& cnt, hipStream_t s) {
     const FineGeom& g = c.f;
-    const int64_t n = 12LL * g.N5;
     const int order = prm->cheb_order;
     tm.begin(PhaseTimer::FINE);
-    cheb_smoother<T>(g, U, r, e, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    cheb_smoother<T>(g, U, r, e, false, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
     launch_dslash<T>(g, U, e, w.t, s);
     tm.begin(PhaseTimer::COARSE);
     launch_restrict<T>(c, basis, r, w.t, w.vc, s);
@@ -209,10 +247,9 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     cnt.coarse_applies += it + 1;
     launch_prolong<T>(c, basis, w.cx, e, e, s);
     tm.begin(PhaseTimer::FINE);
-    launch_dslash<T>(g, U, e, w.t, s);
-    launch_sub<T>(n, r, w.t, w.d, s);
-    cheb_smoother<T>(g, U, w.d, w.s2, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
-    launch_axpby<T>(n, (T)1, w.s2, (T)1, e, s);
+    // d = r - H e2 (fused), e = e2 + S d
+    launch_dslash_epi<T>(g, U, e, w.d, Epi<T>{{r, nullptr, nullptr, nullptr}, {(T)1, 0, 0, 0}, (T)-1, 1}, s);
+    cheb_smoother<T>(g, U, w.d, e, true, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
     cnt.fine += 2 * (2 * order - 1) + 2;
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
@@ -584,11 +621,11 @@ int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int
     if (dtype == HDCR_C128) {
         double2* tmp[4];
         for (int i = 0; i < 4; ++i) tmp[i] = w.take<double2>(n);
-        cheb_smoother<double>(g, (const double2*)U, (const double2*)in, (double2*)out, tmp, order, lo, hi, stream);
+        cheb_smoother<double>(g, (const double2*)U, (const double2*)in, (double2*)out, false, tmp, order, lo, hi, stream);
     } else {
         float2* tmp[4];
         for (int i = 0; i < 4; ++i) tmp[i] = w.take<float2>(n);
-        cheb_smoother<float>(g, (const float2*)U, (const float2*)in, (float2*)out, tmp, order, lo, hi, stream);
+        cheb_smoother<float>(g, (const float2*)U, (const float2*)in, (float2*)out, false, tmp, order, lo, hi, stream);
     }
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
