@@ -88,9 +88,13 @@ template <typename T> struct CoarseCRWork {
     C2<T>* Ap;
     double* part;   // partial sums, 2 * max(Nc, CCR_BLOCKS) entries
     double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
-    int* flags;     // 0 done, 1 iterations, 2 arrival counter, 3 maxiter
+    int* flags;     // 0 done, 1 iterations, 3 maxiter; CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
 };
 constexpr int CCR_BLOCKS = 64;
+constexpr int ARRIVE_GROUPS = 16;   // group counters of the last-arrival test
+constexpr int ARRIVE_STRIDE = 64;   // ints between counters (each counter on its own 256-byte line)
+constexpr int CCR_COUNTERS = 64;    // first arrival counter in flags
+constexpr int CCR_FLAGS = CCR_COUNTERS + (1 + ARRIVE_GROUPS) * ARRIVE_STRIDE;  // ints of the flags array
 // r = b, x = 0, |b|^2; resets the iteration state
 template <typename T>
 void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,

@@ -332,14 +332,90 @@ template <> __device__ __forceinline__ float2 ldA<float, uint32_t>(const uint32_
     return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
 
-// one workgroup per (coarse site, right-hand side); wave w handles the
-// directions d = w, w+4, w+8; the neighbour vectors are staged in LDS
-template <typename T, typename S>
+// E consecutive entries A[.][k][j..j+E) with one 16-byte load (E = 16 / entry
+// size; E = 1 falls back to single-entry loads)
+template <typename T, typename S, int E> struct WideA;
+template <typename T, typename S> struct WideA<T, S, 1> {
+    static __device__ __forceinline__ void ld(const S* p, C2<T> (&e)[1]) { e[0] = ldA<T, S>(p, 0); }
+};
+template <> struct WideA<double, double2, 1> {
+    static __device__ __forceinline__ void ld(const double2* p, double2 (&e)[1]) { e[0] = *p; }
+};
+template <> struct WideA<float, float2, 2> {
+    static __device__ __forceinline__ void ld(const float2* p, float2 (&e)[2]) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        e[0] = make_float2(q.x, q.y);
+        e[1] = make_float2(q.z, q.w);
+    }
+};
+template <> struct WideA<float, uint32_t, 4> {
+    static __device__ __forceinline__ void ld(const uint32_t* p, float2 (&e)[4]) {
+        const uint4 q = *reinterpret_cast<const uint4*>(p);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = make_float2(__uint_as_float(w[i] << 16), __uint_as_float(w[i] & 0xffff0000u));
+    }
+};
+template <typename S> constexpr int wide_entries() { return (int)(16 / sizeof(S)); }
+
+// res[j] = sum_d sum_k A[a][d][k][j] vs[d][k] for one coarse site a (one
+// workgroup).  Work-item t covers E consecutive rows j (t % (Nb/E)) and the
+// columns k = kk, kk + kg, ... (kk = t / (Nb/E), kg = CWG / (Nb/E) groups), so
+// every load of A is a contiguous 16-byte run and a work-item issues
+// 9 Nb / kg independent loads; the kg partial sums are added in a fixed order.
+// red: LDS of CWG * E complex; ends with a barrier.
+template <typename T, typename S, int E>
+__device__ __forceinline__ void site_gemv(const CoarseGeom& c, const S* __restrict__ A, int a, const C2<T>* vs,
+                                          C2<T>* red, C2<T>* res) {
+    const int Nb = c.Nb;
+    const int nj = Nb / E;
+    const int kg = CWG / nj;
+    const int t = threadIdx.x;
+    const int jq = t % nj, kk = t / nj;
+    C2<T> acc[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) acc[q] = mk<T>(0, 0);
+    if (kk < kg) {
+        const size_t blk = (size_t)Nb * Nb;
+        const S* Aa = A + (size_t)a * 9 * blk + (size_t)jq * E;
+        for (int d = 0; d < 9; ++d) {
+            const S* Ad = Aa + d * blk;
+            const C2<T>* vd = vs + d * Nb;
+#pragma unroll 4
+            for (int k = kk; k < Nb; k += kg) {
+                C2<T> e[E];
+                WideA<T, S, E>::ld(Ad + (size_t)k * Nb, e);
+                const C2<T> x = vd[k];
+#pragma unroll
+                for (int q = 0; q < E; ++q) acc[q] = cfma<T>(e[q], x, acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) red[kk * Nb + jq * E + q] = acc[q];
+    }
+    __syncthreads();
+    for (int j = t; j < Nb; j += CWG) {
+        C2<T> sum = red[j];
+        for (int g = 1; g < kg; ++g) sum = cadd<T>(sum, red[g * Nb + j]);
+        res[j] = sum;
+    }
+    __syncthreads();
+}
+
+// LDS bytes of a coarse-apply workgroup: vs [9][Nb], red [CWG * E], res [Nb]
+template <typename T, int E> size_t apply_lds(const CoarseGeom& c) {
+    return (size_t)(10 * c.Nb + CWG * E) * sizeof(C2<T>);
+}
+
+// one workgroup per (coarse site, right-hand side); the neighbour vectors are
+// staged in LDS
+template <typename T, typename S, int E>
 __global__ void __launch_bounds__(CWG) coarse_apply_kernel(CoarseGeom c, const S* __restrict__ A,
                                                            const C2<T>* __restrict__ v, C2<T>* __restrict__ out) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
-    C2<T>* part = vs + 9 * c.Nb;                       // [4][Nb]
+    C2<T>* res = vs + 9 * c.Nb;                        // [Nb]
+    C2<T>* red = res + c.Nb;                           // [CWG * E]
     const int a = blockIdx.x;
     const int rhs = blockIdx.y;
     const C2<T>* vr = v + (size_t)rhs * c.Nc * c.Nb;
@@ -348,24 +424,8 @@ __global__ void __launch_bounds__(CWG) coarse_apply_kernel(CoarseGeom c, const S
         vs[e] = vr[(size_t)coarse_nbr(c, a, d) * c.Nb + k];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j0 = 0; j0 < c.Nb; j0 += 64) {
-        const int j = j0 + lane;
-        C2<T> acc = mk<T>(0, 0);
-        if (j < c.Nb) {
-            for (int d = wave; d < 9; d += 4) {
-                const size_t base = ((size_t)a * 9 + d) * c.Nb * c.Nb + j;
-                const C2<T>* vd = vs + d * c.Nb;
-                for (int k = 0; k < c.Nb; ++k) acc = cfma<T>(ldA<T, S>(A, base + (size_t)k * c.Nb), vd[k], acc);
-            }
-            part[wave * c.Nb + j] = acc;
-        }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < c.Nb; j += CWG) {
-        const C2<T> r = cadd<T>(cadd<T>(part[j], part[c.Nb + j]), cadd<T>(part[2 * c.Nb + j], part[3 * c.Nb + j]));
-        out[((size_t)rhs * c.Nc + a) * c.Nb + j] = r;
-    }
+    site_gemv<T, S, E>(c, A, a, vs, red, res);
+    for (int j = threadIdx.x; j < c.Nb; j += CWG) out[((size_t)rhs * c.Nc + a) * c.Nb + j] = res[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -374,11 +434,33 @@ __global__ void __launch_bounds__(CWG) coarse_apply_kernel(CoarseGeom c, const S
 
 // After every workgroup has stored its partial sums, true in the workgroup
 // that arrived last (which then reduces them in a fixed order).
-__device__ __forceinline__ bool last_arrival(int* counter) {
+__device__ __forceinline__ bool last_arrival(int* counters) {
+    // Arrivals are counted in ARRIVE_GROUPS group counters (workgroup b in group
+    // b % ARRIVE_GROUPS, each on its own cache line) and a master counter that
+    // the last workgroup of each group increments: a single counter hit by
+    // every workgroup serialises ~Nc device-scope atomics.  Counters return to
+    // zero for the next launch.
     __shared__ int is_last;
+    const int nb = (int)(gridDim.x * gridDim.y);
+    const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1) == (int)(gridDim.x * gridDim.y) - 1);
+    if (threadIdx.x == 0) {
+        const int g = b % ARRIVE_GROUPS;
+        const int gsize = (nb - g + ARRIVE_GROUPS - 1) / ARRIVE_GROUPS;
+        const int ngroups = nb < ARRIVE_GROUPS ? nb : ARRIVE_GROUPS;
+        int last = 0;
+        int* cg = counters + (1 + g) * ARRIVE_STRIDE;
+        if (atomicAdd(cg, 1) == gsize - 1) {
+            atomicExch(cg, 0);
+            __threadfence();
+            if (atomicAdd(counters, 1) == ngroups - 1) {
+                atomicExch(counters, 0);
+                last = 1;
+            }
+        }
+        is_last = last;
+    }
     __syncthreads();
     return is_last != 0;
 }
@@ -412,7 +494,7 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
     }
     block_reduce<1>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_arrival(flags + 2)) {
+    if (last_arrival(flags + CCR_COUNTERS)) {
         double s[1];
         reduce_partials<1>(part, gridDim.x, s);
         if (threadIdx.x == 0) {
@@ -422,14 +504,13 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
             flags[3] = maxiter;
             flags[1] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0])) ? 1 : 0;
-            flags[2] = 0;
         }
     }
 }
 
 // Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar and
 // the sums <r,Ar>, |Ar|^2; else the sum <r,Ar> (the new value)
-template <typename T, typename S, bool FIRST>
+template <typename T, typename S, int E, bool FIRST>
 __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* __restrict__ A,
                                                         const C2<T>* __restrict__ r, C2<T>* __restrict__ Ar,
                                                         C2<T>* __restrict__ p, C2<T>* __restrict__ Ap, double* part,
@@ -437,30 +518,18 @@ __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* _
     if (flags[0]) return;
     extern __shared__ unsigned char smem_raw[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
-    C2<T>* prt = vs + 9 * c.Nb;                        // [4][Nb]
+    C2<T>* res = vs + 9 * c.Nb;                        // [Nb]
+    C2<T>* red = res + c.Nb;                           // [CWG * E]
     const int a = blockIdx.x;
     for (int e = threadIdx.x; e < 9 * c.Nb; e += CWG) {
         const int d = e / c.Nb, k = e - d * c.Nb;
         vs[e] = r[(size_t)coarse_nbr(c, a, d) * c.Nb + k];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j0 = 0; j0 < c.Nb; j0 += 64) {
-        const int j = j0 + lane;
-        C2<T> acc = mk<T>(0, 0);
-        if (j < c.Nb) {
-            for (int d = wave; d < 9; d += 4) {
-                const size_t base = ((size_t)a * 9 + d) * c.Nb * c.Nb + j;
-                const C2<T>* vd = vs + d * c.Nb;
-                for (int k = 0; k < c.Nb; ++k) acc = cfma<T>(ldA<T, S>(A, base + (size_t)k * c.Nb), vd[k], acc);
-            }
-            prt[wave * c.Nb + j] = acc;
-        }
-    }
-    __syncthreads();
+    site_gemv<T, S, E>(c, A, a, vs, red, res);
     double sums[2] = {0.0, 0.0};
     for (int j = threadIdx.x; j < c.Nb; j += CWG) {
-        const C2<T> o = cadd<T>(cadd<T>(prt[j], prt[c.Nb + j]), cadd<T>(prt[2 * c.Nb + j], prt[3 * c.Nb + j]));
+        const C2<T> o = res[j];
         const size_t idx = (size_t)a * c.Nb + j;
         Ar[idx] = o;
         const C2<T> rv = vs[j];  // d = 0 slot holds r(a)
@@ -476,7 +545,7 @@ __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* _
         part[a] = sums[0];
         part[c.Nc + a] = sums[1];
     }
-    if (last_arrival(flags + 2)) {
+    if (last_arrival(flags + CCR_COUNTERS)) {
         double t[2];
         reduce_partials<2>(part, c.Nc, t);
         if (threadIdx.x == 0) {
@@ -487,7 +556,6 @@ __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* _
                 cs[1] = t[0];
             }
             if (!(fabs(t[0]) > 0.0) || !isfinite(t[0])) flags[0] = 1;  // breakdown ends the coarse solve
-            flags[2] = 0;
         }
     }
 }
@@ -513,7 +581,7 @@ __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __rest
     }
     block_reduce<1>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_arrival(flags + 2)) {
+    if (last_arrival(flags + CCR_COUNTERS)) {
         double s[1];
         reduce_partials<1>(part, gridDim.x, s);
         if (threadIdx.x == 0) {
@@ -521,7 +589,6 @@ __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __rest
             const int it = flags[1] + 1;
             flags[1] = it;
             if (s[0] <= cs[5] * cs[4] || it >= flags[3] || !isfinite(s[0])) flags[0] = 1;
-            flags[2] = 0;
         }
     }
 }
@@ -547,30 +614,36 @@ __global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* _
     }
     block_reduce<1>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_arrival(flags + 2)) {
+    if (last_arrival(flags + CCR_COUNTERS)) {
         double s[1];
         reduce_partials<1>(part, gridDim.x, s);
         if (threadIdx.x == 0) {
             cs[2] = s[0];
             cs[0] = cs[1];
-            flags[2] = 0;
         }
     }
 }
 
 // coarse vectors are FP64 with C128 storage and FP32 with C64 / BF16 storage
+template <typename T, typename S, bool FIRST>
+void ccr_apply_launch(const CoarseGeom& c, const S* A, const CoarseCRWork<T>& w, hipStream_t s) {
+    constexpr int E = wide_entries<S>();
+    if (c.Nb % E == 0)
+        hipLaunchKernelGGL((ccr_apply_kernel<T, S, E, FIRST>), dim3(c.Nc), dim3(CWG), (apply_lds<T, E>(c)), s, c, A,
+                           w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+    else
+        hipLaunchKernelGGL((ccr_apply_kernel<T, S, 1, FIRST>), dim3(c.Nc), dim3(CWG), (apply_lds<T, 1>(c)), s, c, A,
+                           w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+}
+
 template <typename T, bool FIRST>
 void ccr_apply_dispatch(const CoarseGeom& c, hdcr_dtype dt, const void* A, const CoarseCRWork<T>& w, hipStream_t s) {
-    const size_t lds = 13 * c.Nb * sizeof(C2<T>);
     if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((ccr_apply_kernel<T, double2, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
-                           static_cast<const double2*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+        ccr_apply_launch<T, double2, FIRST>(c, static_cast<const double2*>(A), w, s);
     } else if (dt == HDCR_C64) {
-        hipLaunchKernelGGL((ccr_apply_kernel<T, float2, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
-                           static_cast<const float2*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+        ccr_apply_launch<T, float2, FIRST>(c, static_cast<const float2*>(A), w, s);
     } else {
-        hipLaunchKernelGGL((ccr_apply_kernel<T, uint32_t, FIRST>), dim3(c.Nc), dim3(CWG), lds, s, c,
-                           static_cast<const uint32_t*>(A), w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+        ccr_apply_launch<T, uint32_t, FIRST>(c, static_cast<const uint32_t*>(A), w, s);
     }
 }
 
@@ -801,16 +874,25 @@ void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, con
     hipLaunchKernelGGL(prolong_kernel<T>, dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v, y, psi);
 }
 
+template <typename T, typename S>
+void coarse_apply_launch(const CoarseGeom& c, const S* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s) {
+    constexpr int E = wide_entries<S>();
+    if (c.Nb % E == 0)
+        hipLaunchKernelGGL((coarse_apply_kernel<T, S, E>), dim3(c.Nc, nrhs), dim3(CWG), (apply_lds<T, E>(c)), s, c,
+                           A, v, out);
+    else
+        hipLaunchKernelGGL((coarse_apply_kernel<T, S, 1>), dim3(c.Nc, nrhs), dim3(CWG), (apply_lds<T, 1>(c)), s, c,
+                           A, v, out);
+}
+
 template <typename T>
 void launch_coarse_apply(const CoarseGeom& c, const C2<T>* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((coarse_apply_kernel<T, C2<T>>), dim3(c.Nc, nrhs), dim3(CWG), 13 * c.Nb * sizeof(C2<T>), s, c,
-                       A, v, out);
+    coarse_apply_launch<T, C2<T>>(c, A, v, out, nrhs, s);
 }
 
 void launch_coarse_apply_bf16(const CoarseGeom& c, const uint16_t* A, const float2* v, float2* out, int nrhs,
                               hipStream_t s) {
-    hipLaunchKernelGGL((coarse_apply_kernel<float, uint32_t>), dim3(c.Nc, nrhs), dim3(CWG), 13 * c.Nb * sizeof(float2),
-                       s, c, reinterpret_cast<const uint32_t*>(A), v, out);
+    coarse_apply_launch<float, uint32_t>(c, reinterpret_cast<const uint32_t*>(A), v, out, nrhs, s);
 }
 
 void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,

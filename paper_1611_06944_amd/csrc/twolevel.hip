@@ -74,7 +74,7 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
     k.Ap = w.take<C2<T>>(n);
     k.part = w.take<double>(2 * (size_t)std::max(c.Nc, CCR_BLOCKS));
     k.cs = w.take<double>(8);
-    k.flags = w.take<int>(8);
+    k.flags = w.take<int>(CCR_FLAGS);
     return k;
 }
 template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
@@ -330,7 +330,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
         Uin = U;
         bas = basis64(basis);
     }
-    HDCR_HIP_CHECK(hipMemsetAsync(w.cyc.ccr.flags, 0, 8 * sizeof(int), s));
+    HDCR_HIP_CHECK(hipMemsetAsync(w.cyc.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
 
     double hS[SCOUNT];
     auto readS = [&]() -> hipError_t {
@@ -550,7 +550,7 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
         float2* e32 = w.take<float2>(n);
         CycleWork<float> cw = cycle_carve<float>(w, c);
         if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
-        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, 8 * sizeof(int), s));
+        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
         launch_convert<double2, float2>(36LL * c.f.V4, U, U32, s);
         launch_convert<double2, float2>(n, r, r32, s);
         int st = vcycle<float>(c, p, U32, basis32(c, basis), A, r32, e32, cw, tm, cnt, s);
@@ -559,7 +559,7 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
     } else {
         CycleWork<double> cw = cycle_carve<double>(w, c);
         if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
-        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, 8 * sizeof(int), s));
+        HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
         int st = vcycle<double>(c, p, U, basis64(basis), A, r, e, cw, tm, cnt, s);
         if (st) return st;
     }
