@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cheb-lo", type=float, default=0.5,
                     help="smoother interval low end (the paper's ensemble: 1.0; tuned to the synthetic ensemble)")
     ap.add_argument("--cheb-hi", type=float, default=64.0)
+    ap.add_argument("--basis", choices=["f32", "f16"], default="f16",
+                    help="basis copy used by restriction/prolongation in the FP32 cycle")
     ap.add_argument("--coarse-tol", type=float, default=0.2)
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--applies", type=int, default=20)
@@ -144,13 +146,14 @@ def main():
         torch.cuda.empty_cache()
         setup = {"solver": {"smoother_order": args.order, "smoother_interval": [args.cheb_lo, args.cheb_hi],
                             "coarse_tol": args.coarse_tol, "fgcr_restart": args.restart, "inner": "c64",
-                            "coarse": "bf16c"},
+                            "coarse": "bf16c", "basis_restrict_prolong": args.basis},
                  "lambda_max_sq": round(lam, 4), "filter_degree": args.degree, "nvec": args.nvec,
                  "subspace_s": round(t1 - t0, 3), "coarse_build_s": round(t2 - t1, 3)}
         progress(f"set-up done: subspace {t1 - t0:.1f} s, coarse build {t2 - t1:.1f} s")
         prm_hdcr = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=hd.BF16C,
                                      coarse_tol=args.coarse_tol, coarse_maxiter=500, restart=args.restart, tol=1e-8,
-                                     maxiter=500, cheb_order=args.order, cheb_lo=args.cheb_lo, cheb_hi=args.cheb_hi)
+                                     maxiter=500, cheb_order=args.order, cheb_lo=args.cheb_lo, cheb_hi=args.cheb_hi,
+                                     basis_dtype=hd.F16C if args.basis == "f16" else hd.C64)
         prm_cr = hd.default_params(tol=1e-8, maxiter=20000)
         work_hdcr = torch.empty(hd.workspace_bytes(hd._abi.WS_SOLVE, lat, prm_hdcr), dtype=torch.uint8, device=dev)
         work_cr = torch.empty(hd.workspace_bytes(hd._abi.WS_SOLVE, lat, prm_cr), dtype=torch.uint8, device=dev)

@@ -68,7 +68,8 @@ extern "C" {
 typedef enum {
     HDCR_C128 = 0,  /* complex double */
     HDCR_C64 = 1,   /* complex float */
-    HDCR_BF16C = 2  /* (bf16 re, bf16 im): little Dirac operator storage only */
+    HDCR_BF16C = 2, /* (bf16 re, bf16 im): little Dirac operator storage only */
+    HDCR_F16C = 3   /* (fp16 re, fp16 im): FP16 copy of the block basis used with FP32 vectors */
 } hdcr_dtype;
 
 /* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1
@@ -112,6 +113,8 @@ typedef struct hdcr_solve_params {
     int32_t coarse_maxiter;
     int32_t inner_dtype;    /* HDCR_C64 or HDCR_C128: smoother, restriction, prolongation */
     int32_t coarse_dtype;   /* storage of A passed to hdcr_solve: C128, C64 or BF16C */
+    int32_t basis_dtype;    /* HDCR_F16C: the C64 inner cycle restricts and prolongs with the FP16
+                               basis copy; any other value: the basis in the inner precision */
     int32_t verbose;
 } hdcr_solve_params;
 
@@ -192,8 +195,9 @@ HDCR_API int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, 
 HDCR_API int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields_c128, hipStream_t stream);
 
 /* Restriction v[a][j] = <phi^a_j, psi> (P^dag) and prolongation
- * psi(x) = sum_j phi^{b(x)}_j(x) v[b(x)][j] (P), in C128 or C64 (the basis copy
- * of that precision is used). */
+ * psi(x) = sum_j phi^{b(x)}_j(x) v[b(x)][j] (P) (Sec. 4), in C128 or C64 (the
+ * basis copy of that precision is used), or F16C: FP32 vectors with the FP16
+ * basis copy (entries rounded to 11 significant bits). */
 HDCR_API int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* psi, void* v,
                   hipStream_t stream);
 HDCR_API int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (BF16C, C64, C128, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL, CoarseDesc, FineDesc,  # noqa: F401
+from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL, CoarseDesc, FineDesc,  # noqa: F401
                    SolveParams, SolveStats)
 
 __all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
@@ -185,6 +185,7 @@ def default_params(**kw) -> SolveParams:
     p.coarse_maxiter = 500
     p.inner_dtype = C64
     p.coarse_dtype = C64
+    p.basis_dtype = C64
     p.verbose = 0
     for k, v in kw.items():
         setattr(p, k, v)
@@ -298,22 +299,26 @@ def export_basis(lat: Lattice, basis, stream=None):
     return out
 
 
-def restrict(lat: Lattice, basis, psi, out=None, stream=None):
+def restrict(lat: Lattice, basis, psi, out=None, stream=None, half_basis=False):
+    """v = P^dag psi in the precision of psi; half_basis: complex64 psi with the FP16 basis copy."""
     torch = _torch()
     if out is None:
         out = torch.empty((lat.nc, lat.nb), dtype=psi.dtype, device=psi.device)
     cd = lat.coarse_desc()
-    _abi.check(load().hdcr_restrict(ctypes.byref(cd), _dtype_code(psi), _ptr(basis), _ptr(psi), _ptr(out),
+    code = F16C if half_basis else _dtype_code(psi)
+    _abi.check(load().hdcr_restrict(ctypes.byref(cd), code, _ptr(basis), _ptr(psi), _ptr(out),
                                     _stream(stream)), "hdcr_restrict")
     return out
 
 
-def prolong(lat: Lattice, basis, v, out=None, stream=None):
+def prolong(lat: Lattice, basis, v, out=None, stream=None, half_basis=False):
+    """psi = P v in the precision of v; half_basis: complex64 v with the FP16 basis copy."""
     torch = _torch()
     if out is None:
         out = torch.empty(lat.fshape, dtype=v.dtype, device=v.device)
     cd = lat.coarse_desc()
-    _abi.check(load().hdcr_prolong(ctypes.byref(cd), _dtype_code(v), _ptr(basis), _ptr(v), _ptr(out),
+    code = F16C if half_basis else _dtype_code(v)
+    _abi.check(load().hdcr_prolong(ctypes.byref(cd), code, _ptr(basis), _ptr(v), _ptr(out),
                                    _stream(stream)), "hdcr_prolong")
     return out
 

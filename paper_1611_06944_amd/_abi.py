@@ -16,7 +16,7 @@ HDCR_EBREAKDOWN = 2
 HDCR_ENAN = 3
 HDCR_ERANK = 4
 
-C128, C64, BF16C = 0, 1, 2
+C128, C64, BF16C, F16C = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_TWO_LEVEL = 0, 1
 WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE = 0, 1, 2, 3, 4
 DOT_WORK_BYTES = 32768
@@ -36,7 +36,8 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("cheb_order", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
-                ("inner_dtype", ctypes.c_int32), ("coarse_dtype", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("inner_dtype", ctypes.c_int32), ("coarse_dtype", ctypes.c_int32), ("basis_dtype", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):

@@ -61,7 +61,8 @@ size_t build_workspace_bytes(const CoarseGeom& c) {
     return w.used();
 }
 
-static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4; }
+// bytes of one vector entry: FP32 vectors go with the C64 and F16C (FP16 basis) forms
+static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : (dt == HDCR_C64 || dt == HDCR_F16C) ? 8 : 4; }
 
 }  // namespace hdcr
 
@@ -104,6 +105,7 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     launch_basis_fold(c, static_cast<const double2*>(vecs), b64, stream);
     launch_block_orth(c, b64, flag, stream);
     launch_basis_to_f32(c, b64, basis32(c, basis), stream);
+    launch_basis_to_f16(c, b64, basis16(c, basis), stream);
     HDCR_HIP_CHECK(hipGetLastError());
     // A = P^dag H P, kc columns at a time
     double2* Adst = (A_dtype == HDCR_C128) ? static_cast<double2*>(A) : A64;
@@ -163,7 +165,8 @@ int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* ba
                   hipStream_t stream) {
     int e = check_coarse_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_restrict: dtype C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_restrict: dtype C128, C64 or F16C");
     if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(psi, csize(dtype), "psi")) ||
         (e = check_ptr(v, csize(dtype), "v")))
         return e;
@@ -171,6 +174,9 @@ int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* ba
     if (dtype == HDCR_C128)
         launch_restrict<double>(c, basis64(basis), static_cast<const double2*>(psi), nullptr, static_cast<double2*>(v),
                                 stream);
+    else if (dtype == HDCR_F16C)
+        launch_restrict_h(c, basis16(c, basis), static_cast<const float2*>(psi), nullptr, static_cast<float2*>(v),
+                          stream);
     else
         launch_restrict<float>(c, basis32(c, basis), static_cast<const float2*>(psi), nullptr, static_cast<float2*>(v),
                                stream);
@@ -182,7 +188,8 @@ int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* bas
                  hipStream_t stream) {
     int e = check_coarse_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_prolong: dtype C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_prolong: dtype C128, C64 or F16C");
     if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(psi, csize(dtype), "psi")) ||
         (e = check_ptr(v, csize(dtype), "v")))
         return e;
@@ -190,6 +197,9 @@ int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* bas
     if (dtype == HDCR_C128)
         launch_prolong<double>(c, basis64(basis), static_cast<const double2*>(v), nullptr, static_cast<double2*>(psi),
                                stream);
+    else if (dtype == HDCR_F16C)
+        launch_prolong_h(c, basis16(c, basis), static_cast<const float2*>(v), nullptr, static_cast<float2*>(psi),
+                         stream);
     else
         launch_prolong<float>(c, basis32(c, basis), static_cast<const float2*>(v), nullptr, static_cast<float2*>(psi),
                               stream);

@@ -35,7 +35,11 @@ int check_coarse_desc(const hdcr_coarse_desc* d);
 size_t build_workspace_bytes(const CoarseGeom& c);
 
 inline size_t basis_elems(const CoarseGeom& c) { return (size_t)c.Nc * 2 * c.nvec * c.nhalf; }
-inline size_t basis_bytes(const CoarseGeom& c) { return basis_elems(c) * (16 + 8); }
+// FP64 region, FP32 region, then an FP16 copy for the FP32 inner cycle that
+// holds HBASIS_SCALE * phi as (fp16 re, fp16 im) words (the scale keeps the
+// O(1/sqrt(block dof)) entries in the normal FP16 range)
+inline size_t basis_bytes(const CoarseGeom& c) { return basis_elems(c) * (16 + 8 + 4); }
+constexpr float HBASIS_SCALE = 256.0f;
 inline const double2* basis64(const void* b) { return static_cast<const double2*>(b); }
 inline double2* basis64(void* b) { return static_cast<double2*>(b); }
 inline const float2* basis32(const CoarseGeom& c, const void* b) {
@@ -43,6 +47,12 @@ inline const float2* basis32(const CoarseGeom& c, const void* b) {
 }
 inline float2* basis32(const CoarseGeom& c, void* b) {
     return reinterpret_cast<float2*>(static_cast<char*>(b) + basis_elems(c) * 16);
+}
+inline const uint32_t* basis16(const CoarseGeom& c, const void* b) {
+    return reinterpret_cast<const uint32_t*>(static_cast<const char*>(b) + basis_elems(c) * 24);
+}
+inline uint32_t* basis16(const CoarseGeom& c, void* b) {
+    return reinterpret_cast<uint32_t*>(static_cast<char*>(b) + basis_elems(c) * 24);
 }
 
 // little Dirac operator storage (opaque): [a][d][k][j], column-major Nb x Nb
@@ -57,6 +67,7 @@ void launch_basis_fold(const CoarseGeom& c, const double2* vecs, double2* b64, h
 // order; rank_flag[0] is set to 1 if a vector is dependent (|w| <= 1e-12 |w0|)
 void launch_block_orth(const CoarseGeom& c, double2* b64, int* rank_flag, hipStream_t s);
 void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, hipStream_t s);
+void launch_basis_to_f16(const CoarseGeom& c, const double2* b64, uint32_t* b16, hipStream_t s);
 // full fine fields of basis vectors k0 .. k0+nk-1 (k < nvec: + half, else - half), FP64
 void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk, double2* fields, hipStream_t s);
 
@@ -68,6 +79,11 @@ void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, 
 template <typename T>
 void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
                     hipStream_t s);
+// the same two with the FP16 copy of the basis (FP32 vectors)
+void launch_restrict_h(const CoarseGeom& c, const uint32_t* basis, const float2* psi, const float2* psi2, float2* v,
+                       hipStream_t s);
+void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* v, const float2* y, float2* psi,
+                      hipStream_t s);
 
 // out[r][a] = sum_d A[a][d] v[r][a+d]  (C128 / C64 storage, column-major blocks)
 template <typename T>

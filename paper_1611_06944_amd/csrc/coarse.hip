@@ -153,6 +153,16 @@ __global__ void __launch_bounds__(CWG) basis_to_f32_kernel(size_t n, const doubl
         b[e] = make_float2((float)a[e].x, (float)a[e].y);
 }
 
+// FP16 copy of the basis: HBASIS_SCALE * phi, rounded to nearest even
+__global__ void __launch_bounds__(CWG) basis_to_f16_kernel(size_t n, const double2* __restrict__ a,
+                                                           uint32_t* __restrict__ b) {
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < n; e += (size_t)gridDim.x * CWG) {
+        const _Float16 re = (_Float16)((float)(a[e].x * (double)HBASIS_SCALE));
+        const _Float16 im = (_Float16)((float)(a[e].y * (double)HBASIS_SCALE));
+        b[e] = (uint32_t)__builtin_bit_cast(unsigned short, re) | ((uint32_t)__builtin_bit_cast(unsigned short, im) << 16);
+    }
+}
+
 // fields[kk][comp][site][s] = basis vector k0+kk as a full fine field
 __global__ void __launch_bounds__(CWG) basis_expand_kernel(CoarseGeom c, const double2* __restrict__ b64, int k0,
                                                            int nk, double2* __restrict__ fields) {
@@ -213,6 +223,34 @@ template <typename T> __device__ __forceinline__ Pair<T> ld_pair(const C2<T>* p)
     return r;
 }
 
+// W consecutive basis entries starting at p, as complex T: the FP64 / FP32
+// regions directly, the FP16 copy ((fp16 re, fp16 im) words holding
+// HBASIS_SCALE * phi) decoded and rescaled.
+__device__ __forceinline__ float2 dec_h(uint32_t w) {
+    const float re = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+    const float im = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+    constexpr float inv = 1.0f / HBASIS_SCALE;
+    return make_float2(re * inv, im * inv);
+}
+template <typename T, int W> __device__ __forceinline__ void ld_basis(const C2<T>* p, C2<T> (&o)[W]) {
+    if constexpr (W == 2) {
+        const Pair<T> q = ld_pair<T>(p);
+        o[0] = q.a;
+        o[1] = q.b;
+    } else {
+        o[0] = *p;
+    }
+}
+template <typename T, int W> __device__ __forceinline__ void ld_basis(const uint32_t* p, float2 (&o)[W]) {
+    if constexpr (W == 2) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        o[0] = dec_h(q.x);
+        o[1] = dec_h(q.y);
+    } else {
+        o[0] = dec_h(*p);
+    }
+}
+
 constexpr int RKG = 16;  // basis vectors per restriction workgroup
 
 // grid (Nc, 2 chiralities, ceil(nvec / RKG)): v[a][h*nvec + k] = <phi^{a,h}_k, psi - psi2>
@@ -220,8 +258,8 @@ constexpr int RKG = 16;  // basis vectors per restriction workgroup
 // a row is (component, block site), so the loads of the compressed basis (index
 // row * Lh + s) and of psi are contiguous; W = 2 (Lh even) makes them 16-byte
 // pairs in FP32.
-template <typename T, bool SUB, int W>
-__global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>* __restrict__ basis,
+template <typename T, typename B, bool SUB, int W>
+__global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                        const C2<T>* __restrict__ psi, const C2<T>* __restrict__ psi2,
                                                        C2<T>* __restrict__ v) {
     __shared__ C2<T> sh[4 * RKG];
@@ -233,7 +271,7 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>
     const int sp = threadIdx.x % nsp, q0 = threadIdx.x / nsp;
     const int s = W * sp;
     const int nrows = 12 * c.bvol;
-    const C2<T>* bh = basis + (((size_t)a * 2 + h) * c.nvec + k0) * c.nhalf;
+    const B* bh = basis + (((size_t)a * 2 + h) * c.nvec + k0) * c.nhalf;
     const T r2 = (T)RSQRT2;
     C2<T> acc[RKG];
 #pragma unroll
@@ -269,13 +307,10 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>
 #pragma unroll
             for (int q = 0; q < RKG; ++q) {
                 if (q < kn) {
-                    if constexpr (W == 2) {
-                        const Pair<T> bv = ld_pair<T>(bh + (size_t)q * c.nhalf + i);
-                        acc[q] = cjfma<T>(bv.a, f[0], acc[q]);
-                        acc[q] = cjfma<T>(bv.b, f[W - 1], acc[q]);
-                    } else {
-                        acc[q] = cjfma<T>(bh[(size_t)q * c.nhalf + i], f[0], acc[q]);
-                    }
+                    C2<T> bv[W];
+                    ld_basis<T, W>(bh + (size_t)q * c.nhalf + i, bv);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) acc[q] = cjfma<T>(bv[w], f[w], acc[q]);
                 }
             }
         }
@@ -286,8 +321,12 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const C2<T>
         if (threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const C2<T>* __restrict__ basis,
+// psi = y + P v for coarse site a (one workgroup).  A work-item handles two
+// consecutive compressed indices (nhalf is even), so the basis loads are
+// 16-byte (FP32) or 8-byte (FP16) runs; each index yields the pair of outputs
+// at s and its mirror Ls-1-s.
+template <typename T, typename B>
+__global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                       const C2<T>* __restrict__ v, const C2<T>* __restrict__ y,
                                                       C2<T>* __restrict__ psi) {
     extern __shared__ unsigned char smem_raw[];
@@ -295,28 +334,39 @@ __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const C2<T>*
     const int a = blockIdx.x;
     for (int j = threadIdx.x; j < c.Nb; j += CWG) vs[j] = v[(size_t)a * c.Nb + j];
     __syncthreads();
-    const C2<T>* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
-    const C2<T>* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
+    const B* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
+    const B* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
     const T r2 = (T)RSQRT2;
-    for (int i = threadIdx.x; i < c.nhalf; i += CWG) {
-        C2<T> tp = mk<T>(0, 0), tm = mk<T>(0, 0);
+    for (int i0 = 2 * threadIdx.x; i0 < c.nhalf; i0 += 2 * CWG) {
+        C2<T> tp[2] = {mk<T>(0, 0), mk<T>(0, 0)}, tm[2] = {mk<T>(0, 0), mk<T>(0, 0)};
         for (int k = 0; k < c.nvec; ++k) {
-            tp = cfma<T>(bp[(size_t)k * c.nhalf + i], vs[k], tp);
-            tm = cfma<T>(bm[(size_t)k * c.nhalf + i], vs[c.nvec + k], tm);
+            C2<T> ep[2], em[2];
+            ld_basis<T, 2>(bp + (size_t)k * c.nhalf + i0, ep);
+            ld_basis<T, 2>(bm + (size_t)k * c.nhalf + i0, em);
+            const C2<T> xp = vs[k], xm = vs[c.nvec + k];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                tp[q] = cfma<T>(ep[q], xp, tp[q]);
+                tm[q] = cfma<T>(em[q], xm, tm[q]);
+            }
         }
-        const int s = i % c.Lh;
-        const int sl = (i / c.Lh) % c.bvol;
-        const int comp = i / (c.Lh * c.bvol);
-        const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
-        const T g = (comp < 6) ? (T)1 : (T)-1;
-        C2<T> o1 = mk<T>((tp.x + tm.x) * r2, (tp.y + tm.y) * r2);
-        C2<T> o2 = mk<T>(g * (tp.x - tm.x) * r2, g * (tp.y - tm.y) * r2);
-        if (y) {
-            o1 = cadd<T>(o1, y[fb + s]);
-            o2 = cadd<T>(o2, y[fb + c.f.Ls - 1 - s]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = i0 + q;
+            const int s = i % c.Lh;
+            const int sl = (i / c.Lh) % c.bvol;
+            const int comp = i / (c.Lh * c.bvol);
+            const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
+            const T g = (comp < 6) ? (T)1 : (T)-1;
+            C2<T> o1 = mk<T>((tp[q].x + tm[q].x) * r2, (tp[q].y + tm[q].y) * r2);
+            C2<T> o2 = mk<T>(g * (tp[q].x - tm[q].x) * r2, g * (tp[q].y - tm[q].y) * r2);
+            if (y) {
+                o1 = cadd<T>(o1, y[fb + s]);
+                o2 = cadd<T>(o2, y[fb + c.f.Ls - 1 - s]);
+            }
+            psi[fb + s] = o1;
+            psi[fb + c.f.Ls - 1 - s] = o2;
         }
-        psi[fb + s] = o1;
-        psi[fb + c.f.Ls - 1 - s] = o2;
     }
 }
 
@@ -843,35 +893,57 @@ void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, h
     hipLaunchKernelGGL(basis_to_f32_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, n, b64, b32);
 }
 
+void launch_basis_to_f16(const CoarseGeom& c, const double2* b64, uint32_t* b16, hipStream_t s) {
+    const size_t n = basis_elems(c);
+    hipLaunchKernelGGL(basis_to_f16_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, n, b64, b16);
+}
+
 void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk, double2* fields, hipStream_t s) {
     const size_t n = (size_t)12 * c.f.N5 * nk;
     hipLaunchKernelGGL(basis_expand_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, c, b64, k0, nk, fields);
 }
 
-template <typename T>
-void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
-                     hipStream_t s) {
+template <typename T, typename B>
+void restrict_launch(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v, hipStream_t s) {
     const dim3 grid(c.Nc, 2, (c.nvec + RKG - 1) / RKG);
     // two s slots per work-item when Ls/2 is even and a row fits the workgroup
     const bool two = (c.Lh % 2 == 0) && (c.Lh / 2 <= CWG);
     if (c.Lh > CWG) return;  // not reachable: Ls <= 512 is enforced by the descriptor checks
     if (two) {
         if (psi2)
-            hipLaunchKernelGGL((restrict_kernel<T, true, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+            hipLaunchKernelGGL((restrict_kernel<T, B, true, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
         else
-            hipLaunchKernelGGL((restrict_kernel<T, false, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+            hipLaunchKernelGGL((restrict_kernel<T, B, false, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
     } else {
         if (psi2)
-            hipLaunchKernelGGL((restrict_kernel<T, true, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+            hipLaunchKernelGGL((restrict_kernel<T, B, true, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
         else
-            hipLaunchKernelGGL((restrict_kernel<T, false, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+            hipLaunchKernelGGL((restrict_kernel<T, B, false, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
     }
+}
+
+template <typename T>
+void launch_restrict(const CoarseGeom& c, const C2<T>* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
+                     hipStream_t s) {
+    restrict_launch<T, C2<T>>(c, basis, psi, psi2, v, s);
+}
+
+void launch_restrict_h(const CoarseGeom& c, const uint32_t* basis, const float2* psi, const float2* psi2, float2* v,
+                       hipStream_t s) {
+    restrict_launch<float, uint32_t>(c, basis, psi, psi2, v, s);
 }
 
 template <typename T>
 void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
                     hipStream_t s) {
-    hipLaunchKernelGGL(prolong_kernel<T>, dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v, y, psi);
+    hipLaunchKernelGGL((prolong_kernel<T, C2<T>>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v, y,
+                       psi);
+}
+
+void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* v, const float2* y, float2* psi,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((prolong_kernel<float, uint32_t>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c, basis,
+                       v, y, psi);
 }
 
 template <typename T, typename S>

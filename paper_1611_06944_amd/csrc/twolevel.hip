@@ -228,16 +228,26 @@ struct CycleCounts {
 };
 
 // e = B r:  e1 = S r;  e2 = e1 + Q (r - H e1);  e = e2 + S (r - H e2),  Q = P A^-1 P^dag
+// bh: FP16 copy of the basis used for restriction and prolongation instead of
+// `basis` (FP32 cycle only), or null
 template <typename T>
-int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, const C2<T>* basis, const void* A,
-           const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm, CycleCounts& cnt, hipStream_t s) {
+int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, const C2<T>* basis, const uint32_t* bh,
+           const void* A, const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm, CycleCounts& cnt,
+           hipStream_t s) {
     const FineGeom& g = c.f;
     const int order = prm->cheb_order;
     tm.begin(PhaseTimer::FINE);
     cheb_smoother<T>(g, U, r, e, false, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
     launch_dslash<T>(g, U, e, w.t, s);
     tm.begin(PhaseTimer::COARSE);
-    launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+    if constexpr (sizeof(T) == 4) {
+        if (bh)
+            launch_restrict_h(c, bh, r, w.t, w.vc, s);
+        else
+            launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+    } else {
+        launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+    }
     int it = 0;
     int st = coarse_cr<T>(c, (hdcr_dtype)prm->coarse_dtype, A, w.vc, w.cx, prm->coarse_maxiter, prm->coarse_tol, w.ccr,
                           cnt.last_coarse, s, &it);
@@ -245,7 +255,14 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     cnt.last_coarse = it;
     cnt.coarse_iters += it;
     cnt.coarse_applies += it + 1;
-    launch_prolong<T>(c, basis, w.cx, e, e, s);
+    if constexpr (sizeof(T) == 4) {
+        if (bh)
+            launch_prolong_h(c, bh, w.cx, e, e, s);
+        else
+            launch_prolong<T>(c, basis, w.cx, e, e, s);
+    } else {
+        launch_prolong<T>(c, basis, w.cx, e, e, s);
+    }
     tm.begin(PhaseTimer::FINE);
     // d = r - H e2 (fused), e = e2 + S d
     launch_dslash_epi<T>(g, U, e, w.d, Epi<T>{{r, nullptr, nullptr, nullptr}, {(T)1, 0, 0, 0}, (T)-1, 1}, s);
@@ -322,10 +339,12 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
 
     const C2<T>* Uin;
     const C2<T>* bas;
+    const uint32_t* bh = nullptr;
     if constexpr (sizeof(T) == 4) {
         launch_convert<double2, float2>(36LL * g.V4, U, w.U_in, s);
         Uin = w.U_in;
         bas = basis32(c, basis);
+        if (prm->basis_dtype == HDCR_F16C) bh = basis16(c, basis);
     } else {
         Uin = U;
         bas = basis64(basis);
@@ -374,11 +393,11 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             if constexpr (sizeof(T) == 4) {
                 tm.begin(PhaseTimer::OUTER);
                 launch_convert<double2, float2>(n, w.r, w.r_in, s);
-                e = vcycle<T>(c, prm, Uin, bas, A, w.r_in, w.e_in, w.cyc, tm, cnt, s);
+                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r_in, w.e_in, w.cyc, tm, cnt, s);
                 tm.begin(PhaseTimer::OUTER);
                 launch_convert<float2, double2>(n, w.e_in, w.Z[i], s);
             } else {
-                e = vcycle<T>(c, prm, Uin, bas, A, w.r, w.Z[i], w.cyc, tm, cnt, s);
+                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r, w.Z[i], w.cyc, tm, cnt, s);
             }
             if (e) return e;
             tm.begin(PhaseTimer::OUTER);
@@ -507,6 +526,10 @@ int check_two_level_params(const hdcr_solve_params* p) {
     } else {
         return fail(HDCR_EINVAL, "inner_dtype must be C128 or C64");
     }
+    if (p->basis_dtype == HDCR_F16C && p->inner_dtype != HDCR_C64)
+        return fail(HDCR_EINVAL, "basis_dtype F16C needs inner_dtype C64");
+    if (p->basis_dtype != HDCR_F16C && p->basis_dtype != HDCR_C64 && p->basis_dtype != HDCR_C128)
+        return fail(HDCR_EINVAL, "basis_dtype must be C128, C64 or F16C");
     return HDCR_OK;
 }
 
@@ -553,14 +576,15 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
         HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
         launch_convert<double2, float2>(36LL * c.f.V4, U, U32, s);
         launch_convert<double2, float2>(n, r, r32, s);
-        int st = vcycle<float>(c, p, U32, basis32(c, basis), A, r32, e32, cw, tm, cnt, s);
+        int st = vcycle<float>(c, p, U32, basis32(c, basis), p->basis_dtype == HDCR_F16C ? basis16(c, basis) : nullptr,
+                                A, r32, e32, cw, tm, cnt, s);
         if (st) return st;
         launch_convert<float2, double2>(n, e32, e, s);
     } else {
         CycleWork<double> cw = cycle_carve<double>(w, c);
         if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
         HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
-        int st = vcycle<double>(c, p, U, basis64(basis), A, r, e, cw, tm, cnt, s);
+        int st = vcycle<double>(c, p, U, basis64(basis), nullptr, A, r, e, cw, tm, cnt, s);
         if (st) return st;
     }
     HDCR_HIP_CHECK(hipGetLastError());

@@ -50,8 +50,8 @@ def test_ctypes_mirror_matches_c_layout(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(hdcr_fine_desc), sizeof(hdcr_coarse_desc), sizeof(hdcr_solve_params),
          sizeof(hdcr_solve_stats));
-  printf("%zu %zu %zu\n", offsetof(hdcr_fine_desc, M5), offsetof(hdcr_coarse_desc, nvec),
-         offsetof(hdcr_solve_params, coarse_maxiter));
+  printf("%zu %zu %zu %zu\n", offsetof(hdcr_fine_desc, M5), offsetof(hdcr_coarse_desc, nvec),
+         offsetof(hdcr_solve_params, coarse_maxiter), offsetof(hdcr_solve_params, basis_dtype));
   printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
   return 0;
 }
@@ -62,7 +62,8 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     py = [ctypes.sizeof(_abi.FineDesc), ctypes.sizeof(_abi.CoarseDesc), ctypes.sizeof(_abi.SolveParams),
           ctypes.sizeof(_abi.SolveStats), _abi.FineDesc.M5.offset, _abi.CoarseDesc.nvec.offset,
-          _abi.SolveParams.coarse_maxiter.offset, _abi.SolveStats.true_rel_residual.offset,
+          _abi.SolveParams.coarse_maxiter.offset, _abi.SolveParams.basis_dtype.offset,
+          _abi.SolveStats.true_rel_residual.offset,
           _abi.SolveStats.history_len.offset]
     assert vals == py
 
@@ -122,6 +123,12 @@ def test_two_level_param_validation(lib):
                                                                        coarse_dtype=hd.C128)) == 0
     assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
                                                                        restart=99)) == 0
+    # the FP16 basis copy serves the FP32 inner cycle only
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
+                                                                       basis_dtype=hd.F16C)) > 0
+    assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
+                                                                       inner_dtype=hd.C128, coarse_dtype=hd.C128,
+                                                                       basis_dtype=hd.F16C)) == 0
     assert hd.workspace_bytes(hd._abi.WS_SOLVE, lat, hd.default_params(precond=hd.PRECOND_TWO_LEVEL,
                                                                        cheb_lo=2.0, cheb_hi=1.0)) == 0
     # odd Ls or a block that does not divide the lattice: invalid coarse space

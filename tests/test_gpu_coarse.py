@@ -91,6 +91,35 @@ def test_restrict_prolong_apply_parity(L, Ls, block, nvec):
     assert max_rel_elem(out1, ap_ref[1]) <= 1e-10
 
 
+@pytest.mark.parametrize("L,Ls,block,nvec", CASES[:2] + CASES[3:])
+def test_restrict_prolong_fp16_basis(L, Ls, block, nvec):
+    """Restriction and prolongation with the FP16 basis copy (FP32 vectors), against
+    the FP64 oracle.  Each basis entry carries a relative rounding error of at most
+    2^-11 (the copy stores 256 phi, inside the normal FP16 range), so component by
+    component |r - r_ref| <= 2^-11 sum |phi| |psi| and |P v - P_ref v| <= 2^-11
+    sum |phi| |v|; the sums of absolute values come from the oracle's own restrict
+    and prolong applied to |phi|, |psi| and |v|.  1e-5 of the same sums covers the
+    FP32 arithmetic."""
+    torch = torch_dev()
+    log(f"fp16 basis restrict/prolong L={L} Ls={Ls} block={block} nvec={nvec}")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    basis_ref, _ = oracle.block_basis(vecs, cs)
+    basis, _ = hd.build_coarse(lat, to_dev(hd.pack_gauge(U)), _dev_vecs(vecs), hd.C128)
+    psi = hi.gaussian_fermion(L, Ls, seed=7)
+    v = hi.gaussian_coarse(cs.nc, cs.nb, seed=8)
+    bound_r = (2.0 ** -11 + 1e-5) * oracle.restrict(np.abs(basis_ref), np.abs(psi), cs).real
+    bound_p = (2.0 ** -11 + 1e-5) * oracle.prolong(np.abs(basis_ref), np.abs(v), cs).real
+    r = to_host(hd.restrict(lat, basis, to_dev(hd.pack_fermion(psi), torch.complex64), half_basis=True))
+    err_r = np.abs(r - oracle.restrict(basis_ref, psi, cs))
+    assert np.all(err_r <= bound_r + 1e-30), float((err_r / (bound_r + 1e-30)).max())
+    pr = hd.unpack_fermion(to_host(hd.prolong(lat, basis, to_dev(v, torch.complex64), half_basis=True)), L, Ls)
+    err_p = np.abs(pr - oracle.prolong(basis_ref, v, cs))
+    assert np.all(err_p <= bound_p + 1e-30), float((err_p / (bound_p + 1e-30)).max())
+    # the bound is not vacuous: the FP16 path differs from the FP32 one
+    r32 = to_host(hd.restrict(lat, basis, to_dev(hd.pack_fermion(psi), torch.complex64)))
+    assert np.abs(r - r32).max() > 0
+
+
 def test_rank_deficient_vectors():
     torch_dev()
     L, Ls, block, nvec = (2, 2, 2, 2), 4, (2, 2, 2, 2), 3

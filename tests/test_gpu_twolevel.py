@@ -115,10 +115,11 @@ def test_hdcr_solve_fp64_matches_oracle_iterates():
     assert oracle.norm(b - ap(xs)) <= 1e-8 * bn
 
 
-@pytest.mark.parametrize("coarse", ["c64", "bf16"])
+@pytest.mark.parametrize("coarse", ["c64", "bf16", "bf16_f16basis"])
 def test_hdcr_solve_mixed_precision(coarse):
-    """FP32 inner cycle, C64 or BF16 coarse storage, coarse CR to 1e-2: converges to the
-    FP64 true residual 1e-8 and to the plain-CR solution."""
+    """FP32 inner cycle, C64 or BF16 coarse storage (optionally the FP16 basis copy for
+    restriction and prolongation), coarse CR to 1e-2: converges to the FP64 true
+    residual 1e-8 and to the plain-CR solution."""
     torch = torch_dev()
     L, Ls, block, nvec = (8, 8, 8, 8), 8, (4, 4, 4, 4), 8
     log(f"hdcr solve mixed precision coarse={coarse}")
@@ -134,7 +135,8 @@ def test_hdcr_solve_mixed_precision(coarse):
     cdt = hd.C64 if coarse == "c64" else hd.BF16C
     basis, A = hd.build_coarse(lat, Ud, vecs, cdt)
     prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=cdt, coarse_tol=1e-2,
-                            coarse_maxiter=200, restart=8, tol=1e-8, maxiter=200)
+                            coarse_maxiter=200, restart=8, tol=1e-8, maxiter=200,
+                            basis_dtype=hd.F16C if coarse.endswith("f16basis") else hd.C64)
     x, st, hist = hd.solve(lat, Ud, bd, params=prm, basis=basis, A=A)
     assert st["status"] == 0, st
     xs = hd.unpack_fermion(to_host(x), L, Ls)
