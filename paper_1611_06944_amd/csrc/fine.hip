@@ -82,19 +82,16 @@ template <typename T> __device__ __forceinline__ void axpy_i(T a, C2<T> x, C2<T>
     y.y = fma(a, x.x, y.y);
 }
 
-// One hop in direction MU (0..3 = x, y, z, t), forward (FWD) or backward:
-// psi at the neighbouring 5d site (byte offset noff), link u (U_mu(x) forward,
-// U_mu(x - mu) backward), hop coefficient coef, accumulated into acc.
+// Arithmetic of one hop in direction MU (0..3 = x, y, z, t), forward (FWD) or
+// backward: the 12 components v of psi at the neighbouring 5d site, link u
+// (U_mu(x) forward, U_mu(x - mu) backward), hop coefficient coef, accumulated
+// into acc.
 template <typename T, int MU, bool FWD>
-__device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<T> (&u)[9], T coef,
-                                    C2<T> (&acc)[12]) {
+__device__ __forceinline__ void hop_core(const C2<T> (&v)[12], const C2<T> (&u)[9], T coef, C2<T> (&acc)[12]) {
     C2<T> h0[3], h1[3];
 #pragma unroll
     for (int col = 0; col < 3; ++col) {
-        const C2<T> u0 = Buf<T>::ld(f.in, noff, (uint32_t)(0 * 3 + col) * f.cstride);
-        const C2<T> u1 = Buf<T>::ld(f.in, noff, (uint32_t)(1 * 3 + col) * f.cstride);
-        const C2<T> d0 = Buf<T>::ld(f.in, noff, (uint32_t)(2 * 3 + col) * f.cstride);
-        const C2<T> d1 = Buf<T>::ld(f.in, noff, (uint32_t)(3 * 3 + col) * f.cstride);
+        const C2<T> u0 = v[0 * 3 + col], u1 = v[1 * 3 + col], d0 = v[2 * 3 + col], d1 = v[3 * 3 + col];
         // h = u -+ w_mu d  (minus for the forward hop (1 - g), plus for backward (1 + g))
         if (MU == 0) {        // w_x d = (-i d1, -i d0)
             h0[col] = FWD ? cadd<T>(u0, cmuli<T>(d1)) : csub<T>(u0, cmuli<T>(d1));
@@ -133,6 +130,68 @@ __device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<
             axpy<T>(sl, H1[col], acc[3 * 3 + col]);
         }
     }
+}
+
+// The same hop with the direction given at run time: sg = +1 forward, -1
+// backward, and m the matrix already oriented for it (U_mu(x) forward,
+// U_mu(x - mu)^dag backward), so every hop multiplies by m.  The forward and
+// backward forms of hop_core compute the same floating-point operations.
+template <typename T, int MU>
+__device__ __forceinline__ void hop_core_rt(const C2<T> (&v)[12], const C2<T> (&m)[9], T sg, T coef,
+                                            C2<T> (&acc)[12]) {
+    C2<T> h0[3], h1[3];
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+        const C2<T> u0 = v[0 * 3 + col], u1 = v[1 * 3 + col], d0 = v[2 * 3 + col], d1 = v[3 * 3 + col];
+        // h = u - sg w_mu d
+        if (MU == 0) {        // w_x d = (-i d1, -i d0):  h = u + sg i (d1, d0)
+            h0[col] = mk<T>(fma(-sg, d1.y, u0.x), fma(sg, d1.x, u0.y));
+            h1[col] = mk<T>(fma(-sg, d0.y, u1.x), fma(sg, d0.x, u1.y));
+        } else if (MU == 1) { // w_y d = (-d1, d0):  h = (u0 + sg d1, u1 - sg d0)
+            h0[col] = mk<T>(fma(sg, d1.x, u0.x), fma(sg, d1.y, u0.y));
+            h1[col] = mk<T>(fma(-sg, d0.x, u1.x), fma(-sg, d0.y, u1.y));
+        } else if (MU == 2) { // w_z d = (-i d0, i d1):  h = (u0 + sg i d0, u1 - sg i d1)
+            h0[col] = mk<T>(fma(-sg, d0.y, u0.x), fma(sg, d0.x, u0.y));
+            h1[col] = mk<T>(fma(sg, d1.y, u1.x), fma(-sg, d1.x, u1.y));
+        } else {              // w_t d = (d0, d1):  h = u - sg d
+            h0[col] = mk<T>(fma(-sg, d0.x, u0.x), fma(-sg, d0.y, u0.y));
+            h1[col] = mk<T>(fma(-sg, d1.x, u1.x), fma(-sg, d1.y, u1.y));
+        }
+    }
+    C2<T> H0[3], H1[3];
+    su3_mul<T, false>(m, h0, H0);
+    su3_mul<T, false>(m, h1, H1);
+    const T sl = -sg * coef;
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+        axpy<T>(coef, H0[col], acc[0 * 3 + col]);
+        axpy<T>(coef, H1[col], acc[1 * 3 + col]);
+        if (MU == 0) {
+            axpy_i<T>(sl, H1[col], acc[2 * 3 + col]);
+            axpy_i<T>(sl, H0[col], acc[3 * 3 + col]);
+        } else if (MU == 1) {
+            axpy<T>(sl, H1[col], acc[2 * 3 + col]);
+            axpy<T>(-sl, H0[col], acc[3 * 3 + col]);
+        } else if (MU == 2) {
+            axpy_i<T>(sl, H0[col], acc[2 * 3 + col]);
+            axpy_i<T>(-sl, H1[col], acc[3 * 3 + col]);
+        } else {
+            axpy<T>(sl, H0[col], acc[2 * 3 + col]);
+            axpy<T>(sl, H1[col], acc[3 * 3 + col]);
+        }
+    }
+}
+
+// One hop in direction MU, forward (FWD) or backward: psi at the neighbouring 5d
+// site (byte offset noff) loaded from the field, link u (U_mu(x) forward,
+// U_mu(x - mu) backward), hop coefficient coef, accumulated into acc.
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<T> (&u)[9], T coef,
+                                    C2<T> (&acc)[12]) {
+    C2<T> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = Buf<T>::ld(f.in, noff, (uint32_t)c * f.cstride);
+    hop_core<T, MU, FWD>(v, u, coef, acc);
 }
 
 // Workgroup -> sites.  Hardware dispatch sends workgroup w to XCD w % 8; the
@@ -330,6 +389,102 @@ __global__ void __launch_bounds__(WG) dslash_tile_kernel(FineGeom g, const C2<T>
     store_out<T, NY, NT>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
 }
 
+// Parity-tile kernel (FP32, Ls = 16, every extent even).  The lattice is cut
+// into 2^4 tiles and a workgroup (256 work-items) holds one tile: work-item
+// (p, s) with p the parity pattern of its site inside the tile (bit mu = the
+// site's position along mu).  The tile's spinors are staged in LDS once; in
+// every direction one of the two hops stays in the tile (forward if bit mu is
+// 0, backward if it is 1) and reads the partner site's spinor from LDS, so
+// only four of the eight hops gather through the vector-memory path.  The
+// link matrices are staged already oriented for each hop (U_mu(x) forward,
+// U_mu(x - mu)^dag backward), so the direction is a run-time sign and the code
+// has no branch.
+struct TileGeom {
+    FineGeom t;  // the lattice of tiles (extents L / 2), traversal order of the tiles
+};
+
+template <int NY>
+__global__ void __launch_bounds__(WG) dslash_par_kernel(FineGeom g, TileGeom tg, const float2* U, const float2* in,
+                                                        float2* out, Epi<float> ep) {
+    typedef float T;
+    constexpr int LS = 16;
+    constexpr uint32_t CB = sizeof(float2);
+    __shared__ float2 spin[12 * 16 * LS];   // [c][pattern][s]
+    __shared__ float2 lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
+    const int p = threadIdx.x >> 4, s = threadIdx.x & 15;
+    const int tile = logical_block(blockIdx.x, gridDim.x);
+    const Site tt = traverse(tg.t, tile);
+    Site st;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) st.x[mu] = 2 * tt.x[mu] + ((p >> mu) & 1);
+    st.site = ((st.x[3] * g.L[2] + st.x[2]) * g.L[1] + st.x[1]) * g.L[0] + st.x[0];
+    const Nbrs<T> n = neighbours<T>(g, st);
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    // LDS matrix 2 mu: the hop of direction mu inside the tile, 2 mu + 1: the one
+    // leaving it (backward matrices stored conjugate-transposed)
+    if (s < 9) {
+        const int r = s / 3, cc = s - 3 * (s / 3);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const bool up = (p >> mu) & 1;  // the forward hop stays in the tile for up = 0
+            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + s) * CB, 0u);
+            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + s) * CB, 0u);
+            lds[(p * 8 + 2 * mu + (up ? 1 : 0)) * LPAD + s] = uf;
+            lds[(p * 8 + 2 * mu + (up ? 0 : 1)) * LPAD + cc * 3 + r] = mk<T>(ub.x, -ub.y);
+        }
+    }
+    C2<T> v[12];
+    {
+        const uint32_t o0 = (uint32_t)(st.site * LS + s) * CB;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = Buf<T>::ld(f.in, o0, (uint32_t)c * f.cstride);
+            spin[(c * 16 + p) * LS + s] = v[c];
+        }
+    }
+    __syncthreads();
+    const C2<T>* lnk = lds + p * 8 * LPAD;
+
+    C2<T> acc[12];
+    {
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (s == 0) ? mf : (T)-1;
+        const T cp = (s == LS - 1) ? mf : (T)-1;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const C2<T> w = (c < 6) ? s_neighbour<T, LS, true>(v[c], s) : s_neighbour<T, LS, false>(v[c], s);
+            const T cw = (c < 6) ? cm : cp;
+            acc[c] = mk<T>(fma(diag, v[c].x, cw * w.x), fma(diag, v[c].y, cw * w.y));
+        }
+    }
+    // direction MU: the hop inside the tile reads the partner's spinor from
+    // LDS, the hop leaving the tile gathers from the field
+#define HDCR_PAR_HOPS(MU)                                                                                    \
+    {                                                                                                        \
+        const bool up = (p >> MU) & 1;                                                                       \
+        const T sg_in = up ? (T)-1 : (T)1;                                                                   \
+        const int q = p ^ (1 << MU);                                                                         \
+        C2<T> m[9];                                                                                          \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU) * LPAD + e];                       \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = spin[(c * 16 + q) * LS + s];                   \
+        hop_core_rt<T, MU>(v, m, sg_in, up ? n.cb[MU] : n.cf[MU], acc);                                      \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU + 1) * LPAD + e];                   \
+        const uint32_t noff = (uint32_t)((up ? n.f[MU] : n.b[MU]) * LS + s) * CB;                            \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = Buf<T>::ld(f.in, noff, (uint32_t)c * f.cstride); \
+        hop_core_rt<T, MU>(v, m, -sg_in, up ? n.cf[MU] : n.cb[MU], acc);                                     \
+    }
+    HDCR_PAR_HOPS(0)
+    HDCR_PAR_HOPS(1)
+    HDCR_PAR_HOPS(2)
+    HDCR_PAR_HOPS(3)
+#undef HDCR_PAR_HOPS
+    store_out<T, NY, true>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
+}
+
 // Generic kernel: any Ls, links and fifth-dimension neighbours loaded
 // directly; CLS selects one hop class (coarse-operator build).
 template <typename T, bool CLS, int NY>
@@ -423,8 +578,40 @@ bool launch_tile_ls(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* o
 // output is not re-read by this launch; streaming it keeps the L2 for the
 // neighbour re-reads); generic kernel otherwise.  Tuning switch: variant 1
 // uses cached stores for the plain apply, variant 2 the generic kernel.
+// the lattice of 2^4 tiles for the parity-tile kernel (traversal order chosen
+// as for a lattice of those extents)
+TileGeom tile_geom(const FineGeom& g) {
+    TileGeom t;
+    t.t = g;
+    t.t.V4 = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        t.t.L[mu] = g.L[mu] / 2;
+        t.t.V4 *= t.t.L[mu];
+    }
+    // t slabs of about a quarter of the tile extent and y parts of about 6
+    // tile rows (measured best for 12^4 tiles, the 24^4 lattice)
+    int ts = t.t.L[3] >= 4 ? t.t.L[3] / 4 : t.t.L[3];
+    while (ts > 1 && t.t.L[3] % ts != 0) --ts;
+    int ys = t.t.L[1] / 6 > 0 ? t.t.L[1] / 6 : 1;
+    while (ys > 1 && t.t.L[1] % ys != 0) --ys;
+    choose_traversal(t.t, ts, ys);
+    return t;
+}
+
+bool par_ok(const FineGeom& g) {
+    return g.Ls == 16 && g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0;
+}
+
 template <typename T, int NY>
 void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        // parity-tile kernel for FP32 at Ls = 16 (variant 3 and above: off)
+        if (g.variant == 0 && par_ok(g)) {
+            const TileGeom tg = tile_geom(g);
+            hipLaunchKernelGGL((dslash_par_kernel<NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
+            return;
+        }
+    }
     if (g.variant != 2) {
         if (NY == 0 && g.variant == 1) {
             if (launch_tile_ls<T, false, NY>(g, U, in, out, ep, s)) return;

@@ -19,6 +19,8 @@ SHAPES = [
     ((4, 2, 6, 8), 1),      # Ls = 1 (Wilson limit)
     ((8, 8, 8, 8), 16),     # many workgroups
     ((3, 5, 2, 7), 16),     # tile kernel with DPP fifth-dimension exchange, ragged last workgroup
+    ((2, 2, 2, 6), 16),     # parity-tile kernel (FP32): 3 tiles, one workgroup with an empty slot
+    ((4, 2, 6, 2), 16),     # parity-tile kernel: extent-2 directions, ragged last workgroup
     ((2, 3, 2, 2), 32),     # tile kernel, fifth-dimension neighbours from memory
     ((2, 2, 1, 3), 64),     # one 4d site per wavefront
 ]
@@ -91,19 +93,22 @@ def test_apply_fine_linearity_and_hermiticity_fp64():
     np.testing.assert_allclose(to_host(Hz), to_host(a * Hx + Hy), atol=1e-12 * float(Hx.abs().max()))
 
 
-@pytest.mark.parametrize("L,Ls", [((4, 6, 2, 5), 16), ((3, 2, 4, 2), 8)])
+@pytest.mark.parametrize("L,Ls", [((4, 6, 2, 5), 16), ((4, 6, 2, 6), 16), ((3, 2, 4, 2), 8)])
 def test_kernel_variants_agree(L, Ls, monkeypatch):
-    """The tile kernel (LDS-staged links, DPP fifth-dimension exchange), its
-    cached-store form and the generic kernel give the same FP64 result."""
+    """The kernels of the fine apply give the same result: parity-tile (FP32,
+    even extents, Ls = 16; variant 0), tile kernel with cached (1) and
+    non-temporal (3) stores, generic kernel (2)."""
     torch = torch_dev()
     log(f"kernel variants L={L} Ls={Ls}")
     lat = Lattice(L, Ls, mf=0.05)
-    U = to_dev(pack_gauge(hi.gauge_field(L, seed=4)))
-    x = to_dev(pack_fermion(hi.gaussian_fermion(L, Ls, seed=3)))
-    outs = []
-    for v in ("0", "1", "2"):
-        monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
-        outs.append(to_host(apply_fine(lat, U, x)))
-    scale = np.abs(outs[2]).max()
-    for o in outs[:2]:
-        assert np.abs(o - outs[2]).max() <= 1e-14 * scale
+    Uh = pack_gauge(hi.gauge_field(L, seed=4))
+    xh = pack_fermion(hi.gaussian_fermion(L, Ls, seed=3))
+    for dt, tol in ((torch.complex128, 1e-14), (torch.complex64, 1e-6)):
+        U, x = to_dev(Uh, dt), to_dev(xh, dt)
+        outs = []
+        for v in ("0", "1", "3", "2"):
+            monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
+            outs.append(to_host(apply_fine(lat, U, x)))
+        scale = np.abs(outs[-1]).max()
+        for o in outs[:-1]:
+            assert np.abs(o - outs[-1]).max() <= tol * scale, dt
