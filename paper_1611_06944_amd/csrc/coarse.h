@@ -102,9 +102,10 @@ template <typename T> struct CoarseCRWork {
     C2<T>* p;
     C2<T>* Ar;
     C2<T>* Ap;
-    double* part;   // partial sums, 2 * max(Nc, CCR_BLOCKS) entries
+    double* part;   // partial sums: [2][Nc] of the apply, then CCR_BLOCKS of the update kernels
     double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
-    int* flags;     // 0 done, 1 iterations, 3 maxiter; CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
+    int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter;
+                    // CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
 };
 constexpr int CCR_BLOCKS = 64;
 constexpr int ARRIVE_GROUPS = 16;   // group counters of the last-arrival test

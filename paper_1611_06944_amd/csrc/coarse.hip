@@ -531,6 +531,22 @@ __device__ __forceinline__ void reduce_partials(const double* part, int np, doub
     for (int q = 0; q < NQ; ++q) out[q] = v[q];
 }
 
+// fixed-order sum of nq rows of np partials written by an earlier kernel; every
+// workgroup that calls it gets the same values (no cross-workgroup traffic)
+template <int NQ>
+__device__ __forceinline__ void sum_partials(const double* part, int np, double (&out)[NQ]) {
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] += part[(size_t)q * np + i];
+    }
+    block_reduce<NQ>(v);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = v[q];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __restrict__ b, C2<T>* __restrict__ x,
                                                        C2<T>* __restrict__ r, double* part, double* cs, int* flags,
@@ -552,14 +568,15 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
             cs[3] = s[0];
             cs[5] = tol2;
             flags[3] = maxiter;
+            flags[2] = 1;  // the sums of the first apply are still to be reduced
             flags[1] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0])) ? 1 : 0;
         }
     }
 }
 
-// Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar and
-// the sums <r,Ar>, |Ar|^2; else the sum <r,Ar> (the new value)
+// Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar.
+// Partial sums of <r,Ar> and |Ar|^2 per coarse site go to part[a], part[Nc+a].
 template <typename T, typename S, int E, bool FIRST>
 __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* __restrict__ A,
                                                         const C2<T>* __restrict__ r, C2<T>* __restrict__ Ar,
@@ -591,32 +608,35 @@ __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* _
         sums[1] += (double)o.x * o.x + (double)o.y * o.y;
     }
     block_reduce<2>(sums);
+    // partial sums only: the next update kernel reduces them in every one of
+    // its workgroups (no device-scope fence and atomic per coarse site here)
     if (threadIdx.x == 0) {
         part[a] = sums[0];
         part[c.Nc + a] = sums[1];
     }
-    if (last_arrival(flags + CCR_COUNTERS)) {
-        double t[2];
-        reduce_partials<2>(part, c.Nc, t);
-        if (threadIdx.x == 0) {
-            if (FIRST) {
-                cs[0] = t[0];
-                cs[2] = t[1];
-            } else {
-                cs[1] = t[0];
-            }
-            if (!(fabs(t[0]) > 0.0) || !isfinite(t[0])) flags[0] = 1;  // breakdown ends the coarse solve
-        }
-    }
 }
 
 // x += alpha p; r -= alpha Ap with alpha = <r,Ar>/|Ap|^2; |r|^2, convergence test
+// (right after the first apply: alpha = <r,Ar>/|Ar|^2 from the apply's partials)
 template <typename T>
 __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __restrict__ x, C2<T>* __restrict__ r,
                                                             const C2<T>* __restrict__ p, const C2<T>* __restrict__ Ap,
-                                                            double* part, double* cs, int* flags) {
+                                                            const double* apart, int nc, double* part, double* cs,
+                                                            int* flags) {
     if (flags[0]) return;
-    const T alpha = (T)(cs[0] / cs[2]);
+    const bool first = flags[2] != 0;
+    double rar = cs[0], apap = cs[2];
+    if (first) {
+        double t[2];
+        sum_partials<2>(apart, nc, t);
+        rar = t[0];
+        apap = t[1];
+        if (!(fabs(rar) > 0.0) || !isfinite(rar)) {  // breakdown ends the coarse solve
+            if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+            return;
+        }
+    }
+    const T alpha = (T)(rar / apap);
     double v[1] = {0.0};
     for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
         C2<T> xv = x[i], rv = r[i];
@@ -635,6 +655,11 @@ __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __rest
         double s[1];
         reduce_partials<1>(part, gridDim.x, s);
         if (threadIdx.x == 0) {
+            if (first) {
+                cs[0] = rar;
+                cs[2] = apap;
+                flags[2] = 0;
+            }
             cs[3] = s[0];
             const int it = flags[1] + 1;
             flags[1] = it;
@@ -644,12 +669,21 @@ __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __rest
 }
 
 // p = r + beta p; Ap = Ar + beta Ap with beta = <r,Ar>_new/<r,Ar>; |Ap|^2
+// (<r,Ar>_new reduced from the apply's partials in every workgroup)
 template <typename T>
 __global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* __restrict__ r, C2<T>* __restrict__ p,
                                                            const C2<T>* __restrict__ Ar, C2<T>* __restrict__ Ap,
-                                                           double* part, double* cs, int* flags) {
+                                                           const double* apart, int nc, double* part, double* cs,
+                                                           int* flags) {
     if (flags[0]) return;
-    const T beta = (T)(cs[1] / cs[0]);
+    double t[1];
+    sum_partials<1>(apart, nc, t);
+    const double rar_new = t[0];
+    if (!(fabs(rar_new) > 0.0) || !isfinite(rar_new)) {  // breakdown ends the coarse solve
+        if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+        return;
+    }
+    const T beta = (T)(rar_new / cs[0]);
     double v[1] = {0.0};
     for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
         C2<T> pv = p[i], apv = Ap[i];
@@ -669,7 +703,7 @@ __global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* _
         reduce_partials<1>(part, gridDim.x, s);
         if (threadIdx.x == 0) {
             cs[2] = s[0];
-            cs[0] = cs[1];
+            cs[0] = rar_new;
         }
     }
 }
@@ -847,8 +881,8 @@ template <typename T>
 void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,
                      hipStream_t s) {
     const double tol2 = tol > 0 ? tol * tol : 0.0;
-    hipLaunchKernelGGL(ccr_init_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, c.Nc * c.Nb, b, x, w.r, w.part, w.cs,
-                       w.flags, maxiter, tol2);
+    hipLaunchKernelGGL(ccr_init_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, c.Nc * c.Nb, b, x, w.r,
+                       w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
 }
 
 template <typename T>
@@ -859,11 +893,12 @@ void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<
         ccr_apply_dispatch<T, true>(c, A_dtype, A, w, s);
         return;
     }
-    hipLaunchKernelGGL(ccr_update_xr_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, x, w.r, w.p, w.Ap, w.part, w.cs,
-                       w.flags);
+    double* upart = w.part + 2 * (size_t)c.Nc;  // partials of the update kernels
+    hipLaunchKernelGGL(ccr_update_xr_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, x, w.r, w.p, w.Ap,
+                       (const double*)w.part, c.Nc, upart, w.cs, w.flags);
     ccr_apply_dispatch<T, false>(c, A_dtype, A, w, s);
-    hipLaunchKernelGGL(ccr_update_p_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, w.r, w.p, w.Ar, w.Ap, w.part,
-                       w.cs, w.flags);
+    hipLaunchKernelGGL(ccr_update_p_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, w.r, w.p, w.Ar, w.Ap,
+                       (const double*)w.part, c.Nc, upart, w.cs, w.flags);
 }
 
 template void launch_ccr_init<double>(const CoarseGeom&, const double2*, double2*, const CoarseCRWork<double>&, int,

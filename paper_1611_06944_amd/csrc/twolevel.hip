@@ -72,7 +72,7 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
     k.p = w.take<C2<T>>(n);
     k.Ar = w.take<C2<T>>(n);
     k.Ap = w.take<C2<T>>(n);
-    k.part = w.take<double>(2 * (size_t)std::max(c.Nc, CCR_BLOCKS));
+    k.part = w.take<double>(2 * (size_t)c.Nc + CCR_BLOCKS);
     k.cs = w.take<double>(8);
     k.flags = w.take<int>(CCR_FLAGS);
     return k;
@@ -275,16 +275,18 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
 // ---------------------------------------------------------------------------
 // flexible GCR (FP64 outer iteration) preconditioned with the two-level cycle
 // ---------------------------------------------------------------------------
+// Search directions Z_i (cycle outputs) and W_i = H Z_i are stored in the inner
+// precision T and W_i is computed by the stencil in T; x, r, every inner
+// product and the true residual at each restart are FP64.
 template <typename T> struct FgcrWork {
-    double2* Z[MAXV];
-    double2* W[MAXV];
+    C2<T>* Z[MAXV];
+    C2<T>* W[MAXV];
     double2* r;
     double2* tmp;
     double* part;
     double* S;        // device scalars: D1 [0,17), D2 [17,34), D3 [34,51), rr 51, bb 52
     C2<T>* U_in;      // inner-precision links (FP32 copy, or null for FP64)
-    C2<T>* r_in;
-    C2<T>* e_in;
+    C2<T>* r_in;      // r in the inner precision (FP32 cycle only)
     CycleWork<T> cyc;
 };
 constexpr int SD1 = 0, SD2 = 2 * MAXV + 1, SD3 = 2 * (2 * MAXV + 1), SRR = 3 * (2 * MAXV + 1), SBB = SRR + 1,
@@ -294,8 +296,8 @@ template <typename T> FgcrWork<T> fgcr_carve(Carver& w, const CoarseGeom& c, int
     const size_t n = (size_t)12 * c.f.N5;
     FgcrWork<T> k;
     for (int i = 0; i < MAXV; ++i) {
-        k.Z[i] = (i < m) ? w.take<double2>(n) : nullptr;
-        k.W[i] = (i < m) ? w.take<double2>(n) : nullptr;
+        k.Z[i] = (i < m) ? w.take<C2<T>>(n) : nullptr;
+        k.W[i] = (i < m) ? w.take<C2<T>>(n) : nullptr;
     }
     k.r = w.take<double2>(n);
     k.tmp = w.take<double2>(n);
@@ -304,11 +306,9 @@ template <typename T> FgcrWork<T> fgcr_carve(Carver& w, const CoarseGeom& c, int
     if (sizeof(T) == 4) {
         k.U_in = w.take<C2<T>>((size_t)36 * c.f.V4);
         k.r_in = w.take<C2<T>>(n);
-        k.e_in = w.take<C2<T>>(n);
     } else {
         k.U_in = nullptr;
         k.r_in = nullptr;
-        k.e_in = nullptr;
     }
     k.cyc = cycle_carve<T>(w, c);
     return k;
@@ -381,7 +381,9 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
         status = HDCR_OK;
     }
     typedef std::complex<double> cd;
+    bool true_res = true;  // r is the true residual of x
     while (status == HDCR_ENOTCONV && it < prm->maxiter) {
+        true_res = false;
         // coefficient of the normalised directions zhat_i over the raw Z_j
         std::vector<std::vector<cd>> coef;
         std::vector<cd> alpha;
@@ -393,32 +395,33 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             if constexpr (sizeof(T) == 4) {
                 tm.begin(PhaseTimer::OUTER);
                 launch_convert<double2, float2>(n, w.r, w.r_in, s);
-                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r_in, w.e_in, w.cyc, tm, cnt, s);
-                tm.begin(PhaseTimer::OUTER);
-                launch_convert<float2, double2>(n, w.e_in, w.Z[i], s);
+                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r_in, w.Z[i], w.cyc, tm, cnt, s);
             } else {
                 e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r, w.Z[i], w.cyc, tm, cnt, s);
             }
             if (e) return e;
             tm.begin(PhaseTimer::OUTER);
             // w_i = H z_i, orthogonalised twice against the previous (normalised) w_j
-            launch_dslash<double>(g, U, w.Z[i], w.W[i], s);
-            ++n64;
-            PtrList Wl{};
+            launch_dslash<T>(g, Uin, w.Z[i], w.W[i], s);
+            if (sizeof(T) == 8)
+                ++n64;
+            else
+                ++cnt.fine;
+            PtrListT<T> Wl{};
             for (int j = 0; j < i; ++j) Wl.p[j] = w.W[j];
             if (i > 0) {
-                launch_multidot(n, Wl, i, w.W[i], w.part, w.S + SD1, s);
-                launch_multi_axpy(n, Wl, i, w.S + SD1, w.W[i], s);
-                launch_multidot(n, Wl, i, w.W[i], w.part, w.S + SD2, s);
-                launch_multi_axpy(n, Wl, i, w.S + SD2, w.W[i], s);
+                launch_multidot<T, T>(n, Wl, i, w.W[i], w.part, w.S + SD1, s);
+                launch_multi_axpy<T>(n, Wl, i, w.S + SD1, w.W[i], s);
+                launch_multidot<T, T>(n, Wl, i, w.W[i], w.part, w.S + SD2, s);
+                launch_multi_axpy<T>(n, Wl, i, w.S + SD2, w.W[i], s);
             }
             // <r, w>, |w|^2; r -= (<w, r>/|w|^2) w; normalise w
             PtrList Rl{};
             Rl.p[0] = w.r;
-            launch_multidot(n, Rl, 1, w.W[i], w.part, w.S + SD3, s);
-            launch_r_update(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
+            launch_multidot<double, T>(n, Rl, 1, w.W[i], w.part, w.S + SD3, s);
+            launch_r_update<T>(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
             launch_finalize_real(w.part, 1, w.S, SRR, -1, -1, -1, s);
-            launch_scale_inv_sqrt<double>(n, w.W[i], w.S, SD3 + 2 * MAXV, s);
+            launch_scale_inv_sqrt<T>(n, w.W[i], w.S, SD3 + 2 * MAXV, s);
             tm.end();
             HDCR_HIP_CHECK(readS());
             ++it;
@@ -462,13 +465,13 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
                 for (int k = 0; k < nz; ++k) gq += alpha[k] * coef[k][q];
                 gam[q] = make_double2(gq.real(), gq.imag());
             }
-            PtrList Zl{};
+            PtrListT<T> Zl{};
             for (int q = 0; q < m && q < MAXV; ++q) Zl.p[q] = w.Z[q];
             tm.begin(PhaseTimer::OUTER);
-            launch_multi_update(n, Zl, std::min(m, MAXV), gam.data(), x, s);
+            launch_multi_update<T>(n, Zl, std::min(m, MAXV), gam.data(), x, s);
         }
         if (stop) break;
-        // true residual at every restart
+        // true residual at every restart (r then holds b - H x for the current x)
         tm.begin(PhaseTimer::OUTER);
         launch_dslash<double>(g, U, x, w.tmp, s);
         ++n64;
@@ -482,15 +485,18 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             break;
         }
         if (rr <= tol2) status = HDCR_OK;
+        true_res = true;
     }
-    // final true residual
-    tm.begin(PhaseTimer::OUTER);
-    launch_dslash<double>(g, U, x, w.tmp, s);
-    ++n64;
-    launch_sub<double>(n, b, w.tmp, w.r, s);
-    launch_norm2<double>(n, w.r, w.part, w.S, SRR, s);
-    tm.end();
-    HDCR_HIP_CHECK(readS());
+    // final true residual (unless the restart just computed it for this x)
+    if (!true_res) {
+        tm.begin(PhaseTimer::OUTER);
+        launch_dslash<double>(g, U, x, w.tmp, s);
+        ++n64;
+        launch_sub<double>(n, b, w.tmp, w.r, s);
+        launch_norm2<double>(n, w.r, w.part, w.S, SRR, s);
+        tm.end();
+        HDCR_HIP_CHECK(readS());
+    }
     HDCR_HIP_CHECK(hipGetLastError());
     const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) {
@@ -603,15 +609,15 @@ C2<T>* cheb_filter(const FineGeom& g, const C2<T>* U, int degree, double lo, dou
     const int64_t n = 12LL * g.N5;
     if (degree == 0) return t0;
     const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
+    // the combinations ride in the epilogue of the second stencil pass
     launch_dslash<T>(g, U, t0, v, s);
-    launch_dslash<T>(g, U, v, wv, s);
-    launch_axpby<T>(n, (T)b1, t0, (T)a1, wv, s);   // wv = yhat t0
-    std::swap(t1, wv);                              // t1 = T_1
+    launch_dslash_epi<T>(g, U, v, wv, Epi<T>{{t0, nullptr, nullptr, nullptr}, {(T)b1, 0, 0, 0}, (T)a1, 1}, s);
+    std::swap(t1, wv);                              // t1 = T_1 = yhat t0
     const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
     for (int j = 2; j <= degree; ++j) {
+        // t0 <- 2 yhat t1 - t0 = a2 H (H t1) + b2 t1 - t0 (in place)
         launch_dslash<T>(g, U, t1, v, s);
-        launch_dslash<T>(g, U, v, wv, s);
-        launch_cheb_step<T>(n, (T)a2, wv, (T)b2, t1, t0, (T)0, (C2<T>*)nullptr, s);  // t0 = T_j
+        launch_dslash_epi<T>(g, U, v, t0, Epi<T>{{t1, t0, nullptr, nullptr}, {(T)b2, (T)-1, 0, 0}, (T)a2, 2}, s);
         std::swap(t0, t1);
         if (j % 16 == 0) {
             launch_norm2<T>(n, t1, part, S, 0, s);
@@ -763,7 +769,7 @@ int hdcr_power_max(const hdcr_fine_desc* desc, const void* U, const void* v0, in
         launch_dslash<double>(g, Ud, v, t, stream);
         launch_dslash<double>(g, Ud, t, u, stream);
         Vl.p[0] = v;
-        launch_multidot(n, Vl, 1, u, part, S + 8, stream);  // S[8] = Re<v,u>, S[8+2*MAXV] = |u|^2
+        launch_multidot<double, double>(n, Vl, 1, u, part, S + 8, stream);  // S[8] = Re<v,u>, S[8+2*MAXV] = |u|^2
         launch_scale_inv_sqrt<double>(n, u, S, 8 + 2 * MAXV, stream);
         std::swap(v, u);
     }

@@ -49,26 +49,6 @@ __global__ void __launch_bounds__(VWG) sub_kernel(int64_t n, const C2<T>* __rest
         out[i] = csub<T>(x[i], y[i]);
 }
 
-// Chebyshev step: t0 <- a w + b t1 - t0 ;  acc <- acc + c t0 (the new term)
-template <typename T>
-__global__ void __launch_bounds__(VWG) cheb_step_kernel(int64_t n, T a, const C2<T>* __restrict__ w, T b,
-                                                        const C2<T>* __restrict__ t1, C2<T>* __restrict__ t0, T c,
-                                                        C2<T>* __restrict__ acc) {
-    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
-        const C2<T> wv = w[i], t1v = t1[i], t0v = t0[i];
-        C2<T> nv;
-        nv.x = a * wv.x + b * t1v.x - t0v.x;
-        nv.y = a * wv.y + b * t1v.y - t0v.y;
-        t0[i] = nv;
-        if (acc) {
-            C2<T> av = acc[i];
-            av.x += c * nv.x;
-            av.y += c * nv.y;
-            acc[i] = av;
-        }
-    }
-}
-
 // out = a x (real a)
 template <typename T>
 __global__ void __launch_bounds__(VWG) scale_kernel(int64_t n, T a, const C2<T>* __restrict__ x,
@@ -79,20 +59,24 @@ __global__ void __launch_bounds__(VWG) scale_kernel(int64_t n, T a, const C2<T>*
     }
 }
 
-// partial sums of <V[j], y> for j < nv (and |y|^2 if want_norm) into part[q * REDUCE_BLOCKS + blk]
-__global__ void __launch_bounds__(REDUCE_THREADS) multidot_kernel(int64_t n, PtrList V,
-                                                                  int nv, const double2* __restrict__ y,
+// partial sums of <V[j], y> for j < nv and |y|^2 into part[q * REDUCE_BLOCKS + blk]
+// (V and y in FP64 or FP32 storage, FP64 accumulation)
+template <typename TV, typename TY>
+__global__ void __launch_bounds__(REDUCE_THREADS) multidot_kernel(int64_t n, PtrListT<TV> V, int nv,
+                                                                  const C2<TY>* __restrict__ y,
                                                                   double* __restrict__ part) {
     double acc[2 * MAXV + 1];
 #pragma unroll
     for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double2 yv = y[i];
+        const C2<TY> yt = y[i];
+        const double2 yv = make_double2(yt.x, yt.y);
 #pragma unroll
         for (int j = 0; j < MAXV; ++j) {
             if (j < nv) {
-                const double2 v = V.p[j][i];
+                const C2<TV> vt = V.p[j][i];
+                const double2 v = make_double2(vt.x, vt.y);
                 acc[2 * j] += v.x * yv.x + v.y * yv.y;
                 acc[2 * j + 1] += v.x * yv.y - v.y * yv.x;
             }
@@ -116,47 +100,60 @@ __global__ void __launch_bounds__(REDUCE_THREADS) multidot_finalize_kernel(const
     if (threadIdx.x == 0) out[q] = v[0];
 }
 
-// y <- y - sum_j coef[j] V[j]   (coef: complex, device memory)
-__global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrList V, int nv,
-                                                         const double* __restrict__ coef, double2* __restrict__ y) {
+// y <- y - sum_j coef[j] V[j]   (coef: complex, device memory; FP64 arithmetic, one rounding to TV)
+template <typename TV>
+__global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrListT<TV> V, int nv,
+                                                         const double* __restrict__ coef, C2<TV>* __restrict__ y) {
     double2 cf[MAXV];
 #pragma unroll
     for (int j = 0; j < MAXV; ++j) cf[j] = (j < nv) ? make_double2(coef[2 * j], coef[2 * j + 1]) : make_double2(0, 0);
     for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
-        double2 yv = y[i];
+        const C2<TV> yt = y[i];
+        double2 yv = make_double2(yt.x, yt.y);
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j)
-            if (j < nv) yv = cfma<double>(cneg<double>(cf[j]), V.p[j][i], yv);
-        y[i] = yv;
+        for (int j = 0; j < MAXV; ++j) {
+            if (j < nv) {
+                const C2<TV> vt = V.p[j][i];
+                yv = cfma<double>(cneg<double>(cf[j]), make_double2(vt.x, vt.y), yv);
+            }
+        }
+        y[i] = mk<TV>((TV)yv.x, (TV)yv.y);
     }
 }
 
-// x <- x + sum_j g[j] Z[j]   (g: complex, kernel arguments)
+// x <- x + sum_j g[j] Z[j]   (g: complex, kernel arguments; x FP64)
 struct Coefs {
     double2 g[MAXV];
 };
-__global__ void __launch_bounds__(VWG) multi_update_kernel(int64_t n, PtrList Z, int nz,
-                                                           Coefs g, double2* __restrict__ x) {
+template <typename TV>
+__global__ void __launch_bounds__(VWG) multi_update_kernel(int64_t n, PtrListT<TV> Z, int nz, Coefs g,
+                                                           double2* __restrict__ x) {
     for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
         double2 xv = x[i];
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j)
-            if (j < nz) xv = cfma<double>(g.g[j], Z.p[j][i], xv);
+        for (int j = 0; j < MAXV; ++j) {
+            if (j < nz) {
+                const C2<TV> zt = Z.p[j][i];
+                xv = cfma<double>(g.g[j], make_double2(zt.x, zt.y), xv);
+            }
+        }
         x[i] = xv;
     }
 }
 
 // r <- r - (conj(c) / nn) w with c = (S[ic], S[ic+1]) = <r, w> and nn = S[inn] = |w|^2
-// (so the step is <w, r>/|w|^2); partial |r|^2
+// (so the step is <w, r>/|w|^2); partial |r|^2.  r FP64, w FP64 or FP32.
+template <typename TV>
 __global__ void __launch_bounds__(REDUCE_THREADS) r_update_kernel(int64_t n, const double* __restrict__ S, int ic,
-                                                                  int inn, const double2* __restrict__ w,
+                                                                  int inn, const C2<TV>* __restrict__ w,
                                                                   double2* __restrict__ r, double* __restrict__ part) {
     const double nn = S[inn];
     const double2 a = make_double2(S[ic] / nn, -S[ic + 1] / nn);
     double v[1] = {0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double2 rv = cfma<double>(cneg<double>(a), w[i], r[i]);
+        const C2<TV> wt = w[i];
+        double2 rv = cfma<double>(cneg<double>(a), make_double2(wt.x, wt.y), r[i]);
         r[i] = rv;
         v[0] += rv.x * rv.x + rv.y * rv.y;
     }
@@ -223,43 +220,57 @@ void launch_sub(int64_t n, const C2<T>* x, const C2<T>* y, C2<T>* out, hipStream
     hipLaunchKernelGGL(sub_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, x, y, out);
 }
 template <typename T>
-void launch_cheb_step(int64_t n, T a, const C2<T>* w, T b, const C2<T>* t1, C2<T>* t0, T c, C2<T>* acc,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, a, w, b, t1, t0, c, acc);
-}
-template <typename T>
 void launch_scale(int64_t n, T a, const C2<T>* x, C2<T>* out, hipStream_t s) {
     hipLaunchKernelGGL(scale_kernel<T>, dim3(vgrid(n)), dim3(VWG), 0, s, n, a, x, out);
 }
 #define HDCR_VEC_INST(T)                                                                                      \
     template void launch_axpby<T>(int64_t, T, const C2<T>*, T, C2<T>*, hipStream_t);                           \
     template void launch_sub<T>(int64_t, const C2<T>*, const C2<T>*, C2<T>*, hipStream_t);                     \
-    template void launch_cheb_step<T>(int64_t, T, const C2<T>*, T, const C2<T>*, C2<T>*, T, C2<T>*, hipStream_t); \
     template void launch_scale<T>(int64_t, T, const C2<T>*, C2<T>*, hipStream_t);
 HDCR_VEC_INST(double)
 HDCR_VEC_INST(float)
 #undef HDCR_VEC_INST
 
-void launch_multidot(int64_t n, const PtrList& V, int nv, const double2* y, double* part, double* out,
+template <typename TV, typename TY>
+void launch_multidot(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y, double* part, double* out,
                      hipStream_t s) {
-    hipLaunchKernelGGL(multidot_kernel, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, y, part);
+    hipLaunchKernelGGL((multidot_kernel<TV, TY>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, y, part);
     hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
                        out);
 }
 
-void launch_multi_axpy(int64_t n, const PtrList& V, int nv, const double* coef, double2* y, hipStream_t s) {
-    hipLaunchKernelGGL(multi_axpy_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, V, nv, coef, y);
+template <typename TV>
+void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_kernel<TV>, dim3(vgrid(n)), dim3(VWG), 0, s, n, V, nv, coef, y);
 }
 
-void launch_multi_update(int64_t n, const PtrList& Z, int nz, const double2* g, double2* x, hipStream_t s) {
+template <typename TV>
+void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2* g, double2* x, hipStream_t s) {
     Coefs c;
     for (int j = 0; j < MAXV; ++j) c.g[j] = (j < nz) ? g[j] : make_double2(0, 0);
-    hipLaunchKernelGGL(multi_update_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, Z, nz, c, x);
+    hipLaunchKernelGGL(multi_update_kernel<TV>, dim3(vgrid(n)), dim3(VWG), 0, s, n, Z, nz, c, x);
 }
 
-void launch_r_update(int64_t n, const double* S, int ic, int inn, const double2* w, double2* r, double* part,
+template <typename TV>
+void launch_r_update(int64_t n, const double* S, int ic, int inn, const C2<TV>* w, double2* r, double* part,
                      hipStream_t s) {
-    hipLaunchKernelGGL(r_update_kernel, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, S, ic, inn, w, r, part);
+    hipLaunchKernelGGL(r_update_kernel<TV>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, S, ic, inn, w, r,
+                       part);
 }
+
+template void launch_multidot<double, double>(int64_t, const PtrListT<double>&, int, const double2*, double*, double*,
+                                              hipStream_t);
+template void launch_multidot<float, float>(int64_t, const PtrListT<float>&, int, const float2*, double*, double*,
+                                            hipStream_t);
+template void launch_multidot<double, float>(int64_t, const PtrListT<double>&, int, const float2*, double*, double*,
+                                             hipStream_t);
+template void launch_multi_axpy<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, hipStream_t);
+template void launch_multi_axpy<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, hipStream_t);
+template void launch_multi_update<double>(int64_t, const PtrListT<double>&, int, const double2*, double2*,
+                                          hipStream_t);
+template void launch_multi_update<float>(int64_t, const PtrListT<float>&, int, const double2*, double2*, hipStream_t);
+template void launch_r_update<double>(int64_t, const double*, int, int, const double2*, double2*, double*,
+                                      hipStream_t);
+template void launch_r_update<float>(int64_t, const double*, int, int, const float2*, double2*, double*, hipStream_t);
 
 }  // namespace hdcr
