@@ -206,6 +206,42 @@ def main():
         res["ev64"] = fine_sweep("c128", args.applies)
         return res
 
+    def coarse_batched():
+        """Multi-RHS coarse apply (16^4 x 16 fine, coarse 4^4 from 4^4 blocks, Nb = 64, 12 right-hand
+        sides, BF16 A): autotuned matrix-core kernel vs one single-RHS launch per right-hand side."""
+        latc = hd.Lattice((16, 16, 16, 16), 16, block=(4, 4, 4, 4), nvec=32)
+        nrhs = 12
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(21)
+        raw = torch.randn(hd.coarse_bytes(latc, hd.C128) // 8, dtype=torch.float64, device=dev, generator=gen)
+        Ab = hd.convert_coarse(latc, raw, hd.BF16C)
+        del raw
+        v = torch.randn((nrhs, latc.nc, latc.nb), dtype=torch.complex64, device=dev, generator=gen)
+        out = torch.empty_like(v)
+        best, ms = hd.tune_coarse_batched(latc, Ab, v, out)
+
+        def timed(fn, n=20):
+            for _ in range(3):
+                fn()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+            for a_, b_ in evs:
+                a_.record(stream)
+                fn()
+                b_.record(stream)
+            torch.cuda.synchronize()
+            return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+
+        t_b = timed(lambda: hd.apply_coarse_batched(latc, Ab, v, out))
+        t_1 = timed(lambda: [hd.apply_coarse(latc, Ab, hd.BF16C, v[r], out[r]) for r in range(nrhs)])
+        a_bytes = hd.coarse_bytes(latc, hd.BF16C)
+        flops = 8.0 * latc.nb * latc.nb * 9 * latc.nc * nrhs
+        return {"workload": "16x16x16x16x16, coarse 4^4, Nb=64, 12 rhs, bf16 A (synthetic)",
+                "batched_variant": best, "variant_ms": [round(x, 4) for x in ms],
+                "batched_us": round(t_b * 1e3, 1), "single_rhs_loop_us": round(t_1 * 1e3, 1),
+                "speedup": round(t_1 / t_b, 2), "A_GBps": round(a_bytes / (t_b * 1e-3) / 1e9, 1),
+                "mfma_TFLOPs": round(flops / (t_b * 1e-3) / 1e12, 2),
+                "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5)}
+
     for _ in range(args.warmup):
         r = step()
         if not args.fine_only:
@@ -269,6 +305,9 @@ def main():
             "setup": setup,
             "setup_plus_solve_s": round(hw + setup.get("subspace_s", 0) + setup.get("coarse_build_s", 0), 3),
         }
+    if not args.fine_only:
+        out["coarse_multi_rhs"] = coarse_batched()
+        progress("multi-RHS coarse apply measured")
     if not args.no_cpu_baseline:
         progress("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(U_aos, b_aos, L, Ls, args.cpu_sample_applies)

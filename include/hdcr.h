@@ -187,6 +187,29 @@ HDCR_API int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, cons
 HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* A_dst,
                         hipStream_t stream);
 
+/* Batched coarse apply on the matrix cores (Sec. 4, the little Dirac operator
+ * applied to many right-hand sides at once): out[r] = A v[r], r < nrhs, with A
+ * in BF16C storage and the vectors rounded to bf16 (round to nearest even) for
+ * a BF16 x BF16 contraction with FP32 accumulation.  v, out: C64
+ * [nrhs][site_c][k], not overlapping.  Needs Nb in {16, 32, 64, 128}.
+ * variant 0: the tile shape hdcr_tune_coarse_batched chose for this shape
+ * (variant 2, or 1 for Nb = 16, if it has not been tuned); 1..HDCR_MFMA_VARIANTS:
+ * an explicit tile shape (2, 4, 8 wavefronts per coarse site, blocks read
+ * directly or staged in LDS; 7: 8 wavefronts with all 9 blocks prefetched, Nb =
+ * 64 only); a variant with more wavefronts than Nb / 8 is rejected.  All variants perform the same operations per output element, so
+ * they give identical results.  Stream-ordered. */
+#define HDCR_MFMA_VARIANTS 7
+HDCR_API int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
+                                       int32_t nrhs, int32_t variant, hipStream_t stream);
+/* Autotuner of the batched apply: times every tile shape on the caller's
+ * buffers (out is overwritten), records the fastest for (Nc, Nb, nrhs, device)
+ * in a process-wide table used by variant 0, and reports the winner (best) and
+ * the median time of each variant in ms[HDCR_MFMA_VARIANTS] (-1 for a variant
+ * that does not apply; either pointer may be null).  Returns after the timing
+ * runs have completed. */
+HDCR_API int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
+                                      int32_t nrhs, int32_t* best, double* ms, hipStream_t stream);
+
 /* Read back the opaque buffers: A (any storage) as logical A[a][d][j][k]
  * complex double; the basis as Nb full fine fields (C128, [j][12][V4][Ls]),
  * field j holding phi^a_j on every block a. */

@@ -24,7 +24,8 @@ from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_
 
 __all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
-           "smooth", "vcycle", "make_subspace", "power_max", "load", "HDCRError"]
+           "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
+           "HDCRError"]
 
 load = _abi.load
 
@@ -333,6 +334,33 @@ def apply_coarse(lat: Lattice, A, A_dtype: int, v, out=None, stream=None):
     _abi.check(load().hdcr_apply_coarse(ctypes.byref(cd), int(A_dtype), _ptr(A), _ptr(v), _ptr(out), nrhs,
                                         _stream(stream)), "hdcr_apply_coarse")
     return out
+
+
+def apply_coarse_batched(lat: Lattice, A, v, out=None, variant: int = 0, stream=None):
+    """out[r] = A v[r] on the matrix cores: A in BF16C storage, v complex64 [nrhs, Nc, Nb]
+    rounded to bf16, FP32 accumulation.  variant 0: the autotuned tile shape."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(v)
+    nrhs = 1 if v.dim() == 2 else v.shape[0]
+    cd = lat.coarse_desc()
+    _abi.check(load().hdcr_apply_coarse_batched(ctypes.byref(cd), _ptr(A), _ptr(v), _ptr(out), nrhs, int(variant),
+                                                _stream(stream)), "hdcr_apply_coarse_batched")
+    return out
+
+
+def tune_coarse_batched(lat: Lattice, A, v, out=None, stream=None):
+    """Times every tile shape of the batched apply; returns (best variant, [median ms per variant])."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(v)
+    nrhs = 1 if v.dim() == 2 else v.shape[0]
+    cd = lat.coarse_desc()
+    best = ctypes.c_int32(0)
+    ms = (ctypes.c_double * _abi.MFMA_VARIANTS)()
+    _abi.check(load().hdcr_tune_coarse_batched(ctypes.byref(cd), _ptr(A), _ptr(v), _ptr(out), nrhs,
+                                               ctypes.byref(best), ms, _stream(stream)), "hdcr_tune_coarse_batched")
+    return int(best.value), [float(x) for x in ms]
 
 
 # ----------------------------------------------------------------------------

@@ -1,6 +1,11 @@
 // C-ABI entry points of the coarse space: basis and little Dirac operator
 // build, restriction, prolongation, coarse apply, export.
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "coarse.h"
 #include "solver.h"
@@ -64,6 +69,38 @@ size_t build_workspace_bytes(const CoarseGeom& c) {
 // bytes of one vector entry: FP32 vectors go with the C64 and F16C (FP16 basis) forms
 static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : (dt == HDCR_C64 || dt == HDCR_F16C) ? 8 : 4; }
 
+}  // namespace hdcr
+
+namespace hdcr {
+// tile shape chosen by the autotuner per (Nc, Nb, nrhs, device)
+static std::mutex tune_mutex;
+static std::map<std::tuple<int, int, int, int>, int> tune_table;
+
+static int tuned_variant(const CoarseGeom& c, int nrhs) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lk(tune_mutex);
+    auto it = tune_table.find(std::make_tuple(c.Nc, c.Nb, nrhs, dev));
+    if (it != tune_table.end()) return it->second;
+    return coarse_mfma_eligible(c, 2) ? 2 : 1;
+}
+
+static int check_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int nrhs,
+                         const char* who) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (nrhs < 1) return fail(HDCR_EINVAL, std::string(who) + ": nrhs must be >= 1");
+    const int nb = 2 * desc->nvec;
+    if (nb != 16 && nb != 32 && nb != 64 && nb != 128)
+        return fail(HDCR_EINVAL, std::string(who) + ": needs Nb = 2 nvec in {16, 32, 64, 128}");
+    if ((e = check_ptr(A, 16, "A")) || (e = check_ptr(v, 8, "v")) || (e = check_ptr(out, 8, "out"))) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    const size_t bytes = (size_t)nrhs * c.Nc * c.Nb * 8;
+    const char* pv = static_cast<const char*>(v);
+    const char* po = static_cast<const char*>(out);
+    if (pv < po + bytes && po < pv + bytes) return fail(HDCR_EINVAL, std::string(who) + ": v and out overlap");
+    return HDCR_OK;
+}
 }  // namespace hdcr
 
 using namespace hdcr;
@@ -235,4 +272,71 @@ int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void
     return HDCR_OK;
 }
 
+
+int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int32_t nrhs,
+                              int32_t variant, hipStream_t stream) {
+    int e = check_batched(desc, A, v, out, nrhs, "hdcr_apply_coarse_batched");
+    if (e) return e;
+    if (variant < 0 || variant > coarse_mfma_variants())
+        return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: variant out of range");
+    const CoarseGeom c = make_coarse_geom(desc);
+    if (variant == 0) variant = tuned_variant(c, nrhs);
+    if (!coarse_mfma_eligible(c, variant))
+        return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: variant " + std::to_string(variant) +
+                                     " needs no more waves per site than Nb / 8");
+    launch_coarse_mfma(c, variant, static_cast<const uint32_t*>(A), static_cast<const float2*>(v),
+                       static_cast<float2*>(out), nrhs, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
+int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int32_t nrhs,
+                             int32_t* best, double* ms, hipStream_t stream) {
+    int e = check_batched(desc, A, v, out, nrhs, "hdcr_tune_coarse_batched");
+    if (e) return e;
+    const CoarseGeom c = make_coarse_geom(desc);
+    const int nv = coarse_mfma_variants();
+    constexpr int REPS = 7;
+    hipEvent_t ev[REPS + 1];
+    for (int i = 0; i <= REPS; ++i) HDCR_HIP_CHECK(hipEventCreate(&ev[i]));
+    int win = 0;
+    double win_ms = 0;
+    for (int k = 1; k <= nv; ++k) {
+        if (!coarse_mfma_eligible(c, k)) {
+            if (ms) ms[k - 1] = -1.0;
+            continue;
+        }
+        const uint32_t* Au = static_cast<const uint32_t*>(A);
+        launch_coarse_mfma(c, k, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs, stream);  // warm-up
+        HDCR_HIP_CHECK(hipEventRecord(ev[0], stream));
+        for (int i = 0; i < REPS; ++i) {
+            launch_coarse_mfma(c, k, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs, stream);
+            HDCR_HIP_CHECK(hipEventRecord(ev[i + 1], stream));
+        }
+        HDCR_HIP_CHECK(hipGetLastError());
+        HDCR_HIP_CHECK(hipEventSynchronize(ev[REPS]));
+        std::vector<double> t(REPS);
+        for (int i = 0; i < REPS; ++i) {
+            float f = 0;
+            HDCR_HIP_CHECK(hipEventElapsedTime(&f, ev[i], ev[i + 1]));
+            t[i] = f;
+        }
+        std::sort(t.begin(), t.end());
+        const double med = t[REPS / 2];
+        if (ms) ms[k - 1] = med;
+        if (win == 0 || med < win_ms) {
+            win = k;
+            win_ms = med;
+        }
+    }
+    for (int i = 0; i <= REPS; ++i) (void)hipEventDestroy(ev[i]);
+    int dev = 0;
+    HDCR_HIP_CHECK(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex);
+        tune_table[std::make_tuple(c.Nc, c.Nb, (int)nrhs, dev)] = win;
+    }
+    if (best) *best = win;
+    return HDCR_OK;
+}
 }  // extern "C"

@@ -1029,3 +1029,178 @@ template void launch_coarse_apply<double>(const CoarseGeom&, const double2*, con
 template void launch_coarse_apply<float>(const CoarseGeom&, const float2*, const float2*, float2*, int, hipStream_t);
 
 }  // namespace hdcr
+
+// ---------------------------------------------------------------------------
+// batched coarse apply on the matrix cores: out[r] = A v[r] for many right-hand
+// sides with A in BF16C storage, v rounded to bf16, FP32 accumulation
+// ---------------------------------------------------------------------------
+namespace hdcr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MR = 16;  // right-hand sides per pass (the N of a 16x16x32 tile)
+
+// bf16 pair (re, im) of a complex float, rounded to nearest even
+__device__ __forceinline__ uint32_t pack_bf16c(float2 v) {
+    return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v.x) |
+           ((uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v.y) << 16);
+}
+
+// One workgroup per coarse site; NW wavefronts split the 2 Nb / 16 row tiles of
+// the real form [[Ar, -Ai], [Ai, Ar]] (rows 2j + re/im, columns 2k + re/im) of
+// each block A[a][d]; the right-hand sides are the 16 columns of a tile.  ALDS:
+// the block is first staged in LDS with 16-byte loads (else each lane reads its
+// 4 words from memory).  Every variant issues the same MFMA sequence per output.
+// PRE (with ALDS): the 9 blocks of the site are loaded into registers up front
+// (PRE 16-byte loads per work-item and block), so their latencies overlap
+template <int NW, int TPW, bool ALDS, int PRE = 0>
+__global__ void __launch_bounds__(64 * NW) coarse_mfma_kernel(CoarseGeom c, const uint32_t* __restrict__ A,
+                                                              const float2* __restrict__ v, float2* __restrict__ out,
+                                                              int nrhs) {
+    extern __shared__ unsigned char smem_raw[];
+    uint32_t* vb = reinterpret_cast<uint32_t*>(smem_raw);  // [9][MR][Nb] bf16 pairs
+    uint32_t* ab = vb + 9 * MR * c.Nb;                      // [Nb][Nb] one block (ALDS)
+    const int a = blockIdx.x;
+    const int Nb = c.Nb;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // scalar: uniform row-tile tests
+    const int kq = lane >> 4, col = lane & 15;
+    // A-operand word of row 2j + (col & 1): (re, -im) for even rows, (im, re) for
+    // odd rows; built branch-free (rotate by 0 or 16 bits, then flip a sign bit)
+    const uint32_t rot = (col & 1) ? 16u : 0u;
+    const uint32_t flip = (col & 1) ? 0u : 0x80000000u;
+    for (int r0 = 0; r0 < nrhs; r0 += MR) {
+        const int nr = min(MR, nrhs - r0);
+        __syncthreads();  // the previous pass has finished reading vb
+        for (int e = threadIdx.x; e < 9 * MR * Nb; e += 64 * NW) {
+            const int d = e / (MR * Nb), rem = e - d * MR * Nb;
+            const int r = rem / Nb, k = rem - r * Nb;
+            const float2 x = (r < nr) ? v[((size_t)(r0 + r) * c.Nc + coarse_nbr(c, a, d)) * Nb + k] : make_float2(0, 0);
+            vb[e] = pack_bf16c(x);
+        }
+        f32x4 acc[TPW];  // row tiles wave + NW t of this wavefront
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0, 0, 0, 0};
+        u32x4 pre[PRE > 0 ? 9 : 1][PRE > 0 ? PRE : 1];
+        if constexpr (PRE > 0) {
+            const uint32_t* Aa = A + (size_t)a * 9 * Nb * Nb;
+#pragma unroll
+            for (int d = 0; d < 9; ++d)
+#pragma unroll
+                for (int u = 0; u < PRE; ++u) {
+                    const int e = 4 * (threadIdx.x + u * 64 * NW);
+                    if (e < Nb * Nb) pre[d][u] = *reinterpret_cast<const u32x4*>(Aa + (size_t)d * Nb * Nb + e);
+                }
+        }
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            const uint32_t* Ad = A + ((size_t)a * 9 + d) * Nb * Nb;
+            if constexpr (ALDS) {
+                __syncthreads();  // previous block consumed
+                if constexpr (PRE > 0) {
+#pragma unroll
+                    for (int u = 0; u < PRE; ++u) {
+                        const int e = 4 * (threadIdx.x + u * 64 * NW);
+                        if (e < Nb * Nb) *reinterpret_cast<u32x4*>(ab + e) = pre[d][u];
+                    }
+                } else {
+                    for (int e = 4 * threadIdx.x; e < Nb * Nb; e += 4 * 64 * NW)
+                        *reinterpret_cast<u32x4*>(ab + e) = *reinterpret_cast<const u32x4*>(Ad + e);
+                }
+            }
+            __syncthreads();
+            const uint32_t* vd = vb + d * MR * Nb;
+            for (int ks = 0; ks < Nb / 16; ++ks) {
+                const int k0 = 16 * ks + 4 * kq;
+                const u32x4 bw = *reinterpret_cast<const u32x4*>(vd + col * Nb + k0);
+                const bf16x8 bop = __builtin_bit_cast(bf16x8, bw);
+                // ntiles = NW * TPW exactly: every wavefront owns TPW row tiles, and
+                // the accumulation chains carry no branch
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int rt = wave + NW * t;
+                    const int row = 16 * rt + col;
+                    const int j = row >> 1;
+                    u32x4 aw;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t w = ALDS ? ab[(k0 + q) * Nb + j] : Ad[(size_t)(k0 + q) * Nb + j];
+                        aw[q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+                    }
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aw), bop, acc[t], 0,
+                                                                      0, 0);
+                }
+            }
+        }
+        // lane holds rows 16 rt + 4 kq + (0..3) = complex rows 8 rt + 2 kq + (0, 1) of column col
+        if (col < nr) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int j0 = 8 * (wave + NW * t) + 2 * kq;
+                float2* o = out + ((size_t)(r0 + col) * c.Nc + a) * Nb + j0;
+                o[0] = make_float2(acc[t][0], acc[t][1]);
+                o[1] = make_float2(acc[t][2], acc[t][3]);
+            }
+        }
+    }
+}
+
+template <int NW, bool ALDS>
+void mfma_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
+    const size_t lds = (size_t)9 * MR * c.Nb * 4 + (ALDS ? (size_t)c.Nb * c.Nb * 4 : 0);
+    const int tpw = (2 * c.Nb / 16) / NW;  // exact (coarse_mfma_eligible)
+    if (tpw == 1) {
+        hipLaunchKernelGGL((coarse_mfma_kernel<NW, 1, ALDS>), dim3(c.Nc), dim3(64 * NW), lds, s, c, A, v, out, nrhs);
+    } else if (tpw == 2) {
+        hipLaunchKernelGGL((coarse_mfma_kernel<NW, 2, ALDS>), dim3(c.Nc), dim3(64 * NW), lds, s, c, A, v, out, nrhs);
+    } else if constexpr (NW <= 4) {
+        if (tpw == 4) {
+            hipLaunchKernelGGL((coarse_mfma_kernel<NW, 4, ALDS>), dim3(c.Nc), dim3(64 * NW), lds, s, c, A, v, out,
+                               nrhs);
+        } else if constexpr (NW <= 2) {
+            hipLaunchKernelGGL((coarse_mfma_kernel<NW, 8, ALDS>), dim3(c.Nc), dim3(64 * NW), lds, s, c, A, v, out,
+                               nrhs);
+        }
+    }
+}
+
+}  // namespace
+
+// tile-shape variants of the batched apply: waves per coarse site x block staging
+int coarse_mfma_variants() { return 7; }
+const char* coarse_mfma_variant_name(int k) {
+    static const char* names[7] = {"2 waves/site, A direct",  "4 waves/site, A direct",  "8 waves/site, A direct",
+                                   "2 waves/site, A via LDS", "4 waves/site, A via LDS", "8 waves/site, A via LDS",
+                                   "8 waves/site, A prefetched (Nb 64)"};
+    return (k >= 1 && k <= 7) ? names[k - 1] : "";
+}
+// waves per coarse site of a variant
+static int mfma_waves(int variant) { return variant == 1 || variant == 4 ? 2 : variant == 2 || variant == 5 ? 4 : 8; }
+bool coarse_mfma_eligible(const CoarseGeom& c, int variant) {
+    const int nb = c.Nb;
+    if (nb != 16 && nb != 32 && nb != 64 && nb != 128) return false;
+    if (variant == 7 && nb != 64) return false;  // register prefetch sized for Nb = 64 blocks
+    return mfma_waves(variant) <= 2 * nb / 16;
+}
+void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, const float2* v, float2* out, int nrhs,
+                        hipStream_t s) {
+    switch (variant) {
+        case 1: mfma_launch<2, false>(c, A, v, out, nrhs, s); break;
+        case 2: mfma_launch<4, false>(c, A, v, out, nrhs, s); break;
+        case 3: mfma_launch<8, false>(c, A, v, out, nrhs, s); break;
+        case 4: mfma_launch<2, true>(c, A, v, out, nrhs, s); break;
+        case 5: mfma_launch<4, true>(c, A, v, out, nrhs, s); break;
+        case 6: mfma_launch<8, true>(c, A, v, out, nrhs, s); break;
+        default: {
+            // 8 waves, Nb = 64: 16 KB blocks, 2 loads of 16 B per work-item and block
+            const size_t lds = (size_t)9 * MR * c.Nb * 4 + (size_t)c.Nb * c.Nb * 4;
+            hipLaunchKernelGGL((coarse_mfma_kernel<8, 1, true, 2>), dim3(c.Nc), dim3(512), lds, s, c, A, v, out, nrhs);
+            break;
+        }
+    }
+}
+
+}  // namespace hdcr

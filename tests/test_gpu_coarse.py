@@ -120,6 +120,42 @@ def test_restrict_prolong_fp16_basis(L, Ls, block, nvec):
     assert np.abs(r - r32).max() > 0
 
 
+@pytest.mark.parametrize("L,block,nvec,nrhs", [((4, 4, 4, 4), (2, 2, 2, 2), 8, 12),   # Nb 16, 16 coarse sites
+                                                ((6, 4, 2, 4), (2, 2, 2, 2), 16, 5),   # Nb 32, extents 3 x 2 x 1 x 2
+                                                ((4, 4, 4, 4), (2, 2, 2, 2), 32, 17)])  # Nb 64, two passes of rhs
+def test_batched_coarse_apply_mfma(L, block, nvec, nrhs):
+    """Batched BF16 contraction on the matrix cores against the FP64 coarse apply of the
+    same (bf16-valued) A.  The vectors are rounded to bf16 (relative error <= 2^-8 per
+    entry) and the sums accumulate in FP32, so |out - ref| <= (2^-8 + 1e-5) sum |A| |v|
+    element by element, the sums of absolute values taken from the oracle's coarse apply
+    of |A| and |v|.  Every tile shape gives the same result bit for bit, and the
+    autotuned choice (variant 0) is one of them."""
+    torch = torch_dev()
+    log(f"batched coarse apply L={L} block={block} nvec={nvec} nrhs={nrhs}")
+    lat = hd.Lattice(L, 4, block=block, nvec=nvec)
+    cs = oracle.Coarse(oracle.Params(L, 4), block, nvec)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    raw = torch.randn(hd.coarse_bytes(lat, hd.C128) // 8, dtype=torch.float64, device="cuda:0", generator=g)
+    Ab = hd.convert_coarse(lat, raw, hd.BF16C)
+    A_log = to_host(hd.export_coarse(lat, Ab, hd.BF16C))       # exact values of the bf16 entries
+    v = hi.gaussian_coarse(cs.nc, cs.nb, seed=12, nrhs=nrhs)
+    vd = to_dev(v, torch.complex64)
+    ref = oracle.coarse_apply(A_log, v.astype(np.complex64).astype(np.complex128), cs.cdims)
+    bound = (2.0 ** -8 + 1e-5) * oracle.coarse_apply(np.abs(A_log), np.abs(v), cs.cdims).real
+    # variants with at most Nb / 8 wavefronts per coarse site apply
+    waves = {1: 2, 2: 4, 3: 8, 4: 2, 5: 4, 6: 8, 7: 8}
+    ok = [k for k in range(1, hd._abi.MFMA_VARIANTS + 1) if waves[k] <= cs.nb // 8 and (k != 7 or cs.nb == 64)]
+    outs = [to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=k)) for k in ok]
+    err = np.abs(outs[0] - ref)
+    assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    best, ms = hd.tune_coarse_batched(lat, Ab, vd)
+    assert best in ok and all((ms[k - 1] > 0) == (k in ok) for k in range(1, hd._abi.MFMA_VARIANTS + 1))
+    assert np.array_equal(to_host(hd.apply_coarse_batched(lat, Ab, vd)), outs[0])
+
+
 def test_rank_deficient_vectors():
     torch_dev()
     L, Ls, block, nvec = (2, 2, 2, 2), 4, (2, 2, 2, 2), 3
