@@ -148,6 +148,59 @@ def apply_gamma5_field(psi) -> np.ndarray:
 # Coarse space (Sec. 4)
 # ----------------------------------------------------------------------------
 
+def loss(U, chi, psi, p: Params) -> float:
+    """L = Re <chi, H psi> (the scalar whose gradient the force kernel computes)."""
+    return float(np.vdot(_c(chi), apply_h(U, psi, p)).real)
+
+
+def link_grad(U, chi, psi, p: Params) -> np.ndarray:
+    """W_mu(x) = dL/dRe U_mu(x) + i dL/dIm U_mu(x) for L = Re <chi, H psi>.
+
+    The paper motivates the solver by its use inside HMC evolution (Sec. 1 and
+    Sec. 5), whose fermion force is this gradient.  Written out from the hop
+    terms of D (the Shamir form of Sec. 3 used by apply_h): with
+    chi' = Gamma5 chi, chi'(x, s) = gamma5 chi(x, Ls-1-s), only the forward hop
+    at x and the backward hop at x + mu contain U_mu(x), so
+
+      W_mu(x) = -1/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
+                                   + psi(x,s) (x) ((1 + g_mu) chi'(x+mu,s))^dag ],
+
+    (x) the spin-traced colour outer product, b_mu(x) = bc[mu] on the link that
+    crosses the boundary (x_mu = L_mu - 1), else 1.  Plain numpy, 4x4 gammas.
+    """
+    U, chi, psi = _c(U), _c(chi), _c(psi)
+    Lx, Ly, Lz, Lt = p.L
+    g5 = gamma(4)
+    eye = np.eye(4, dtype=np.complex128)
+    chip = np.einsum("ab,tzyxsbc->tzyxsac", g5, chi[:, :, :, :, ::-1, :, :])
+    axis = {0: 3, 1: 2, 2: 1, 3: 0}  # mu -> array axis of (t, z, y, x)
+    ext = {0: Lx, 1: Ly, 2: Lz, 3: Lt}
+    W = np.zeros(U.shape, dtype=np.complex128)
+    for mu in range(4):
+        gm = gamma(mu)
+        psi_f = np.roll(psi, -1, axis=axis[mu])
+        chip_f = np.roll(chip, -1, axis=axis[mu])
+        a = np.einsum("ab,tzyxsbc->tzyxsac", eye - gm, chip)
+        b = np.einsum("ab,tzyxsbc->tzyxsac", eye + gm, chip_f)
+        w = np.einsum("tzyxsac,tzyxsad->tzyxcd", a, psi_f.conj()) + \
+            np.einsum("tzyxsac,tzyxsad->tzyxcd", psi, b.conj())
+        sign = np.ones(ext[mu])
+        sign[-1] = p.bc[mu]
+        shape = [1, 1, 1, 1]
+        shape[axis[mu]] = ext[mu]
+        W[:, :, :, :, mu] = -0.5 * sign.reshape(shape)[..., None, None] * w
+    return W
+
+
+def force(U, W) -> np.ndarray:
+    """su(3) force T_mu(x) = P_TA(U_mu(x) W_mu(x)^dag), P_TA(M) = (M - M^dag)/2 - tr(M - M^dag)/6:
+    under U -> exp(eps X) U (X traceless anti-Hermitian) dL/deps = Re tr(X T)."""
+    M = _c(U) @ np.conj(np.swapaxes(_c(W), -1, -2))
+    A = 0.5 * (M - np.conj(np.swapaxes(M, -1, -2)))
+    tr = np.trace(A, axis1=-2, axis2=-1) / 3.0
+    return A - tr[..., None, None] * np.eye(3)
+
+
 @dataclass
 class Coarse:
     p: Params
