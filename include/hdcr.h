@@ -143,6 +143,24 @@ HDCR_API const char* hdcr_last_error(void);
 HDCR_API int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
                     hipStream_t stream);
 
+/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC
+ * fermion force of the setting named in the abstract, Sec. 1 and Sec. 5; H as
+ * in Sec. 3 and the conventions above):
+ *   W[site4][mu][a][b] = dL/dRe U_mu(x)[a][b] + i dL/dIm U_mu(x)[a][b]
+ *                      = -1/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
+ *                                          + psi(x,s) (x) ((1 + g_mu) chi'(x+mu,s))^dag ]_ab,
+ *   chi'(x,s) = g5 chi(x, Ls-1-s), (x) the colour outer product summed over
+ *   spin, b_mu(x) = bc[mu] on the link that crosses the lattice boundary;
+ *   T[site4][mu] = P_TA(U_mu(x) W_mu(x)^dag), P_TA(M) = (M - M^dag)/2 - tr(M - M^dag)/6,
+ *   so that under U_mu(x) -> exp(eps X) U_mu(x) (X traceless anti-Hermitian)
+ *   dL/deps = Re tr(X T_mu(x)).
+ * W and T use the gauge-field layout; either may be NULL (not both).  The
+ * gradient with respect to psi is H chi (H is Hermitian): hdcr_apply_fine.
+ * dtype C128 or C64 for every buffer.  One kernel launch on `stream`;
+ * outputs must not overlap the inputs or each other. */
+HDCR_API int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* chi,
+                       const void* psi, void* W, void* T, hipStream_t stream);
+
 /* <x, y> = sum conj(x_i) y_i over n complex entries (C128 or C64 data, FP64
  * accumulation, fixed reduction order), written to out[0] (re), out[1] (im) on
  * the host.  work: device scratch of at least HDCR_DOT_WORK_BYTES bytes.

@@ -192,6 +192,29 @@ def link_grad(U, chi, psi, p: Params) -> np.ndarray:
     return W
 
 
+def link_grad_at(U, chi, psi, p: Params, links) -> np.ndarray:
+    """link_grad evaluated only at the listed links [(t, z, y, x, mu), ...]
+    (lattices too large for the whole-field version): the same sum over s of
+    the two spin-traced outer products, taken link by link.  Returns [n, 3, 3]."""
+    g5 = gamma(4)
+    eye = np.eye(4, dtype=np.complex128)
+    out = np.empty((len(links), 3, 3), dtype=np.complex128)
+    for n, (t, z, y, x, mu) in enumerate(links):
+        c = [x, y, z, t]
+        f = list(c)
+        f[mu] = (c[mu] + 1) % p.L[mu]
+        X, Xf = (t, z, y, x), (f[3], f[2], f[1], f[0])
+        gm = gamma(mu)
+        chip = np.einsum("ab,sbc->sac", g5, _c(chi[X])[::-1])
+        chipf = np.einsum("ab,sbc->sac", g5, _c(chi[Xf])[::-1])
+        a = np.einsum("ab,sbc->sac", eye - gm, chip)
+        b = np.einsum("ab,sbc->sac", eye + gm, chipf)
+        w = np.einsum("sac,sad->cd", a, np.conj(psi[Xf])) + np.einsum("sac,sad->cd", psi[X], np.conj(b))
+        sign = p.bc[mu] if c[mu] == p.L[mu] - 1 else 1
+        out[n] = -0.5 * sign * w
+    return out
+
+
 def force(U, W) -> np.ndarray:
     """su(3) force T_mu(x) = P_TA(U_mu(x) W_mu(x)^dag), P_TA(M) = (M - M^dag)/2 - tr(M - M^dag)/6:
     under U -> exp(eps X) U (X traceless anti-Hermitian) dL/deps = Re tr(X T)."""

@@ -8,7 +8,7 @@ is no CPU fallback: without the built library every call raises.
 
 Device layouts (see ``include/hdcr.h``):
   fine field   [12, V4, Ls]  complex128 / complex64   (component c = spin*3 + colour)
-  gauge field  [4, 3, 3, V4] complex128 / complex64
+  gauge field  [V4, 4, 3, 3] complex128 / complex64   (mu, row, col)
   coarse vec   [nrhs, Nc, Nb] or [Nc, Nb]
 """
 from __future__ import annotations
@@ -22,7 +22,7 @@ from . import _abi
 from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL, CoarseDesc, FineDesc,  # noqa: F401
                    SolveParams, SolveStats)
 
-__all__ = ["Lattice", "apply_fine", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
+__all__ = ["Lattice", "apply_fine", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
            "HDCRError"]
@@ -146,6 +146,18 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _check_fields(lat: Lattice, U, *fields):
+    """The kernels read whole fields: a tensor of the wrong size or dtype would
+    be read past its end, so sizes and dtypes are checked before any launch."""
+    if U.numel() != 36 * lat.V4:
+        raise ValueError(f"gauge field has {U.numel()} entries, expected 36*V4 = {36 * lat.V4}")
+    for f in fields:
+        if f.numel() != 12 * lat.N5:
+            raise ValueError(f"fine field has {f.numel()} entries, expected 12*V4*Ls = {12 * lat.N5}")
+        if f.dtype != U.dtype:
+            raise TypeError(f"field dtype {f.dtype} differs from the gauge field's {U.dtype}")
+
+
 # ----------------------------------------------------------------------------
 # entry points
 # ----------------------------------------------------------------------------
@@ -154,12 +166,33 @@ def apply_fine(lat: Lattice, U, psi, out=None, stream=None):
     """out = H psi, H = Gamma5 D_dwf (one HIP kernel launch)."""
     torch = _torch()
     lib = load()
+    _check_fields(lat, U, psi)
     if out is None:
         out = torch.empty_like(psi)
+    _check_fields(lat, U, out)
     d = lat.fine_desc()
     _abi.check(lib.hdcr_apply_fine(ctypes.byref(d), _dtype_code(psi), _ptr(U), _ptr(psi), _ptr(out), _stream(stream)),
                "hdcr_apply_fine")
     return out
+
+
+def fermion_force(lat: Lattice, U, chi, psi, W=None, T=None, want_w=True, want_t=True, stream=None):
+    """Gauge-link gradient W = dL/dRe U + i dL/dIm U and su(3) force
+    T = P_TA(U W^dag) of L = Re <chi, H psi> (one HIP kernel launch).
+    Returns (W, T), each [V4, 4, 3, 3] like U, or None where not wanted."""
+    torch = _torch()
+    lib = load()
+    _check_fields(lat, U, chi, psi)
+    if want_w and W is None:
+        W = torch.empty_like(U)
+    if want_t and T is None:
+        T = torch.empty_like(U)
+    W = W if want_w else None
+    T = T if want_t else None
+    d = lat.fine_desc()
+    _abi.check(lib.hdcr_fermion_force(ctypes.byref(d), _dtype_code(psi), _ptr(U), _ptr(chi), _ptr(psi), _ptr(W), _ptr(T),
+                                      _stream(stream)), "hdcr_fermion_force")
+    return W, T
 
 
 def vec_dot(x, y, stream=None, work=None) -> complex:

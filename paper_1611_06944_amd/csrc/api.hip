@@ -138,6 +138,39 @@ int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U,
     return HDCR_OK;
 }
 
+int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* chi, const void* psi,
+                       void* W, void* T, hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64)
+        return fail(HDCR_EINVAL, "hdcr_fermion_force: dtype must be C128 or C64");
+    if (!W && !T) return fail(HDCR_EINVAL, "hdcr_fermion_force: W and T are both NULL");
+    const size_t cs = csize(dtype);
+    if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(chi, cs, "chi")) || (e = check_ptr(psi, cs, "psi"))) return e;
+    if ((W && (e = check_ptr(W, cs, "W"))) || (T && (e = check_ptr(T, cs, "T")))) return e;
+    const FineGeom g = make_geom(desc);
+    const size_t fbytes = (size_t)12 * g.N5 * cs, gbytes = (size_t)36 * g.V4 * cs;
+    for (void* o : {W, T}) {
+        if (!o) continue;
+        if (overlap(o, gbytes, U, gbytes) || overlap(o, gbytes, chi, fbytes) || overlap(o, gbytes, psi, fbytes))
+            return fail(HDCR_EINVAL, "hdcr_fermion_force: an output overlaps an input");
+    }
+    if (W && T && overlap(W, gbytes, T, gbytes)) return fail(HDCR_EINVAL, "hdcr_fermion_force: W and T overlap");
+    int r = 0, ms = 0;
+    if (const char* s = std::getenv("HDCR_FORCE_R")) r = std::atoi(s);
+    if (const char* s = std::getenv("HDCR_FORCE_MS")) ms = std::atoi(s);
+    const ForceShape f = choose_force_shape(g, (int)cs, r, ms);
+    if (!force_shape_ok(g, f)) return fail(HDCR_EINVAL, "hdcr_fermion_force: unsupported work split (HDCR_FORCE_R/MS)");
+    if (dtype == HDCR_C128)
+        launch_link_force<double>(g, f, (const double2*)U, (const double2*)chi, (const double2*)psi, (double2*)W,
+                                  (double2*)T, stream);
+    else
+        launch_link_force<float>(g, f, (const float2*)U, (const float2*)chi, (const float2*)psi, (float2*)W,
+                                 (float2*)T, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
 int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work, size_t work_bytes,
                  hipStream_t stream) {
     if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_vec_dot: dtype must be C128 or C64");

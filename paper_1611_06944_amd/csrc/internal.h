@@ -168,6 +168,19 @@ template <typename T>
 void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& e,
                        hipStream_t s);
 
+// Gauge-link gradient W and su(3) force T of L = Re <chi, H psi> (W or T may be
+// null).  Shape: r lanes per 4d site (power of two <= min(Ls, 16)), ms wave
+// groups splitting the four directions (1, 2 or 4).
+struct ForceShape {
+    int r;
+    int ms;
+};
+ForceShape choose_force_shape(const FineGeom& g, int dtype_bytes, int r, int ms);
+bool force_shape_ok(const FineGeom& g, const ForceShape& f);
+template <typename T>
+void launch_link_force(const FineGeom& g, const ForceShape& f, const C2<T>* U, const C2<T>* chi, const C2<T>* psi,
+                       C2<T>* W, C2<T>* T_, hipStream_t s);
+
 // Reductions: every reduction writes REDUCE_BLOCKS partial sums (as double2)
 // into `partials` and a finalize step sums them in fixed order into `result`.
 constexpr int REDUCE_BLOCKS = 1024;

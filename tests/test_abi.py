@@ -95,6 +95,27 @@ def test_argument_validation_before_launch(lib):
     assert lib.hdcr_strerror(_abi.HDCR_ENOTCONV) == b"not converged within maxiter"
 
 
+def test_force_argument_validation_before_launch(lib):
+    from paper_1611_06944_amd import Lattice, _abi
+    lat = Lattice((4, 4, 4, 4), 8)
+    d = lat.fine_desc()
+    U, chi, psi = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 28)
+    W, T = ctypes.c_void_p(1 << 32), ctypes.c_void_p(1 << 33)
+    f = lib.hdcr_fermion_force
+    assert f(None, 0, U, chi, psi, W, T, None) == _abi.HDCR_EINVAL
+    assert f(ctypes.byref(d), 2, U, chi, psi, W, T, None) == _abi.HDCR_EINVAL       # coarse-only dtype
+    assert f(ctypes.byref(d), 0, U, chi, psi, None, None, None) == _abi.HDCR_EINVAL  # nothing to write
+    assert f(ctypes.byref(d), 0, U, None, psi, W, T, None) == _abi.HDCR_EINVAL
+    assert b"chi" in lib.hdcr_last_error()
+    assert f(ctypes.byref(d), 0, U, chi, psi, ctypes.c_void_p((1 << 32) + 8), T, None) == _abi.HDCR_EINVAL
+    assert b"misaligned" in lib.hdcr_last_error()
+    # W on top of psi, and W overlapping T
+    assert f(ctypes.byref(d), 0, U, chi, psi, psi, T, None) == _abi.HDCR_EINVAL
+    assert b"overlap" in lib.hdcr_last_error()
+    assert f(ctypes.byref(d), 0, U, chi, psi, W, ctypes.c_void_p((1 << 32) + 4096), None) == _abi.HDCR_EINVAL
+    assert b"overlap" in lib.hdcr_last_error()
+
+
 def test_layout_roundtrip():
     import hdcr_inputs as hi
     from paper_1611_06944_amd import pack_fermion, pack_gauge, unpack_fermion

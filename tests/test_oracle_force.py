@@ -125,3 +125,15 @@ def test_psi_gradient_is_h_chi():
         dre = (oracle.loss(U, chi, psi + EPS * E, p) - oracle.loss(U, chi, psi - EPS * E, p)) / (2 * EPS)
         dim = (oracle.loss(U, chi, psi + 1j * EPS * E, p) - oracle.loss(U, chi, psi - 1j * EPS * E, p)) / (2 * EPS)
         assert abs(g[ix] - (dre + 1j * dim)) <= bound
+
+
+def test_link_grad_at_matches_whole_field():
+    """The link-by-link form used for sampled checks on large lattices agrees with the whole-field form."""
+    L, Ls = (3, 2, 2, 3), 3
+    p, U, chi, psi = _setup(L, Ls, (1, -1, 1, -1))
+    W = oracle.link_grad(U, chi, psi, p)
+    links = [(t, z, y, x, mu) for t in range(3) for z in range(2) for y in range(2) for x in range(3)
+             for mu in range(4)]
+    got = oracle.link_grad_at(U, chi, psi, p, links)
+    ref = np.stack([W[l] for l in links])
+    np.testing.assert_allclose(got, ref, atol=1e-13)
