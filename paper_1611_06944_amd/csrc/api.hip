@@ -156,11 +156,15 @@ int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void*
             return fail(HDCR_EINVAL, "hdcr_fermion_force: an output overlaps an input");
     }
     if (W && T && overlap(W, gbytes, T, gbytes)) return fail(HDCR_EINVAL, "hdcr_fermion_force: W and T overlap");
-    int r = 0, ms = 0;
+    // work-split overrides (benchmark sweeps and tests only)
+    int r = 0, ms = 0, p = 0, lds = -1;
     if (const char* s = std::getenv("HDCR_FORCE_R")) r = std::atoi(s);
     if (const char* s = std::getenv("HDCR_FORCE_MS")) ms = std::atoi(s);
-    const ForceShape f = choose_force_shape(g, (int)cs, r, ms);
-    if (!force_shape_ok(g, f)) return fail(HDCR_EINVAL, "hdcr_fermion_force: unsupported work split (HDCR_FORCE_R/MS)");
+    if (const char* s = std::getenv("HDCR_FORCE_P")) p = std::atoi(s);
+    if (const char* s = std::getenv("HDCR_FORCE_LDS")) lds = std::atoi(s);
+    const ForceShape f = choose_force_shape(g, (int)cs, r, ms, p, lds);
+    if (!force_shape_ok(g, (int)cs, f))
+        return fail(HDCR_EINVAL, "hdcr_fermion_force: unsupported work split (HDCR_FORCE_R/MS/P/LDS)");
     if (dtype == HDCR_C128)
         launch_link_force<double>(g, f, (const double2*)U, (const double2*)chi, (const double2*)psi, (double2*)W,
                                   (double2*)T, stream);

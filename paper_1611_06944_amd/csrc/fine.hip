@@ -194,39 +194,6 @@ __device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<
     hop_core<T, MU, FWD>(v, u, coef, acc);
 }
 
-// Workgroup -> sites.  Hardware dispatch sends workgroup w to XCD w % 8; the
-// remap gives each XCD one contiguous range of logical workgroups.
-__device__ __forceinline__ int logical_block(int w, int nwg) {
-    const int per = nwg / NUM_XCD, rem = nwg % NUM_XCD;
-    const int xcd = w % NUM_XCD, local = w / NUM_XCD;
-    return xcd * per + (xcd < rem ? xcd : rem) + local;
-}
-
-struct Site {
-    int site;  // lexicographic 4d site index
-    int x[4];
-};
-
-// logical site l -> coordinates, traversal order x, y-part, t-in-slab, z, y-split, t-slab
-__device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
-    Site tr;
-    const int yq = g.L[1] / g.ysplit;
-    tr.x[0] = l % g.L[0];
-    l /= g.L[0];
-    const int yi = l % yq;
-    l /= yq;
-    const int ti = l % g.tslab;
-    l /= g.tslab;
-    tr.x[2] = l % g.L[2];
-    l /= g.L[2];
-    const int yo = l % g.ysplit;
-    l /= g.ysplit;
-    tr.x[1] = yo * yq + yi;
-    tr.x[3] = l * g.tslab + ti;
-    tr.site = ((tr.x[3] * g.L[2] + tr.x[2]) * g.L[1] + tr.x[1]) * g.L[0] + tr.x[0];
-    return tr;
-}
-
 // Neighbouring 4d sites of a work-item's site and the hop coefficients
 // (-1/2, times bc[mu] for a hop across the lattice boundary).  The wrap-around
 // is a select between uniform steps, so no branch depends on the lane.

@@ -17,12 +17,19 @@
 // swapped.  The force is T_mu(x) = P_TA(U_mu(x) W_mu(x)^dag) (traceless
 // anti-Hermitian part): under U -> exp(eps X) U, dL/deps = Re tr(X T).
 //
-// Work split: a workgroup owns SITES = 64/R consecutive 4d sites and runs
-// 2*MS wavefronts over them.  Wave w computes term (w & 1) for the MU group
-// (w >> 1) of 4/MS directions; each of its lanes is one (site, s-lane) pair and
-// walks s = s-lane, s-lane + R, ... < Ls.  The R lanes of a site sum their
-// partial outer products with DPP moves inside a 16-lane row, the two terms
-// meet in LDS, and the whole workgroup then forms W and T per (site, mu).
+// Work split: a workgroup owns SITES = 64/R consecutive 4d sites of the fine
+// stencil's traversal order (t slabs inside z, so the z and t neighbours of a
+// site are re-read from the XCD's L2) and runs 2*MS wavefronts over them.
+// Wave w computes term (w & 1) for the direction group (w >> 1) of 4/MS
+// directions; each lane is one (site, s-lane) pair and owns load units of P
+// adjacent fifth-dimension slices (P = 2: two FP32 complex numbers per 16-byte
+// load).  Per direction the R lanes of a site sum their partial outer
+// products, with DPP adds inside a 16-lane row (FP32) or through a transpose
+// in LDS (FP64, where a DPP move of a double costs two moves plus the add);
+// the two terms meet in LDS and the whole workgroup then forms W and T per
+// (site, mu).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace hdcr {
@@ -97,141 +104,192 @@ template <int R, typename T> __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-// One direction of one term at one s: neighbour components at byte offset on,
-// local components v, accumulated into w.
-template <typename T, int MU>
-__device__ __forceinline__ void link_term(__amdgpu_buffer_rsrc_t rn, uint32_t cstride, uint32_t on,
-                                          const C2<T> (&v)[12], C2<T> (&w)[9]) {
-    C2<T> n[12];
+// Load unit: P consecutive fifth-dimension slices of the 12 components at one
+// 4d site, one buffer load per component (P = 2: two FP32 complex numbers in
+// one 16-byte load).
+template <typename T, int P>
+__device__ __forceinline__ void load_unit(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t cstride,
+                                          C2<T> (&v)[P][12]) {
+    if constexpr (P == 1) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) n[c] = Buf<T>::ld(rn, on, (uint32_t)c * cstride);
-    C2<T> a[6], b[6];
-    half_spinor<T, 1, MU>(v, a);
-    half_spinor<T, -1, MU>(n, b);
-    outer_acc<T>(a, b, w);
+        for (int c = 0; c < 12; ++c) v[0][c] = Buf<T>::ld(r, off, (uint32_t)c * cstride);
+    } else {
+        static_assert(P == 2 && sizeof(T) == 4, "paired slices are loaded for FP32 only");
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, c * cstride, 0));
+            v[0][c] = mk<float>(q.x, q.y);
+            v[1][c] = mk<float>(q.z, q.w);
+        }
+    }
 }
 
-template <typename T, int K, int MU, int NM>
-__device__ __forceinline__ void dir_step(__amdgpu_buffer_rsrc_t rn, uint32_t cstride, const int (&nb)[4], int Ls,
-                                         int sn, const C2<T> (&v)[12], C2<T> (&w)[NM][9]) {
-    link_term<T, MU>(rn, cstride, (uint32_t)(nb[MU] * Ls + sn) * (uint32_t)sizeof(C2<T>), v, w[K]);
+// Outer products of one unit in direction MU.  The unit at s0 = P*k pairs the
+// local slices with the neighbour's in reverse order: one of the two fields is
+// read at the reflected slices Ls-P-s0 .. Ls-1-s0 (chi~), so local slice p
+// meets neighbour slice P-1-p in both terms.
+template <typename T, int P, int MU>
+__device__ __forceinline__ void unit_products(const C2<T> (&v)[P][12], const C2<T> (&n)[P][12], C2<T> (&w)[9]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        C2<T> a[6], b[6];
+        half_spinor<T, 1, MU>(v[p], a);
+        half_spinor<T, -1, MU>(n[P - 1 - p], b);
+        outer_acc<T>(a, b, w);
+    }
 }
 
-// Workgroup-index remap: hardware dispatch sends workgroup b to XCD b % 8; the
-// remap gives each XCD one contiguous range of sites.
-__device__ __forceinline__ int xcd_block(int b, int nwg) {
-    const int per = nwg / NUM_XCD, rem = nwg % NUM_XCD;
-    const int xcd = b % NUM_XCD, local = b / NUM_XCD;
-    return xcd * per + (xcd < rem ? xcd : rem) + local;
-}
+template <int N> using IC = std::integral_constant<int, N>;
 
-template <typename T, int R, int MS>
+template <typename T, int R, int MS, int P, bool LDSRED>
 __global__ void __launch_bounds__(128 * MS) link_force_kernel(FineGeom g, const C2<T>* U, const C2<T>* chi,
                                                                 const C2<T>* psi, C2<T>* Wout, C2<T>* Tout) {
+    static_assert(R >= 2 && R <= 16, "2 <= R <= 16 lanes per site");
     constexpr int SITES = 64 / R;
-    constexpr int NM = 4 / MS;
     constexpr int NT = 128 * MS;
     constexpr uint32_t CB = sizeof(C2<T>);
-    __shared__ C2<T> red[SITES * 4 * 9];
+    // RSTRIDE: row stride of the per-wave transpose buffer (one complex of
+    // padding keeps the nine rows on distinct LDS banks)
+    constexpr int RSTRIDE = 65;
+    __shared__ C2<T> red[2][SITES * 4 * 9];
+    __shared__ C2<T> tbuf[LDSRED ? 2 * MS : 1][LDSRED ? 9 * RSTRIDE : 1];
 
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int term = wave & 1;  // 0: chi~ local, psi neighbour;  1: psi local, chi~ neighbour
     const int mg = wave >> 1;   // directions mg*NM .. mg*NM + NM-1
     const int lane = threadIdx.x & 63;
-    const int site0 = xcd_block(blockIdx.x, gridDim.x) * SITES;
+    // logical sites l0 .. l0 + SITES-1 in the stencil's traversal order
+    const int l0 = logical_block(blockIdx.x, gridDim.x) * SITES;
+    const int lsite = lane / R;
     // past the last site a group repeats the last site and stores nothing
-    const int site = min(site0 + lane / R, g.V4 - 1);
+    const Site st = traverse(g, min(l0 + lsite, g.V4 - 1));
+    const int site = st.site;
     const int sl = lane % R;
 
     int nb[4];
-    {
-        int r = site;
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const int xm = r % g.L[mu];
-            r /= g.L[mu];
-            nb[mu] = site + (xm == g.L[mu] - 1 ? -g.wrap[mu] : g.stride[mu]);
-        }
-    }
+    for (int mu = 0; mu < 4; ++mu) nb[mu] = site + (st.x[mu] == g.L[mu] - 1 ? -g.wrap[mu] : g.stride[mu]);
 
     const uint32_t cstride = (uint32_t)g.N5 * CB;
     const uint32_t fbytes = 12u * cstride;
     const __amdgpu_buffer_rsrc_t rl = make_rsrc(term ? psi : chi, fbytes);
     const __amdgpu_buffer_rsrc_t rn = make_rsrc(term ? chi : psi, fbytes);
+    // units of P slices per lane group of R lanes
+    const int nunits = (g.Ls / P + R - 1) / R;
+    // slice offsets of unit k: the local field and the neighbour's
+    auto s_local = [&](int s0) { return term ? s0 : g.Ls - P - s0; };
+    auto s_nbr = [&](int s0) { return term ? g.Ls - P - s0 : s0; };
 
-    C2<T> w[NM][9];
+    // sum of the R lanes' partial products of one direction, into red[term]
+    auto finish = [&](int mu, C2<T> (&w)[9]) {
+        C2<T>* dst = &red[term][(lsite * 4 + mu) * 9];
+        if constexpr (LDSRED) {
+            // transpose through LDS: each lane writes its nine entries, then
+            // lane sl of a group adds entry sl (and sl + R, ...) over the
+            // group's lanes in lane order
+            C2<T>* tb = tbuf[wave];
 #pragma unroll
-    for (int k = 0; k < NM; ++k)
+            for (int e = 0; e < 9; ++e) tb[e * RSTRIDE + lane] = w[e];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const int g0 = lane - sl;
+            for (int e = sl; e < 9; e += R) {
+                C2<T> acc = tb[e * RSTRIDE + g0];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) w[k][e] = mk<T>(0, 0);
-
-    for (int s = sl; s < g.Ls; s += R) {
-        const int sr = g.Ls - 1 - s;
-        const int sloc = term ? s : sr, sn = term ? sr : s;
-        C2<T> v[12];
-        const uint32_t ol = (uint32_t)(site * g.Ls + sloc) * CB;
+                for (int k = 1; k < R; ++k) acc = cadd<T>(acc, tb[e * RSTRIDE + g0 + k]);
+                dst[e] = acc;
+            }
+            // the next direction overwrites the buffer only after every lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = Buf<T>::ld(rl, ol, (uint32_t)c * cstride);
+            for (int e = 0; e < 9; ++e) w[e] = mk<T>(group_sum<R>(w[e].x), group_sum<R>(w[e].y));
+            if (sl == 0) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) dst[e] = w[e];
+            }
+        }
+    };
+    auto for_dirs = [&](auto&& body) {
         if constexpr (MS == 1) {
-            dir_step<T, 0, 0, NM>(rn, cstride, nb, g.Ls, sn, v, w);
-            dir_step<T, 1, 1, NM>(rn, cstride, nb, g.Ls, sn, v, w);
-            dir_step<T, 2, 2, NM>(rn, cstride, nb, g.Ls, sn, v, w);
-            dir_step<T, 3, 3, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+            body(IC<0>{});
+            body(IC<1>{});
+            body(IC<2>{});
+            body(IC<3>{});
         } else if constexpr (MS == 2) {
             if (mg == 0) {
-                dir_step<T, 0, 0, NM>(rn, cstride, nb, g.Ls, sn, v, w);
-                dir_step<T, 1, 1, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<0>{});
+                body(IC<1>{});
             } else {
-                dir_step<T, 0, 2, NM>(rn, cstride, nb, g.Ls, sn, v, w);
-                dir_step<T, 1, 3, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<2>{});
+                body(IC<3>{});
             }
         } else {
             if (mg == 0)
-                dir_step<T, 0, 0, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<0>{});
             else if (mg == 1)
-                dir_step<T, 0, 1, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<1>{});
             else if (mg == 2)
-                dir_step<T, 0, 2, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<2>{});
             else
-                dir_step<T, 0, 3, NM>(rn, cstride, nb, g.Ls, sn, v, w);
+                body(IC<3>{});
         }
-    }
+    };
 
+    if (nunits == 1) {
+        // one unit per lane: the local slices stay in registers across directions
+        const int s0 = sl * P;
+        const bool on = s0 < g.Ls;
+        C2<T> v[P][12];
+        if (on) load_unit<T, P>(rl, (uint32_t)(site * g.Ls + s_local(s0)) * CB, cstride, v);
+        for_dirs([&](auto MUc) {
+            constexpr int MU = decltype(MUc)::value;
+            C2<T> w[9];
 #pragma unroll
-    for (int k = 0; k < NM; ++k)
+            for (int e = 0; e < 9; ++e) w[e] = mk<T>(0, 0);
+            if (on) {
+                C2<T> n[P][12];
+                load_unit<T, P>(rn, (uint32_t)(nb[MU] * g.Ls + s_nbr(s0)) * CB, cstride, n);
+                unit_products<T, P, MU>(v, n, w);
+            }
+            finish(MU, w);
+        });
+    } else {
+        for_dirs([&](auto MUc) {
+            constexpr int MU = decltype(MUc)::value;
+            C2<T> w[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) w[k][e] = mk<T>(group_sum<R>(w[k][e].x), group_sum<R>(w[k][e].y));
-
-    // the two terms meet in LDS: term 0 stores, then term 1 adds
-    const int slot = (lane / R) * 4 + mg * NM;
-    if (term == 0 && sl == 0) {
-#pragma unroll
-        for (int k = 0; k < NM; ++k)
-#pragma unroll
-            for (int e = 0; e < 9; ++e) red[(slot + k) * 9 + e] = w[k][e];
+            for (int e = 0; e < 9; ++e) w[e] = mk<T>(0, 0);
+            for (int k = 0; k < nunits; ++k) {
+                const int s0 = (sl + R * k) * P;
+                if (s0 < g.Ls) {
+                    C2<T> v[P][12], n[P][12];
+                    load_unit<T, P>(rl, (uint32_t)(site * g.Ls + s_local(s0)) * CB, cstride, v);
+                    load_unit<T, P>(rn, (uint32_t)(nb[MU] * g.Ls + s_nbr(s0)) * CB, cstride, n);
+                    unit_products<T, P, MU>(v, n, w);
+                }
+            }
+            finish(MU, w);
+        });
     }
     __syncthreads();
-    if (term == 1 && sl == 0) {
-#pragma unroll
-        for (int k = 0; k < NM; ++k)
-#pragma unroll
-            for (int e = 0; e < 9; ++e) red[(slot + k) * 9 + e] = cadd<T>(red[(slot + k) * 9 + e], w[k][e]);
-    }
-    __syncthreads();
 
-    // W = -1/2 b (sum), T = P_TA(U W^dag), one (site, mu) per work-item
+    // W = -1/2 b (sum of both terms), T = P_TA(U W^dag), one (site, mu) per work-item
     for (int p = threadIdx.x; p < SITES * 4; p += NT) {
-        const int st = site0 + (p >> 2), mu = p & 3;
-        if (st >= g.V4) break;
-        const int stride = mu == 0 ? g.stride[0] : mu == 1 ? g.stride[1] : mu == 2 ? g.stride[2] : g.stride[3];
+        const int l = l0 + (p >> 2), mu = p & 3;
+        if (l >= g.V4) break;
+        const Site sp = traverse(g, l);
+        const int xm = mu == 0 ? sp.x[0] : mu == 1 ? sp.x[1] : mu == 2 ? sp.x[2] : sp.x[3];
         const int ext = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
         const int bc = mu == 0 ? g.bc[0] : mu == 1 ? g.bc[1] : mu == 2 ? g.bc[2] : g.bc[3];
-        const bool cross = (st / stride) % ext == ext - 1;
-        const T f = cross ? (T)(-0.5) * (T)bc : (T)(-0.5);
-        const size_t base = ((size_t)st * 4 + mu) * 9;
+        const T f = (xm == ext - 1) ? (T)(-0.5) * (T)bc : (T)(-0.5);
+        const size_t base = ((size_t)sp.site * 4 + mu) * 9;
         C2<T> W[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) W[e] = cscale<T>(f, red[p * 9 + e]);
+        for (int e = 0; e < 9; ++e) W[e] = cscale<T>(f, cadd<T>(red[0][p * 9 + e], red[1][p * 9 + e]));
         if (Wout) {
 #pragma unroll
             for (int e = 0; e < 9; ++e) Wout[base + e] = W[e];
@@ -276,58 +334,85 @@ __global__ void __launch_bounds__(128 * MS) link_force_kernel(FineGeom g, const 
     }
 }
 
-template <typename T, int R, int MS>
+template <typename T, int R, int MS, int P, bool LDSRED>
 void launch_r(const FineGeom& g, const C2<T>* U, const C2<T>* chi, const C2<T>* psi, C2<T>* W, C2<T>* T_,
               hipStream_t s) {
     constexpr int SITES = 64 / R;
     const int nwg = (g.V4 + SITES - 1) / SITES;
-    hipLaunchKernelGGL((link_force_kernel<T, R, MS>), dim3(nwg), dim3(128 * MS), 0, s, g, U, chi, psi, W, T_);
+    hipLaunchKernelGGL((link_force_kernel<T, R, MS, P, LDSRED>), dim3(nwg), dim3(128 * MS), 0, s, g, U, chi, psi, W,
+                       T_);
 }
 
-template <typename T, int R>
-void launch_ms(const FineGeom& g, int ms, const C2<T>* U, const C2<T>* chi, const C2<T>* psi, C2<T>* W,
+template <typename T, int R, int P>
+void launch_ms(const FineGeom& g, const ForceShape& f, const C2<T>* U, const C2<T>* chi, const C2<T>* psi, C2<T>* W,
                C2<T>* T_, hipStream_t s) {
-    if (ms == 1)
-        launch_r<T, R, 1>(g, U, chi, psi, W, T_, s);
-    else if (ms == 2)
-        launch_r<T, R, 2>(g, U, chi, psi, W, T_, s);
-    else
-        launch_r<T, R, 4>(g, U, chi, psi, W, T_, s);
+    if (f.ms == 1) {
+        if (f.lds_sum)
+            launch_r<T, R, 1, P, true>(g, U, chi, psi, W, T_, s);
+        else
+            launch_r<T, R, 1, P, false>(g, U, chi, psi, W, T_, s);
+    } else {
+        if (f.lds_sum)
+            launch_r<T, R, 2, P, true>(g, U, chi, psi, W, T_, s);
+        else
+            launch_r<T, R, 2, P, false>(g, U, chi, psi, W, T_, s);
+    }
+}
+
+template <typename T, int P>
+void launch_p(const FineGeom& g, const ForceShape& f, const C2<T>* U, const C2<T>* chi, const C2<T>* psi, C2<T>* W,
+              C2<T>* T_, hipStream_t s) {
+    switch (f.r) {
+        case 2: launch_ms<T, 2, P>(g, f, U, chi, psi, W, T_, s); break;
+        case 4: launch_ms<T, 4, P>(g, f, U, chi, psi, W, T_, s); break;
+        case 8: launch_ms<T, 8, P>(g, f, U, chi, psi, W, T_, s); break;
+        default: launch_ms<T, 16, P>(g, f, U, chi, psi, W, T_, s); break;
+    }
 }
 
 }  // namespace
 
-ForceShape choose_force_shape(const FineGeom& g, int dtype_bytes, int r, int ms) {
+ForceShape choose_force_shape(const FineGeom& g, int dtype_bytes, int r, int ms, int p, int lds_sum) {
     ForceShape f;
-    // lanes per site: a power of two <= min(Ls, 4); at Ls = 16 each lane takes
-    // four fifth-dimension slices, so the cross-lane sums are few per product
+    // slices per load: two FP32 complex numbers per 16-byte load when Ls is even
+    if (p <= 0) p = (dtype_bytes == 8 && g.Ls % 2 == 0) ? 2 : 1;
+    // lanes per site: one load unit per lane where Ls allows (a power of two
+    // between 2 and 16)
     if (r <= 0) {
-        r = 1;
-        while (r * 2 <= g.Ls && r * 2 <= 4) r *= 2;
+        const int units = g.Ls / p;
+        r = 2;
+        while (r * 2 <= units && r * 2 <= 16) r *= 2;
     }
-    // directions per wave: all four need the most registers
-    if (ms <= 0) ms = (dtype_bytes == 16) ? 4 : 2;
+    // directions per wave: two wave groups with paired FP32 loads (measured
+    // best at 16^4 x 16), one otherwise
+    if (ms <= 0) ms = (p == 2) ? 2 : 1;
+    // cross-lane sums: through LDS for FP64 (a DPP move of a double takes two
+    // moves and the add its own instruction), DPP adds for FP32
+    if (lds_sum < 0) lds_sum = (dtype_bytes == 16) ? 1 : 0;
     f.r = r;
     f.ms = ms;
+    f.p = p;
+    f.lds_sum = lds_sum != 0;
     return f;
 }
 
-bool force_shape_ok(const FineGeom& g, const ForceShape& f) {
-    const bool r_ok = (f.r == 1 || f.r == 2 || f.r == 4 || f.r == 8 || f.r == 16) && f.r <= g.Ls;
-    const bool ms_ok = (f.ms == 1 || f.ms == 2 || f.ms == 4);
-    return r_ok && ms_ok;
+bool force_shape_ok(const FineGeom& g, int dtype_bytes, const ForceShape& f) {
+    const bool r_ok = (f.r == 2 || f.r == 4 || f.r == 8 || f.r == 16);
+    const bool ms_ok = (f.ms == 1 || f.ms == 2);
+    const bool p_ok = f.p == 1 || (f.p == 2 && dtype_bytes == 8 && g.Ls % 2 == 0);
+    return r_ok && ms_ok && p_ok;
 }
 
 template <typename T>
 void launch_link_force(const FineGeom& g, const ForceShape& f, const C2<T>* U, const C2<T>* chi, const C2<T>* psi,
                        C2<T>* W, C2<T>* T_, hipStream_t s) {
-    switch (f.r) {
-        case 1: launch_ms<T, 1>(g, f.ms, U, chi, psi, W, T_, s); break;
-        case 2: launch_ms<T, 2>(g, f.ms, U, chi, psi, W, T_, s); break;
-        case 4: launch_ms<T, 4>(g, f.ms, U, chi, psi, W, T_, s); break;
-        case 8: launch_ms<T, 8>(g, f.ms, U, chi, psi, W, T_, s); break;
-        default: launch_ms<T, 16>(g, f.ms, U, chi, psi, W, T_, s); break;
+    if constexpr (std::is_same<T, float>::value) {
+        if (f.p == 2) {
+            launch_p<float, 2>(g, f, U, chi, psi, W, T_, s);
+            return;
+        }
     }
+    launch_p<T, 1>(g, f, U, chi, psi, W, T_, s);
 }
 
 template void launch_link_force<double>(const FineGeom&, const ForceShape&, const double2*, const double2*,

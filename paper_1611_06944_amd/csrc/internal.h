@@ -126,6 +126,41 @@ struct FineGeom {
 // round-robins over on gfx950
 constexpr int NUM_XCD = 8;
 
+// Device side of the stencil traversal (the fine operator and the force
+// kernel visit sites in this order).
+// Workgroup -> sites.  Hardware dispatch sends workgroup w to XCD w % 8; the
+// remap gives each XCD one contiguous range of logical workgroups.
+__device__ __forceinline__ int logical_block(int w, int nwg) {
+    const int per = nwg / NUM_XCD, rem = nwg % NUM_XCD;
+    const int xcd = w % NUM_XCD, local = w / NUM_XCD;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+struct Site {
+    int site;  // lexicographic 4d site index
+    int x[4];
+};
+
+// logical site l -> coordinates, traversal order x, y-part, t-in-slab, z, y-split, t-slab
+__device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
+    Site tr;
+    const int yq = g.L[1] / g.ysplit;
+    tr.x[0] = l % g.L[0];
+    l /= g.L[0];
+    const int yi = l % yq;
+    l /= yq;
+    const int ti = l % g.tslab;
+    l /= g.tslab;
+    tr.x[2] = l % g.L[2];
+    l /= g.L[2];
+    const int yo = l % g.ysplit;
+    l /= g.ysplit;
+    tr.x[1] = yo * yq + yi;
+    tr.x[3] = l * g.tslab + ti;
+    tr.site = ((tr.x[3] * g.L[2] + tr.x[2]) * g.L[1] + tr.x[1]) * g.L[0] + tr.x[0];
+    return tr;
+}
+
 // choose the traversal parameters for a lattice (host)
 void choose_traversal(FineGeom& g, int tslab, int ysplit);
 
@@ -169,14 +204,18 @@ void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>
                        hipStream_t s);
 
 // Gauge-link gradient W and su(3) force T of L = Re <chi, H psi> (W or T may be
-// null).  Shape: r lanes per 4d site (power of two <= min(Ls, 16)), ms wave
-// groups splitting the four directions (1, 2 or 4).
+// null).  Shape: r lanes per 4d site (2, 4, 8 or 16), ms wave groups splitting
+// the four directions (1 or 2), p fifth-dimension slices per load (2: FP32
+// with even Ls only), lds_sum: cross-lane sums through LDS instead of DPP.
 struct ForceShape {
     int r;
     int ms;
+    int p;
+    bool lds_sum;
 };
-ForceShape choose_force_shape(const FineGeom& g, int dtype_bytes, int r, int ms);
-bool force_shape_ok(const FineGeom& g, const ForceShape& f);
+// r, ms, p <= 0 and lds_sum < 0 select the defaults
+ForceShape choose_force_shape(const FineGeom& g, int dtype_bytes, int r, int ms, int p, int lds_sum);
+bool force_shape_ok(const FineGeom& g, int dtype_bytes, const ForceShape& f);
 template <typename T>
 void launch_link_force(const FineGeom& g, const ForceShape& f, const C2<T>* U, const C2<T>* chi, const C2<T>* psi,
                        C2<T>* W, C2<T>* T_, hipStream_t s);
