@@ -452,6 +452,150 @@ __global__ void __launch_bounds__(WG) dslash_par_kernel(FineGeom g, TileGeom tg,
     store_out<T, NY, true>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
 }
 
+// Paired parity-tile kernel (FP32, Ls = 16): the tile scheme above with each
+// work-item holding two adjacent fifth-dimension slices (s0 = 2k, s0 + 1), so
+// that every field access is one 16-byte load or store of two FP32 complex
+// numbers.  The vector-memory data path returns a fixed number of lanes per
+// clock whatever the access width, so 16-byte accesses move twice the bytes
+// per cycle of the 8-byte ones.  A workgroup of 128 work-items holds one
+// tile: work-item (p, k), p the parity pattern of its site, k the slice pair.
+// The fifth-dimension neighbours of a pair are the partner slice in the same
+// work-item and one slice of the neighbouring pair, read from the staged tile
+// in LDS; the output pair lands at slices Ls-2-s0, Ls-1-s0 in reverse order.
+constexpr int PAR2_WG = 128;
+
+__device__ __forceinline__ float4 ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st_pair_nt(float4 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    store_b128<CPOL_NT>(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, voff, soff);
+}
+
+template <int NY>
+__global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGeom tg, const float2* U,
+                                                               const float2* in, float2* out, Epi<float> ep) {
+    typedef float T;
+    constexpr int LS = 16, NK = LS / 2;
+    constexpr uint32_t CB = sizeof(float2);
+    __shared__ float4 spin[12 * 16 * NK];   // [c][pattern][k]: slices 2k, 2k+1
+    __shared__ float2 lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
+    const int p = threadIdx.x >> 3, k = threadIdx.x & 7;
+    const int s0 = 2 * k;
+    const int tile = logical_block(blockIdx.x, gridDim.x);
+    const Site tt = traverse(tg.t, tile);
+    Site st;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) st.x[mu] = 2 * tt.x[mu] + ((p >> mu) & 1);
+    st.site = ((st.x[3] * g.L[2] + st.x[2]) * g.L[1] + st.x[1]) * g.L[0] + st.x[0];
+    const Nbrs<T> n = neighbours<T>(g, st);
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    // LDS matrix 2 mu: the hop of direction mu inside the tile, 2 mu + 1: the
+    // one leaving it (backward matrices stored conjugate-transposed)
+    for (int e = k; e < 9; e += NK) {
+        const int r = e / 3, cc = e - 3 * (e / 3);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const bool up = (p >> mu) & 1;
+            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + e) * CB, 0u);
+            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + e) * CB, 0u);
+            lds[(p * 8 + 2 * mu + (up ? 1 : 0)) * LPAD + e] = uf;
+            lds[(p * 8 + 2 * mu + (up ? 0 : 1)) * LPAD + cc * 3 + r] = mk<T>(ub.x, -ub.y);
+        }
+    }
+    C2<T> v0[12], v1[12];
+    {
+        const uint32_t o0 = (uint32_t)(st.site * LS + s0) * CB;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const float4 q = ld_pair(f.in, o0, (uint32_t)c * f.cstride);
+            v0[c] = mk<T>(q.x, q.y);
+            v1[c] = mk<T>(q.z, q.w);
+            spin[(c * 16 + p) * NK + k] = q;
+        }
+    }
+    __syncthreads();
+    const C2<T>* lnk = lds + p * 8 * LPAD;
+
+    // diagonal and fifth-dimension terms: upper spins take slice s - 1, lower
+    // spins slice s + 1 (wall coefficient mf at s = 0 and s = Ls - 1); the
+    // slices of the neighbouring pairs come from the staged tile in LDS
+    C2<T> a0[12], a1[12];
+    {
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (k == 0) ? mf : (T)-1;
+        const T cp = (k == NK - 1) ? mf : (T)-1;
+        const int kd = (k + NK - 1) & (NK - 1), ku = (k + 1) & (NK - 1);
+        const float2* sp = reinterpret_cast<const float2*>(spin);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            if (c < 6) {
+                const C2<T> w = sp[((c * 16 + p) * NK + kd) * 2 + 1];  // slice s0 - 1
+                a0[c] = mk<T>(fma(diag, v0[c].x, cm * w.x), fma(diag, v0[c].y, cm * w.y));
+                a1[c] = mk<T>(fma(diag, v1[c].x, -v0[c].x), fma(diag, v1[c].y, -v0[c].y));
+            } else {
+                const C2<T> w = sp[((c * 16 + p) * NK + ku) * 2];  // slice s0 + 2
+                a0[c] = mk<T>(fma(diag, v0[c].x, -v1[c].x), fma(diag, v0[c].y, -v1[c].y));
+                a1[c] = mk<T>(fma(diag, v1[c].x, cp * w.x), fma(diag, v1[c].y, cp * w.y));
+            }
+        }
+    }
+#define HDCR_PAR2_HOPS(MU)                                                                                    \
+    {                                                                                                         \
+        const bool up = (p >> MU) & 1;                                                                        \
+        const T sg_in = up ? (T)-1 : (T)1;                                                                    \
+        const int q = p ^ (1 << MU);                                                                          \
+        C2<T> m[9];                                                                                           \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU) * LPAD + e];                        \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) {                                                      \
+            const float4 w = spin[(c * 16 + q) * NK + k];                                                     \
+            v0[c] = mk<T>(w.x, w.y);                                                                          \
+            v1[c] = mk<T>(w.z, w.w);                                                                          \
+        }                                                                                                     \
+        hop_core_rt<T, MU>(v0, m, sg_in, up ? n.cb[MU] : n.cf[MU], a0);                                       \
+        hop_core_rt<T, MU>(v1, m, sg_in, up ? n.cb[MU] : n.cf[MU], a1);                                       \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU + 1) * LPAD + e];                    \
+        const uint32_t noff = (uint32_t)((up ? n.f[MU] : n.b[MU]) * LS + s0) * CB;                            \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) {                                                      \
+            const float4 w = ld_pair(f.in, noff, (uint32_t)c * f.cstride);                                    \
+            v0[c] = mk<T>(w.x, w.y);                                                                          \
+            v1[c] = mk<T>(w.z, w.w);                                                                          \
+        }                                                                                                     \
+        hop_core_rt<T, MU>(v0, m, -sg_in, up ? n.cf[MU] : n.cb[MU], a0);                                      \
+        hop_core_rt<T, MU>(v1, m, -sg_in, up ? n.cf[MU] : n.cb[MU], a1);                                      \
+    }
+    HDCR_PAR2_HOPS(0)
+    HDCR_PAR2_HOPS(1)
+    HDCR_PAR2_HOPS(2)
+    HDCR_PAR2_HOPS(3)
+#undef HDCR_PAR2_HOPS
+    // slice s0 goes to Ls-1-s0, slice s0+1 to Ls-2-s0: one pair at Ls-2-s0,
+    // lower spins negated (H = gamma5 R5 D)
+    const uint32_t oo = (uint32_t)(st.site * LS + (LS - 2 - s0)) * CB;
+    __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
+#pragma unroll
+    for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        C2<T> lo = (c < 6) ? a1[c] : cneg<T>(a1[c]);
+        C2<T> hi = (c < 6) ? a0[c] : cneg<T>(a0[c]);
+        if constexpr (NY > 0) {
+            lo = cscale<T>(ep.beta, lo);
+            hi = cscale<T>(ep.beta, hi);
+#pragma unroll
+            for (int i = 0; i < NY; ++i) {
+                const float4 y = ld_pair(yr[i], oo, (uint32_t)c * f.cstride);
+                axpy<T>(ep.g[i], mk<T>(y.x, y.y), lo);
+                axpy<T>(ep.g[i], mk<T>(y.z, y.w), hi);
+            }
+        }
+        st_pair_nt(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)c * f.cstride);
+    }
+}
+
 // Generic kernel: any Ls, links and fifth-dimension neighbours loaded
 // directly; CLS selects one hop class (coarse-operator build).
 template <typename T, bool CLS, int NY>
@@ -572,10 +716,15 @@ bool par_ok(const FineGeom& g) {
 template <typename T, int NY>
 void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
-        // parity-tile kernel for FP32 at Ls = 16 (variant 3 and above: off)
-        if (g.variant == 0 && par_ok(g)) {
+        // parity-tile kernels for FP32 at Ls = 16: paired slices by default,
+        // variant 4 one slice per work-item (variants 1 to 3: off)
+        if ((g.variant == 0 || g.variant == 4) && par_ok(g)) {
             const TileGeom tg = tile_geom(g);
-            hipLaunchKernelGGL((dslash_par_kernel<NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
+            if (g.variant == 0)
+                hipLaunchKernelGGL((dslash_par2_kernel<NY>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, in, out,
+                                   ep);
+            else
+                hipLaunchKernelGGL((dslash_par_kernel<NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
             return;
         }
     }

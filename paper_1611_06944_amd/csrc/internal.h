@@ -70,19 +70,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, BUF_FLAGS);
 }
 
+// 16-byte buffer stores.  A store wider than 8 bytes reads its data registers
+// after issue, and a vector instruction that overwrites the first of them right
+// behind the store can change what is written (observed on gfx950 as a wrong
+// first dword, at random).  The compiler separates the two only for stores
+// whose scalar offset is an inline constant, so these helpers fold the scalar
+// offset into the per-lane offset and pass 0.
+template <int CPOL>
+__device__ __forceinline__ void store_b128(__attribute__((ext_vector_type(4))) unsigned v, __amdgpu_buffer_rsrc_t r,
+                                           uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff + soff, 0, CPOL);
+}
+
 template <typename T> struct Buf;
 template <> struct Buf<double> {
     static __device__ __forceinline__ double2 ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
         return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
     }
     static __device__ __forceinline__ void st(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
-                                               voff, soff, 0);
+        store_b128<0>(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, voff, soff);
     }
     // store with the non-temporal hint (cache policy bit NT)
     static __device__ __forceinline__ void st_nt(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r,
-                                               voff, soff, CPOL_NT);
+        store_b128<CPOL_NT>(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, voff, soff);
     }
 };
 template <> struct Buf<float> {

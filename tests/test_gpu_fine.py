@@ -74,6 +74,34 @@ def test_apply_fine_full_size_sampled():
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("Ls", [8, 16])
+def test_apply_fine_large_sampled_and_deterministic(Ls):
+    """16^4 at Ls = 8 (tile kernel with the fifth-dimension exchange inside groups
+    of 8 lanes) and Ls = 16 (parity-tile kernels): sampled sites against the
+    oracle, and two launches bitwise equal (the kernels have a fixed order)."""
+    torch = torch_dev()
+    L = (16, 16, 16, 16)
+    log(f"apply_fine sampled L={L} Ls={Ls}")
+    p = oracle.Params(L, Ls)
+    lat = Lattice(L, Ls)
+    U = hi.gauge_field(L, seed=1)
+    psi = hi.gaussian_fermion(L, Ls, seed=0)
+    rng = np.random.default_rng(6)
+    N5 = lat.N5
+    sel = np.unique(np.concatenate([rng.integers(0, N5, 4000), [0, Ls - 1, N5 - 1, N5 - Ls]]))
+    ref = oracle.apply_h_sites(U, psi, p, sel)
+    for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+        Ud = to_dev(pack_gauge(U), dt)
+        pd = to_dev(pack_fermion(psi), dt)
+        out = apply_fine(lat, Ud, pd)
+        out2 = apply_fine(lat, Ud, pd)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out2), dt
+        o = to_host(out)
+        got = o[:, sel // Ls, sel % Ls].T.reshape(-1, 4, 3)
+        assert max_rel_elem(got, ref) <= tol, dt
+
+
 def test_apply_fine_linearity_and_hermiticity_fp64():
     """<x, H y> = <H x, y> on the device result (1e-12), and H(a x + y) = a Hx + Hy."""
     torch = torch_dev()
@@ -95,9 +123,10 @@ def test_apply_fine_linearity_and_hermiticity_fp64():
 
 @pytest.mark.parametrize("L,Ls", [((4, 6, 2, 5), 16), ((4, 6, 2, 6), 16), ((3, 2, 4, 2), 8)])
 def test_kernel_variants_agree(L, Ls, monkeypatch):
-    """The kernels of the fine apply give the same result: parity-tile (FP32,
-    even extents, Ls = 16; variant 0), tile kernel with cached (1) and
-    non-temporal (3) stores, generic kernel (2)."""
+    """The kernels of the fine apply give the same result: parity-tile with
+    paired slices (FP32, even extents, Ls = 16; variant 0) and with one slice
+    per work-item (4), tile kernel with cached (1) and non-temporal (3) stores,
+    generic kernel (2)."""
     torch = torch_dev()
     log(f"kernel variants L={L} Ls={Ls}")
     lat = Lattice(L, Ls, mf=0.05)
@@ -106,7 +135,7 @@ def test_kernel_variants_agree(L, Ls, monkeypatch):
     for dt, tol in ((torch.complex128, 1e-14), (torch.complex64, 1e-6)):
         U, x = to_dev(Uh, dt), to_dev(xh, dt)
         outs = []
-        for v in ("0", "1", "3", "2"):
+        for v in ("0", "4", "1", "3", "2"):
             monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
             outs.append(to_host(apply_fine(lat, U, x)))
         scale = np.abs(outs[-1]).max()

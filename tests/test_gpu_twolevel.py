@@ -17,11 +17,11 @@ def _lat(L, Ls, block=(2, 2, 2, 2), nvec=4, mf=0.01):
     return p, oracle.Coarse(p, block, nvec), hd.Lattice(L, Ls, M5=1.8, mf=mf, block=block, nvec=nvec)
 
 
-@pytest.mark.parametrize("order", [1, 2, 10])
-def test_smoother_parity(order):
+@pytest.mark.parametrize("order,L,Ls", [(1, (4, 4, 4, 6), 8), (2, (4, 4, 4, 6), 8), (10, (4, 4, 4, 6), 8),
+                                         (10, (2, 4, 2, 4), 16)])   # Ls = 16: the fused epilogues of the FP32 tile kernels
+def test_smoother_parity(order, L, Ls):
     torch = torch_dev()
-    L, Ls = (4, 4, 4, 6), 8
-    log(f"smoother order={order}")
+    log(f"smoother order={order} L={L} Ls={Ls}")
     p, _, lat = _lat(L, Ls)
     U = hi.gauge_field(L)
     r = hi.gaussian_fermion(L, Ls, seed=4)
