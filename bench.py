@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--fine-only", action="store_true", help="only the fine-operator sweep (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--force-only", action="store_true", help="only the fermion-force measurement (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device-to-device copies (reference for the HBM byte counters)")
     ap.add_argument("--cpu-sample-applies", type=int, default=30)
@@ -69,19 +70,25 @@ def parse():
 
 
 # HBM traffic of the FP32 fine apply at 24^4 x 16 from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a 1 GiB copy), for the stencil source with this sha256;
-# reported as null for any other source or lattice.
-MEASURED_TRAFFIC = {"fine_hip_sha256": "0a7aba8c0f96d0cca3523683b9d7a135e993f95aa7d619815ff23b9eccae05ab",
-                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2255037874,
+# WRITE_SIZE (scaled by a 1 GiB copy), for the stencil sources (fine.hip and the
+# shared header) with this sha256; reported as null for any other source or lattice.
+MEASURED_TRAFFIC = {"stencil_sha256": "2a44c3510b36d190c984c401af7b765b3bc86ef548c5f4a7f532f6a05df67243",
+                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2206492668,
                     "summary": "profiles/dslash_fine_24x24x24x24x16_traffic.md"}
 
 
-def measured_traffic(L, Ls):
+def stencil_sha256():
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1611_06944_amd", "csrc", "fine.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1611_06944_amd", "csrc")
+    for f in ("fine.hip", "internal.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(L, Ls):
     m = MEASURED_TRAFFIC
-    if sha != m["fine_hip_sha256"] or list(L) != m["L"] or Ls != m["Ls"]:
+    if stencil_sha256() != m["stencil_sha256"] or list(L) != m["L"] or Ls != m["Ls"]:
         return None
     return m["fp32_bytes_per_launch"]
 
@@ -106,6 +113,61 @@ def cpu_baseline(U, b, L, Ls, n_applies):
                                         f"({dt * 1e3:.0f} ms each)"}
 
 
+def force_section(hd, hi, torch):
+    """Fermion force of L = Re <chi, H psi> (16^4 x 16, Gaussian chi and psi): link gradient W and
+    su(3) force T in one launch, FP64 and FP32.  'cold': a 512 MiB copy before every launch evicts
+    L2 and the last-level cache, so the inputs come from HBM; 'warm': back-to-back launches (the
+    FP32 inputs fit the 256 MB last-level cache).  Also the two launches of the autograd backward
+    (H grad_y for psi, W for U)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    Lf, Lsf = (16, 16, 16, 16), 16
+    latf = hd.Lattice(Lf, Lsf)
+    Uf = hd.pack_gauge(hi.gauge_field(Lf, seed=hi.LINK_SEED))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(31)
+    flush_a = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+    flush_b = torch.empty_like(flush_a)
+    res = {"workload": "16x16x16x16x16, Gaussian chi and psi, W and T per launch"}
+    for name, dt, cb in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        Ud = torch.from_numpy(Uf).to(dev).to(dt)
+        chi = torch.randn((12, latf.V4, Lsf), dtype=dt, device=dev, generator=gen)
+        psi = torch.randn((12, latf.V4, Lsf), dtype=dt, device=dev, generator=gen)
+        W, T = torch.empty_like(Ud), torch.empty_like(Ud)
+        Hg = torch.empty_like(chi)
+
+        def launch():
+            hd.fermion_force(latf, Ud, chi, psi, W, T)
+
+        def per_launch(fn, n, flush):
+            for _ in range(3):
+                fn()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+            for a_, b_ in evs:
+                if flush:
+                    flush_b.copy_(flush_a)
+                a_.record(stream)
+                fn()
+                b_.record(stream)
+            torch.cuda.synchronize()
+            return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+
+        cold = per_launch(launch, 20, True)
+        warm = per_launch(launch, 20, False)
+        bwd = per_launch(lambda: (hd.apply_fine(latf, Ud, chi, Hg),
+                                  hd.fermion_force(latf, Ud, chi, psi, W, None, want_t=False)), 20, True)
+        nbytes = latf.V4 * (24 * Lsf + 36 + 72) * cb
+        res[name] = {"cold_us": round(cold * 1e3, 1), "warm_us": round(warm * 1e3, 1),
+                     "cold_GBps": round(nbytes / (cold * 1e-3) / 1e9, 1),
+                     "cold_pct_hbm": round(100 * nbytes / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 1),
+                     "warm_GBps": round(nbytes / (warm * 1e-3) / 1e9, 1),
+                     "bytes_per_launch": nbytes, "backward_cold_us": round(bwd * 1e3, 1)}
+        del Ud, chi, psi, W, T, Hg
+    del flush_a, flush_b
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +187,10 @@ def main():
 
     import hdcr_inputs as hi
     import paper_1611_06944_amd as hd
+
+    if args.force_only:
+        print(json.dumps({"fermion_force": force_section(hd, hi, torch)}), flush=True)
+        return
 
     L, Ls = tuple(args.L), args.Ls
     lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01, block=tuple(args.block), nvec=args.nvec)
@@ -286,7 +352,7 @@ def main():
                        "c128_GFLOPs": round(1416 * lat.N5 / (ms64 * 1e-3) / 1e9, 1)},
         "roofline": {"bound": "hbm", "achieved": round(gbs32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs32 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(L, Ls), "traffic_unit": "B/launch",
-                     "kernel": "dslash_par_kernel<0>", "bytes_per_launch": fine_bytes(V4, Ls, 8)},
+                     "kernel": "dslash_par2_kernel<0>", "bytes_per_launch": fine_bytes(V4, Ls, 8)},
     }
     if not args.fine_only:
         h, c = results[-1]["hdcr"], results[-1]["cr"]
@@ -308,6 +374,8 @@ def main():
     if not args.fine_only:
         out["coarse_multi_rhs"] = coarse_batched()
         progress("multi-RHS coarse apply measured")
+        out["fermion_force"] = force_section(hd, hi, torch)
+        progress("fermion force measured")
     if not args.no_cpu_baseline:
         progress("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(U_aos, b_aos, L, Ls, args.cpu_sample_applies)
