@@ -370,14 +370,13 @@ struct TileGeom {
     FineGeom t;  // the lattice of tiles (extents L / 2), traversal order of the tiles
 };
 
-template <int NY>
-__global__ void __launch_bounds__(WG) dslash_par_kernel(FineGeom g, TileGeom tg, const float2* U, const float2* in,
-                                                        float2* out, Epi<float> ep) {
-    typedef float T;
+template <typename T, int NY>
+__global__ void __launch_bounds__(WG) dslash_par_kernel(FineGeom g, TileGeom tg, const C2<T>* U, const C2<T>* in,
+                                                        C2<T>* out, Epi<T> ep) {
     constexpr int LS = 16;
-    constexpr uint32_t CB = sizeof(float2);
-    __shared__ float2 spin[12 * 16 * LS];   // [c][pattern][s]
-    __shared__ float2 lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
+    constexpr uint32_t CB = sizeof(C2<T>);
+    __shared__ C2<T> spin[12 * 16 * LS];   // [c][pattern][s]
+    __shared__ C2<T> lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
     const int p = threadIdx.x >> 4, s = threadIdx.x & 15;
     const int tile = logical_block(blockIdx.x, gridDim.x);
     const Site tt = traverse(tg.t, tile);
@@ -715,18 +714,21 @@ bool par_ok(const FineGeom& g) {
 
 template <typename T, int NY>
 void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
-    if constexpr (sizeof(T) == 4) {
-        // parity-tile kernels for FP32 at Ls = 16: paired slices by default,
-        // variant 4 one slice per work-item (variants 1 to 3: off)
-        if ((g.variant == 0 || g.variant == 4) && par_ok(g)) {
-            const TileGeom tg = tile_geom(g);
-            if (g.variant == 0)
+    // parity-tile kernels at Ls = 16 with even extents: FP32 with paired slices
+    // by default (variant 4: one slice per work-item), FP64 with one slice per
+    // work-item (variants 0 and 4); variants 1 to 3 select the tile and generic
+    // kernels
+    if ((g.variant == 0 || g.variant == 4) && par_ok(g)) {
+        const TileGeom tg = tile_geom(g);
+        if constexpr (sizeof(T) == 4) {
+            if (g.variant == 0) {
                 hipLaunchKernelGGL((dslash_par2_kernel<NY>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, in, out,
                                    ep);
-            else
-                hipLaunchKernelGGL((dslash_par_kernel<NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
-            return;
+                return;
+            }
         }
+        hipLaunchKernelGGL((dslash_par_kernel<T, NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
+        return;
     }
     if (g.variant != 2) {
         if (NY == 0 && g.variant == 1) {
