@@ -63,12 +63,14 @@ def lib():
 
 @dataclass
 class Params:
-    """Fine-lattice parameters: L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc per direction."""
+    """Fine-lattice parameters: L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc per direction, and
+    b, the scale of the 4d part in the Cayley form with c = 0 (Sec. 3; b = 1 is Shamir)."""
     L: tuple
     Ls: int
     M5: float = 1.8
     mf: float = 0.01
     bc: tuple = (1, 1, 1, -1)
+    b: float = 1.0
 
     @property
     def dims(self):
@@ -107,14 +109,14 @@ def gamma(mu: int) -> np.ndarray:
 def apply_dw(U, psi, p: Params) -> np.ndarray:
     U, psi = _c(U), _c(psi)
     out = np.empty_like(psi)
-    lib().or_apply_dw(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi), _dp(out))
+    lib().or_apply_dw(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), _dp(U), _dp(psi), _dp(out))
     return out
 
 
 def apply_h(U, psi, p: Params) -> np.ndarray:
     U, psi = _c(U), _c(psi)
     out = np.empty_like(psi)
-    lib().or_apply_h(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi), _dp(out))
+    lib().or_apply_h(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), _dp(U), _dp(psi), _dp(out))
     return out
 
 
@@ -123,7 +125,7 @@ def apply_h_sites(U, psi, p: Params, sel) -> np.ndarray:
     U, psi = _c(U), _c(psi)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
     out = np.empty((len(sel), 4, 3), dtype=np.complex128)
-    lib().or_apply_h_sites(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), _dp(U), _dp(psi),
+    lib().or_apply_h_sites(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), _dp(U), _dp(psi),
                            ctypes.c_long(len(sel)), sel.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))
     return out
 
@@ -133,7 +135,7 @@ def apply_h_classes(U, psi, p: Params, block) -> np.ndarray:
     U, psi = _c(U), _c(psi)
     out = np.empty((9,) + psi.shape, dtype=np.complex128)
     blk = (ctypes.c_int * 4)(*[int(b) for b in block])
-    lib().or_apply_h_classes(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), blk,
+    lib().or_apply_h_classes(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), blk,
                              _dp(U), _dp(psi), _dp(out))
     return out
 
@@ -162,11 +164,12 @@ def link_grad(U, chi, psi, p: Params) -> np.ndarray:
     chi' = Gamma5 chi, chi'(x, s) = gamma5 chi(x, Ls-1-s), only the forward hop
     at x and the backward hop at x + mu contain U_mu(x), so
 
-      W_mu(x) = -1/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
+      W_mu(x) = -b/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
                                    + psi(x,s) (x) ((1 + g_mu) chi'(x+mu,s))^dag ],
 
-    (x) the spin-traced colour outer product, b_mu(x) = bc[mu] on the link that
-    crosses the boundary (x_mu = L_mu - 1), else 1.  Plain numpy, 4x4 gammas.
+    (x) the spin-traced colour outer product, b the Cayley scale of the 4d part
+    (p.b), b_mu(x) = bc[mu] on the link that crosses the boundary
+    (x_mu = L_mu - 1), else 1.  Plain numpy, 4x4 gammas.
     """
     U, chi, psi = _c(U), _c(chi), _c(psi)
     Lx, Ly, Lz, Lt = p.L
@@ -188,7 +191,7 @@ def link_grad(U, chi, psi, p: Params) -> np.ndarray:
         sign[-1] = p.bc[mu]
         shape = [1, 1, 1, 1]
         shape[axis[mu]] = ext[mu]
-        W[:, :, :, :, mu] = -0.5 * sign.reshape(shape)[..., None, None] * w
+        W[:, :, :, :, mu] = -0.5 * p.b * sign.reshape(shape)[..., None, None] * w
     return W
 
 
@@ -211,7 +214,7 @@ def link_grad_at(U, chi, psi, p: Params, links) -> np.ndarray:
         b = np.einsum("ab,sbc->sac", eye + gm, chipf)
         w = np.einsum("sac,sad->cd", a, np.conj(psi[Xf])) + np.einsum("sac,sad->cd", psi[X], np.conj(b))
         sign = p.bc[mu] if c[mu] == p.L[mu] - 1 else 1
-        out[n] = -0.5 * sign * w
+        out[n] = -0.5 * p.b * sign * w
     return out
 
 
@@ -279,7 +282,7 @@ def coarse_build(U, basis, cs: Coarse) -> np.ndarray:
     U, basis = _c(U), _c(basis)
     A = np.empty((cs.nc, 9, cs.nb, cs.nb), dtype=np.complex128)
     p = cs.p
-    lib().or_coarse_build(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), cs.cblock,
+    lib().or_coarse_build(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), cs.cblock,
                           ctypes.c_int(cs.nb), _dp(U), _dp(basis), _dp(A))
     return A
 
@@ -290,7 +293,7 @@ def coarse_columns(U, basis, cs: Coarse, kcols) -> np.ndarray:
     kc = (ctypes.c_int * len(kcols))(*[int(k) for k in kcols])
     out = np.empty((len(kcols), cs.nc, 9, cs.nb), dtype=np.complex128)
     p = cs.p
-    lib().or_coarse_columns(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), cs.cblock,
+    lib().or_coarse_columns(p.dims, p.cbc, ctypes.c_double(p.M5), ctypes.c_double(p.mf), ctypes.c_double(p.b), cs.cblock,
                             ctypes.c_int(cs.nb), _dp(U), _dp(basis), ctypes.c_int(len(kcols)), kc, _dp(out))
     return out
 

@@ -13,9 +13,10 @@
 // conjugate residual", Lattice 2016):
 //   * H = gamma5 R5 D_dwf = Gamma5 D_dwf, the Hermitian indefinite domain wall
 //     operator (Sec. 3). The paper does not write D_dwf out; the oracle uses
-//     the Shamir form (Cayley b = 1, c = 0):
-//       (D psi)(x,s) = (5 - M5) psi(x,s)
-//          - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu,s) ]
+//     the Cayley form with c = 0 that Sec. 3 names, scale b = mob_b (b = 1: the
+//     Shamir kernel):
+//       (D psi)(x,s) = (b (4 - M5) + 1) psi(x,s)
+//          - b/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu,s) ]
 //          - P- psi(x,s+1) - P+ psi(x,s-1)
 //       with the walls  -P- psi(x,Ls) -> +mf P- psi(x,0)  and  -P+ psi(x,-1) -> +mf P+ psi(x,Ls-1),
 //       P+- = (1 +- g5)/2, a boundary-crossing 4d hop picks up bc[mu] (+1 periodic, -1 antiperiodic),
@@ -141,13 +142,13 @@ inline void colour_mul(cd* chi, const cd* U, const cd* psi, bool dag) {
 //   1+mu = forward mu hop whose source lies across the +mu face of the block,
 //   5+mu = backward mu hop whose source lies across the -mu face.
 // With block == nullptr every term goes to class 0.
-void dwf_site(const Geom& g, const int bc[4], double M5, double mf, const int* block,
+void dwf_site(const Geom& g, const int bc[4], double M5, double mf, double mob_b, const int* block,
               const cd* U, const cd* in, long x4, int s, cd acc[9][12]) {
     const Gammas& G = gam();
     int x[4];
     g.coords(x4, x);
     const cd* psi = in + g.idx(x4, s, 0, 0);
-    for (int c = 0; c < 12; ++c) acc[0][c] += (5.0 - M5) * psi[c];
+    for (int c = 0; c < 12; ++c) acc[0][c] += (mob_b * (4.0 - M5) + 1.0) * psi[c];
 
     Mat4 one_m[4], one_p[4];
     for (int mu = 0; mu < 4; ++mu)
@@ -160,22 +161,22 @@ void dwf_site(const Geom& g, const int bc[4], double M5, double mf, const int* b
 
     cd chi[12];
     for (int mu = 0; mu < 4; ++mu) {
-        // forward hop: -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
+        // forward hop: -b/2 (1 - g_mu) U_mu(x) psi(x + mu)
         int xp[4] = {x[0], x[1], x[2], x[3]};
         xp[mu] = (x[mu] + 1) % g.L[mu];
         double sgn_p = (x[mu] == g.L[mu] - 1) ? (double)bc[mu] : 1.0;
         int cls_p = (block && (x[mu] % block[mu] == block[mu] - 1)) ? 1 + mu : 0;
         colour_mul(chi, U + (x4 * 4 + mu) * 9, in + g.idx(g.site(xp), s, 0, 0), false);
-        spin_mul_acc(acc[cls_p], one_m[mu], chi, cd(-0.5 * sgn_p));
+        spin_mul_acc(acc[cls_p], one_m[mu], chi, cd(-0.5 * mob_b * sgn_p));
 
-        // backward hop: -1/2 (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
+        // backward hop: -b/2 (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
         int xm[4] = {x[0], x[1], x[2], x[3]};
         xm[mu] = (x[mu] - 1 + g.L[mu]) % g.L[mu];
         double sgn_m = (x[mu] == 0) ? (double)bc[mu] : 1.0;
         int cls_m = (block && (x[mu] % block[mu] == 0)) ? 5 + mu : 0;
         long xm4 = g.site(xm);
         colour_mul(chi, U + (xm4 * 4 + mu) * 9, in + g.idx(xm4, s, 0, 0), true);
-        spin_mul_acc(acc[cls_m], one_p[mu], chi, cd(-0.5 * sgn_m));
+        spin_mul_acc(acc[cls_m], one_p[mu], chi, cd(-0.5 * mob_b * sgn_m));
     }
 
     // fifth dimension: -P- psi(x,s+1) - P+ psi(x,s-1), mass mf on the walls
@@ -270,7 +271,7 @@ void or_gamma(int mu, double* out) {
 }
 
 // out = D_dwf in  (dims = Lx, Ly, Lz, Lt, Ls)
-void or_apply_dw(const int* dims, const int* bc, double M5, double mf, const double* U_, const double* in_,
+void or_apply_dw(const int* dims, const int* bc, double M5, double mf, double mob_b, const double* U_, const double* in_,
                  double* out_) {
     Geom g(dims);
     const cd* U = reinterpret_cast<const cd*>(U_);
@@ -282,13 +283,13 @@ void or_apply_dw(const int* dims, const int* bc, double M5, double mf, const dou
             cd acc[9][12];
             for (int k = 0; k < 9; ++k)
                 for (int c = 0; c < 12; ++c) acc[k][c] = 0;
-            dwf_site(g, bc, M5, mf, nullptr, U, in, x4, s, acc);
+            dwf_site(g, bc, M5, mf, mob_b, nullptr, U, in, x4, s, acc);
             for (int c = 0; c < 12; ++c) out[g.idx(x4, s, 0, 0) + c] = acc[0][c];
         }
 }
 
 // out = H in = gamma5 R5 D_dwf in
-void or_apply_h(const int* dims, const int* bc, double M5, double mf, const double* U_, const double* in_,
+void or_apply_h(const int* dims, const int* bc, double M5, double mf, double mob_b, const double* U_, const double* in_,
                 double* out_) {
     Geom g(dims);
     const cd* U = reinterpret_cast<const cd*>(U_);
@@ -300,14 +301,14 @@ void or_apply_h(const int* dims, const int* bc, double M5, double mf, const doub
             cd acc[9][12];
             for (int k = 0; k < 9; ++k)
                 for (int c = 0; c < 12; ++c) acc[k][c] = 0;
-            dwf_site(g, bc, M5, mf, nullptr, U, in, x4, s, acc);
+            dwf_site(g, bc, M5, mf, mob_b, nullptr, U, in, x4, s, acc);
             g5_mul(out + g.idx(x4, g.Ls - 1 - s, 0, 0), acc[0]);
         }
 }
 
 // (H in) at nsel selected 5d output sites: sel[i] = site4 * Ls + s; out_sel[i][12].
 // Used for spot checks on lattices too large to apply H to in full.
-void or_apply_h_sites(const int* dims, const int* bc, double M5, double mf, const double* U_, const double* in_,
+void or_apply_h_sites(const int* dims, const int* bc, double M5, double mf, double mob_b, const double* U_, const double* in_,
                       long nsel, const long* sel, double* out_) {
     Geom g(dims);
     const cd* U = reinterpret_cast<const cd*>(U_);
@@ -320,14 +321,14 @@ void or_apply_h_sites(const int* dims, const int* bc, double M5, double mf, cons
         cd acc[9][12];
         for (int k = 0; k < 9; ++k)
             for (int c = 0; c < 12; ++c) acc[k][c] = 0;
-        dwf_site(g, bc, M5, mf, nullptr, U, in, x4, g.Ls - 1 - s_out, acc);
+        dwf_site(g, bc, M5, mf, mob_b, nullptr, U, in, x4, g.Ls - 1 - s_out, acc);
         g5_mul(out + i * 12, acc[0]);
     }
 }
 
 // out9[cls] = H^(cls) in: H split by hop class relative to blocks of extent `block`
 // (nine full fields, D9 order). Summing the nine gives H in.
-void or_apply_h_classes(const int* dims, const int* bc, double M5, double mf, const int* block,
+void or_apply_h_classes(const int* dims, const int* bc, double M5, double mf, double mob_b, const int* block,
                         const double* U_, const double* in_, double* out9_) {
     Geom g(dims);
     const cd* U = reinterpret_cast<const cd*>(U_);
@@ -340,7 +341,7 @@ void or_apply_h_classes(const int* dims, const int* bc, double M5, double mf, co
             cd acc[9][12];
             for (int k = 0; k < 9; ++k)
                 for (int c = 0; c < 12; ++c) acc[k][c] = 0;
-            dwf_site(g, bc, M5, mf, block, U, in, x4, s, acc);
+            dwf_site(g, bc, M5, mf, mob_b, block, U, in, x4, s, acc);
             for (int k = 0; k < 9; ++k) g5_mul(out9 + k * n + g.idx(x4, g.Ls - 1 - s, 0, 0), acc[k]);
         }
 }
@@ -472,7 +473,7 @@ void or_prolong(const int* dims, const int* block, int nb, const double* basis_,
 // (d = 0: everything inside a). The basis field k carries phi^b_k on every block b,
 // so applying the class-split H to it once gives, on block a, class d exactly
 // H^(d) phi^{a+d}_k.  Output A_cols[c][a][d][j] (complex), c < ncols.
-void or_coarse_columns(const int* dims, const int* bc, double M5, double mf, const int* block, int nb,
+void or_coarse_columns(const int* dims, const int* bc, double M5, double mf, double mob_b, const int* block, int nb,
                        const double* U_, const double* basis_, int ncols, const int* kcols, double* out_) {
     Geom g(dims);
     CGeom cg(g, block);
@@ -482,7 +483,7 @@ void or_coarse_columns(const int* dims, const int* bc, double M5, double mf, con
     std::vector<cd> cls((size_t)9 * n);
     for (int c = 0; c < ncols; ++c) {
         int k = kcols[c];
-        or_apply_h_classes(dims, bc, M5, mf, block, U_, basis_ + 2L * k * n,
+        or_apply_h_classes(dims, bc, M5, mf, mob_b, block, U_, basis_ + 2L * k * n,
                            reinterpret_cast<double*>(cls.data()));
 #pragma omp parallel for schedule(static)
         for (long a = 0; a < cg.Nc; ++a) {
@@ -504,14 +505,14 @@ void or_coarse_columns(const int* dims, const int* bc, double M5, double mf, con
 }
 
 // Full little Dirac operator A[a][d][j][k].
-void or_coarse_build(const int* dims, const int* bc, double M5, double mf, const int* block, int nb,
+void or_coarse_build(const int* dims, const int* bc, double M5, double mf, double mob_b, const int* block, int nb,
                      const double* U_, const double* basis_, double* A_) {
     Geom g(dims);
     CGeom cg(g, block);
     cd* A = reinterpret_cast<cd*>(A_);
     std::vector<cd> col((size_t)cg.Nc * 9 * nb);
     for (int k = 0; k < nb; ++k) {
-        or_coarse_columns(dims, bc, M5, mf, block, nb, U_, basis_, 1, &k, reinterpret_cast<double*>(col.data()));
+        or_coarse_columns(dims, bc, M5, mf, mob_b, block, nb, U_, basis_, 1, &k, reinterpret_cast<double*>(col.data()));
         for (long a = 0; a < cg.Nc; ++a)
             for (int d = 0; d < 9; ++d)
                 for (int j = 0; j < nb; ++j)

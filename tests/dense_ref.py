@@ -87,13 +87,14 @@ def dense_gamma5R5(L, Ls):
     return np.kron(np.eye(V), np.kron(R5, np.kron(g5, np.eye(3))))
 
 
-def free_h_momentum(p, Ls, M5, mf):
-    """Free-field H(p) = gamma5 R5 [D_W(p) x 1_s + D_5] on (s, spin), 4Ls x 4Ls.
+def free_h_momentum(p, Ls, M5, mf, b=1.0):
+    """Free-field H(p) = gamma5 R5 [b D_W(p) x 1_s + D_5] on (s, spin), 4Ls x 4Ls
+    (Cayley form with c = 0; b = 1 is the Shamir kernel).
 
     D_W(p) = (4 - M5 - sum cos p) + i sum gamma_mu sin p_mu.
     """
     g, g5 = chiral_gammas()
-    dw = (4.0 - M5 - sum(np.cos(p))) * np.eye(4) + 1j * sum(g[mu] * np.sin(p[mu]) for mu in range(4))
+    dw = b * ((4.0 - M5 - sum(np.cos(p))) * np.eye(4) + 1j * sum(g[mu] * np.sin(p[mu]) for mu in range(4)))
     Pp = 0.5 * (np.eye(4) + g5)
     Pm = 0.5 * (np.eye(4) - g5)
     D = np.kron(np.eye(Ls), dw) + np.kron(np.eye(Ls), np.eye(4))
@@ -119,11 +120,11 @@ def momenta(L, bc):
     return [np.array(p) for p in itertools.product(*axes)]
 
 
-def free_spectrum(L, Ls, M5, mf, bc):
+def free_spectrum(L, Ls, M5, mf, bc, b=1.0):
     """Union over momenta of eig(H(p)), each with colour multiplicity 3."""
     ev = []
     for p in momenta(L, bc):
-        e = np.linalg.eigvalsh(free_h_momentum(p, Ls, M5, mf))
+        e = np.linalg.eigvalsh(free_h_momentum(p, Ls, M5, mf, b))
         ev.extend(list(e) * 3)
     return np.sort(np.array(ev))
 

@@ -41,37 +41,39 @@ def test_dwf_matches_dense_shift_construction(L, Ls):
         np.testing.assert_allclose(Ho, Ho.conj().T, atol=1e-13)
 
 
-def test_free_field_spectrum_closed_form():
+@pytest.mark.parametrize("b", [1.0, 1.7])   # b != 1: the Cayley form with c = 0 (Sec. 3)
+def test_free_field_spectrum_closed_form(b):
     L, Ls = (2, 2, 2, 4), 4
-    p = oracle.Params(L, Ls, M5=1.8, mf=0.05)
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.05, b=b)
     U = hi.gauge_field(L, eps=0.0)
     Ho = dense_ref.dense_from_apply(lambda v: oracle.apply_h(U, v, p), p.fshape)
     ev = np.linalg.eigvalsh(Ho)
-    ref = dense_ref.free_spectrum(L, Ls, p.M5, p.mf, p.bc)
+    ref = dense_ref.free_spectrum(L, Ls, p.M5, p.mf, p.bc, b)
     np.testing.assert_allclose(ev, ref, atol=1e-12)
 
 
-def test_free_field_ls1_wilson_closed_form():
-    """Ls = 1: H = gamma5 D_W(m) with m = 1 - M5 + mf; eigenvalues +-sqrt(a^2 + sum sin^2 p),
-    a = m + sum (1 - cos p), each sign twice (spin) times three colours."""
+@pytest.mark.parametrize("b", [1.0, 1.7])
+def test_free_field_ls1_wilson_closed_form(b):
+    """Ls = 1: H = gamma5 (b D_W(-M5) + 1 + mf); eigenvalues +-sqrt(a^2 + b^2 sum sin^2 p),
+    a = b (sum (1 - cos p) - M5) + 1 + mf, each sign twice (spin) times three colours."""
     L, Ls = (2, 2, 2, 4), 1
-    p = oracle.Params(L, Ls, M5=1.8, mf=0.05)
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.05, b=b)
     U = hi.gauge_field(L, eps=0.0)
     Ho = dense_ref.dense_from_apply(lambda v: oracle.apply_h(U, v, p), p.fshape)
     ev = np.linalg.eigvalsh(Ho)
-    m = 1.0 - p.M5 + p.mf
     ref = []
     for mom in dense_ref.momenta(L, p.bc):
-        a = m + np.sum(1 - np.cos(mom))
-        w = np.sqrt(a * a + np.sum(np.sin(mom) ** 2))
+        a = b * (np.sum(1 - np.cos(mom)) - p.M5) + 1.0 + p.mf
+        w = np.sqrt(a * a + b * b * np.sum(np.sin(mom) ** 2))
         ref += [w] * 6 + [-w] * 6
     np.testing.assert_allclose(ev, np.sort(ref), atol=1e-12)
 
 
-def test_free_field_plane_wave_action():
+@pytest.mark.parametrize("b", [1.0, 1.5])
+def test_free_field_plane_wave_action(b):
     """On a plane wave e^{ipx} chi, H acts as the 4Ls x 4Ls matrix H(p) (momentum space)."""
     L, Ls = (4, 4, 4, 6), 6
-    p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.01, b=b)
     U = hi.gauge_field(L, eps=0.0)
     rng = np.random.default_rng(7)
     for mom in [np.array([0.0, 0.0, 0.0, np.pi / 6]),
@@ -79,14 +81,15 @@ def test_free_field_plane_wave_action():
                 np.array([np.pi / 2, 0.0, np.pi, 2 * np.pi * 4.5 / 6])]:
         chi = rng.standard_normal(4 * Ls) + 1j * rng.standard_normal(4 * Ls)
         f = dense_ref.plane_wave(L, Ls, mom, chi, colour=1)
-        hp = dense_ref.free_h_momentum(mom, Ls, p.M5, p.mf)
+        hp = dense_ref.free_h_momentum(mom, Ls, p.M5, p.mf, b)
         ref = dense_ref.plane_wave(L, Ls, mom, hp @ chi, colour=1)
         np.testing.assert_allclose(oracle.apply_h(U, f, p), ref, atol=1e-12)
 
 
-def test_hermiticity_and_gamma5():
+@pytest.mark.parametrize("b", [1.0, 1.5])
+def test_hermiticity_and_gamma5(b):
     L, Ls = (4, 4, 4, 4), 8
-    p = oracle.Params(L, Ls)
+    p = oracle.Params(L, Ls, b=b)
     U = hi.gauge_field(L)
     x = hi.gaussian_fermion(L, Ls, seed=21)
     y = hi.gaussian_fermion(L, Ls, seed=22)

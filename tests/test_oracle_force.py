@@ -20,8 +20,8 @@ U53 = 2.0 ** -53
 EPS = 1e-6
 
 
-def _setup(L, Ls, bc=(1, 1, 1, -1), mf=0.1, seed=1):
-    p = oracle.Params(L, Ls, M5=1.8, mf=mf, bc=bc)
+def _setup(L, Ls, bc=(1, 1, 1, -1), mf=0.1, seed=1, b=1.0):
+    p = oracle.Params(L, Ls, M5=1.8, mf=mf, bc=bc, b=b)
     U = hi.gauge_field(L, seed=seed)
     chi = hi.gaussian_fermion(L, Ls, seed=3)
     psi = hi.gaussian_fermion(L, Ls, seed=4)
@@ -33,11 +33,12 @@ def _fd_bound(U, chi, psi, p):
     return 64 * U53 * S / EPS
 
 
-@pytest.mark.parametrize("L,Ls,bc", [((2, 2, 2, 4), 4, (1, 1, 1, -1)),   # extent 2: both hops of a link coincide
-                                     ((3, 2, 2, 3), 3, (1, -1, 1, -1)),  # odd extents and Ls, antiperiodic in y
-                                     ((2, 3, 1, 2), 2, (-1, 1, 1, -1))])  # extent 1: a site is its own neighbour
-def test_link_grad_matches_finite_differences(L, Ls, bc):
-    p, U, chi, psi = _setup(L, Ls, bc)
+@pytest.mark.parametrize("L,Ls,bc,b", [((2, 2, 2, 4), 4, (1, 1, 1, -1), 1.0),   # extent 2: both hops of a link coincide
+                                       ((3, 2, 2, 3), 3, (1, -1, 1, -1), 1.0),  # odd extents and Ls, antiperiodic in y
+                                       ((2, 3, 1, 2), 2, (-1, 1, 1, -1), 1.0),  # extent 1: a site is its own neighbour
+                                       ((2, 2, 3, 2), 3, (1, 1, 1, -1), 1.6)])  # Cayley scale b != 1 (Sec. 3)
+def test_link_grad_matches_finite_differences(L, Ls, bc, b):
+    p, U, chi, psi = _setup(L, Ls, bc, b=b)
     W = oracle.link_grad(U, chi, psi, p)
     bound = _fd_bound(U, chi, psi, p)
     rng = np.random.default_rng(7)
