@@ -10,9 +10,10 @@
  * Nb x Nb blocks (Sec. 4).  To solve D_dwf psi = eta, pass b = Gamma5 eta.
  *
  * Conventions (fixed; the paper leaves them open):
- *   D_dwf (Shamir form, Cayley b = 1, c = 0):
- *     (D psi)(x,s) = (5 - M5) psi(x,s)
- *        - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu,s)]
+ *   D_dwf (Cayley form with c = 0, scale b of the 4d part; Sec. 3 names this
+ *   Mobius case under the same H; b = 1 is the Shamir kernel):
+ *     (D psi)(x,s) = (b (4 - M5) + 1) psi(x,s)
+ *        - b/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu,s)]
  *        - P- psi(x,s+1) - P+ psi(x,s-1),
  *     walls: -P- psi(x,Ls) -> +mf P- psi(x,0), -P+ psi(x,-1) -> +mf P+ psi(x,Ls-1);
  *     a 4d hop that crosses the lattice boundary in direction mu picks up bc[mu].
@@ -73,7 +74,9 @@ typedef enum {
 } hdcr_dtype;
 
 /* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1
- * antiperiodic), domain wall height M5 and quark mass mf. */
+ * antiperiodic), domain wall height M5, quark mass mf, and cayley_b, the scale b
+ * of the 4d part (0 is read as 1, the Shamir kernel, so a zero-initialised
+ * descriptor describes the Shamir operator). */
 typedef struct hdcr_fine_desc {
     int32_t L[4];
     int32_t Ls;
@@ -81,6 +84,7 @@ typedef struct hdcr_fine_desc {
     int32_t reserved;
     double M5;
     double mf;
+    double cayley_b;
 } hdcr_fine_desc;
 
 /* Coarse space: blocks of block[mu] sites in 4d covering the whole fifth
@@ -147,7 +151,7 @@ HDCR_API int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const
  * fermion force of the setting named in the abstract, Sec. 1 and Sec. 5; H as
  * in Sec. 3 and the conventions above):
  *   W[site4][mu][a][b] = dL/dRe U_mu(x)[a][b] + i dL/dIm U_mu(x)[a][b]
- *                      = -1/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
+ *                      = -b/2 b_mu(x) sum_s [ ((1 - g_mu) chi'(x,s)) (x) psi(x+mu,s)^dag
  *                                          + psi(x,s) (x) ((1 + g_mu) chi'(x+mu,s))^dag ]_ab,
  *   chi'(x,s) = g5 chi(x, Ls-1-s), (x) the colour outer product summed over
  *   spin, b_mu(x) = bc[mu] on the link that crosses the lattice boundary;

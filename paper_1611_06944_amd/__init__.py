@@ -32,7 +32,8 @@ load = _abi.load
 
 @dataclass(frozen=True)
 class Lattice:
-    """Fine lattice L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc; optional coarse blocking."""
+    """Fine lattice L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc, Cayley scale b of the 4d part
+    (b = 1: Shamir); optional coarse blocking."""
     L: tuple
     Ls: int
     M5: float = 1.8
@@ -40,6 +41,7 @@ class Lattice:
     bc: tuple = (1, 1, 1, -1)
     block: tuple = (1, 1, 1, 1)
     nvec: int = 0
+    b: float = 1.0
 
     @property
     def V4(self):
@@ -72,6 +74,7 @@ class Lattice:
         d.bc[:] = [int(v) for v in self.bc]
         d.M5 = float(self.M5)
         d.mf = float(self.mf)
+        d.cayley_b = float(self.b)
         return d
 
     def coarse_desc(self) -> CoarseDesc:

@@ -25,7 +25,8 @@ DOT_WORK_BYTES = 32768
 
 class FineDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
-                ("reserved", ctypes.c_int32), ("M5", ctypes.c_double), ("mf", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("M5", ctypes.c_double), ("mf", ctypes.c_double),
+                ("cayley_b", ctypes.c_double)]
 
 
 class CoarseDesc(ctypes.Structure):

@@ -35,7 +35,9 @@ FineGeom make_geom(const hdcr_fine_desc* d) {
         g.wrap[i] = (d->L[i] - 1) * st;
         st *= d->L[i];
     }
-    g.diag = 5.0 - d->M5;
+    const double b = (d->cayley_b == 0.0) ? 1.0 : d->cayley_b;
+    g.diag = b * (4.0 - d->M5) + 1.0;
+    g.hop = -0.5 * b;
     g.mf = d->mf;
     choose_traversal(g, 0, 0);
     return g;
@@ -80,6 +82,8 @@ int check_fine_desc(const hdcr_fine_desc* d) {
     if (v * d->Ls * 12 * 16 >= (int64_t(1) << 32) || v * 36 * 16 >= (int64_t(1) << 32))
         return fail(HDCR_EINVAL, "lattice too large (an FP64 fine field and gauge field must stay below 4 GiB)");
     if (!std::isfinite(d->M5) || !std::isfinite(d->mf)) return fail(HDCR_EINVAL, "M5 and mf must be finite");
+    if (!std::isfinite(d->cayley_b) || d->cayley_b < 0.0)
+        return fail(HDCR_EINVAL, "cayley_b must be finite and >= 0 (0 selects b = 1)");
     return HDCR_OK;
 }
 

@@ -195,7 +195,7 @@ __device__ __forceinline__ void hop(const FieldRefs& f, uint32_t noff, const C2<
 }
 
 // Neighbouring 4d sites of a work-item's site and the hop coefficients
-// (-1/2, times bc[mu] for a hop across the lattice boundary).  The wrap-around
+// (-b/2, times bc[mu] for a hop across the lattice boundary).  The wrap-around
 // is a select between uniform steps, so no branch depends on the lane.
 template <typename T> struct Nbrs {
     int f[4], b[4];
@@ -208,7 +208,7 @@ template <typename T> __device__ __forceinline__ Nbrs<T> neighbours(const FineGe
         const bool wf = (st.x[mu] == g.L[mu] - 1), wb = (st.x[mu] == 0);
         n.f[mu] = st.site + (wf ? -g.wrap[mu] : g.stride[mu]);
         n.b[mu] = st.site + (wb ? g.wrap[mu] : -g.stride[mu]);
-        const T half = (T)(-0.5);
+        const T half = (T)g.hop;
         n.cf[mu] = wf ? half * (T)g.bc[mu] : half;
         n.cb[mu] = wb ? half * (T)g.bc[mu] : half;
     }

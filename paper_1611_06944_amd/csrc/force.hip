@@ -6,8 +6,9 @@
 // hop at x + mu.  With chi~(x,s) = chi(x, Ls-1-s) (the R5 reflection of
 // Gamma5 = gamma5 R5, whose gamma5 is absorbed below) the gradient
 //   W_mu(x) = dL/dRe U_mu(x) + i dL/dIm U_mu(x)
-// is -1/2 b_mu(x) times the sum over s of two colour outer products traced
-// over spin, b_mu(x) = bc[mu] on the link that crosses the lattice boundary.
+// is -b/2 b_mu(x) times the sum over s of two colour outer products traced
+// over spin (b the Cayley scale of the 4d part), b_mu(x) = bc[mu] on the link
+// that crosses the lattice boundary.
 // In the chiral basis, with v = (v_u, v_d) (upper and lower spin pairs),
 // g_mu = [[0, w_mu], [w_mu^dag, 0]] and the half spinors P+-_mu v = v_u +- w_mu v_d,
 // both products take one form, local (x) neighbour^*:
@@ -277,7 +278,7 @@ __global__ void __launch_bounds__(128 * MS) link_force_kernel(FineGeom g, const 
     }
     __syncthreads();
 
-    // W = -1/2 b (sum of both terms), T = P_TA(U W^dag), one (site, mu) per work-item
+    // W = -b/2 b_mu (sum of both terms), T = P_TA(U W^dag), one (site, mu) per work-item
     for (int p = threadIdx.x; p < SITES * 4; p += NT) {
         const int l = l0 + (p >> 2), mu = p & 3;
         if (l >= g.V4) break;
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(128 * MS) link_force_kernel(FineGeom g, const 
         const int xm = mu == 0 ? sp.x[0] : mu == 1 ? sp.x[1] : mu == 2 ? sp.x[2] : sp.x[3];
         const int ext = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
         const int bc = mu == 0 ? g.bc[0] : mu == 1 ? g.bc[1] : mu == 2 ? g.bc[2] : g.bc[3];
-        const T f = (xm == ext - 1) ? (T)(-0.5) * (T)bc : (T)(-0.5);
+        const T f = (xm == ext - 1) ? (T)g.hop * (T)bc : (T)g.hop;
         const size_t base = ((size_t)sp.site * 4 + mu) * 9;
         C2<T> W[9];
 #pragma unroll

@@ -120,7 +120,8 @@ struct FineGeom {
     int bc[4];
     int stride[4];  // 4d site-index stride of direction mu
     int wrap[4];    // (L[mu] - 1) * stride[mu]
-    double diag;    // 5 - M5
+    double diag;    // b (4 - M5) + 1 (5 - M5 for the Shamir kernel b = 1)
+    double hop;     // -b/2, the coefficient of a 4d hop
     double mf;
     // traversal order of the stencil kernels (see Traversal in fine.hip):
     // t is cut into slabs of tslab slices and y into ysplit parts; inside a

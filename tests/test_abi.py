@@ -53,6 +53,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(hdcr_fine_desc, M5), offsetof(hdcr_coarse_desc, nvec),
          offsetof(hdcr_solve_params, coarse_maxiter), offsetof(hdcr_solve_params, basis_dtype));
   printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
+  printf("%zu\n", offsetof(hdcr_fine_desc, cayley_b));
   return 0;
 }
 ''')
@@ -64,7 +65,7 @@ int main(void) {
           ctypes.sizeof(_abi.SolveStats), _abi.FineDesc.M5.offset, _abi.CoarseDesc.nvec.offset,
           _abi.SolveParams.coarse_maxiter.offset, _abi.SolveParams.basis_dtype.offset,
           _abi.SolveStats.true_rel_residual.offset,
-          _abi.SolveStats.history_len.offset]
+          _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset]
     assert vals == py
 
 
@@ -92,6 +93,12 @@ def test_argument_validation_before_launch(lib):
     d.bc[3] = -1
     d.L[0] = 0
     assert lib.hdcr_apply_fine(ctypes.byref(d), 0, fake, fake, ctypes.c_void_p(1 << 30), None) == _abi.HDCR_EINVAL
+    # Cayley scale: negative is refused, 0 means the Shamir kernel (b = 1)
+    d.L[0] = 4
+    d.cayley_b = -0.5
+    assert lib.hdcr_apply_fine(ctypes.byref(d), 0, fake, fake, ctypes.c_void_p(1 << 30), None) == _abi.HDCR_EINVAL
+    assert b"cayley_b" in lib.hdcr_last_error()
+    d.cayley_b = 0.0
     assert lib.hdcr_strerror(_abi.HDCR_ENOTCONV) == b"not converged within maxiter"
 
 

@@ -48,6 +48,28 @@ def test_apply_fine_parity(L, Ls, prec):
     assert rel_err(got, ref) <= tol
 
 
+@pytest.mark.parametrize("L,Ls", [((4, 2, 6, 2), 16),   # parity-tile kernels (FP32 paired, FP64)
+                                  ((3, 5, 2, 7), 16),   # tile kernel, odd extents
+                                  ((3, 2, 4, 2), 8),    # tile kernel, Ls = 8
+                                  ((2, 3, 2, 2), 5)])   # generic kernel
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_apply_fine_cayley_b(L, Ls, prec):
+    """The Cayley form with c = 0 and b = 1.5 (Sec. 3: Mobius fermions with c = 0, b != 1)."""
+    torch = torch_dev()
+    log(f"apply_fine cayley b=1.5 L={L} Ls={Ls} prec={prec}")
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.05, bc=(1, -1, 1, -1), b=1.5)
+    lat = Lattice(L, Ls, M5=p.M5, mf=p.mf, bc=p.bc, b=1.5)
+    U = hi.gauge_field(L, seed=2)
+    psi = hi.gaussian_fermion(L, Ls, seed=6)
+    ref = oracle.apply_h(U, psi, p)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    out = apply_fine(lat, to_dev(pack_gauge(U), dt), to_dev(pack_fermion(psi), dt))
+    torch.cuda.synchronize()
+    got = unpack_fermion(to_host(out), L, Ls)
+    tol = 1e-10 if prec == "c128" else 1e-5
+    assert max_rel_elem(got, ref) <= tol
+
+
 def test_apply_fine_full_size_sampled():
     """24^4 x 16 (the benchmark's lattice), FP64 and FP32, checked on sampled sites."""
     torch = torch_dev()

@@ -25,9 +25,9 @@ SHAPES = [
 ]
 
 
-def _inputs(L, Ls, bc, seed=1):
-    p = oracle.Params(L, Ls, M5=1.8, mf=0.07, bc=bc)
-    lat = Lattice(L, Ls, M5=p.M5, mf=p.mf, bc=p.bc)
+def _inputs(L, Ls, bc, seed=1, b=1.0):
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.07, bc=bc, b=b)
+    lat = Lattice(L, Ls, M5=p.M5, mf=p.mf, bc=p.bc, b=b)
     U = hi.gauge_field(L, seed=seed)
     chi = hi.gaussian_fermion(L, Ls, seed=3)
     psi = hi.gaussian_fermion(L, Ls, seed=4)
@@ -61,6 +61,21 @@ def test_force_parity(L, Ls, bc, prec):
     assert T1 is None and np.array_equal(W1, W)
     W2, T2 = _force(lat, U, chi, psi, dt, want_w=False)
     assert W2 is None and np.array_equal(T2, T)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_force_parity_cayley_b(prec):
+    """W and T for the Cayley form with c = 0 and b = 1.5 (Sec. 3)."""
+    torch = torch_dev()
+    L, Ls = (2, 4, 2, 4), 16
+    log(f"fermion_force cayley b=1.5 L={L} Ls={Ls} prec={prec}")
+    p, lat, U, chi, psi = _inputs(L, Ls, (1, -1, 1, -1), b=1.5)
+    Wref = oracle.link_grad(U, chi, psi, p)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    W, T = _force(lat, U, chi, psi, dt)
+    tol = 1e-10 if prec == "c128" else 1e-5
+    assert max_rel_elem(W, Wref) <= tol
+    assert max_rel_elem(T, oracle.force(U, Wref)) <= tol
 
 
 WORK_SPLITS = [(r, ms, pp, lds) for r in (2, 4, 8, 16) for ms in (1, 2) for pp in (1, 2) for lds in (0, 1)]

@@ -12,9 +12,9 @@ from tests.gpu_util import log, max_rel_elem, rel_err, to_dev, to_host, torch_de
 pytestmark = pytest.mark.gpu
 
 
-def _lat(L, Ls, block=(2, 2, 2, 2), nvec=4, mf=0.01):
-    p = oracle.Params(L, Ls, M5=1.8, mf=mf)
-    return p, oracle.Coarse(p, block, nvec), hd.Lattice(L, Ls, M5=1.8, mf=mf, block=block, nvec=nvec)
+def _lat(L, Ls, block=(2, 2, 2, 2), nvec=4, mf=0.01, b=1.0):
+    p = oracle.Params(L, Ls, M5=1.8, mf=mf, b=b)
+    return p, oracle.Coarse(p, block, nvec), hd.Lattice(L, Ls, M5=1.8, mf=mf, block=block, nvec=nvec, b=b)
 
 
 @pytest.mark.parametrize("order,L,Ls", [(1, (4, 4, 4, 6), 8), (2, (4, 4, 4, 6), 8), (10, (4, 4, 4, 6), 8),
@@ -68,12 +68,12 @@ def _coarse(L, Ls, block, nvec, p, cs, U, filtered=True):
 
 
 @pytest.mark.parametrize("inner", ["c128", "c64"])
-def test_vcycle_parity_fixed_coarse_iterations(inner):
+def test_vcycle_parity_fixed_coarse_iterations(inner, b=1.0):
     """One application of B (the paper's M_outer) with exactly 6 coarse CR iterations."""
     torch = torch_dev()
     L, Ls, block, nvec = (4, 4, 4, 4), 8, (2, 2, 2, 2), 4
-    log(f"vcycle parity inner={inner}")
-    p, cs, lat = _lat(L, Ls, block, nvec)
+    log(f"vcycle parity inner={inner} b={b}")
+    p, cs, lat = _lat(L, Ls, block, nvec, b=b)
     U = hi.gauge_field(L)
     vecs, basis_ref, A_ref = _coarse(L, Ls, block, nvec, p, cs, U)
     r = hi.gaussian_fermion(L, Ls, seed=5)
@@ -86,6 +86,13 @@ def test_vcycle_parity_fixed_coarse_iterations(inner):
     e = hd.unpack_fermion(to_host(hd.vcycle(lat, Ud, basis, A, to_dev(hd.pack_fermion(r)), prm)), L, Ls)
     tol = 1e-10 if inner == "c128" else 1e-5
     assert max_rel_elem(e, ref) <= tol
+
+
+@pytest.mark.parametrize("inner", ["c128", "c64"])
+def test_vcycle_parity_cayley_b(inner):
+    """The cycle (smoother, coarse build, restriction, coarse CR, prolongation) for the
+    Cayley form with b = 1.5 (Sec. 3: Mobius with c = 0)."""
+    test_vcycle_parity_fixed_coarse_iterations(inner, b=1.5)
 
 
 def test_hdcr_solve_fp64_matches_oracle_iterates():
