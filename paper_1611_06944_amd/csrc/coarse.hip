@@ -4,6 +4,8 @@
 // coarse apply.  Layouts are described in coarse.h.
 #include <cmath>
 
+#include <cstdlib>
+
 #include "coarse.h"
 
 namespace hdcr {
@@ -233,7 +235,13 @@ __device__ __forceinline__ float2 dec_h(uint32_t w) {
     return make_float2(re * inv, im * inv);
 }
 template <typename T, int W> __device__ __forceinline__ void ld_basis(const C2<T>* p, C2<T> (&o)[W]) {
-    if constexpr (W == 2) {
+    if constexpr (W == 4) {
+        const Pair<T> q0 = ld_pair<T>(p), q1 = ld_pair<T>(p + 2);
+        o[0] = q0.a;
+        o[1] = q0.b;
+        o[2] = q1.a;
+        o[3] = q1.b;
+    } else if constexpr (W == 2) {
         const Pair<T> q = ld_pair<T>(p);
         o[0] = q.a;
         o[1] = q.b;
@@ -242,7 +250,13 @@ template <typename T, int W> __device__ __forceinline__ void ld_basis(const C2<T
     }
 }
 template <typename T, int W> __device__ __forceinline__ void ld_basis(const uint32_t* p, float2 (&o)[W]) {
-    if constexpr (W == 2) {
+    if constexpr (W == 4) {
+        const uint4 q = *reinterpret_cast<const uint4*>(p);
+        o[0] = dec_h(q.x);
+        o[1] = dec_h(q.y);
+        o[2] = dec_h(q.z);
+        o[3] = dec_h(q.w);
+    } else if constexpr (W == 2) {
         const uint2 q = *reinterpret_cast<const uint2*>(p);
         o[0] = dec_h(q.x);
         o[1] = dec_h(q.y);
@@ -251,14 +265,16 @@ template <typename T, int W> __device__ __forceinline__ void ld_basis(const uint
     }
 }
 
-constexpr int RKG = 16;  // basis vectors per restriction workgroup
+// basis vectors per restriction workgroup: all 32 at nvec >= 32 (psi is then
+// read by two workgroups per coarse site), else 16
+constexpr int RKG_MAX = 32;
 
 // grid (Nc, 2 chiralities, ceil(nvec / RKG)): v[a][h*nvec + k] = <phi^{a,h}_k, psi - psi2>
 // for the RKG vectors k of the workgroup.  Work-item = (row slot, W consecutive s):
 // a row is (component, block site), so the loads of the compressed basis (index
 // row * Lh + s) and of psi are contiguous; W = 2 (Lh even) makes them 16-byte
 // pairs in FP32.
-template <typename T, typename B, bool SUB, int W>
+template <typename T, typename B, bool SUB, int W, int RKG>
 __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                        const C2<T>* __restrict__ psi, const C2<T>* __restrict__ psi2,
                                                        C2<T>* __restrict__ v) {
@@ -282,7 +298,18 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
             const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
             // slot s + w pairs with the mirrored Ls-1-s-w
             C2<T> p1[W], p2[W];
-            if constexpr (W == 2) {
+            if constexpr (W == 4) {
+                const Pair<T> a0 = ld_pair<T>(psi + fb + s), a1 = ld_pair<T>(psi + fb + s + 2);
+                const Pair<T> b1 = ld_pair<T>(psi + fb + c.f.Ls - 4 - s), b0 = ld_pair<T>(psi + fb + c.f.Ls - 2 - s);
+                p1[0] = a0.a;
+                p1[1] = a0.b;
+                p1[2] = a1.a;
+                p1[3] = a1.b;
+                p2[0] = b0.b;
+                p2[1] = b0.a;
+                p2[2] = b1.b;
+                p2[3] = b1.a;
+            } else if constexpr (W == 2) {
                 const Pair<T> lo = ld_pair<T>(psi + fb + s), hi = ld_pair<T>(psi + fb + c.f.Ls - 2 - s);
                 p1[0] = lo.a;
                 p1[1] = lo.b;
@@ -321,11 +348,11 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
         if (threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
-// psi = y + P v for coarse site a (one workgroup).  A work-item handles two
-// consecutive compressed indices (nhalf is even), so the basis loads are
-// 16-byte (FP32) or 8-byte (FP16) runs; each index yields the pair of outputs
-// at s and its mirror Ls-1-s.
-template <typename T, typename B>
+// psi = y + P v for coarse site a (one workgroup).  A work-item handles NI
+// consecutive compressed indices (4 when nhalf is a multiple of 4, else 2; nhalf
+// is even), so the basis loads are 16-byte (FP16 at NI = 4, FP32 at NI = 2) or
+// 8-byte runs; each index yields the pair of outputs at s and its mirror Ls-1-s.
+template <typename T, typename B, int NI>
 __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                       const C2<T>* __restrict__ v, const C2<T>* __restrict__ y,
                                                       C2<T>* __restrict__ psi) {
@@ -337,21 +364,23 @@ __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __r
     const B* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
     const B* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
     const T r2 = (T)RSQRT2;
-    for (int i0 = 2 * threadIdx.x; i0 < c.nhalf; i0 += 2 * CWG) {
-        C2<T> tp[2] = {mk<T>(0, 0), mk<T>(0, 0)}, tm[2] = {mk<T>(0, 0), mk<T>(0, 0)};
+    for (int i0 = NI * threadIdx.x; i0 < c.nhalf; i0 += NI * CWG) {
+        C2<T> tp[NI], tm[NI];
+#pragma unroll
+        for (int q = 0; q < NI; ++q) tp[q] = tm[q] = mk<T>(0, 0);
         for (int k = 0; k < c.nvec; ++k) {
-            C2<T> ep[2], em[2];
-            ld_basis<T, 2>(bp + (size_t)k * c.nhalf + i0, ep);
-            ld_basis<T, 2>(bm + (size_t)k * c.nhalf + i0, em);
+            C2<T> ep[NI], em[NI];
+            ld_basis<T, NI>(bp + (size_t)k * c.nhalf + i0, ep);
+            ld_basis<T, NI>(bm + (size_t)k * c.nhalf + i0, em);
             const C2<T> xp = vs[k], xm = vs[c.nvec + k];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < NI; ++q) {
                 tp[q] = cfma<T>(ep[q], xp, tp[q]);
                 tm[q] = cfma<T>(em[q], xm, tm[q]);
             }
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NI; ++q) {
             const int i = i0 + q;
             const int s = i % c.Lh;
             const int sl = (i / c.Lh) % c.bvol;
@@ -938,23 +967,41 @@ void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk
     hipLaunchKernelGGL(basis_expand_kernel, dim3(grid_for(n)), dim3(CWG), 0, s, c, b64, k0, nk, fields);
 }
 
+template <typename T, typename B, int W, int RKG>
+void restrict_launch_w(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
+                       hipStream_t s) {
+    const dim3 grid(c.Nc, 2, (c.nvec + RKG - 1) / RKG);
+    if (psi2)
+        hipLaunchKernelGGL((restrict_kernel<T, B, true, W, RKG>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+    else
+        hipLaunchKernelGGL((restrict_kernel<T, B, false, W, RKG>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
+}
+
+template <typename T, typename B, int RKG>
+void restrict_launch_r(const CoarseGeom& c, int wmax, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
+                       hipStream_t s) {
+    // W consecutive s slots per work-item: 4 when Ls/2 is a multiple of 4 (16-byte
+    // basis loads in FP16, 16-byte psi pairs in FP32), 2 when it is even, and a
+    // row must fit the workgroup
+    if (wmax >= 4 && c.Lh % 4 == 0 && c.Lh / 4 <= CWG)
+        restrict_launch_w<T, B, 4, RKG>(c, basis, psi, psi2, v, s);
+    else if (wmax >= 2 && c.Lh % 2 == 0 && c.Lh / 2 <= CWG)
+        restrict_launch_w<T, B, 2, RKG>(c, basis, psi, psi2, v, s);
+    else
+        restrict_launch_w<T, B, 1, RKG>(c, basis, psi, psi2, v, s);
+}
+
 template <typename T, typename B>
 void restrict_launch(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v, hipStream_t s) {
-    const dim3 grid(c.Nc, 2, (c.nvec + RKG - 1) / RKG);
-    // two s slots per work-item when Ls/2 is even and a row fits the workgroup
-    const bool two = (c.Lh % 2 == 0) && (c.Lh / 2 <= CWG);
     if (c.Lh > CWG) return;  // not reachable: Ls <= 512 is enforced by the descriptor checks
-    if (two) {
-        if (psi2)
-            hipLaunchKernelGGL((restrict_kernel<T, B, true, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
-        else
-            hipLaunchKernelGGL((restrict_kernel<T, B, false, 2>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
-    } else {
-        if (psi2)
-            hipLaunchKernelGGL((restrict_kernel<T, B, true, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
-        else
-            hipLaunchKernelGGL((restrict_kernel<T, B, false, 1>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
-    }
+    // shape overrides (benchmark sweeps only)
+    int wmax = 4, rkg = 16;
+    if (const char* e = std::getenv("HDCR_RESTRICT_W")) wmax = std::atoi(e);
+    if (const char* e = std::getenv("HDCR_RESTRICT_RKG")) rkg = std::atoi(e);
+    if (rkg >= RKG_MAX && c.nvec >= RKG_MAX)
+        restrict_launch_r<T, B, RKG_MAX>(c, wmax, basis, psi, psi2, v, s);
+    else
+        restrict_launch_r<T, B, 16>(c, wmax, basis, psi, psi2, v, s);
 }
 
 template <typename T>
@@ -971,14 +1018,23 @@ void launch_restrict_h(const CoarseGeom& c, const uint32_t* basis, const float2*
 template <typename T>
 void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
                     hipStream_t s) {
-    hipLaunchKernelGGL((prolong_kernel<T, C2<T>>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v, y,
-                       psi);
+    hipLaunchKernelGGL((prolong_kernel<T, C2<T>, 2>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v,
+                       y, psi);
 }
 
 void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* v, const float2* y, float2* psi,
                       hipStream_t s) {
-    hipLaunchKernelGGL((prolong_kernel<float, uint32_t>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c, basis,
-                       v, y, psi);
+    // two indices per work-item (measured faster at 24^4 x 16 than four with
+    // 16-byte FP16 loads: 1.88 against 1.94 ms); HDCR_PROLONG_NI=4 selects four
+    // (benchmark sweeps only)
+    int ni = 2;
+    if (const char* e = std::getenv("HDCR_PROLONG_NI")) ni = std::atoi(e);
+    if (ni >= 4 && c.nhalf % 4 == 0)
+        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 4>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c,
+                           basis, v, y, psi);
+    else
+        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 2>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c,
+                           basis, v, y, psi);
 }
 
 template <typename T, typename S>
