@@ -72,8 +72,8 @@ def parse():
 # HBM traffic of the FP32 fine apply at 24^4 x 16 from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy), for the stencil sources (fine.hip and the
 # shared header) with this sha256; reported as null for any other source or lattice.
-MEASURED_TRAFFIC = {"stencil_sha256": "2a44c3510b36d190c984c401af7b765b3bc86ef548c5f4a7f532f6a05df67243",
-                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2206492668,
+MEASURED_TRAFFIC = {"stencil_sha256": "c78539722dcc3595d17c71401ba6ec8fc34983dfca18dce392b7d6bd10cd952e",
+                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2210009235,
                     "summary": "profiles/dslash_fine_24x24x24x24x16_traffic.md"}
 
 
