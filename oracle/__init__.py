@@ -497,28 +497,76 @@ def power_max(apply, v0, iters=30):
     return lam
 
 
-def coarse_cr(A, v, cdims, tol=1e-2, maxiter=500):
-    """Coarse solve A c = v by CR from c = 0 (Sec. 4: the subspace inverse by a Krylov method).
+def coarse_cr(A, v, cdims, tol=1e-2, maxiter=500, defl=None):
+    """Coarse solve A c = v by CR from c = 0 (Sec. 4: the subspace inverse by a Krylov method),
+    or, with a deflation space ``defl`` (``coarse_deflation``), from the Galerkin start
+    c0 = V diag(1/theta) V^dag v, which removes the deflated eigenmodes from the residual.
 
     tol = 0 runs exactly maxiter iterations (fixed-work mode used for parity).
     """
-    return cr(lambda u: coarse_apply(A, u, cdims), v, tol=tol, maxiter=maxiter, check_true=False)
+    x0 = None
+    if defl is not None:
+        theta, V = defl[0], defl[1]
+        x0 = np.zeros_like(v)
+        for th, vi in zip(theta, V):
+            x0 = x0 + (vdot(vi, v) / th) * vi
+    return cr(lambda u: coarse_apply(A, u, cdims), v, tol=tol, maxiter=maxiter, x0=x0, check_true=False)
+
+
+def coarse_deflation(A, cdims, V0, k, degree=40, iters=4, cut=0.05, power_iters=30):
+    """Low eigenpairs of the little Dirac operator A for deflating the coarse solve (Sec. 5
+    names coarse-space eigenvector deflation as the open option for the coarse cost).
+
+    Chebyshev-filtered subspace iteration in A^2 on the start block V0 (m >= k vectors).
+    Each pass applies the filter of ``cheby_filter`` on [lo, hi] to every vector, makes the
+    block orthonormal (Gram-Schmidt in index order, twice) and rotates it to the Ritz vectors
+    of A^2 (eig of (AV)^dag (AV)).  hi = 1.1 lambda_max^2 from ``power_max``; the first pass
+    uses lo = cut * hi, later ones lo = the largest Ritz value of A^2 in the block, which
+    bounds the part of the spectrum the block does not hold (A^2 is positive definite, so its
+    Ritz values never fall below its spectrum, unlike those of the indefinite A).  A final
+    Rayleigh-Ritz on A (theta, Y = eig(V^dag A V)) gives the pairs; the k of smallest |theta|
+    are returned as (theta[k], V[k], W[k] = A V[k]).
+    """
+    apply = lambda u: coarse_apply(A, u, cdims)
+    hi = 1.1 * power_max(apply, V0[0], power_iters)
+    lo = cut * hi
+    V = [np.array(v, dtype=np.complex128) for v in V0]
+    m = len(V)
+    for _ in range(iters):
+        V = [cheby_filter(apply, v, degree, lo, hi, normalise=True) for v in V]
+        for i in range(m):
+            for _ in range(2):
+                for j in range(i):
+                    V[i] = V[i] - vdot(V[j], V[i]) * V[j]
+            V[i] = V[i] / norm(V[i])
+        W = [apply(v) for v in V]
+        G2 = np.array([[vdot(W[i], W[j]) for j in range(m)] for i in range(m)])
+        mu, Y = np.linalg.eigh(0.5 * (G2 + G2.conj().T))
+        V = [sum(Y[i, q] * V[i] for i in range(m)) for q in range(m)]
+        lo = min(float(mu.max()), 0.99 * hi)
+    W = [apply(v) for v in V]
+    G = np.array([[vdot(V[i], W[j]) for j in range(m)] for i in range(m)])
+    theta, Y = np.linalg.eigh(0.5 * (G + G.conj().T))
+    order = np.argsort(np.abs(theta))[:k]
+    Vk = [sum(Y[i, q] * V[i] for i in range(m)) for q in order]
+    Wk = [sum(Y[i, q] * W[i] for i in range(m)) for q in order]
+    return theta[order], Vk, Wk
 
 
 def vcycle(apply, A, basis, cs: Coarse, r, order=10, lo=1.0, hi=64.0, ctol=1e-2, cmaxiter=500,
-           coarse_solve=None):
+           coarse_solve=None, defl=None):
     """Two-level cycle B r (Sec. 4, the M_outer display), symmetric form:
 
     e1 = S r;  e2 = e1 + Q (r - H e1);  e3 = e2 + S (r - H e2),  Q = P A^-1 P^dag.
     Expanding gives S P_L + P_R S + Q - S P_L H S with P_L = 1 - HQ, P_R = 1 - QH.
-    The coarse inverse is CR on A (``coarse_cr``) unless ``coarse_solve(v, cdims)``
-    is given (the tests pass an exact dense solve there).
+    The coarse inverse is CR on A (``coarse_cr``, deflated when ``defl`` is given) unless
+    ``coarse_solve(v, cdims)`` is given (the tests pass an exact dense solve there).
     """
     e1 = smoother(apply, r, order, lo, hi)
     t = r - apply(e1)
     vc = restrict(basis, t, cs)
     if coarse_solve is None:
-        c = coarse_cr(A, vc, cs.cdims, tol=ctol, maxiter=cmaxiter).x
+        c = coarse_cr(A, vc, cs.cdims, tol=ctol, maxiter=cmaxiter, defl=defl).x
     else:
         c = coarse_solve(vc, cs.cdims)
     e2 = e1 + prolong(basis, c, cs)

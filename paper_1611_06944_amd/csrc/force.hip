@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(128 * MS) link_force_kernel(FineGeom g, const 
 
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int term = wave & 1;  // 0: chi~ local, psi neighbour;  1: psi local, chi~ neighbour
-    const int mg = wave >> 1;   // directions mg*NM .. mg*NM + NM-1
+    const int mg = wave >> 1;   // direction group: directions mg*(4/MS) .. (mg+1)*(4/MS) - 1
     const int lane = threadIdx.x & 63;
     // logical sites l0 .. l0 + SITES-1 in the stencil's traversal order
     const int l0 = logical_block(blockIdx.x, gridDim.x) * SITES;

@@ -206,3 +206,57 @@ def test_hdcr_oracle_converges():
     ref = oracle.cr(ap, b, tol=1e-10, maxiter=10000)
     np.testing.assert_allclose(res.x, ref.x, atol=1e-6 * oracle.norm(ref.x))
     assert res.iters < ref.iters
+
+
+# ---------------------------------------------------------------------------
+# coarse-space eigenvector deflation (Sec. 5 names it for the coarse cost)
+# ---------------------------------------------------------------------------
+
+def _small_coarse(nvec=4):
+    L, Ls, block = (4, 4, 4, 4), 4, (2, 2, 2, 2)
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
+    cs = oracle.Coarse(p, block, nvec)
+    U = hi.gauge_field(L, seed=1)
+    vecs = hi.subspace_noise(L, Ls, nvec)
+    basis, st = oracle.block_basis(vecs, cs)
+    assert st == 0
+    return cs, oracle.coarse_build(U, basis, cs)
+
+
+def test_coarse_deflation_matches_dense_eigenpairs():
+    """The Ritz pairs of the filtered subspace iteration are the k eigenpairs of smallest
+    |lambda| of the dense coarse matrix (numpy eigh of the matrix assembled column by column)."""
+    cs, A = _small_coarse()
+    k, m = 6, 12
+    V0 = [hi.gaussian_coarse(cs.nc, cs.nb, seed=40 + i) for i in range(m)]
+    theta, V, W = oracle.coarse_deflation(A, cs.cdims, V0, k, degree=40, iters=4, cut=0.05)
+    D = oracle.coarse_dense(A, cs.cdims)
+    ev, evec = np.linalg.eigh(D)
+    ref = ev[np.argsort(np.abs(ev))[:k]]
+    anorm = np.abs(ev).max()
+    np.testing.assert_allclose(np.sort(theta), np.sort(ref), atol=1e-9 * anorm)
+    G = np.array([[oracle.vdot(a, b) for b in V] for a in V])
+    np.testing.assert_allclose(G, np.eye(k), atol=1e-12)
+    for th, v, w in zip(theta, V, W):
+        np.testing.assert_allclose(w, oracle.coarse_apply(A, v, cs.cdims), atol=1e-12 * anorm)
+        assert oracle.norm(w - th * v) <= 1e-7 * anorm
+
+
+def test_deflated_coarse_cr():
+    """The Galerkin start leaves a residual orthogonal to the deflation space; the deflated
+    solve reaches the same solution in no more iterations."""
+    cs, A = _small_coarse()
+    k, m = 6, 12
+    V0 = [hi.gaussian_coarse(cs.nc, cs.nb, seed=40 + i) for i in range(m)]
+    defl = oracle.coarse_deflation(A, cs.cdims, V0, k, degree=40, iters=4, cut=0.05)
+    b = hi.gaussian_coarse(cs.nc, cs.nb, seed=7)
+    theta, V = defl[0], defl[1]
+    x0 = sum((oracle.vdot(v, b) / th) * v for th, v in zip(theta, V))
+    r0 = b - oracle.coarse_apply(A, x0, cs.cdims)
+    for v in V:
+        assert abs(oracle.vdot(v, r0)) <= 1e-10 * oracle.norm(b)
+    plain = oracle.coarse_cr(A, b, cs.cdims, tol=1e-10, maxiter=5000)
+    defl_res = oracle.coarse_cr(A, b, cs.cdims, tol=1e-10, maxiter=5000, defl=defl)
+    assert plain.status == 0 and defl_res.status == 0
+    assert defl_res.iters <= plain.iters
+    np.testing.assert_allclose(defl_res.x, plain.x, atol=1e-7 * oracle.norm(plain.x))
