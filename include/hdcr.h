@@ -35,8 +35,9 @@
  * Ownership: the caller owns every buffer.  The library never allocates or
  * frees device memory; scratch space comes in through (work, work_bytes),
  * sized by hdcr_workspace_bytes().  Every call except hdcr_solve,
- * hdcr_make_subspace, hdcr_power_max and hdcr_vec_dot is stream-ordered and
- * returns before the work is done; those four return after it has completed.
+ * hdcr_coarse_solve, hdcr_build_deflation, hdcr_make_subspace, hdcr_power_max
+ * and hdcr_vec_dot is stream-ordered and returns before the work is done;
+ * those six return after it has completed.
  * In and out buffers of one call must not overlap.
  *
  * Errors: 0 = success.  Negative codes are caller errors found before any
@@ -139,6 +140,35 @@ typedef struct hdcr_solve_stats {
     int32_t reserved;
 } hdcr_solve_stats;
 
+/* Coarse-space eigenvector deflation (Sec. 5 names it as the way to cut the
+ * coarse-solve cost): k orthonormal approximate eigenvectors V_i of the little
+ * Dirac operator A with the smallest |theta_i|, W_i = A V_i and the Ritz values
+ * theta_i.  The coarse CR then starts from the Galerkin projection
+ * x0 = sum_i (<V_i, b> / theta_i) V_i with r0 = b - sum_i (<V_i, b> / theta_i) W_i,
+ * which removes the deflated modes from the residual.  theta, V, W are device
+ * buffers owned by the caller (V, W: [k][site_c][Nb], the coarse vector
+ * layout); dtype C128 for an FP64 coarse solve (C128 storage of A), C64 for an
+ * FP32 one (C64 or BF16C storage). */
+#define HDCR_DEFL_MAX 64
+typedef struct hdcr_coarse_deflation {
+    int32_t k;            /* 1 <= k <= HDCR_DEFL_MAX */
+    int32_t dtype;        /* C128 or C64 */
+    const double* theta;  /* k Ritz values (device) */
+    const void* V;
+    const void* W;
+} hdcr_coarse_deflation;
+
+/* Set-up parameters of hdcr_build_deflation. */
+typedef struct hdcr_deflation_params {
+    int32_t k;            /* eigenpairs kept, 1 <= k <= m */
+    int32_t m;            /* block size (start vectors), k <= m <= HDCR_DEFL_MAX, m <= Nc * Nb */
+    int32_t degree;       /* Chebyshev filter degree in A^2 per pass, 1 .. 1000 */
+    int32_t iters;        /* filtered passes, 1 .. 100 */
+    int32_t power_iters;  /* power iterations for the top of the A^2 spectrum, 1 .. 10000 */
+    int32_t reserved;
+    double cut;           /* lower filter edge of the first pass as a fraction of the top, 0 < cut < 1 */
+} hdcr_deflation_params;
+
 HDCR_API const char* hdcr_strerror(int code);
 HDCR_API const char* hdcr_last_error(void);
 
@@ -176,12 +206,14 @@ HDCR_API int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void
 /* Scratch bytes needed by the calls below: which = HDCR_WS_SOLVE (hdcr_solve
  * with the given params), HDCR_WS_BUILD (hdcr_build_coarse), HDCR_WS_SUBSPACE
  * (hdcr_make_subspace / hdcr_power_max), HDCR_WS_SMOOTH (hdcr_smooth),
- * HDCR_WS_VCYCLE (hdcr_vcycle with the given params). */
+ * HDCR_WS_VCYCLE (hdcr_vcycle with the given params), HDCR_WS_COARSE
+ * (hdcr_coarse_solve with A in params->coarse_dtype). */
 #define HDCR_WS_SOLVE 0
 #define HDCR_WS_BUILD 1
 #define HDCR_WS_SUBSPACE 2
 #define HDCR_WS_SMOOTH 3
 #define HDCR_WS_VCYCLE 4
+#define HDCR_WS_COARSE 5
 HDCR_API size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
 
 /* Bytes of the opaque basis buffer (FP64 and FP32 copies of the chirally
@@ -265,12 +297,49 @@ HDCR_API int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const voi
 
 /* One application of the symmetric two-level cycle (Sec. 4, M_outer):
  *   e1 = S r;  e2 = e1 + Q (r - H e1);  e = e2 + S (r - H e2),  Q = P CR_A(P^dag .)
- * with the smoother and coarse solve of params (coarse CR from 0 to
- * coarse_tol, or exactly coarse_maxiter iterations when coarse_tol <= 0).
+ * with the smoother and coarse solve of params (coarse CR from 0, or from the
+ * Galerkin start of defl when it is not NULL, to coarse_tol, or exactly
+ * coarse_maxiter iterations when coarse_tol <= 0).
  * r, e, U: C128; computed in params->inner_dtype.  work:
  * hdcr_workspace_bytes(HDCR_WS_VCYCLE). */
 HDCR_API int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
-                const void* A, const void* r, void* e, void* work, size_t work_bytes, hipStream_t stream);
+                const void* A, const hdcr_coarse_deflation* defl, const void* r, void* e, void* work,
+                size_t work_bytes, hipStream_t stream);
+
+/* Coarse solve A x = b by conjugate residual (Sec. 4: the subspace inverse by
+ * a Krylov method), the solve inside the two-level cycle: from x = 0, or from
+ * the Galerkin start of the deflation space defl (host struct, may be NULL;
+ * dtype as for the solve).  tol <= 0 runs exactly maxiter iterations, else CR
+ * stops when the updated |r| <= tol |b| or after maxiter.  b, x: C128 for
+ * C128 storage of A, C64 for C64 / BF16C; not overlapping.  *iters (may be
+ * NULL) gets the iteration count.  work: hdcr_workspace_bytes(HDCR_WS_COARSE)
+ * with params->coarse_dtype = A_dtype.  Synchronous. */
+HDCR_API int hdcr_coarse_solve(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
+                               const hdcr_coarse_deflation* defl, const void* b, void* x, int32_t maxiter, double tol,
+                               int32_t* iters, void* work, size_t work_bytes, hipStream_t stream);
+
+/* Deflation set-up (Sec. 5, coarse-space eigenvector deflation): the k
+ * eigenpairs of A of smallest |lambda| by Chebyshev-filtered subspace
+ * iteration in A^2 (positive definite, so its Ritz values bound its spectrum
+ * from above, unlike those of the indefinite A) on the m start vectors v0:
+ * hi = 1.1 x the power-iteration estimate of the top of A^2 from v0[0]; each
+ * pass filters the block with T_degree((2 A^2 - hi - lo)/(hi - lo)), makes it
+ * orthonormal (Gram-Schmidt in index order, twice) and rotates it to the Ritz
+ * vectors of A^2; lo = cut * hi in the first pass and the largest Ritz value
+ * of A^2 in the block (at most 0.99 hi) afterwards.  A final Rayleigh-Ritz on A
+ * gives theta and V; the k of smallest |theta| are written to theta (device,
+ * k doubles), V and W = A V (device, [k][site_c][Nb] in C128 for C128 storage
+ * of A, C64 otherwise: the vector precision of the coarse solve that uses
+ * them), and to theta_host (may be NULL) in ascending |theta|.  Computed in
+ * that vector precision with FP64 inner products; the small dense eigenproblems
+ * are solved on the host.  v0: m C128 coarse vectors.  work:
+ * hdcr_deflation_workspace_bytes().  Synchronous; HDCR_ENAN if the spectrum
+ * estimate or a Ritz value is not finite. */
+HDCR_API size_t hdcr_deflation_workspace_bytes(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype,
+                                               const hdcr_deflation_params* params);
+HDCR_API int hdcr_build_deflation(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
+                                  const hdcr_deflation_params* params, const void* v0, double* theta, void* V, void* W,
+                                  double* theta_host, void* work, size_t work_bytes, hipStream_t stream);
 
 /* Subspace generation (Sec. 4, Fig. 1): vecs[k] = T_degree(yhat) noise[k] / |.|
  * with yhat = (2 H^2 - hi - lo)/(hi - lo): the Chebyshev low-pass filter that
@@ -291,12 +360,13 @@ HDCR_API int hdcr_power_max(const hdcr_fine_desc* desc, const void* U, const voi
 /* Solve H x = b to |b - H x| <= tol |b| (x: initial guess in, solution out;
  * C128 fields; U in C128).  precond NONE ignores basis and A (may be NULL).
  * TWO_LEVEL needs the basis and A of hdcr_build_coarse (A in
- * params->coarse_dtype).  history (host, may be NULL) receives up to
+ * params->coarse_dtype); defl (host struct, may be NULL) deflates every coarse
+ * solve (vectors in params->inner_dtype).  history (host, may be NULL) receives up to
  * history_cap relative residual norms, one per outer iteration.  Returns 0 or
  * a positive status (stats->status holds the same).  Synchronous. */
 HDCR_API int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
-               const void* A, const void* b, void* x, hdcr_solve_stats* stats, double* history, int32_t history_cap,
-               void* work, size_t work_bytes, hipStream_t stream);
+               const void* A, const hdcr_coarse_deflation* defl, const void* b, void* x, hdcr_solve_stats* stats,
+               double* history, int32_t history_cap, void* work, size_t work_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_
 __all__ = ["Lattice", "apply_fine", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
-           "HDCRError"]
+           "HDCRError", "Deflation", "build_deflation", "coarse_solve"]
 
 load = _abi.load
 
@@ -236,8 +236,9 @@ def workspace_bytes(which: int, lat: Lattice, params: SolveParams | None = None)
 
 
 def solve(lat: Lattice, U, b, x=None, params: SolveParams | None = None, basis=None, A=None, work=None,
-          history_cap: int = 100000, stream=None):
-    """Solve H x = b (synchronous).  Returns (x, stats dict, relative-residual history)."""
+          history_cap: int = 100000, stream=None, defl: "Deflation | None" = None):
+    """Solve H x = b (synchronous).  Returns (x, stats dict, relative-residual history).
+    defl: coarse deflation space (``build_deflation``) used by every coarse solve."""
     torch = _torch()
     lib = load()
     params = params or default_params()
@@ -248,8 +249,10 @@ def solve(lat: Lattice, U, b, x=None, params: SolveParams | None = None, basis=N
         work = _workspace(workspace_bytes(_abi.WS_SOLVE, lat, params), b.device)
     st = SolveStats()
     hist = (ctypes.c_double * max(1, history_cap))()
-    code = lib.hdcr_solve(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A), _ptr(b), _ptr(x),
-                          ctypes.byref(st), hist, history_cap, _ptr(work), work.numel(), _stream(stream))
+    ds = _defl_struct(defl)
+    code = lib.hdcr_solve(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A),
+                          ctypes.byref(ds) if ds is not None else None, _ptr(b), _ptr(x), ctypes.byref(st), hist,
+                          history_cap, _ptr(work), work.numel(), _stream(stream))
     _abi.check(code, "hdcr_solve")
     return x, st.as_dict(), list(hist[:st.history_len])
 
@@ -416,16 +419,19 @@ def smooth(lat: Lattice, U, x, order=10, lo=1.0, hi=64.0, out=None, work=None, s
     return out
 
 
-def vcycle(lat: Lattice, U, basis, A, r, params: SolveParams, out=None, work=None, stream=None):
-    """One application of the two-level cycle to r (complex128)."""
+def vcycle(lat: Lattice, U, basis, A, r, params: SolveParams, out=None, work=None, stream=None,
+           defl: "Deflation | None" = None):
+    """One application of the two-level cycle to r (complex128); defl deflates its coarse solve."""
     torch = _torch()
     if out is None:
         out = torch.empty_like(r)
     if work is None:
         work = _workspace(workspace_bytes(_abi.WS_VCYCLE, lat, params), r.device)
     cd = lat.coarse_desc()
-    _abi.check(load().hdcr_vcycle(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A), _ptr(r),
-                                  _ptr(out), _ptr(work), work.numel(), _stream(stream)), "hdcr_vcycle")
+    ds = _defl_struct(defl)
+    _abi.check(load().hdcr_vcycle(ctypes.byref(cd), ctypes.byref(params), _ptr(U), _ptr(basis), _ptr(A),
+                                  ctypes.byref(ds) if ds is not None else None, _ptr(r), _ptr(out), _ptr(work),
+                                  work.numel(), _stream(stream)), "hdcr_vcycle")
     return out
 
 
@@ -453,3 +459,92 @@ def power_max(lat: Lattice, U, v0, iters=30, work=None, stream=None) -> float:
     _abi.check(lib.hdcr_power_max(ctypes.byref(d), _ptr(U), _ptr(v0), int(iters), ctypes.byref(lam), _ptr(work),
                                   work.numel(), _stream(stream)), "hdcr_power_max")
     return lam.value
+
+
+# ----------------------------------------------------------------------------
+# coarse-space eigenvector deflation
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Deflation:
+    """Deflation space of the coarse solve: Ritz values theta [k] (float64) and the
+    vectors V, W = A V [k, Nc, Nb] (complex128 for an FP64 coarse solve, complex64
+    for FP32), all device tensors; theta_host: the same Ritz values on the host."""
+    theta: object
+    V: object
+    W: object
+    theta_host: list
+
+    @property
+    def k(self) -> int:
+        return int(self.theta.numel())
+
+
+def _defl_struct(defl):
+    if defl is None:
+        return None
+    return _abi.CoarseDeflation(defl.k, _dtype_code(defl.V), _ptr(defl.theta).value, _ptr(defl.V).value,
+                                _ptr(defl.W).value)
+
+
+def _coarse_vec_dtype(A_dtype: int):
+    torch = _torch()
+    return torch.complex128 if int(A_dtype) == C128 else torch.complex64
+
+
+def _check_coarse_operator(lat: Lattice, A, A_dtype: int):
+    need = coarse_bytes(lat, A_dtype)
+    if A.numel() * A.element_size() < need:
+        raise ValueError(f"A holds {A.numel() * A.element_size()} bytes, {need} needed for dtype {A_dtype}")
+
+
+def build_deflation(lat: Lattice, A, A_dtype: int, v0, k: int, degree: int = 40, iters: int = 4, cut: float = 0.05,
+                    power_iters: int = 30, work=None, stream=None) -> Deflation:
+    """The k eigenpairs of smallest |lambda| of the little Dirac operator A by Chebyshev-filtered
+    subspace iteration in A^2 from the m start vectors v0 (complex128 [m, Nc, Nb]); synchronous."""
+    torch = _torch()
+    lib = load()
+    _check_coarse_operator(lat, A, A_dtype)
+    if v0.dtype != torch.complex128 or v0.dim() != 3 or tuple(v0.shape[1:]) != (lat.nc, lat.nb):
+        raise ValueError(f"v0 must be complex128 [m, {lat.nc}, {lat.nb}], got {v0.dtype} {tuple(v0.shape)}")
+    m = int(v0.shape[0])
+    cd = lat.coarse_desc()
+    prm = _abi.DeflationParams(int(k), m, int(degree), int(iters), int(power_iters), 0, float(cut))
+    if work is None:
+        nbytes = int(lib.hdcr_deflation_workspace_bytes(ctypes.byref(cd), int(A_dtype), ctypes.byref(prm)))
+        if nbytes == 0:
+            raise ValueError(f"invalid deflation parameters k={k} m={m} degree={degree} iters={iters} cut={cut}")
+        work = _workspace(nbytes, v0.device)
+    vdt = _coarse_vec_dtype(A_dtype)
+    theta = torch.empty(int(k), dtype=torch.float64, device=v0.device)
+    V = torch.empty((int(k), lat.nc, lat.nb), dtype=vdt, device=v0.device)
+    W = torch.empty_like(V)
+    th = (ctypes.c_double * int(k))()
+    _abi.check(lib.hdcr_build_deflation(ctypes.byref(cd), int(A_dtype), _ptr(A), ctypes.byref(prm), _ptr(v0),
+                                        _ptr(theta), _ptr(V), _ptr(W), th, _ptr(work), work.numel(),
+                                        _stream(stream)), "hdcr_build_deflation")
+    return Deflation(theta, V, W, [float(t) for t in th])
+
+
+def coarse_solve(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: float = 1e-2, defl: Deflation | None = None,
+                 x=None, work=None, stream=None):
+    """x = CR_A(b) on the coarse lattice (from 0, or from the Galerkin start of defl); tol <= 0:
+    exactly maxiter iterations.  b: [Nc, Nb] complex128 for C128 storage, complex64 otherwise.
+    Synchronous; returns (x, iterations)."""
+    torch = _torch()
+    lib = load()
+    _check_coarse_operator(lat, A, A_dtype)
+    if b.dtype != _coarse_vec_dtype(A_dtype) or b.numel() != lat.nc * lat.nb:
+        raise ValueError(f"b must be {_coarse_vec_dtype(A_dtype)} with {lat.nc * lat.nb} entries")
+    if x is None:
+        x = torch.empty_like(b)
+    cd = lat.coarse_desc()
+    if work is None:
+        prm = default_params(coarse_dtype=int(A_dtype))
+        work = _workspace(workspace_bytes(_abi.WS_COARSE, lat, prm), b.device)
+    ds = _defl_struct(defl)
+    it = ctypes.c_int32(0)
+    _abi.check(lib.hdcr_coarse_solve(ctypes.byref(cd), int(A_dtype), _ptr(A), ctypes.byref(ds) if ds is not None else None,
+                                     _ptr(b), _ptr(x), int(maxiter), float(tol), ctypes.byref(it), _ptr(work),
+                                     work.numel(), _stream(stream)), "hdcr_coarse_solve")
+    return x, int(it.value)

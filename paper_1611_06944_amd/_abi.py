@@ -19,7 +19,8 @@ HDCR_ERANK = 4
 C128, C64, BF16C, F16C = 0, 1, 2, 3
 MFMA_VARIANTS = 7  # tile shapes of the batched coarse apply
 PRECOND_NONE, PRECOND_TWO_LEVEL = 0, 1
-WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE = 0, 1, 2, 3, 4
+WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE, WS_COARSE = 0, 1, 2, 3, 4, 5
+DEFL_MAX = 64
 DOT_WORK_BYTES = 32768
 
 
@@ -54,6 +55,16 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class CoarseDeflation(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("dtype", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("W", ctypes.c_void_p)]
+
+
+class DeflationParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("m", ctypes.c_int32), ("degree", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cut", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 _i32 = ctypes.c_int32
@@ -68,8 +79,14 @@ PROTOTYPES = {
     "hdcr_fermion_force": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "hdcr_vec_dot": (ctypes.c_int, [_i32, _i64, _vp, _vp, _dbl_p, _vp, _sz, _vp]),
     "hdcr_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams)]),
-    "hdcr_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp, _vp, _vp,
-                                  ctypes.POINTER(SolveStats), _dbl_p, _i32, _vp, _sz, _vp]),
+    "hdcr_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp,
+                                  ctypes.POINTER(CoarseDeflation), _vp, _vp, ctypes.POINTER(SolveStats), _dbl_p, _i32,
+                                  _vp, _sz, _vp]),
+    "hdcr_coarse_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(CoarseDeflation), _vp,
+                                         _vp, _i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp]),
+    "hdcr_deflation_workspace_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32, ctypes.POINTER(DeflationParams)]),
+    "hdcr_build_deflation": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(DeflationParams),
+                                            _vp, _vp, _vp, _vp, _dbl_p, _vp, _sz, _vp]),
     "hdcr_basis_bytes": (_sz, [ctypes.POINTER(CoarseDesc)]),
     "hdcr_coarse_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32]),
     "hdcr_build_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
@@ -84,8 +101,8 @@ PROTOTYPES = {
                                                  ctypes.POINTER(ctypes.c_int32), _dbl_p, _vp]),
     "hdcr_smooth": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp,
                                    _vp, _vp, _sz, _vp]),
-    "hdcr_vcycle": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp, _vp, _vp,
-                                   _vp, _sz, _vp]),
+    "hdcr_vcycle": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp,
+                                   ctypes.POINTER(CoarseDeflation), _vp, _vp, _vp, _sz, _vp]),
     "hdcr_subspace_workspace_bytes": (_sz, [ctypes.POINTER(FineDesc), _i32]),
     "hdcr_make_subspace": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _i32, _i32, ctypes.c_double,
                                           ctypes.c_double, _vp, _vp, _vp, _vp, _sz, _vp]),

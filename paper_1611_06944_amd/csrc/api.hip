@@ -96,12 +96,6 @@ int check_ptr(const void* p, size_t align, const char* name) {
 
 static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4; }
 
-static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-    const char* pa = static_cast<const char*>(a);
-    const char* pb = static_cast<const char*>(b);
-    return pa < pb + nb && pb < pa + na;
-}
-
 }  // namespace hdcr
 
 using namespace hdcr;
@@ -222,14 +216,20 @@ size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_
         case HDCR_WS_BUILD:
             if (check_coarse_desc(desc)) return 0;
             return build_workspace_bytes(make_coarse_geom(desc));
+        case HDCR_WS_COARSE:
+            if (!params || check_coarse_desc(desc)) return 0;
+            if (params->coarse_dtype == HDCR_C128) return coarse_cr_bytes<double>(make_coarse_geom(desc));
+            if (params->coarse_dtype == HDCR_C64 || params->coarse_dtype == HDCR_BF16C)
+                return coarse_cr_bytes<float>(make_coarse_geom(desc));
+            return 0;
         default:
             return 0;
     }
 }
 
 int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
-               const void* A, const void* b, void* x, hdcr_solve_stats* stats, double* history, int32_t history_cap,
-               void* work, size_t work_bytes, hipStream_t stream) {
+               const void* A, const hdcr_coarse_deflation* defl, const void* b, void* x, hdcr_solve_stats* stats,
+               double* history, int32_t history_cap, void* work, size_t work_bytes, hipStream_t stream) {
     if (!desc || !params) return fail(HDCR_EINVAL, "hdcr_solve: null descriptor or params");
     int e = check_fine_desc(&desc->fine);
     if (e) return e;
@@ -251,9 +251,10 @@ int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, co
     if ((e = check_two_level_params(params))) return e;
     if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(A, 4, "A"))) return e;
     const CoarseGeom c = make_coarse_geom(desc);
+    if (defl && (e = check_deflation(c, defl, (hdcr_dtype)params->inner_dtype, "hdcr_solve"))) return e;
     if (work_bytes < two_level_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_solve: workspace too small");
-    return two_level_solve(c, params, (const double2*)U, basis, A, (const double2*)b, (double2*)x, stats, history,
-                           history_cap, work, work_bytes, stream);
+    return two_level_solve(c, params, (const double2*)U, basis, A, defl, (const double2*)b, (double2*)x, stats,
+                           history, history_cap, work, work_bytes, stream);
 }
 
 }  // extern "C"

@@ -110,10 +110,21 @@ template <typename T> struct CoarseCRWork {
     C2<T>* p;
     C2<T>* Ar;
     C2<T>* Ap;
-    double* part;   // partial sums: [2][Nc] of the apply, then CCR_BLOCKS of the update kernels
+    double* part;   // partial sums: [2][Nc] of the apply, then [2][CCR_BLOCKS] of the update and init kernels
     double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
     int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter;
                     // CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
+    double* dpart;  // partial sums of the deflated start: [2 * DEFL_KMAX][DEFL_BLOCKS]
+};
+// Deflation space of the coarse solve: k orthonormal approximate eigenvectors V_i
+// of A, W_i = A V_i and the Ritz values theta_i (device arrays; V, W [k][Nc*Nb]).
+constexpr int DEFL_KMAX = 64;
+constexpr int DEFL_BLOCKS = 64;
+template <typename T> struct DeflView {
+    int k;
+    const double* theta;
+    const C2<T>* V;
+    const C2<T>* W;
 };
 constexpr int CCR_BLOCKS = 64;
 constexpr int ARRIVE_GROUPS = 16;   // group counters of the last-arrival test
@@ -124,6 +135,12 @@ constexpr int CCR_FLAGS = CCR_COUNTERS + (1 + ARRIVE_GROUPS) * ARRIVE_STRIDE;  /
 template <typename T>
 void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,
                      hipStream_t s);
+// the Galerkin start from the deflation space: x = sum_i (<V_i, b> / theta_i) V_i,
+// r = b - sum_i (<V_i, b> / theta_i) W_i (so V^dag r = 0 when W = A V and the V_i
+// are eigenvectors); |b|^2, |r|^2 and the iteration state as launch_ccr_init
+template <typename T>
+void launch_ccr_init_defl(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w,
+                          const DeflView<T>& d, int maxiter, double tol, hipStream_t s);
 // one CR iteration (x, r update; Ar = A r; p, Ap update); first = true issues
 // the start-up step (p = r, Ap = A r) instead
 template <typename T>

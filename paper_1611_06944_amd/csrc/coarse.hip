@@ -604,6 +604,86 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
     }
 }
 
+// Partial sums of <V_j, b> for the eight deflation vectors j = 8*blockIdx.y + jj:
+// dpart[(16*blockIdx.y + 2*jj (+1)) * DEFL_BLOCKS + blockIdx.x] (re, im).
+template <typename T>
+__global__ void __launch_bounds__(CWG) defl_dot_kernel(int n, DeflView<T> d, const C2<T>* __restrict__ b,
+                                                       double* __restrict__ dpart) {
+    const int j0 = blockIdx.y * 8;
+    const int nv = min(8, d.k - j0);
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
+        const C2<T> bv = b[i];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            if (jj < nv) {
+                const C2<T> v = d.V[(size_t)(j0 + jj) * n + i];
+                acc[2 * jj] += (double)v.x * bv.x + (double)v.y * bv.y;
+                acc[2 * jj + 1] += (double)v.x * bv.y - (double)v.y * bv.x;
+            }
+        }
+    }
+    block_reduce<16>(acc);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 16; ++q) dpart[((size_t)blockIdx.y * 16 + q) * DEFL_BLOCKS + blockIdx.x] = acc[q];
+    }
+}
+
+// x = sum_j g_j V_j, r = b - sum_j g_j W_j with g_j = <V_j, b> / theta_j (every
+// workgroup sums the dot partials itself, in a fixed order); then as ccr_init
+// with cs[3] = |r|^2 and cs[4] = |b|^2
+template <typename T>
+__global__ void __launch_bounds__(CWG) ccr_init_defl_kernel(int n, const C2<T>* __restrict__ b, C2<T>* __restrict__ x,
+                                                            C2<T>* __restrict__ r, DeflView<T> d,
+                                                            const double* __restrict__ dpart, double* part,
+                                                            double* cs, int* flags, int maxiter, double tol2) {
+    __shared__ double gs[2 * DEFL_KMAX];
+    for (int q = threadIdx.x; q < 2 * d.k; q += CWG) {
+        const int j = q >> 1;
+        const double* row = dpart + ((size_t)(j >> 3) * 16 + 2 * (j & 7) + (q & 1)) * DEFL_BLOCKS;
+        double sum = 0.0;
+        for (int i = 0; i < DEFL_BLOCKS; ++i) sum += row[i];
+        gs[q] = sum / d.theta[j];
+    }
+    __syncthreads();
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
+        const C2<T> bv = b[i];
+        double2 xa = make_double2(0.0, 0.0), ra = make_double2(bv.x, bv.y);
+        for (int j = 0; j < d.k; ++j) {
+            const double2 g = make_double2(gs[2 * j], gs[2 * j + 1]);
+            const C2<T> vv = d.V[(size_t)j * n + i], wv = d.W[(size_t)j * n + i];
+            xa = cfma<double>(g, make_double2(vv.x, vv.y), xa);
+            ra = cfma<double>(cneg<double>(g), make_double2(wv.x, wv.y), ra);
+        }
+        const C2<T> xo = mk<T>((T)xa.x, (T)xa.y), ro = mk<T>((T)ra.x, (T)ra.y);
+        x[i] = xo;
+        r[i] = ro;
+        v[0] += (double)bv.x * bv.x + (double)bv.y * bv.y;
+        v[1] += (double)ro.x * ro.x + (double)ro.y * ro.y;
+    }
+    block_reduce<2>(v);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[gridDim.x + blockIdx.x] = v[1];
+    }
+    if (last_arrival(flags + CCR_COUNTERS)) {
+        double s[2];
+        reduce_partials<2>(part, gridDim.x, s);
+        if (threadIdx.x == 0) {
+            cs[4] = s[0];
+            cs[3] = s[1];
+            cs[5] = tol2;
+            flags[3] = maxiter;
+            flags[2] = 1;
+            flags[1] = 0;
+            flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0]) || !isfinite(s[1])) ? 1 : 0;
+        }
+    }
+}
+
 // Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar.
 // Partial sums of <r,Ar> and |Ar|^2 per coarse site go to part[a], part[Nc+a].
 template <typename T, typename S, int E, bool FIRST>
@@ -915,6 +995,16 @@ void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const Coarse
 }
 
 template <typename T>
+void launch_ccr_init_defl(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w,
+                          const DeflView<T>& d, int maxiter, double tol, hipStream_t s) {
+    const double tol2 = tol > 0 ? tol * tol : 0.0;
+    const int n = c.Nc * c.Nb;
+    hipLaunchKernelGGL(defl_dot_kernel<T>, dim3(DEFL_BLOCKS, (d.k + 7) / 8), dim3(CWG), 0, s, n, d, b, w.dpart);
+    hipLaunchKernelGGL(ccr_init_defl_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, b, x, w.r, d,
+                       (const double*)w.dpart, w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
+}
+
+template <typename T>
 void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
                      bool first, hipStream_t s) {
     const int n = c.Nc * c.Nb;
@@ -934,6 +1024,10 @@ template void launch_ccr_init<double>(const CoarseGeom&, const double2*, double2
                                       double, hipStream_t);
 template void launch_ccr_init<float>(const CoarseGeom&, const float2*, float2*, const CoarseCRWork<float>&, int,
                                      double, hipStream_t);
+template void launch_ccr_init_defl<double>(const CoarseGeom&, const double2*, double2*, const CoarseCRWork<double>&,
+                                           const DeflView<double>&, int, double, hipStream_t);
+template void launch_ccr_init_defl<float>(const CoarseGeom&, const float2*, float2*, const CoarseCRWork<float>&,
+                                          const DeflView<float>&, int, double, hipStream_t);
 template void launch_ccr_step<double>(const CoarseGeom&, hdcr_dtype, const void*, double2*,
                                       const CoarseCRWork<double>&, bool, hipStream_t);
 template void launch_ccr_step<float>(const CoarseGeom&, hdcr_dtype, const void*, float2*, const CoarseCRWork<float>&,

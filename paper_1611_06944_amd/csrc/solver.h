@@ -25,6 +25,13 @@ class Carver {
     size_t off_ = 0;
 };
 
+// true if the byte ranges [a, a + na) and [b, b + nb) intersect
+inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
 // Sums nq rows of REDUCE_BLOCKS partials (row q at partials + q*REDUCE_BLOCKS)
 // in fixed order; S[d0] = row 0, S[d1] = row 1 (if nq == 2).  Afterwards, if
 // csrc >= 0, S[cdst] = S[csrc] (old value of csrc).

@@ -37,9 +37,11 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
 // |r| <= tol |b| or maxiter.  Asynchronous except that the tolerance mode may
 // synchronise to decide how many iterations to enqueue; *iters gets the count
 // (after the stream has been synchronised) through flags[1].
+// defl (may be null): start from the Galerkin projection on the deflation space
 template <typename T>
 int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T>* b, C2<T>* x, int maxiter,
-              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters);
+              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters,
+              const DeflView<T>* defl = nullptr);
 
 // Chebyshev smoother acc = p(H^2) H in, p the order-term Chebyshev interpolant
 // of 1/y on [lo, hi] (Sec. 4); tmp: 4 fine vectors of precision T.
@@ -51,11 +53,14 @@ void cheby_coeffs(int n, double lo, double hi, double* c);
 
 int check_two_level_params(const hdcr_solve_params* p);
 size_t two_level_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p);
+// defl: the coarse deflation space (may be null), vectors in the inner precision
+int check_deflation(const CoarseGeom& c, const hdcr_coarse_deflation* d, hdcr_dtype dtype, const char* where);
 int two_level_solve(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis,
-                    const void* A, const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap,
-                    void* work, size_t work_bytes, hipStream_t s);
+                    const void* A, const hdcr_coarse_deflation* defl, const double2* b, double2* x,
+                    hdcr_solve_stats* st, double* history, int hcap, void* work, size_t work_bytes, hipStream_t s);
 size_t vcycle_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p);
 int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis, const void* A,
-                 const double2* r, double2* e, void* work, size_t work_bytes, hipStream_t s);
+                 const hdcr_coarse_deflation* defl, const double2* r, double2* e, void* work, size_t work_bytes,
+                 hipStream_t s);
 
 }  // namespace hdcr

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <string>
 
 #include <initializer_list>
 #include <utility>
@@ -72,9 +73,10 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
     k.p = w.take<C2<T>>(n);
     k.Ar = w.take<C2<T>>(n);
     k.Ap = w.take<C2<T>>(n);
-    k.part = w.take<double>(2 * (size_t)c.Nc + CCR_BLOCKS);
+    k.part = w.take<double>(2 * (size_t)c.Nc + 2 * CCR_BLOCKS);
     k.cs = w.take<double>(8);
     k.flags = w.take<int>(CCR_FLAGS);
+    k.dpart = w.take<double>((size_t)2 * DEFL_KMAX * DEFL_BLOCKS);
     return k;
 }
 template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
@@ -85,8 +87,11 @@ template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
 
 template <typename T>
 int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T>* b, C2<T>* x, int maxiter,
-              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters) {
-    launch_ccr_init<T>(c, b, x, w, maxiter, tol, s);
+              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters, const DeflView<T>* defl) {
+    if (defl)
+        launch_ccr_init_defl<T>(c, b, x, w, *defl, maxiter, tol, s);
+    else
+        launch_ccr_init<T>(c, b, x, w, maxiter, tol, s);
     launch_ccr_step<T>(c, A_dtype, A, x, w, true, s);
     if (tol <= 0) {
         for (int i = 0; i < maxiter; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
@@ -111,6 +116,15 @@ int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
 }
+
+template CoarseCRWork<double> coarse_cr_carve<double>(Carver&, const CoarseGeom&);
+template CoarseCRWork<float> coarse_cr_carve<float>(Carver&, const CoarseGeom&);
+template size_t coarse_cr_bytes<double>(const CoarseGeom&);
+template size_t coarse_cr_bytes<float>(const CoarseGeom&);
+template int coarse_cr<double>(const CoarseGeom&, hdcr_dtype, const void*, const double2*, double2*, int, double,
+                               const CoarseCRWork<double>&, int, hipStream_t, int*, const DeflView<double>*);
+template int coarse_cr<float>(const CoarseGeom&, hdcr_dtype, const void*, const float2*, float2*, int, double,
+                              const CoarseCRWork<float>&, int, hipStream_t, int*, const DeflView<float>*);
 
 // ---------------------------------------------------------------------------
 // Chebyshev smoother
@@ -232,8 +246,8 @@ struct CycleCounts {
 // `basis` (FP32 cycle only), or null
 template <typename T>
 int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, const C2<T>* basis, const uint32_t* bh,
-           const void* A, const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm, CycleCounts& cnt,
-           hipStream_t s) {
+           const void* A, const DeflView<T>* defl, const C2<T>* r, C2<T>* e, const CycleWork<T>& w, PhaseTimer& tm,
+           CycleCounts& cnt, hipStream_t s) {
     const FineGeom& g = c.f;
     const int order = prm->cheb_order;
     tm.begin(PhaseTimer::FINE);
@@ -250,7 +264,7 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     }
     int it = 0;
     int st = coarse_cr<T>(c, (hdcr_dtype)prm->coarse_dtype, A, w.vc, w.cx, prm->coarse_maxiter, prm->coarse_tol, w.ccr,
-                          cnt.last_coarse, s, &it);
+                          cnt.last_coarse, s, &it, defl);
     if (st) return st;
     cnt.last_coarse = it;
     cnt.coarse_iters += it;
@@ -322,8 +336,8 @@ template <typename T> size_t fgcr_bytes(const CoarseGeom& c, int m) {
 
 template <typename T>
 int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2* U, const void* basis, const void* A,
-               const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap, void* work,
-               size_t work_bytes, hipStream_t s) {
+               const DeflView<T>* defl, const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap,
+               void* work, size_t work_bytes, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const FineGeom& g = c.f;
     const int64_t n = 12LL * g.N5;
@@ -395,9 +409,9 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             if constexpr (sizeof(T) == 4) {
                 tm.begin(PhaseTimer::OUTER);
                 launch_convert<double2, float2>(n, w.r, w.r_in, s);
-                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r_in, w.Z[i], w.cyc, tm, cnt, s);
+                e = vcycle<T>(c, prm, Uin, bas, bh, A, defl, w.r_in, w.Z[i], w.cyc, tm, cnt, s);
             } else {
-                e = vcycle<T>(c, prm, Uin, bas, bh, A, w.r, w.Z[i], w.cyc, tm, cnt, s);
+                e = vcycle<T>(c, prm, Uin, bas, bh, A, defl, w.r, w.Z[i], w.cyc, tm, cnt, s);
             }
             if (e) return e;
             tm.begin(PhaseTimer::OUTER);
@@ -544,12 +558,33 @@ size_t two_level_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p
     return fgcr_bytes<double>(c, p->restart);
 }
 
+int check_deflation(const CoarseGeom& c, const hdcr_coarse_deflation* d, hdcr_dtype dtype, const char* where) {
+    (void)c;
+    const std::string w(where);
+    if (d->k < 1 || d->k > DEFL_KMAX)
+        return fail(HDCR_EINVAL, w + ": deflation k must be in [1, " + std::to_string(DEFL_KMAX) + "]");
+    if (d->dtype != dtype)
+        return fail(HDCR_EINVAL, w + ": deflation vectors must be C128 with an FP64 coarse solve, C64 with FP32");
+    if (!d->theta || !d->V || !d->W || (reinterpret_cast<uintptr_t>(d->theta) & 7) ||
+        (reinterpret_cast<uintptr_t>(d->V) & 7) || (reinterpret_cast<uintptr_t>(d->W) & 7))
+        return fail(HDCR_EINVAL, w + ": deflation theta, V and W must be non-null and 8-byte aligned");
+    return HDCR_OK;
+}
+
+template <typename T> DeflView<T> defl_view(const hdcr_coarse_deflation* d) {
+    return DeflView<T>{d->k, d->theta, static_cast<const C2<T>*>(d->V), static_cast<const C2<T>*>(d->W)};
+}
+
 int two_level_solve(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis,
-                    const void* A, const double2* b, double2* x, hdcr_solve_stats* st, double* history, int hcap,
-                    void* work, size_t work_bytes, hipStream_t s) {
-    if (p->inner_dtype == HDCR_C64)
-        return fgcr_solve<float>(c, p, U, basis, A, b, x, st, history, hcap, work, work_bytes, s);
-    return fgcr_solve<double>(c, p, U, basis, A, b, x, st, history, hcap, work, work_bytes, s);
+                    const void* A, const hdcr_coarse_deflation* defl, const double2* b, double2* x,
+                    hdcr_solve_stats* st, double* history, int hcap, void* work, size_t work_bytes, hipStream_t s) {
+    if (p->inner_dtype == HDCR_C64) {
+        const DeflView<float> dv = defl ? defl_view<float>(defl) : DeflView<float>{};
+        return fgcr_solve<float>(c, p, U, basis, A, defl ? &dv : nullptr, b, x, st, history, hcap, work, work_bytes,
+                                 s);
+    }
+    const DeflView<double> dv = defl ? defl_view<double>(defl) : DeflView<double>{};
+    return fgcr_solve<double>(c, p, U, basis, A, defl ? &dv : nullptr, b, x, st, history, hcap, work, work_bytes, s);
 }
 
 // one application of the two-level cycle on a C128 vector (inner precision from p)
@@ -568,7 +603,8 @@ size_t vcycle_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p) {
 }
 
 int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis, const void* A,
-                 const double2* r, double2* e, void* work, size_t work_bytes, hipStream_t s) {
+                 const hdcr_coarse_deflation* defl, const double2* r, double2* e, void* work, size_t work_bytes,
+                 hipStream_t s) {
     Carver w(work, work_bytes);
     PhaseTimer tm;
     CycleCounts cnt;
@@ -582,15 +618,17 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
         HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
         launch_convert<double2, float2>(36LL * c.f.V4, U, U32, s);
         launch_convert<double2, float2>(n, r, r32, s);
+        const DeflView<float> dv = defl ? defl_view<float>(defl) : DeflView<float>{};
         int st = vcycle<float>(c, p, U32, basis32(c, basis), p->basis_dtype == HDCR_F16C ? basis16(c, basis) : nullptr,
-                                A, r32, e32, cw, tm, cnt, s);
+                               A, defl ? &dv : nullptr, r32, e32, cw, tm, cnt, s);
         if (st) return st;
         launch_convert<float2, double2>(n, e32, e, s);
     } else {
         CycleWork<double> cw = cycle_carve<double>(w, c);
         if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
         HDCR_HIP_CHECK(hipMemsetAsync(cw.ccr.flags, 0, CCR_FLAGS * sizeof(int), s));
-        int st = vcycle<double>(c, p, U, basis64(basis), nullptr, A, r, e, cw, tm, cnt, s);
+        const DeflView<double> dv = defl ? defl_view<double>(defl) : DeflView<double>{};
+        int st = vcycle<double>(c, p, U, basis64(basis), nullptr, A, defl ? &dv : nullptr, r, e, cw, tm, cnt, s);
         if (st) return st;
     }
     HDCR_HIP_CHECK(hipGetLastError());
@@ -662,7 +700,8 @@ int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int
 }
 
 int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, const void* U, const void* basis,
-                const void* A, const void* r, void* e, void* work, size_t work_bytes, hipStream_t stream) {
+                const void* A, const hdcr_coarse_deflation* defl, const void* r, void* e, void* work,
+                size_t work_bytes, hipStream_t stream) {
     int st = check_coarse_desc(desc);
     if (st) return st;
     if (!params) return fail(HDCR_EINVAL, "hdcr_vcycle: null params");
@@ -671,9 +710,10 @@ int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, c
         (st = check_ptr(r, 16, "r")) || (st = check_ptr(e, 16, "e")) || (st = check_ptr(work, 256, "work")))
         return st;
     const CoarseGeom c = make_coarse_geom(desc);
+    if (defl && (st = check_deflation(c, defl, (hdcr_dtype)params->inner_dtype, "hdcr_vcycle"))) return st;
     if (work_bytes < vcycle_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
-    return vcycle_apply(c, params, (const double2*)U, basis, A, (const double2*)r, (double2*)e, work, work_bytes,
-                        stream);
+    return vcycle_apply(c, params, (const double2*)U, basis, A, defl, (const double2*)r, (double2*)e, work,
+                        work_bytes, stream);
 }
 
 size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_dtype dtype) {

@@ -54,6 +54,8 @@ int main(void) {
          offsetof(hdcr_solve_params, coarse_maxiter), offsetof(hdcr_solve_params, basis_dtype));
   printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
   printf("%zu\n", offsetof(hdcr_fine_desc, cayley_b));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(hdcr_coarse_deflation), offsetof(hdcr_coarse_deflation, theta),
+         offsetof(hdcr_coarse_deflation, W), sizeof(hdcr_deflation_params), offsetof(hdcr_deflation_params, cut));
   return 0;
 }
 ''')
@@ -65,7 +67,9 @@ int main(void) {
           ctypes.sizeof(_abi.SolveStats), _abi.FineDesc.M5.offset, _abi.CoarseDesc.nvec.offset,
           _abi.SolveParams.coarse_maxiter.offset, _abi.SolveParams.basis_dtype.offset,
           _abi.SolveStats.true_rel_residual.offset,
-          _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset]
+          _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset,
+          ctypes.sizeof(_abi.CoarseDeflation), _abi.CoarseDeflation.theta.offset, _abi.CoarseDeflation.W.offset,
+          ctypes.sizeof(_abi.DeflationParams), _abi.DeflationParams.cut.offset]
     assert vals == py
 
 
@@ -163,3 +167,56 @@ def test_two_level_param_validation(lib):
     assert hd.workspace_bytes(hd._abi.WS_SOLVE, hd.Lattice((4, 4, 4, 4), 5, block=(2, 2, 2, 2), nvec=4), good) == 0
     assert hd.workspace_bytes(hd._abi.WS_BUILD, hd.Lattice((4, 4, 4, 4), 4, block=(3, 2, 2, 2), nvec=4)) == 0
     assert hd.workspace_bytes(hd._abi.WS_BUILD, hd.Lattice((4, 4, 4, 4), 4, block=(2, 2, 2, 2), nvec=4)) > 0
+
+
+def test_deflation_argument_validation_before_launch(lib):
+    from paper_1611_06944_amd import Lattice, _abi
+    lat = Lattice((8, 8, 8, 8), 8, block=(4, 4, 4, 4), nvec=4)
+    cd = lat.coarse_desc()
+    n = lat.nc * lat.nb
+    A, v0, th = ctypes.c_void_p(1 << 32), ctypes.c_void_p(1 << 33), ctypes.c_void_p(1 << 34)
+    V, W, work = ctypes.c_void_p(1 << 35), ctypes.c_void_p(1 << 36), ctypes.c_void_p(1 << 37)
+    p = _abi.DeflationParams(4, 8, 10, 2, 10, 0, 0.05)
+    ws = lib.hdcr_deflation_workspace_bytes(ctypes.byref(cd), _abi.C128, ctypes.byref(p))
+    assert ws > 0
+    b = lib.hdcr_build_deflation
+
+    def call(dt=_abi.C128, prm=p, V_=V, W_=W, nbytes=ws):
+        return b(ctypes.byref(cd), dt, A, ctypes.byref(prm), v0, th, V_, W_, None, work, nbytes, None)
+
+    for bad in [_abi.DeflationParams(9, 8, 10, 2, 10, 0, 0.05),   # k > m
+                _abi.DeflationParams(4, 65, 10, 2, 10, 0, 0.05),  # m above the maximum
+                _abi.DeflationParams(4, 8, 0, 2, 10, 0, 0.05),    # degree
+                _abi.DeflationParams(4, 8, 10, 0, 10, 0, 0.05),   # iters
+                _abi.DeflationParams(4, 8, 10, 2, 10, 0, 1.0)]:   # cut
+        assert call(prm=bad) == _abi.HDCR_EINVAL
+        assert lib.hdcr_deflation_workspace_bytes(ctypes.byref(cd), _abi.C128, ctypes.byref(bad)) == 0
+    assert call(dt=_abi.F16C) == _abi.HDCR_EINVAL
+    assert call(W_=ctypes.c_void_p((1 << 35) + 16 * n)) == _abi.HDCR_EINVAL   # V and W overlap
+    assert b"overlap" in lib.hdcr_last_error()
+    assert call(nbytes=ws - 1) == _abi.HDCR_ENOMEM
+    # the FP32 build needs less scratch than the FP64 one
+    assert 0 < lib.hdcr_deflation_workspace_bytes(ctypes.byref(cd), _abi.BF16C, ctypes.byref(p)) < ws
+
+    cs = lib.hdcr_coarse_solve
+    bb, xx = ctypes.c_void_p(1 << 38), ctypes.c_void_p(1 << 39)
+    prm = _abi.SolveParams()
+    prm.coarse_dtype = _abi.C64
+    cws = lib.hdcr_workspace_bytes(_abi.WS_COARSE, ctypes.byref(cd), ctypes.byref(prm))
+    assert cws > 0
+    d = _abi.CoarseDeflation(4, _abi.C64, th.value, V.value, W.value)
+    it = ctypes.c_int32(0)
+    assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, bb, 10, 0.0, ctypes.byref(it), work, cws,
+              None) == _abi.HDCR_EINVAL                                                    # b and x overlap
+    d.dtype = _abi.C128
+    assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, xx, 10, 0.0, ctypes.byref(it), work, cws,
+              None) == _abi.HDCR_EINVAL                                                    # vector precision
+    d.dtype, d.k = _abi.C64, 0
+    assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, xx, 10, 0.0, ctypes.byref(it), work, cws,
+              None) == _abi.HDCR_EINVAL
+    assert b"deflation" in lib.hdcr_last_error()
+    d.k = 4
+    assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, xx, -1, 0.0, ctypes.byref(it), work, cws,
+              None) == _abi.HDCR_EINVAL
+    assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, xx, 10, 0.0, ctypes.byref(it), work, cws - 1,
+              None) == _abi.HDCR_ENOMEM
