@@ -166,15 +166,29 @@ def _check_fields(lat: Lattice, U, *fields):
 # ----------------------------------------------------------------------------
 
 def apply_fine(lat: Lattice, U, psi, out=None, stream=None):
-    """out = H psi, H = Gamma5 D_dwf (one HIP kernel launch)."""
+    """out = H psi, H = Gamma5 D_dwf (one HIP kernel launch).
+
+    psi may also be an FP16-stored field: a float16 tensor [12, V4, Ls, 2] of (re, im)
+    pairs, with complex64 links (FP32 arithmetic; Ls = 16 and even extents)."""
     torch = _torch()
     lib = load()
-    _check_fields(lat, U, psi)
-    if out is None:
-        out = torch.empty_like(psi)
-    _check_fields(lat, U, out)
+    if psi.dtype == torch.float16:
+        if U.dtype != torch.complex64 or U.numel() != 36 * lat.V4:
+            raise TypeError("FP16 fields take complex64 links of 36*V4 entries")
+        if out is None:
+            out = torch.empty_like(psi)
+        for f in (psi, out):
+            if f.dtype != torch.float16 or f.numel() != 24 * lat.N5:
+                raise ValueError(f"FP16 field must be float16 with 24*V4*Ls = {24 * lat.N5} entries")
+        code = F16C
+    else:
+        _check_fields(lat, U, psi)
+        if out is None:
+            out = torch.empty_like(psi)
+        _check_fields(lat, U, out)
+        code = _dtype_code(psi)
     d = lat.fine_desc()
-    _abi.check(lib.hdcr_apply_fine(ctypes.byref(d), _dtype_code(psi), _ptr(U), _ptr(psi), _ptr(out), _stream(stream)),
+    _abi.check(lib.hdcr_apply_fine(ctypes.byref(d), code, _ptr(U), _ptr(psi), _ptr(out), _stream(stream)),
                "hdcr_apply_fine")
     return out
 
@@ -406,15 +420,23 @@ def tune_coarse_batched(lat: Lattice, A, v, out=None, stream=None):
 # smoother, two-level cycle, subspace filter
 # ----------------------------------------------------------------------------
 
-def smooth(lat: Lattice, U, x, order=10, lo=1.0, hi=64.0, out=None, work=None, stream=None):
-    """out = p(H^2) H x (Chebyshev smoother); precision of x (U in the same precision)."""
+def smooth(lat: Lattice, U, x, order=10, lo=1.0, hi=64.0, out=None, work=None, stream=None, f16: bool = False):
+    """out = p(H^2) H x (Chebyshev smoother); precision of x (U in the same precision).
+    f16: complex64 x, U and out, with the smoother's own fields stored in FP16."""
     torch = _torch()
+    _check_fields(lat, U, x)
     if out is None:
         out = torch.empty_like(x)
+    _check_fields(lat, U, out)
     if work is None:
         work = _workspace(workspace_bytes(_abi.WS_SMOOTH, lat), x.device)
+    code = _dtype_code(x)
+    if f16:
+        if code != C64:
+            raise TypeError("the FP16-storage smoother takes complex64 fields")
+        code = F16C
     d = lat.fine_desc()
-    _abi.check(load().hdcr_smooth(ctypes.byref(d), _dtype_code(x), _ptr(U), int(order), float(lo), float(hi), _ptr(x),
+    _abi.check(load().hdcr_smooth(ctypes.byref(d), code, _ptr(U), int(order), float(lo), float(hi), _ptr(x),
                                   _ptr(out), _ptr(work), work.numel(), _stream(stream)), "hdcr_smooth")
     return out
 

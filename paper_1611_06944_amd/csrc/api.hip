@@ -122,13 +122,19 @@ int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U,
                     hipStream_t stream) {
     int e = check_fine_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_apply_fine: dtype must be C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_apply_fine: dtype must be C128, C64 or F16C");
     const size_t cs = csize(dtype);
-    if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(psi, cs, "psi")) || (e = check_ptr(out, cs, "out"))) return e;
+    const size_t us = dtype == HDCR_F16C ? 8 : cs;  // F16C fields take C64 links
+    if ((e = check_ptr(U, us, "U")) || (e = check_ptr(psi, cs, "psi")) || (e = check_ptr(out, cs, "out"))) return e;
     const FineGeom g = make_geom(desc);
     const size_t fbytes = (size_t)12 * g.N5 * cs;
     if (overlap(psi, fbytes, out, fbytes)) return fail(HDCR_EINVAL, "hdcr_apply_fine: psi and out overlap");
-    if (dtype == HDCR_C128)
+    if (dtype == HDCR_F16C) {
+        if (!dslash_h16_ok(g)) return fail(HDCR_EINVAL, "hdcr_apply_fine: F16C needs Ls = 16 and even extents");
+        launch_dslash_h16(g, (const float2*)U, psi, out,
+                          Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0}, stream);
+    } else if (dtype == HDCR_C128)
         launch_dslash<double>(g, (const double2*)U, (const double2*)psi, (double2*)out, stream);
     else
         launch_dslash<float>(g, (const float2*)U, (const float2*)psi, (float2*)out, stream);
@@ -251,7 +257,10 @@ int hdcr_solve(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, co
     if ((e = check_two_level_params(params))) return e;
     if ((e = check_ptr(basis, 16, "basis")) || (e = check_ptr(A, 4, "A"))) return e;
     const CoarseGeom c = make_coarse_geom(desc);
-    if (defl && (e = check_deflation(c, defl, (hdcr_dtype)params->inner_dtype, "hdcr_solve"))) return e;
+    if (params->inner_dtype == HDCR_F16C && !dslash_h16_ok(c.f))
+        return fail(HDCR_EINVAL, "hdcr_solve: inner F16C needs Ls = 16 and even extents");
+    if (defl && (e = check_deflation(c, defl, params->inner_dtype == HDCR_C128 ? HDCR_C128 : HDCR_C64, "hdcr_solve")))
+        return e;
     if (work_bytes < two_level_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_solve: workspace too small");
     return two_level_solve(c, params, (const double2*)U, basis, A, defl, (const double2*)b, (double2*)x, stats,
                            history, history_cap, work, work_bytes, stream);

@@ -470,12 +470,37 @@ __device__ __forceinline__ void st_pair_nt(float4 v, __amdgpu_buffer_rsrc_t r, u
     store_b128<CPOL_NT>(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, voff, soff);
 }
 
-template <int NY>
-__global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGeom tg, const float2* U,
+// FP16 field storage (H16): a complex entry is (fp16 re, fp16 im) in 4 bytes,
+// a slice pair one 8-byte access; conversion to FP32 on load, round to nearest
+// on store.  The staged tile, the links and the arithmetic stay FP32.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef unsigned uint2_t __attribute__((ext_vector_type(2)));
+template <bool H16>
+__device__ __forceinline__ float4 ld_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (H16) {
+        const half4_t h = __builtin_bit_cast(half4_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+    } else {
+        return ld_pair(r, voff, soff);
+    }
+}
+template <bool H16>
+__device__ __forceinline__ void st_pair_s_nt(float4 v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (H16) {
+        const half4_t h = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(uint2_t, h), r, voff + soff, 0, CPOL_NT);
+    } else {
+        st_pair_nt(v, r, voff, soff);
+    }
+}
+
+template <int NY, bool H16>
+__global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2))) dslash_par2_kernel(FineGeom g, TileGeom tg, const float2* U,
                                                                const float2* in, float2* out, Epi<float> ep) {
     typedef float T;
     constexpr int LS = 16, NK = LS / 2;
-    constexpr uint32_t CB = sizeof(float2);
+    constexpr uint32_t CB = H16 ? 4u : (uint32_t)sizeof(float2);  // bytes per complex entry of a field
+    constexpr uint32_t UB = sizeof(float2);                         // bytes per complex entry of a link
     __shared__ float4 spin[12 * 16 * NK];   // [c][pattern][k]: slices 2k, 2k+1
     __shared__ float2 lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
     const int p = threadIdx.x >> 3, k = threadIdx.x & 7;
@@ -491,7 +516,7 @@ __global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGe
     f.cstride = (uint32_t)g.N5 * CB;
     f.in = make_rsrc(in, 12u * f.cstride);
     f.out = make_rsrc(out, 12u * f.cstride);
-    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * (uint32_t)sizeof(float2));
     // LDS matrix 2 mu: the hop of direction mu inside the tile, 2 mu + 1: the
     // one leaving it (backward matrices stored conjugate-transposed)
     for (int e = k; e < 9; e += NK) {
@@ -499,8 +524,8 @@ __global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGe
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
             const bool up = (p >> mu) & 1;
-            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + e) * CB, 0u);
-            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + e) * CB, 0u);
+            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + e) * UB, 0u);
+            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + e) * UB, 0u);
             lds[(p * 8 + 2 * mu + (up ? 1 : 0)) * LPAD + e] = uf;
             lds[(p * 8 + 2 * mu + (up ? 0 : 1)) * LPAD + cc * 3 + r] = mk<T>(ub.x, -ub.y);
         }
@@ -510,7 +535,7 @@ __global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGe
         const uint32_t o0 = (uint32_t)(st.site * LS + s0) * CB;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const float4 q = ld_pair(f.in, o0, (uint32_t)c * f.cstride);
+            const float4 q = ld_pair_s<H16>(f.in, o0, (uint32_t)c * f.cstride);
             v0[c] = mk<T>(q.x, q.y);
             v1[c] = mk<T>(q.z, q.w);
             spin[(c * 16 + p) * NK + k] = q;
@@ -559,7 +584,7 @@ __global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGe
         _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU + 1) * LPAD + e];                    \
         const uint32_t noff = (uint32_t)((up ? n.f[MU] : n.b[MU]) * LS + s0) * CB;                            \
         _Pragma("unroll") for (int c = 0; c < 12; ++c) {                                                      \
-            const float4 w = ld_pair(f.in, noff, (uint32_t)c * f.cstride);                                    \
+            const float4 w = ld_pair_s<H16>(f.in, noff, (uint32_t)c * f.cstride);                                    \
             v0[c] = mk<T>(w.x, w.y);                                                                          \
             v1[c] = mk<T>(w.z, w.w);                                                                          \
         }                                                                                                     \
@@ -586,12 +611,12 @@ __global__ void __launch_bounds__(PAR2_WG) dslash_par2_kernel(FineGeom g, TileGe
             hi = cscale<T>(ep.beta, hi);
 #pragma unroll
             for (int i = 0; i < NY; ++i) {
-                const float4 y = ld_pair(yr[i], oo, (uint32_t)c * f.cstride);
+                const float4 y = ld_pair_s<H16>(yr[i], oo, (uint32_t)c * f.cstride);
                 axpy<T>(ep.g[i], mk<T>(y.x, y.y), lo);
                 axpy<T>(ep.g[i], mk<T>(y.z, y.w), hi);
             }
         }
-        st_pair_nt(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)c * f.cstride);
+        st_pair_s_nt<H16>(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)c * f.cstride);
     }
 }
 
@@ -722,8 +747,8 @@ void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, c
         const TileGeom tg = tile_geom(g);
         if constexpr (sizeof(T) == 4) {
             if (g.variant == 0) {
-                hipLaunchKernelGGL((dslash_par2_kernel<NY>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, in, out,
-                                   ep);
+                hipLaunchKernelGGL((dslash_par2_kernel<NY, false>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, in,
+                                   out, ep);
                 return;
             }
         }
@@ -758,6 +783,24 @@ void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>
         default: launch_ny<T, 0>(g, U, in, out, e, s); break;
     }
 }
+
+bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void* out, const Epi<float>& e,
+                       hipStream_t s) {
+    if (!par_ok(g) || e.ny < 0 || e.ny > 4) return false;
+    const TileGeom tg = tile_geom(g);
+    const float2* x = static_cast<const float2*>(in);
+    float2* y = static_cast<float2*>(out);
+    switch (e.ny) {
+        case 0: hipLaunchKernelGGL((dslash_par2_kernel<0, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
+        case 1: hipLaunchKernelGGL((dslash_par2_kernel<1, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
+        case 2: hipLaunchKernelGGL((dslash_par2_kernel<2, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
+        case 3: hipLaunchKernelGGL((dslash_par2_kernel<3, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
+        default: hipLaunchKernelGGL((dslash_par2_kernel<4, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
+    }
+    return true;
+}
+
+bool dslash_h16_ok(const FineGeom& g) { return par_ok(g); }
 
 void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
                          hipStream_t s) {

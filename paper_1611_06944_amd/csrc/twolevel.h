@@ -43,11 +43,18 @@ int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T
               double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters,
               const DeflView<T>* defl = nullptr);
 
-// Chebyshev smoother acc = p(H^2) H in, p the order-term Chebyshev interpolant
+// Chebyshev smoother out (+)= p(H^2) H in, p the order-term Chebyshev interpolant
 // of 1/y on [lo, hi] (Sec. 4); tmp: 4 fine vectors of precision T.
 template <typename T>
-void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* acc, C2<T>* const tmp[4], int order,
-                   double lo, double hi, hipStream_t s);
+void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, bool accumulate,
+                   C2<T>* const tmp[4], int order, double lo, double hi, hipStream_t s);
+// The same with FP16 storage of the smoother's fields (Ls = 16, even extents,
+// order >= 2): in is scaled to unit RMS per entry and rounded to FP16 (the
+// smoother is linear), the recurrence runs through the FP16-storage stencil,
+// and the result is scaled back into the FP32 out.  h: five FP16 fields of
+// 12 N5 entries (4 bytes each); part: REDUCE_BLOCKS doubles; S: one double.
+void cheb_smoother_h16(const FineGeom& g, const float2* U, const float2* in, float2* out, bool accumulate,
+                       void* const h[5], double* part, double* S, int order, double lo, double hi, hipStream_t s);
 
 void cheby_coeffs(int n, double lo, double hi, double* c);
 

@@ -144,6 +144,34 @@ void cheby_coeffs(int n, double lo, double hi, double* c) {
     }
 }
 
+// Stencil operations of the smoother on fields of precision T.
+template <typename T> struct SmootherOps {
+    const FineGeom& g;
+    const C2<T>* U;
+    hipStream_t s;
+    void apply(const C2<T>* a, C2<T>* b) const { launch_dslash<T>(g, U, a, b, s); }
+    void epi(const C2<T>* a, C2<T>* b, const Epi<T>& e) const { launch_dslash_epi<T>(g, U, a, b, e, s); }
+    void scale_u(const C2<T>* u, double c0, C2<T>* out, bool accumulate) const {
+        const int64_t n = 12LL * g.N5;
+        if (accumulate)
+            launch_axpby<T>(n, (T)c0, u, (T)1, out, s);
+        else
+            launch_scale<T>(n, (T)c0, u, out, s);
+    }
+};
+// The same on FP16-stored fields (the float2 pointers address (fp16 re, fp16 im)
+// entries; FP32 links and arithmetic).  Needs at least two Chebyshev terms.
+struct SmootherOpsH16 {
+    const FineGeom& g;
+    const float2* U;
+    hipStream_t s;
+    void apply(const float2* a, float2* b) const {
+        launch_dslash_h16(g, U, a, b, Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0}, s);
+    }
+    void epi(const float2* a, float2* b, const Epi<float>& e) const { launch_dslash_h16(g, U, a, b, e, s); }
+    void scale_u(const float2*, double, float2*, bool) const {}
+};
+
 // out = p(H^2) H in   (accumulate: out += p(H^2) H in), with
 // p(y) = sum_{j<n} c'_j T_j(yhat), c'_0 = c_0 / 2, c'_j = c_j, yhat = a1 y + b1,
 // evaluated by Clenshaw's recurrence on u = H in:
@@ -151,11 +179,11 @@ void cheby_coeffs(int n, double lo, double hi, double* c) {
 //   result = c'_0 u + yhat b_1 - b_2,
 // where yhat b = a1 H (H b) + b1 b.  Each step's second stencil application
 // carries the combination in its epilogue, so a step costs two stencil passes
-// and no separate vector pass.  tmp: four fields (u, V, and two b_k).
-template <typename T>
-void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, bool accumulate,
-                   C2<T>* const tmp[4], int order, double lo, double hi, hipStream_t s) {
-    const int64_t n = 12LL * g.N5;
+// and no separate vector pass.  tmp: four fields (u, V, and two b_k); `in` is
+// read only by the first stencil pass.
+template <typename T, typename Ops>
+void clenshaw(const Ops& ops, const C2<T>* in, C2<T>* out, bool accumulate, C2<T>* const tmp[4], int order,
+              double lo, double hi) {
     const int nc = order;
     std::vector<double> c(nc);
     cheby_coeffs(nc, lo, hi, c.data());
@@ -165,12 +193,9 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
     C2<T>* V = tmp[1];
     C2<T>* bk1 = tmp[2];  // b_{k+1}
     C2<T>* bk2 = tmp[3];  // b_{k+2}, overwritten in place by b_k
-    launch_dslash<T>(g, U, in, u, s);
+    ops.apply(in, u);
     if (nc == 1) {
-        if (accumulate)
-            launch_axpby<T>(n, (T)c[0], u, (T)1, out, s);
-        else
-            launch_scale<T>(n, (T)c[0], u, out, s);
+        ops.scale_u(u, c[0], out, accumulate);
         return;
     }
     auto epi = [&](const C2<T>* src, C2<T>* dst, double beta, std::initializer_list<std::pair<const C2<T>*, double>> ys,
@@ -186,9 +211,9 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
             e.g[e.ny] = (T)1;
             ++e.ny;
         }
-        launch_dslash_epi<T>(g, U, src, dst, e, s);
+        ops.epi(src, dst, e);
     };
-    launch_dslash<T>(g, U, u, V, s);
+    ops.apply(u, V);
     if (nc == 2) {
         // result = c'_0 u + yhat (c'_1 u) = (c'_0 + b1 c'_1) u + a1 c'_1 H H u
         epi(V, out, a1 * c[1], {{u, c[0] + b1 * c[1]}}, accumulate);
@@ -198,7 +223,7 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
     epi(V, bk1, 2 * a1 * c[nc - 1], {{u, c[nc - 2] + 2 * b1 * c[nc - 1]}}, false);
     bool implicit2 = true;  // b_{k+2} = b_{n-1} = c'_{n-1} u is not stored
     for (int k = nc - 3; k >= 1; --k) {
-        launch_dslash<T>(g, U, bk1, V, s);
+        ops.apply(bk1, V);
         if (implicit2)
             epi(V, bk2, 2 * a1, {{u, c[k] - c[nc - 1]}, {bk1, 2 * b1}}, false);
         else
@@ -206,11 +231,30 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
         implicit2 = false;
         std::swap(bk1, bk2);
     }
-    launch_dslash<T>(g, U, bk1, V, s);
+    ops.apply(bk1, V);
     if (implicit2)
         epi(V, out, a1, {{u, c[0] - c[nc - 1]}, {bk1, b1}}, accumulate);
     else
         epi(V, out, a1, {{u, c[0]}, {bk1, b1}, {bk2, -1.0}}, accumulate);
+}
+
+template <typename T>
+void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, bool accumulate,
+                   C2<T>* const tmp[4], int order, double lo, double hi, hipStream_t s) {
+    clenshaw<T>(SmootherOps<T>{g, U, s}, in, out, accumulate, tmp, order, lo, hi);
+}
+
+void cheb_smoother_h16(const FineGeom& g, const float2* U, const float2* in, float2* out, bool accumulate,
+                       void* const h[5], double* part, double* S, int order, double lo, double hi, hipStream_t s) {
+    const int64_t n = 12LL * g.N5;
+    float2* hb[5];
+    for (int i = 0; i < 5; ++i) hb[i] = static_cast<float2*>(h[i]);
+    launch_norm2<float>(n, in, part, S, 0, s);
+    launch_to_h16_scaled(n, in, S, 0, hb[0], s);
+    float2* const tmp[4] = {hb[1], hb[2], hb[3], hb[4]};
+    // hb[0] holds the scaled input for the first pass and then the result
+    clenshaw<float>(SmootherOpsH16{g, U, s}, hb[0], hb[0], false, tmp, order, lo, hi);
+    launch_from_h16_scaled(n, hb[0], S, 0, out, accumulate, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -223,6 +267,9 @@ template <typename T> struct CycleWork {
     C2<T>* vc;
     C2<T>* cx;
     CoarseCRWork<T> ccr;
+    void* h16[5];   // FP16 smoother fields (inside sm[0..2], FP32 cycle only)
+    double* hpart;  // reduction scratch of the FP16 smoother
+    double* hS;
 };
 template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
     const size_t n = (size_t)12 * c.f.N5;
@@ -233,6 +280,10 @@ template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
     k.vc = w.take<C2<T>>((size_t)c.Nc * c.Nb);
     k.cx = w.take<C2<T>>((size_t)c.Nc * c.Nb);
     k.ccr = coarse_cr_carve<T>(w, c);
+    for (int j = 0; j < 5; ++j)
+        k.h16[j] = k.sm[j / 2] ? static_cast<void*>(reinterpret_cast<char*>(k.sm[j / 2]) + (j % 2) * n * 4) : nullptr;
+    k.hpart = w.take<double>(REDUCE_BLOCKS);
+    k.hS = w.take<double>(8);
     return k;
 }
 
@@ -251,7 +302,17 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     const FineGeom& g = c.f;
     const int order = prm->cheb_order;
     tm.begin(PhaseTimer::FINE);
-    cheb_smoother<T>(g, U, r, e, false, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    const bool h16 = sizeof(T) == 4 && prm->inner_dtype == HDCR_F16C;
+    auto smooth = [&](const C2<T>* in, C2<T>* out, bool acc) {
+        if constexpr (sizeof(T) == 4) {
+            if (h16) {
+                cheb_smoother_h16(g, U, in, out, acc, w.h16, w.hpart, w.hS, order, prm->cheb_lo, prm->cheb_hi, s);
+                return;
+            }
+        }
+        cheb_smoother<T>(g, U, in, out, acc, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    };
+    smooth(r, e, false);
     launch_dslash<T>(g, U, e, w.t, s);
     tm.begin(PhaseTimer::COARSE);
     if constexpr (sizeof(T) == 4) {
@@ -280,7 +341,7 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     tm.begin(PhaseTimer::FINE);
     // d = r - H e2 (fused), e = e2 + S d
     launch_dslash_epi<T>(g, U, e, w.d, Epi<T>{{r, nullptr, nullptr, nullptr}, {(T)1, 0, 0, 0}, (T)-1, 1}, s);
-    cheb_smoother<T>(g, U, w.d, e, true, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
+    smooth(w.d, e, true);
     cnt.fine += 2 * (2 * order - 1) + 2;
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
@@ -540,21 +601,23 @@ int check_two_level_params(const hdcr_solve_params* p) {
     if (p->coarse_maxiter < 0) return fail(HDCR_EINVAL, "coarse_maxiter must be >= 0");
     if (p->inner_dtype == HDCR_C128) {
         if (p->coarse_dtype != HDCR_C128) return fail(HDCR_EINVAL, "inner C128 needs coarse_dtype C128");
-    } else if (p->inner_dtype == HDCR_C64) {
+    } else if (p->inner_dtype == HDCR_C64 || p->inner_dtype == HDCR_F16C) {
         if (p->coarse_dtype != HDCR_C64 && p->coarse_dtype != HDCR_BF16C)
-            return fail(HDCR_EINVAL, "inner C64 needs coarse_dtype C64 or BF16C");
+            return fail(HDCR_EINVAL, "inner C64 / F16C needs coarse_dtype C64 or BF16C");
+        if (p->inner_dtype == HDCR_F16C && p->cheb_order < 2)
+            return fail(HDCR_EINVAL, "inner F16C needs cheb_order >= 2");
     } else {
-        return fail(HDCR_EINVAL, "inner_dtype must be C128 or C64");
+        return fail(HDCR_EINVAL, "inner_dtype must be C128, C64 or F16C");
     }
-    if (p->basis_dtype == HDCR_F16C && p->inner_dtype != HDCR_C64)
-        return fail(HDCR_EINVAL, "basis_dtype F16C needs inner_dtype C64");
+    if (p->basis_dtype == HDCR_F16C && p->inner_dtype == HDCR_C128)
+        return fail(HDCR_EINVAL, "basis_dtype F16C needs an FP32 cycle (inner_dtype C64 or F16C)");
     if (p->basis_dtype != HDCR_F16C && p->basis_dtype != HDCR_C64 && p->basis_dtype != HDCR_C128)
         return fail(HDCR_EINVAL, "basis_dtype must be C128, C64 or F16C");
     return HDCR_OK;
 }
 
 size_t two_level_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p) {
-    if (p->inner_dtype == HDCR_C64) return fgcr_bytes<float>(c, p->restart);
+    if (p->inner_dtype != HDCR_C128) return fgcr_bytes<float>(c, p->restart);
     return fgcr_bytes<double>(c, p->restart);
 }
 
@@ -578,7 +641,7 @@ template <typename T> DeflView<T> defl_view(const hdcr_coarse_deflation* d) {
 int two_level_solve(const CoarseGeom& c, const hdcr_solve_params* p, const double2* U, const void* basis,
                     const void* A, const hdcr_coarse_deflation* defl, const double2* b, double2* x,
                     hdcr_solve_stats* st, double* history, int hcap, void* work, size_t work_bytes, hipStream_t s) {
-    if (p->inner_dtype == HDCR_C64) {
+    if (p->inner_dtype != HDCR_C128) {
         const DeflView<float> dv = defl ? defl_view<float>(defl) : DeflView<float>{};
         return fgcr_solve<float>(c, p, U, basis, A, defl ? &dv : nullptr, b, x, st, history, hcap, work, work_bytes,
                                  s);
@@ -591,7 +654,7 @@ int two_level_solve(const CoarseGeom& c, const hdcr_solve_params* p, const doubl
 size_t vcycle_workspace_bytes(const CoarseGeom& c, const hdcr_solve_params* p) {
     Carver w(nullptr, 0);
     const size_t n = (size_t)12 * c.f.N5;
-    if (p->inner_dtype == HDCR_C64) {
+    if (p->inner_dtype != HDCR_C128) {
         w.take<float2>((size_t)36 * c.f.V4);
         w.take<float2>(n);
         w.take<float2>(n);
@@ -609,7 +672,7 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
     PhaseTimer tm;
     CycleCounts cnt;
     const int64_t n = 12LL * c.f.N5;
-    if (p->inner_dtype == HDCR_C64) {
+    if (p->inner_dtype != HDCR_C128) {
         float2* U32 = w.take<float2>((size_t)36 * c.f.V4);
         float2* r32 = w.take<float2>(n);
         float2* e32 = w.take<float2>(n);
@@ -676,9 +739,10 @@ int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int
                 const void* in, void* out, void* work, size_t work_bytes, hipStream_t stream) {
     int e = check_fine_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_smooth: dtype C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_smooth: dtype C128, C64 or F16C");
     if (order < 1 || order > 1000 || !(lo > 0) || !(hi > lo)) return fail(HDCR_EINVAL, "hdcr_smooth: bad polynomial");
-    const size_t cs = dtype == HDCR_C128 ? 16 : 8;
+    const size_t cs = dtype == HDCR_C128 ? 16 : 8;  // F16C: U, in and out are C64
     if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(in, cs, "in")) || (e = check_ptr(out, cs, "out")) ||
         (e = check_ptr(work, 256, "work")))
         return e;
@@ -686,7 +750,18 @@ int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int
     const size_t n = (size_t)12 * g.N5;
     if (work_bytes < 4 * n * cs + 4 * 256) return fail(HDCR_ENOMEM, "hdcr_smooth: workspace too small");
     Carver w(work, work_bytes);
-    if (dtype == HDCR_C128) {
+    if (dtype == HDCR_F16C) {
+        if (!dslash_h16_ok(g)) return fail(HDCR_EINVAL, "hdcr_smooth: F16C needs Ls = 16 and even extents");
+        if (order < 2) return fail(HDCR_EINVAL, "hdcr_smooth: F16C needs order >= 2");
+        if (overlap(in, n * cs, out, n * cs)) return fail(HDCR_EINVAL, "hdcr_smooth: in and out overlap");
+        void* h[5];
+        for (int i = 0; i < 5; ++i) h[i] = w.take<uint32_t>(n);
+        double* part = w.take<double>(REDUCE_BLOCKS);
+        double* S = w.take<double>(8);
+        if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_smooth: workspace too small");
+        cheb_smoother_h16(g, (const float2*)U, (const float2*)in, (float2*)out, false, h, part, S, order, lo, hi,
+                          stream);
+    } else if (dtype == HDCR_C128) {
         double2* tmp[4];
         for (int i = 0; i < 4; ++i) tmp[i] = w.take<double2>(n);
         cheb_smoother<double>(g, (const double2*)U, (const double2*)in, (double2*)out, false, tmp, order, lo, hi, stream);
@@ -710,7 +785,11 @@ int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* params, c
         (st = check_ptr(r, 16, "r")) || (st = check_ptr(e, 16, "e")) || (st = check_ptr(work, 256, "work")))
         return st;
     const CoarseGeom c = make_coarse_geom(desc);
-    if (defl && (st = check_deflation(c, defl, (hdcr_dtype)params->inner_dtype, "hdcr_vcycle"))) return st;
+    if (params->inner_dtype == HDCR_F16C && !dslash_h16_ok(c.f))
+        return fail(HDCR_EINVAL, "hdcr_vcycle: inner F16C needs Ls = 16 and even extents");
+    if (defl && (st = check_deflation(c, defl, params->inner_dtype == HDCR_C128 ? HDCR_C128 : HDCR_C64,
+                                      "hdcr_vcycle")))
+        return st;
     if (work_bytes < vcycle_workspace_bytes(c, params)) return fail(HDCR_ENOMEM, "hdcr_vcycle: workspace too small");
     return vcycle_apply(c, params, (const double2*)U, basis, A, defl, (const double2*)r, (double2*)e, work,
                         work_bytes, stream);

@@ -36,6 +36,14 @@ template <typename TV>
 void launch_r_update(int64_t n, const double* S, int ic, int inn, const C2<TV>* w, double2* r, double* part,
                      hipStream_t s);
 
+// FP16 field storage, (fp16 re, fp16 im) per complex entry: y = fp16(f x) with
+// f = sqrt(n / S[idx]), so that y has unit RMS per entry (f = 0 when S[idx] = 0;
+// S[idx] = |x|^2 from launch_norm2), and back: out = float(y) / f (+ out when
+// accumulate).  Rounding to nearest.
+void launch_to_h16_scaled(int64_t n, const float2* x, const double* S, int idx, void* y, hipStream_t s);
+void launch_from_h16_scaled(int64_t n, const void* y, const double* S, int idx, float2* out, bool accumulate,
+                            hipStream_t s);
+
 // S[idx] = |x|^2 (FP64 accumulation, fixed order); part: REDUCE_BLOCKS doubles
 template <typename T> void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s);
 // x <- x / sqrt(S[idx])

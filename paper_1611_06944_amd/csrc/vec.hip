@@ -186,7 +186,46 @@ __global__ void __launch_bounds__(VWG) scale_inv_sqrt_kernel(int64_t n, C2<T>* _
     }
 }
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__global__ void __launch_bounds__(VWG) to_h16_scaled_kernel(int64_t n, const float2* __restrict__ x,
+                                                            const double* __restrict__ S, int idx,
+                                                            uint32_t* __restrict__ y) {
+    const double nn = S[idx];
+    const float f = nn > 0.0 ? (float)sqrt((double)n / nn) : 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const float2 v = x[i];
+        const half2_t h = {(_Float16)(f * v.x), (_Float16)(f * v.y)};
+        y[i] = __builtin_bit_cast(uint32_t, h);
+    }
+}
+
+__global__ void __launch_bounds__(VWG) from_h16_scaled_kernel(int64_t n, const uint32_t* __restrict__ y,
+                                                              const double* __restrict__ S, int idx,
+                                                              float2* __restrict__ out, int accumulate) {
+    const float f = (float)sqrt(S[idx] / (double)n);
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const half2_t h = __builtin_bit_cast(half2_t, y[i]);
+        float2 o = make_float2(f * (float)h.x, f * (float)h.y);
+        if (accumulate) {
+            const float2 a = out[i];
+            o.x += a.x;
+            o.y += a.y;
+        }
+        out[i] = o;
+    }
+}
+
 }  // namespace
+
+void launch_to_h16_scaled(int64_t n, const float2* x, const double* S, int idx, void* y, hipStream_t s) {
+    hipLaunchKernelGGL(to_h16_scaled_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, x, S, idx, static_cast<uint32_t*>(y));
+}
+void launch_from_h16_scaled(int64_t n, const void* y, const double* S, int idx, float2* out, bool accumulate,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(from_h16_scaled_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, static_cast<const uint32_t*>(y), S,
+                       idx, out, accumulate ? 1 : 0);
+}
 
 template <typename T>
 void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s) {
