@@ -70,14 +70,16 @@ def parse():
     ap.add_argument("--defl-m", type=int, default=64, help="coarse deflation: block size of the set-up")
     ap.add_argument("--defl-degree", type=int, default=60)
     ap.add_argument("--defl-iters", type=int, default=5)
+    ap.add_argument("--defl-only", action="store_true",
+                    help="only the set-up and the deflated HDCR solve (profiling runs)")
     return ap.parse_args()
 
 
 # HBM traffic of the FP32 fine apply at 24^4 x 16 from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy), for the stencil sources (fine.hip and the
 # shared header) with this sha256; reported as null for any other source or lattice.
-MEASURED_TRAFFIC = {"stencil_sha256": "c78539722dcc3595d17c71401ba6ec8fc34983dfca18dce392b7d6bd10cd952e",
-                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2210009235,
+MEASURED_TRAFFIC = {"stencil_sha256": "0d1d31ca76ccb24487ebfe93ee1019e32a43b9e579e22df6f968e418a46b27d5",
+                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 2210418538,
                     "summary": "profiles/dslash_fine_24x24x24x24x16_traffic.md"}
 
 
@@ -209,7 +211,11 @@ def main():
     U32 = U64.to(torch.complex64)
     sweep = {"c128": (U64, [b64.clone() for _ in range(2)], [torch.empty_like(b64) for _ in range(2)]),
              "c64": (U32, [b64.to(torch.complex64) for _ in range(2)],
-                     [torch.empty(b64.shape, dtype=torch.complex64, device=dev) for _ in range(2)])}
+                     [torch.empty(b64.shape, dtype=torch.complex64, device=dev) for _ in range(2)]),
+             # FP16 field storage (fp16 re, fp16 im), FP32 links
+             "f16": (U32, [torch.view_as_real(b64.to(torch.complex64)).to(torch.float16).contiguous()
+                           for _ in range(2)],
+                     [torch.empty(b64.shape + (2,), dtype=torch.float16, device=dev) for _ in range(2)])}
     torch.cuda.synchronize()
     progress(f"inputs on device ({time.perf_counter() - t_in:.1f} s, plaquette {plaq:.6f})")
     stream = torch.cuda.current_stream()
@@ -274,6 +280,7 @@ def main():
             res["cr_wall"] = time.perf_counter() - t
         res["ev32"] = fine_sweep("c64", args.applies)
         res["ev64"] = fine_sweep("c128", args.applies)
+        res["ev16"] = fine_sweep("f16", args.applies)
         return res
 
     def coarse_batched():
@@ -312,6 +319,33 @@ def main():
                 "mfma_TFLOPs": round(flops / (t_b * 1e-3) / 1e12, 2),
                 "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5)}
 
+    defl_space = {}
+
+    def f16_section():
+        """The HDCR solve with the smoother's fields stored in FP16 (inner_dtype F16C; everything
+        else as in hdcr_vs_cr), without and with the coarse deflation space."""
+        prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.F16C, coarse_dtype=hd.BF16C,
+                                coarse_tol=args.coarse_tol, coarse_maxiter=500, restart=args.restart, tol=1e-8,
+                                maxiter=500, cheb_order=args.order, cheb_lo=args.cheb_lo, cheb_hi=args.cheb_hi,
+                                basis_dtype=hd.F16C if args.basis == "f16" else hd.C64)
+        work = torch.empty(hd.workspace_bytes(hd._abi.WS_SOLVE, lat, prm), dtype=torch.uint8, device=dev)
+        res = {}
+        for name, d in (("no_deflation", None), ("deflation", defl_space.get("d"))):
+            if name == "deflation" and d is None:
+                continue
+            runs = []
+            for _ in range(max(1, args.steps)):
+                x = torch.zeros_like(b64)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, st, _ = hd.solve(lat, U64, b64, x, params=prm, basis=basis, A=A, work=work, defl=d)
+                runs.append(time.perf_counter() - t)
+            res[name] = {"solve_s": round(float(np.mean(runs)), 4), "outer_iters": st["outer_iters"],
+                         "coarse_iters": st["coarse_iters"], "fine_s": round(st["seconds_fine"], 4),
+                         "coarse_s": round(st["seconds_coarse"], 4), "true_rel_residual": st["true_rel_residual"],
+                         "status": st["status"]}
+        return res
+
     def deflation_section():
         """Coarse-space eigenvector deflation: set-up time, then the HDCR solve of the timed
         steps with every coarse CR started from the Galerkin projection on the deflation space."""
@@ -336,6 +370,7 @@ def main():
         st = runs[-1][1]
         # eigenpair residuals |A v - theta v| (|v| = 1) of the stored operator
         res = (d.W - d.theta.to(d.V.real.dtype)[:, None, None] * d.V).reshape(d.k, -1).norm(dim=1)
+        defl_space["d"] = d
         return {"k": args.defl_k, "m": args.defl_m, "degree": args.defl_degree, "passes": args.defl_iters,
                 "setup_s": round(t_setup, 3), "ritz_abs_min_max": [round(abs(d.theta_host[0]), 5),
                                                                   round(abs(d.theta_host[-1]), 5)],
@@ -344,6 +379,10 @@ def main():
                 "coarse_iters": st["coarse_iters"], "coarse_s": round(st["seconds_coarse"], 4),
                 "fine_s": round(st["seconds_fine"], 4), "outer_s": round(st["seconds_outer"], 4),
                 "true_rel_residual": st["true_rel_residual"], "status": st["status"]}
+
+    if args.defl_only:
+        print(json.dumps({"coarse_deflation": deflation_section()}), flush=True)
+        return
 
     for _ in range(args.warmup):
         r = step()
@@ -362,7 +401,9 @@ def main():
     def avg_ms(key):
         return float(np.mean([a.elapsed_time(b) for r in results for a, b in r[key]]))
 
-    ms64, ms32 = avg_ms("ev64"), avg_ms("ev32")
+    ms64, ms32, ms16 = avg_ms("ev64"), avg_ms("ev32"), avg_ms("ev16")
+    bytes16 = 2 * 12 * V4 * Ls * 4 + 36 * V4 * 8   # FP16 fields, FP32 links
+    gbs16 = bytes16 / (ms16 * 1e-3) / 1e9
     gbs64 = fine_bytes(V4, Ls, 16) / (ms64 * 1e-3) / 1e9
     gbs32 = fine_bytes(V4, Ls, 8) / (ms32 * 1e-3) / 1e9
     out = {
@@ -386,7 +427,10 @@ def main():
                        "c128_us": round(ms64 * 1e3, 1), "c128_GBps": round(gbs64, 1),
                        "c128_pct_hbm": round(100 * gbs64 / HBM_PEAK_GBS, 1),
                        "c64_GFLOPs": round(1416 * lat.N5 / (ms32 * 1e-3) / 1e9, 1),
-                       "c128_GFLOPs": round(1416 * lat.N5 / (ms64 * 1e-3) / 1e9, 1)},
+                       "c128_GFLOPs": round(1416 * lat.N5 / (ms64 * 1e-3) / 1e9, 1),
+                       "f16_storage_us": round(ms16 * 1e3, 1), "f16_storage_GBps": round(gbs16, 1),
+                       "f16_storage_pct_hbm": round(100 * gbs16 / HBM_PEAK_GBS, 1),
+                       "f16_storage_bytes_per_launch": bytes16},
         "roofline": {"bound": "hbm", "achieved": round(gbs32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs32 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(L, Ls), "traffic_unit": "B/launch",
                      "kernel": "dslash_par2_kernel<0>", "bytes_per_launch": fine_bytes(V4, Ls, 8)},
@@ -414,6 +458,12 @@ def main():
         dsec["speedup_vs_hdcr"] = round(hw / dsec["hdcr_defl_solve_s"], 3)
         out["coarse_deflation"] = dsec
         progress("deflated HDCR solve measured")
+    if not args.fine_only:
+        fsec = f16_section()
+        for v in fsec.values():
+            v["speedup_vs_cr"] = round(cw / v["solve_s"], 3)
+        out["hdcr_f16_smoother"] = fsec
+        progress("HDCR with the FP16-storage smoother measured")
     if not args.fine_only:
         out["coarse_multi_rhs"] = coarse_batched()
         progress("multi-RHS coarse apply measured")
