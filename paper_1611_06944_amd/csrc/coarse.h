@@ -110,16 +110,18 @@ template <typename T> struct CoarseCRWork {
     C2<T>* p;
     C2<T>* Ar;
     C2<T>* Ap;
-    double* part;   // partial sums: [2][Nc] of the apply, then [2][CCR_BLOCKS] of the update and init kernels
+    double* part;   // partial sums: [2][Nc] of the apply, then [2][DEFL_INIT_BLOCKS] of the update and init kernels
     double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
     int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter;
                     // CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
     double* dpart;  // partial sums of the deflated start: [2 * DEFL_KMAX][DEFL_BLOCKS]
+    double* dcoef;  // its coefficients <V_j, b> / theta_j: [2 * DEFL_KMAX] (re, im)
 };
 // Deflation space of the coarse solve: k orthonormal approximate eigenvectors V_i
 // of A, W_i = A V_i and the Ritz values theta_i (device arrays; V, W [k][Nc*Nb]).
 constexpr int DEFL_KMAX = 64;
-constexpr int DEFL_BLOCKS = 64;
+constexpr int DEFL_BLOCKS = 256;       // work-groups per chunk of 8 dot products
+constexpr int DEFL_INIT_BLOCKS = 512;  // work-groups of the start kernel
 template <typename T> struct DeflView {
     int k;
     const double* theta;

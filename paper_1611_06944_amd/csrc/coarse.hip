@@ -631,27 +631,34 @@ __global__ void __launch_bounds__(CWG) defl_dot_kernel(int n, DeflView<T> d, con
     }
 }
 
-// x = sum_j g_j V_j, r = b - sum_j g_j W_j with g_j = <V_j, b> / theta_j (every
-// workgroup sums the dot partials itself, in a fixed order); then as ccr_init
-// with cs[3] = |r|^2 and cs[4] = |b|^2
+// coef[q] = (sum of the dot partials of row q, fixed order) / theta_{q/2}: one
+// work-group per real or imaginary part q < 2k
+template <typename T>
+__global__ void __launch_bounds__(CWG) defl_coef_kernel(DeflView<T> d, const double* __restrict__ dpart,
+                                                        double* __restrict__ coef) {
+    const int q = blockIdx.x, j = q >> 1;
+    const double* row = dpart + ((size_t)(j >> 3) * 16 + 2 * (j & 7) + (q & 1)) * DEFL_BLOCKS;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < DEFL_BLOCKS; i += CWG) v[0] += row[i];
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) coef[q] = v[0] / d.theta[j];
+}
+
+// x = sum_j g_j V_j, r = b - sum_j g_j W_j with g_j = <V_j, b> / theta_j (from
+// defl_coef_kernel); then as ccr_init with cs[3] = |r|^2 and cs[4] = |b|^2
 template <typename T>
 __global__ void __launch_bounds__(CWG) ccr_init_defl_kernel(int n, const C2<T>* __restrict__ b, C2<T>* __restrict__ x,
                                                             C2<T>* __restrict__ r, DeflView<T> d,
-                                                            const double* __restrict__ dpart, double* part,
+                                                            const double* __restrict__ coef, double* part,
                                                             double* cs, int* flags, int maxiter, double tol2) {
     __shared__ double gs[2 * DEFL_KMAX];
-    for (int q = threadIdx.x; q < 2 * d.k; q += CWG) {
-        const int j = q >> 1;
-        const double* row = dpart + ((size_t)(j >> 3) * 16 + 2 * (j & 7) + (q & 1)) * DEFL_BLOCKS;
-        double sum = 0.0;
-        for (int i = 0; i < DEFL_BLOCKS; ++i) sum += row[i];
-        gs[q] = sum / d.theta[j];
-    }
+    for (int q = threadIdx.x; q < 2 * d.k; q += CWG) gs[q] = coef[q];
     __syncthreads();
     double v[2] = {0.0, 0.0};
     for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
         const C2<T> bv = b[i];
         double2 xa = make_double2(0.0, 0.0), ra = make_double2(bv.x, bv.y);
+#pragma unroll 8
         for (int j = 0; j < d.k; ++j) {
             const double2 g = make_double2(gs[2 * j], gs[2 * j + 1]);
             const C2<T> vv = d.V[(size_t)j * n + i], wv = d.W[(size_t)j * n + i];
@@ -1000,8 +1007,9 @@ void launch_ccr_init_defl(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const C
     const double tol2 = tol > 0 ? tol * tol : 0.0;
     const int n = c.Nc * c.Nb;
     hipLaunchKernelGGL(defl_dot_kernel<T>, dim3(DEFL_BLOCKS, (d.k + 7) / 8), dim3(CWG), 0, s, n, d, b, w.dpart);
-    hipLaunchKernelGGL(ccr_init_defl_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, b, x, w.r, d,
-                       (const double*)w.dpart, w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
+    hipLaunchKernelGGL(defl_coef_kernel<T>, dim3(2 * d.k), dim3(CWG), 0, s, d, (const double*)w.dpart, w.dcoef);
+    hipLaunchKernelGGL(ccr_init_defl_kernel<T>, dim3(DEFL_INIT_BLOCKS), dim3(CWG), 0, s, n, b, x, w.r, d,
+                       (const double*)w.dcoef, w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
 }
 
 template <typename T>
@@ -1131,9 +1139,112 @@ void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* 
                            basis, v, y, psi);
 }
 
+namespace {
+
+// The same for R right-hand sides per work-group (blockIdx.y = group of R):
+// each A entry is read once for all R vectors.  Every output element takes the
+// same products in the same order as site_gemv (over d, then k in steps of kg
+// per thread, then the fixed sum over the kg thread groups), so the results
+// equal the one-vector kernel's bit for bit.
+template <typename T, typename S, int E, int R>
+__global__ void __launch_bounds__(CWG) coarse_apply_multi_kernel(CoarseGeom c, const S* __restrict__ A,
+                                                                 const C2<T>* __restrict__ v, C2<T>* __restrict__ out,
+                                                                 int nrhs) {
+    extern __shared__ unsigned char smem_raw[];
+    const int Nb = c.Nb;
+    C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);  // [R][9][Nb]
+    C2<T>* red = vs + R * 9 * Nb;                    // [CWG * E]
+    const int a = blockIdx.x;
+    const int r0 = blockIdx.y * R;
+    const int nr = min(R, nrhs - r0);
+    const size_t nv = (size_t)c.Nc * Nb;
+    for (int e = threadIdx.x; e < R * 9 * Nb; e += CWG) {
+        const int r = e / (9 * Nb), rem = e - r * 9 * Nb;
+        const int d = rem / Nb, k = rem - d * Nb;
+        vs[e] = (r < nr) ? v[(size_t)(r0 + r) * nv + (size_t)coarse_nbr(c, a, d) * Nb + k] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    const int nj = Nb / E;
+    const int kg = CWG / nj;
+    const int t = threadIdx.x;
+    const int jq = t % nj, kk = t / nj;
+    C2<T> acc[R][E];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < E; ++q) acc[r][q] = mk<T>(0, 0);
+    if (kk < kg) {
+        const size_t blk = (size_t)Nb * Nb;
+        const S* Aa = A + (size_t)a * 9 * blk + (size_t)jq * E;
+        for (int d = 0; d < 9; ++d) {
+            const S* Ad = Aa + d * blk;
+#pragma unroll 2
+            for (int k = kk; k < Nb; k += kg) {
+                C2<T> e[E];
+                WideA<T, S, E>::ld(Ad + (size_t)k * Nb, e);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C2<T> x = vs[(r * 9 + d) * Nb + k];
+#pragma unroll
+                    for (int q = 0; q < E; ++q) acc[r][q] = cfma<T>(e[q], x, acc[r][q]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r >= nr) break;  // nr is the same for the whole work-group
+        if (kk < kg) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) red[kk * Nb + jq * E + q] = acc[r][q];
+        }
+        __syncthreads();
+        for (int j = t; j < Nb; j += CWG) {
+            C2<T> sum = red[j];
+            for (int g = 1; g < kg; ++g) sum = cadd<T>(sum, red[g * Nb + j]);
+            out[((size_t)(r0 + r) * c.Nc + a) * Nb + j] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr size_t MULTI_LDS_MAX = 65536;
+template <typename T, int E, int R> size_t multi_lds(const CoarseGeom& c) {
+    return ((size_t)R * 9 * c.Nb + (size_t)CWG * E) * sizeof(C2<T>);
+}
+
+template <typename T, typename S, int E>
+bool coarse_apply_multi_launch(const CoarseGeom& c, const S* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s) {
+    if (nrhs >= 8 && multi_lds<T, E, 8>(c) <= MULTI_LDS_MAX) {
+        hipLaunchKernelGGL((coarse_apply_multi_kernel<T, S, E, 8>), dim3(c.Nc, (nrhs + 7) / 8), dim3(CWG),
+                           (multi_lds<T, E, 8>(c)), s, c, A, v, out, nrhs);
+        return true;
+    }
+    if (nrhs >= 4 && multi_lds<T, E, 4>(c) <= MULTI_LDS_MAX) {
+        hipLaunchKernelGGL((coarse_apply_multi_kernel<T, S, E, 4>), dim3(c.Nc, (nrhs + 3) / 4), dim3(CWG),
+                           (multi_lds<T, E, 4>(c)), s, c, A, v, out, nrhs);
+        return true;
+    }
+    if (nrhs >= 2 && multi_lds<T, E, 2>(c) <= MULTI_LDS_MAX) {
+        hipLaunchKernelGGL((coarse_apply_multi_kernel<T, S, E, 2>), dim3(c.Nc, (nrhs + 1) / 2), dim3(CWG),
+                           (multi_lds<T, E, 2>(c)), s, c, A, v, out, nrhs);
+        return true;
+    }
+    return false;
+}
+
+}  // namespace
+
 template <typename T, typename S>
 void coarse_apply_launch(const CoarseGeom& c, const S* A, const C2<T>* v, C2<T>* out, int nrhs, hipStream_t s) {
     constexpr int E = wide_entries<S>();
+    if (nrhs > 1) {
+        if (c.Nb % E == 0) {
+            if (coarse_apply_multi_launch<T, S, E>(c, A, v, out, nrhs, s)) return;
+        } else if (coarse_apply_multi_launch<T, S, 1>(c, A, v, out, nrhs, s)) {
+            return;
+        }
+    }
     if (c.Nb % E == 0)
         hipLaunchKernelGGL((coarse_apply_kernel<T, S, E>), dim3(c.Nc, nrhs), dim3(CWG), (apply_lds<T, E>(c)), s, c,
                            A, v, out);

@@ -73,10 +73,11 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
     k.p = w.take<C2<T>>(n);
     k.Ar = w.take<C2<T>>(n);
     k.Ap = w.take<C2<T>>(n);
-    k.part = w.take<double>(2 * (size_t)c.Nc + 2 * CCR_BLOCKS);
+    k.part = w.take<double>(2 * (size_t)c.Nc + 2 * std::max(CCR_BLOCKS, DEFL_INIT_BLOCKS));
     k.cs = w.take<double>(8);
     k.flags = w.take<int>(CCR_FLAGS);
     k.dpart = w.take<double>((size_t)2 * DEFL_KMAX * DEFL_BLOCKS);
+    k.dcoef = w.take<double>((size_t)2 * DEFL_KMAX);
     return k;
 }
 template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
