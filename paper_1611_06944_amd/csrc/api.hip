@@ -132,8 +132,7 @@ int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U,
     if (overlap(psi, fbytes, out, fbytes)) return fail(HDCR_EINVAL, "hdcr_apply_fine: psi and out overlap");
     if (dtype == HDCR_F16C) {
         if (!dslash_h16_ok(g)) return fail(HDCR_EINVAL, "hdcr_apply_fine: F16C needs Ls = 16 and even extents");
-        launch_dslash_h16(g, (const float2*)U, psi, out,
-                          Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0}, stream);
+        launch_dslash_h16(g, (const float2*)U, psi, out, stream);
     } else if (dtype == HDCR_C128)
         launch_dslash<double>(g, (const double2*)U, (const double2*)psi, (double2*)out, stream);
     else

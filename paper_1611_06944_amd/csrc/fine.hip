@@ -784,19 +784,12 @@ void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>
     }
 }
 
-bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void* out, const Epi<float>& e,
-                       hipStream_t s) {
-    if (!par_ok(g) || e.ny < 0 || e.ny > 4) return false;
+bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void* out, hipStream_t s) {
+    if (!par_ok(g)) return false;
     const TileGeom tg = tile_geom(g);
-    const float2* x = static_cast<const float2*>(in);
-    float2* y = static_cast<float2*>(out);
-    switch (e.ny) {
-        case 0: hipLaunchKernelGGL((dslash_par2_kernel<0, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
-        case 1: hipLaunchKernelGGL((dslash_par2_kernel<1, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
-        case 2: hipLaunchKernelGGL((dslash_par2_kernel<2, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
-        case 3: hipLaunchKernelGGL((dslash_par2_kernel<3, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
-        default: hipLaunchKernelGGL((dslash_par2_kernel<4, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, x, y, e); break;
-    }
+    hipLaunchKernelGGL((dslash_par2_kernel<0, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U,
+                       static_cast<const float2*>(in), static_cast<float2*>(out),
+                       Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
     return true;
 }
 

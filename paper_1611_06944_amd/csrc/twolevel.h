@@ -51,10 +51,10 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
 // The same with FP16 storage of the smoother's fields (Ls = 16, even extents,
 // order >= 2): in is scaled to unit RMS per entry and rounded to FP16 (the
 // smoother is linear), the recurrence runs through the FP16-storage stencil,
-// and the result is scaled back into the FP32 out.  h: five FP16 fields of
+// and the result is scaled back into the FP32 out.  h: six FP16 fields of
 // 12 N5 entries (4 bytes each); part: REDUCE_BLOCKS doubles; S: one double.
 void cheb_smoother_h16(const FineGeom& g, const float2* U, const float2* in, float2* out, bool accumulate,
-                       void* const h[5], double* part, double* S, int order, double lo, double hi, hipStream_t s);
+                       void* const h[6], double* part, double* S, int order, double lo, double hi, hipStream_t s);
 
 void cheby_coeffs(int n, double lo, double hi, double* c);
 

@@ -161,15 +161,20 @@ template <typename T> struct SmootherOps {
     }
 };
 // The same on FP16-stored fields (the float2 pointers address (fp16 re, fp16 im)
-// entries; FP32 links and arithmetic).  Needs at least two Chebyshev terms.
+// entries; FP32 links and arithmetic): the combination of a fused epilogue is
+// a separate element-wise pass over tmp, the stencil's output.  Needs at least
+// two Chebyshev terms.
 struct SmootherOpsH16 {
     const FineGeom& g;
     const float2* U;
+    void* tmp;
     hipStream_t s;
-    void apply(const float2* a, float2* b) const {
-        launch_dslash_h16(g, U, a, b, Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0}, s);
+    void apply(const float2* a, float2* b) const { launch_dslash_h16(g, U, a, b, s); }
+    void epi(const float2* a, float2* b, const Epi<float>& e) const {
+        launch_dslash_h16(g, U, a, tmp, s);
+        const void* z[4] = {e.y[0], e.y[1], e.y[2], e.y[3]};
+        launch_h16_combine(12LL * g.N5, e.beta, tmp, z, e.g, e.ny, b, s);
     }
-    void epi(const float2* a, float2* b, const Epi<float>& e) const { launch_dslash_h16(g, U, a, b, e, s); }
     void scale_u(const float2*, double, float2*, bool) const {}
 };
 
@@ -246,7 +251,7 @@ void cheb_smoother(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* ou
 }
 
 void cheb_smoother_h16(const FineGeom& g, const float2* U, const float2* in, float2* out, bool accumulate,
-                       void* const h[5], double* part, double* S, int order, double lo, double hi, hipStream_t s) {
+                       void* const h[6], double* part, double* S, int order, double lo, double hi, hipStream_t s) {
     const int64_t n = 12LL * g.N5;
     float2* hb[5];
     for (int i = 0; i < 5; ++i) hb[i] = static_cast<float2*>(h[i]);
@@ -254,7 +259,7 @@ void cheb_smoother_h16(const FineGeom& g, const float2* U, const float2* in, flo
     launch_to_h16_scaled(n, in, S, 0, hb[0], s);
     float2* const tmp[4] = {hb[1], hb[2], hb[3], hb[4]};
     // hb[0] holds the scaled input for the first pass and then the result
-    clenshaw<float>(SmootherOpsH16{g, U, s}, hb[0], hb[0], false, tmp, order, lo, hi);
+    clenshaw<float>(SmootherOpsH16{g, U, h[5], s}, hb[0], hb[0], false, tmp, order, lo, hi);
     launch_from_h16_scaled(n, hb[0], S, 0, out, accumulate, s);
 }
 
@@ -268,7 +273,7 @@ template <typename T> struct CycleWork {
     C2<T>* vc;
     C2<T>* cx;
     CoarseCRWork<T> ccr;
-    void* h16[5];   // FP16 smoother fields (inside sm[0..2], FP32 cycle only)
+    void* h16[6];   // FP16 smoother fields (inside sm[0..2], FP32 cycle only)
     double* hpart;  // reduction scratch of the FP16 smoother
     double* hS;
 };
@@ -281,7 +286,7 @@ template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
     k.vc = w.take<C2<T>>((size_t)c.Nc * c.Nb);
     k.cx = w.take<C2<T>>((size_t)c.Nc * c.Nb);
     k.ccr = coarse_cr_carve<T>(w, c);
-    for (int j = 0; j < 5; ++j)
+    for (int j = 0; j < 6; ++j)
         k.h16[j] = k.sm[j / 2] ? static_cast<void*>(reinterpret_cast<char*>(k.sm[j / 2]) + (j % 2) * n * 4) : nullptr;
     k.hpart = w.take<double>(REDUCE_BLOCKS);
     k.hS = w.take<double>(8);
@@ -755,8 +760,8 @@ int hdcr_smooth(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, int
         if (!dslash_h16_ok(g)) return fail(HDCR_EINVAL, "hdcr_smooth: F16C needs Ls = 16 and even extents");
         if (order < 2) return fail(HDCR_EINVAL, "hdcr_smooth: F16C needs order >= 2");
         if (overlap(in, n * cs, out, n * cs)) return fail(HDCR_EINVAL, "hdcr_smooth: in and out overlap");
-        void* h[5];
-        for (int i = 0; i < 5; ++i) h[i] = w.take<uint32_t>(n);
+        void* h[6];
+        for (int i = 0; i < 6; ++i) h[i] = w.take<uint32_t>(n);
         double* part = w.take<double>(REDUCE_BLOCKS);
         double* S = w.take<double>(8);
         if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_smooth: workspace too small");

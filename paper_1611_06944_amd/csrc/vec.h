@@ -44,6 +44,11 @@ void launch_to_h16_scaled(int64_t n, const float2* x, const double* S, int idx, 
 void launch_from_h16_scaled(int64_t n, const void* y, const double* S, int idx, float2* out, bool accumulate,
                             hipStream_t s);
 
+// y = beta x + sum_{i < ny} g[i] z[i] on FP16-stored fields (0 <= ny <= 4; FP32
+// arithmetic, one rounding per entry); y may be one of the z[i], not x
+void launch_h16_combine(int64_t n, float beta, const void* x, const void* const z[4], const float g[4], int ny, void* y,
+                        hipStream_t s);
+
 // S[idx] = |x|^2 (FP64 accumulation, fixed order); part: REDUCE_BLOCKS doubles
 template <typename T> void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s);
 // x <- x / sqrt(S[idx])

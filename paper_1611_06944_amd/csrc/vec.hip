@@ -216,7 +216,53 @@ __global__ void __launch_bounds__(VWG) from_h16_scaled_kernel(int64_t n, const u
     }
 }
 
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef unsigned uint2_t __attribute__((ext_vector_type(2)));
+struct H16Combine {
+    const uint2_t* z[4];
+    float g[4];
+};
+// two complex entries (8 bytes) per work-item and step
+template <int NY>
+__global__ void __launch_bounds__(VWG) h16_combine_kernel(int64_t n2, float beta, const uint2_t* x, H16Combine c,
+                                                          uint2_t* y) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n2; i += (int64_t)gridDim.x * VWG) {
+        const half4_t hx = __builtin_bit_cast(half4_t, x[i]);
+        float o[4] = {beta * (float)hx.x, beta * (float)hx.y, beta * (float)hx.z, beta * (float)hx.w};
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+            const half4_t hz = __builtin_bit_cast(half4_t, c.z[q][i]);
+            o[0] = fmaf(c.g[q], (float)hz.x, o[0]);
+            o[1] = fmaf(c.g[q], (float)hz.y, o[1]);
+            o[2] = fmaf(c.g[q], (float)hz.z, o[2]);
+            o[3] = fmaf(c.g[q], (float)hz.w, o[3]);
+        }
+        const half4_t ho = {(_Float16)o[0], (_Float16)o[1], (_Float16)o[2], (_Float16)o[3]};
+        y[i] = __builtin_bit_cast(uint2_t, ho);
+    }
+}
+
 }  // namespace
+
+void launch_h16_combine(int64_t n, float beta, const void* x, const void* const z[4], const float g[4], int ny, void* y,
+                        hipStream_t s) {
+    // n complex entries = n / 2 eight-byte pairs (n is even: 12 components per site)
+    const int64_t n2 = n / 2;
+    H16Combine c{};
+    for (int q = 0; q < 4; ++q) {
+        c.z[q] = q < ny ? static_cast<const uint2_t*>(z[q]) : nullptr;
+        c.g[q] = q < ny ? g[q] : 0.0f;
+    }
+    const uint2_t* xp = static_cast<const uint2_t*>(x);
+    uint2_t* yp = static_cast<uint2_t*>(y);
+    switch (ny) {
+        case 0: hipLaunchKernelGGL(h16_combine_kernel<0>, dim3(vgrid(n2)), dim3(VWG), 0, s, n2, beta, xp, c, yp); break;
+        case 1: hipLaunchKernelGGL(h16_combine_kernel<1>, dim3(vgrid(n2)), dim3(VWG), 0, s, n2, beta, xp, c, yp); break;
+        case 2: hipLaunchKernelGGL(h16_combine_kernel<2>, dim3(vgrid(n2)), dim3(VWG), 0, s, n2, beta, xp, c, yp); break;
+        case 3: hipLaunchKernelGGL(h16_combine_kernel<3>, dim3(vgrid(n2)), dim3(VWG), 0, s, n2, beta, xp, c, yp); break;
+        default: hipLaunchKernelGGL(h16_combine_kernel<4>, dim3(vgrid(n2)), dim3(VWG), 0, s, n2, beta, xp, c, yp); break;
+    }
+}
 
 void launch_to_h16_scaled(int64_t n, const float2* x, const double* S, int idx, void* y, hipStream_t s) {
     hipLaunchKernelGGL(to_h16_scaled_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, x, S, idx, static_cast<uint32_t*>(y));
