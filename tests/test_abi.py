@@ -220,3 +220,41 @@ def test_deflation_argument_validation_before_launch(lib):
               None) == _abi.HDCR_EINVAL
     assert cs(ctypes.byref(cd), _abi.C64, A, ctypes.byref(d), bb, xx, 10, 0.0, ctypes.byref(it), work, cws - 1,
               None) == _abi.HDCR_ENOMEM
+
+
+def test_f16_storage_validation_before_launch(lib):
+    from paper_1611_06944_amd import Lattice, _abi
+    U, x, y, work = (ctypes.c_void_p(1 << 32), ctypes.c_void_p(1 << 33), ctypes.c_void_p(1 << 34),
+                     ctypes.c_void_p(1 << 35))
+    # FP16 fields need Ls = 16 and even extents
+    d8 = Lattice((4, 4, 4, 4), 8).fine_desc()
+    assert lib.hdcr_apply_fine(ctypes.byref(d8), _abi.F16C, U, x, y, None) == _abi.HDCR_EINVAL
+    assert b"F16C" in lib.hdcr_last_error()
+    dodd = Lattice((4, 4, 3, 4), 16).fine_desc()
+    assert lib.hdcr_apply_fine(ctypes.byref(dodd), _abi.F16C, U, x, y, None) == _abi.HDCR_EINVAL
+    d16 = Lattice((4, 4, 4, 4), 16).fine_desc()
+    # F16C takes C64 links: an 8-byte-aligned U is accepted, a misaligned one is not
+    assert lib.hdcr_apply_fine(ctypes.byref(d16), _abi.F16C, ctypes.c_void_p((1 << 32) + 4), x, y,
+                               None) == _abi.HDCR_EINVAL
+    # the FP16 smoother needs at least two Chebyshev terms
+    assert lib.hdcr_smooth(ctypes.byref(d16), _abi.F16C, U, 1, 1.0, 64.0, x, y, work, 1 << 30,
+                           None) == _abi.HDCR_EINVAL
+    assert lib.hdcr_smooth(ctypes.byref(d8), _abi.F16C, U, 10, 1.0, 64.0, x, y, work, 1 << 30,
+                           None) == _abi.HDCR_EINVAL
+    # solve parameters: inner F16C needs an FP32 coarse operator and order >= 2
+    cd = Lattice((8, 8, 8, 8), 16, block=(4, 4, 4, 4), nvec=4).coarse_desc()
+    p = _abi.SolveParams()
+    p.tol, p.maxiter, p.restart, p.precond = 1e-8, 10, 4, _abi.PRECOND_TWO_LEVEL
+    p.cheb_order, p.cheb_lo, p.cheb_hi = 10, 1.0, 64.0
+    p.inner_dtype, p.coarse_dtype, p.basis_dtype = _abi.F16C, _abi.BF16C, _abi.F16C
+    assert lib.hdcr_workspace_bytes(_abi.WS_SOLVE, ctypes.byref(cd), ctypes.byref(p)) > 0
+    p.cheb_order = 1
+    assert lib.hdcr_workspace_bytes(_abi.WS_SOLVE, ctypes.byref(cd), ctypes.byref(p)) == 0
+    p.cheb_order, p.coarse_dtype = 10, _abi.C128
+    assert lib.hdcr_workspace_bytes(_abi.WS_SOLVE, ctypes.byref(cd), ctypes.byref(p)) == 0
+    # ... and a lattice the FP16 stencil takes (Ls = 16, even extents)
+    p.coarse_dtype = _abi.C64
+    cd8 = Lattice((8, 8, 8, 8), 8, block=(4, 4, 4, 4), nvec=4).coarse_desc()
+    assert lib.hdcr_vcycle(ctypes.byref(cd8), ctypes.byref(p), U, x, y, None, x, y, work, 1 << 30,
+                           None) == _abi.HDCR_EINVAL
+    assert b"F16C" in lib.hdcr_last_error()
