@@ -53,6 +53,7 @@ CoarseGeom make_coarse_geom(const hdcr_coarse_desc* d) {
 }
 
 // columns of A built per pass of the class-split stencil
+// columns per projection launch: at most 4 (one per wavefront of the projection work-group)
 static int build_chunk(const CoarseGeom& c) { return c.Nb < 4 ? c.Nb : 4; }
 
 size_t build_workspace_bytes(const CoarseGeom& c) {
@@ -62,6 +63,7 @@ size_t build_workspace_bytes(const CoarseGeom& c) {
     w.take<double2>(fsz * kc);          // expanded basis fields
     w.take<double2>(fsz * kc * 9);      // class-split images
     w.take<double2>(coarse_elems(c));   // A in FP64
+    w.take<double2>(coarse_project_scratch_elems(c));  // projection partial sums
     w.take<int>(64);                    // rank flag
     return w.used();
 }
@@ -135,6 +137,7 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     double2* X = w.take<double2>(fsz * kc);
     double2* Y = w.take<double2>(fsz * kc * 9);
     double2* A64 = w.take<double2>(coarse_elems(c));
+    double2* Pp = w.take<double2>(coarse_project_scratch_elems(c));
     int* flag = w.take<int>(64);
     double2* b64 = basis64(basis);
     // chiral split and block orthonormalisation
@@ -152,7 +155,7 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
         launch_basis_expand(c, b64, k0, nk, X, stream);
         for (int kk = 0; kk < nk; ++kk)
             for (int d = 0; d < 9; ++d) launch_dslash_class(c, U64, X + kk * fsz, Y + (kk * 9 + d) * fsz, d, stream);
-        launch_coarse_project(c, b64, Y, k0, nk, Adst, stream);
+        launch_coarse_project(c, b64, Y, k0, nk, Pp, Adst, stream);
         HDCR_HIP_CHECK(hipGetLastError());
     }
     if (A_dtype != HDCR_C128) launch_coarse_convert(c, A64, A_dtype, A, stream);

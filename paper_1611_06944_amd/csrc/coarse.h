@@ -149,10 +149,13 @@ template <typename T>
 void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
                      bool first, hipStream_t s);
 
-// little Dirac operator build: A64[a][d][k][j] for basis vectors in [k0, k0+nk)
-// given the class-split fine fields Y[(kk*9 + d)] = H^(d) Phi_{k0+kk}
-void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,
-                           hipStream_t s);
+// little Dirac operator build: A64[a][d][k][j] for basis vectors in [k0, k0+nk),
+// nk <= 4, given the class-split fine fields Y[(kk*9 + d)] = H^(d) Phi_{k0+kk}
+// (read only on the sites of class d); P: coarse_project_scratch_elems() of
+// partial sums
+size_t coarse_project_scratch_elems(const CoarseGeom& c);
+void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* P,
+                           double2* A64, hipStream_t s);
 // out = H^(cls) in: the terms of H whose hop class is cls (0 = diagonal, fifth
 // dimension and hops inside a block; 1+mu / 5+mu = forward / backward mu hops
 // that cross the block face)

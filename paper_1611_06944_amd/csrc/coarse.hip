@@ -851,94 +851,119 @@ void ccr_apply_dispatch(const CoarseGeom& c, hdcr_dtype dt, const void* A, const
 // coarse build: projection of the class-split fields onto the block basis
 // ---------------------------------------------------------------------------
 
-// site sl of block-face class d: d = 0 -> all bvol sites; d = 1+mu -> local
-// x_mu = B_mu - 1; d = 5+mu -> local x_mu = 0 (f enumerates the face)
-__device__ __forceinline__ int class_site(const CoarseGeom& c, int d, int f) {
-    if (d == 0) return f;
-    const int mu = (d - 1) & 3;
-    const int fixed = (d <= 4) ? c.B[mu] - 1 : 0;
-    int x[4], r = f;
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == mu) {
-            x[nu] = fixed;
-        } else {
-            x[nu] = r % c.B[nu];
-            r /= c.B[nu];
-        }
-    }
-    return ((x[3] * c.B[2] + x[2]) * c.B[1] + x[1]) * c.B[0] + x[0];
-}
+constexpr int PROJ_NK = 4;     // basis vectors (columns) per launch: one per wavefront of the work-group
+constexpr int PROJ_ROWS = 64;  // basis rows per work-group
+constexpr int PROJ_CHUNK = 16; // compressed indices of the block staged per step
+constexpr int PROJ_PARTS = 4;  // work-groups splitting one block's indices
 
-constexpr int PROJ_NK = 8;     // basis vectors (columns) per launch
-constexpr int PROJ_CHUNK = 32; // compressed indices staged per step
-
-// grid (Nc, 9): the workgroup computes A64[a][d][k0+kk][j] for all j < Nb, kk < nk,
-// summing conj(phi^a_j) . (H^(d) Phi_k) over the sites of class d in block a
+// grid (Nc, ceil(Nb / 64), PROJ_PARTS): the work-group sums conj(phi^a_j) . (H^(d) Phi_k)
+// for all nine classes d, 64 rows j and nk <= 4 columns kk over part blockIdx.z of
+// block a's compressed indices, and writes the partial sums to
+// P[((part * Nc + a) * 9 + d) * PROJ_NK + kk][j].  One pass over the indices
+// serves all classes: class 0 takes every site, the face classes only the sites
+// on their face (a per-index test, the same for the whole work-group), so every
+// basis entry is read once per launch.  Chunks of the 64 basis rows are staged
+// in LDS with coalesced loads.
 __global__ void __launch_bounds__(CWG) coarse_project_kernel(CoarseGeom c, const double2* __restrict__ b64,
-                                                             const double2* __restrict__ Y, int k0, int nk,
-                                                             double2* __restrict__ A64) {
-    __shared__ double2 F[2][PROJ_NK][PROJ_CHUNK];  // chiral folds of the fields
-    const int a = blockIdx.x, d = blockIdx.y;
-    const int nsites = (d == 0) ? c.bvol : c.bvol / c.B[(d - 1) & 3];
-    const int nidx = 12 * nsites * c.Lh;
+                                                             const double2* __restrict__ Y, int nk,
+                                                             double2* __restrict__ P) {
+    __shared__ double2 F[2][PROJ_NK][9][PROJ_CHUNK];  // chiral folds of the class fields
+    __shared__ double2 Bs[PROJ_ROWS][PROJ_CHUNK + 1];  // basis rows of the chunk
+    __shared__ int mask[PROJ_CHUNK];                  // classes of each staged index
+    const int a = blockIdx.x;
+    const int j0 = blockIdx.y * PROJ_ROWS;
+    const int ntot = 12 * c.bvol * c.Lh;
+    // this part's index range, in whole chunks
+    const int nchunk = (ntot + PROJ_CHUNK - 1) / PROJ_CHUNK;
+    const int cb = (int)(((long long)nchunk * blockIdx.z) / gridDim.z);
+    const int ce = (int)(((long long)nchunk * (blockIdx.z + 1)) / gridDim.z);
+    const int nidx = min(ntot, ce * PROJ_CHUNK);
     const size_t fsz = (size_t)12 * c.f.N5;
-    // work-item -> (row j, column group): 64 rows x 4 groups
-    const int jl = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    double2 acc[2][PROJ_NK / 4];
-    for (int r = 0; r < 2; ++r)
-        for (int q = 0; q < PROJ_NK / 4; ++q) acc[r][q] = make_double2(0, 0);
-    for (int i0 = 0; i0 < nidx; i0 += PROJ_CHUNK) {
-        // stage the folds of the chunk
-        for (int e = threadIdx.x; e < nk * PROJ_CHUNK; e += CWG) {
-            const int kk = e / PROJ_CHUNK, ii = e % PROJ_CHUNK;
-            const int idx = i0 + ii;
-            double2 fp = make_double2(0, 0), fm = make_double2(0, 0);
-            if (idx < nidx) {
-                const int s = idx % c.Lh;
-                const int f = (idx / c.Lh) % nsites;
-                const int comp = idx / (c.Lh * nsites);
-                const int site = block_site(c, a, class_site(c, d, f));
-                const size_t fb = (((size_t)kk * 9 + d) * fsz) + ((size_t)comp * c.f.V4 + site) * c.f.Ls;
-                const double2 p1 = Y[fb + s], p2 = Y[fb + c.f.Ls - 1 - s];
-                const double g = (comp < 6) ? 1.0 : -1.0;
-                fp = make_double2((p1.x + g * p2.x) * RSQRT2, (p1.y + g * p2.y) * RSQRT2);
-                fm = make_double2((p1.x - g * p2.x) * RSQRT2, (p1.y - g * p2.y) * RSQRT2);
-            }
-            F[0][kk][ii] = fp;
-            F[1][kk][ii] = fm;
-        }
-        __syncthreads();
-        for (int r = 0; r < 2; ++r) {
-            const int j = jl + 64 * r;
-            if (j < c.Nb) {
-                const int h = (j < c.nvec) ? 0 : 1;
-                const double2* bj = b64 + (((size_t)a * 2 + h) * c.nvec + (j - h * c.nvec)) * c.nhalf;
-                const int iend = min(PROJ_CHUNK, nidx - i0);
-                for (int ii = 0; ii < iend; ++ii) {
-                    const int idx = i0 + ii;
-                    const int s = idx % c.Lh;
-                    const int f = (idx / c.Lh) % nsites;
-                    const int comp = idx / (c.Lh * nsites);
-                    const double2 bv = bj[(comp * c.bvol + class_site(c, d, f)) * c.Lh + s];
+    const int jl = threadIdx.x % PROJ_ROWS, kk = threadIdx.x / PROJ_ROWS;
+    const int j = j0 + jl;
+    const int h = (j < c.nvec) ? 0 : 1;
+    double2 acc[9];
 #pragma unroll
-                    for (int q = 0; q < PROJ_NK / 4; ++q) {
-                        const int kk = grp + 4 * q;
-                        if (kk < nk) acc[r][q] = cjfma<double>(bv, F[h][kk][ii], acc[r][q]);
-                    }
+    for (int d = 0; d < 9; ++d) acc[d] = make_double2(0, 0);
+    for (int i0 = cb * PROJ_CHUNK; i0 < nidx; i0 += PROJ_CHUNK) {
+        // classes of the staged indices: 0, and the faces the site lies on
+        if (threadIdx.x < PROJ_CHUNK) {
+            const int idx = i0 + threadIdx.x;
+            int m = 0;
+            if (idx < nidx) {
+                int f = (idx / c.Lh) % c.bvol;
+                m = 1;
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) {
+                    const int x = f % c.B[mu];
+                    f /= c.B[mu];
+                    if (x == c.B[mu] - 1) m |= 1 << (1 + mu);
+                    if (x == 0) m |= 1 << (5 + mu);
                 }
             }
+            mask[threadIdx.x] = m;
+        }
+        // basis rows: 64 rows x 16 consecutive indices, one 256-byte run per row
+        for (int e = threadIdx.x; e < PROJ_ROWS * PROJ_CHUNK; e += CWG) {
+            const int r = e / PROJ_CHUNK, ii = e % PROJ_CHUNK;
+            const int jr = j0 + r, idx = i0 + ii;
+            double2 v = make_double2(0, 0);
+            if (jr < c.Nb && idx < nidx) {
+                const int hr = (jr < c.nvec) ? 0 : 1;
+                v = b64[(((size_t)a * 2 + hr) * c.nvec + (jr - hr * c.nvec)) * c.nhalf + idx];
+            }
+            Bs[r][ii] = v;
+        }
+        __syncthreads();
+        // folds of the class fields at the staged indices (only the classes present)
+        for (int e = threadIdx.x; e < nk * 9 * PROJ_CHUNK; e += CWG) {
+            const int ii = e % PROJ_CHUNK, dk = e / PROJ_CHUNK;
+            const int d = dk % 9, q = dk / 9;
+            const int idx = i0 + ii;
+            if (idx >= nidx || !((mask[ii] >> d) & 1)) continue;
+            const int s = idx % c.Lh;
+            const int f = (idx / c.Lh) % c.bvol;
+            const int comp = idx / (c.Lh * c.bvol);
+            const int site = block_site(c, a, f);
+            const size_t fb = (((size_t)q * 9 + d) * fsz) + ((size_t)comp * c.f.V4 + site) * c.f.Ls;
+            const double2 p1 = Y[fb + s], p2 = Y[fb + c.f.Ls - 1 - s];
+            const double g = (comp < 6) ? 1.0 : -1.0;
+            F[0][q][d][ii] = make_double2((p1.x + g * p2.x) * RSQRT2, (p1.y + g * p2.y) * RSQRT2);
+            F[1][q][d][ii] = make_double2((p1.x - g * p2.x) * RSQRT2, (p1.y - g * p2.y) * RSQRT2);
+        }
+        __syncthreads();
+        if (j < c.Nb && kk < nk) {
+            const int iend = min(PROJ_CHUNK, nidx - i0);
+            for (int ii = 0; ii < iend; ++ii) {
+                const double2 bv = Bs[jl][ii];
+                const int m = mask[ii];
+                acc[0] = cjfma<double>(bv, F[h][kk][0][ii], acc[0]);
+#pragma unroll
+                for (int d = 1; d < 9; ++d)
+                    if ((m >> d) & 1) acc[d] = cjfma<double>(bv, F[h][kk][d][ii], acc[d]);
+            }
         }
         __syncthreads();
     }
-    for (int r = 0; r < 2; ++r) {
-        const int j = jl + 64 * r;
-        if (j >= c.Nb) continue;
+    if (j < c.Nb && kk < nk) {
 #pragma unroll
-        for (int q = 0; q < PROJ_NK / 4; ++q) {
-            const int kk = grp + 4 * q;
-            if (kk < nk) A64[(((size_t)a * 9 + d) * c.Nb + (k0 + kk)) * c.Nb + j] = acc[r][q];
-        }
+        for (int d = 0; d < 9; ++d)
+            P[((((size_t)blockIdx.z * c.Nc + a) * 9 + d) * PROJ_NK + kk) * c.Nb + j] = acc[d];
+    }
+}
+
+// A64[a][d][k0+kk][j] = sum over the parts, in part order
+__global__ void __launch_bounds__(CWG) coarse_project_sum_kernel(CoarseGeom c, const double2* __restrict__ P, int k0,
+                                                                 int nk, double2* __restrict__ A64) {
+    const size_t n = (size_t)c.Nc * 9 * nk * c.Nb;
+    for (size_t e = (size_t)blockIdx.x * CWG + threadIdx.x; e < n; e += (size_t)gridDim.x * CWG) {
+        const int j = (int)(e % c.Nb);
+        const size_t r = e / c.Nb;
+        const int kk = (int)(r % nk);
+        const size_t ad = r / nk;  // a * 9 + d
+        double2 sum = P[(ad * PROJ_NK + kk) * c.Nb + j];
+        for (int q = 1; q < PROJ_PARTS; ++q) sum = cadd<double>(sum, P[(((size_t)q * c.Nc * 9 + ad) * PROJ_NK + kk) * c.Nb + j]);
+        A64[(ad * c.Nb + (k0 + kk)) * c.Nb + j] = sum;
     }
 }
 
@@ -1263,9 +1288,14 @@ void launch_coarse_apply_bf16(const CoarseGeom& c, const uint16_t* A, const floa
     coarse_apply_launch<float, uint32_t>(c, reinterpret_cast<const uint32_t*>(A), v, out, nrhs, s);
 }
 
-void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* A64,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(coarse_project_kernel, dim3(c.Nc, 9), dim3(CWG), 0, s, c, b64, Y, k0, nk, A64);
+size_t coarse_project_scratch_elems(const CoarseGeom& c) { return (size_t)PROJ_PARTS * c.Nc * 9 * PROJ_NK * c.Nb; }
+
+void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* P,
+                           double2* A64, hipStream_t s) {
+    hipLaunchKernelGGL(coarse_project_kernel, dim3(c.Nc, (c.Nb + PROJ_ROWS - 1) / PROJ_ROWS, PROJ_PARTS), dim3(CWG), 0,
+                       s, c, b64, Y, nk, P);
+    hipLaunchKernelGGL(coarse_project_sum_kernel, dim3(grid_for((size_t)c.Nc * 9 * nk * c.Nb)), dim3(CWG), 0, s, c,
+                       (const double2*)P, k0, nk, A64);
 }
 
 void launch_coarse_convert(const CoarseGeom& c, const double2* A64, hdcr_dtype dt, void* dst, hipStream_t s) {
