@@ -154,7 +154,7 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
         const int nk = (c.Nb - k0 < kc) ? c.Nb - k0 : kc;
         launch_basis_expand(c, b64, k0, nk, X, stream);
         for (int kk = 0; kk < nk; ++kk)
-            for (int d = 0; d < 9; ++d) launch_dslash_class(c, U64, X + kk * fsz, Y + (kk * 9 + d) * fsz, d, stream);
+            launch_dslash_classes(c, U64, X + kk * fsz, Y + kk * 9 * fsz, fsz, stream);
         launch_coarse_project(c, b64, Y, k0, nk, Pp, Adst, stream);
         HDCR_HIP_CHECK(hipGetLastError());
     }

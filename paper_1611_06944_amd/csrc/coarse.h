@@ -156,11 +156,12 @@ void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<
 size_t coarse_project_scratch_elems(const CoarseGeom& c);
 void launch_coarse_project(const CoarseGeom& c, const double2* b64, const double2* Y, int k0, int nk, double2* P,
                            double2* A64, hipStream_t s);
-// out = H^(cls) in: the terms of H whose hop class is cls (0 = diagonal, fifth
-// dimension and hops inside a block; 1+mu / 5+mu = forward / backward mu hops
-// that cross the block face)
-void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
-                         hipStream_t s);
+// The nine hop classes of H in: out + d * fstride = H^(d) in, d = 0: diagonal,
+// fifth dimension and hops inside a block, at every site; d = 1+mu / 5+mu: the
+// forward / backward mu hop that crosses the block face, written only at the
+// sites on that face (the other entries of those fields are left as they were)
+void launch_dslash_classes(const CoarseGeom& c, const double2* U, const double2* in, double2* out, size_t fstride,
+                           hipStream_t s);
 // A64 (column-major) -> other storage
 void launch_coarse_convert(const CoarseGeom& c, const double2* A64, hdcr_dtype dt, void* dst, hipStream_t s);
 // any storage -> logical A[a][d][j][k] complex double

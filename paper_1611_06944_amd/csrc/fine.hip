@@ -41,13 +41,10 @@ namespace {
 constexpr int WG = 256;
 constexpr int LPAD = 10;  // complex entries per staged link matrix (9 used; keeps FP32 matrices 16-byte aligned)
 
-// Hop-class selection used by the little-Dirac-operator build: cls = -1 keeps
-// every term; cls = 0 keeps the diagonal, the fifth-dimension hops and the 4d
-// hops that stay inside a block of extent B; cls = 1+mu (5+mu) keeps only the
-// forward (backward) mu hops that cross the block face.
+// Blocks of the little-Dirac-operator build: a mu hop from a site with local
+// coordinate B[mu] - 1 (forward) or 0 (backward) crosses the block face.
 struct ClassSel {
-    int B[4];
-    int cls;
+    int B[4];  // block extents
 };
 
 struct FieldRefs {
@@ -621,10 +618,10 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
 }
 
 // Generic kernel: any Ls, links and fifth-dimension neighbours loaded
-// directly; CLS selects one hop class (coarse-operator build).
-template <typename T, bool CLS, int NY>
+// directly.
+template <typename T, int NY>
 __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>* U, const C2<T>* in, C2<T>* out,
-                                                        ClassSel cs, Epi<T> ep) {
+                                                        Epi<T> ep) {
     constexpr uint32_t CB = sizeof(C2<T>);
     const int lb = logical_block(blockIdx.x, gridDim.x);
     const int Ls = g.Ls;
@@ -638,25 +635,12 @@ __global__ void __launch_bounds__(WG) dslash_dwf_kernel(FineGeom g, const C2<T>*
     const int lsite = gid / Ls;
     const int s = gid - lsite * Ls;
     const Site st = traverse(g, lsite);
-    Nbrs<T> n = neighbours<T>(g, st);
-    if constexpr (CLS) {
-        // keep a hop only if its class is the selected one
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const int lx = st.x[mu] % cs.B[mu];
-            const bool keep_f = (lx == cs.B[mu] - 1) ? (cs.cls == 1 + mu) : (cs.cls == 0);
-            const bool keep_b = (lx == 0) ? (cs.cls == 5 + mu) : (cs.cls == 0);
-            n.cf[mu] = keep_f ? n.cf[mu] : (T)0;
-            n.cb[mu] = keep_b ? n.cb[mu] : (T)0;
-        }
-    }
+    const Nbrs<T> n = neighbours<T>(g, st);
     C2<T> acc[12];
     {
-        // the diagonal and fifth-dimension terms belong to hop class 0
-        const T keep = (!CLS || cs.cls == 0) ? (T)1 : (T)0;
-        const T diag = keep * (T)g.diag, mf = keep * (T)g.mf;
-        const T cm = (s == 0) ? mf : -keep;
-        const T cp = (s == Ls - 1) ? mf : -keep;
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (s == 0) ? mf : (T)-1;
+        const T cp = (s == Ls - 1) ? mf : (T)-1;
         const uint32_t o0 = (uint32_t)(st.site * Ls + s) * CB;
         const uint32_t om = (uint32_t)(st.site * Ls + (s == 0 ? Ls - 1 : s - 1)) * CB;
         const uint32_t op = (uint32_t)(st.site * Ls + (s == Ls - 1 ? 0 : s + 1)) * CB;
@@ -690,11 +674,83 @@ void launch_tile(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out,
     hipLaunchKernelGGL((dslash_tile_kernel<T, LS, NT, NY>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, ep);
 }
 
-template <typename T, bool CLS, int NY>
-void launch_generic(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s,
-                    ClassSel cs = ClassSel{{1, 1, 1, 1}, -1}) {
+template <typename T, int NY>
+void launch_generic(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, const Epi<T>& ep, hipStream_t s) {
     const int blocks = (g.N5 + WG - 1) / WG;
-    hipLaunchKernelGGL((dslash_dwf_kernel<T, CLS, NY>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, cs, ep);
+    hipLaunchKernelGGL((dslash_dwf_kernel<T, NY>), dim3(blocks), dim3(WG), 0, s, g, U, in, out, ep);
+}
+
+// All nine hop classes of the coarse build in one FP64 pass: class field d is
+// out + d * fstride.  d = 0 gets the diagonal, fifth-dimension and block-interior
+// hop terms at every site; d = 1 + mu (5 + mu) gets the forward (backward) mu hop
+// that crosses the face of the site's block, written only at the sites on that
+// face, where the projection reads it (elsewhere the class field is not
+// written).  Each output is H's output element: lower spins negated, at s ->
+// Ls - 1 - s.
+__global__ void __launch_bounds__(WG) dslash_classes_kernel(FineGeom g, ClassSel cs, const double2* U,
+                                                            const double2* in, double2* out, size_t fstride) {
+    typedef double T;
+    constexpr uint32_t CB = sizeof(double2);
+    const int lb = logical_block(blockIdx.x, gridDim.x);
+    const int Ls = g.Ls;
+    const int gid = lb * WG + threadIdx.x;
+    if (gid >= g.N5) return;
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    const int lsite = gid / Ls;
+    const int s = gid - lsite * Ls;
+    const Site st = traverse(g, lsite);
+    const Nbrs<T> n = neighbours<T>(g, st);
+    const uint32_t oo = (uint32_t)(st.site * Ls + (Ls - 1 - s)) * CB;
+    const Epi<T> none{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0, 0};
+    C2<T> acc[12];
+    {
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (s == 0) ? mf : (T)-1;
+        const T cp = (s == Ls - 1) ? mf : (T)-1;
+        const uint32_t o0 = (uint32_t)(st.site * Ls + s) * CB;
+        const uint32_t om = (uint32_t)(st.site * Ls + (s == 0 ? Ls - 1 : s - 1)) * CB;
+        const uint32_t op = (uint32_t)(st.site * Ls + (s == Ls - 1 ? 0 : s + 1)) * CB;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const C2<T> v = Buf<T>::ld(f.in, o0, (uint32_t)c * f.cstride);
+            const C2<T> w = Buf<T>::ld(f.in, (c < 6) ? om : op, (uint32_t)c * f.cstride);
+            const T cw = (c < 6) ? cm : cp;
+            acc[c] = mk<T>(fma(diag, v.x, cw * w.x), fma(diag, v.y, cw * w.y));
+        }
+    }
+    // a hop term into tmp, then either into class 0 or out to its face class
+    auto route = [&](const C2<T> (&tmp)[12], bool face, int cls) {
+        if (face) {
+            f.out = make_rsrc(out + (size_t)cls * fstride, 12u * f.cstride);
+            store_out<T, 0, false>(f, oo, none, tmp);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = cadd<T>(acc[c], tmp[c]);
+        }
+    };
+#define HDCR_CLASS_HOPS(MU)                                                                                \
+    {                                                                                                      \
+        const int lx = st.x[MU] % cs.B[MU];                                                                \
+        C2<T> u[9], tmp[12];                                                                               \
+        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)st.site * (36u * CB), (uint32_t)(MU * 9 + e) * CB); \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) tmp[c] = mk<T>(0, 0);                               \
+        hop<T, MU, true>(f, (uint32_t)(n.f[MU] * Ls + s) * CB, u, n.cf[MU], tmp);                          \
+        route(tmp, lx == cs.B[MU] - 1, 1 + MU);                                                            \
+        for (int e = 0; e < 9; ++e) u[e] = Buf<T>::ld(f.U, (uint32_t)n.b[MU] * (36u * CB), (uint32_t)(MU * 9 + e) * CB); \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) tmp[c] = mk<T>(0, 0);                               \
+        hop<T, MU, false>(f, (uint32_t)(n.b[MU] * Ls + s) * CB, u, n.cb[MU], tmp);                         \
+        route(tmp, lx == 0, 5 + MU);                                                                       \
+    }
+    HDCR_CLASS_HOPS(0)
+    HDCR_CLASS_HOPS(1)
+    HDCR_CLASS_HOPS(2)
+    HDCR_CLASS_HOPS(3)
+#undef HDCR_CLASS_HOPS
+    f.out = make_rsrc(out, 12u * f.cstride);
+    store_out<T, 0, false>(f, oo, none, acc);
 }
 
 template <typename T, bool NT, int NY>
@@ -762,7 +818,7 @@ void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, c
             return;
         }
     }
-    launch_generic<T, false, NY>(g, U, in, out, ep, s);
+    launch_generic<T, NY>(g, U, in, out, ep, s);
 }
 
 }  // namespace
@@ -795,13 +851,12 @@ bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void*
 
 bool dslash_h16_ok(const FineGeom& g) { return par_ok(g); }
 
-void launch_dslash_class(const CoarseGeom& c, const double2* U, const double2* in, double2* out, int cls,
-                         hipStream_t s) {
+void launch_dslash_classes(const CoarseGeom& c, const double2* U, const double2* in, double2* out, size_t fstride,
+                           hipStream_t s) {
     ClassSel cs;
     for (int mu = 0; mu < 4; ++mu) cs.B[mu] = c.B[mu];
-    cs.cls = cls;
-    launch_generic<double, true, 0>(c.f, U, in, out, Epi<double>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0, 0},
-                                    s, cs);
+    const int blocks = (c.f.N5 + WG - 1) / WG;
+    hipLaunchKernelGGL(dslash_classes_kernel, dim3(blocks), dim3(WG), 0, s, c.f, cs, U, in, out, fstride);
 }
 
 template void launch_dslash<double>(const FineGeom&, const double2*, const double2*, double2*, hipStream_t);
