@@ -35,9 +35,10 @@
  * Ownership: the caller owns every buffer.  The library never allocates or
  * frees device memory; scratch space comes in through (work, work_bytes),
  * sized by hdcr_workspace_bytes().  Every call except hdcr_solve,
- * hdcr_coarse_solve, hdcr_build_deflation, hdcr_make_subspace, hdcr_power_max
- * and hdcr_vec_dot is stream-ordered and returns before the work is done;
- * those six return after it has completed.
+ * hdcr_coarse_solve, hdcr_build_deflation, hdcr_make_subspace,
+ * hdcr_make_subspace_degrees, hdcr_power_max and hdcr_vec_dot is stream-ordered
+ * and returns before the work is done; those seven return after it has
+ * completed.
  * In and out buffers of one call must not overlap.
  *
  * Errors: 0 = success.  Negative codes are caller errors found before any
@@ -350,6 +351,18 @@ HDCR_API size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_d
 HDCR_API int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nvec, int32_t degree, double lo,
                        double hi, const void* U, const void* noise, void* vecs, void* work, size_t work_bytes,
                        hipStream_t stream);
+
+/* Several filter degrees from one recurrence per noise field (Sec. 5 notes that
+ * the Chebyshev recurrence yields every lower order along the way at no extra
+ * cost): vecs[k * ndeg + q] = T_{degrees[q]}(yhat) noise[k] / |.| for k < nnoise,
+ * q < ndeg, with yhat as for hdcr_make_subspace; degrees (host, ndeg entries)
+ * strictly ascending in [0, 100000].  Each output equals hdcr_make_subspace's at
+ * that degree up to rounding.  noise: nnoise C128 fields, vecs: nnoise * ndeg
+ * C128 fields (not overlapping noise); U: C128; computed in dtype (C128 or
+ * C64).  work: hdcr_subspace_workspace_bytes().  Synchronous. */
+HDCR_API int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nnoise, int32_t ndeg,
+                                        const int32_t* degrees, double lo, double hi, const void* U, const void* noise,
+                                        void* vecs, void* work, size_t work_bytes, hipStream_t stream);
 
 /* Power-iteration estimate of the largest eigenvalue of H^2 (Rayleigh quotient
  * after `iters` steps from v0); C128.  work: hdcr_subspace_workspace_bytes(desc,

@@ -25,7 +25,7 @@ from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_
 __all__ = ["Lattice", "apply_fine", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
-           "HDCRError", "Deflation", "build_deflation", "coarse_solve"]
+           "HDCRError", "Deflation", "build_deflation", "coarse_solve", "make_subspace_degrees"]
 
 load = _abi.load
 
@@ -468,6 +468,25 @@ def make_subspace(lat: Lattice, U, noise, degree, lo, hi, dtype=C64, work=None, 
     _abi.check(lib.hdcr_make_subspace(ctypes.byref(d), int(dtype), int(noise.shape[0]), int(degree), float(lo),
                                       float(hi), _ptr(U), _ptr(noise), _ptr(out), _ptr(work), work.numel(),
                                       _stream(stream)), "hdcr_make_subspace")
+    return out
+
+
+def make_subspace_degrees(lat: Lattice, U, noise, degrees, lo, hi, dtype=C64, work=None, stream=None):
+    """Normalised T_d(yhat) noise[k] for every d in degrees (ascending) from one recurrence per
+    noise field; noise: complex128 [nnoise, 12, V4, Ls].  Returns [nnoise * len(degrees), 12, V4, Ls],
+    field k * len(degrees) + q holding degree degrees[q] of noise k."""
+    torch = _torch()
+    lib = load()
+    d = lat.fine_desc()
+    degs = [int(x) for x in degrees]
+    nn = int(noise.shape[0])
+    out = torch.empty((nn * len(degs),) + tuple(noise.shape[1:]), dtype=noise.dtype, device=noise.device)
+    if work is None:
+        work = _workspace(lib.hdcr_subspace_workspace_bytes(ctypes.byref(d), int(dtype)), noise.device)
+    arr = (ctypes.c_int32 * len(degs))(*degs)
+    _abi.check(lib.hdcr_make_subspace_degrees(ctypes.byref(d), int(dtype), nn, len(degs), arr, float(lo), float(hi),
+                                              _ptr(U), _ptr(noise), _ptr(out), _ptr(work), work.numel(),
+                                              _stream(stream)), "hdcr_make_subspace_degrees")
     return out
 
 

@@ -106,6 +106,9 @@ PROTOTYPES = {
     "hdcr_subspace_workspace_bytes": (_sz, [ctypes.POINTER(FineDesc), _i32]),
     "hdcr_make_subspace": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _i32, _i32, ctypes.c_double,
                                           ctypes.c_double, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "hdcr_make_subspace_degrees": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _i32, _i32,
+                                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double,
+                                                  _vp, _vp, _vp, _vp, _sz, _vp]),
     "hdcr_power_max": (ctypes.c_int, [ctypes.POINTER(FineDesc), _vp, _vp, _i32, _dbl_p, _vp, _sz, _vp]),
 }
 

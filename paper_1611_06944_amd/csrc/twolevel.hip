@@ -707,19 +707,23 @@ int vcycle_apply(const CoarseGeom& c, const hdcr_solve_params* p, const double2*
 // ---------------------------------------------------------------------------
 // subspace generation: Chebyshev low-pass filter of Gaussian noise (Sec. 4)
 // ---------------------------------------------------------------------------
-// returns the buffer (one of t0, t1, wv) that holds the result
-template <typename T>
+// T_d(yhat) eta with yhat = (2 H^2 - hi - lo)/(hi - lo) for d = degree; emit(buf, j)
+// is called with the buffer holding T_j eta (times a positive constant) for
+// every j <= degree, after step j.  The pair (t0, t1) is rescaled every 16
+// steps (the recurrence is linear) so FP32 cannot overflow.  Returns the buffer
+// (one of t0, t1) that holds the result.
+template <typename T, typename Emit>
 C2<T>* cheb_filter(const FineGeom& g, const C2<T>* U, int degree, double lo, double hi, C2<T>* t0, C2<T>* t1,
-                   C2<T>* v, C2<T>* wv, double* part, double* S, hipStream_t s) {
-    // T_d(yhat) eta with yhat = (2 H^2 - hi - lo)/(hi - lo); the pair (t0, t1) is
-    // rescaled every 16 steps (the recurrence is linear) so FP32 cannot overflow
+                   C2<T>* v, C2<T>* wv, double* part, double* S, hipStream_t s, Emit emit) {
     const int64_t n = 12LL * g.N5;
+    emit(t0, 0);
     if (degree == 0) return t0;
     const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
     // the combinations ride in the epilogue of the second stencil pass
     launch_dslash<T>(g, U, t0, v, s);
     launch_dslash_epi<T>(g, U, v, wv, Epi<T>{{t0, nullptr, nullptr, nullptr}, {(T)b1, 0, 0, 0}, (T)a1, 1}, s);
     std::swap(t1, wv);                              // t1 = T_1 = yhat t0
+    emit(t1, 1);
     const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
     for (int j = 2; j <= degree; ++j) {
         // t0 <- 2 yhat t1 - t0 = a2 H (H t1) + b2 t1 - t0 (in place)
@@ -731,8 +735,48 @@ C2<T>* cheb_filter(const FineGeom& g, const C2<T>* U, int degree, double lo, dou
             launch_scale_inv_sqrt<T>(n, t0, S, 0, s);
             launch_scale_inv_sqrt<T>(n, t1, S, 0, s);
         }
+        emit(t1, j);
     }
     return t1;
+}
+
+// Filters nnoise noise fields and writes the normalised T_d eta for each degree
+// d in degrees (ascending) to out[k * ndeg + q] (FP64); the arithmetic of the
+// recurrence is T's.
+template <typename T>
+int make_subspace_degrees(const FineGeom& g, const double2* U, const double2* noise, int nnoise, const int* degrees,
+                          int ndeg, double lo, double hi, double2* out, void* work, size_t work_bytes, hipStream_t s) {
+    const int64_t n = 12LL * g.N5;
+    Carver w(work, work_bytes);
+    const C2<T>* Uin;
+    if constexpr (sizeof(T) == 4) {
+        float2* U32 = w.take<float2>((size_t)36 * g.V4);
+        launch_convert<double2, float2>(36LL * g.V4, U, U32, s);
+        Uin = U32;
+    } else {
+        Uin = U;
+    }
+    C2<T>* b[4];
+    for (int i = 0; i < 4; ++i) b[i] = w.take<C2<T>>(n);
+    double* part = w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+    double* S = w.take<double>(64);
+    if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_make_subspace: workspace too small");
+    for (int k = 0; k < nnoise; ++k) {
+        launch_convert<double2, C2<T>>(n, noise + k * n, b[0], s);
+        int q = 0;
+        double2* dst = out + (size_t)k * ndeg * n;
+        cheb_filter<T>(g, Uin, degrees[ndeg - 1], lo, hi, b[0], b[1], b[2], b[3], part, S, s,
+                       [&](const C2<T>* t, int j) {
+                           if (q < ndeg && degrees[q] == j) {
+                               // a normalised FP64 copy; the recurrence keeps its own scale
+                               launch_convert<C2<T>, double2>(n, t, dst + (size_t)q * n, s);
+                               launch_norm2<double>(n, dst + (size_t)q * n, part, S, 1, s);
+                               launch_scale_inv_sqrt<double>(n, dst + (size_t)q * n, S, 1, s);
+                               ++q;
+                           }
+                       });
+    }
+    return HDCR_OK;
 }
 
 }  // namespace hdcr
@@ -843,7 +887,8 @@ int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nve
         launch_convert<double2, float2>(36LL * g.V4, (const double2*)U, U32, stream);
         for (int k = 0; k < nvec; ++k) {
             launch_convert<double2, float2>(n, nz + k * n, b[0], stream);
-            float2* res = cheb_filter<float>(g, U32, degree, lo, hi, b[0], b[1], b[2], b[3], part, S, stream);
+            float2* res = cheb_filter<float>(g, U32, degree, lo, hi, b[0], b[1], b[2], b[3], part, S, stream,
+                                             [](const float2*, int) {});
             launch_norm2<float>(n, res, part, S, 1, stream);
             launch_scale_inv_sqrt<float>(n, res, S, 1, stream);
             launch_convert<float2, double2>(n, res, out + k * n, stream);
@@ -856,12 +901,46 @@ int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nve
         for (int k = 0; k < nvec; ++k) {
             launch_convert<double2, double2>(n, nz + k * n, b[0], stream);
             double2* res = cheb_filter<double>(g, (const double2*)U, degree, lo, hi, b[0], b[1], b[2], b[3], part, S,
-                                               stream);
+                                               stream, [](const double2*, int) {});
             launch_norm2<double>(n, res, part, S, 1, stream);
             launch_scale_inv_sqrt<double>(n, res, S, 1, stream);
             launch_convert<double2, double2>(n, res, out + k * n, stream);
         }
     }
+    HDCR_HIP_CHECK(hipGetLastError());
+    HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+    return HDCR_OK;
+}
+
+int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nnoise, int32_t ndeg,
+                               const int32_t* degrees, double lo, double hi, const void* U, const void* noise, void* vecs,
+                               void* work, size_t work_bytes, hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64)
+        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: dtype C128 or C64");
+    if (nnoise < 1 || ndeg < 1 || !degrees || !(hi > lo))
+        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: bad args");
+    for (int q = 0; q < ndeg; ++q)
+        if (degrees[q] < 0 || degrees[q] > 100000 || (q > 0 && degrees[q] <= degrees[q - 1]))
+            return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: degrees must be ascending, in [0, 100000]");
+    if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(noise, 16, "noise")) || (e = check_ptr(vecs, 16, "vecs")) ||
+        (e = check_ptr(work, 256, "work")))
+        return e;
+    const FineGeom g = make_geom(desc);
+    const size_t fbytes = (size_t)12 * g.N5 * 16;
+    if (overlap(noise, fbytes * nnoise, vecs, fbytes * nnoise * ndeg))
+        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: noise and vecs overlap");
+    if (work_bytes < hdcr_subspace_workspace_bytes(desc, dtype))
+        return fail(HDCR_ENOMEM, "hdcr_make_subspace_degrees: workspace too small");
+    const std::vector<int> deg(degrees, degrees + ndeg);
+    if (dtype == HDCR_C64)
+        e = make_subspace_degrees<float>(g, (const double2*)U, (const double2*)noise, nnoise, deg.data(), ndeg, lo, hi,
+                                         (double2*)vecs, work, work_bytes, stream);
+    else
+        e = make_subspace_degrees<double>(g, (const double2*)U, (const double2*)noise, nnoise, deg.data(), ndeg, lo,
+                                          hi, (double2*)vecs, work, work_bytes, stream);
+    if (e) return e;
     HDCR_HIP_CHECK(hipGetLastError());
     HDCR_HIP_CHECK(hipStreamSynchronize(stream));
     return HDCR_OK;

@@ -54,6 +54,35 @@ def test_subspace_filter_and_power_parity():
             assert max_rel_elem(hd.unpack_fermion(out[k], L, Ls), ref[k]) <= tol, (dt, k)
 
 
+def test_subspace_degrees_parity():
+    """Several degrees from one recurrence per noise field (hdcr_make_subspace_degrees) against the
+    oracle's filter at each degree: degree 0 and 1, and both sides of a rescaling step (16, 17)."""
+    torch = torch_dev()
+    L, Ls = (4, 4, 4, 4), 8
+    log("subspace filter, several degrees per recurrence")
+    p, _, lat = _lat(L, Ls)
+    U = hi.gauge_field(L)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    lam = oracle.power_max(ap, hi.gaussian_fermion(L, Ls, seed=99), iters=25)
+    lo, hi_ = 0.05 * lam, 1.1 * lam
+    noise = hi.subspace_noise(L, Ls, 2)
+    degrees = [0, 1, 5, 16, 17, 40]
+    Ud = to_dev(hd.pack_gauge(U))
+    nd = to_dev(np.stack([hd.pack_fermion(e) for e in noise]))
+    for dt, tol in ((hd.C128, 1e-10), (hd.C64, 1e-5)):
+        out = to_host(hd.make_subspace_degrees(lat, Ud, nd, degrees, lo, hi_, dtype=dt))
+        for k in range(2):
+            for q, deg in enumerate(degrees):
+                ref = oracle.cheby_filter(ap, noise[k], deg, lo, hi_)
+                got = hd.unpack_fermion(out[k * len(degrees) + q], L, Ls)
+                assert max_rel_elem(got, ref) <= tol, (dt, k, deg)
+    # the last degree agrees with the one-degree entry point
+    one = to_host(hd.make_subspace(lat, Ud, nd, 40, lo, hi_, dtype=hd.C128))
+    many = to_host(hd.make_subspace_degrees(lat, Ud, nd, degrees, lo, hi_, dtype=hd.C128))
+    for k in range(2):
+        assert max_rel_elem(many[k * len(degrees) + len(degrees) - 1], one[k]) <= 1e-14
+
+
 def _coarse(L, Ls, block, nvec, p, cs, U, filtered=True):
     ap = lambda f: oracle.apply_h(U, f, p)
     if filtered:
