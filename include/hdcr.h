@@ -345,8 +345,11 @@ HDCR_API int hdcr_build_deflation(const hdcr_coarse_desc* desc, hdcr_dtype A_dty
 /* Subspace generation (Sec. 4, Fig. 1): vecs[k] = T_degree(yhat) noise[k] / |.|
  * with yhat = (2 H^2 - hi - lo)/(hi - lo): the Chebyshev low-pass filter that
  * leaves the modes with lo <= lambda^2 <= hi bounded by 1 and amplifies those
- * below lo.  noise, vecs: nvec C128 fields; U: C128; computed in dtype (C128 or
- * C64).  work: hdcr_subspace_workspace_bytes().  Synchronous. */
+ * below lo.  noise, vecs: nvec C128 fields; U: C128; computed in dtype: C128, C64,
+ * or F16C (FP32 links and arithmetic, the recurrence's fields stored as (fp16 re,
+ * fp16 im), brought to unit RMS per entry at the start and every 16 steps;
+ * Ls = 16 and even extents).  work: hdcr_subspace_workspace_bytes().
+ * Synchronous. */
 HDCR_API size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_dtype dtype);
 HDCR_API int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nvec, int32_t degree, double lo,
                        double hi, const void* U, const void* noise, void* vecs, void* work, size_t work_bytes,
@@ -358,8 +361,9 @@ HDCR_API int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, in
  * q < ndeg, with yhat as for hdcr_make_subspace; degrees (host, ndeg entries)
  * strictly ascending in [0, 100000].  Each output equals hdcr_make_subspace's at
  * that degree up to rounding.  noise: nnoise C128 fields, vecs: nnoise * ndeg
- * C128 fields (not overlapping noise); U: C128; computed in dtype (C128 or
- * C64).  work: hdcr_subspace_workspace_bytes().  Synchronous. */
+ * C128 fields (not overlapping noise); U: C128; computed in dtype (C128, C64 or
+ * F16C, as for hdcr_make_subspace).  work: hdcr_subspace_workspace_bytes().
+ * Synchronous. */
 HDCR_API int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nnoise, int32_t ndeg,
                                         const int32_t* degrees, double lo, double hi, const void* U, const void* noise,
                                         void* vecs, void* work, size_t work_bytes, hipStream_t stream);

@@ -779,6 +779,72 @@ int make_subspace_degrees(const FineGeom& g, const double2* U, const double2* no
     return HDCR_OK;
 }
 
+// The same with FP16 storage of the recurrence's fields (Ls = 16, even extents):
+// the noise is scaled to unit RMS per entry before rounding, and the pair (t0,
+// t1) is brought back to unit RMS every 16 steps (the recurrence is linear and
+// the outputs are normalised), so the FP16 range holds the growth of the low
+// modes.  Each step: two FP16 stencil passes and one element-wise combination.
+int make_subspace_degrees_h16(const FineGeom& g, const double2* U, const double2* noise, int nnoise,
+                              const int* degrees, int ndeg, double lo, double hi, double2* out, void* work,
+                              size_t work_bytes, hipStream_t s) {
+    const int64_t n = 12LL * g.N5;
+    Carver w(work, work_bytes);
+    float2* U32 = w.take<float2>((size_t)36 * g.V4);
+    float2* f32 = w.take<float2>(n);
+    void* h[4];
+    for (int i = 0; i < 4; ++i) h[i] = w.take<uint32_t>(n);
+    double* part = w.take<double>(REDUCE_BLOCKS * (2 * MAXV + 1));
+    double* S = w.take<double>(64);
+    if (!w.ok()) return fail(HDCR_ENOMEM, "hdcr_make_subspace: workspace too small");
+    launch_convert<double2, float2>(36LL * g.V4, U, U32, s);
+    const double a1 = 2.0 / (hi - lo), b1 = -(hi + lo) / (hi - lo);
+    const double a2 = 4.0 / (hi - lo), b2 = -2.0 * (hi + lo) / (hi - lo);
+    const int degree = degrees[ndeg - 1];
+    for (int k = 0; k < nnoise; ++k) {
+        launch_convert<double2, float2>(n, noise + k * n, f32, s);
+        launch_norm2<float>(n, f32, part, S, 0, s);
+        void *t0 = h[0], *t1 = h[1], *v = h[2], *wv = h[3];
+        launch_to_h16_scaled(n, f32, S, 0, t0, s);
+        int q = 0;
+        double2* dst = out + (size_t)k * ndeg * n;
+        auto emit = [&](const void* t, int j) {
+            if (q < ndeg && degrees[q] == j) {
+                launch_h16_to_c128(n, t, dst + (size_t)q * n, s);
+                launch_norm2<double>(n, dst + (size_t)q * n, part, S, 1, s);
+                launch_scale_inv_sqrt<double>(n, dst + (size_t)q * n, S, 1, s);
+                ++q;
+            }
+        };
+        emit(t0, 0);
+        if (degree == 0) continue;
+        // t1 = yhat t0 = a1 H (H t0) + b1 t0
+        launch_dslash_h16(g, U32, t0, v, s);
+        launch_dslash_h16(g, U32, v, wv, s);
+        {
+            const void* z[4] = {t0, nullptr, nullptr, nullptr};
+            const float gz[4] = {(float)b1, 0, 0, 0};
+            launch_h16_combine(n, (float)a1, wv, z, gz, 1, t1, s);
+        }
+        emit(t1, 1);
+        for (int j = 2; j <= degree; ++j) {
+            // t0 <- 2 yhat t1 - t0 = a2 H (H t1) + b2 t1 - t0 (in place)
+            launch_dslash_h16(g, U32, t1, v, s);
+            launch_dslash_h16(g, U32, v, wv, s);
+            const void* z[4] = {t1, t0, nullptr, nullptr};
+            const float gz[4] = {(float)b2, -1.0f, 0, 0};
+            launch_h16_combine(n, (float)a2, wv, z, gz, 2, t0, s);
+            std::swap(t0, t1);
+            if (j % 16 == 0) {
+                launch_h16_norm2(n, t1, part, S, 0, s);
+                launch_h16_scale_rms(n, t0, S, 0, s);
+                launch_h16_scale_rms(n, t1, S, 0, s);
+            }
+            emit(t1, j);
+        }
+    }
+    return HDCR_OK;
+}
+
 }  // namespace hdcr
 
 using namespace hdcr;
@@ -853,6 +919,10 @@ size_t hdcr_subspace_workspace_bytes(const hdcr_fine_desc* desc, hdcr_dtype dtyp
     if (dtype == HDCR_C64) {
         w.take<float2>((size_t)36 * g.V4);
         for (int i = 0; i < 4; ++i) w.take<float2>(n);
+    } else if (dtype == HDCR_F16C) {
+        w.take<float2>((size_t)36 * g.V4);
+        w.take<float2>(n);
+        for (int i = 0; i < 4; ++i) w.take<uint32_t>(n);
     } else {
         for (int i = 0; i < 4; ++i) w.take<double2>(n);
     }
@@ -866,7 +936,8 @@ int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nve
                        hipStream_t stream) {
     int e = check_fine_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_make_subspace: dtype C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_make_subspace: dtype C128, C64 or F16C");
     if (nvec < 1 || degree < 0 || degree > 100000 || !(hi > lo)) return fail(HDCR_EINVAL, "hdcr_make_subspace: bad args");
     if ((e = check_ptr(U, 16, "U")) || (e = check_ptr(noise, 16, "noise")) || (e = check_ptr(vecs, 16, "vecs")) ||
         (e = check_ptr(work, 256, "work")))
@@ -878,7 +949,12 @@ int hdcr_make_subspace(const hdcr_fine_desc* desc, hdcr_dtype dtype, int32_t nve
     Carver w(work, work_bytes);
     const double2* nz = static_cast<const double2*>(noise);
     double2* out = static_cast<double2*>(vecs);
-    if (dtype == HDCR_C64) {
+    if (dtype == HDCR_F16C) {
+        if (!dslash_h16_ok(g)) return fail(HDCR_EINVAL, "hdcr_make_subspace: F16C needs Ls = 16 and even extents");
+        if ((e = make_subspace_degrees_h16(g, (const double2*)U, nz, nvec, &degree, 1, lo, hi, out, work, work_bytes,
+                                           stream)))
+            return e;
+    } else if (dtype == HDCR_C64) {
         float2* U32 = w.take<float2>((size_t)36 * g.V4);
         float2* b[4];
         for (int i = 0; i < 4; ++i) b[i] = w.take<float2>(n);
@@ -917,8 +993,8 @@ int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype dtype, int
                                void* work, size_t work_bytes, hipStream_t stream) {
     int e = check_fine_desc(desc);
     if (e) return e;
-    if (dtype != HDCR_C128 && dtype != HDCR_C64)
-        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: dtype C128 or C64");
+    if (dtype != HDCR_C128 && dtype != HDCR_C64 && dtype != HDCR_F16C)
+        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: dtype C128, C64 or F16C");
     if (nnoise < 1 || ndeg < 1 || !degrees || !(hi > lo))
         return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: bad args");
     for (int q = 0; q < ndeg; ++q)
@@ -933,8 +1009,13 @@ int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype dtype, int
         return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: noise and vecs overlap");
     if (work_bytes < hdcr_subspace_workspace_bytes(desc, dtype))
         return fail(HDCR_ENOMEM, "hdcr_make_subspace_degrees: workspace too small");
+    if (dtype == HDCR_F16C && !dslash_h16_ok(g))
+        return fail(HDCR_EINVAL, "hdcr_make_subspace_degrees: F16C needs Ls = 16 and even extents");
     const std::vector<int> deg(degrees, degrees + ndeg);
-    if (dtype == HDCR_C64)
+    if (dtype == HDCR_F16C)
+        e = make_subspace_degrees_h16(g, (const double2*)U, (const double2*)noise, nnoise, deg.data(), ndeg, lo, hi,
+                                      (double2*)vecs, work, work_bytes, stream);
+    else if (dtype == HDCR_C64)
         e = make_subspace_degrees<float>(g, (const double2*)U, (const double2*)noise, nnoise, deg.data(), ndeg, lo, hi,
                                          (double2*)vecs, work, work_bytes, stream);
     else

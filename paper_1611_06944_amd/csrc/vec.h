@@ -49,6 +49,13 @@ void launch_from_h16_scaled(int64_t n, const void* y, const double* S, int idx, 
 void launch_h16_combine(int64_t n, float beta, const void* x, const void* const z[4], const float g[4], int ny, void* y,
                         hipStream_t s);
 
+// FP16-stored fields: S[idx] = |x|^2 (FP64 accumulation, fixed order; part:
+// REDUCE_BLOCKS doubles); x <- sqrt(n / S[idx]) x (unit RMS per entry; unchanged
+// when S[idx] is 0); out (C128) = x
+void launch_h16_norm2(int64_t n, const void* x, double* part, double* S, int idx, hipStream_t s);
+void launch_h16_scale_rms(int64_t n, void* x, const double* S, int idx, hipStream_t s);
+void launch_h16_to_c128(int64_t n, const void* x, double2* out, hipStream_t s);
+
 // S[idx] = |x|^2 (FP64 accumulation, fixed order); part: REDUCE_BLOCKS doubles
 template <typename T> void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s);
 // x <- x / sqrt(S[idx])

@@ -242,7 +242,54 @@ __global__ void __launch_bounds__(VWG) h16_combine_kernel(int64_t n2, float beta
     }
 }
 
+// partial |x|^2 over pairs of complex entries (FP64 accumulation)
+__global__ void __launch_bounds__(REDUCE_THREADS) h16_norm2_kernel(int64_t n2, const uint2_t* __restrict__ x,
+                                                                   double* __restrict__ part) {
+    double v[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+        const half4_t h = __builtin_bit_cast(half4_t, x[i]);
+        const double a = (float)h.x, b = (float)h.y, c = (float)h.z, d = (float)h.w;
+        v[0] += a * a + b * b + c * c + d * d;
+    }
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(VWG) h16_scale_rms_kernel(int64_t n2, uint2_t* __restrict__ x,
+                                                            const double* __restrict__ S, int idx) {
+    const double nn = S[idx];
+    const float f = nn > 0.0 ? (float)sqrt((double)(2 * n2) / nn) : 1.0f;
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n2; i += (int64_t)gridDim.x * VWG) {
+        const half4_t h = __builtin_bit_cast(half4_t, x[i]);
+        const half4_t o = {(_Float16)(f * (float)h.x), (_Float16)(f * (float)h.y), (_Float16)(f * (float)h.z),
+                           (_Float16)(f * (float)h.w)};
+        x[i] = __builtin_bit_cast(uint2_t, o);
+    }
+}
+
+__global__ void __launch_bounds__(VWG) h16_to_c128_kernel(int64_t n, const uint32_t* __restrict__ x,
+                                                          double2* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
+        const half2_t h = __builtin_bit_cast(half2_t, x[i]);
+        out[i] = make_double2((float)h.x, (float)h.y);
+    }
+}
+
 }  // namespace
+
+void launch_h16_norm2(int64_t n, const void* x, double* part, double* S, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(h16_norm2_kernel, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n / 2,
+                       static_cast<const uint2_t*>(x), part);
+    launch_finalize_real(part, 1, S, idx, -1, -1, -1, s);
+}
+void launch_h16_scale_rms(int64_t n, void* x, const double* S, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(h16_scale_rms_kernel, dim3(vgrid(n / 2)), dim3(VWG), 0, s, n / 2, static_cast<uint2_t*>(x), S,
+                       idx);
+}
+void launch_h16_to_c128(int64_t n, const void* x, double2* out, hipStream_t s) {
+    hipLaunchKernelGGL(h16_to_c128_kernel, dim3(vgrid(n)), dim3(VWG), 0, s, n, static_cast<const uint32_t*>(x), out);
+}
 
 void launch_h16_combine(int64_t n, float beta, const void* x, const void* const z[4], const float g[4], int ny, void* y,
                         hipStream_t s) {

@@ -146,3 +146,37 @@ def test_hdcr_solve_f16_smoother(coarse):
     xh = hd.unpack_fermion(to_host(res[hd.F16C][0]), L, Ls)
     bh = hd.unpack_fermion(to_host(b), L, Ls)
     assert oracle.norm(bh - oracle.apply_h(U, xh, p)) <= 1.01e-8 * oracle.norm(bh)
+
+
+def test_subspace_filter_f16_parity():
+    """The subspace filter with FP16-stored recurrence fields (make_subspace with F16C, and several
+    degrees per recurrence) against the oracle's FP64 filter.  Each step rounds three fields (two
+    stencil passes and the combination) and each rescaling two more; the filter never amplifies an
+    error injected at step j more than it amplifies the signal from step 0, so every rounding
+    contributes at most 2^-11 of the result's scale: (3 d + 2 floor(d / 16)) 2^-11 bounds the
+    element error of the normalised result relative to its largest entry."""
+    torch = torch_dev()
+    L, Ls = (4, 4, 4, 6), 16
+    log("subspace filter f16")
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
+    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01)
+    U = hi.gauge_field(L)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    lam = oracle.power_max(ap, hi.gaussian_fermion(L, Ls, seed=99), iters=25)
+    lo, hi_ = 0.02 * lam, 1.1 * lam
+    noise = hi.subspace_noise(L, Ls, 2)
+    Ud = to_dev(hd.pack_gauge(U))
+    nd = to_dev(np.stack([hd.pack_fermion(e) for e in noise]))
+    degrees = [0, 1, 16, 17, 40]
+    many = to_host(hd.make_subspace_degrees(lat, Ud, nd, degrees, lo, hi_, dtype=hd.F16C))
+    one = to_host(hd.make_subspace(lat, Ud, nd, 40, lo, hi_, dtype=hd.F16C))
+    for k in range(2):
+        for q, deg in enumerate(degrees):
+            ref = oracle.cheby_filter(ap, noise[k], deg, lo, hi_)
+            got = hd.unpack_fermion(many[k * len(degrees) + q], L, Ls)
+            err = max_rel_elem(got, ref)
+            bound = (3 * deg + 2 * (deg // 16) + 1) * U16
+            log(f"  noise {k} degree {deg}: max rel elem {err:.2e} (bound {bound:.2e})")
+            assert err <= bound
+        assert max_rel_elem(hd.unpack_fermion(one[k], L, Ls), hd.unpack_fermion(many[k * len(degrees) + 4], L, Ls)) \
+            <= 1e-12
