@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--nvec", type=int, default=32)
     ap.add_argument("--degree", type=int, default=200, help="Chebyshev filter degree of the subspace set-up")
     ap.add_argument("--cut", type=float, default=0.02, help="filter cut lambda_cut^2 / lambda_max^2")
+    ap.add_argument("--filter-storage", choices=["f32", "f16"], default="f16",
+                    help="field storage of the subspace filter's recurrence (arithmetic FP32 either way)")
     ap.add_argument("--order", type=int, default=10, help="smoother terms (the paper: 10)")
     ap.add_argument("--cheb-lo", type=float, default=0.5,
                     help="smoother interval low end (the paper's ensemble: 1.0; tuned to the synthetic ensemble)")
@@ -239,8 +241,8 @@ def main():
         sub_work = None
         for k in range(args.nvec):
             noise = hi.gaussian_fermion_device(L, Ls, hi.SUBSPACE_SEED0 + k).unsqueeze(0).contiguous()
-            vecs[k:k + 1] = hd.make_subspace(lat, U64, noise, args.degree, args.cut * hi2, hi2, dtype=hd.C64,
-                                             work=sub_work)
+            vecs[k:k + 1] = hd.make_subspace(lat, U64, noise, args.degree, args.cut * hi2, hi2,
+                                             dtype=hd.F16C if args.filter_storage == "f16" else hd.C64, work=sub_work)
             del noise
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -253,6 +255,7 @@ def main():
                             "coarse_tol": args.coarse_tol, "fgcr_restart": args.restart, "inner": "c64",
                             "coarse": "bf16c", "basis_restrict_prolong": args.basis},
                  "lambda_max_sq": round(lam, 4), "filter_degree": args.degree, "nvec": args.nvec,
+                 "filter_storage": args.filter_storage,
                  "subspace_s": round(t1 - t0, 3), "coarse_build_s": round(t2 - t1, 3)}
         progress(f"set-up done: subspace {t1 - t0:.1f} s, coarse build {t2 - t1:.1f} s")
         prm_hdcr = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=hd.BF16C,
