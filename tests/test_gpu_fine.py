@@ -94,6 +94,17 @@ def test_apply_fine_full_size_sampled():
         assert max_rel_elem(got, ref) <= tol, dt
         del Ud, pd, out
         torch.cuda.empty_cache()
+    # FP16 field storage (FP32 links): against the oracle on the same FP16-rounded input, one
+    # rounding of each output component (2^-11 |ref|) plus the FP32 arithmetic (2e-5 max|ref|)
+    psi16 = psi.real.astype(np.float16).astype(np.float64) + 1j * psi.imag.astype(np.float16).astype(np.float64)
+    ref16 = oracle.apply_h_sites(U, psi16, p, sel)
+    p16 = torch.view_as_real(to_dev(pack_fermion(psi16), torch.complex64)).to(torch.float16).contiguous()
+    out16 = apply_fine(lat, to_dev(pack_gauge(U), torch.complex64), p16)
+    o = torch.view_as_complex(out16.to(torch.float32).contiguous()).to("cpu").numpy().astype(np.complex128)
+    got = o[:, sel // Ls, sel % Ls].T.reshape(-1, 4, 3)
+    e = 2e-5 * np.abs(ref16).max()
+    for part in (np.real, np.imag):
+        assert np.all(np.abs(part(got) - part(ref16)) <= 2.0 ** -11 * np.abs(part(ref16)) + e)
 
 
 @pytest.mark.parametrize("Ls", [8, 16])
