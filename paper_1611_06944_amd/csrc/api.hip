@@ -43,11 +43,13 @@ FineGeom make_geom(const hdcr_fine_desc* d) {
     return g;
 }
 
-void choose_traversal(FineGeom& g, int tslab, int ysplit) {
+void choose_traversal(FineGeom& g, int tslab, int ysplit, int xsplit) {
     const int Lt = g.L[3], Ly = g.L[1];
     // tuning overrides (benchmark sweeps only)
     if (const char* e = std::getenv("HDCR_TSLAB")) tslab = std::atoi(e);
     if (const char* e = std::getenv("HDCR_YSPLIT")) ysplit = std::atoi(e);
+    if (const char* e = std::getenv("HDCR_XSPLIT")) xsplit = std::atoi(e);
+    if (xsplit < 1 || g.L[0] % xsplit != 0) xsplit = 1;
     if (tslab <= 0) {
         // one slab per XCD when Lt allows it, else the whole t extent
         tslab = (Lt % NUM_XCD == 0) ? Lt / NUM_XCD : Lt;
@@ -63,6 +65,7 @@ void choose_traversal(FineGeom& g, int tslab, int ysplit) {
     }
     if (Ly % ysplit != 0) ysplit = 1;
     g.tslab = tslab;
+    g.xsplit = xsplit;
     g.ysplit = ysplit;
     g.variant = 0;
     if (const char* e = std::getenv("HDCR_DSLASH_VARIANT")) g.variant = std::atoi(e);

@@ -617,6 +617,156 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
     }
 }
 
+// FP16-storage kernel with four fifth-dimension slices per work-item (Ls = 16,
+// even extents): every field access is one 16-byte run of four (fp16 re, fp16
+// im) entries, and the tile is staged in LDS in its FP16 form (12 KB), so a
+// workgroup of 64 work-items holds one 2^4 tile: work-item (p, k), p the parity
+// pattern of its site, slices 4k .. 4k + 3.  Per slice this issues half the
+// vector-memory instructions of the paired kernel on FP16 fields.  Links,
+// arithmetic and the order of the operations per output are the paired
+// kernel's.  The output quad lands at slices Ls-4-4k .. Ls-1-4k in reverse order.
+constexpr int QUAD_WG = 64;
+typedef _Float16 half2v_t __attribute__((ext_vector_type(2)));
+typedef unsigned uint4_t __attribute__((ext_vector_type(4)));
+
+// slice i (0 .. 3) of a quad word as an FP32 complex entry.  The element goes
+// through a named scalar: this clang reads element 0 whatever the index when
+// __builtin_bit_cast is applied to the subscript of a vector directly.
+__device__ __forceinline__ C2<float> quad_slice(uint4_t w, int i) {
+    const unsigned e = w[i];
+    const half2v_t h = __builtin_bit_cast(half2v_t, e);
+    return mk<float>((float)h.x, (float)h.y);
+}
+
+__global__ void __launch_bounds__(QUAD_WG) __attribute__((amdgpu_waves_per_eu(2)))
+dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* in, uint4_t* out) {
+    typedef float T;
+    constexpr int LS = 16, NQ = LS / 4;
+    constexpr uint32_t CB = 4;  // bytes per complex entry of a field
+    constexpr uint32_t UB = sizeof(float2);
+    __shared__ uint4_t spin[12 * 16 * NQ];  // [c][pattern][k]: slices 4k .. 4k+3, FP16
+    __shared__ float2 lds[16 * 8 * LPAD];   // [pattern][matrix][entry]
+    const int p = threadIdx.x >> 2, k = threadIdx.x & 3;
+    const int s0 = 4 * k;
+    const int tile = logical_block(blockIdx.x, gridDim.x);
+    const Site tt = traverse(tg.t, tile);
+    Site st;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) st.x[mu] = 2 * tt.x[mu] + ((p >> mu) & 1);
+    st.site = ((st.x[3] * g.L[2] + st.x[2]) * g.L[1] + st.x[1]) * g.L[0] + st.x[0];
+    const Nbrs<T> n = neighbours<T>(g, st);
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * UB);
+    // LDS matrix 2 mu: the hop of direction mu inside the tile, 2 mu + 1: the
+    // one leaving it (backward matrices stored conjugate-transposed)
+    for (int e = k; e < 9; e += NQ) {
+        const int r = e / 3, cc = e - 3 * (e / 3);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const bool up = (p >> mu) & 1;
+            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + e) * UB, 0u);
+            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + e) * UB, 0u);
+            lds[(p * 8 + 2 * mu + (up ? 1 : 0)) * LPAD + e] = uf;
+            lds[(p * 8 + 2 * mu + (up ? 0 : 1)) * LPAD + cc * 3 + r] = mk<T>(ub.x, -ub.y);
+        }
+    }
+    uint4_t w[12];  // the four slices of all 12 components, as stored
+    {
+        const uint32_t o0 = (uint32_t)(st.site * LS + s0) * CB;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            w[c] = __builtin_amdgcn_raw_buffer_load_b128(f.in, o0, (uint32_t)c * f.cstride, 0);
+            spin[(c * 16 + p) * NQ + k] = w[c];
+        }
+    }
+    __syncthreads();
+    const C2<T>* lnk = lds + p * 8 * LPAD;
+
+    // diagonal and fifth-dimension terms: upper spins take slice s - 1, lower
+    // spins slice s + 1 (wall coefficient mf at s = 0 and s = Ls - 1); the
+    // slices of the neighbouring quads come from the staged tile in LDS
+    C2<T> a[4][12];
+    {
+        const T diag = (T)g.diag, mf = (T)g.mf;
+        const T cm = (k == 0) ? mf : (T)-1;
+        const T cp = (k == NQ - 1) ? mf : (T)-1;
+        const int kd = (k + NQ - 1) & (NQ - 1), ku = (k + 1) & (NQ - 1);
+        const unsigned* sp = reinterpret_cast<const unsigned*>(spin);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            C2<T> x[6];  // slices s0 - 1 .. s0 + 4
+            x[1] = quad_slice(w[c], 0);
+            x[2] = quad_slice(w[c], 1);
+            x[3] = quad_slice(w[c], 2);
+            x[4] = quad_slice(w[c], 3);
+            if (c < 6) {
+                const half2v_t hw = __builtin_bit_cast(half2v_t, sp[((c * 16 + p) * NQ + kd) * 4 + 3]);
+                x[0] = mk<T>(cm * (float)hw.x, cm * (float)hw.y);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T cl = (i == 0) ? (T)1 : (T)-1;  // the wall coefficient is folded into x[0]
+                    a[i][c] = mk<T>(fma(diag, x[i + 1].x, cl * x[i].x), fma(diag, x[i + 1].y, cl * x[i].y));
+                }
+            } else {
+                const half2v_t hw = __builtin_bit_cast(half2v_t, sp[((c * 16 + p) * NQ + ku) * 4]);
+                x[5] = mk<T>(cp * (float)hw.x, cp * (float)hw.y);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T cl = (i == 3) ? (T)1 : (T)-1;
+                    a[i][c] = mk<T>(fma(diag, x[i + 1].x, cl * x[i + 2].x), fma(diag, x[i + 1].y, cl * x[i + 2].y));
+                }
+            }
+        }
+    }
+#define HDCR_QUAD_HOPS(MU)                                                                                    \
+    {                                                                                                         \
+        const bool up = (p >> MU) & 1;                                                                        \
+        const T sg_in = up ? (T)-1 : (T)1;                                                                    \
+        const int q = p ^ (1 << MU);                                                                          \
+        C2<T> m[9], v[12];                                                                                    \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU) * LPAD + e];                        \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) w[c] = spin[(c * 16 + q) * NQ + k];                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                                       \
+            _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = quad_slice(w[c], i);                        \
+            hop_core_rt<T, MU>(v, m, sg_in, up ? n.cb[MU] : n.cf[MU], a[i]);                                  \
+        }                                                                                                     \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU + 1) * LPAD + e];                    \
+        const uint32_t noff = (uint32_t)((up ? n.f[MU] : n.b[MU]) * LS + s0) * CB;                            \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c)                                                        \
+            w[c] = __builtin_amdgcn_raw_buffer_load_b128(f.in, noff, (uint32_t)c * f.cstride, 0);             \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                                       \
+            _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = quad_slice(w[c], i);                        \
+            hop_core_rt<T, MU>(v, m, -sg_in, up ? n.cf[MU] : n.cb[MU], a[i]);                                 \
+        }                                                                                                     \
+    }
+    // the scheduling barriers keep each direction's loads from being hoisted
+    // above the previous direction's arithmetic (that hoisting spills)
+    HDCR_QUAD_HOPS(0)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_QUAD_HOPS(1)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_QUAD_HOPS(2)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_QUAD_HOPS(3)
+#undef HDCR_QUAD_HOPS
+    // slice s0 + i goes to Ls-1-s0-i: one quad at Ls-4-s0 holding slices
+    // s0+3, s0+2, s0+1, s0; lower spins negated (H = gamma5 R5 D)
+    const uint32_t oo = (uint32_t)(st.site * LS + (LS - 4 - s0)) * CB;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        C2<T> o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = (c < 6) ? a[3 - i][c] : cneg<T>(a[3 - i][c]);
+        const half4_t h0 = {(_Float16)o[0].x, (_Float16)o[0].y, (_Float16)o[1].x, (_Float16)o[1].y};
+        const half4_t h1 = {(_Float16)o[2].x, (_Float16)o[2].y, (_Float16)o[3].x, (_Float16)o[3].y};
+        const uint2_t w0 = __builtin_bit_cast(uint2_t, h0), w1 = __builtin_bit_cast(uint2_t, h1);
+        store_b128<CPOL_NT>(uint4_t{w0.x, w0.y, w1.x, w1.y}, f.out, oo, (uint32_t)c * f.cstride);
+    }
+}
+
 // Generic kernel: any Ls, links and fifth-dimension neighbours loaded
 // directly.
 template <typename T, int NY>
@@ -779,13 +929,18 @@ TileGeom tile_geom(const FineGeom& g) {
         t.t.L[mu] = g.L[mu] / 2;
         t.t.V4 *= t.t.L[mu];
     }
-    // t slabs of about a quarter of the tile extent and y parts of about 6
-    // tile rows (measured best for 12^4 tiles, the 24^4 lattice)
+    // t slabs of about a quarter of the tile extent, x and y parts of about 3
+    // tiles: each block is swept along z with a cross-section of some 27
+    // tiles, so the z and t neighbours of a tile are still in the XCD's L2
+    // when it is processed (measured best for 12^4 tiles, the 24^4 lattice,
+    // among cross-sections of 8 to 216 tiles)
     int ts = t.t.L[3] >= 4 ? t.t.L[3] / 4 : t.t.L[3];
     while (ts > 1 && t.t.L[3] % ts != 0) --ts;
-    int ys = t.t.L[1] / 6 > 0 ? t.t.L[1] / 6 : 1;
+    int ys = t.t.L[1] / 3 > 0 ? t.t.L[1] / 3 : 1;
     while (ys > 1 && t.t.L[1] % ys != 0) --ys;
-    choose_traversal(t.t, ts, ys);
+    int xs = t.t.L[0] / 3 > 0 ? t.t.L[0] / 3 : 1;
+    while (xs > 1 && t.t.L[0] % xs != 0) --xs;
+    choose_traversal(t.t, ts, ys, xs);
     return t;
 }
 
@@ -843,9 +998,14 @@ void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>
 bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void* out, hipStream_t s) {
     if (!par_ok(g)) return false;
     const TileGeom tg = tile_geom(g);
-    hipLaunchKernelGGL((dslash_par2_kernel<0, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U,
-                       static_cast<const float2*>(in), static_cast<float2*>(out),
-                       Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
+    if (g.variant == 5) {  // the paired kernel on FP16 fields (two slices per work-item)
+        hipLaunchKernelGGL((dslash_par2_kernel<0, true>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U,
+                           static_cast<const float2*>(in), static_cast<float2*>(out),
+                           Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
+        return true;
+    }
+    hipLaunchKernelGGL(dslash_quad_h16_kernel, dim3(tg.t.V4), dim3(QUAD_WG), 0, s, g, tg, U,
+                       static_cast<const uint4_t*>(in), static_cast<uint4_t*>(out));
     return true;
 }
 

@@ -123,12 +123,14 @@ struct FineGeom {
     double diag;    // b (4 - M5) + 1 (5 - M5 for the Shamir kernel b = 1)
     double hop;     // -b/2, the coefficient of a 4d hop
     double mf;
-    // traversal order of the stencil kernels (see Traversal in fine.hip):
-    // t is cut into slabs of tslab slices and y into ysplit parts; inside a
-    // slab the order is x, y-part, t, z, so t and z neighbours are a few
-    // rows apart; workgroups are remapped so each XCD sweeps one contiguous
-    // range of that order.
+    // traversal order of the stencil kernels:
+    // t is cut into slabs of tslab slices, x into xsplit and y into ysplit
+    // parts; inside a block the order is x-part, y-part, t, z, so a block is
+    // swept along z with a cross-section of (Lx/xsplit)(Ly/ysplit) tslab
+    // sites, and its t and z neighbours are a few rows apart; workgroups are
+    // remapped so each XCD sweeps one contiguous range of that order.
     int tslab;
+    int xsplit;
     int ysplit;
     int variant;  // fine-stencil kernel variant (0 = default choice)
 };
@@ -152,20 +154,24 @@ struct Site {
     int x[4];
 };
 
-// logical site l -> coordinates, traversal order x, y-part, t-in-slab, z, y-split, t-slab
+// logical site l -> coordinates, traversal order x-part, y-part, t-in-slab, z,
+// x-split, y-split, t-slab
 __device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
     Site tr;
-    const int yq = g.L[1] / g.ysplit;
-    tr.x[0] = l % g.L[0];
-    l /= g.L[0];
+    const int xq = g.L[0] / g.xsplit, yq = g.L[1] / g.ysplit;
+    const int xi = l % xq;
+    l /= xq;
     const int yi = l % yq;
     l /= yq;
     const int ti = l % g.tslab;
     l /= g.tslab;
     tr.x[2] = l % g.L[2];
     l /= g.L[2];
+    const int xo = l % g.xsplit;
+    l /= g.xsplit;
     const int yo = l % g.ysplit;
     l /= g.ysplit;
+    tr.x[0] = xo * xq + xi;
     tr.x[1] = yo * yq + yi;
     tr.x[3] = l * g.tslab + ti;
     tr.site = ((tr.x[3] * g.L[2] + tr.x[2]) * g.L[1] + tr.x[1]) * g.L[0] + tr.x[0];
@@ -173,7 +179,7 @@ __device__ __forceinline__ Site traverse(const FineGeom& g, int l) {
 }
 
 // choose the traversal parameters for a lattice (host)
-void choose_traversal(FineGeom& g, int tslab, int ysplit);
+void choose_traversal(FineGeom& g, int tslab, int ysplit, int xsplit = 1);
 
 FineGeom make_geom(const hdcr_fine_desc* d);
 

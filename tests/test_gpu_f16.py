@@ -1,5 +1,5 @@
-"""GPU parity of the FP16-storage path against the FP64 oracle, through the C-ABI: the paired
-parity-tile stencil reading and writing (fp16 re, fp16 im) fields (FP32 links and arithmetic),
+"""GPU parity of the FP16-storage path against the FP64 oracle, through the C-ABI: the
+parity-tile stencils reading and writing (fp16 re, fp16 im) fields (FP32 links and arithmetic),
 the smoother whose recurrence fields are stored in FP16, and the two-level cycle and HDCR solve
 with that smoother (inner_dtype F16C).
 
@@ -64,6 +64,23 @@ def test_apply_fine_f16_parity(L, bc):
         err = np.abs(part(got) - part(ref))
         assert np.all(err <= U16 * np.abs(part(ref)) + e), float((err - U16 * np.abs(part(ref))).max())
     log(f"  max rel elem {max_rel_elem(got, ref):.2e}")
+
+
+@pytest.mark.parametrize("L,bc", [((4, 4, 2, 6), (1, 1, 1, -1)), ((6, 4, 8, 2), (-1, 1, -1, -1))])
+def test_f16_kernels_agree(L, bc, monkeypatch):
+    """The two FP16-storage kernels (four slices per work-item, the default, and the paired
+    kernel, variant 5) do the same operations in the same order per output: bitwise equal."""
+    torch = torch_dev()
+    Ls = 16
+    log(f"f16 kernels agree L={L} bc={bc}")
+    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01, bc=bc)
+    U = to_dev(hd.pack_gauge(hi.gauge_field(L, seed=5)), torch.complex64)
+    x = _to_f16_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=6)))
+    outs = []
+    for v in ("0", "5"):
+        monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
+        outs.append(hd.apply_fine(lat, U, x))
+    assert torch.equal(outs[0].view(torch.int16), outs[1].view(torch.int16))
 
 
 @pytest.mark.parametrize("order", [2, 3, 10])
