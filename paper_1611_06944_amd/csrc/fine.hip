@@ -638,8 +638,9 @@ __device__ __forceinline__ C2<float> quad_slice(uint4_t w, int i) {
     return mk<float>((float)h.x, (float)h.y);
 }
 
+template <int NY>
 __global__ void __launch_bounds__(QUAD_WG) __attribute__((amdgpu_waves_per_eu(2)))
-dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* in, uint4_t* out) {
+dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* in, uint4_t* out, Epi<float> ep) {
     typedef float T;
     constexpr int LS = 16, NQ = LS / 4;
     constexpr uint32_t CB = 4;  // bytes per complex entry of a field
@@ -753,13 +754,27 @@ dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* 
     HDCR_QUAD_HOPS(3)
 #undef HDCR_QUAD_HOPS
     // slice s0 + i goes to Ls-1-s0-i: one quad at Ls-4-s0 holding slices
-    // s0+3, s0+2, s0+1, s0; lower spins negated (H = gamma5 R5 D)
+    // s0+3, s0+2, s0+1, s0; lower spins negated (H = gamma5 R5 D); epilogue
+    // out = beta H in + sum_i g_i y_i on the FP16-stored y_i
     const uint32_t oo = (uint32_t)(st.site * LS + (LS - 4 - s0)) * CB;
+    __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
+#pragma unroll
+    for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         C2<T> o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] = (c < 6) ? a[3 - i][c] : cneg<T>(a[3 - i][c]);
+        if constexpr (NY > 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = cscale<T>(ep.beta, o[i]);
+#pragma unroll
+            for (int q = 0; q < NY; ++q) {
+                const uint4_t yw = __builtin_amdgcn_raw_buffer_load_b128(yr[q], oo, (uint32_t)c * f.cstride, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) axpy<T>(ep.g[q], quad_slice(yw, i), o[i]);
+            }
+        }
         const half4_t h0 = {(_Float16)o[0].x, (_Float16)o[0].y, (_Float16)o[1].x, (_Float16)o[1].y};
         const half4_t h1 = {(_Float16)o[2].x, (_Float16)o[2].y, (_Float16)o[3].x, (_Float16)o[3].y};
         const uint2_t w0 = __builtin_bit_cast(uint2_t, h0), w1 = __builtin_bit_cast(uint2_t, h1);
@@ -1004,8 +1019,39 @@ bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void*
                            Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
         return true;
     }
-    hipLaunchKernelGGL(dslash_quad_h16_kernel, dim3(tg.t.V4), dim3(QUAD_WG), 0, s, g, tg, U,
-                       static_cast<const uint4_t*>(in), static_cast<uint4_t*>(out));
+    hipLaunchKernelGGL(dslash_quad_h16_kernel<0>, dim3(tg.t.V4), dim3(QUAD_WG), 0, s, g, tg, U,
+                       static_cast<const uint4_t*>(in), static_cast<uint4_t*>(out),
+                       Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
+    return true;
+}
+
+bool launch_dslash_h16_epi(const FineGeom& g, const float2* U, const void* in, void* out, const Epi<float>& e,
+                           hipStream_t s) {
+    if (!par_ok(g) || e.ny < 0 || e.ny > 4) return false;
+    const TileGeom tg = tile_geom(g);
+    if (g.variant == 5) {  // the paired kernel (two slices per work-item, 8-byte accesses)
+        const float2* ip = static_cast<const float2*>(in);
+        float2* op = static_cast<float2*>(out);
+        const dim3 grid(tg.t.V4), block(PAR2_WG);
+        switch (e.ny) {
+            case 0: hipLaunchKernelGGL((dslash_par2_kernel<0, true>), grid, block, 0, s, g, tg, U, ip, op, e); break;
+            case 1: hipLaunchKernelGGL((dslash_par2_kernel<1, true>), grid, block, 0, s, g, tg, U, ip, op, e); break;
+            case 2: hipLaunchKernelGGL((dslash_par2_kernel<2, true>), grid, block, 0, s, g, tg, U, ip, op, e); break;
+            case 3: hipLaunchKernelGGL((dslash_par2_kernel<3, true>), grid, block, 0, s, g, tg, U, ip, op, e); break;
+            default: hipLaunchKernelGGL((dslash_par2_kernel<4, true>), grid, block, 0, s, g, tg, U, ip, op, e); break;
+        }
+        return true;
+    }
+    const uint4_t* ip = static_cast<const uint4_t*>(in);
+    uint4_t* op = static_cast<uint4_t*>(out);
+    const dim3 grid(tg.t.V4), block(QUAD_WG);
+    switch (e.ny) {
+        case 0: hipLaunchKernelGGL(dslash_quad_h16_kernel<0>, grid, block, 0, s, g, tg, U, ip, op, e); break;
+        case 1: hipLaunchKernelGGL(dslash_quad_h16_kernel<1>, grid, block, 0, s, g, tg, U, ip, op, e); break;
+        case 2: hipLaunchKernelGGL(dslash_quad_h16_kernel<2>, grid, block, 0, s, g, tg, U, ip, op, e); break;
+        case 3: hipLaunchKernelGGL(dslash_quad_h16_kernel<3>, grid, block, 0, s, g, tg, U, ip, op, e); break;
+        default: hipLaunchKernelGGL(dslash_quad_h16_kernel<4>, grid, block, 0, s, g, tg, U, ip, op, e); break;
+    }
     return true;
 }
 

@@ -221,11 +221,14 @@ void launch_dslash_epi(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>
                        hipStream_t s);
 // out = H in with FP16 field storage: in and out hold (fp16 re, fp16 im) per
 // complex entry; links FP32, FP32 arithmetic.  Only Ls = 16 with even extents
-// (dslash_h16_ok); returns false otherwise.  No fused epilogue: with FP16
-// operands those variants need more registers than two waves per SIMD allow
-// and ran slower than a plain pass followed by an element-wise combination.
+// (dslash_h16_ok); returns false otherwise.
 bool dslash_h16_ok(const FineGeom& g);
 bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void* out, hipStream_t s);
+// out = beta H in + sum_i g_i y_i with every field FP16-stored (e.y point at
+// FP16 fields; ny 0 to 4), one rounding per output component; out may be one
+// of the y_i.  Same conditions as launch_dslash_h16.
+bool launch_dslash_h16_epi(const FineGeom& g, const float2* U, const void* in, void* out, const Epi<float>& e,
+                           hipStream_t s);
 
 // Gauge-link gradient W and su(3) force T of L = Re <chi, H psi> (W or T may be
 // null).  Shape: r lanes per 4d site (2, 4, 8 or 16), ms wave groups splitting

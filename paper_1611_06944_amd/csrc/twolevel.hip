@@ -170,7 +170,14 @@ struct SmootherOpsH16 {
     void* tmp;
     hipStream_t s;
     void apply(const float2* a, float2* b) const { launch_dslash_h16(g, U, a, b, s); }
+    // the combination fused into the stencil's epilogue; variant 6: a plain
+    // pass into tmp, then an element-wise combination (one more FP16 write
+    // and read of the field, one more rounding)
     void epi(const float2* a, float2* b, const Epi<float>& e) const {
+        if (g.variant != 6) {
+            launch_dslash_h16_epi(g, U, a, b, e, s);
+            return;
+        }
         launch_dslash_h16(g, U, a, tmp, s);
         const void* z[4] = {e.y[0], e.y[1], e.y[2], e.y[3]};
         launch_h16_combine(12LL * g.N5, e.beta, tmp, z, e.g, e.ny, b, s);
@@ -817,22 +824,29 @@ int make_subspace_degrees_h16(const FineGeom& g, const double2* U, const double2
         };
         emit(t0, 0);
         if (degree == 0) continue;
+        // the second pass of each step carries the combination in its epilogue
+        // (variant 6: a plain pass, then an element-wise combination)
+        auto second = [&](const void* src, void* dst, float beta, int ny, const void* y0, float g0, const void* y1,
+                          float g1) {
+            if (g.variant != 6) {
+                const Epi<float> e{{static_cast<const float2*>(y0), static_cast<const float2*>(y1), nullptr, nullptr},
+                                   {g0, g1, 0.0f, 0.0f}, beta, ny};
+                launch_dslash_h16_epi(g, U32, src, dst, e, s);
+                return;
+            }
+            launch_dslash_h16(g, U32, src, wv, s);
+            const void* z[4] = {y0, y1, nullptr, nullptr};
+            const float gz[4] = {g0, g1, 0, 0};
+            launch_h16_combine(n, beta, wv, z, gz, ny, dst, s);
+        };
         // t1 = yhat t0 = a1 H (H t0) + b1 t0
         launch_dslash_h16(g, U32, t0, v, s);
-        launch_dslash_h16(g, U32, v, wv, s);
-        {
-            const void* z[4] = {t0, nullptr, nullptr, nullptr};
-            const float gz[4] = {(float)b1, 0, 0, 0};
-            launch_h16_combine(n, (float)a1, wv, z, gz, 1, t1, s);
-        }
+        second(v, t1, (float)a1, 1, t0, (float)b1, nullptr, 0.0f);
         emit(t1, 1);
         for (int j = 2; j <= degree; ++j) {
             // t0 <- 2 yhat t1 - t0 = a2 H (H t1) + b2 t1 - t0 (in place)
             launch_dslash_h16(g, U32, t1, v, s);
-            launch_dslash_h16(g, U32, v, wv, s);
-            const void* z[4] = {t1, t0, nullptr, nullptr};
-            const float gz[4] = {(float)b2, -1.0f, 0, 0};
-            launch_h16_combine(n, (float)a2, wv, z, gz, 2, t0, s);
+            second(v, t0, (float)a2, 2, t1, (float)b2, t0, -1.0f);
             std::swap(t0, t1);
             if (j % 16 == 0) {
                 launch_h16_norm2(n, t1, part, S, 0, s);

@@ -9,8 +9,9 @@ Bounds.
   FP16-rounded input, |got - ref| <= 2^-11 |ref| + e per real component, with e = 2e-5 max|ref|
   covering the FP32 arithmetic (the FP32 kernel's own parity bound is 1e-5) and FP16 subnormals.
 * The smoother p(H^2) H x rounds to FP16 once at its input (after scaling to unit RMS, which the
-  result undoes exactly up to FP32 rounding), once after each plain stencil pass and twice per
-  combination step (the pass, then the combination): 3 order - 1 roundings in all.  With
+  result undoes exactly up to FP32 rounding), once after each plain stencil pass and once per
+  fused combination step, or twice when the combination is a separate pass (variant 6): at most
+  3 order - 1 roundings in all.  With
   Clenshaw's recurrence bounded on the polynomial's interval, each rounding contributes at most
   2^-11 of the field's size to the result, so 2 (3 order - 1) 2^-11 max|ref| bounds the error:
   2.8e-2 at order 10.
@@ -69,25 +70,32 @@ def test_apply_fine_f16_parity(L, bc):
 @pytest.mark.parametrize("L,bc", [((4, 4, 2, 6), (1, 1, 1, -1)), ((6, 4, 8, 2), (-1, 1, -1, -1))])
 def test_f16_kernels_agree(L, bc, monkeypatch):
     """The two FP16-storage kernels (four slices per work-item, the default, and the paired
-    kernel, variant 5) do the same operations in the same order per output: bitwise equal."""
+    kernel, variant 5) do the same operations in the same order per output: bitwise equal, for
+    the plain apply and for the smoother, whose steps use the fused epilogues."""
     torch = torch_dev()
     Ls = 16
     log(f"f16 kernels agree L={L} bc={bc}")
     lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01, bc=bc)
     U = to_dev(hd.pack_gauge(hi.gauge_field(L, seed=5)), torch.complex64)
     x = _to_f16_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=6)))
-    outs = []
+    outs, sm = [], []
+    r = to_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=7)), torch.complex64)
     for v in ("0", "5"):
         monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
         outs.append(hd.apply_fine(lat, U, x))
+        sm.append(hd.smooth(lat, U, r, order=4, f16=True))  # fused epilogues with 1, 2 and 3 fields
     assert torch.equal(outs[0].view(torch.int16), outs[1].view(torch.int16))
+    assert torch.equal(sm[0], sm[1])
 
 
-@pytest.mark.parametrize("order", [2, 3, 10])
-def test_smoother_f16_parity(order):
+@pytest.mark.parametrize("order,variant", [(2, "0"), (3, "0"), (10, "0"), (10, "6")])
+def test_smoother_f16_parity(order, variant, monkeypatch):
+    """Variant 0: each Clenshaw step's combination fused into the second stencil pass (2 order
+    roundings in all); variant 6: a plain pass, then an element-wise combination (3 order - 1)."""
+    monkeypatch.setenv("HDCR_DSLASH_VARIANT", variant)
     torch = torch_dev()
     L, Ls = (4, 4, 4, 6), 16
-    log(f"smoother f16 order={order}")
+    log(f"smoother f16 order={order} variant={variant}")
     p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
     lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01)
     U = hi.gauge_field(L)
@@ -165,16 +173,19 @@ def test_hdcr_solve_f16_smoother(coarse):
     assert oracle.norm(bh - oracle.apply_h(U, xh, p)) <= 1.01e-8 * oracle.norm(bh)
 
 
-def test_subspace_filter_f16_parity():
+@pytest.mark.parametrize("variant", ["0", "6"])
+def test_subspace_filter_f16_parity(variant, monkeypatch):
     """The subspace filter with FP16-stored recurrence fields (make_subspace with F16C, and several
     degrees per recurrence) against the oracle's FP64 filter.  Each step rounds three fields (two
     stencil passes and the combination) and each rescaling two more; the filter never amplifies an
     error injected at step j more than it amplifies the signal from step 0, so every rounding
     contributes at most 2^-11 of the result's scale: (3 d + 2 floor(d / 16)) 2^-11 bounds the
-    element error of the normalised result relative to its largest entry."""
+    element error of the normalised result relative to its largest entry.  Variant 0 fuses the
+    combination into the second stencil pass (one rounding fewer per step), variant 6 does not."""
+    monkeypatch.setenv("HDCR_DSLASH_VARIANT", variant)
     torch = torch_dev()
     L, Ls = (4, 4, 4, 6), 16
-    log("subspace filter f16")
+    log(f"subspace filter f16 variant={variant}")
     p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
     lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01)
     U = hi.gauge_field(L)
