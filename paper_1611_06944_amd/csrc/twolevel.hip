@@ -497,10 +497,9 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
                 ++cnt.fine;
             PtrListT<T> Wl{};
             for (int j = 0; j < i; ++j) Wl.p[j] = w.W[j];
-            if (i > 0) {
+            if (i > 0) {  // the second pass's inner products ride on the first pass's update
                 launch_multidot<T, T>(n, Wl, i, w.W[i], w.part, w.S + SD1, s);
-                launch_multi_axpy<T>(n, Wl, i, w.S + SD1, w.W[i], s);
-                launch_multidot<T, T>(n, Wl, i, w.W[i], w.part, w.S + SD2, s);
+                launch_multi_axpy_dot<T>(n, Wl, i, w.S + SD1, w.W[i], w.part, w.S + SD2, s);
                 launch_multi_axpy<T>(n, Wl, i, w.S + SD2, w.W[i], s);
             }
             // <r, w>, |w|^2; r -= (<w, r>/|w|^2) w; normalise w

@@ -28,6 +28,11 @@ void launch_multidot(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y, 
 // y <- y - sum_j (coef[2j] + i coef[2j+1]) V[j]
 template <typename TV>
 void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s);
+// y <- y - sum_j (coef[2j] + i coef[2j+1]) V[j], then out as launch_multidot(V, y) of the stored
+// result (bitwise the same sums), in one pass over V and y
+template <typename TV>
+void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, double* part,
+                           double* out, hipStream_t s);
 // x <- x + sum_j g[j] Z[j]   (g on the host, x FP64)
 template <typename TV>
 void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2* g, double2* x, hipStream_t s);

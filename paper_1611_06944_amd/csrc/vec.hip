@@ -121,6 +121,52 @@ __global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrListT<TV>
     }
 }
 
+// y <- y - sum_j coef[j] V[j] as multi_axpy_kernel, and the partial sums of
+// <V[j], y> and |y|^2 of the stored result as multidot_kernel: same grid, same
+// index per work-item and same reduction, so the sums are bitwise those of a
+// separate multidot pass over the updated y
+template <typename TV>
+__global__ void __launch_bounds__(REDUCE_THREADS) multi_axpy_dot_kernel(int64_t n, PtrListT<TV> V, int nv,
+                                                                        const double* __restrict__ coef,
+                                                                        C2<TV>* __restrict__ y,
+                                                                        double* __restrict__ part) {
+    double2 cf[MAXV];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j) cf[j] = (j < nv) ? make_double2(coef[2 * j], coef[2 * j + 1]) : make_double2(0, 0);
+    double acc[2 * MAXV + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const C2<TV> yt = y[i];
+        double2 yv = make_double2(yt.x, yt.y);
+        C2<TV> vt[MAXV];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+            if (j < nv) {
+                vt[j] = V.p[j][i];
+                yv = cfma<double>(cneg<double>(cf[j]), make_double2(vt[j].x, vt[j].y), yv);
+            }
+        }
+        const C2<TV> yo = mk<TV>((TV)yv.x, (TV)yv.y);
+        y[i] = yo;
+        const double2 ys = make_double2(yo.x, yo.y);
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+            if (j < nv) {
+                const double2 v = make_double2(vt[j].x, vt[j].y);
+                acc[2 * j] += v.x * ys.x + v.y * ys.y;
+                acc[2 * j + 1] += v.x * ys.y - v.y * ys.x;
+            }
+        }
+        acc[2 * MAXV] += ys.x * ys.x + ys.y * ys.y;
+    }
+    block_reduce<2 * MAXV + 1>(acc);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 2 * MAXV + 1; ++q) part[(int64_t)q * REDUCE_BLOCKS + blockIdx.x] = acc[q];
+    }
+}
+
 // x <- x + sum_j g[j] Z[j]   (g: complex, kernel arguments; x FP64)
 struct Coefs {
     double2 g[MAXV];
@@ -377,6 +423,15 @@ void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* c
 }
 
 template <typename TV>
+void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, double* part,
+                           double* out, hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_dot_kernel<TV>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, coef, y,
+                       part);
+    hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
+                       out);
+}
+
+template <typename TV>
 void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2* g, double2* x, hipStream_t s) {
     Coefs c;
     for (int j = 0; j < MAXV; ++j) c.g[j] = (j < nz) ? g[j] : make_double2(0, 0);
@@ -398,6 +453,10 @@ template void launch_multidot<double, float>(int64_t, const PtrListT<double>&, i
                                              hipStream_t);
 template void launch_multi_axpy<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, hipStream_t);
 template void launch_multi_axpy<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, hipStream_t);
+template void launch_multi_axpy_dot<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, double*,
+                                            double*, hipStream_t);
+template void launch_multi_axpy_dot<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, double*,
+                                           double*, hipStream_t);
 template void launch_multi_update<double>(int64_t, const PtrListT<double>&, int, const double2*, double2*,
                                           hipStream_t);
 template void launch_multi_update<float>(int64_t, const PtrListT<float>&, int, const double2*, double2*, hipStream_t);
