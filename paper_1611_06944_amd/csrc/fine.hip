@@ -596,24 +596,48 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
     // slice s0 goes to Ls-1-s0, slice s0+1 to Ls-2-s0: one pair at Ls-2-s0,
     // lower spins negated (H = gamma5 R5 D)
     const uint32_t oo = (uint32_t)(st.site * LS + (LS - 2 - s0)) * CB;
-    __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
+    if constexpr (NY == 0) {
 #pragma unroll
-    for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
+        for (int c = 0; c < 12; ++c) {
+            const C2<T> lo = (c < 6) ? a1[c] : cneg<T>(a1[c]);
+            const C2<T> hi = (c < 6) ? a0[c] : cneg<T>(a0[c]);
+            st_pair_s_nt<H16>(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)c * f.cstride);
+        }
+    } else {
+        // every epilogue load is issued before the first combination: left to
+        // itself the compiler loads one component's fields, stores it and only
+        // then loads the next, twelve dependent round trips at the end of the
+        // workgroup.  The hop temporaries are dead here, so the NY x 12 loaded
+        // pairs fit the register budget (in two halves of 6 components for
+        // four FP32 fields).
+        constexpr int CH = (!H16 && NY >= 4) ? 6 : 12;
+        __amdgpu_buffer_rsrc_t yr[NY];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        C2<T> lo = (c < 6) ? a1[c] : cneg<T>(a1[c]);
-        C2<T> hi = (c < 6) ? a0[c] : cneg<T>(a0[c]);
-        if constexpr (NY > 0) {
-            lo = cscale<T>(ep.beta, lo);
-            hi = cscale<T>(ep.beta, hi);
+        for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
 #pragma unroll
-            for (int i = 0; i < NY; ++i) {
-                const float4 y = ld_pair_s<H16>(yr[i], oo, (uint32_t)c * f.cstride);
-                axpy<T>(ep.g[i], mk<T>(y.x, y.y), lo);
-                axpy<T>(ep.g[i], mk<T>(y.z, y.w), hi);
+        for (int c0 = 0; c0 < 12; c0 += CH) {
+            float4 yv[NY][CH];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int i = 0; i < NY; ++i) yv[i][c] = ld_pair_s<H16>(yr[i], oo, (uint32_t)(c0 + c) * f.cstride);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int cc = c0 + c;
+                C2<T> lo = (cc < 6) ? a1[cc] : cneg<T>(a1[cc]);
+                C2<T> hi = (cc < 6) ? a0[cc] : cneg<T>(a0[cc]);
+                lo = cscale<T>(ep.beta, lo);
+                hi = cscale<T>(ep.beta, hi);
+#pragma unroll
+                for (int i = 0; i < NY; ++i) {
+                    axpy<T>(ep.g[i], mk<T>(yv[i][c].x, yv[i][c].y), lo);
+                    axpy<T>(ep.g[i], mk<T>(yv[i][c].z, yv[i][c].w), hi);
+                }
+                st_pair_s_nt<H16>(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)cc * f.cstride);
             }
         }
-        st_pair_s_nt<H16>(make_float4(lo.x, lo.y, hi.x, hi.y), f.out, oo, (uint32_t)c * f.cstride);
     }
 }
 
@@ -757,28 +781,44 @@ dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* 
     // s0+3, s0+2, s0+1, s0; lower spins negated (H = gamma5 R5 D); epilogue
     // out = beta H in + sum_i g_i y_i on the FP16-stored y_i
     const uint32_t oo = (uint32_t)(st.site * LS + (LS - 4 - s0)) * CB;
+    // epilogue loads issued a chunk of components at a time before any of
+    // them is combined (as in the paired kernel); chunks sized so the loaded
+    // quads and the 4 x 12 accumulators fit the register budget
+    constexpr int CH = NY <= 1 ? 12 : (NY == 2 ? 6 : (NY == 3 ? 4 : 3));
     __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
 #pragma unroll
     for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        C2<T> o[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = (c < 6) ? a[3 - i][c] : cneg<T>(a[3 - i][c]);
+    for (int c0 = 0; c0 < 12; c0 += CH) {
+        uint4_t yv[NY > 0 ? NY : 1][CH];
         if constexpr (NY > 0) {
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] = cscale<T>(ep.beta, o[i]);
+            for (int c = 0; c < CH; ++c)
 #pragma unroll
-            for (int q = 0; q < NY; ++q) {
-                const uint4_t yw = __builtin_amdgcn_raw_buffer_load_b128(yr[q], oo, (uint32_t)c * f.cstride, 0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) axpy<T>(ep.g[q], quad_slice(yw, i), o[i]);
-            }
+                for (int q = 0; q < NY; ++q)
+                    yv[q][c] = __builtin_amdgcn_raw_buffer_load_b128(yr[q], oo, (uint32_t)(c0 + c) * f.cstride, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        const half4_t h0 = {(_Float16)o[0].x, (_Float16)o[0].y, (_Float16)o[1].x, (_Float16)o[1].y};
-        const half4_t h1 = {(_Float16)o[2].x, (_Float16)o[2].y, (_Float16)o[3].x, (_Float16)o[3].y};
-        const uint2_t w0 = __builtin_bit_cast(uint2_t, h0), w1 = __builtin_bit_cast(uint2_t, h1);
-        store_b128<CPOL_NT>(uint4_t{w0.x, w0.y, w1.x, w1.y}, f.out, oo, (uint32_t)c * f.cstride);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int cc = c0 + c;
+            C2<T> o[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = (cc < 6) ? a[3 - i][cc] : cneg<T>(a[3 - i][cc]);
+            if constexpr (NY > 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = cscale<T>(ep.beta, o[i]);
+#pragma unroll
+                for (int q = 0; q < NY; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) axpy<T>(ep.g[q], quad_slice(yv[q][c], i), o[i]);
+            }
+            const half4_t h0 = {(_Float16)o[0].x, (_Float16)o[0].y, (_Float16)o[1].x, (_Float16)o[1].y};
+            const half4_t h1 = {(_Float16)o[2].x, (_Float16)o[2].y, (_Float16)o[3].x, (_Float16)o[3].y};
+            const uint2_t w0 = __builtin_bit_cast(uint2_t, h0), w1 = __builtin_bit_cast(uint2_t, h1);
+            store_b128<CPOL_NT>(uint4_t{w0.x, w0.y, w1.x, w1.y}, f.out, oo, (uint32_t)cc * f.cstride);
+        }
     }
 }
 
