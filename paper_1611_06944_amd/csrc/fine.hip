@@ -538,6 +538,17 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
             spin[(c * 16 + p) * NK + k] = q;
         }
     }
+    // out-of-tile partners, two directions in flight: directions 0 and 1 are
+    // requested before the barrier, direction mu + 2 once direction mu's
+    // partners have been used
+#define HDCR_PAR2_GATHER(MU, DST)                                                                             \
+    {                                                                                                         \
+        const uint32_t noff = (uint32_t)((((p >> MU) & 1) ? n.f[MU] : n.b[MU]) * LS + s0) * CB;              \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) DST[c] = ld_pair_s<H16>(f.in, noff, (uint32_t)c * f.cstride); \
+    }
+    float4 nx0[12], nx1[12];
+    HDCR_PAR2_GATHER(0, nx0)
+    HDCR_PAR2_GATHER(1, nx1)
     __syncthreads();
     const C2<T>* lnk = lds + p * 8 * LPAD;
 
@@ -564,7 +575,7 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
             }
         }
     }
-#define HDCR_PAR2_HOPS(MU)                                                                                    \
+#define HDCR_PAR2_HOPS(MU, NX)                                                                                \
     {                                                                                                         \
         const bool up = (p >> MU) & 1;                                                                        \
         const T sg_in = up ? (T)-1 : (T)1;                                                                    \
@@ -579,20 +590,25 @@ __global__ void __launch_bounds__(PAR2_WG) __attribute__((amdgpu_waves_per_eu(2)
         hop_core_rt<T, MU>(v0, m, sg_in, up ? n.cb[MU] : n.cf[MU], a0);                                       \
         hop_core_rt<T, MU>(v1, m, sg_in, up ? n.cb[MU] : n.cf[MU], a1);                                       \
         _Pragma("unroll") for (int e = 0; e < 9; ++e) m[e] = lnk[(2 * MU + 1) * LPAD + e];                    \
-        const uint32_t noff = (uint32_t)((up ? n.f[MU] : n.b[MU]) * LS + s0) * CB;                            \
         _Pragma("unroll") for (int c = 0; c < 12; ++c) {                                                      \
-            const float4 w = ld_pair_s<H16>(f.in, noff, (uint32_t)c * f.cstride);                                    \
-            v0[c] = mk<T>(w.x, w.y);                                                                          \
-            v1[c] = mk<T>(w.z, w.w);                                                                          \
+            v0[c] = mk<T>(NX[c].x, NX[c].y);                                                                  \
+            v1[c] = mk<T>(NX[c].z, NX[c].w);                                                                  \
         }                                                                                                     \
         hop_core_rt<T, MU>(v0, m, -sg_in, up ? n.cf[MU] : n.cb[MU], a0);                                      \
         hop_core_rt<T, MU>(v1, m, -sg_in, up ? n.cf[MU] : n.cb[MU], a1);                                      \
     }
-    HDCR_PAR2_HOPS(0)
-    HDCR_PAR2_HOPS(1)
-    HDCR_PAR2_HOPS(2)
-    HDCR_PAR2_HOPS(3)
+    HDCR_PAR2_HOPS(0, nx0)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_PAR2_GATHER(2, nx0)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_PAR2_HOPS(1, nx1)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_PAR2_GATHER(3, nx1)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_PAR2_HOPS(2, nx0)
+    HDCR_PAR2_HOPS(3, nx1)
 #undef HDCR_PAR2_HOPS
+#undef HDCR_PAR2_GATHER
     // slice s0 goes to Ls-1-s0, slice s0+1 to Ls-2-s0: one pair at Ls-2-s0,
     // lower spins negated (H = gamma5 R5 D)
     const uint32_t oo = (uint32_t)(st.site * LS + (LS - 2 - s0)) * CB;
