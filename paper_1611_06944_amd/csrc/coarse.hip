@@ -279,8 +279,14 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
                                                        const C2<T>* __restrict__ psi, const C2<T>* __restrict__ psi2,
                                                        C2<T>* __restrict__ v) {
     __shared__ C2<T> sh[4 * RKG];
-    const int a = blockIdx.x, h = blockIdx.y;
-    const int k0 = blockIdx.z * RKG;
+    // one-dimensional grid of Nc x 2 x (vector groups) workgroups, remapped
+    // so that the workgroups of one coarse site (both chiralities, every
+    // vector group) are consecutive on one XCD: the site's psi block is then
+    // read from memory once and served from that XCD's L2 to the others
+    const int ng = (c.nvec + RKG - 1) / RKG;
+    const int lb = logical_block(blockIdx.x, gridDim.x);
+    const int a = lb / (2 * ng), h = (lb / ng) % 2;
+    const int k0 = (lb % ng) * RKG;
     const int kn = min(RKG, c.nvec - k0);
     const int nsp = c.Lh / W;                 // s slots per row
     const int slots = CWG / nsp;              // rows processed per sweep
@@ -1097,7 +1103,7 @@ void launch_basis_expand(const CoarseGeom& c, const double2* b64, int k0, int nk
 template <typename T, typename B, int W, int RKG>
 void restrict_launch_w(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
                        hipStream_t s) {
-    const dim3 grid(c.Nc, 2, (c.nvec + RKG - 1) / RKG);
+    const dim3 grid(c.Nc * 2 * ((c.nvec + RKG - 1) / RKG));
     if (psi2)
         hipLaunchKernelGGL((restrict_kernel<T, B, true, W, RKG>), grid, dim3(CWG), 0, s, c, basis, psi, psi2, v);
     else
