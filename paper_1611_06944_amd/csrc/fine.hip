@@ -259,23 +259,44 @@ __device__ __forceinline__ void hop_pair_lds(const FieldRefs& f, const Nbrs<T>& 
 // Writes the 12 components of a work-item's output element (byte offset oo):
 // H = gamma5 R5 D negates the lower spins; with NY > 0 the result is
 // beta (H in) + sum_i g[i] y[i].  NT: non-temporal stores.
-template <typename T, int NY, bool NT>
+template <typename T, int NY, bool NT, bool BATCH = false>
 __device__ __forceinline__ void store_out(const FieldRefs& f, uint32_t oo, const Epi<T>& ep, const C2<T> (&acc)[12]) {
+    // BATCH: the epilogue fields of a chunk of components are all requested
+    // before the first of them is combined (otherwise the compiler serialises
+    // one round trip per component); chunks of about 48 registers of loaded
+    // data.  Only where the registers do not lower the occupancy.
+    constexpr int PER = NY > 0 ? NY * (int)sizeof(C2<T>) / 4 : 1;  // registers per component
+    constexpr int CH =
+        (NY == 0 || !BATCH) ? 1 : (48 / PER >= 12 ? 12 : (48 / PER >= 6 ? 6 : (48 / PER >= 4 ? 4 : 3)));
     __amdgpu_buffer_rsrc_t yr[NY > 0 ? NY : 1];
 #pragma unroll
     for (int i = 0; i < NY; ++i) yr[i] = make_rsrc(ep.y[i], 12u * f.cstride);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        C2<T> o = (c < 6) ? acc[c] : cneg<T>(acc[c]);
-        if constexpr (NY > 0) {
-            o = cscale<T>(ep.beta, o);
+    for (int c0 = 0; c0 < 12; c0 += CH) {
+        C2<T> yv[NY > 0 ? NY : 1][CH];
+        if constexpr (NY > 0 && BATCH) {
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < NY; ++i) axpy<T>(ep.g[i], Buf<T>::ld(yr[i], oo, (uint32_t)c * f.cstride), o);
+            for (int c = 0; c < CH; ++c)
+#pragma unroll
+                for (int i = 0; i < NY; ++i) yv[i][c] = Buf<T>::ld(yr[i], oo, (uint32_t)(c0 + c) * f.cstride);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (NT)
-            Buf<T>::st_nt(o, f.out, oo, (uint32_t)c * f.cstride);
-        else
-            Buf<T>::st(o, f.out, oo, (uint32_t)c * f.cstride);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int cc = c0 + c;
+            C2<T> o = (cc < 6) ? acc[cc] : cneg<T>(acc[cc]);
+            if constexpr (NY > 0) {
+                o = cscale<T>(ep.beta, o);
+#pragma unroll
+                for (int i = 0; i < NY; ++i)
+                    axpy<T>(ep.g[i], BATCH ? yv[i][c] : Buf<T>::ld(yr[i], oo, (uint32_t)cc * f.cstride), o);
+            }
+            if constexpr (NT)
+                Buf<T>::st_nt(o, f.out, oo, (uint32_t)cc * f.cstride);
+            else
+                Buf<T>::st(o, f.out, oo, (uint32_t)cc * f.cstride);
+        }
     }
 }
 
@@ -445,7 +466,7 @@ __global__ void __launch_bounds__(WG) dslash_par_kernel(FineGeom g, TileGeom tg,
     HDCR_PAR_HOPS(2)
     HDCR_PAR_HOPS(3)
 #undef HDCR_PAR_HOPS
-    store_out<T, NY, true>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
+    store_out<T, NY, true, (sizeof(T) == 8)>(f, (uint32_t)(st.site * LS + (LS - 1 - s)) * CB, ep, acc);
 }
 
 // Paired parity-tile kernel (FP32, Ls = 16): the tile scheme above with each
