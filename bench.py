@@ -80,8 +80,8 @@ def parse():
 # HBM traffic of the FP32 fine apply at 24^4 x 16 from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy), for the stencil sources (fine.hip and the
 # shared header) with this sha256; reported as null for any other source or lattice.
-MEASURED_TRAFFIC = {"stencil_sha256": "db535e85baeecbdccbb1fec3e26e742b7c921926bd608298da9388100c3d7c2c",
-                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 1992107365,
+MEASURED_TRAFFIC = {"stencil_sha256": "50e9f9dcde0290eec9ca67e274e49918122849850c53edca997cbe270e975c74",
+                    "L": [24, 24, 24, 24], "Ls": 16, "fp32_bytes_per_launch": 1862926543,
                     "summary": "profiles/dslash_fine_24x24x24x24x16_traffic.md"}
 
 
