@@ -828,8 +828,8 @@ dslash_quad_h16_kernel(FineGeom g, TileGeom tg, const float2* U, const uint4_t* 
 #pragma unroll
     for (int c0 = 0; c0 < 12; c0 += CH) {
         uint4_t yv[NY > 0 ? NY : 1][CH];
+        __builtin_amdgcn_sched_barrier(0);
         if constexpr (NY > 0) {
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < CH; ++c)
 #pragma unroll
