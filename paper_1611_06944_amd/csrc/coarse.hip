@@ -97,55 +97,113 @@ __global__ void __launch_bounds__(CWG) basis_fold_kernel(CoarseGeom c, const dou
 }
 
 // One workgroup per (block, chirality): the vectors are orthonormalised in
-// index order; each is projected against the previous ones in chunks of 8
-// (classical Gram-Schmidt inside a chunk), the projection is applied twice,
-// then the vector is normalised.  Every work-item owns the same indices i of
-// all vectors, so only the reductions cross work-items.
-constexpr int ORTH_CHUNK = 8;
+// index order, a panel of ORTH_P at a time (block classical Gram-Schmidt
+// applied twice).  Each round projects the panel against all finished vectors,
+// ORTH_Q of them per sweep, so a finished vector is read once per panel and
+// round rather than once per vector and pass, then orthogonalises the panel
+// in index order and normalises it.  The result is the Q factor of the thin
+// QR in index order with a positive real R diagonal, as for vector-by-vector
+// Gram-Schmidt.  Rank test: a vector whose squared norm after the first round
+// is at most 1e-24 of its squared norm before any projection sets the flag
+// and is left unnormalised.  Every work-item owns the same indices i of all
+// vectors, so only the reductions cross work-items.
+constexpr int ORTH_P = 4;
+constexpr int ORTH_Q = 4;
 
 __global__ void __launch_bounds__(CWG) block_orth_kernel(CoarseGeom c, double2* __restrict__ b64,
                                                          int* __restrict__ rank_flag) {
-    __shared__ double2 sh[4 * ORTH_CHUNK];
+    __shared__ double2 sh[4 * ORTH_P * ORTH_Q];
     double2* base = b64 + (size_t)blockIdx.x * c.nvec * c.nhalf;
     const int n = c.nhalf;
-    for (int k = 0; k < c.nvec; ++k) {
-        double2* w = base + (size_t)k * n;
-        double2 nn[1] = {make_double2(0, 0)};
-        for (int i = threadIdx.x; i < n; i += CWG) nn[0].x += w[i].x * w[i].x + w[i].y * w[i].y;
-        wg_sum<double, 1>(nn, sh);
-        const double n0 = nn[0].x;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int j0 = 0; j0 < k; j0 += ORTH_CHUNK) {
-                const int jn = min(ORTH_CHUNK, k - j0);
-                double2 r[ORTH_CHUNK];
+    for (int k0 = 0; k0 < c.nvec; k0 += ORTH_P) {
+        const int kp = min(ORTH_P, c.nvec - k0);
+        double2* W = base + (size_t)k0 * n;
+        double2 n0[ORTH_P];
 #pragma unroll
-                for (int q = 0; q < ORTH_CHUNK; ++q) r[q] = make_double2(0, 0);
-                for (int i = threadIdx.x; i < n; i += CWG) {
-                    const double2 wi = w[i];
+        for (int p = 0; p < ORTH_P; ++p) n0[p] = make_double2(0, 0);
+        for (int i = threadIdx.x; i < n; i += CWG) {
 #pragma unroll
-                    for (int q = 0; q < ORTH_CHUNK; ++q)
-                        if (q < jn) r[q] = cjfma<double>(base[(size_t)(j0 + q) * n + i], wi, r[q]);
+            for (int p = 0; p < ORTH_P; ++p)
+                if (p < kp) {
+                    const double2 w = W[(size_t)p * n + i];
+                    n0[p].x += w.x * w.x + w.y * w.y;
                 }
-                wg_sum<double, ORTH_CHUNK>(r, sh);
-                for (int i = threadIdx.x; i < n; i += CWG) {
-                    double2 wi = w[i];
+        }
+        wg_sum<double, ORTH_P>(n0, sh);
+        bool bad[ORTH_P];
 #pragma unroll
-                    for (int q = 0; q < ORTH_CHUNK; ++q)
-                        if (q < jn) wi = cfma<double>(cneg<double>(r[q]), base[(size_t)(j0 + q) * n + i], wi);
-                    w[i] = wi;
+        for (int p = 0; p < ORTH_P; ++p) bad[p] = false;
+        for (int round = 0; round < 2; ++round) {
+            // W -= Q (Q^dag W) over the k0 finished vectors Q
+            for (int j0 = 0; j0 < k0; j0 += ORTH_Q) {
+                const int jn = min(ORTH_Q, k0 - j0);
+                double2 r[ORTH_P * ORTH_Q];
+#pragma unroll
+                for (int e = 0; e < ORTH_P * ORTH_Q; ++e) r[e] = make_double2(0, 0);
+                for (int i = threadIdx.x; i < n; i += CWG) {
+                    double2 wv[ORTH_P];
+#pragma unroll
+                    for (int p = 0; p < ORTH_P; ++p) wv[p] = (p < kp) ? W[(size_t)p * n + i] : make_double2(0, 0);
+#pragma unroll
+                    for (int q = 0; q < ORTH_Q; ++q)
+                        if (q < jn) {
+                            const double2 qv = base[(size_t)(j0 + q) * n + i];
+#pragma unroll
+                            for (int p = 0; p < ORTH_P; ++p) r[p * ORTH_Q + q] = cjfma<double>(qv, wv[p], r[p * ORTH_Q + q]);
+                        }
+                }
+                wg_sum<double, ORTH_P * ORTH_Q>(r, sh);
+                for (int i = threadIdx.x; i < n; i += CWG) {
+                    double2 qv[ORTH_Q];
+#pragma unroll
+                    for (int q = 0; q < ORTH_Q; ++q) qv[q] = (q < jn) ? base[(size_t)(j0 + q) * n + i] : make_double2(0, 0);
+#pragma unroll
+                    for (int p = 0; p < ORTH_P; ++p)
+                        if (p < kp) {
+                            double2 wv = W[(size_t)p * n + i];
+#pragma unroll
+                            for (int q = 0; q < ORTH_Q; ++q)
+                                if (q < jn) wv = cfma<double>(cneg<double>(r[p * ORTH_Q + q]), qv[q], wv);
+                            W[(size_t)p * n + i] = wv;
+                        }
                 }
             }
+            // the panel itself in index order, then normalisation
+#pragma unroll
+            for (int p = 0; p < ORTH_P; ++p) {
+                if (p >= kp) break;
+                double2* w = W + (size_t)p * n;
+                if (p > 0) {
+                    double2 r[ORTH_P];
+#pragma unroll
+                    for (int q = 0; q < ORTH_P; ++q) r[q] = make_double2(0, 0);
+                    for (int i = threadIdx.x; i < n; i += CWG) {
+                        const double2 wi = w[i];
+#pragma unroll
+                        for (int q = 0; q < ORTH_P; ++q)
+                            if (q < p) r[q] = cjfma<double>(W[(size_t)q * n + i], wi, r[q]);
+                    }
+                    wg_sum<double, ORTH_P>(r, sh);
+                    for (int i = threadIdx.x; i < n; i += CWG) {
+                        double2 wi = w[i];
+#pragma unroll
+                        for (int q = 0; q < ORTH_P; ++q)
+                            if (q < p) wi = cfma<double>(cneg<double>(r[q]), W[(size_t)q * n + i], wi);
+                        w[i] = wi;
+                    }
+                }
+                double2 nn[1] = {make_double2(0, 0)};
+                for (int i = threadIdx.x; i < n; i += CWG) nn[0].x += w[i].x * w[i].x + w[i].y * w[i].y;
+                wg_sum<double, 1>(nn, sh);
+                if (round == 0 && !(nn[0].x > 1e-24 * n0[p].x)) {
+                    if (threadIdx.x == 0) rank_flag[0] = 1;
+                    bad[p] = true;
+                }
+                if (bad[p]) continue;
+                const double inv = 1.0 / sqrt(nn[0].x);
+                for (int i = threadIdx.x; i < n; i += CWG) w[i] = make_double2(w[i].x * inv, w[i].y * inv);
+            }
         }
-        nn[0] = make_double2(0, 0);
-        for (int i = threadIdx.x; i < n; i += CWG) nn[0].x += w[i].x * w[i].x + w[i].y * w[i].y;
-        wg_sum<double, 1>(nn, sh);
-        double nr = nn[0].x;
-        if (!(nr > 1e-24 * n0)) {
-            if (threadIdx.x == 0) rank_flag[0] = 1;
-            nr = 1.0;
-        }
-        const double inv = 1.0 / sqrt(nr);
-        for (int i = threadIdx.x; i < n; i += CWG) w[i] = make_double2(w[i].x * inv, w[i].y * inv);
     }
 }
 
