@@ -75,10 +75,37 @@ typedef enum {
     HDCR_F16C = 3   /* (fp16 re, fp16 im): FP16 copy of the block basis used with FP32 vectors */
 } hdcr_dtype;
 
+/* Kernel-shape choices of one call, for tests and tuning sweeps.  Every field 0
+ * selects the library's own choice; the results of every choice agree (bit for
+ * bit for the traversal and the FP16 kernels, to rounding for the others).
+ *   dslash_variant  fine-apply kernel: 1 tile kernel with cached stores, 2 generic
+ *                   kernel, 3 tile kernel with non-temporal stores, 4 parity-tile
+ *                   kernel with one fifth-dimension slice per work-item (FP32),
+ *                   5 paired-slice kernel on FP16 fields, 6 FP16 smoother and filter
+ *                   steps as a plain pass plus a separate combination
+ *   tslab, ysplit, xsplit  traversal blocking of the stencil's tiles (or sites):
+ *                   t slabs of tslab tiles, y and x cut into ysplit and xsplit parts
+ *                   (a value that does not divide the extent selects no cut)
+ *   force_r, force_ms, force_p, force_sum  work split of hdcr_fermion_force: lanes
+ *                   per 4d site (2, 4, 8, 16), wave groups over the directions (1, 2),
+ *                   fifth-dimension slices per load (1, 2: FP32, even Ls), cross-lane
+ *                   sums by DPP (1) or through LDS (2); an unsupported split is
+ *                   rejected with HDCR_EINVAL
+ *   restrict_w, restrict_rkg  restriction: s slots per work-item (1, 2, 4), vectors
+ *                   per workgroup (16, 32)
+ *   prolong_ni      prolongation with the FP16 basis: indices per work-item (2, 4) */
+typedef struct hdcr_tuning {
+    int32_t dslash_variant;
+    int32_t tslab, ysplit, xsplit;
+    int32_t force_r, force_ms, force_p, force_sum;
+    int32_t restrict_w, restrict_rkg, prolong_ni;
+    int32_t reserved;
+} hdcr_tuning;
+
 /* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1
  * antiperiodic), domain wall height M5, quark mass mf, and cayley_b, the scale b
  * of the 4d part (0 is read as 1, the Shamir kernel, so a zero-initialised
- * descriptor describes the Shamir operator). */
+ * descriptor describes the Shamir operator with the library's kernel choices). */
 typedef struct hdcr_fine_desc {
     int32_t L[4];
     int32_t Ls;
@@ -87,6 +114,7 @@ typedef struct hdcr_fine_desc {
     double M5;
     double mf;
     double cayley_b;
+    hdcr_tuning tune;
 } hdcr_fine_desc;
 
 /* Coarse space: blocks of block[mu] sites in 4d covering the whole fifth
@@ -138,7 +166,8 @@ typedef struct hdcr_solve_stats {
     double seconds_coarse;      /* restriction + coarse solve + prolongation */
     double seconds_outer;       /* FP64 apply + orthogonalisation + updates */
     int32_t history_len;        /* entries written to the caller's history array */
-    int32_t reserved;
+    int32_t coarse_breakdowns;  /* coarse solves that stopped early on near-breakdown
+                                   (|<r,Ar>| < eps |r||Ar|, see hdcr_coarse_solve) */
 } hdcr_solve_stats;
 
 /* Coarse-space eigenvector deflation (Sec. 5 names it as the way to cut the
@@ -170,6 +199,8 @@ typedef struct hdcr_deflation_params {
     double cut;           /* lower filter edge of the first pass as a fraction of the top, 0 < cut < 1 */
 } hdcr_deflation_params;
 
+/* Text of a status code, and a thread-local description of the last failure
+ * (library plumbing, not a step of the method). */
 HDCR_API const char* hdcr_strerror(int code);
 HDCR_API const char* hdcr_last_error(void);
 
@@ -198,7 +229,8 @@ HDCR_API int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, co
 
 /* <x, y> = sum conj(x_i) y_i over n complex entries (C128 or C64 data, FP64
  * accumulation, fixed reduction order), written to out[0] (re), out[1] (im) on
- * the host.  work: device scratch of at least HDCR_DOT_WORK_BYTES bytes.
+ * the host: the inner product of the conjugate residual iterations (Sec. 3) and
+ * of the GCR orthogonalisation (Sec. 4).  work: device scratch of at least HDCR_DOT_WORK_BYTES bytes.
  * Synchronises `stream`. */
 #define HDCR_DOT_WORK_BYTES 32768
 HDCR_API int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work,
@@ -217,8 +249,10 @@ HDCR_API int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void
 #define HDCR_WS_COARSE 5
 HDCR_API size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params);
 
-/* Bytes of the opaque basis buffer (FP64 and FP32 copies of the chirally
- * compressed block basis) and of the little Dirac operator in `dtype`. */
+/* Bytes of the opaque basis buffer (FP64, FP32 and FP16 copies of the chirally
+ * compressed block basis phi^b_k of Sec. 4; it always holds all three, so its size
+ * does not depend on the precision the caller's cycles run in) and of the little
+ * Dirac operator A of Sec. 4 in `dtype` storage. */
 HDCR_API size_t hdcr_basis_bytes(const hdcr_coarse_desc* desc);
 HDCR_API size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype);
 
@@ -238,7 +272,8 @@ HDCR_API size_t hdcr_coarse_bytes(const hdcr_coarse_desc* desc, hdcr_dtype dtype
 HDCR_API int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* vecs, void* basis, void* A,
                       hdcr_dtype A_dtype, void* work, size_t work_bytes, hipStream_t stream);
 
-/* A in C128 storage -> A in C64 or BF16C storage (round to nearest). */
+/* The little Dirac operator A of Sec. 4 in C128 storage -> A in C64 or BF16C
+ * storage (round to nearest; the paper leaves the storage precision open). */
 HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128, hdcr_dtype dtype, void* A_dst,
                         hipStream_t stream);
 
@@ -256,7 +291,7 @@ HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128,
 #define HDCR_MFMA_VARIANTS 7
 HDCR_API int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
                                        int32_t nrhs, int32_t variant, hipStream_t stream);
-/* Autotuner of the batched apply: times every tile shape on the caller's
+/* Autotuner of the batched apply of A (Sec. 4): times every tile shape on the caller's
  * buffers (out is overwritten), records the fastest for (Nc, Nb, nrhs, device)
  * in a process-wide table used by variant 0, and reports the winner (best) and
  * the median time of each variant in ms[HDCR_MFMA_VARIANTS] (-1 for a variant
@@ -265,9 +300,10 @@ HDCR_API int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void*
 HDCR_API int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
                                       int32_t nrhs, int32_t* best, double* ms, hipStream_t stream);
 
-/* Read back the opaque buffers: A (any storage) as logical A[a][d][j][k]
- * complex double; the basis as Nb full fine fields (C128, [j][12][V4][Ls]),
- * field j holding phi^a_j on every block a. */
+/* Read back the opaque buffers: the little Dirac operator of Sec. 4 (any
+ * storage) as logical A[a][d][j][k] complex double; the block basis phi^b_k of
+ * Sec. 4 as Nb full fine fields (C128, [j][12][V4][Ls]), field j holding phi^a_j
+ * on every block a. */
 HDCR_API int hdcr_export_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, void* A_c128,
                        hipStream_t stream);
 HDCR_API int hdcr_export_basis(const hdcr_coarse_desc* desc, const void* basis, void* fields_c128, hipStream_t stream);
@@ -281,8 +317,10 @@ HDCR_API int hdcr_restrict(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const
 HDCR_API int hdcr_prolong(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* basis, const void* v, void* psi,
                  hipStream_t stream);
 
-/* Coarse 9-point apply out[r][a] = sum_d A[a][d] v[r][a+d] (coarse-periodic;
- * the fine antiperiodic sign is inside A) for nrhs right-hand sides.  dtype is
+/* The little Dirac operator of Sec. 4 (the coarse matrix A = P^dag H P, whose
+ * nearest-neighbour block structure Sec. 3 and Sec. 4 point out) applied as a
+ * 9-point stencil: out[r][a] = sum_d A[a][d] v[r][a+d] (coarse-periodic; the fine
+ * antiperiodic sign is inside A) for nrhs right-hand sides.  dtype is
  * A's storage; vectors are C128 for C128 storage, C64 otherwise (BF16C storage
  * accumulates in FP32). */
 HDCR_API int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void* A, const void* v, void* out,
@@ -311,7 +349,10 @@ HDCR_API int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* 
  * a Krylov method), the solve inside the two-level cycle: from x = 0, or from
  * the Galerkin start of the deflation space defl (host struct, may be NULL;
  * dtype as for the solve).  tol <= 0 runs exactly maxiter iterations, else CR
- * stops when the updated |r| <= tol |b| or after maxiter.  b, x: C128 for
+ * stops when the updated |r| <= tol |b| or after maxiter.  Either way it stops
+ * early, keeping the current iterate, at a near-breakdown |<r,Ar>| < eps |r| |Ar|
+ * (eps = 1e-13 with C128 vectors, 1e-6 with C64 vectors) and returns
+ * HDCR_EBREAKDOWN, or HDCR_ENAN if <r,Ar> or |Ar| is not finite.  b, x: C128 for
  * C128 storage of A, C64 for C64 / BF16C; not overlapping.  *iters (may be
  * NULL) gets the iteration count.  work: hdcr_workspace_bytes(HDCR_WS_COARSE)
  * with params->coarse_dtype = A_dtype.  Synchronous. */
@@ -369,13 +410,17 @@ HDCR_API int hdcr_make_subspace_degrees(const hdcr_fine_desc* desc, hdcr_dtype d
                                         void* vecs, void* work, size_t work_bytes, hipStream_t stream);
 
 /* Power-iteration estimate of the largest eigenvalue of H^2 (Rayleigh quotient
- * after `iters` steps from v0); C128.  work: hdcr_subspace_workspace_bytes(desc,
+ * after `iters` steps from v0), the upper edge lambda_max of the Chebyshev
+ * filter interval (Sec. 4, Fig. 1 caption); C128.  work: hdcr_subspace_workspace_bytes(desc,
  * HDCR_C128).  Synchronous. */
 HDCR_API int hdcr_power_max(const hdcr_fine_desc* desc, const void* U, const void* v0, int32_t iters, double* lam,
                    void* work, size_t work_bytes, hipStream_t stream);
 
 /* Solve H x = b to |b - H x| <= tol |b| (x: initial guess in, solution out;
- * C128 fields; U in C128).  precond NONE ignores basis and A (may be NULL).
+ * C128 fields; U in C128): plain conjugate residual on the Hermitian indefinite
+ * H (Sec. 3) with precond NONE, or variable-preconditioned GCR whose
+ * preconditioner is the two-level cycle M_outer (Sec. 4) with TWO_LEVEL.
+ * precond NONE ignores basis and A (may be NULL).
  * TWO_LEVEL needs the basis and A of hdcr_build_coarse (A in
  * params->coarse_dtype); defl (host struct, may be NULL) deflates every coarse
  * solve (vectors in params->inner_dtype).  history (host, may be NULL) receives up to

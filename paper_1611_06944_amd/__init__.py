@@ -14,7 +14,7 @@ Device layouts (see ``include/hdcr.h``):
 from __future__ import annotations
 
 import ctypes
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -33,7 +33,9 @@ load = _abi.load
 @dataclass(frozen=True)
 class Lattice:
     """Fine lattice L = (Lx, Ly, Lz, Lt), Ls, M5, mf, bc, Cayley scale b of the 4d part
-    (b = 1: Shamir); optional coarse blocking."""
+    (b = 1: Shamir); optional coarse blocking; tune: kernel-shape choices of the calls
+    made with this lattice, as (name, value) pairs of ``hdcr_tuning`` fields (empty: the
+    library's choices; see ``with_tune``)."""
     L: tuple
     Ls: int
     M5: float = 1.8
@@ -42,6 +44,15 @@ class Lattice:
     block: tuple = (1, 1, 1, 1)
     nvec: int = 0
     b: float = 1.0
+    tune: tuple = ()
+
+    def with_tune(self, **kw) -> "Lattice":
+        """A copy whose calls use the given ``hdcr_tuning`` choices, e.g.
+        ``lat.with_tune(dslash_variant=5)`` or ``lat.with_tune(xsplit=3, tslab=2)``."""
+        for k in kw:
+            if k not in _abi.TUNE_FIELDS:
+                raise ValueError(f"unknown tuning field {k!r}")
+        return replace(self, tune=tuple(sorted(kw.items())))
 
     @property
     def V4(self):
@@ -75,6 +86,8 @@ class Lattice:
         d.M5 = float(self.M5)
         d.mf = float(self.mf)
         d.cayley_b = float(self.b)
+        for k, v in self.tune:
+            setattr(d.tune, k, int(v))
         return d
 
     def coarse_desc(self) -> CoarseDesc:
@@ -568,10 +581,11 @@ def build_deflation(lat: Lattice, A, A_dtype: int, v0, k: int, degree: int = 40,
 
 
 def coarse_solve(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: float = 1e-2, defl: Deflation | None = None,
-                 x=None, work=None, stream=None):
+                 x=None, work=None, stream=None, return_status: bool = False):
     """x = CR_A(b) on the coarse lattice (from 0, or from the Galerkin start of defl); tol <= 0:
     exactly maxiter iterations.  b: [Nc, Nb] complex128 for C128 storage, complex64 otherwise.
-    Synchronous; returns (x, iterations)."""
+    Synchronous; returns (x, iterations), or (x, iterations, status) with return_status
+    (0, or HDCR_EBREAKDOWN / HDCR_ENAN when the iteration stopped at a near-breakdown)."""
     torch = _torch()
     lib = load()
     _check_coarse_operator(lat, A, A_dtype)
@@ -585,7 +599,10 @@ def coarse_solve(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: floa
         work = _workspace(workspace_bytes(_abi.WS_COARSE, lat, prm), b.device)
     ds = _defl_struct(defl)
     it = ctypes.c_int32(0)
-    _abi.check(lib.hdcr_coarse_solve(ctypes.byref(cd), int(A_dtype), _ptr(A), ctypes.byref(ds) if ds is not None else None,
-                                     _ptr(b), _ptr(x), int(maxiter), float(tol), ctypes.byref(it), _ptr(work),
-                                     work.numel(), _stream(stream)), "hdcr_coarse_solve")
+    code = _abi.check(lib.hdcr_coarse_solve(ctypes.byref(cd), int(A_dtype), _ptr(A),
+                                            ctypes.byref(ds) if ds is not None else None, _ptr(b), _ptr(x), int(maxiter),
+                                            float(tol), ctypes.byref(it), _ptr(work), work.numel(), _stream(stream)),
+                      "hdcr_coarse_solve")
+    if return_status:
+        return x, int(it.value), int(code)
     return x, int(it.value)

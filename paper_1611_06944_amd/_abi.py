@@ -24,10 +24,18 @@ DEFL_MAX = 64
 DOT_WORK_BYTES = 32768
 
 
+TUNE_FIELDS = ("dslash_variant", "tslab", "ysplit", "xsplit", "force_r", "force_ms", "force_p", "force_sum",
+               "restrict_w", "restrict_rkg", "prolong_ni")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in TUNE_FIELDS] + [("reserved", ctypes.c_int32)]
+
+
 class FineDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
                 ("reserved", ctypes.c_int32), ("M5", ctypes.c_double), ("mf", ctypes.c_double),
-                ("cayley_b", ctypes.c_double)]
+                ("cayley_b", ctypes.c_double), ("tune", Tuning)]
 
 
 class CoarseDesc(ctypes.Structure):
@@ -49,7 +57,7 @@ class SolveStats(ctypes.Structure):
                 ("coarse_applies", ctypes.c_int64), ("true_rel_residual", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("seconds_fine", ctypes.c_double),
                 ("seconds_coarse", ctypes.c_double), ("seconds_outer", ctypes.c_double),
-                ("history_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("coarse_breakdowns", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

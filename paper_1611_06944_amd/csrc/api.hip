@@ -39,16 +39,17 @@ FineGeom make_geom(const hdcr_fine_desc* d) {
     g.diag = b * (4.0 - d->M5) + 1.0;
     g.hop = -0.5 * b;
     g.mf = d->mf;
+    g.tune = d->tune;
     choose_traversal(g, 0, 0);
     return g;
 }
 
 void choose_traversal(FineGeom& g, int tslab, int ysplit, int xsplit) {
     const int Lt = g.L[3], Ly = g.L[1];
-    // tuning overrides (benchmark sweeps only)
-    if (const char* e = std::getenv("HDCR_TSLAB")) tslab = std::atoi(e);
-    if (const char* e = std::getenv("HDCR_YSPLIT")) ysplit = std::atoi(e);
-    if (const char* e = std::getenv("HDCR_XSPLIT")) xsplit = std::atoi(e);
+    // the caller's traversal choices replace the defaults
+    if (g.tune.tslab) tslab = g.tune.tslab;
+    if (g.tune.ysplit) ysplit = g.tune.ysplit;
+    if (g.tune.xsplit) xsplit = g.tune.xsplit;
     if (xsplit < 1 || g.L[0] % xsplit != 0) xsplit = 1;
     if (tslab <= 0) {
         // one slab per XCD when Lt allows it, else the whole t extent
@@ -67,8 +68,7 @@ void choose_traversal(FineGeom& g, int tslab, int ysplit, int xsplit) {
     g.tslab = tslab;
     g.xsplit = xsplit;
     g.ysplit = ysplit;
-    g.variant = 0;
-    if (const char* e = std::getenv("HDCR_DSLASH_VARIANT")) g.variant = std::atoi(e);
+    g.variant = g.tune.dslash_variant;
 }
 
 int check_fine_desc(const hdcr_fine_desc* d) {
@@ -162,15 +162,14 @@ int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void*
             return fail(HDCR_EINVAL, "hdcr_fermion_force: an output overlaps an input");
     }
     if (W && T && overlap(W, gbytes, T, gbytes)) return fail(HDCR_EINVAL, "hdcr_fermion_force: W and T overlap");
-    // work-split overrides (benchmark sweeps and tests only)
-    int r = 0, ms = 0, p = 0, lds = -1;
-    if (const char* s = std::getenv("HDCR_FORCE_R")) r = std::atoi(s);
-    if (const char* s = std::getenv("HDCR_FORCE_MS")) ms = std::atoi(s);
-    if (const char* s = std::getenv("HDCR_FORCE_P")) p = std::atoi(s);
-    if (const char* s = std::getenv("HDCR_FORCE_LDS")) lds = std::atoi(s);
-    const ForceShape f = choose_force_shape(g, (int)cs, r, ms, p, lds);
+    // the caller's work split (tune.force_*; 0 = the default choice)
+    const hdcr_tuning& tu = desc->tune;
+    if (tu.force_sum < 0 || tu.force_sum > 2)
+        return fail(HDCR_EINVAL, "hdcr_fermion_force: tune.force_sum must be 0, 1 (DPP) or 2 (LDS)");
+    const ForceShape f =
+        choose_force_shape(g, (int)cs, tu.force_r, tu.force_ms, tu.force_p, tu.force_sum == 0 ? -1 : tu.force_sum - 1);
     if (!force_shape_ok(g, (int)cs, f))
-        return fail(HDCR_EINVAL, "hdcr_fermion_force: unsupported work split (HDCR_FORCE_R/MS/P/LDS)");
+        return fail(HDCR_EINVAL, "hdcr_fermion_force: unsupported work split (tune.force_r/ms/p)");
     if (dtype == HDCR_C128)
         launch_link_force<double>(g, f, (const double2*)U, (const double2*)chi, (const double2*)psi, (double2*)W,
                                   (double2*)T, stream);

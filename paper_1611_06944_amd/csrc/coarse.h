@@ -112,7 +112,8 @@ template <typename T> struct CoarseCRWork {
     C2<T>* Ap;
     double* part;   // partial sums: [2][Nc] of the apply, then [2][DEFL_INIT_BLOCKS] of the update and init kernels
     double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
-    int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter;
+    int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter,
+                    // 4 stop reason (0 none, 2 near-breakdown, 3 not finite);
                     // CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
     double* dpart;  // partial sums of the deflated start: [2 * DEFL_KMAX][DEFL_BLOCKS]
     double* dcoef;  // its coefficients <V_j, b> / theta_j: [2 * DEFL_KMAX] (re, im)
@@ -133,6 +134,8 @@ constexpr int ARRIVE_GROUPS = 16;   // group counters of the last-arrival test
 constexpr int ARRIVE_STRIDE = 64;   // ints between counters (each counter on its own 256-byte line)
 constexpr int CCR_COUNTERS = 64;    // first arrival counter in flags
 constexpr int CCR_FLAGS = CCR_COUNTERS + (1 + ARRIVE_GROUPS) * ARRIVE_STRIDE;  // ints of the flags array
+// p[0 .. n) = 0 with a fill kernel (no memset node in the stream)
+void launch_zero_i32(int* p, int n, hipStream_t s);
 // r = b, x = 0, |b|^2; resets the iteration state
 template <typename T>
 void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,

@@ -640,6 +640,19 @@ __device__ __forceinline__ void sum_partials(const double* part, int np, double 
     for (int q = 0; q < NQ; ++q) out[q] = v[q];
 }
 
+// Near-breakdown test of the coarse CR: <r, Ar> is the numerator of alpha and the
+// denominator of the next beta; once |<r, Ar>| < eps |r| |Ar| the recurrence makes
+// no progress (alpha ~ 0) or loses its conjugacy (beta unbounded), so the solve
+// stops with the iterate it has.  eps = 1e-13 for FP64 vectors (the fine CR's and
+// the oracle's threshold) and 1e-6 for FP32 vectors, about 8 units of FP32
+// roundoff, below which <r, Ar> of an FP32 apply is rounding noise.
+// Returns 0 (go on), 2 (breakdown) or 3 (not finite).
+template <typename T> __device__ __forceinline__ int ccr_breakdown(double rar, double rr, double arar) {
+    constexpr double eps = sizeof(T) == 8 ? 1e-13 : 1e-6;
+    if (!isfinite(rar) || !isfinite(arar)) return 3;
+    return (fabs(rar) > eps * sqrt(rr) * sqrt(arar)) ? 0 : 2;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __restrict__ b, C2<T>* __restrict__ x,
                                                        C2<T>* __restrict__ r, double* part, double* cs, int* flags,
@@ -663,6 +676,7 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
             flags[3] = maxiter;
             flags[2] = 1;  // the sums of the first apply are still to be reduced
             flags[1] = 0;
+            flags[4] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0])) ? 1 : 0;
         }
     }
@@ -750,6 +764,7 @@ __global__ void __launch_bounds__(CWG) ccr_init_defl_kernel(int n, const C2<T>* 
             flags[3] = maxiter;
             flags[2] = 1;
             flags[1] = 0;
+            flags[4] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0]) || !isfinite(s[1])) ? 1 : 0;
         }
     }
@@ -810,9 +825,13 @@ __global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __rest
         double t[2];
         sum_partials<2>(apart, nc, t);
         rar = t[0];
-        apap = t[1];
-        if (!(fabs(rar) > 0.0) || !isfinite(rar)) {  // breakdown ends the coarse solve
-            if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+        apap = t[1];  // |Ap|^2 = |Ar|^2 on the first step
+        const int bd = ccr_breakdown<T>(rar, cs[3], apap);
+        if (bd) {  // (near-)breakdown ends the coarse solve; every workgroup takes the same decision
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                flags[4] = bd;
+                flags[0] = 1;
+            }
             return;
         }
     }
@@ -856,11 +875,15 @@ __global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* _
                                                            const double* apart, int nc, double* part, double* cs,
                                                            int* flags) {
     if (flags[0]) return;
-    double t[1];
-    sum_partials<1>(apart, nc, t);
+    double t[2];
+    sum_partials<2>(apart, nc, t);
     const double rar_new = t[0];
-    if (!(fabs(rar_new) > 0.0) || !isfinite(rar_new)) {  // breakdown ends the coarse solve
-        if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+    const int bd = ccr_breakdown<T>(rar_new, cs[3], t[1]);
+    if (bd) {  // (near-)breakdown ends the coarse solve; every workgroup takes the same decision
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            flags[4] = bd;
+            flags[0] = 1;
+        }
         return;
     }
     const T beta = (T)(rar_new / cs[0]);
@@ -1082,6 +1105,17 @@ int grid_for(size_t n) {
 
 }  // namespace
 
+namespace {
+__global__ void __launch_bounds__(CWG) zero_i32_kernel(int* __restrict__ p, int n) {
+    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) p[i] = 0;
+}
+}  // namespace
+
+void launch_zero_i32(int* p, int n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + CWG - 1) / CWG), dim3(CWG), 0, s, p, n);
+}
+
 template <typename T>
 void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w, int maxiter, double tol,
                      hipStream_t s) {
@@ -1185,10 +1219,9 @@ void restrict_launch_r(const CoarseGeom& c, int wmax, const B* basis, const C2<T
 template <typename T, typename B>
 void restrict_launch(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v, hipStream_t s) {
     if (c.Lh > CWG) return;  // not reachable: Ls <= 512 is enforced by the descriptor checks
-    // shape overrides (benchmark sweeps only)
-    int wmax = 4, rkg = 16;
-    if (const char* e = std::getenv("HDCR_RESTRICT_W")) wmax = std::atoi(e);
-    if (const char* e = std::getenv("HDCR_RESTRICT_RKG")) rkg = std::atoi(e);
+    // the caller's shape (tune.restrict_w / restrict_rkg; 0 = 4 slots, 16 vectors)
+    const int wmax = c.f.tune.restrict_w > 0 ? c.f.tune.restrict_w : 4;
+    const int rkg = c.f.tune.restrict_rkg > 0 ? c.f.tune.restrict_rkg : 16;
     if (rkg >= RKG_MAX && c.nvec >= RKG_MAX)
         restrict_launch_r<T, B, RKG_MAX>(c, wmax, basis, psi, psi2, v, s);
     else
@@ -1216,10 +1249,8 @@ void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, con
 void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* v, const float2* y, float2* psi,
                       hipStream_t s) {
     // two indices per work-item (measured faster at 24^4 x 16 than four with
-    // 16-byte FP16 loads: 1.88 against 1.94 ms); HDCR_PROLONG_NI=4 selects four
-    // (benchmark sweeps only)
-    int ni = 2;
-    if (const char* e = std::getenv("HDCR_PROLONG_NI")) ni = std::atoi(e);
+    // 16-byte FP16 loads: 1.88 against 1.94 ms); tune.prolong_ni = 4 selects four
+    const int ni = c.f.tune.prolong_ni > 0 ? c.f.tune.prolong_ni : 2;
     if (ni >= 4 && c.nhalf % 4 == 0)
         hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 4>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c,
                            basis, v, y, psi);

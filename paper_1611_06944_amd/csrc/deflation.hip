@@ -395,16 +395,18 @@ int coarse_solve(const CoarseGeom& c, hdcr_dtype dt, const void* A, const hdcr_c
     Carver cw(work, work_bytes);
     CoarseCRWork<T> w = coarse_cr_carve<T>(cw, c);
     if (!cw.ok()) return fail(HDCR_ENOMEM, "hdcr_coarse_solve: workspace too small");
-    HDCR_HIP_CHECK(hipMemsetAsync(w.flags, 0, CCR_FLAGS * sizeof(int), s));
+    launch_zero_i32(w.flags, CCR_FLAGS, s);  // the arrival counters must start at zero
     DeflView<T> dv{};
     if (defl) dv = DeflView<T>{defl->k, defl->theta, static_cast<const C2<T>*>(defl->V), static_cast<const C2<T>*>(defl->W)};
     int it = 0;
     int e = coarse_cr<T>(c, dt, A, b, x, maxiter, tol, w, 0, s, &it, defl ? &dv : nullptr);
     if (e) return e;
-    int hf[2] = {0, 0};
-    HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    int hf[5] = {0, 0, 0, 0, 0};
+    HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
     HDCR_HIP_CHECK(hipStreamSynchronize(s));
     if (iters) *iters = hf[1];
+    if (hf[4] == 2) return HDCR_EBREAKDOWN;
+    if (hf[4] == 3) return HDCR_ENAN;
     return HDCR_OK;
 }
 

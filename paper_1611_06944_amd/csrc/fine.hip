@@ -1032,7 +1032,7 @@ TileGeom tile_geom(const FineGeom& g) {
     while (ys > 1 && t.t.L[1] % ys != 0) --ys;
     int xs = t.t.L[0] / 3 > 0 ? t.t.L[0] / 3 : 1;
     while (xs > 1 && t.t.L[0] % xs != 0) --xs;
-    choose_traversal(t.t, ts, ys, xs);
+    choose_traversal(t.t, ts, ys, xs);  // the caller's choices in g.tune, if any, replace these
     return t;
 }
 

@@ -133,6 +133,7 @@ struct FineGeom {
     int xsplit;
     int ysplit;
     int variant;  // fine-stencil kernel variant (0 = default choice)
+    hdcr_tuning tune;  // the caller's kernel-shape choices (0 = the library's)
 };
 
 // number of XCDs (separate L2 caches) that hardware workgroup dispatch

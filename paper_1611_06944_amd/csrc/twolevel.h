@@ -37,11 +37,13 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
 // |r| <= tol |b| or maxiter.  Asynchronous except that the tolerance mode may
 // synchronise to decide how many iterations to enqueue; *iters gets the count
 // (after the stream has been synchronised) through flags[1].
-// defl (may be null): start from the Galerkin projection on the deflation space
+// defl (may be null): start from the Galerkin projection on the deflation space.
+// reason (may be null; tolerance mode only): why the iteration stopped early, 0
+// (tolerance or maxiter), 2 (near-breakdown: |<r,Ar>| < eps |r||Ar|) or 3 (not finite).
 template <typename T>
 int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T>* b, C2<T>* x, int maxiter,
               double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters,
-              const DeflView<T>* defl = nullptr);
+              const DeflView<T>* defl = nullptr, int* reason = nullptr);
 
 // Chebyshev smoother out (+)= p(H^2) H in, p the order-term Chebyshev interpolant
 // of 1/y on [lo, hi] (Sec. 4); tmp: 4 fine vectors of precision T.

@@ -88,7 +88,9 @@ template <typename T> size_t coarse_cr_bytes(const CoarseGeom& c) {
 
 template <typename T>
 int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T>* b, C2<T>* x, int maxiter,
-              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters, const DeflView<T>* defl) {
+              double tol, const CoarseCRWork<T>& w, int hint, hipStream_t s, int* iters, const DeflView<T>* defl,
+              int* reason) {
+    if (reason) *reason = 0;
     if (defl)
         launch_ccr_init_defl<T>(c, b, x, w, *defl, maxiter, tol, s);
     else
@@ -103,17 +105,18 @@ int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T
     // enqueue a batch sized by the previous solve, then check the device flag
     int enq = 0;
     int batch = std::max(4, std::min(hint > 0 ? hint + 2 : 16, maxiter));
-    int hf[2] = {0, 0};
+    int hf[5] = {0, 0, 0, 0, 0};
     while (enq < maxiter) {
         const int nb = std::min(batch, maxiter - enq);
         for (int i = 0; i < nb; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
         enq += nb;
-        HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
         HDCR_HIP_CHECK(hipStreamSynchronize(s));
         if (hf[0]) break;
         batch = 8;
     }
     if (iters) *iters = hf[1];
+    if (reason) *reason = hf[4];
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
 }
@@ -123,9 +126,9 @@ template CoarseCRWork<float> coarse_cr_carve<float>(Carver&, const CoarseGeom&);
 template size_t coarse_cr_bytes<double>(const CoarseGeom&);
 template size_t coarse_cr_bytes<float>(const CoarseGeom&);
 template int coarse_cr<double>(const CoarseGeom&, hdcr_dtype, const void*, const double2*, double2*, int, double,
-                               const CoarseCRWork<double>&, int, hipStream_t, int*, const DeflView<double>*);
+                               const CoarseCRWork<double>&, int, hipStream_t, int*, const DeflView<double>*, int*);
 template int coarse_cr<float>(const CoarseGeom&, hdcr_dtype, const void*, const float2*, float2*, int, double,
-                              const CoarseCRWork<float>&, int, hipStream_t, int*, const DeflView<float>*);
+                              const CoarseCRWork<float>&, int, hipStream_t, int*, const DeflView<float>*, int*);
 
 // ---------------------------------------------------------------------------
 // Chebyshev smoother
@@ -303,6 +306,7 @@ template <typename T> CycleWork<T> cycle_carve(Carver& w, const CoarseGeom& c) {
 struct CycleCounts {
     int64_t fine = 0, coarse_iters = 0, coarse_applies = 0;
     int last_coarse = 0;
+    int coarse_stops = 0;  // coarse solves ended by near-breakdown or a non-finite value
 };
 
 // e = B r:  e1 = S r;  e2 = e1 + Q (r - H e1);  e = e2 + S (r - H e2),  Q = P A^-1 P^dag
@@ -336,10 +340,11 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
     } else {
         launch_restrict<T>(c, basis, r, w.t, w.vc, s);
     }
-    int it = 0;
+    int it = 0, reason = 0;
     int st = coarse_cr<T>(c, (hdcr_dtype)prm->coarse_dtype, A, w.vc, w.cx, prm->coarse_maxiter, prm->coarse_tol, w.ccr,
-                          cnt.last_coarse, s, &it, defl);
+                          cnt.last_coarse, s, &it, defl, &reason);
     if (st) return st;
+    if (reason) ++cnt.coarse_stops;
     cnt.last_coarse = it;
     cnt.coarse_iters += it;
     cnt.coarse_applies += it + 1;
@@ -601,6 +606,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
         st->seconds_coarse = ph[PhaseTimer::COARSE];
         st->seconds_outer = ph[PhaseTimer::OUTER];
         st->history_len = hl;
+        st->coarse_breakdowns = cnt.coarse_stops;
     }
     return status;
 }

@@ -53,7 +53,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(hdcr_fine_desc, M5), offsetof(hdcr_coarse_desc, nvec),
          offsetof(hdcr_solve_params, coarse_maxiter), offsetof(hdcr_solve_params, basis_dtype));
   printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
-  printf("%zu\n", offsetof(hdcr_fine_desc, cayley_b));
+  printf("%zu %zu %zu %zu\n", offsetof(hdcr_fine_desc, cayley_b), offsetof(hdcr_fine_desc, tune),
+         offsetof(hdcr_tuning, prolong_ni), offsetof(hdcr_solve_stats, coarse_breakdowns));
   printf("%zu %zu %zu %zu %zu\n", sizeof(hdcr_coarse_deflation), offsetof(hdcr_coarse_deflation, theta),
          offsetof(hdcr_coarse_deflation, W), sizeof(hdcr_deflation_params), offsetof(hdcr_deflation_params, cut));
   return 0;
@@ -67,7 +68,8 @@ int main(void) {
           ctypes.sizeof(_abi.SolveStats), _abi.FineDesc.M5.offset, _abi.CoarseDesc.nvec.offset,
           _abi.SolveParams.coarse_maxiter.offset, _abi.SolveParams.basis_dtype.offset,
           _abi.SolveStats.true_rel_residual.offset,
-          _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset,
+          _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset, _abi.FineDesc.tune.offset,
+          _abi.Tuning.prolong_ni.offset, _abi.SolveStats.coarse_breakdowns.offset,
           ctypes.sizeof(_abi.CoarseDeflation), _abi.CoarseDeflation.theta.offset, _abi.CoarseDeflation.W.offset,
           ctypes.sizeof(_abi.DeflationParams), _abi.DeflationParams.cut.offset]
     assert vals == py
@@ -258,3 +260,19 @@ def test_f16_storage_validation_before_launch(lib):
     assert lib.hdcr_vcycle(ctypes.byref(cd8), ctypes.byref(p), U, x, y, None, x, y, work, 1 << 30,
                            None) == _abi.HDCR_EINVAL
     assert b"F16C" in lib.hdcr_last_error()
+
+
+def test_tuning_travels_in_the_descriptor():
+    """Kernel-shape choices are per call (hdcr_fine_desc.tune), set through Lattice.with_tune;
+    the library reads no environment variable."""
+    from paper_1611_06944_amd import Lattice
+    lat = Lattice((4, 4, 4, 4), 8)
+    d = lat.with_tune(dslash_variant=5, xsplit=3, force_sum=2, restrict_rkg=32).fine_desc()
+    assert (d.tune.dslash_variant, d.tune.xsplit, d.tune.force_sum, d.tune.restrict_rkg) == (5, 3, 2, 32)
+    z = lat.fine_desc()
+    assert all(getattr(z.tune, k) == 0 for k, _ in z.tune._fields_)
+    with pytest.raises(ValueError):
+        lat.with_tune(no_such_knob=1)
+    src = os.path.join(ROOT, "paper_1611_06944_amd", "csrc")
+    for fn in os.listdir(src):
+        assert "getenv" not in open(os.path.join(src, fn)).read(), fn

@@ -1,6 +1,7 @@
 """GPU parity of the coarse space (Sec. 4) against the FP64 oracle, through the C-ABI:
 chirally split block basis, restriction/prolongation, little Dirac operator and coarse
-apply (FP64 1e-10; FP32 1e-5; BF16 storage 1e-2, its rounding error being 2^-9 per entry)."""
+apply (FP64 1e-10; FP32 1e-5; BF16 storage element by element against the oracle's apply of the
+stored bf16 values within the FP32 accumulation bound)."""
 import numpy as np
 import pytest
 
@@ -83,9 +84,19 @@ def test_restrict_prolong_apply_parity(L, Ls, block, nvec):
     A64 = hd.convert_coarse(lat, A, hd.C64)
     out = to_host(hd.apply_coarse(lat, A64, hd.C64, to_dev(v, torch.complex64)))
     assert max_rel_elem(out, ap_ref) <= 1e-5
+    # BF16 storage: element by element against the oracle's apply of the exported bf16 values
+    # (and FP32-rounded vectors), within the FP32 accumulation bound
+    # (9 Nb + 2) sqrt(2) 2^-24 sum |A| |v| (a complex product carries at most sqrt(2) 2u, a sum of
+    # n terms at most (n - 1) u); and within the storage rounding of the FP64 result
     Ab = hd.convert_coarse(lat, A, hd.BF16C)
-    out = to_host(hd.apply_coarse(lat, Ab, hd.BF16C, to_dev(v, torch.complex64)))
-    assert rel_err(out, ap_ref) <= 1e-2
+    Ab_log = to_host(hd.export_coarse(lat, Ab, hd.BF16C))
+    v32 = v.astype(np.complex64).astype(np.complex128)
+    bound = (9 * cs.nb + 2) * np.sqrt(2.0) * 2.0 ** -24 * oracle.coarse_apply(np.abs(Ab_log), np.abs(v32), cs.cdims).real
+    for vv, k in ((v, slice(None)), (v[1], 1)):
+        out = to_host(hd.apply_coarse(lat, Ab, hd.BF16C, to_dev(vv, torch.complex64)))
+        err = np.abs(out - oracle.coarse_apply(Ab_log, v32, cs.cdims)[k])
+        assert np.all(err <= bound[k]), float((err / bound[k]).max())
+    assert rel_err(out, ap_ref[1]) <= 1e-2
     # single right-hand side
     out1 = to_host(hd.apply_coarse(lat, A, hd.C128, to_dev(v[1])))
     assert max_rel_elem(out1, ap_ref[1]) <= 1e-10
@@ -214,3 +225,37 @@ def test_multi_rhs_apply_matches_single_rhs_bitwise(nrhs):
             assert torch.equal(many[r], one), (dt, r)
         if dt == hd.C128:
             assert max_rel_elem(to_host(many), oracle.coarse_apply(A_ref, v, cs.cdims)) <= 1e-10
+
+
+def test_coarse_cr_near_breakdown():
+    """Coarse CR on an indefinite little Dirac operator stops at a near-breakdown as the oracle's CR
+    does (status 2, iterate kept): the source b = sqrt|l-| u+ + sqrt(l+) u- built from the extreme
+    eigenpairs of the dense stored operator (the exported values of each storage: bf16 rounding alone
+    moves <b, A b> by ~4e-3 |b||Ab|) has <b, A b> = 0 up to rounding, so the first step already breaks
+    down (0 iterations, x = 0).  FP64 vectors (C128 storage) and FP32 vectors (C64 and BF16C
+    storage; the FP32 threshold is 1e-6 |r| |Ar|).  A Gaussian source runs normally."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (4, 4, 4, 4), 4, (2, 2, 2, 2), 4
+    log("coarse CR near-breakdown")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    _, A = hd.build_coarse(lat, to_dev(hd.pack_gauge(U)), _dev_vecs(vecs), hd.C128)
+    for dt in (hd.C128, hd.C64, hd.BF16C):
+        store = A if dt == hd.C128 else hd.convert_coarse(lat, A, dt)
+        A_log = to_host(hd.export_coarse(lat, store, dt))
+        M = oracle.coarse_dense(A_log, cs.cdims)
+        lam, vec = np.linalg.eigh(0.5 * (M + M.conj().T))
+        assert lam[0] < 0 < lam[-1]
+        b = (np.sqrt(-lam[0]) * vec[:, -1] + np.sqrt(lam[-1]) * vec[:, 0]).reshape(cs.nc, cs.nb)
+        if dt == hd.C128:
+            assert np.abs(M - M.conj().T).max() <= 1e-12 * np.abs(M).max()
+            ref = oracle.coarse_cr(A_log, b, cs.cdims, tol=1e-8, maxiter=50)
+            assert ref.status == 2 and ref.iters == 0
+        bd = to_dev(b) if dt == hd.C128 else to_dev(b, torch.complex64)
+        for tol in (1e-8, 0.0):
+            x, it, code = hd.coarse_solve(lat, store, dt, bd, maxiter=50, tol=tol, return_status=True)
+            assert code == hd._abi.HDCR_EBREAKDOWN and it == 0, (dt, tol, code, it)
+            assert np.all(to_host(x) == 0)
+        g = hi.gaussian_coarse(cs.nc, cs.nb, seed=31)
+        gd = to_dev(g) if dt == hd.C128 else to_dev(g, torch.complex64)
+        x, it, code = hd.coarse_solve(lat, store, dt, gd, maxiter=50, tol=1e-2, return_status=True)
+        assert code == 0 and 0 < it <= 50, (dt, code, it)

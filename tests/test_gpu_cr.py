@@ -81,3 +81,36 @@ def test_cr_exact_breakdown():
     b = (np.sqrt(-lam[im]) * vec[:, ip] + np.sqrt(lam[ip]) * vec[:, im]).reshape(p.fshape)
     x, st, _ = _run(lat, U, b)
     assert st["status"] == _abi.HDCR_EBREAKDOWN
+
+
+def test_cr_resume_from_nonzero_x0():
+    """Resuming from an initial guess (the x argument of hdcr_solve holds x0 on entry): CR
+    starts from r = b - H x0.  x0 is the 40-iteration iterate of a first solve plus a Gaussian
+    perturbation of 1e-3 of its norm; the residual history follows the oracle's CR from the same
+    x0, and the solution meets 1e-8 under the oracle's H."""
+    torch = torch_dev()
+    L, Ls = (4, 4, 4, 4), 8
+    log("CR from x0 != 0")
+    p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
+    lat = Lattice(L, Ls, M5=1.8, mf=0.01)
+    U = hi.gauge_field(L, seed=1)
+    b = hi.gaussian_fermion(L, Ls, seed=0)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    x40 = oracle.cr(ap, b, tol=1e-30, maxiter=40, check_true=False).x
+    x0 = x40 + 1e-3 * oracle.norm(x40) / np.sqrt(x40.size) * hi.gaussian_fermion(L, Ls, seed=17)
+    x = to_dev(pack_fermion(x0))
+    x, st, hist = solve(lat, to_dev(pack_gauge(U)), to_dev(pack_fermion(b)), x=x, params=default_params(tol=1e-8))
+    assert st["status"] == 0
+    xs = unpack_fermion(to_host(x), L, Ls)
+    bn = oracle.norm(b)
+    assert oracle.norm(b - ap(xs)) <= 1e-8 * bn
+    ref = oracle.cr(ap, b, tol=1e-8, maxiter=10000, x0=x0)
+    k = min(len(hist), len(ref.history), 60)
+    np.testing.assert_allclose(np.array(hist[:k]), np.array(ref.history[:k]) / bn, rtol=1e-6)
+    assert abs(st["outer_iters"] - ref.iters) <= 2
+    # the guess was used: fewer iterations than from zero, whose count is pinned above
+    assert st["outer_iters"] < oracle.cr(ap, b, tol=1e-8, maxiter=10000).iters
+    # an exact solution as x0 returns at once with no iteration
+    x, st, _ = solve(lat, to_dev(pack_gauge(U)), to_dev(pack_fermion(b)), x=to_dev(pack_fermion(xs)),
+                     params=default_params(tol=1e-8))
+    assert st["status"] == 0 and st["outer_iters"] == 0

@@ -68,7 +68,7 @@ def test_apply_fine_f16_parity(L, bc):
 
 
 @pytest.mark.parametrize("L,bc", [((4, 4, 2, 6), (1, 1, 1, -1)), ((6, 4, 8, 2), (-1, 1, -1, -1))])
-def test_f16_kernels_agree(L, bc, monkeypatch):
+def test_f16_kernels_agree(L, bc):
     """The two FP16-storage kernels (four slices per work-item, the default, and the paired
     kernel, variant 5) do the same operations in the same order per output: bitwise equal, for
     the plain apply and for the smoother, whose steps use the fused epilogues."""
@@ -80,24 +80,23 @@ def test_f16_kernels_agree(L, bc, monkeypatch):
     x = _to_f16_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=6)))
     outs, sm = [], []
     r = to_dev(hd.pack_fermion(hi.gaussian_fermion(L, Ls, seed=7)), torch.complex64)
-    for v in ("0", "5"):
-        monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
-        outs.append(hd.apply_fine(lat, U, x))
-        sm.append(hd.smooth(lat, U, r, order=4, f16=True))  # fused epilogues with 1, 2 and 3 fields
+    for v in (0, 5):
+        lv = lat.with_tune(dslash_variant=v)
+        outs.append(hd.apply_fine(lv, U, x))
+        sm.append(hd.smooth(lv, U, r, order=4, f16=True))  # fused epilogues with 1, 2 and 3 fields
     assert torch.equal(outs[0].view(torch.int16), outs[1].view(torch.int16))
     assert torch.equal(sm[0], sm[1])
 
 
-@pytest.mark.parametrize("order,variant", [(2, "0"), (3, "0"), (10, "0"), (10, "6")])
-def test_smoother_f16_parity(order, variant, monkeypatch):
+@pytest.mark.parametrize("order,variant", [(2, 0), (3, 0), (10, 0), (10, 6)])
+def test_smoother_f16_parity(order, variant):
     """Variant 0: each Clenshaw step's combination fused into the second stencil pass (2 order
     roundings in all); variant 6: a plain pass, then an element-wise combination (3 order - 1)."""
-    monkeypatch.setenv("HDCR_DSLASH_VARIANT", variant)
     torch = torch_dev()
     L, Ls = (4, 4, 4, 6), 16
     log(f"smoother f16 order={order} variant={variant}")
     p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
-    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01)
+    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01).with_tune(dslash_variant=variant)
     U = hi.gauge_field(L)
     r = hi.gaussian_fermion(L, Ls, seed=4) * 1e-3   # the scaling to unit RMS makes the size irrelevant
     ref = oracle.smoother(lambda f: oracle.apply_h(U, f, p), r, order=order, lo=1.0, hi=64.0)
@@ -173,8 +172,8 @@ def test_hdcr_solve_f16_smoother(coarse):
     assert oracle.norm(bh - oracle.apply_h(U, xh, p)) <= 1.01e-8 * oracle.norm(bh)
 
 
-@pytest.mark.parametrize("variant", ["0", "6"])
-def test_subspace_filter_f16_parity(variant, monkeypatch):
+@pytest.mark.parametrize("variant", [0, 6])
+def test_subspace_filter_f16_parity(variant):
     """The subspace filter with FP16-stored recurrence fields (make_subspace with F16C, and several
     degrees per recurrence) against the oracle's FP64 filter.  Each step rounds three fields (two
     stencil passes and the combination) and each rescaling two more; the filter never amplifies an
@@ -182,12 +181,11 @@ def test_subspace_filter_f16_parity(variant, monkeypatch):
     contributes at most 2^-11 of the result's scale: (3 d + 2 floor(d / 16)) 2^-11 bounds the
     element error of the normalised result relative to its largest entry.  Variant 0 fuses the
     combination into the second stencil pass (one rounding fewer per step), variant 6 does not."""
-    monkeypatch.setenv("HDCR_DSLASH_VARIANT", variant)
     torch = torch_dev()
     L, Ls = (4, 4, 4, 6), 16
     log(f"subspace filter f16 variant={variant}")
     p = oracle.Params(L, Ls, M5=1.8, mf=0.01)
-    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01)
+    lat = hd.Lattice(L, Ls, M5=1.8, mf=0.01).with_tune(dslash_variant=variant)
     U = hi.gauge_field(L)
     ap = lambda f: oracle.apply_h(U, f, p)
     lam = oracle.power_max(ap, hi.gaussian_fermion(L, Ls, seed=99), iters=25)

@@ -155,7 +155,7 @@ def test_apply_fine_linearity_and_hermiticity_fp64():
 
 
 @pytest.mark.parametrize("L", [(12, 8, 4, 12), (8, 12, 6, 8)])
-def test_traversal_orders_agree(L, monkeypatch):
+def test_traversal_orders_agree(L):
     """The traversal blocking (x split, y split, t slab of the tile lattice) changes only the order
     in which workgroups visit the tiles: FP64, FP32 and FP16-storage applies are bitwise identical
     for every blocking, including splits that do not divide an extent (which fall back to none)."""
@@ -170,10 +170,8 @@ def test_traversal_orders_agree(L, monkeypatch):
     x16 = torch.view_as_real(x32).to(torch.float16).contiguous()
     ref = None
     for xs, ys, ts in ((1, 1, 1), (3, 2, 3), (2, 3, 2), (6, 4, 6), (5, 7, 5)):
-        monkeypatch.setenv("HDCR_XSPLIT", str(xs))
-        monkeypatch.setenv("HDCR_YSPLIT", str(ys))
-        monkeypatch.setenv("HDCR_TSLAB", str(ts))
-        outs = (apply_fine(lat, U64, x64), apply_fine(lat, U32, x32), apply_fine(lat, U32, x16).view(torch.int16))
+        lt = lat.with_tune(xsplit=xs, ysplit=ys, tslab=ts)
+        outs = (apply_fine(lt, U64, x64), apply_fine(lt, U32, x32), apply_fine(lt, U32, x16).view(torch.int16))
         if ref is None:
             ref = outs
         else:
@@ -181,7 +179,7 @@ def test_traversal_orders_agree(L, monkeypatch):
 
 
 @pytest.mark.parametrize("L,Ls", [((4, 6, 2, 5), 16), ((4, 6, 2, 6), 16), ((3, 2, 4, 2), 8)])
-def test_kernel_variants_agree(L, Ls, monkeypatch):
+def test_kernel_variants_agree(L, Ls):
     """The kernels of the fine apply give the same result: parity-tile with
     paired slices (FP32, even extents, Ls = 16; variant 0) and with one slice
     per work-item (4), tile kernel with cached (1) and non-temporal (3) stores,
@@ -194,9 +192,8 @@ def test_kernel_variants_agree(L, Ls, monkeypatch):
     for dt, tol in ((torch.complex128, 1e-14), (torch.complex64, 1e-6)):
         U, x = to_dev(Uh, dt), to_dev(xh, dt)
         outs = []
-        for v in ("0", "4", "1", "3", "2"):
-            monkeypatch.setenv("HDCR_DSLASH_VARIANT", v)
-            outs.append(to_host(apply_fine(lat, U, x)))
+        for v in (0, 4, 1, 3, 2):
+            outs.append(to_host(apply_fine(lat.with_tune(dslash_variant=v), U, x)))
         scale = np.abs(outs[-1]).max()
         for o in outs[:-1]:
             assert np.abs(o - outs[-1]).max() <= tol * scale, dt

@@ -82,7 +82,7 @@ WORK_SPLITS = [(r, ms, pp, lds) for r in (2, 4, 8, 16) for ms in (1, 2) for pp i
 
 
 @pytest.mark.parametrize("L,Ls", [((3, 2, 2, 5), 16), ((2, 3, 1, 2), 8), ((2, 1, 3, 2), 6)])
-def test_force_every_work_split(L, Ls, monkeypatch):
+def test_force_every_work_split(L, Ls):
     """Each (lanes per site, direction groups, slices per load, cross-lane sum)
     split of the kernel, FP64 and FP32; Ls = 6 gives lanes with one, two or no
     load units."""
@@ -91,27 +91,26 @@ def test_force_every_work_split(L, Ls, monkeypatch):
     Wref = oracle.link_grad(U, chi, psi, p)
     Tref = oracle.force(U, Wref)
     for r, ms, pp, lds in WORK_SPLITS:
-        monkeypatch.setenv("HDCR_FORCE_R", str(r))
-        monkeypatch.setenv("HDCR_FORCE_MS", str(ms))
-        monkeypatch.setenv("HDCR_FORCE_P", str(pp))
-        monkeypatch.setenv("HDCR_FORCE_LDS", str(lds))
+        ls = lat.with_tune(force_r=r, force_ms=ms, force_p=pp, force_sum=1 + lds)
         for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
             if pp == 2 and dt == torch.complex128:
                 continue  # paired slices are an FP32 load shape
             log(f"fermion_force split r={r} ms={ms} p={pp} lds={lds} L={L} Ls={Ls} {dt}")
-            W, T = _force(lat, U, chi, psi, dt)
+            W, T = _force(ls, U, chi, psi, dt)
             assert max_rel_elem(W, Wref) <= tol, (r, ms, pp, lds, dt)
             assert max_rel_elem(T, Tref) <= tol, (r, ms, pp, lds, dt)
 
 
-def test_force_rejects_unsupported_split(monkeypatch):
-    """A paired-slice load is refused for FP64 (before any launch)."""
+def test_force_rejects_unsupported_split():
+    """A paired-slice load is refused for FP64, and an unknown cross-lane sum for any
+    precision (before any launch)."""
     torch = torch_dev()
     from paper_1611_06944_amd import HDCRError
     p, lat, U, chi, psi = _inputs((2, 2, 2, 2), 4, (1, 1, 1, -1))
-    monkeypatch.setenv("HDCR_FORCE_P", "2")
     with pytest.raises(HDCRError):
-        _force(lat, U, chi, psi, torch.complex128)
+        _force(lat.with_tune(force_p=2), U, chi, psi, torch.complex128)
+    with pytest.raises(HDCRError):
+        _force(lat.with_tune(force_sum=3), U, chi, psi, torch.complex64)
 
 
 def _sample_links(L, n, rng):

@@ -188,8 +188,11 @@ def test_hdcr_solve_mixed_precision(coarse):
 def test_hdcr_solve_full_size_sampled_residual():
     """The benchmark's HDCR solve at 24^4 x 16 (32 subspace vectors filtered with FP16 storage,
     4^4 blocks, Nb = 64, FP32 cycle with the FP16 basis copy, BF16 coarse operator, FGCR(8) in
-    FP64) reaches 1e-8, and the oracle's H at 3000 sampled sites confirms it: every entry of
-    b - H x is at most |b - H x| <= 1e-8 |b|."""
+    FP64) reaches 1e-8, and the oracle's H confirms it on a uniform sample of n = 20000 of the N5
+    5d sites: (N5 / n) sum_sample |r_i|^2 estimates |b - H x|^2 without bias, with a relative
+    standard deviation of about sqrt(2 / (24 n)) ~ 0.2% for a residual spread over the lattice
+    (24 real entries per site).  The estimate must lie below (1.5e-8 |b|)^2 and within a factor
+    1.5 of the library's own FP64 true residual."""
     torch = torch_dev()
     L, Ls, nvec = (24, 24, 24, 24), 16, 32
     log(f"HDCR solve at L={L} Ls={Ls} nvec={nvec}")
@@ -217,8 +220,52 @@ def test_hdcr_solve_full_size_sampled_residual():
     torch.cuda.empty_cache()
     x_aos = hd.unpack_fermion(to_host(x), L, Ls)
     rng = np.random.default_rng(6)
-    sel = np.unique(np.concatenate([rng.integers(0, lat.N5, 3000), [0, Ls - 1, lat.N5 - 1, lat.N5 - Ls]]))
+    n = 20000
+    sel = rng.choice(lat.N5, size=n, replace=False)
     hx = oracle.apply_h_sites(U, x_aos, p, sel)
     t, z, y, xx = np.unravel_index(sel // Ls, (L[3], L[2], L[1], L[0]))
     r = b_aos[t, z, y, xx, sel % Ls] - hx
-    assert np.abs(r).max() <= 1.01e-8 * np.linalg.norm(b_aos)
+    est = np.sqrt(lat.N5 / n * float(np.sum(np.abs(r) ** 2)))
+    bn = np.linalg.norm(b_aos)
+    log(f"  sampled |b - Hx|/|b| = {est / bn:.3e}, library {st['true_rel_residual']:.3e}")
+    assert est <= 1.5e-8 * bn
+    assert 1 / 1.5 <= est / (st["true_rel_residual"] * bn) <= 1.5
+
+
+def test_hdcr_solve_resume_from_nonzero_x0():
+    """TWO_LEVEL from an initial guess: FGCR starts from r = b - H x0 (FP64), the residual
+    history follows the oracle's FGCR from the same x0 (FP64 cycle, 6 coarse iterations), and
+    the solution meets 1e-8 under the oracle's H.  x0 is a partial CR solution plus noise."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (4, 4, 4, 4), 8, (2, 2, 2, 2), 4
+    log("hdcr solve from x0 != 0")
+    p, cs, lat = _lat(L, Ls, block, nvec)
+    U = hi.gauge_field(L)
+    vecs, basis_ref, A_ref = _coarse(L, Ls, block, nvec, p, cs, U)
+    b = hi.gaussian_fermion(L, Ls, seed=0)
+    ap = lambda f: oracle.apply_h(U, f, p)
+    x20 = oracle.cr(ap, b, tol=1e-30, maxiter=20, check_true=False).x
+    x0 = x20 + 1e-2 * oracle.norm(x20) / np.sqrt(x20.size) * hi.gaussian_fermion(L, Ls, seed=18)
+    ref = oracle.fgcr(ap, lambda r: oracle.vcycle(ap, A_ref, basis_ref, cs, r, ctol=0.0, cmaxiter=6), b,
+                      tol=1e-8, maxiter=100, restart=8, x0=x0)
+    Ud = to_dev(hd.pack_gauge(U))
+    basis, A = hd.build_coarse(lat, Ud, to_dev(np.stack([hd.pack_fermion(v) for v in vecs])), hd.C128)
+    prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C128, coarse_dtype=hd.C128,
+                            coarse_tol=0.0, coarse_maxiter=6, restart=8, tol=1e-8, maxiter=100)
+    x, st, hist = hd.solve(lat, Ud, to_dev(hd.pack_fermion(b)), x=to_dev(hd.pack_fermion(x0)), params=prm,
+                           basis=basis, A=A)
+    assert st["status"] == 0
+    bn = oracle.norm(b)
+    k = min(5, len(hist), len(ref.history))
+    np.testing.assert_allclose(np.array(hist[:k]), np.array(ref.history[:k]) / bn, rtol=1e-6)
+    assert abs(st["outer_iters"] - ref.iters) <= 1
+    xs = hd.unpack_fermion(to_host(x), L, Ls)
+    assert oracle.norm(b - ap(xs)) <= 1e-8 * bn
+    # mixed precision (FP32 cycle, BF16 coarse) from the same x0 also converges
+    prm32 = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=hd.BF16C,
+                              coarse_tol=0.1, coarse_maxiter=100, restart=8, tol=1e-8, maxiter=100)
+    _, A16 = hd.build_coarse(lat, Ud, to_dev(np.stack([hd.pack_fermion(v) for v in vecs])), hd.BF16C)
+    x, st, _ = hd.solve(lat, Ud, to_dev(hd.pack_fermion(b)), x=to_dev(hd.pack_fermion(x0)), params=prm32,
+                        basis=basis, A=A16)
+    assert st["status"] == 0
+    assert oracle.norm(b - ap(hd.unpack_fermion(to_host(x), L, Ls))) <= 1e-8 * bn

@@ -48,9 +48,12 @@ def test_block_basis_matches_numpy_qr():
             Q = Q * ph[None, :]
             got = np.stack([basis[h * nvec + k][m].ravel() for k in range(nvec)], axis=1)
             np.testing.assert_allclose(got, Q, atol=1e-13)
-            # zero outside the block
-        for k in range(cs.nb):
-            assert np.all(basis[k][~m][..., :] == 0) or True
+    # every basis field (phi^a_k on all blocks a) is a Gamma5 eigenvector of its
+    # chirality: +1 for k < nvec, -1 for k >= nvec
+    for k in range(cs.nb):
+        sgn = 1.0 if k < nvec else -1.0
+        np.testing.assert_allclose(_g5r5(basis[k]), sgn * basis[k], atol=1e-14)
+        assert oracle.norm(basis[k]) > 0.5
 
 
 def test_projector_identities_and_span():
