@@ -34,11 +34,12 @@
  *
  * Ownership: the caller owns every buffer.  The library never allocates or
  * frees device memory; scratch space comes in through (work, work_bytes),
- * sized by hdcr_workspace_bytes().  Every call except hdcr_solve,
- * hdcr_coarse_solve, hdcr_build_deflation, hdcr_make_subspace,
- * hdcr_make_subspace_degrees, hdcr_power_max and hdcr_vec_dot is stream-ordered
- * and returns before the work is done; those seven return after it has
- * completed.
+ * sized by hdcr_workspace_bytes(), except for hdcr_coarse_solve_static, whose
+ * scratch is a fixed array in the library's own device memory.  Every call
+ * except hdcr_solve, hdcr_coarse_solve, hdcr_coarse_solve_static,
+ * hdcr_build_deflation, hdcr_make_subspace, hdcr_make_subspace_degrees,
+ * hdcr_power_max and hdcr_vec_dot is stream-ordered and returns before the
+ * work is done; those eight return after it has completed.
  * In and out buffers of one call must not overlap.
  *
  * Errors: 0 = success.  Negative codes are caller errors found before any
@@ -359,6 +360,23 @@ HDCR_API int hdcr_vcycle(const hdcr_coarse_desc* desc, const hdcr_solve_params* 
 HDCR_API int hdcr_coarse_solve(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
                                const hdcr_coarse_deflation* defl, const void* b, void* x, int32_t maxiter, double tol,
                                int32_t* iters, void* work, size_t work_bytes, hipStream_t stream);
+
+/* hdcr_coarse_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the scratch taken from a static device array
+ * of the library instead of a workspace argument.  That array holds
+ * HDCR_COARSE_STATIC_BYTES (8 MiB) per GPU for as long as the process runs; a
+ * coarse space whose solve needs more (hdcr_workspace_bytes(HDCR_WS_COARSE)) is
+ * rejected with HDCR_ENOMEM before any launch (8 MiB covers, e.g., 6^4 coarse
+ * sites with Nb = 64 in FP64).  The caller passes A, defl, b and x as for
+ * hdcr_coarse_solve.  Every call on one GPU uses that GPU's single array, so
+ * calls that overlap on one GPU (other host threads, other streams) race and
+ * must be serialised by the caller; each call clears the counters it needs.
+ * The call itself allocates nothing.  Synchronous. */
+#define HDCR_COARSE_STATIC_BYTES (8u << 20)
+HDCR_API int hdcr_coarse_solve_static(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
+                                      const hdcr_coarse_deflation* defl, const void* b, void* x, int32_t maxiter,
+                                      double tol, int32_t* iters, hipStream_t stream);
 
 /* Deflation set-up (Sec. 5, coarse-space eigenvector deflation): the k
  * eigenpairs of A of smallest |lambda| by Chebyshev-filtered subspace

@@ -25,7 +25,7 @@ from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_
 __all__ = ["Lattice", "apply_fine", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
-           "HDCRError", "Deflation", "build_deflation", "coarse_solve", "make_subspace_degrees"]
+           "HDCRError", "Deflation", "build_deflation", "coarse_solve", "coarse_solve_static", "make_subspace_degrees"]
 
 load = _abi.load
 
@@ -603,6 +603,30 @@ def coarse_solve(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: floa
                                             ctypes.byref(ds) if ds is not None else None, _ptr(b), _ptr(x), int(maxiter),
                                             float(tol), ctypes.byref(it), _ptr(work), work.numel(), _stream(stream)),
                       "hdcr_coarse_solve")
+    if return_status:
+        return x, int(it.value), int(code)
+    return x, int(it.value)
+
+
+def coarse_solve_static(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: float = 1e-2,
+                        defl: Deflation | None = None, x=None, stream=None, return_status: bool = False):
+    """coarse_solve without a workspace: the library's static device scratch
+    (``hdcr_coarse_solve_static``; at most COARSE_STATIC_BYTES of scratch, calls on one GPU must
+    not overlap).  Returns as coarse_solve."""
+    torch = _torch()
+    lib = load()
+    _check_coarse_operator(lat, A, A_dtype)
+    if b.dtype != _coarse_vec_dtype(A_dtype) or b.numel() != lat.nc * lat.nb:
+        raise ValueError(f"b must be {_coarse_vec_dtype(A_dtype)} with {lat.nc * lat.nb} entries")
+    if x is None:
+        x = torch.empty_like(b)
+    cd = lat.coarse_desc()
+    ds = _defl_struct(defl)
+    it = ctypes.c_int32(0)
+    code = _abi.check(lib.hdcr_coarse_solve_static(ctypes.byref(cd), int(A_dtype), _ptr(A),
+                                                   ctypes.byref(ds) if ds is not None else None, _ptr(b), _ptr(x),
+                                                   int(maxiter), float(tol), ctypes.byref(it), _stream(stream)),
+                      "hdcr_coarse_solve_static")
     if return_status:
         return x, int(it.value), int(code)
     return x, int(it.value)

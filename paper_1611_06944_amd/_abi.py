@@ -22,6 +22,7 @@ PRECOND_NONE, PRECOND_TWO_LEVEL = 0, 1
 WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE, WS_COARSE = 0, 1, 2, 3, 4, 5
 DEFL_MAX = 64
 DOT_WORK_BYTES = 32768
+COARSE_STATIC_BYTES = 8 << 20
 
 
 TUNE_FIELDS = ("dslash_variant", "tslab", "ysplit", "xsplit", "force_r", "force_ms", "force_p", "force_sum",
@@ -92,6 +93,8 @@ PROTOTYPES = {
                                   _vp, _sz, _vp]),
     "hdcr_coarse_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(CoarseDeflation), _vp,
                                          _vp, _i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp]),
+    "hdcr_coarse_solve_static": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(CoarseDeflation),
+                                                _vp, _vp, _i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _vp]),
     "hdcr_deflation_workspace_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32, ctypes.POINTER(DeflationParams)]),
     "hdcr_build_deflation": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(DeflationParams),
                                             _vp, _vp, _vp, _vp, _dbl_p, _vp, _sz, _vp]),

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -410,6 +411,34 @@ int coarse_solve(const CoarseGeom& c, hdcr_dtype dt, const void* A, const hdcr_c
     return HDCR_OK;
 }
 
+// Scratch of hdcr_coarse_solve_static: one array per GPU, in the library's own
+// device memory (it lives until the process ends).  Host code never passes the
+// array's name to a kernel (on the host it only names the symbol); it takes the
+// device address from hipGetSymbolAddress once per device and uses that.
+static __device__ __align__(256) unsigned char scratch[HDCR_COARSE_STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the
+// first call on that device).
+int static_scratch(void** out) {
+    int dev = -1;
+    HDCR_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(HDCR_EINVAL, "hdcr_coarse_solve_static: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HDCR_EHIP, std::string("hdcr_coarse_solve_static: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HDCR_OK;
+}
+
 }  // namespace
 
 size_t deflation_workspace_bytes(const CoarseGeom& c, hdcr_dtype dt, int m) {
@@ -486,6 +515,26 @@ int hdcr_coarse_solve(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const vo
                                     work_bytes, stream);
     return coarse_solve<float>(c, A_dtype, A, defl, (const float2*)b, (float2*)x, maxiter, tol, iters, work,
                                work_bytes, stream);
+}
+
+int hdcr_coarse_solve_static(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
+                             const hdcr_coarse_deflation* defl, const void* b, void* x, int32_t maxiter, double tol,
+                             int32_t* iters, hipStream_t stream) {
+    int e = check_coarse_desc(desc);
+    if (e) return e;
+    if (!coarse_dtype_ok(A_dtype))
+        return fail(HDCR_EINVAL, "hdcr_coarse_solve_static: A_dtype must be C128, C64 or BF16C");
+    const CoarseGeom c = make_coarse_geom(desc);
+    const size_t need = A_dtype == HDCR_C128 ? coarse_cr_bytes<double>(c) : coarse_cr_bytes<float>(c);
+    if (need > (size_t)HDCR_COARSE_STATIC_BYTES)
+        return fail(HDCR_ENOMEM, "hdcr_coarse_solve_static: the coarse solve needs " + std::to_string(need) +
+                                     " bytes of scratch, more than the static " +
+                                     std::to_string((size_t)HDCR_COARSE_STATIC_BYTES) +
+                                     " (use hdcr_coarse_solve with a workspace)");
+    void* ws = nullptr;
+    if ((e = static_scratch(&ws))) return e;
+    return hdcr_coarse_solve(desc, A_dtype, A, defl, b, x, maxiter, tol, iters, ws, (size_t)HDCR_COARSE_STATIC_BYTES,
+                             stream);
 }
 
 }  // extern "C"
