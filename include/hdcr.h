@@ -94,13 +94,16 @@ typedef enum {
  *                   rejected with HDCR_EINVAL
  *   restrict_w, restrict_rkg  restriction: s slots per work-item (1, 2, 4), vectors
  *                   per workgroup (16, 32)
- *   prolong_ni      prolongation with the FP16 basis: indices per work-item (2, 4) */
+ *   prolong_ni      prolongation with the FP16 basis: indices per work-item (2, 4)
+ *   wg_per_cu       at most this many workgroups of the parity-tile stencil kernels
+ *                   resident per compute unit (enforced through their LDS size; 0 or a
+ *                   value above what fits: no cap) */
 typedef struct hdcr_tuning {
     int32_t dslash_variant;
     int32_t tslab, ysplit, xsplit;
     int32_t force_r, force_ms, force_p, force_sum;
     int32_t restrict_w, restrict_rkg, prolong_ni;
-    int32_t reserved;
+    int32_t wg_per_cu;
 } hdcr_tuning;
 
 /* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1

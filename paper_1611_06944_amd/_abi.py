@@ -26,11 +26,11 @@ COARSE_STATIC_BYTES = 8 << 20
 
 
 TUNE_FIELDS = ("dslash_variant", "tslab", "ysplit", "xsplit", "force_r", "force_ms", "force_p", "force_sum",
-               "restrict_w", "restrict_rkg", "prolong_ni")
+               "restrict_w", "restrict_rkg", "prolong_ni", "wg_per_cu")
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int32) for k in TUNE_FIELDS] + [("reserved", ctypes.c_int32)]
+    _fields_ = [(k, ctypes.c_int32) for k in TUNE_FIELDS]
 
 
 class FineDesc(ctypes.Structure):

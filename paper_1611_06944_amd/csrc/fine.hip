@@ -1036,6 +1036,22 @@ TileGeom tile_geom(const FineGeom& g) {
     return t;
 }
 
+// Dynamic LDS that caps the resident workgroups of a parity-tile kernel at
+// g.tune.wg_per_cu per compute unit (160 KB of LDS each): fewer tiles in flight
+// per XCD keep more of the L2 for the neighbours a tile re-reads.  0: no cap.
+constexpr int LDS_PER_CU = 160 * 1024;
+template <typename K> int lds_pad(const FineGeom& g, K kernel) {
+    const int cap = g.tune.wg_per_cu;
+    if (cap <= 0) return 0;
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+    const int want = LDS_PER_CU / (cap + 1) + 1 - (int)a.sharedSizeBytes;  // one byte over the share of cap + 1
+    if (want <= 0) return 0;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              want);
+    return want;
+}
+
 bool par_ok(const FineGeom& g) {
     return g.Ls == 16 && g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0;
 }
@@ -1050,12 +1066,14 @@ void launch_ny(const FineGeom& g, const C2<T>* U, const C2<T>* in, C2<T>* out, c
         const TileGeom tg = tile_geom(g);
         if constexpr (sizeof(T) == 4) {
             if (g.variant == 0) {
-                hipLaunchKernelGGL((dslash_par2_kernel<NY, false>), dim3(tg.t.V4), dim3(PAR2_WG), 0, s, g, tg, U, in,
-                                   out, ep);
+                const int pad = lds_pad(g, dslash_par2_kernel<NY, false>);
+                hipLaunchKernelGGL((dslash_par2_kernel<NY, false>), dim3(tg.t.V4), dim3(PAR2_WG), pad, s, g, tg, U,
+                                   in, out, ep);
                 return;
             }
         }
-        hipLaunchKernelGGL((dslash_par_kernel<T, NY>), dim3(tg.t.V4), dim3(WG), 0, s, g, tg, U, in, out, ep);
+        const int pad = lds_pad(g, dslash_par_kernel<T, NY>);
+        hipLaunchKernelGGL((dslash_par_kernel<T, NY>), dim3(tg.t.V4), dim3(WG), pad, s, g, tg, U, in, out, ep);
         return;
     }
     if (g.variant != 2) {
@@ -1096,8 +1114,8 @@ bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void*
                            Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
         return true;
     }
-    hipLaunchKernelGGL(dslash_quad_h16_kernel<0>, dim3(tg.t.V4), dim3(QUAD_WG), 0, s, g, tg, U,
-                       static_cast<const uint4_t*>(in), static_cast<uint4_t*>(out),
+    hipLaunchKernelGGL(dslash_quad_h16_kernel<0>, dim3(tg.t.V4), dim3(QUAD_WG), lds_pad(g, dslash_quad_h16_kernel<0>),
+                       s, g, tg, U, static_cast<const uint4_t*>(in), static_cast<uint4_t*>(out),
                        Epi<float>{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, 1.0f, 0});
     return true;
 }

@@ -158,7 +158,8 @@ def test_apply_fine_linearity_and_hermiticity_fp64():
 def test_traversal_orders_agree(L):
     """The traversal blocking (x split, y split, t slab of the tile lattice) changes only the order
     in which workgroups visit the tiles: FP64, FP32 and FP16-storage applies are bitwise identical
-    for every blocking, including splits that do not divide an extent (which fall back to none)."""
+    for every blocking, including splits that do not divide an extent (which fall back to none),
+    and for every cap on the resident workgroups per compute unit (tune.wg_per_cu)."""
     torch = torch_dev()
     Ls = 16
     log(f"traversal orders L={L}")
@@ -169,8 +170,8 @@ def test_traversal_orders_agree(L):
     U32, x32 = to_dev(Uh, torch.complex64), to_dev(xh, torch.complex64)
     x16 = torch.view_as_real(x32).to(torch.float16).contiguous()
     ref = None
-    for xs, ys, ts in ((1, 1, 1), (3, 2, 3), (2, 3, 2), (6, 4, 6), (5, 7, 5)):
-        lt = lat.with_tune(xsplit=xs, ysplit=ys, tslab=ts)
+    for xs, ys, ts, cap in ((1, 1, 1, 0), (3, 2, 3, 0), (2, 3, 2, 2), (6, 4, 6, 1), (5, 7, 5, 3), (1, 1, 1, 40)):
+        lt = lat.with_tune(xsplit=xs, ysplit=ys, tslab=ts, wg_per_cu=cap)
         outs = (apply_fine(lt, U64, x64), apply_fine(lt, U32, x32), apply_fine(lt, U32, x16).view(torch.int16))
         if ref is None:
             ref = outs
