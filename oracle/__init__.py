@@ -20,7 +20,10 @@ are plain C++ loops in ``hdcr_oracle.cpp``.  This module adds, in numpy:
   (Sec. 4 and the Fig. 1 caption),
 * the coarse Krylov solve Q = P A^-1 P^dag (Sec. 4, coarse-inverse display),
 * the symmetric two-level cycle (Sec. 4, the M_outer display) and the
-  flexible (variable-preconditioned) GCR outer iteration (Sec. 4).
+  flexible (variable-preconditioned) GCR outer iteration (Sec. 4),
+* the Hermitian Wilson kernel H_W = gamma5 D_W(-M5) and the continued-fraction
+  form of the overlap operator as a 5d matrix (Sec. 3, the continued-fraction
+  display), with its coefficients beta_i and R as inputs.
 
 Each function names the passage it follows.
 """
@@ -144,6 +147,81 @@ def apply_gamma5_field(psi) -> np.ndarray:
     """Gamma5 = gamma5 R5 on a fine field: (Gamma5 psi)(x,s) = gamma5 psi(x, Ls-1-s)."""
     g5 = gamma(4)
     return np.einsum("ab,...sbc->...sac", g5, psi[..., ::-1, :, :])
+
+
+# ----------------------------------------------------------------------------
+# Continued-fraction overlap operator (Sec. 3, the continued-fraction matrix)
+# ----------------------------------------------------------------------------
+
+def apply_hw(U, psi, M5: float, bc=(1, 1, 1, -1)) -> np.ndarray:
+    """H_W psi = gamma5 D_W(-M5) psi, the Hermitian Wilson kernel of the overlap operator
+    (Sec. 3), slice by slice on a field psi[t, z, y, x, s, spin, colour]:
+
+        D_W psi(x) = (4 - M5) psi(x)
+                     - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x + mu) + (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)],
+
+    with the factor bc[mu] on a hop that crosses the lattice boundary (the 4d part of the
+    domain wall operator's conventions).  Plain numpy: each hop is a shift of the whole
+    field by one site along the array axis of mu.
+    """
+    U, psi = _c(U), _c(psi)
+    axis = {0: 3, 1: 2, 2: 1, 3: 0}   # mu -> array axis of (t, z, y, x)
+    out = (4.0 - M5) * psi
+    eye = np.eye(4)
+    for mu in range(4):
+        ax, L = axis[mu], psi.shape[axis[mu]]
+        g = gamma(mu)
+        Umu = U[..., mu, :, :]
+        # forward: psi(x + mu), with bc[mu] where x + mu wraps (x = L - 1)
+        fwd = np.roll(psi, -1, axis=ax)
+        edge = [slice(None)] * psi.ndim
+        edge[ax] = L - 1
+        fwd[tuple(edge)] *= bc[mu]
+        t = np.einsum("tzyxab,tzyxsjb->tzyxsja", Umu, fwd)            # colour: U psi
+        out -= 0.5 * np.einsum("ij,tzyxsja->tzyxsia", eye - g, t)     # spin: (1 - g)
+        # backward: U_mu(x - mu)^dag psi(x - mu), with bc[mu] where x - mu wraps (x = 0)
+        bwd = np.roll(psi, 1, axis=ax)
+        Ub = np.roll(Umu, 1, axis=ax)
+        edge[ax] = 0
+        bwd[tuple(edge)] *= bc[mu]
+        t = np.einsum("tzyxba,tzyxsjb->tzyxsja", Ub.conj(), bwd)      # colour: U^dag psi
+        out -= 0.5 * np.einsum("ij,tzyxsja->tzyxsia", eye + g, t)     # spin: (1 + g)
+    return np.einsum("ij,tzyxsja->tzyxsia", gamma(4), out)
+
+
+def cf_coefficients(beta):
+    """Diagonal signs and couplings of the continued-fraction matrix (Sec. 3) for m = len(beta)
+    pole slices plus the last slice (Ls = m + 1), read off the printed matrix and continued to any
+    m: slice i < m carries (-1)^i H, slice m carries R gamma5 + beta_0 H; slices i and i + 1 are
+    coupled by 1/sqrt(beta_i beta_(i+1)) for i < m - 1 and by 1/sqrt(beta_(m-1)) for i = m - 1.
+    Returns (sigma[Ls], c[Ls - 1])."""
+    beta = np.asarray(beta, dtype=np.float64)
+    m = len(beta)
+    assert m >= 1 and np.all(beta > 0)
+    sigma = np.array([(-1.0) ** i for i in range(m)] + [beta[0]])
+    c = np.array([1.0 / np.sqrt(beta[i] * beta[i + 1]) for i in range(m - 1)] + [1.0 / np.sqrt(beta[m - 1])])
+    return sigma, c
+
+
+def apply_cf(U, psi, M5: float, beta, R: float, bc=(1, 1, 1, -1)) -> np.ndarray:
+    """The continued-fraction form of the overlap operator as a 5d Hermitian indefinite matrix
+    (Sec. 3): on a field with Ls = len(beta) + 1 slices,
+
+        (A psi)_i = sigma_i H_W psi_i + [i = m] R gamma5 psi_m + c_(i-1) psi_(i-1) + c_i psi_(i+1),
+
+    sigma and c from ``cf_coefficients``, no coupling beyond the first and last slices.  The
+    paper gives the structure but neither the beta_i nor R; both are inputs here."""
+    psi = _c(psi)
+    sigma, c = cf_coefficients(beta)
+    m = len(beta)
+    assert psi.shape[4] == m + 1
+    hw = apply_hw(U, psi, M5, bc)
+    out = sigma[None, None, None, None, :, None, None] * hw
+    out[..., m, :, :] += R * np.einsum("ij,tzyxjc->tzyxic", gamma(4), psi[..., m, :, :])
+    for i in range(m):
+        out[..., i, :, :] += c[i] * psi[..., i + 1, :, :]
+        out[..., i + 1, :, :] += c[i] * psi[..., i, :, :]
+    return out
 
 
 # ----------------------------------------------------------------------------

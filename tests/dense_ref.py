@@ -149,3 +149,71 @@ def dense_from_apply(apply, shape):
         e[i] = 1
         M[:, i] = apply(e.reshape(shape)).ravel()
     return M
+
+
+def dense_wilson(U, L, M5, bc):
+    """Dense 4d D_W(-M5) = (4 - M5) - 1/2 sum_mu [(1 - g) U delta_{x+mu} + (1 + g) U^dag delta_{x-mu}]
+    from shift operators, on (site4, spin, colour)."""
+    g, _ = chiral_gammas()
+    V = L[0] * L[1] * L[2] * L[3]
+    D = (4.0 - M5) * np.eye(V * 12, dtype=complex)
+    Uf = U.reshape(V, 4, 3, 3)
+    for x in itertools.product(*[range(l) for l in L]):
+        i = site_index(x, L)
+        for mu in range(4):
+            xp = list(x)
+            xp[mu] = (x[mu] + 1) % L[mu]
+            sp = bc[mu] if x[mu] == L[mu] - 1 else 1.0
+            j = site_index(xp, L)
+            D[i * 12:(i + 1) * 12, j * 12:(j + 1) * 12] += -0.5 * sp * np.kron(np.eye(4) - g[mu], Uf[i, mu])
+            xm = list(x)
+            xm[mu] = (x[mu] - 1) % L[mu]
+            sm = bc[mu] if x[mu] == 0 else 1.0
+            j = site_index(xm, L)
+            D[i * 12:(i + 1) * 12, j * 12:(j + 1) * 12] += -0.5 * sm * np.kron(np.eye(4) + g[mu], Uf[j, mu].conj().T)
+    return D
+
+
+def dense_cf(U, L, M5, bc, beta, R):
+    """The continued-fraction matrix of Sec. 3 as a dense matrix on (site4, s, spin, colour):
+    tridiagonal in s with H_W, -H_W, H_W, ... on the first m = len(beta) diagonal blocks,
+    R gamma5 + beta_0 H_W on the last, 1/sqrt(beta_i beta_(i+1)) between slices i and i + 1 < m and
+    1/sqrt(beta_(m-1)) between slices m - 1 and m."""
+    _, g5 = chiral_gammas()
+    V = L[0] * L[1] * L[2] * L[3]
+    m = len(beta)
+    Ls = m + 1
+    HW = np.kron(np.eye(V), np.kron(g5, np.eye(3))) @ dense_wilson(U, L, M5, bc)
+    T = np.zeros((Ls, Ls))
+    for i in range(m - 1):
+        T[i, i + 1] = T[i + 1, i] = 1.0 / np.sqrt(beta[i] * beta[i + 1])
+    T[m - 1, m] = T[m, m - 1] = 1.0 / np.sqrt(beta[m - 1])
+    sig = np.diag([(-1.0) ** i for i in range(m)] + [beta[0]])
+    last = np.zeros((Ls, Ls))
+    last[m, m] = 1.0
+    # order (site4, s, spin*3 + colour): site-major blocks of Ls * 12
+    P = np.zeros((V * Ls * 12, V * Ls * 12))
+    for v in range(V):
+        for s in range(Ls):
+            for a in range(12):
+                P[(v * Ls + s) * 12 + a, (s * V + v) * 12 + a] = 1.0   # from (s, site4, a) order
+    A_s = np.kron(sig, HW) + np.kron(T, np.eye(V * 12)) + R * np.kron(last, np.kron(np.eye(V), np.kron(g5, np.eye(3))))
+    return P @ A_s @ P.T
+
+
+def free_cf_momentum(p, M5, beta, R):
+    """Free-field continued-fraction matrix at momentum p on (s, spin): 4 Ls x 4 Ls, with
+    H_W(p) = gamma5 [(4 - M5 - sum cos p) + i sum gamma_mu sin p_mu]."""
+    g, g5 = chiral_gammas()
+    hw = g5 @ ((4.0 - M5 - sum(np.cos(p))) * np.eye(4) + 1j * sum(g[mu] * np.sin(p[mu]) for mu in range(4)))
+    m = len(beta)
+    Ls = m + 1
+    A = np.zeros((4 * Ls, 4 * Ls), dtype=complex)
+    for i in range(m):
+        A[4 * i:4 * i + 4, 4 * i:4 * i + 4] = (-1.0) ** i * hw
+    A[4 * m:, 4 * m:] = R * g5 + beta[0] * hw
+    for i in range(m):
+        c = 1.0 / np.sqrt(beta[i] * beta[i + 1]) if i < m - 1 else 1.0 / np.sqrt(beta[m - 1])
+        A[4 * i:4 * i + 4, 4 * (i + 1):4 * (i + 2)] += c * np.eye(4)
+        A[4 * (i + 1):4 * (i + 2), 4 * i:4 * i + 4] += c * np.eye(4)
+    return A
