@@ -213,7 +213,26 @@ HDCR_API const char* hdcr_last_error(void);
 HDCR_API int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* psi, void* out,
                     hipStream_t stream);
 
-/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC
+/* The continued-fraction form of the overlap operator (Sec. 3, the
+ * continued-fraction matrix: a 5d operator that is already Hermitian indefinite
+ * and nearest-neighbour) on a field of Ls = m + 1 slices, m >= 1 pole slices:
+ *   out_i = sigma_i H_W psi_i + [i = m] R g5 psi_m + c_(i-1) psi_(i-1) + c_i psi_(i+1),
+ *   H_W = g5 D_W(-M5), D_W psi(x) = (4 - M5) psi(x) - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *         + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)] (bc[mu] on boundary-crossing hops),
+ *   sigma_i = (-1)^i for i < m, sigma_m = beta[0];
+ *   c_i = 1/sqrt(beta[i] beta[i+1]) for i < m - 1, c_(m-1) = 1/sqrt(beta[m-1]),
+ *   and no coupling beyond the first and last slices (c_(-1) = c_m = 0).
+ * The paper prints this matrix for four pole slices and gives neither the
+ * beta_i nor R; they are the caller's (beta: host array of the m = Ls - 1 values,
+ * each finite and > 0; R finite), e.g. from a Zolotarev approximation of the
+ * sign function.  desc: Ls = m + 1 in [2, 64], M5 the Wilson mass, bc; mf unused;
+ * cayley_b 0 or 1.  Fields in the fine-field layout with s = the slice i; U, psi,
+ * out in dtype (C128 or C64); psi and out must not overlap.  One kernel launch
+ * on `stream`. */
+HDCR_API int hdcr_apply_cf(const hdcr_fine_desc* desc, hdcr_dtype dtype, const double* beta, double R, const void* U,
+                           const void* psi, void* out, hipStream_t stream);
+
+/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC
  * fermion force of the setting named in the abstract, Sec. 1 and Sec. 5; H as
  * in Sec. 3 and the conventions above):
  *   W[site4][mu][a][b] = dL/dRe U_mu(x)[a][b] + i dL/dIm U_mu(x)[a][b]

@@ -22,7 +22,7 @@ from . import _abi
 from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_LEVEL, CoarseDesc, FineDesc,  # noqa: F401
                    SolveParams, SolveStats)
 
-__all__ = ["Lattice", "apply_fine", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
+__all__ = ["Lattice", "apply_fine", "apply_cf", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
            "HDCRError", "Deflation", "build_deflation", "coarse_solve", "coarse_solve_static", "make_subspace_degrees"]
@@ -203,6 +203,24 @@ def apply_fine(lat: Lattice, U, psi, out=None, stream=None):
     d = lat.fine_desc()
     _abi.check(lib.hdcr_apply_fine(ctypes.byref(d), code, _ptr(U), _ptr(psi), _ptr(out), _stream(stream)),
                "hdcr_apply_fine")
+    return out
+
+
+def apply_cf(lat: Lattice, U, psi, beta, R: float, out=None, stream=None):
+    """out = A psi for the continued-fraction form of the overlap operator (Sec. 3): lat.Ls = m + 1
+    slices with m = len(beta) pole slices, H_W = gamma5 D_W(-lat.M5), caller coefficients beta
+    (m positive values) and R (one HIP kernel launch; see hdcr_apply_cf)."""
+    lib = load()
+    beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+    if beta.ndim != 1 or len(beta) != lat.Ls - 1:
+        raise ValueError(f"beta must hold Ls - 1 = {lat.Ls - 1} values")
+    _check_fields(lat, U, psi)
+    if out is None:
+        out = _torch().empty_like(psi)
+    _check_fields(lat, U, out)
+    d = lat.fine_desc()
+    _abi.check(lib.hdcr_apply_cf(ctypes.byref(d), _dtype_code(psi), beta.ctypes.data_as(_abi._dbl_p), float(R),
+                                 _ptr(U), _ptr(psi), _ptr(out), _stream(stream)), "hdcr_apply_cf")
     return out
 
 

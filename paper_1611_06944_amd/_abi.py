@@ -85,6 +85,7 @@ PROTOTYPES = {
     "hdcr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "hdcr_last_error": (ctypes.c_char_p, []),
     "hdcr_apply_fine": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _vp, _vp, _vp]),
+    "hdcr_apply_cf": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _dbl_p, ctypes.c_double, _vp, _vp, _vp, _vp]),
     "hdcr_fermion_force": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "hdcr_vec_dot": (ctypes.c_int, [_i32, _i64, _vp, _vp, _dbl_p, _vp, _sz, _vp]),
     "hdcr_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams)]),

@@ -144,6 +144,48 @@ int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U,
     return HDCR_OK;
 }
 
+int hdcr_apply_cf(const hdcr_fine_desc* desc, hdcr_dtype dtype, const double* beta, double R, const void* U,
+                  const void* psi, void* out, hipStream_t stream) {
+    int e = check_fine_desc(desc);
+    if (e) return e;
+    if (dtype != HDCR_C128 && dtype != HDCR_C64) return fail(HDCR_EINVAL, "hdcr_apply_cf: dtype must be C128 or C64");
+    const int Ls = desc->Ls, m = Ls - 1;
+    if (Ls < 2 || Ls > CF_MAX_LS)
+        return fail(HDCR_EINVAL, "hdcr_apply_cf: Ls (pole slices + 1) must be in [2, " + std::to_string(CF_MAX_LS) + "]");
+    if (desc->cayley_b != 0.0 && desc->cayley_b != 1.0)
+        return fail(HDCR_EINVAL, "hdcr_apply_cf: the Wilson kernel has no Cayley scale (cayley_b must be 0 or 1)");
+    if (!beta) return fail(HDCR_EINVAL, "hdcr_apply_cf: null beta");
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(beta[i]) || !(beta[i] > 0.0))
+            return fail(HDCR_EINVAL, "hdcr_apply_cf: beta[" + std::to_string(i) + "] must be finite and > 0");
+    if (!std::isfinite(R)) return fail(HDCR_EINVAL, "hdcr_apply_cf: R must be finite");
+    const size_t cs = csize(dtype);
+    if ((e = check_ptr(U, cs, "U")) || (e = check_ptr(psi, cs, "psi")) || (e = check_ptr(out, cs, "out"))) return e;
+    const FineGeom g = make_geom(desc);
+    const size_t fbytes = (size_t)12 * g.N5 * cs;
+    if (overlap(psi, fbytes, out, fbytes)) return fail(HDCR_EINVAL, "hdcr_apply_cf: psi and out overlap");
+    // the printed matrix continued to m pole slices: (-1)^i H_W on slice i < m,
+    // R gamma5 + beta_0 H_W on slice m; slices i, i + 1 coupled by
+    // 1/sqrt(beta_i beta_(i+1)) (i < m - 1) and 1/sqrt(beta_(m-1)) (i = m - 1)
+    CfCoef k{};
+    for (int i = 0; i < Ls; ++i) {
+        k.sigma[i] = (i < m) ? ((i % 2) ? -1.0 : 1.0) : beta[0];
+        const double c_up = (i < m - 1) ? 1.0 / std::sqrt(beta[i] * beta[i + 1]) : (i == m - 1 ? 1.0 / std::sqrt(beta[i]) : 0.0);
+        k.cup[i] = c_up;
+        if (i + 1 < Ls) k.cdn[i + 1] = c_up;
+    }
+    k.cdn[0] = 0.0;
+    k.R = R;
+    k.wdiag = 4.0 - desc->M5;
+    k.sites = Ls <= 16 ? 16 : 256 / Ls;
+    if (dtype == HDCR_C128)
+        launch_cf<double>(g, k, (const double2*)U, (const double2*)psi, (double2*)out, stream);
+    else
+        launch_cf<float>(g, k, (const float2*)U, (const float2*)psi, (float2*)out, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
 int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, const void* U, const void* chi, const void* psi,
                        void* W, void* T, hipStream_t stream) {
     int e = check_fine_desc(desc);

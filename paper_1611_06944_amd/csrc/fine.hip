@@ -1160,6 +1160,90 @@ void launch_dslash_classes(const CoarseGeom& c, const double2* U, const double2*
     hipLaunchKernelGGL(dslash_classes_kernel, dim3(blocks), dim3(WG), 0, s, c.f, cs, U, in, out, fstride);
 }
 
+namespace {
+
+// Continued-fraction operator (Sec. 3): one work-item per 5d site (4d site j of
+// the workgroup, slice s), s fastest, k.sites whole 4d sites per workgroup.
+// The 8 link matrices of each site (U_mu(x), then U_mu(x - mu)) and the
+// workgroup's own spinors are staged in LDS: the slice couplings read their
+// partners psi(s -+ 1) from there, so only the 4d hops gather through the
+// vector-memory path.  Each output is written once, at its own slice.
+constexpr int CF_WG = 256;
+constexpr int CF_SITES_MAX = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(CF_WG) cf_kernel(FineGeom g, CfCoef k, const C2<T>* U, const C2<T>* in, C2<T>* out) {
+    constexpr uint32_t CB = sizeof(C2<T>);
+    __shared__ C2<T> lds[CF_SITES_MAX * 8 * LPAD];
+    __shared__ C2<T> spin[12 * CF_WG];  // [c][work-item]
+    const int Ls = g.Ls, m = Ls - 1;
+    const int lb = logical_block(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x;
+    const int j = tid / Ls, s = tid - (tid / Ls) * Ls;
+    const int lsite = lb * k.sites + j;
+    const bool active = (j < k.sites) && (lsite < g.V4);
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    const Site st = traverse(g, active ? lsite : 0);
+    const Nbrs<T> n = neighbours<T>(g, st);
+    const uint32_t o0 = (uint32_t)(st.site * Ls + s) * CB;
+    C2<T> v[12];
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = Buf<T>::ld(f.in, o0, (uint32_t)c * f.cstride);
+            spin[c * CF_WG + tid] = v[c];
+        }
+        // matrix d < 4: U_d(x); d >= 4: U_(d-4)(x - (d-4)); the site's Ls work-items share the loads
+        for (int q = s; q < 72; q += Ls) {
+            const int d = q / 9, e = q - 9 * (q / 9);
+            // a select, not n.b[d - 4]: a run-time index would put the neighbour table in scratch
+            const int src = (d < 4) ? st.site : (d == 4 ? n.b[0] : d == 5 ? n.b[1] : d == 6 ? n.b[2] : n.b[3]);
+            lds[(j * 8 + d) * LPAD + e] = Buf<T>::ld(f.U, (uint32_t)(src * 36 + (d & 3) * 9 + e) * CB, 0u);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    // D_W(-M5) psi_s: diagonal 4 - M5, then the eight 4d hops
+    C2<T> acc[12];
+    const T wd = (T)k.wdiag;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cscale<T>(wd, v[c]);
+    const C2<T>* lnk = lds + j * 8 * LPAD;
+    hop_pair_lds<T, 0>(f, n, Ls, s, lnk, acc);
+    hop_pair_lds<T, 1>(f, n, Ls, s, lnk, acc);
+    hop_pair_lds<T, 2>(f, n, Ls, s, lnk, acc);
+    hop_pair_lds<T, 3>(f, n, Ls, s, lnk, acc);
+    // sigma_s gamma5 D_W psi_s + [s = m] R gamma5 psi_s + couplings to the neighbouring slices
+    const T sg = (T)k.sigma[s];
+    const T rr = (s == m) ? (T)k.R : (T)0;
+    const T cd = (T)k.cdn[s], cu = (T)k.cup[s];
+    const int td = (s > 0) ? tid - 1 : tid, tu = (s < m) ? tid + 1 : tid;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const T g5 = (c < 6) ? (T)1 : (T)-1;
+        C2<T> o = cscale<T>(g5 * sg, acc[c]);
+        axpy<T>(g5 * rr, v[c], o);
+        axpy<T>(cd, spin[c * CF_WG + td], o);
+        axpy<T>(cu, spin[c * CF_WG + tu], o);
+        Buf<T>::st_nt(o, f.out, o0, (uint32_t)c * f.cstride);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_cf(const FineGeom& g, const CfCoef& k, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+    const int blocks = (g.V4 + k.sites - 1) / k.sites;
+    hipLaunchKernelGGL((cf_kernel<T>), dim3(blocks), dim3(k.sites * g.Ls), 0, s, g, k, U, in, out);
+}
+
+template void launch_cf<double>(const FineGeom&, const CfCoef&, const double2*, const double2*, double2*, hipStream_t);
+template void launch_cf<float>(const FineGeom&, const CfCoef&, const float2*, const float2*, float2*, hipStream_t);
+
 template void launch_dslash<double>(const FineGeom&, const double2*, const double2*, double2*, hipStream_t);
 template void launch_dslash<float>(const FineGeom&, const float2*, const float2*, float2*, hipStream_t);
 template void launch_dslash_epi<double>(const FineGeom&, const double2*, const double2*, double2*, const Epi<double>&,

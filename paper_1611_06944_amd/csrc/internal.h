@@ -231,6 +231,23 @@ bool launch_dslash_h16(const FineGeom& g, const float2* U, const void* in, void*
 bool launch_dslash_h16_epi(const FineGeom& g, const float2* U, const void* in, void* out, const Epi<float>& e,
                            hipStream_t s);
 
+// Continued-fraction form of the overlap operator (Sec. 3) on Ls = m + 1 slices:
+//   out_s = sigma_s H_W psi_s + [s = m] R gamma5 psi_s + cdn_s psi_(s-1) + cup_s psi_(s+1),
+// H_W = gamma5 D_W(-M5) with D_W's diagonal wdiag = 4 - M5 and the 4d hops of
+// FineGeom (coefficient g.hop = -1/2, boundary factors bc).  sites: 4d sites per
+// workgroup (sites * Ls <= 256 work-items).
+constexpr int CF_MAX_LS = 64;
+struct CfCoef {
+    double sigma[CF_MAX_LS];
+    double cdn[CF_MAX_LS];  // coupling to slice s - 1 (0 at s = 0)
+    double cup[CF_MAX_LS];  // coupling to slice s + 1 (0 at s = m)
+    double R;
+    double wdiag;
+    int sites;
+};
+template <typename T>
+void launch_cf(const FineGeom& g, const CfCoef& k, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s);
+
 // Gauge-link gradient W and su(3) force T of L = Re <chi, H psi> (W or T may be
 // null).  Shape: r lanes per 4d site (2, 4, 8 or 16), ms wave groups splitting
 // the four directions (1 or 2), p fifth-dimension slices per load (2: FP32
