@@ -306,12 +306,14 @@ HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128,
  * a BF16 x BF16 contraction with FP32 accumulation.  v, out: C64
  * [nrhs][site_c][k], not overlapping.  Needs Nb in {16, 32, 64, 128}.
  * variant 0: the tile shape hdcr_tune_coarse_batched chose for this shape
- * (variant 2, or 1 for Nb = 16, if it has not been tuned); 1..HDCR_MFMA_VARIANTS:
+ * (if it has not been tuned: variant 8 for Nb = 64, else 2, or 1 for Nb = 16); 1..HDCR_MFMA_VARIANTS:
  * an explicit tile shape (2, 4, 8 wavefronts per coarse site, blocks read
  * directly or staged in LDS; 7: 8 wavefronts with all 9 blocks prefetched, Nb =
- * 64 only); a variant with more wavefronts than Nb / 8 is rejected.  All variants perform the same operations per output element, so
+ * 64 only; 8: as 7 with the blocks held in registers across passes of 16
+ * right-hand sides and every load of a pass issued before its first use, Nb = 64
+ * only); a variant with more wavefronts than Nb / 8 is rejected.  All variants perform the same operations per output element, so
  * they give identical results.  Stream-ordered. */
-#define HDCR_MFMA_VARIANTS 7
+#define HDCR_MFMA_VARIANTS 8
 HDCR_API int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
                                        int32_t nrhs, int32_t variant, hipStream_t stream);
 /* Autotuner of the batched apply of A (Sec. 4): times every tile shape on the caller's

@@ -17,7 +17,7 @@ HDCR_ENAN = 3
 HDCR_ERANK = 4
 
 C128, C64, BF16C, F16C = 0, 1, 2, 3
-MFMA_VARIANTS = 7  # tile shapes of the batched coarse apply
+MFMA_VARIANTS = 8  # tile shapes of the batched coarse apply
 PRECOND_NONE, PRECOND_TWO_LEVEL = 0, 1
 WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE, WS_COARSE = 0, 1, 2, 3, 4, 5
 DEFL_MAX = 64

@@ -84,6 +84,9 @@ static int tuned_variant(const CoarseGeom& c, int nrhs) {
     std::lock_guard<std::mutex> lk(tune_mutex);
     auto it = tune_table.find(std::make_tuple(c.Nc, c.Nb, nrhs, dev));
     if (it != tune_table.end()) return it->second;
+    // untuned: the batched-load variant for Nb = 64 (fastest measured at 12 to 96
+    // right-hand sides), else four wavefronts per site where Nb allows them
+    if (coarse_mfma_eligible(c, 8)) return 8;
     return coarse_mfma_eligible(c, 2) ? 2 : 1;
 }
 

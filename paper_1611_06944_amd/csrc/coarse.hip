@@ -1447,10 +1447,11 @@ __global__ void __launch_bounds__(64 * NW) coarse_mfma_kernel(CoarseGeom c, cons
                                                               const float2* __restrict__ v, float2* __restrict__ out,
                                                               int nrhs) {
     extern __shared__ unsigned char smem_raw[];
-    uint32_t* vb = reinterpret_cast<uint32_t*>(smem_raw);  // [9][MR][Nb] bf16 pairs
-    uint32_t* ab = vb + 9 * MR * c.Nb;                      // [Nb][Nb] one block (ALDS)
-    const int a = blockIdx.x;
     const int Nb = c.Nb;
+    const int VST = Nb + 4;  // row stride of the staged vectors: the 16 columns of an operand load in distinct banks
+    uint32_t* vb = reinterpret_cast<uint32_t*>(smem_raw);  // [9][MR][VST] bf16 pairs
+    uint32_t* ab = vb + 9 * MR * VST;                       // [Nb][Nb] one block (ALDS)
+    const int a = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // scalar: uniform row-tile tests
     const int kq = lane >> 4, col = lane & 15;
@@ -1465,7 +1466,7 @@ __global__ void __launch_bounds__(64 * NW) coarse_mfma_kernel(CoarseGeom c, cons
             const int d = e / (MR * Nb), rem = e - d * MR * Nb;
             const int r = rem / Nb, k = rem - r * Nb;
             const float2 x = (r < nr) ? v[((size_t)(r0 + r) * c.Nc + coarse_nbr(c, a, d)) * Nb + k] : make_float2(0, 0);
-            vb[e] = pack_bf16c(x);
+            vb[(d * MR + r) * VST + k] = pack_bf16c(x);
         }
         f32x4 acc[TPW];  // row tiles wave + NW t of this wavefront
 #pragma unroll
@@ -1498,10 +1499,10 @@ __global__ void __launch_bounds__(64 * NW) coarse_mfma_kernel(CoarseGeom c, cons
                 }
             }
             __syncthreads();
-            const uint32_t* vd = vb + d * MR * Nb;
+            const uint32_t* vd = vb + d * MR * VST;
             for (int ks = 0; ks < Nb / 16; ++ks) {
                 const int k0 = 16 * ks + 4 * kq;
-                const u32x4 bw = *reinterpret_cast<const u32x4*>(vd + col * Nb + k0);
+                const u32x4 bw = *reinterpret_cast<const u32x4*>(vd + col * VST + k0);
                 const bf16x8 bop = __builtin_bit_cast(bf16x8, bw);
                 // ntiles = NW * TPW exactly: every wavefront owns TPW row tiles, and
                 // the accumulation chains carry no branch
@@ -1534,9 +1535,115 @@ __global__ void __launch_bounds__(64 * NW) coarse_mfma_kernel(CoarseGeom c, cons
     }
 }
 
+// Nb = 64, 8 wavefronts, one row tile each: the variant that keeps the memory
+// system busy.  Every load is issued before the first of them is used: the
+// first pass's neighbour vectors (16-byte pairs of complex entries, nine per
+// work-item), then the 9 blocks of the site (two 16-byte words per work-item and
+// block, held in registers across all passes of right-hand sides), so that the
+// vectors are rounded to bf16 into LDS and block d is multiplied while the later
+// blocks are still arriving.  The vector rows and the
+// block copy in LDS have a row stride of Nb + 4 words, so the 16 columns of a
+// B-operand load and the four k rows of an A-operand load fall in different banks.  The MFMA sequence per output is the
+// other variants', so the results are the same bits.
+constexpr int PF_NB = 64, PF_NW = 8, PF_AST = PF_NB + 4;
+__global__ void __launch_bounds__(64 * PF_NW) coarse_mfma_pf_kernel(CoarseGeom c, const uint32_t* __restrict__ A,
+                                                                    const float2* __restrict__ v,
+                                                                    float2* __restrict__ out, int nrhs) {
+    constexpr int NB = PF_NB, NT = 64 * PF_NW;
+    constexpr int NV4 = 9 * MR * NB / 2 / NT;  // 16-byte vector loads per work-item and pass (9)
+    constexpr int NA4 = NB * NB / 4 / NT;       // 16-byte block loads per work-item and block (2)
+    extern __shared__ unsigned char smem_raw[];
+    uint32_t* vb = reinterpret_cast<uint32_t*>(smem_raw);  // [9][MR][PF_AST] bf16 pairs
+    uint32_t* ab = vb + 9 * MR * PF_AST;                    // [NB][PF_AST] one block
+    const int a = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int kq = lane >> 4, col = lane & 15;
+    const uint32_t rot = (col & 1) ? 16u : 0u;
+    const uint32_t flip = (col & 1) ? 0u : 0x80000000u;
+    const uint32_t* Aa = A + (size_t)a * 9 * NB * NB;
+    int nbr[9];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) nbr[d] = coarse_nbr(c, a, d);
+    // the pass's neighbour vectors: 16-byte pairs [9][MR][NB / 2], zero beyond nrhs
+    float4 vx[NV4];
+    auto load_vectors = [&](int r0, int nr) {
+#pragma unroll
+        for (int u = 0; u < NV4; ++u) {
+            const int e2 = threadIdx.x + u * NT;
+            const int d = e2 / (MR * NB / 2), rem = e2 - d * (MR * NB / 2);
+            const int r = rem / (NB / 2), kp = rem - r * (NB / 2);
+            int nd = nbr[0];
+#pragma unroll
+            for (int q = 1; q < 9; ++q) nd = (d == q) ? nbr[q] : nd;
+            vx[u] = (r < nr) ? *reinterpret_cast<const float4*>(v + ((size_t)(r0 + r) * c.Nc + nd) * NB + 2 * kp)
+                             : make_float4(0, 0, 0, 0);
+        }
+    };
+    // the first pass's vectors are requested before the blocks: loads complete in
+    // order, so the vectors are usable while the blocks are still arriving, and
+    // block d is consumed while blocks d + 1 .. 8 arrive
+    load_vectors(0, min(MR, nrhs));
+    __builtin_amdgcn_sched_barrier(0);
+    u32x4 pre[9][NA4];
+#pragma unroll
+    for (int d = 0; d < 9; ++d)
+#pragma unroll
+        for (int u = 0; u < NA4; ++u)
+            pre[d][u] = *reinterpret_cast<const u32x4*>(Aa + (size_t)d * NB * NB + 4 * (threadIdx.x + u * NT));
+    __builtin_amdgcn_sched_barrier(0);
+    for (int r0 = 0; r0 < nrhs; r0 += MR) {
+        const int nr = min(MR, nrhs - r0);
+        if (r0 > 0) load_vectors(r0, nr);
+        __syncthreads();  // the previous pass has finished reading vb
+#pragma unroll
+        for (int u = 0; u < NV4; ++u) {
+            const int e2 = threadIdx.x + u * NT;
+            uint2 w;
+            w.x = pack_bf16c(make_float2(vx[u].x, vx[u].y));
+            w.y = pack_bf16c(make_float2(vx[u].z, vx[u].w));
+            const int dr = e2 / (NB / 2), kp = e2 - dr * (NB / 2);  // (d, r) row and pair in the row
+            *reinterpret_cast<uint2*>(vb + dr * PF_AST + 2 * kp) = w;
+        }
+        f32x4 acc = f32x4{0, 0, 0, 0};
+        const int row = 16 * wave + col;
+        const int j = row >> 1;
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            __syncthreads();  // previous block consumed (and, for d = 0, vb written)
+#pragma unroll
+            for (int u = 0; u < NA4; ++u) {
+                const int e = 4 * (threadIdx.x + u * NT);
+                const int k = e / NB, jj = e - k * NB;
+                *reinterpret_cast<u32x4*>(ab + k * PF_AST + jj) = pre[d][u];
+            }
+            __syncthreads();
+            const uint32_t* vd = vb + d * MR * PF_AST;
+#pragma unroll
+            for (int ks = 0; ks < NB / 16; ++ks) {
+                const int k0 = 16 * ks + 4 * kq;
+                const bf16x8 bop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(vd + col * PF_AST + k0));
+                u32x4 aw;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t w = ab[(k0 + q) * PF_AST + j];
+                    aw[q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aw), bop, acc, 0, 0, 0);
+            }
+        }
+        if (col < nr) {
+            const int j0 = 8 * wave + 2 * kq;
+            float2* o = out + ((size_t)(r0 + col) * c.Nc + a) * NB + j0;
+            o[0] = make_float2(acc[0], acc[1]);
+            o[1] = make_float2(acc[2], acc[3]);
+        }
+    }
+}
+
 template <int NW, bool ALDS>
 void mfma_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
-    const size_t lds = (size_t)9 * MR * c.Nb * 4 + (ALDS ? (size_t)c.Nb * c.Nb * 4 : 0);
+    const size_t lds = (size_t)9 * MR * (c.Nb + 4) * 4 + (ALDS ? (size_t)c.Nb * c.Nb * 4 : 0);
     const int tpw = (2 * c.Nb / 16) / NW;  // exact (coarse_mfma_eligible)
     if (tpw == 1) {
         hipLaunchKernelGGL((coarse_mfma_kernel<NW, 1, ALDS>), dim3(c.Nc), dim3(64 * NW), lds, s, c, A, v, out, nrhs);
@@ -1556,19 +1663,20 @@ void mfma_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2
 }  // namespace
 
 // tile-shape variants of the batched apply: waves per coarse site x block staging
-int coarse_mfma_variants() { return 7; }
+int coarse_mfma_variants() { return 8; }
 const char* coarse_mfma_variant_name(int k) {
-    static const char* names[7] = {"2 waves/site, A direct",  "4 waves/site, A direct",  "8 waves/site, A direct",
+    static const char* names[8] = {"2 waves/site, A direct",  "4 waves/site, A direct",  "8 waves/site, A direct",
                                    "2 waves/site, A via LDS", "4 waves/site, A via LDS", "8 waves/site, A via LDS",
-                                   "8 waves/site, A prefetched (Nb 64)"};
-    return (k >= 1 && k <= 7) ? names[k - 1] : "";
+                                   "8 waves/site, A prefetched (Nb 64)",
+                                   "8 waves/site, A held across passes, loads batched (Nb 64)"};
+    return (k >= 1 && k <= 8) ? names[k - 1] : "";
 }
 // waves per coarse site of a variant
 static int mfma_waves(int variant) { return variant == 1 || variant == 4 ? 2 : variant == 2 || variant == 5 ? 4 : 8; }
 bool coarse_mfma_eligible(const CoarseGeom& c, int variant) {
     const int nb = c.Nb;
     if (nb != 16 && nb != 32 && nb != 64 && nb != 128) return false;
-    if (variant == 7 && nb != 64) return false;  // register prefetch sized for Nb = 64 blocks
+    if ((variant == 7 || variant == 8) && nb != 64) return false;  // register prefetch sized for Nb = 64 blocks
     return mfma_waves(variant) <= 2 * nb / 16;
 }
 void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, const float2* v, float2* out, int nrhs,
@@ -1580,9 +1688,14 @@ void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, con
         case 4: mfma_launch<2, true>(c, A, v, out, nrhs, s); break;
         case 5: mfma_launch<4, true>(c, A, v, out, nrhs, s); break;
         case 6: mfma_launch<8, true>(c, A, v, out, nrhs, s); break;
+        case 8: {
+            const size_t lds = (size_t)9 * MR * PF_AST * 4 + (size_t)PF_NB * PF_AST * 4;
+            hipLaunchKernelGGL(coarse_mfma_pf_kernel, dim3(c.Nc), dim3(64 * PF_NW), lds, s, c, A, v, out, nrhs);
+            break;
+        }
         default: {
             // 8 waves, Nb = 64: 16 KB blocks, 2 loads of 16 B per work-item and block
-            const size_t lds = (size_t)9 * MR * c.Nb * 4 + (size_t)c.Nb * c.Nb * 4;
+            const size_t lds = (size_t)9 * MR * (c.Nb + 4) * 4 + (size_t)c.Nb * c.Nb * 4;
             hipLaunchKernelGGL((coarse_mfma_kernel<8, 1, true, 2>), dim3(c.Nc), dim3(512), lds, s, c, A, v, out, nrhs);
             break;
         }

@@ -155,8 +155,8 @@ def test_batched_coarse_apply_mfma(L, block, nvec, nrhs):
     ref = oracle.coarse_apply(A_log, v.astype(np.complex64).astype(np.complex128), cs.cdims)
     bound = (2.0 ** -8 + 1e-5) * oracle.coarse_apply(np.abs(A_log), np.abs(v), cs.cdims).real
     # variants with at most Nb / 8 wavefronts per coarse site apply
-    waves = {1: 2, 2: 4, 3: 8, 4: 2, 5: 4, 6: 8, 7: 8}
-    ok = [k for k in range(1, hd._abi.MFMA_VARIANTS + 1) if waves[k] <= cs.nb // 8 and (k != 7 or cs.nb == 64)]
+    waves = {1: 2, 2: 4, 3: 8, 4: 2, 5: 4, 6: 8, 7: 8, 8: 8}
+    ok = [k for k in range(1, hd._abi.MFMA_VARIANTS + 1) if waves[k] <= cs.nb // 8 and (k < 7 or cs.nb == 64)]
     outs = [to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=k)) for k in ok]
     err = np.abs(outs[0] - ref)
     assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
