@@ -6,20 +6,26 @@ exp(0.3 i A) with A Gaussian su(3), seed 1; complex Gaussian source, seed 0).
 
 Setup (timed and reported on its own, as the paper reports its subspace
 set-up apart from the solve): power iteration for lambda_max^2, 32 subspace
-vectors by a degree-D Chebyshev low-pass filter of seeded Gaussian noise (FP32),
-chirally split block basis on 4^4 x Ls blocks (Nb = 64, coarse 6^4) and the
-little Dirac operator in BF16 storage.
+vectors by a degree-200 Chebyshev low-pass filter of seeded Gaussian noise
+(FP32 arithmetic on FP16-stored fields), chirally split block basis on
+4^4 x Ls blocks (Nb = 64, coarse 6^4) and the little Dirac operator in BF16
+storage.
 
 One timed step = one pass of the whole solve path on that system:
   * the HDCR solve to |b - Hx| <= 1e-8 |b| (FP64 flexible GCR(8), FP32
-    two-level cycle with the order-10 Chebyshev smoother on [1, 64], coarse CR
-    on the BF16 little Dirac operator to 5e-2);
+    two-level cycle with the order-10 Chebyshev smoother on [0.5, 64], the FP16
+    copy of the basis for restriction and prolongation, coarse CR on the BF16
+    little Dirac operator to 0.2);
   * the plain conjugate-residual solve of the same system (FP64);
-  * a fine-operator sweep: 20 applications of H in FP32 and 20 in FP64, each
-    launch bracketed by HIP events on the stream it runs on.
+  * a fine-operator sweep: 20 applications of H in FP32, 20 in FP64 and 20 with
+    FP16 field storage, each launch bracketed by HIP events on the stream it
+    runs on.
 The printed value is the achieved algorithmic bandwidth of the FP32 fine apply
 (the dominant kernel of the HDCR solve): bytes = (2 * 12 * N5 spinor entries +
 36 * V4 link entries) * 8, i.e. psi read once, written once, links once.
+Further sections: the project's copy-kernel ceiling, the deflated and
+FP16-smoother solves, the continued-fraction overlap operator, the batched
+coarse apply on the matrix cores, the fermion force and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -67,7 +73,10 @@ def parse():
     ap.add_argument("--force-only", action="store_true", help="only the fermion-force measurement (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device-to-device copies (reference for the HBM byte counters)")
-    ap.add_argument("--cpu-sample-applies", type=int, default=30)
+    ap.add_argument("--cpu-sample-applies", type=int, default=6)
+    ap.add_argument("--coarse-multi-only", action="store_true",
+                    help="only the batched coarse apply sweep (profiling runs)")
+    ap.add_argument("--cf-only", action="store_true", help="only the continued-fraction operator (profiling runs)")
     ap.add_argument("--defl-k", type=int, default=48, help="coarse deflation: eigenpairs kept (0: skip)")
     ap.add_argument("--defl-m", type=int, default=64, help="coarse deflation: block size of the set-up")
     ap.add_argument("--defl-degree", type=int, default=60)
@@ -105,20 +114,217 @@ def fine_bytes(V4, Ls, csize):
     return (2 * 12 * V4 * Ls + 36 * V4) * csize
 
 
-def cpu_baseline(U, b, L, Ls, n_applies):
-    """The FP64 oracle's fine apply on the host cores (a bounded sample: n_applies applications)."""
+def cpu_model():
+    """The host CPU's model name (lscpu's 'Model name', from /proc/cpuinfo) and its thread count."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline(U, b, L, Ls, n_applies, gpu_counts):
+    """The FP64 oracle on the host cores, on bounded samples (about 20-30 s of CPU work).
+
+    value: the oracle's fine apply at the benchmark lattice in algorithmic GB/s (n_applies
+    applications).  legs: the other steps of the path measured directly where they fit the
+    budget (coarse apply at the cfg-2 and cfg-3 coarse shapes), or timed on a smaller piece and
+    scaled by the work ratio, labelled 'extrapolated': the coarse build (block basis and A per
+    column, timed at 8^4 x 16 with the benchmark's blocks and Nb = 64, scaled by N5 and by the
+    number of columns), plain CR and HDCR at 24^4 x 16 (the measured per-operation times times
+    the operation counts of the GPU solves of the same system)."""
     import oracle
+    import hdcr_inputs as hi
     p = oracle.Params(tuple(L), Ls, M5=1.8, mf=0.01)
     oracle.apply_h(U, b, p)  # warm up / load
     t0 = time.perf_counter()
     for _ in range(n_applies):
         oracle.apply_h(U, b, p)
-    dt = (time.perf_counter() - t0) / n_applies
+    t_apply = (time.perf_counter() - t0) / n_applies
     V4 = int(np.prod(L))
+    N5 = V4 * Ls
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(fine_bytes(V4, Ls, 16) / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
-            "kind": "oracle", "sample": f"{n_applies} FP64 applications of H at {'x'.join(map(str, L))}x{Ls} "
-                                        f"({dt * 1e3:.0f} ms each)"}
+    model, threads = cpu_model()
+    legs = {"fine_apply_s": round(t_apply, 4)}
+    # numpy vector work of one CR iteration on fields of this size (2 inner products, 4 axpys, 1 norm)
+    x, y = b.copy(), b.copy()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        a = np.vdot(x, y)
+        x += 0.1 * y
+        y -= 0.1 * x
+        np.vdot(y, y)
+        a = np.vdot(x, y)
+        x += 0.1 * y
+        y += 0.1 * x
+    t_vec = (time.perf_counter() - t0) / 2
+    del x, y
+    legs["cr_vector_work_per_iter_s"] = round(t_vec, 4)
+    # coarse apply at the cfg-2 (4^4, Nb 48) and cfg-3 (6^4, Nb 64) coarse shapes, Gaussian A
+    rng = np.random.default_rng(5)
+    t_capply = {}
+    for name, cd, nb in (("cfg2_4x4x4x4_nb48", (4, 4, 4, 4), 48), ("cfg3_6x6x6x6_nb64", (6, 6, 6, 6), 64)):
+        nc = int(np.prod(cd))
+        A = rng.standard_normal((nc, 9, nb, nb)) + 1j * rng.standard_normal((nc, 9, nb, nb))
+        v = rng.standard_normal((nc, nb)) + 1j * rng.standard_normal((nc, nb))
+        oracle.coarse_apply(A, v, cd)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            oracle.coarse_apply(A, v, cd)
+        t_capply[name] = (time.perf_counter() - t0) / 5
+        legs[f"coarse_apply_{name}_s"] = round(t_capply[name], 5)
+        del A
+    # coarse build pieces at 8^4 x 16 with 4^4 blocks and nvec = 32 (Nb = 64)
+    Ls_ = Ls
+    Lb = (8, 8, 8, 8)
+    pb = oracle.Params(Lb, Ls_, M5=1.8, mf=0.01)
+    csb = oracle.Coarse(pb, (4, 4, 4, 4), 32)
+    Ub = hi.gauge_field(Lb, seed=1)
+    vecs = [hi.gaussian_fermion(Lb, Ls_, seed=100 + k) for k in range(32)]
+    t0 = time.perf_counter()
+    basis, _ = oracle.block_basis(vecs, csb)
+    t_basis = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.coarse_columns(Ub, basis, csb, [0, 40])
+    t_col = (time.perf_counter() - t0) / 2
+    psi_b = vecs[0]
+    t0 = time.perf_counter()
+    oracle.prolong(basis, oracle.restrict(basis, psi_b, csb), csb)
+    t_rp = time.perf_counter() - t0
+    del vecs, basis
+    N5b = int(np.prod(Lb)) * Ls_
+    for name, n5, nvec in (("cfg2_16x16x16x16x16_nb48", 16 ** 4 * 16, 24), ("cfg3_24x24x24x24x16_nb64", 24 ** 4 * 16, 32)):
+        r = n5 / N5b
+        legs[f"coarse_build_{name}_s_extrapolated"] = round(t_basis * r * (nvec / 32) ** 2 + t_col * r * 2 * nvec, 1)
+    tag = f"{'x'.join(map(str, L))}x{Ls}"
+    t_rp24 = t_rp * N5 / N5b
+    legs[f"restrict_plus_prolong_{tag}_nb64_s_extrapolated"] = round(t_rp24, 3)
+    if gpu_counts:
+        cr_it = gpu_counts["cr_iters"]
+        legs[f"plain_cr_{tag}_s_extrapolated"] = round(cr_it * (t_apply + t_vec) + 2 * t_apply, 1)
+        h = gpu_counts["hdcr"]
+        # every fine apply at FP64 oracle cost, every coarse apply at the cfg-3 cost, one restriction
+        # and prolongation per cycle (two cycles of smoothing share one coarse solve), FGCR vector
+        # work of about one CR iteration's per outer iteration and window vector
+        n_fine = h["fine_applies_inner"] + h["fine_applies_f64"]
+        t_h = (n_fine * t_apply + h["coarse_applies"] * t_capply["cfg3_6x6x6x6_nb64"]
+               + h["outer_iters"] * (t_rp24 + 8 * t_vec))
+        legs[f"hdcr_{tag}_s_extrapolated"] = round(t_h, 1)
+        legs["extrapolation_counts"] = {"cr_iters": cr_it, "hdcr_fine_applies": n_fine,
+                                        "hdcr_coarse_applies": h["coarse_applies"], "hdcr_outer": h["outer_iters"]}
+    return {"value": round(fine_bytes(V4, Ls, 16) / t_apply / 1e9, 3), "unit": "GB/s", "cores": cores,
+            "kind": "oracle", "cpu_model": model, "host_threads": threads,
+            "sample": f"{n_applies} FP64 applications of H at {'x'.join(map(str, L))}x{Ls} "
+                      f"({t_apply * 1e3:.0f} ms each); legs as listed",
+            "legs": legs}
+
+
+def copy_ceiling(hd, torch):
+    """The project's plain streaming copy kernel (hdcr_stream_copy) on 1 GiB: read + write bytes
+    per second, the practical bandwidth ceiling beside the datasheet peak."""
+    stream = torch.cuda.current_stream()
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        hd.stream_copy(src, dst)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a_, b_ in evs:
+        a_.record(stream)
+        hd.stream_copy(src, dst)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * (1 << 30) / (ms * 1e-3) / 1e9
+    return {"kernel": "hdcr_stream_copy, 1 GiB", "us": round(ms * 1e3, 1), "GBps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def timed_launches(torch, fn, n=20):
+    """Median ms of n launches of fn, each bracketed by HIP events on the current stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a_, b_ in evs:
+        a_.record(stream)
+        fn()
+        b_.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+
+
+def cf_section(hd, hi, torch):
+    """The continued-fraction overlap operator (Sec. 3) at 24^4 with 8 pole slices (Ls = 9) and
+    with 15 (Ls = 16): the seeded links, Gaussian field, beta_i spaced evenly in [0.5, 2], R = 0.3.
+    Algorithmic bytes as for H: the field read and written once, the links once."""
+    dev = torch.device("cuda:0")
+    L = (24, 24, 24, 24)
+    Uh = hd.pack_gauge(hi.gauge_field(L, seed=hi.LINK_SEED))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(41)
+    res = {"workload": "24x24x24x24, M5=1.8, beta_i in [0.5, 2], R=0.3 (synthetic)"}
+    for m in (8, 15):
+        Ls = m + 1
+        lat = hd.Lattice(L, Ls, M5=1.8)
+        beta = list(np.linspace(0.5, 2.0, m))
+        for name, dt, cb in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+            U = torch.from_numpy(Uh).to(dev).to(dt)
+            x = torch.randn((12, lat.V4, Ls), dtype=dt, device=dev, generator=gen)
+            o = torch.empty_like(x)
+            ms = timed_launches(torch, lambda: hd.apply_cf(lat, U, x, beta, 0.3, out=o))
+            nbytes = fine_bytes(lat.V4, Ls, cb)
+            res[f"Ls{Ls}_{name}"] = {"us": round(ms * 1e3, 1), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                     "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                     "bytes_per_launch": nbytes}
+            del U, x, o
+    torch.cuda.empty_cache()
+    return res
+
+
+def coarse_multi_section(hd, torch):
+    """Multi-RHS coarse apply (16^4 x 16 fine, coarse 4^4 from 4^4 blocks, Nb = 64, BF16 A with
+    Gaussian entries): at 12 right-hand sides the autotuned matrix-core kernel against one
+    single-RHS launch per right-hand side and against the complex64 VALU multi-RHS kernel on a C64
+    copy of A (the precision the 12-RHS configuration names); at 48 and 96 right-hand sides the
+    matrix-core kernel's rate."""
+    dev = torch.device("cuda:0")
+    latc = hd.Lattice((16, 16, 16, 16), 16, block=(4, 4, 4, 4), nvec=32)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(21)
+    raw = torch.randn(hd.coarse_bytes(latc, hd.C128) // 8, dtype=torch.float64, device=dev, generator=gen)
+    Ab = hd.convert_coarse(latc, raw, hd.BF16C)
+    A64 = hd.convert_coarse(latc, raw, hd.C64)
+    del raw
+    a_bytes = hd.coarse_bytes(latc, hd.BF16C)
+    res = {"workload": "16x16x16x16x16, coarse 4^4, Nb=64, bf16 A (synthetic)"}
+    for nrhs in (12, 48, 96):
+        v = torch.randn((nrhs, latc.nc, latc.nb), dtype=torch.complex64, device=dev, generator=gen)
+        out = torch.empty_like(v)
+        best, ms = hd.tune_coarse_batched(latc, Ab, v, out)
+        t_b = timed_launches(torch, lambda: hd.apply_coarse_batched(latc, Ab, v, out))
+        flops = 8.0 * latc.nb * latc.nb * 9 * latc.nc * nrhs
+        r = {"batched_variant": best, "variant_ms": [round(x, 4) for x in ms], "batched_us": round(t_b * 1e3, 1),
+             "A_GBps": round(a_bytes / (t_b * 1e-3) / 1e9, 1),
+             "mfma_TFLOPs": round(flops / (t_b * 1e-3) / 1e12, 2),
+             "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5)}
+        if nrhs == 12:
+            t_1 = timed_launches(torch, lambda: [hd.apply_coarse(latc, Ab, hd.BF16C, v[q], out[q])
+                                                 for q in range(nrhs)])
+            t_c64 = timed_launches(torch, lambda: hd.apply_coarse(latc, A64, hd.C64, v, out))
+            r.update({"single_rhs_loop_us": round(t_1 * 1e3, 1), "speedup_vs_loop": round(t_1 / t_b, 2),
+                      "c64_valu_multi_rhs_us": round(t_c64 * 1e3, 1),
+                      "c64_valu_TFLOPs": round(flops / (t_c64 * 1e-3) / 1e12, 2)})
+        res[f"nrhs{nrhs}"] = r
+        del v, out
+    del Ab, A64
+    torch.cuda.empty_cache()
+    return res
 
 
 def force_section(hd, hi, torch):
@@ -184,20 +390,26 @@ def main():
         sys.exit(2)
     import torch
 
-    if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print("copied 5 x 1 GiB", flush=True)
-        return
-
     import hdcr_inputs as hi
     import paper_1611_06944_amd as hd
 
+    if args.copy_calibration:
+        # the project's copy kernel on 1 GiB, five times: the reference of the traffic counters
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            hd.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        print("copied 5 x 1 GiB with hdcr_stream_copy", flush=True)
+        return
     if args.force_only:
         print(json.dumps({"fermion_force": force_section(hd, hi, torch)}), flush=True)
+        return
+    if args.coarse_multi_only:
+        print(json.dumps({"coarse_multi_rhs": coarse_multi_section(hd, torch)}), flush=True)
+        return
+    if args.cf_only:
+        print(json.dumps({"cf_overlap": cf_section(hd, hi, torch)}), flush=True)
         return
 
     L, Ls = tuple(args.L), args.Ls
@@ -285,42 +497,6 @@ def main():
         res["ev64"] = fine_sweep("c128", args.applies)
         res["ev16"] = fine_sweep("f16", args.applies)
         return res
-
-    def coarse_batched():
-        """Multi-RHS coarse apply (16^4 x 16 fine, coarse 4^4 from 4^4 blocks, Nb = 64, 12 right-hand
-        sides, BF16 A): autotuned matrix-core kernel vs one single-RHS launch per right-hand side."""
-        latc = hd.Lattice((16, 16, 16, 16), 16, block=(4, 4, 4, 4), nvec=32)
-        nrhs = 12
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(21)
-        raw = torch.randn(hd.coarse_bytes(latc, hd.C128) // 8, dtype=torch.float64, device=dev, generator=gen)
-        Ab = hd.convert_coarse(latc, raw, hd.BF16C)
-        del raw
-        v = torch.randn((nrhs, latc.nc, latc.nb), dtype=torch.complex64, device=dev, generator=gen)
-        out = torch.empty_like(v)
-        best, ms = hd.tune_coarse_batched(latc, Ab, v, out)
-
-        def timed(fn, n=20):
-            for _ in range(3):
-                fn()
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-            for a_, b_ in evs:
-                a_.record(stream)
-                fn()
-                b_.record(stream)
-            torch.cuda.synchronize()
-            return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
-
-        t_b = timed(lambda: hd.apply_coarse_batched(latc, Ab, v, out))
-        t_1 = timed(lambda: [hd.apply_coarse(latc, Ab, hd.BF16C, v[r], out[r]) for r in range(nrhs)])
-        a_bytes = hd.coarse_bytes(latc, hd.BF16C)
-        flops = 8.0 * latc.nb * latc.nb * 9 * latc.nc * nrhs
-        return {"workload": "16x16x16x16x16, coarse 4^4, Nb=64, 12 rhs, bf16 A (synthetic)",
-                "batched_variant": best, "variant_ms": [round(x, 4) for x in ms],
-                "batched_us": round(t_b * 1e3, 1), "single_rhs_loop_us": round(t_1 * 1e3, 1),
-                "speedup": round(t_1 / t_b, 2), "A_GBps": round(a_bytes / (t_b * 1e-3) / 1e9, 1),
-                "mfma_TFLOPs": round(flops / (t_b * 1e-3) / 1e12, 2),
-                "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5)}
 
     defl_space = {}
 
@@ -468,13 +644,24 @@ def main():
         out["hdcr_f16_smoother"] = fsec
         progress("HDCR with the FP16-storage smoother measured")
     if not args.fine_only:
-        out["coarse_multi_rhs"] = coarse_batched()
+        del basis, A, work_hdcr, work_cr
+        defl_space.clear()
+        torch.cuda.empty_cache()
+        out["coarse_multi_rhs"] = coarse_multi_section(hd, torch)
         progress("multi-RHS coarse apply measured")
+        out["cf_overlap"] = cf_section(hd, hi, torch)
+        progress("continued-fraction operator measured")
         out["fermion_force"] = force_section(hd, hi, torch)
         progress("fermion force measured")
+    out["copy_ceiling"] = copy_ceiling(hd, torch)
+    out["roofline"]["copy_ceiling_GBps"] = out["copy_ceiling"]["GBps"]
+    out["roofline"]["frac_of_copy_ceiling"] = round(gbs32 / out["copy_ceiling"]["GBps"], 4)
     if not args.no_cpu_baseline:
         progress("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(U_aos, b_aos, L, Ls, args.cpu_sample_applies)
+        counts = None
+        if not args.fine_only:
+            counts = {"cr_iters": c["outer_iters"], "hdcr": h}
+        out["cpu_baseline"] = cpu_baseline(U_aos, b_aos, L, Ls, args.cpu_sample_applies, counts)
     print(json.dumps(out), flush=True)
 
 

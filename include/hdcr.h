@@ -259,6 +259,13 @@ HDCR_API int hdcr_fermion_force(const hdcr_fine_desc* desc, hdcr_dtype dtype, co
 HDCR_API int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, double* out, void* work,
                  size_t work_bytes, hipStream_t stream);
 
+/* dst = src for `bytes` bytes (a multiple of 16; 16-byte aligned, not
+ * overlapping) with a plain streaming kernel: not a step of the method but the
+ * device's measured copy rate, the practical ceiling beside the datasheet HBM
+ * bandwidth, and the reference the memory-traffic counters are scaled by.
+ * Stream-ordered. */
+HDCR_API int hdcr_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
 /* Scratch bytes needed by the calls below: which = HDCR_WS_SOLVE (hdcr_solve
  * with the given params), HDCR_WS_BUILD (hdcr_build_coarse), HDCR_WS_SUBSPACE
  * (hdcr_make_subspace / hdcr_power_max), HDCR_WS_SMOOTH (hdcr_smooth),

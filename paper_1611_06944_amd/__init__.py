@@ -25,7 +25,7 @@ from ._abi import (BF16C, C64, C128, F16C, HDCRError, PRECOND_NONE, PRECOND_TWO_
 __all__ = ["Lattice", "apply_fine", "apply_cf", "fermion_force", "vec_dot", "solve", "pack_fermion", "unpack_fermion", "pack_gauge",
            "build_coarse", "convert_coarse", "export_coarse", "export_basis", "restrict", "prolong", "apply_coarse",
            "apply_coarse_batched", "tune_coarse_batched", "smooth", "vcycle", "make_subspace", "power_max", "load",
-           "HDCRError", "Deflation", "build_deflation", "coarse_solve", "coarse_solve_static", "make_subspace_degrees"]
+           "HDCRError", "stream_copy", "Deflation", "build_deflation", "coarse_solve", "coarse_solve_static", "make_subspace_degrees"]
 
 load = _abi.load
 
@@ -252,6 +252,15 @@ def vec_dot(x, y, stream=None, work=None) -> complex:
     _abi.check(lib.hdcr_vec_dot(_dtype_code(x), x.numel(), _ptr(x), _ptr(y), out, _ptr(work), work.numel(),
                                 _stream(stream)), "hdcr_vec_dot")
     return complex(out[0], out[1])
+
+
+def stream_copy(src, dst, stream=None):
+    """dst = src with the library's plain streaming copy kernel (bandwidth calibration)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _abi.check(load().hdcr_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "hdcr_stream_copy")
+    return dst
 
 
 def default_params(**kw) -> SolveParams:

@@ -88,6 +88,7 @@ PROTOTYPES = {
     "hdcr_apply_cf": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _dbl_p, ctypes.c_double, _vp, _vp, _vp, _vp]),
     "hdcr_fermion_force": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "hdcr_vec_dot": (ctypes.c_int, [_i32, _i64, _vp, _vp, _dbl_p, _vp, _sz, _vp]),
+    "hdcr_stream_copy": (ctypes.c_int, [_vp, _vp, _sz, _vp]),
     "hdcr_workspace_bytes": (_sz, [ctypes.c_int, ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams)]),
     "hdcr_solve": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), ctypes.POINTER(SolveParams), _vp, _vp, _vp,
                                   ctypes.POINTER(CoarseDeflation), _vp, _vp, ctypes.POINTER(SolveStats), _dbl_p, _i32,

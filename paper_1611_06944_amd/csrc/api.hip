@@ -245,6 +245,17 @@ int hdcr_vec_dot(hdcr_dtype dtype, int64_t n, const void* x, const void* y, doub
     return HDCR_OK;
 }
 
+int hdcr_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+    int e;
+    if (bytes % 16) return fail(HDCR_EINVAL, "hdcr_stream_copy: bytes must be a multiple of 16");
+    if (bytes == 0) return HDCR_OK;
+    if ((e = check_ptr(src, 16, "src")) || (e = check_ptr(dst, 16, "dst"))) return e;
+    if (overlap(src, bytes, dst, bytes)) return fail(HDCR_EINVAL, "hdcr_stream_copy: src and dst overlap");
+    launch_stream_copy(src, dst, bytes, stream);
+    HDCR_HIP_CHECK(hipGetLastError());
+    return HDCR_OK;
+}
+
 size_t hdcr_workspace_bytes(int which, const hdcr_coarse_desc* desc, const hdcr_solve_params* params) {
     if (!desc || check_fine_desc(&desc->fine)) return 0;
     const FineGeom g = make_geom(&desc->fine);

@@ -68,6 +68,35 @@ void launch_dot(int64_t n, const C2<T>* x, const C2<T>* y, double2* partials, do
     launch_finalize(partials, REDUCE_BLOCKS, result, s);
 }
 
+namespace {
+// Plain streaming copy: each workgroup moves one contiguous 64 KiB chunk, every
+// work-item issuing its sixteen 16-byte loads before its first store.
+constexpr int COPY_UNROLL = 16;
+__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                          size_t n) {
+    const size_t base = (size_t)blockIdx.x * (256 * COPY_UNROLL) + threadIdx.x;
+    uint4 v[COPY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i < n) dst[i] = v[u];
+    }
+}
+}  // namespace
+
+void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (n == 0) return;
+    const size_t per = (size_t)256 * COPY_UNROLL;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, s,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+}
+
 template void launch_dot<double>(int64_t, const double2*, const double2*, double2*, double2*, hipStream_t);
 template void launch_dot<float>(int64_t, const float2*, const float2*, double2*, double2*, hipStream_t);
 

@@ -294,6 +294,8 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ]) {
 
 template <typename T>
 void launch_dot(int64_t n, const C2<T>* x, const C2<T>* y, double2* partials, double2* result, hipStream_t s);
+// dst = src, bytes a multiple of 16 (the bandwidth-calibration copy)
+void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 void launch_finalize(const double2* partials, int np, double2* result, hipStream_t s);
 
 }  // namespace hdcr

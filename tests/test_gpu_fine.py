@@ -198,3 +198,20 @@ def test_kernel_variants_agree(L, Ls):
         scale = np.abs(outs[-1]).max()
         for o in outs[:-1]:
             assert np.abs(o - outs[-1]).max() <= tol * scale, dt
+
+
+def test_stream_copy_exact():
+    """The bandwidth-calibration copy moves every byte: sizes with a ragged last chunk, and a
+    size that is not a multiple of 16 is refused."""
+    torch = torch_dev()
+    from paper_1611_06944_amd import HDCRError, stream_copy
+    log("stream copy")
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(3)
+    for nbytes in (16, 4096 * 16 + 48, (1 << 22) + 16 * 257):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda:0", generator=g)
+        dst = torch.zeros_like(src)
+        stream_copy(src, dst)
+        assert torch.equal(src, dst), nbytes
+    with pytest.raises(HDCRError):
+        stream_copy(src[:40], dst[:40])
