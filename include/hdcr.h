@@ -232,7 +232,7 @@ HDCR_API int hdcr_apply_fine(const hdcr_fine_desc* desc, hdcr_dtype dtype, const
 HDCR_API int hdcr_apply_cf(const hdcr_fine_desc* desc, hdcr_dtype dtype, const double* beta, double R, const void* U,
                            const void* psi, void* out, hipStream_t stream);
 
-/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC
+/* Gauge-link gradient and su(3) force of L = Re <chi, H psi> (the HMC
  * fermion force of the setting named in the abstract, Sec. 1 and Sec. 5; H as
  * in Sec. 3 and the conventions above):
  *   W[site4][mu][a][b] = dL/dRe U_mu(x)[a][b] + i dL/dIm U_mu(x)[a][b]

@@ -70,31 +70,36 @@ void launch_dot(int64_t n, const C2<T>* x, const C2<T>* y, double2* partials, do
 
 namespace {
 // Plain streaming copy: each workgroup moves one contiguous 64 KiB chunk, every
-// work-item issuing its sixteen 16-byte loads before its first store.
+// work-item issuing its sixteen 16-byte loads before its first store.  It uses
+// the memory instructions of the library's field kernels (raw buffer loads and
+// non-temporal buffer stores through a descriptor of the workgroup's chunk), so
+// that the memory-traffic counters, whose request-size accounting differs
+// between instruction types, read it as they read those kernels.  Loads past the
+// descriptor's range return zero and stores past it are dropped, so the last,
+// partial chunk needs no per-load test (a guarded load in an unrolled loop ends
+// in a wait for it at the branch's join, which would serialise the loads).
 constexpr int COPY_UNROLL = 16;
-__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                                                          size_t n) {
-    const size_t base = (size_t)blockIdx.x * (256 * COPY_UNROLL) + threadIdx.x;
-    uint4 v[COPY_UNROLL];
+constexpr uint32_t COPY_CHUNK = 256u * COPY_UNROLL * 16u;  // bytes per workgroup
+__global__ void __launch_bounds__(256) stream_copy_kernel(const unsigned char* __restrict__ src,
+                                                          unsigned char* __restrict__ dst, size_t bytes) {
+    const size_t off = (size_t)blockIdx.x * COPY_CHUNK;
+    const size_t left = bytes - off;
+    const uint32_t range = left < COPY_CHUNK ? (uint32_t)left : COPY_CHUNK;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + off, range), rd = make_rsrc(dst + off, range);
+    typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+    u32x4_t v[COPY_UNROLL];
 #pragma unroll
-    for (int u = 0; u < COPY_UNROLL; ++u) {
-        const size_t i = base + (size_t)u * 256;
-        if (i < n) v[u] = src[i];
-    }
+    for (int u = 0; u < COPY_UNROLL; ++u)
+        v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (threadIdx.x + u * 256u) * 16u, 0, 0);
 #pragma unroll
-    for (int u = 0; u < COPY_UNROLL; ++u) {
-        const size_t i = base + (size_t)u * 256;
-        if (i < n) dst[i] = v[u];
-    }
+    for (int u = 0; u < COPY_UNROLL; ++u) store_b128<CPOL_NT>(v[u], rd, (threadIdx.x + u * 256u) * 16u, 0u);
 }
 }  // namespace
 
 void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
-    const size_t n = bytes / 16;
-    if (n == 0) return;
-    const size_t per = (size_t)256 * COPY_UNROLL;
-    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, s,
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+    if (bytes == 0) return;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((bytes + COPY_CHUNK - 1) / COPY_CHUNK)), dim3(256), 0, s,
+                       static_cast<const unsigned char*>(src), static_cast<unsigned char*>(dst), bytes);
 }
 
 template void launch_dot<double>(int64_t, const double2*, const double2*, double2*, double2*, hipStream_t);
