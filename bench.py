@@ -290,10 +290,11 @@ def cf_section(hd, hi, torch):
 
 def coarse_multi_section(hd, torch):
     """Multi-RHS coarse apply (16^4 x 16 fine, coarse 4^4 from 4^4 blocks, Nb = 64, BF16 A with
-    Gaussian entries): at 12 right-hand sides the autotuned matrix-core kernel against one
-    single-RHS launch per right-hand side and against the complex64 VALU multi-RHS kernel on a C64
-    copy of A (the precision the 12-RHS configuration names); at 48 and 96 right-hand sides the
-    matrix-core kernel's rate."""
+    Gaussian entries) on the matrix cores, at 12, 48, 96 and 192 right-hand sides: the autotuned
+    tile shape with the vectors rounded to bf16, and the same apply with each complex64 entry
+    carried as three bf16 terms (exact products, FP32 sums: the complex64 apply of the stored A).
+    At 12 right-hand sides (the multi-RHS configuration) also one single-RHS launch per
+    right-hand side and the complex64 vector-unit multi-RHS kernel on a C64 copy of A."""
     dev = torch.device("cuda:0")
     latc = hd.Lattice((16, 16, 16, 16), 16, block=(4, 4, 4, 4), nvec=32)
     gen = torch.Generator(device=dev)
@@ -304,16 +305,19 @@ def coarse_multi_section(hd, torch):
     del raw
     a_bytes = hd.coarse_bytes(latc, hd.BF16C)
     res = {"workload": "16x16x16x16x16, coarse 4^4, Nb=64, bf16 A (synthetic)"}
-    for nrhs in (12, 48, 96):
+    for nrhs in (12, 48, 96, 192):
         v = torch.randn((nrhs, latc.nc, latc.nb), dtype=torch.complex64, device=dev, generator=gen)
         out = torch.empty_like(v)
         best, ms = hd.tune_coarse_batched(latc, Ab, v, out)
         t_b = timed_launches(torch, lambda: hd.apply_coarse_batched(latc, Ab, v, out))
+        t_3 = timed_launches(torch, lambda: hd.apply_coarse_batched(latc, Ab, v, out, terms=3))
         flops = 8.0 * latc.nb * latc.nb * 9 * latc.nc * nrhs
         r = {"batched_variant": best, "variant_ms": [round(x, 4) for x in ms], "batched_us": round(t_b * 1e3, 1),
              "A_GBps": round(a_bytes / (t_b * 1e-3) / 1e9, 1),
              "mfma_TFLOPs": round(flops / (t_b * 1e-3) / 1e12, 2),
-             "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5)}
+             "mfma_frac_bf16_peak": round(flops / (t_b * 1e-3) / 2.5e15, 5),
+             "c64_exact_3terms_us": round(t_3 * 1e3, 1),
+             "c64_exact_3terms_TFLOPs": round(flops / (t_3 * 1e-3) / 1e12, 2)}
         if nrhs == 12:
             t_1 = timed_launches(torch, lambda: [hd.apply_coarse(latc, Ab, hd.BF16C, v[q], out[q])
                                                  for q in range(nrhs)])
@@ -521,7 +525,8 @@ def main():
                 _, st, _ = hd.solve(lat, U64, b64, x, params=prm, basis=basis, A=A, work=work, defl=d)
                 runs.append(time.perf_counter() - t)
             res[name] = {"solve_s": round(float(np.mean(runs)), 4), "outer_iters": st["outer_iters"],
-                         "coarse_iters": st["coarse_iters"], "fine_s": round(st["seconds_fine"], 4),
+                         "coarse_iters": st["coarse_iters"], "coarse_breakdowns": st["coarse_breakdowns"],
+                         "fine_s": round(st["seconds_fine"], 4),
                          "coarse_s": round(st["seconds_coarse"], 4), "true_rel_residual": st["true_rel_residual"],
                          "status": st["status"]}
         return res
@@ -556,7 +561,8 @@ def main():
                                                                   round(abs(d.theta_host[-1]), 5)],
                 "ritz_residual_max": float(res.max()),
                 "hdcr_defl_solve_s": round(w, 4), "outer_iters": st["outer_iters"],
-                "coarse_iters": st["coarse_iters"], "coarse_s": round(st["seconds_coarse"], 4),
+                "coarse_iters": st["coarse_iters"], "coarse_breakdowns": st["coarse_breakdowns"],
+                "coarse_s": round(st["seconds_coarse"], 4),
                 "fine_s": round(st["seconds_fine"], 4), "outer_s": round(st["seconds_outer"], 4),
                 "true_rel_residual": st["true_rel_residual"], "status": st["status"]}
 
@@ -623,6 +629,7 @@ def main():
             "speedup": round(cw / hw, 3),
             "hdcr_solve_s": round(hw, 4), "cr_solve_s": round(cw, 4),
             "hdcr": {"outer_iters": h["outer_iters"], "coarse_iters": h["coarse_iters"],
+                     "coarse_breakdowns": h["coarse_breakdowns"],
                      "fine_applies_f32": h["fine_applies_inner"], "fine_applies_f64": h["fine_applies_f64"],
                      "true_rel_residual": h["true_rel_residual"], "status": h["status"],
                      "fine_s": round(h["seconds_fine"], 4), "coarse_s": round(h["seconds_coarse"], 4),

@@ -309,28 +309,36 @@ HDCR_API int hdcr_convert_coarse(const hdcr_coarse_desc* desc, const void* A128,
 
 /* Batched coarse apply on the matrix cores (Sec. 4, the little Dirac operator
  * applied to many right-hand sides at once): out[r] = A v[r], r < nrhs, with A
- * in BF16C storage and the vectors rounded to bf16 (round to nearest even) for
- * a BF16 x BF16 contraction with FP32 accumulation.  v, out: C64
- * [nrhs][site_c][k], not overlapping.  Needs Nb in {16, 32, 64, 128}.
- * variant 0: the tile shape hdcr_tune_coarse_batched chose for this shape
- * (if it has not been tuned: variant 8 for Nb = 64, else 2, or 1 for Nb = 16); 1..HDCR_MFMA_VARIANTS:
- * an explicit tile shape (2, 4, 8 wavefronts per coarse site, blocks read
- * directly or staged in LDS; 7: 8 wavefronts with all 9 blocks prefetched, Nb =
- * 64 only; 8: as 7 with the blocks held in registers across passes of 16
- * right-hand sides and every load of a pass issued before its first use, Nb = 64
- * only); a variant with more wavefronts than Nb / 8 is rejected.  All variants perform the same operations per output element, so
- * they give identical results.  Stream-ordered. */
-#define HDCR_MFMA_VARIANTS 8
+ * in BF16C storage and a BF16 x BF16 contraction with FP32 accumulation.
+ * rhs_terms says how each FP32 component of v enters it: 1, rounded to bf16
+ * (round to nearest even; relative error up to 2^-9 per entry); 2 or 3, as the
+ * sum of that many bf16 terms, each rounding what the earlier ones leave, so
+ * that two terms carry it to within 2^-16 and three exactly (every product is
+ * then exact and only the FP32 sums round: the complex64 apply of the stored A).
+ * v, out: C64 [nrhs][site_c][k], not overlapping.  Needs Nb in {16, 32, 64, 128}.
+ * variant 0: the tile shape hdcr_tune_coarse_batched chose for this shape and
+ * rhs_terms (if it has not been tuned: 9 for Nb = 64, else 2, or 1 for Nb =
+ * 16); 1..HDCR_MFMA_VARIANTS: an explicit tile shape (2,
+ * 4, 8 wavefronts per coarse site, blocks read directly or staged in LDS; 7: 8
+ * wavefronts with all 9 blocks prefetched; 8: as 7 with the blocks held in
+ * registers across passes of 16 right-hand sides and every load of a pass
+ * issued before its first use; 9: the direction loop outside the passes, each
+ * block staged once per chunk of up to 64 right-hand sides).  Variants 7 to 9
+ * need Nb = 64, rhs_terms 2 and 3 need variant 9, and a variant with more
+ * wavefronts than Nb / 8 is rejected (HDCR_EINVAL).  For one rhs_terms, all
+ * variants perform the same operations per output element in the same order,
+ * so they give identical results.  Stream-ordered. */
+#define HDCR_MFMA_VARIANTS 9
 HDCR_API int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
-                                       int32_t nrhs, int32_t variant, hipStream_t stream);
-/* Autotuner of the batched apply of A (Sec. 4): times every tile shape on the caller's
- * buffers (out is overwritten), records the fastest for (Nc, Nb, nrhs, device)
- * in a process-wide table used by variant 0, and reports the winner (best) and
- * the median time of each variant in ms[HDCR_MFMA_VARIANTS] (-1 for a variant
- * that does not apply; either pointer may be null).  Returns after the timing
- * runs have completed. */
+                                       int32_t nrhs, int32_t variant, int32_t rhs_terms, hipStream_t stream);
+/* Autotuner of the batched apply of A (Sec. 4): times every tile shape that
+ * takes rhs_terms on the caller's buffers (out is overwritten), records the
+ * fastest for (Nc, Nb, nrhs, rhs_terms, device) in a process-wide table used by
+ * variant 0, and reports the winner (best) and the median time of each variant
+ * in ms[HDCR_MFMA_VARIANTS] (-1 for a variant that does not apply; either
+ * pointer may be null).  Returns after the timing runs have completed. */
 HDCR_API int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out,
-                                      int32_t nrhs, int32_t* best, double* ms, hipStream_t stream);
+                                      int32_t nrhs, int32_t rhs_terms, int32_t* best, double* ms, hipStream_t stream);
 
 /* Read back the opaque buffers: the little Dirac operator of Sec. 4 (any
  * storage) as logical A[a][d][j][k] complex double; the block basis phi^b_k of

@@ -429,21 +429,24 @@ def apply_coarse(lat: Lattice, A, A_dtype: int, v, out=None, stream=None):
     return out
 
 
-def apply_coarse_batched(lat: Lattice, A, v, out=None, variant: int = 0, stream=None):
-    """out[r] = A v[r] on the matrix cores: A in BF16C storage, v complex64 [nrhs, Nc, Nb]
-    rounded to bf16, FP32 accumulation.  variant 0: the autotuned tile shape."""
+def apply_coarse_batched(lat: Lattice, A, v, out=None, variant: int = 0, terms: int = 1, stream=None):
+    """out[r] = A v[r] on the matrix cores: A in BF16C storage, v complex64 [nrhs, Nc, Nb],
+    FP32 accumulation.  terms: bf16 terms per FP32 component of v (1: v rounded to bf16;
+    3: v exact, so the result is the complex64 apply of the stored A).  variant 0: the
+    autotuned tile shape."""
     torch = _torch()
     if out is None:
         out = torch.empty_like(v)
     nrhs = 1 if v.dim() == 2 else v.shape[0]
     cd = lat.coarse_desc()
     _abi.check(load().hdcr_apply_coarse_batched(ctypes.byref(cd), _ptr(A), _ptr(v), _ptr(out), nrhs, int(variant),
-                                                _stream(stream)), "hdcr_apply_coarse_batched")
+                                                int(terms), _stream(stream)), "hdcr_apply_coarse_batched")
     return out
 
 
-def tune_coarse_batched(lat: Lattice, A, v, out=None, stream=None):
-    """Times every tile shape of the batched apply; returns (best variant, [median ms per variant])."""
+def tune_coarse_batched(lat: Lattice, A, v, out=None, terms: int = 1, stream=None):
+    """Times every tile shape of the batched apply that takes ``terms``; returns
+    (best variant, [median ms per variant, -1 where it does not apply])."""
     torch = _torch()
     if out is None:
         out = torch.empty_like(v)
@@ -451,7 +454,7 @@ def tune_coarse_batched(lat: Lattice, A, v, out=None, stream=None):
     cd = lat.coarse_desc()
     best = ctypes.c_int32(0)
     ms = (ctypes.c_double * _abi.MFMA_VARIANTS)()
-    _abi.check(load().hdcr_tune_coarse_batched(ctypes.byref(cd), _ptr(A), _ptr(v), _ptr(out), nrhs,
+    _abi.check(load().hdcr_tune_coarse_batched(ctypes.byref(cd), _ptr(A), _ptr(v), _ptr(out), nrhs, int(terms),
                                                ctypes.byref(best), ms, _stream(stream)), "hdcr_tune_coarse_batched")
     return int(best.value), [float(x) for x in ms]
 

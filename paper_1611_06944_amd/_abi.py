@@ -17,7 +17,7 @@ HDCR_ENAN = 3
 HDCR_ERANK = 4
 
 C128, C64, BF16C, F16C = 0, 1, 2, 3
-MFMA_VARIANTS = 8  # tile shapes of the batched coarse apply
+MFMA_VARIANTS = 9  # tile shapes of the batched coarse apply
 PRECOND_NONE, PRECOND_TWO_LEVEL = 0, 1
 WS_SOLVE, WS_BUILD, WS_SUBSPACE, WS_SMOOTH, WS_VCYCLE, WS_COARSE = 0, 1, 2, 3, 4, 5
 DEFL_MAX = 64
@@ -109,8 +109,8 @@ PROTOTYPES = {
     "hdcr_restrict": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
     "hdcr_prolong": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _vp]),
     "hdcr_apply_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, _vp, _vp, _i32, _vp]),
-    "hdcr_apply_coarse_batched": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _i32, _i32, _vp]),
-    "hdcr_tune_coarse_batched": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _i32,
+    "hdcr_apply_coarse_batched": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _i32, _i32, _i32, _vp]),
+    "hdcr_tune_coarse_batched": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _i32, _i32,
                                                  ctypes.POINTER(ctypes.c_int32), _dbl_p, _vp]),
     "hdcr_smooth": (ctypes.c_int, [ctypes.POINTER(FineDesc), _i32, _vp, _i32, ctypes.c_double, ctypes.c_double, _vp,
                                    _vp, _vp, _sz, _vp]),

@@ -74,20 +74,21 @@ static size_t csize(hdcr_dtype dt) { return dt == HDCR_C128 ? 16 : (dt == HDCR_C
 }  // namespace hdcr
 
 namespace hdcr {
-// tile shape chosen by the autotuner per (Nc, Nb, nrhs, device)
+// tile shape chosen by the autotuner per (Nc, Nb, nrhs, terms, device)
 static std::mutex tune_mutex;
-static std::map<std::tuple<int, int, int, int>, int> tune_table;
+static std::map<std::tuple<int, int, int, int, int>, int> tune_table;
 
-static int tuned_variant(const CoarseGeom& c, int nrhs) {
+static int tuned_variant(const CoarseGeom& c, int nrhs, int terms) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     std::lock_guard<std::mutex> lk(tune_mutex);
-    auto it = tune_table.find(std::make_tuple(c.Nc, c.Nb, nrhs, dev));
+    auto it = tune_table.find(std::make_tuple(c.Nc, c.Nb, nrhs, terms, dev));
     if (it != tune_table.end()) return it->second;
-    // untuned: the batched-load variant for Nb = 64 (fastest measured at 12 to 96
-    // right-hand sides), else four wavefronts per site where Nb allows them
-    if (coarse_mfma_eligible(c, 8)) return 8;
-    return coarse_mfma_eligible(c, 2) ? 2 : 1;
+    // untuned: for Nb = 64 the direction-outside variant (fastest measured at 12
+    // to 192 right-hand sides; the only one for split vectors), else four
+    // wavefronts per site where Nb allows them
+    if (terms > 1 || coarse_mfma_eligible(c, 9, 1)) return 9;
+    return coarse_mfma_eligible(c, 2, 1) ? 2 : 1;
 }
 
 static int check_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int nrhs,
@@ -280,26 +281,30 @@ int hdcr_apply_coarse(const hdcr_coarse_desc* desc, hdcr_dtype dtype, const void
 
 
 int hdcr_apply_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int32_t nrhs,
-                              int32_t variant, hipStream_t stream) {
+                              int32_t variant, int32_t rhs_terms, hipStream_t stream) {
     int e = check_batched(desc, A, v, out, nrhs, "hdcr_apply_coarse_batched");
     if (e) return e;
     if (variant < 0 || variant > coarse_mfma_variants())
         return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: variant out of range");
+    if (rhs_terms < 1 || rhs_terms > 3) return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: rhs_terms must be 1, 2 or 3");
     const CoarseGeom c = make_coarse_geom(desc);
-    if (variant == 0) variant = tuned_variant(c, nrhs);
-    if (!coarse_mfma_eligible(c, variant))
-        return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: variant " + std::to_string(variant) +
-                                     " needs no more waves per site than Nb / 8");
-    launch_coarse_mfma(c, variant, static_cast<const uint32_t*>(A), static_cast<const float2*>(v),
+    if (variant == 0) variant = tuned_variant(c, nrhs, rhs_terms);
+    if (!coarse_mfma_eligible(c, variant, rhs_terms))
+        return fail(HDCR_EINVAL, "hdcr_apply_coarse_batched: variant " + std::to_string(variant) + " with " +
+                                     std::to_string(rhs_terms) +
+                                     " term(s) does not apply to this shape (waves per site <= Nb / 8; variants 7 to "
+                                     "9 need Nb = 64; 2 or 3 terms need variant 9)");
+    launch_coarse_mfma(c, variant, rhs_terms, static_cast<const uint32_t*>(A), static_cast<const float2*>(v),
                        static_cast<float2*>(out), nrhs, stream);
     HDCR_HIP_CHECK(hipGetLastError());
     return HDCR_OK;
 }
 
 int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const void* v, void* out, int32_t nrhs,
-                             int32_t* best, double* ms, hipStream_t stream) {
+                             int32_t rhs_terms, int32_t* best, double* ms, hipStream_t stream) {
     int e = check_batched(desc, A, v, out, nrhs, "hdcr_tune_coarse_batched");
     if (e) return e;
+    if (rhs_terms < 1 || rhs_terms > 3) return fail(HDCR_EINVAL, "hdcr_tune_coarse_batched: rhs_terms must be 1, 2 or 3");
     const CoarseGeom c = make_coarse_geom(desc);
     const int nv = coarse_mfma_variants();
     constexpr int REPS = 7;
@@ -308,15 +313,17 @@ int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const 
     int win = 0;
     double win_ms = 0;
     for (int k = 1; k <= nv; ++k) {
-        if (!coarse_mfma_eligible(c, k)) {
+        if (!coarse_mfma_eligible(c, k, rhs_terms)) {
             if (ms) ms[k - 1] = -1.0;
             continue;
         }
         const uint32_t* Au = static_cast<const uint32_t*>(A);
-        launch_coarse_mfma(c, k, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs, stream);  // warm-up
+        launch_coarse_mfma(c, k, rhs_terms, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs,
+                           stream);  // warm-up
         HDCR_HIP_CHECK(hipEventRecord(ev[0], stream));
         for (int i = 0; i < REPS; ++i) {
-            launch_coarse_mfma(c, k, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs, stream);
+            launch_coarse_mfma(c, k, rhs_terms, Au, static_cast<const float2*>(v), static_cast<float2*>(out), nrhs,
+                               stream);
             HDCR_HIP_CHECK(hipEventRecord(ev[i + 1], stream));
         }
         HDCR_HIP_CHECK(hipGetLastError());
@@ -340,7 +347,7 @@ int hdcr_tune_coarse_batched(const hdcr_coarse_desc* desc, const void* A, const 
     HDCR_HIP_CHECK(hipGetDevice(&dev));
     {
         std::lock_guard<std::mutex> lk(tune_mutex);
-        tune_table[std::make_tuple(c.Nc, c.Nb, (int)nrhs, dev)] = win;
+        tune_table[std::make_tuple(c.Nc, c.Nb, (int)nrhs, (int)rhs_terms, dev)] = win;
     }
     if (best) *best = win;
     return HDCR_OK;

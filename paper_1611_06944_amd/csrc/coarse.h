@@ -88,10 +88,11 @@ void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* 
 // batched BF16 contraction on the matrix cores (variant 1..coarse_mfma_variants())
 int coarse_mfma_variants();
 const char* coarse_mfma_variant_name(int k);
-// Nb in {16, 32, 64, 128} and no more waves than 16-row tiles (2 Nb / 16)
-bool coarse_mfma_eligible(const CoarseGeom& c, int variant);
-void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, const float2* v, float2* out, int nrhs,
-                        hipStream_t s);
+// Nb in {16, 32, 64, 128}, no more waves than 16-row tiles (2 Nb / 16); terms:
+// bf16 terms per vector entry, 1 for every variant, 2 or 3 for variant 9 only
+bool coarse_mfma_eligible(const CoarseGeom& c, int variant, int terms);
+void launch_coarse_mfma(const CoarseGeom& c, int variant, int terms, const uint32_t* A, const float2* v, float2* out,
+                        int nrhs, hipStream_t s);
 
 // out[r][a] = sum_d A[a][d] v[r][a+d]  (C128 / C64 storage, column-major blocks)
 template <typename T>

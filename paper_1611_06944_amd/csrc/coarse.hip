@@ -1641,6 +1641,157 @@ __global__ void __launch_bounds__(64 * PF_NW) coarse_mfma_pf_kernel(CoarseGeom c
     }
 }
 
+// bf16 terms of a complex float: t = 1 is the rounding of v, t = 2 and 3 round
+// what the earlier terms leave.  Each remainder is exact in FP32 (it holds the
+// bits of v below the previous term's 8-bit significand), so three terms sum to
+// v exactly and two to within 2^-16 of |v|.
+template <int T>
+__device__ __forceinline__ void split_bf16c(float2 x, uint32_t (&w)[T]) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const __bf16 hr = (__bf16)x.x, hi = (__bf16)x.y;
+        w[t] = (uint32_t)__builtin_bit_cast(unsigned short, hr) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+        x.x -= (float)hr;
+        x.y -= (float)hi;
+    }
+}
+
+// Nb = NB, 2 NB / 16 wavefronts with one row tile each, the blocks of the site
+// held for every right-hand side: the direction loop is outside the loop over
+// passes of 16 right-hand sides, so each block goes through LDS and into the
+// A-operand registers once per chunk of 16 NP right-hand sides (NP <= 4; one
+// FP32 accumulator tile per pass), instead of once per pass; the blocks stay in
+// registers across chunks.  The vectors of direction d + 1 are requested before
+// the products of direction d.  Every load and store is a raw buffer access
+// whose range ends at the chunk's last right-hand side, so the rows of a
+// partial last pass read zero and their results are dropped, with no test in
+// the kernel.  TERMS
+// bf16 terms of each vector entry (split_bf16c) are multiplied in turn: with 1
+// the products and their order per output are those of the other tile shapes
+// (the same bits); with 3 the products are exact and only the FP32 sums round.
+constexpr int RS_NB = 64;
+template <int NB, int TERMS, int NP>
+__global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, const uint32_t* __restrict__ A,
+                                                                const float2* __restrict__ v,
+                                                                float2* __restrict__ out, int nrhs) {
+    constexpr int NT = 8 * NB, VST = NB + 4, RPC = 16 * NP;  // work-items, LDS row stride, rows per chunk
+    constexpr int NA4 = NB * NB / 4 / NT;                     // 16-byte block loads per work-item and block
+    static_assert(NA4 * 4 * NT == NB * NB, "block loads must tile the block");
+    extern __shared__ unsigned char smem_raw[];
+    uint32_t* ab = reinterpret_cast<uint32_t*>(smem_raw);  // [NB][VST] one block
+    uint32_t* vb = ab + NB * VST;                           // [TERMS][RPC][VST] bf16 terms of one direction's vectors
+    const int a = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int kq = lane >> 4, col = lane & 15;
+    const uint32_t rot = (col & 1) ? 16u : 0u;
+    const uint32_t flip = (col & 1) ? 0u : 0x80000000u;
+    const int j = (16 * wave + col) >> 1;  // complex row of this lane's A-operand words
+    int nbr[9];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) nbr[d] = coarse_nbr(c, a, d);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (size_t)a * 9 * NB * NB, 9u * NB * NB * 4u);
+    u32x4 pre[9][NA4];
+#pragma unroll
+    for (int d = 0; d < 9; ++d)
+#pragma unroll
+        for (int u = 0; u < NA4; ++u)
+            pre[d][u] = __builtin_amdgcn_raw_buffer_load_b128(ra, (d * NB * NB + 4 * (threadIdx.x + u * NT)) * 4u, 0, 0);
+    // work-item's vector pair: row 16 p + vr of pass p, complex entries 2 kp, 2 kp + 1
+    const int vr = threadIdx.x / (NB / 2), kp = threadIdx.x % (NB / 2);
+    for (int r0 = 0; r0 < nrhs; r0 += RPC) {
+        const int nr = min(RPC, nrhs - r0);
+        const size_t chunk = (size_t)r0 * c.Nc * NB;
+        const uint32_t bytes = (uint32_t)((size_t)nr * c.Nc * NB * 8);
+        const __amdgpu_buffer_rsrc_t rv = make_rsrc(v + chunk, bytes), ro = make_rsrc(out + chunk, bytes);
+        float4 vx[NP];
+        auto load_dir = [&](int nd) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                vx[p] = __builtin_bit_cast(
+                        float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                    rv, (((uint32_t)(16 * p + vr) * c.Nc + nd) * NB + 2 * kp) * 8u, 0, 0));
+        };
+        f32x4 acc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[p] = f32x4{0, 0, 0, 0};
+        load_dir(nbr[0]);
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            __syncthreads();  // the previous direction's operands have been read
+#pragma unroll
+            for (int u = 0; u < NA4; ++u) {
+                const int e = 4 * (threadIdx.x + u * NT);
+                *reinterpret_cast<u32x4*>(ab + (e / NB) * VST + e % NB) = pre[d][u];
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                uint32_t w0[TERMS], w1[TERMS];
+                split_bf16c<TERMS>(make_float2(vx[p].x, vx[p].y), w0);
+                split_bf16c<TERMS>(make_float2(vx[p].z, vx[p].w), w1);
+#pragma unroll
+                for (int t = 0; t < TERMS; ++t)
+                    *reinterpret_cast<uint2*>(vb + (t * RPC + 16 * p + vr) * VST + 2 * kp) = make_uint2(w0[t], w1[t]);
+            }
+            if (d < 8) load_dir(nbr[d < 8 ? d + 1 : 0]);  // in flight during this direction's products
+            __syncthreads();
+            u32x4 aw[NB / 16];
+#pragma unroll
+            for (int ks = 0; ks < NB / 16; ++ks)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t w = ab[(16 * ks + 4 * kq + q) * VST + j];
+                    aw[ks][q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+                }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int ks = 0; ks < NB / 16; ++ks)
+#pragma unroll
+                    for (int t = 0; t < TERMS; ++t) {
+                        const u32x4 bw =
+                            *reinterpret_cast<const u32x4*>(vb + (t * RPC + 16 * p + col) * VST + 16 * ks + 4 * kq);
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aw[ks]),
+                                                                         __builtin_bit_cast(bf16x8, bw), acc[p], 0, 0,
+                                                                         0);
+                    }
+        }
+        // lane holds complex rows j0, j0 + 1 of right-hand side 16 p + col; rows
+        // past the chunk's last right-hand side fall outside ro and are dropped
+        const int j0 = 8 * wave + 2 * kq;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            store_b128<0>(__builtin_bit_cast(u32x4, acc[p]), ro, (((uint32_t)(16 * p + col) * c.Nc + a) * NB + j0) * 8u,
+                          0u);
+    }
+}
+
+template <int TERMS, int NP>
+void rs_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
+    constexpr int NB = RS_NB;
+    const size_t lds = (size_t)NB * (NB + 4) * 4 + (size_t)TERMS * 16 * NP * (NB + 4) * 4;
+    static bool attr = false;  // per instantiation: raise the dynamic LDS limit once
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(coarse_mfma_rs_kernel<NB, TERMS, NP>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((coarse_mfma_rs_kernel<NB, TERMS, NP>), dim3(c.Nc), dim3(8 * NB), lds, s, c, A, v, out, nrhs);
+}
+
+template <int TERMS>
+void rs_dispatch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
+    // passes per chunk: all of them up to 4 (8 passes need more than the 256
+    // registers of two waves per SIMD), else 3 or 4, whichever leaves fewer
+    // empty passes in the last chunk (4 on a tie)
+    const int passes = (nrhs + 15) / 16;
+    const int np = passes <= 4 ? passes : ((passes + 2) / 3 * 3 - passes < (passes + 3) / 4 * 4 - passes ? 3 : 4);
+    if (np == 1) rs_launch<TERMS, 1>(c, A, v, out, nrhs, s);
+    else if (np == 2) rs_launch<TERMS, 2>(c, A, v, out, nrhs, s);
+    else if (np == 3) rs_launch<TERMS, 3>(c, A, v, out, nrhs, s);
+    else rs_launch<TERMS, 4>(c, A, v, out, nrhs, s);
+}
+
 template <int NW, bool ALDS>
 void mfma_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
     const size_t lds = (size_t)9 * MR * (c.Nb + 4) * 4 + (ALDS ? (size_t)c.Nb * c.Nb * 4 : 0);
@@ -1663,24 +1814,28 @@ void mfma_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2
 }  // namespace
 
 // tile-shape variants of the batched apply: waves per coarse site x block staging
-int coarse_mfma_variants() { return 8; }
+int coarse_mfma_variants() { return 9; }
 const char* coarse_mfma_variant_name(int k) {
-    static const char* names[8] = {"2 waves/site, A direct",  "4 waves/site, A direct",  "8 waves/site, A direct",
+    static const char* names[9] = {"2 waves/site, A direct",  "4 waves/site, A direct",  "8 waves/site, A direct",
                                    "2 waves/site, A via LDS", "4 waves/site, A via LDS", "8 waves/site, A via LDS",
                                    "8 waves/site, A prefetched (Nb 64)",
-                                   "8 waves/site, A held across passes, loads batched (Nb 64)"};
-    return (k >= 1 && k <= 8) ? names[k - 1] : "";
+                                   "8 waves/site, A held across passes, loads batched (Nb 64)",
+                                   "8 waves/site, direction outside the passes, up to 64 rhs per chunk (Nb 64)"};
+    return (k >= 1 && k <= 9) ? names[k - 1] : "";
 }
 // waves per coarse site of a variant
 static int mfma_waves(int variant) { return variant == 1 || variant == 4 ? 2 : variant == 2 || variant == 5 ? 4 : 8; }
-bool coarse_mfma_eligible(const CoarseGeom& c, int variant) {
+bool coarse_mfma_eligible(const CoarseGeom& c, int variant, int terms) {
     const int nb = c.Nb;
     if (nb != 16 && nb != 32 && nb != 64 && nb != 128) return false;
-    if ((variant == 7 || variant == 8) && nb != 64) return false;  // register prefetch sized for Nb = 64 blocks
+    if (terms < 1 || terms > 3 || (terms > 1 && variant != 9)) return false;  // split vectors: variant 9 only
+    if (variant >= 7 && nb != RS_NB) return false;  // register prefetch sized for Nb = 64 blocks
+    // variant 9 addresses a chunk of up to 64 right-hand sides with 32-bit byte offsets
+    if (variant == 9 && (size_t)64 * c.Nc * nb * 8 > 0xffffffffu) return false;
     return mfma_waves(variant) <= 2 * nb / 16;
 }
-void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, const float2* v, float2* out, int nrhs,
-                        hipStream_t s) {
+void launch_coarse_mfma(const CoarseGeom& c, int variant, int terms, const uint32_t* A, const float2* v, float2* out,
+                        int nrhs, hipStream_t s) {
     switch (variant) {
         case 1: mfma_launch<2, false>(c, A, v, out, nrhs, s); break;
         case 2: mfma_launch<4, false>(c, A, v, out, nrhs, s); break;
@@ -1693,6 +1848,11 @@ void launch_coarse_mfma(const CoarseGeom& c, int variant, const uint32_t* A, con
             hipLaunchKernelGGL(coarse_mfma_pf_kernel, dim3(c.Nc), dim3(64 * PF_NW), lds, s, c, A, v, out, nrhs);
             break;
         }
+        case 9:
+            if (terms == 1) rs_dispatch<1>(c, A, v, out, nrhs, s);
+            else if (terms == 2) rs_dispatch<2>(c, A, v, out, nrhs, s);
+            else rs_dispatch<3>(c, A, v, out, nrhs, s);
+            break;
         default: {
             // 8 waves, Nb = 64: 16 KB blocks, 2 loads of 16 B per work-item and block
             const size_t lds = (size_t)9 * MR * (c.Nb + 4) * 4 + (size_t)c.Nb * c.Nb * 4;

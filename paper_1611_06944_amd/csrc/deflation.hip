@@ -174,6 +174,11 @@ void coarse_apply_any(const CoarseGeom& c, hdcr_dtype dt, const void* A, const C
         launch_coarse_apply<double>(c, static_cast<const double2*>(A), v, out, nrhs, s);
     } else if (dt == HDCR_C64) {
         launch_coarse_apply<float>(c, static_cast<const float2*>(A), v, out, nrhs, s);
+    } else if (nrhs >= 8 && coarse_mfma_eligible(c, 9, 3)) {
+        // a block of vectors on the matrix cores, each FP32 entry as three bf16
+        // terms: the products are exact and only the FP32 sums round, as in the
+        // vector-unit kernel
+        launch_coarse_mfma(c, 9, 3, static_cast<const uint32_t*>(A), v, out, nrhs, s);
     } else {
         launch_coarse_apply_bf16(c, static_cast<const uint16_t*>(A), v, out, nrhs, s);
     }

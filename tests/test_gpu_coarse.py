@@ -154,8 +154,8 @@ def test_batched_coarse_apply_mfma(L, block, nvec, nrhs):
     vd = to_dev(v, torch.complex64)
     ref = oracle.coarse_apply(A_log, v.astype(np.complex64).astype(np.complex128), cs.cdims)
     bound = (2.0 ** -8 + 1e-5) * oracle.coarse_apply(np.abs(A_log), np.abs(v), cs.cdims).real
-    # variants with at most Nb / 8 wavefronts per coarse site apply
-    waves = {1: 2, 2: 4, 3: 8, 4: 2, 5: 4, 6: 8, 7: 8, 8: 8}
+    # variants with at most Nb / 8 wavefronts per coarse site apply; 7 to 9 need Nb = 64
+    waves = {1: 2, 2: 4, 3: 8, 4: 2, 5: 4, 6: 8, 7: 8, 8: 8, 9: 8}
     ok = [k for k in range(1, hd._abi.MFMA_VARIANTS + 1) if waves[k] <= cs.nb // 8 and (k < 7 or cs.nb == 64)]
     outs = [to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=k)) for k in ok]
     err = np.abs(outs[0] - ref)
@@ -165,6 +165,71 @@ def test_batched_coarse_apply_mfma(L, block, nvec, nrhs):
     best, ms = hd.tune_coarse_batched(lat, Ab, vd)
     assert best in ok and all((ms[k - 1] > 0) == (k in ok) for k in range(1, hd._abi.MFMA_VARIANTS + 1))
     assert np.array_equal(to_host(hd.apply_coarse_batched(lat, Ab, vd)), outs[0])
+
+
+@pytest.mark.parametrize("nrhs", [1, 12, 40, 96, 101])
+def test_batched_coarse_apply_split_terms(nrhs):
+    """The batched apply at the 16^4 x 16 multi-RHS shape (coarse 4^4 from 4^4 blocks,
+    Nb = 64, BF16 A) with complex64 right-hand sides carried as 3 bf16 terms: every
+    product is exact, so the only error is FP32 summation of n = 9 * 128 * 3 products
+    per real output component, |out - ref| <= (n - 1) 2^-24 / (1 - (n - 1) 2^-24)
+    * sum |terms| with sum |terms| <= (1 + 2^-7) sum |A| |v| (the terms' magnitudes sum
+    to at most that much; |Ar vr| + |Ai vi| <= |A| |v|), element by element against
+    the oracle's FP64 apply of the stored bf16 A to the complex64 vectors.  In norm it
+    must meet the FP32 target 1e-5 and beat the one-term (bf16-rounded) result by
+    100x; two terms carry each component to within 2^-16 of its value.  Chunks of
+    48 or 64 right-hand sides with a partial last pass (40, 101) and the one-term
+    identity with variant 8 are covered."""
+    torch = torch_dev()
+    L, block, nvec = (16, 16, 16, 16), (4, 4, 4, 4), 32
+    log(f"batched coarse apply, split terms, L={L} nvec={nvec} nrhs={nrhs}")
+    lat = hd.Lattice(L, 16, block=block, nvec=nvec)
+    cs = oracle.Coarse(oracle.Params(L, 16), block, nvec)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(41)
+    raw = torch.randn(hd.coarse_bytes(lat, hd.C128) // 8, dtype=torch.float64, device="cuda:0", generator=g)
+    Ab = hd.convert_coarse(lat, raw, hd.BF16C)
+    del raw
+    A_log = to_host(hd.export_coarse(lat, Ab, hd.BF16C))
+    v = hi.gaussian_coarse(cs.nc, cs.nb, seed=42, nrhs=nrhs).astype(np.complex64)
+    vd = to_dev(v, torch.complex64)
+    ref = oracle.coarse_apply(A_log, v.astype(np.complex128), cs.cdims)
+    absum = oracle.coarse_apply(np.abs(A_log), np.abs(v).astype(np.float64), cs.cdims).real
+    n = 9 * 2 * cs.nb * 3
+    gam = (n - 1) * 2.0 ** -24 / (1 - (n - 1) * 2.0 ** -24)
+    o3 = to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=9, terms=3))
+    for part in (np.real, np.imag):
+        err = np.abs(part(o3) - part(ref))
+        assert np.all(err <= gam * (1 + 2.0 ** -7) * absum + 1e-30), float((err / (absum + 1e-30)).max())
+    e3 = rel_err(o3, ref)
+    assert e3 <= 1e-5, e3
+    o1 = to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=9, terms=1))
+    assert rel_err(o1, ref) >= 100 * e3
+    assert np.array_equal(o1, to_host(hd.apply_coarse_batched(lat, Ab, vd, variant=8)))
+    o2 = to_host(hd.apply_coarse_batched(lat, Ab, vd, terms=2))  # variant 0 -> 9 for split vectors
+    for part in (np.real, np.imag):
+        err = np.abs(part(o2) - part(ref))
+        assert np.all(err <= (2.0 ** -16 + gam * (1 + 2.0 ** -7)) * absum + 1e-30)
+    assert np.array_equal(to_host(hd.apply_coarse_batched(lat, Ab, vd, terms=3)), o3)
+    best, ms = hd.tune_coarse_batched(lat, Ab, vd, terms=3)
+    assert best == 9 and ms[8] > 0 and all(x == -1.0 for x in ms[:8])
+
+
+def test_batched_coarse_apply_argument_checks():
+    """Split right-hand sides run on variant 9 only, and variant 9 needs Nb = 64; terms
+    outside 1..3 and variants past the last are rejected."""
+    torch = torch_dev()
+    for nvec in (16, 32):  # Nb 32 and 64
+        lt = hd.Lattice((4, 4, 4, 4), 4, block=(2, 2, 2, 2), nvec=nvec)
+        A = torch.zeros(hd.coarse_bytes(lt, hd.BF16C) // 4, dtype=torch.int32, device="cuda:0")
+        v = torch.zeros((3, lt.nc, lt.nb), dtype=torch.complex64, device="cuda:0")
+        bad = [{"variant": 8, "terms": 3}, {"variant": 0, "terms": 4}, {"variant": 0, "terms": 0},
+               {"variant": hd._abi.MFMA_VARIANTS + 1}]
+        if nvec == 16:
+            bad += [{"variant": 9}, {"variant": 0, "terms": 3}]
+        for kw in bad:
+            with pytest.raises(hd.HDCRError):
+                hd.apply_coarse_batched(lt, A, v, **kw)
 
 
 def test_rank_deficient_vectors():

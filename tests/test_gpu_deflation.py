@@ -36,6 +36,8 @@ CASES = [
     ((4, 4, 4, 4), 8, (2, 2, 2, 2), 4, 12, 6),   # n = 128
     ((8, 8, 8, 8), 8, (2, 2, 2, 2), 4, 18, 7),   # n = 2048: ragged Gram tiles and rotation chunks
 ]
+# Nb = 64, n = 1024: with BF16C storage the set-up's block applies run on the matrix cores
+CASE_NB64 = ((8, 8, 8, 8), 4, (4, 4, 4, 4), 32, 40, 12)
 
 _cache = {}
 
@@ -144,12 +146,14 @@ def test_deflated_coarse_cr_parity(L, Ls, block, nvec, m, k):
     assert np.linalg.norm(res) <= 1.0001e-2 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("dt", ["c64", "bf16"])
-def test_deflation_fp32_storage(dt):
+@pytest.mark.parametrize("dt,case", [("c64", 1), ("bf16", 1), ("bf16", 2)])
+def test_deflation_fp32_storage(dt, case):
     """Set-up with A in C64 or BF16C storage (FP32 vectors): Ritz values of the stored
-    operator, orthonormal V, W = A V, and the deflated FP32 coarse CR converging."""
+    operator, orthonormal V, W = A V, and the deflated FP32 coarse CR converging.  With
+    BF16C and Nb = 64 the set-up's block applies run on the matrix cores with the
+    vectors split into three bf16 terms."""
     torch = torch_dev()
-    L, Ls, block, nvec, m, k = CASES[1]
+    L, Ls, block, nvec, m, k = CASES[1] if case == 1 else CASE_NB64
     log(f"deflation {dt} L={L} m={m} k={k}")
     p, cs, lat, U, vecs, basis_ref, A_ref = _problem(L, Ls, block, nvec)
     code = hd.C64 if dt == "c64" else hd.BF16C
