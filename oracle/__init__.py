@@ -224,6 +224,55 @@ def apply_cf(U, psi, M5: float, beta, R: float, bc=(1, 1, 1, -1)) -> np.ndarray:
     return out
 
 
+def apply_cf_sites(U, psi, M5: float, beta, R: float, sel, bc=(1, 1, 1, -1)) -> np.ndarray:
+    """``apply_cf`` at the selected output sites only, sel = site4 * Ls + s with
+    site4 = ((t Lz + z) Ly + y) Lx + x; returns [len(sel), 4, 3].  The same terms as
+    ``apply_cf`` and ``apply_hw``, gathered per output site (for lattices where the whole
+    field is too large for the plain numpy form)."""
+    U, psi = _c(U), _c(psi)
+    Lt, Lz, Ly, Lx, Ls = psi.shape[:5]
+    sigma, c = cf_coefficients(beta)
+    m = len(beta)
+    assert Ls == m + 1
+    sel = np.asarray(sel, dtype=np.int64)
+    s = sel % Ls
+    site = sel // Ls
+    x = site % Lx
+    y = (site // Lx) % Ly
+    z = (site // (Lx * Ly)) % Lz
+    t = site // (Lx * Ly * Lz)
+    coord = [x, y, z, t]
+    ext = [Lx, Ly, Lz, Lt]
+
+    def field(cs, sl):   # psi at coordinates cs = (x, y, z, t), slices sl: [n, 4, 3]
+        return psi[cs[3], cs[2], cs[1], cs[0], sl]
+
+    hw = (4.0 - M5) * field(coord, s)
+    eye = np.eye(4)
+    for mu in range(4):
+        g = gamma(mu)
+        fw = list(coord)
+        fw[mu] = (coord[mu] + 1) % ext[mu]
+        sf = np.where(coord[mu] == ext[mu] - 1, bc[mu], 1.0)[:, None, None]
+        Uf = U[t, z, y, x, mu]                                              # U_mu(x)
+        hop = np.einsum("nab,njb->nja", Uf, field(fw, s)) * sf
+        hw -= 0.5 * np.einsum("ij,nja->nia", eye - g, hop)
+        bw = list(coord)
+        bw[mu] = (coord[mu] - 1) % ext[mu]
+        sb = np.where(coord[mu] == 0, bc[mu], 1.0)[:, None, None]
+        Ub = U[bw[3], bw[2], bw[1], bw[0], mu]                              # U_mu(x - mu)
+        hop = np.einsum("nba,njb->nja", Ub.conj(), field(bw, s)) * sb
+        hw -= 0.5 * np.einsum("ij,nja->nia", eye + g, hop)
+    out = sigma[s][:, None, None] * np.einsum("ij,nja->nia", gamma(4), hw)
+    last = s == m
+    out[last] += R * np.einsum("ij,nja->nia", gamma(4), field(coord, s)[last])
+    lo = s > 0
+    out[lo] += c[s[lo] - 1][:, None, None] * field([q[lo] for q in coord], s[lo] - 1)
+    hi_ = s < m
+    out[hi_] += c[s[hi_]][:, None, None] * field([q[hi_] for q in coord], s[hi_] + 1)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Coarse space (Sec. 4)
 # ----------------------------------------------------------------------------

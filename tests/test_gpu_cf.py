@@ -1,8 +1,8 @@
 """GPU parity of the continued-fraction overlap operator (Sec. 3, the continued-fraction
 matrix) against the FP64 oracle through the C-ABI: element by element at 1e-10 (FP64) and 1e-5
 (FP32) over pole counts 1 to 63 (Ls = 2 to 64, so workgroups of 16 whole sites and of 256 / Ls
-sites), odd and extent-1 lattices, both boundary conditions; Hermiticity at 16^4; argument
-checks before any launch."""
+sites), odd and extent-1 lattices, both boundary conditions; sampled sites at 24^4, the
+benchmark's lattice; Hermiticity at 16^4; argument checks before any launch."""
 import numpy as np
 import pytest
 
@@ -59,6 +59,32 @@ def test_cf_parity_12x12x12x12():
     for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
         out = hd.apply_cf(lat, to_dev(hd.pack_gauge(U), dt), to_dev(hd.pack_fermion(x), dt), beta, R)
         assert max_rel_elem(hd.unpack_fermion(to_host(out), L, m + 1), ref) <= tol, dt
+
+
+@pytest.mark.parametrize("m", [8, 15])
+def test_cf_parity_full_size_sampled(m):
+    """24^4 with 8 and 15 pole slices (the benchmark's shapes: workgroups of 16 and of 16 / Ls
+    sites), FP64 and FP32, on 3000 sampled output sites plus the lattice corners (every
+    boundary crossing, first and last slice) against the oracle's per-site form."""
+    torch = torch_dev()
+    L, bc, M5, R = (24, 24, 24, 24), (1, 1, 1, -1), 1.8, 0.3
+    Ls = m + 1
+    log(f"continued fraction sampled L={L} m={m}")
+    beta = _beta(m, seed=30 + m)
+    U = hi.gauge_field(L, seed=1)
+    x = hi.gaussian_fermion(L, Ls, seed=2)
+    lat = hd.Lattice(L, Ls, M5=M5, bc=bc)
+    N5 = lat.N5
+    rng = np.random.default_rng(9)
+    sel = np.unique(np.concatenate([rng.integers(0, N5, 3000), [0, Ls - 1, N5 - 1, N5 - Ls]]))
+    ref = oracle.apply_cf_sites(U, x, M5, beta, R, sel, bc)
+    for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+        out = hd.apply_cf(lat, to_dev(hd.pack_gauge(U), dt), to_dev(hd.pack_fermion(x), dt), beta, R)
+        o = to_host(out)                                   # [12, V4, Ls]
+        got = o[:, sel // Ls, sel % Ls].T.reshape(-1, 4, 3)
+        assert max_rel_elem(got, ref) <= tol, dt
+        del out
+        torch.cuda.empty_cache()
 
 
 def test_cf_hermitian_on_device():

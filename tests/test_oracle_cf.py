@@ -1,7 +1,8 @@
 """Pins of the oracle's continued-fraction overlap operator (Sec. 3, the continued-fraction
 matrix): the Wilson kernel H_W against the domain wall oracle at Ls = 1, the 5d matrix against
 an independent dense construction on 2^4 and against its free-field momentum form, Hermiticity
-(real spectrum of both signs) and gauge covariance."""
+(real spectrum of both signs) and gauge covariance; the per-site form against the whole-field
+form."""
 import numpy as np
 import pytest
 
@@ -74,3 +75,18 @@ def test_cf_hermitian_and_gauge_covariant():
     lhs = oracle.apply_cf(Ug, xg, M5, BETA3, R, bc)
     rhs = np.einsum("tzyxab,tzyxsjb->tzyxsja", G, oracle.apply_cf(U, x, M5, BETA3, R, bc))
     np.testing.assert_allclose(lhs, rhs, atol=1e-12)
+
+
+def test_cf_sites_matches_full_apply():
+    """The per-site form equals the whole-field form on every site of a small lattice with
+    odd extents and both boundary-condition patterns (Ls = 6), and on a sample of a larger one."""
+    for L, bc, m in (((3, 2, 5, 3), (-1, 1, -1, 1), 5), ((4, 4, 4, 6), (1, 1, 1, -1), 8)):
+        beta = list(0.3 + np.arange(m) * 0.17)
+        U = hi.gauge_field(L, seed=7)
+        x = hi.gaussian_fermion(L, m + 1, seed=8)
+        full = oracle.apply_cf(U, x, 1.7, beta, 0.45, bc)
+        n5 = int(np.prod(L)) * (m + 1)
+        sel = np.arange(n5) if n5 < 2000 else np.random.default_rng(3).choice(n5, 700, replace=False)
+        got = oracle.apply_cf_sites(U, x, 1.7, beta, 0.45, sel, bc)
+        ref = full.reshape(-1, 4, 3)[sel]
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
