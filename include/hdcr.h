@@ -83,7 +83,9 @@ typedef enum {
  *                   kernel, 3 tile kernel with non-temporal stores, 4 parity-tile
  *                   kernel with one fifth-dimension slice per work-item (FP32),
  *                   5 paired-slice kernel on FP16 fields, 6 FP16 smoother and filter
- *                   steps as a plain pass plus a separate combination
+ *                   steps as a plain pass plus a separate combination; for
+ *                   hdcr_apply_cf: 2 one work-item per 5d site, 4 parity tiles with
+ *                   one slice per work-item (else paired slices in FP32 with even Ls)
  *   tslab, ysplit, xsplit  traversal blocking of the stencil's tiles (or sites):
  *                   t slabs of tslab tiles, y and x cut into ysplit and xsplit parts
  *                   (a value that does not divide the extent selects no cut)

@@ -1233,10 +1233,176 @@ __global__ void __launch_bounds__(CF_WG) cf_kernel(FineGeom g, CfCoef k, const C
     }
 }
 
+// Continued-fraction operator on 2^4 parity tiles (even extents, Ls <= 16): the
+// tile scheme of the domain wall kernels.  A workgroup holds one tile, 16 sites
+// x Ls slices; work-item (p, kk) handles the site whose position in the tile is
+// the bit pattern p and slice kk (W = 1), or slices 2 kk, 2 kk + 1 with every
+// field access one 16-byte load or store of two FP32 complex numbers (W = 2,
+// FP32, even Ls).  The tile's spinors are staged in LDS; in each direction one
+// of the two hops stays in the tile and reads its partner there, the other is
+// gathered from the field, two directions ahead.  The links are staged already
+// oriented (U_mu(x) forward, U_mu(x - mu)^dag backward), so the hop direction is
+// a run-time sign.  The slice couplings read psi(s -+ 1) of the same site from
+// the staged tile.  The output lands at its own slice.
+constexpr int CFT_LS = 16;
+
+template <typename T, int W> struct CfWord;
+template <typename T> struct CfWord<T, 1> {
+    typedef C2<T> type;
+    static __device__ __forceinline__ type ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return Buf<T>::ld(r, voff, soff);
+    }
+    static __device__ __forceinline__ C2<T> slice(type w, int) { return w; }
+};
+template <> struct CfWord<float, 2> {
+    typedef float4 type;
+    static __device__ __forceinline__ type ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        return ld_pair(r, voff, soff);
+    }
+    static __device__ __forceinline__ C2<float> slice(type w, int i) {
+        return i == 0 ? mk<float>(w.x, w.y) : mk<float>(w.z, w.w);
+    }
+};
+
+template <typename T, int W>
+__global__ void __launch_bounds__(16 * CFT_LS / W) __attribute__((amdgpu_waves_per_eu(2))) cf_tile_kernel(FineGeom g, TileGeom tg, CfCoef k,
+                                                                  const C2<T>* U, const C2<T>* in, C2<T>* out) {
+    static_assert(W == 1 || sizeof(T) == 4, "paired slices are FP32 only");
+    typedef CfWord<T, W> Wd;
+    typedef typename Wd::type Word;
+    constexpr int NKMAX = CFT_LS / W;
+    constexpr uint32_t CB = sizeof(C2<T>);
+    __shared__ Word spin[12 * 16 * NKMAX];  // [c][pattern][kk]
+    __shared__ C2<T> lds[16 * 8 * LPAD];     // [pattern][matrix][entry]
+    const int Ls = g.Ls, m = Ls - 1, NK = Ls / W;
+    const int p = threadIdx.x / NK, kk = threadIdx.x - (threadIdx.x / NK) * NK;
+    const int s0 = W * kk;
+    const int tile = logical_block(blockIdx.x, gridDim.x);
+    const Site tt = traverse(tg.t, tile);
+    Site st;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) st.x[mu] = 2 * tt.x[mu] + ((p >> mu) & 1);
+    st.site = ((st.x[3] * g.L[2] + st.x[2]) * g.L[1] + st.x[1]) * g.L[0] + st.x[0];
+    const Nbrs<T> n = neighbours<T>(g, st);
+    FieldRefs f;
+    f.cstride = (uint32_t)g.N5 * CB;
+    f.in = make_rsrc(in, 12u * f.cstride);
+    f.out = make_rsrc(out, 12u * f.cstride);
+    f.U = make_rsrc(U, (uint32_t)g.V4 * 36u * CB);
+    for (int e = kk; e < 9; e += NK) {
+        const int r = e / 3, cc = e - 3 * (e / 3);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const bool up = (p >> mu) & 1;
+            const C2<T> uf = Buf<T>::ld(f.U, (uint32_t)(st.site * 36 + mu * 9 + e) * CB, 0u);
+            const C2<T> ub = Buf<T>::ld(f.U, (uint32_t)(n.b[mu] * 36 + mu * 9 + e) * CB, 0u);
+            lds[(p * 8 + 2 * mu + (up ? 1 : 0)) * LPAD + e] = uf;
+            lds[(p * 8 + 2 * mu + (up ? 0 : 1)) * LPAD + cc * 3 + r] = mk<T>(ub.x, -ub.y);
+        }
+    }
+    C2<T> acc[W][12];
+    {
+        // D_W(-M5) psi starts with the diagonal 4 - M5; the own spinor is read
+        // back from the staged tile for the slice terms at the end
+        const uint32_t o0 = (uint32_t)(st.site * Ls + s0) * CB;
+        const T wd = (T)k.wdiag;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const Word w = Wd::ld(f.in, o0, (uint32_t)c * f.cstride);
+            spin[(c * 16 + p) * NKMAX + kk] = w;
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[i][c] = cscale<T>(wd, Wd::slice(w, i));
+        }
+    }
+#define HDCR_CFT_GATHER(MU, DST)                                                                              \
+    {                                                                                                         \
+        const uint32_t noff = (uint32_t)((((p >> MU) & 1) ? n.f[MU] : n.b[MU]) * Ls + s0) * CB;              \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) DST[c] = Wd::ld(f.in, noff, (uint32_t)c * f.cstride);  \
+    }
+    Word nx0[12], nx1[12];
+    HDCR_CFT_GATHER(0, nx0)
+    HDCR_CFT_GATHER(1, nx1)
+    __syncthreads();
+    const C2<T>* lnk = lds + p * 8 * LPAD;
+    // the eight 4d hops
+#define HDCR_CFT_HOPS(MU, NX)                                                                                 \
+    {                                                                                                         \
+        const bool up = (p >> MU) & 1;                                                                        \
+        const T sg_in = up ? (T)-1 : (T)1;                                                                    \
+        const int q = p ^ (1 << MU);                                                                          \
+        C2<T> mm[9], v[12];                                                                                   \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) mm[e] = lnk[(2 * MU) * LPAD + e];                       \
+        _Pragma("unroll") for (int i = 0; i < W; ++i) {                                                       \
+            _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = Wd::slice(spin[(c * 16 + q) * NKMAX + kk], i); \
+            hop_core_rt<T, MU>(v, mm, sg_in, up ? n.cb[MU] : n.cf[MU], acc[i]);                              \
+        }                                                                                                     \
+        _Pragma("unroll") for (int e = 0; e < 9; ++e) mm[e] = lnk[(2 * MU + 1) * LPAD + e];                   \
+        _Pragma("unroll") for (int i = 0; i < W; ++i) {                                                       \
+            _Pragma("unroll") for (int c = 0; c < 12; ++c) v[c] = Wd::slice(NX[c], i);                        \
+            hop_core_rt<T, MU>(v, mm, -sg_in, up ? n.cf[MU] : n.cb[MU], acc[i]);                             \
+        }                                                                                                     \
+    }
+    HDCR_CFT_HOPS(0, nx0)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_CFT_GATHER(2, nx0)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_CFT_HOPS(1, nx1)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_CFT_GATHER(3, nx1)
+    __builtin_amdgcn_sched_barrier(0);
+    HDCR_CFT_HOPS(2, nx0)
+    HDCR_CFT_HOPS(3, nx1)
+#undef HDCR_CFT_HOPS
+#undef HDCR_CFT_GATHER
+    // sigma_s gamma5 D_W psi_s + [s = m] R gamma5 psi_s + couplings to slices s -+ 1
+    // of the same site, from the staged tile (a coupling of 0 at s = 0 and s = m)
+    const int kd = kk > 0 ? kk - 1 : kk, ku = kk < NK - 1 ? kk + 1 : kk;
+    const uint32_t oo = (uint32_t)(st.site * Ls + s0) * CB;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const T g5 = (c < 6) ? (T)1 : (T)-1;
+        const Word wown = spin[(c * 16 + p) * NKMAX + kk];
+        const Word wdn = spin[(c * 16 + p) * NKMAX + kd], wup = spin[(c * 16 + p) * NKMAX + ku];
+        C2<T> o[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const int si = s0 + i;
+            // slice si - 1: the other half of this word, else the last slice of the word below
+            const C2<T> dn = (i > 0) ? Wd::slice(wown, i - 1) : Wd::slice(wdn, W - 1);
+            const C2<T> upn = (i < W - 1) ? Wd::slice(wown, i + 1) : Wd::slice(wup, 0);
+            o[i] = cscale<T>(g5 * (T)k.sigma[si], acc[i][c]);
+            axpy<T>(g5 * ((si == m) ? (T)k.R : (T)0), Wd::slice(wown, i), o[i]);
+            axpy<T>((T)k.cdn[si], dn, o[i]);
+            axpy<T>((T)k.cup[si], upn, o[i]);
+        }
+        if constexpr (W == 2)
+            st_pair_nt(make_float4(o[0].x, o[0].y, o[1].x, o[1].y), f.out, oo, (uint32_t)c * f.cstride);
+        else
+            Buf<T>::st_nt(o[0], f.out, oo, (uint32_t)c * f.cstride);
+    }
+}
+
 }  // namespace
 
 template <typename T>
 void launch_cf(const FineGeom& g, const CfCoef& k, const C2<T>* U, const C2<T>* in, C2<T>* out, hipStream_t s) {
+    // parity tiles for even extents and Ls <= 16 (paired slices in FP32 with even
+    // Ls; tune.dslash_variant 4: one slice per work-item), else one work-item
+    // per 5d site (tune.dslash_variant 2 forces it)
+    const bool tiles = g.variant != 2 && g.Ls <= CFT_LS && g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 &&
+                       g.L[3] % 2 == 0;
+    if (tiles) {
+        const TileGeom tg = tile_geom(g);
+        if constexpr (sizeof(T) == 4) {
+            if (g.Ls % 2 == 0 && g.variant != 4) {
+                hipLaunchKernelGGL((cf_tile_kernel<float, 2>), dim3(tg.t.V4), dim3(16 * g.Ls / 2), 0, s, g, tg, k, U,
+                                   in, out);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((cf_tile_kernel<T, 1>), dim3(tg.t.V4), dim3(16 * g.Ls), 0, s, g, tg, k, U, in, out);
+        return;
+    }
     const int blocks = (g.V4 + k.sites - 1) / k.sites;
     hipLaunchKernelGGL((cf_kernel<T>), dim3(blocks), dim3(k.sites * g.Ls), 0, s, g, k, U, in, out);
 }

@@ -2,7 +2,9 @@
 matrix) against the FP64 oracle through the C-ABI: element by element at 1e-10 (FP64) and 1e-5
 (FP32) over pole counts 1 to 63 (Ls = 2 to 64, so workgroups of 16 whole sites and of 256 / Ls
 sites), odd and extent-1 lattices, both boundary conditions; sampled sites at 24^4, the
-benchmark's lattice; Hermiticity at 16^4; argument checks before any launch."""
+benchmark's lattice; Hermiticity at 16^4; argument checks before any launch.  Even extents
+with Ls <= 16 take the parity-tile kernels (paired slices in FP32 with even Ls), the rest the
+one-site-per-work-item kernel; every path is compared."""
 import numpy as np
 import pytest
 
@@ -44,6 +46,26 @@ def test_cf_parity(L, m, bc, M5, R):
         out = hd.apply_cf(lat, to_dev(hd.pack_gauge(U), dt), to_dev(hd.pack_fermion(x), dt), beta, R)
         got = hd.unpack_fermion(to_host(out), L, Ls)
         assert max_rel_elem(got, ref) <= tol, dt
+
+
+@pytest.mark.parametrize("L,m", [((2, 2, 2, 2), 1), ((4, 4, 2, 6), 7), ((4, 2, 6, 4), 15), ((2, 4, 4, 2), 10)])
+def test_cf_kernel_paths(L, m):
+    """Even extents with Ls <= 16 run on parity tiles: paired slices in FP32 with even Ls
+    (the default), one slice per work-item (tune variant 4, and FP64), and the one-site-per-
+    work-item kernel (tune variant 2); every path against the oracle at 1e-10 / 1e-5."""
+    torch = torch_dev()
+    Ls, bc, M5, R = m + 1, (1, -1, 1, -1), 1.7, 0.35
+    log(f"continued fraction kernel paths L={L} m={m}")
+    beta = _beta(m, seed=50 + m)
+    U = hi.gauge_field(L, seed=8)
+    x = hi.gaussian_fermion(L, Ls, seed=9)
+    ref = oracle.apply_cf(U, x, M5, beta, R, bc)
+    for variant in (0, 4, 2):
+        lat = hd.Lattice(L, Ls, M5=M5, bc=bc).with_tune(dslash_variant=variant)
+        for dt, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-5)):
+            out = hd.apply_cf(lat, to_dev(hd.pack_gauge(U), dt), to_dev(hd.pack_fermion(x), dt), beta, R)
+            got = hd.unpack_fermion(to_host(out), L, Ls)
+            assert max_rel_elem(got, ref) <= tol, (variant, dt)
 
 
 def test_cf_parity_12x12x12x12():
