@@ -64,7 +64,8 @@ size_t build_workspace_bytes(const CoarseGeom& c) {
     w.take<double2>(fsz * kc * 9);      // class-split images
     w.take<double2>(coarse_elems(c));   // A in FP64
     w.take<double2>(coarse_project_scratch_elems(c));  // projection partial sums
-    w.take<int>(64);                    // rank flag
+    w.take<int>(64);                    // flags of the orthonormalisation
+    w.take<double2>(chq_scratch_elems(c));  // Gram matrices and R^-1 of the Cholesky QR
     return w.used();
 }
 
@@ -143,11 +144,27 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     double2* A64 = w.take<double2>(coarse_elems(c));
     double2* Pp = w.take<double2>(coarse_project_scratch_elems(c));
     int* flag = w.take<int>(64);
+    double2* chq = w.take<double2>(chq_scratch_elems(c));
     double2* b64 = basis64(basis);
-    // chiral split and block orthonormalisation
-    HDCR_HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), stream));
+    // chiral split and block orthonormalisation: Cholesky QR twice where its
+    // first round's pivots are in reach (flag[1] clear), else Gram-Schmidt with
+    // its rank test (flag[0])
+    HDCR_HIP_CHECK(hipMemsetAsync(flag, 0, 3 * sizeof(int), stream));
     launch_basis_fold(c, static_cast<const double2*>(vecs), b64, stream);
-    launch_block_orth(c, b64, flag, stream);
+    bool gs = !chq_ok(c);
+    if (!gs) {
+        launch_chq_round(c, b64, chq, 0, flag, stream);
+        int hf[2] = {0, 0};
+        HDCR_HIP_CHECK(hipMemcpyAsync(hf, flag + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+        HDCR_HIP_CHECK(hipStreamSynchronize(stream));
+        gs = hf[0] != 0;
+        if (!gs) {
+            launch_chq_apply(c, b64, chq, stream);
+            launch_chq_round(c, b64, chq, 1, flag, stream);
+            launch_chq_apply(c, b64, chq, stream);
+        }
+    }
+    if (gs) launch_block_orth(c, b64, flag, stream);
     launch_basis_to_f32(c, b64, basis32(c, basis), stream);
     launch_basis_to_f16(c, b64, basis16(c, basis), stream);
     HDCR_HIP_CHECK(hipGetLastError());
@@ -164,10 +181,12 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     }
     if (A_dtype != HDCR_C128) launch_coarse_convert(c, A64, A_dtype, A, stream);
     HDCR_HIP_CHECK(hipGetLastError());
-    int hflag = 0;
-    HDCR_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+    int hflag[3] = {0, 0, 0};
+    HDCR_HIP_CHECK(hipMemcpyAsync(hflag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, stream));
     HDCR_HIP_CHECK(hipStreamSynchronize(stream));
-    if (hflag) return fail(HDCR_ERANK, "hdcr_build_coarse: a block's subspace vectors are numerically dependent");
+    if (hflag[0]) return fail(HDCR_ERANK, "hdcr_build_coarse: a block's subspace vectors are numerically dependent");
+    if (hflag[2])
+        return fail(HDCR_ERANK, "hdcr_build_coarse: the second Cholesky QR round lost positive definiteness");
     return HDCR_OK;
 }
 

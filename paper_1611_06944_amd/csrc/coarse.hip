@@ -2,6 +2,7 @@
 // block orthonormalisation of the subspace vectors, restriction P^dag and
 // prolongation P, the little Dirac operator A = P^dag H P and its 9-point
 // coarse apply.  Layouts are described in coarse.h.
+#include <algorithm>
 #include <cmath>
 
 #include <cstdlib>
@@ -203,6 +204,160 @@ __global__ void __launch_bounds__(CWG) block_orth_kernel(CoarseGeom c, double2* 
                 const double inv = 1.0 / sqrt(nn[0].x);
                 for (int i = threadIdx.x; i < n; i += CWG) w[i] = make_double2(w[i].x * inv, w[i].y * inv);
             }
+        }
+    }
+}
+
+// The same Q by Cholesky QR applied twice (nvec <= 32): per block and
+// chirality the Gram matrix G = V^dag V, its Cholesky factor R (G = R^dag R,
+// R upper triangular with a positive real diagonal, so V = Q R is the thin QR
+// in index order) and Q = V R^-1; the second round repeats this on Q, which
+// restores orthogonality to rounding.  It reads the vectors 6 times instead of
+// about 2 nvec times.  A pivot of the first round at most 1e-8 of its diagonal
+// entry (a vector whose part outside the span of the previous ones is below
+// 1e-4 of its norm) is out of reach of Cholesky QR in FP64; the caller then
+// runs the Gram-Schmidt kernel above, whose rank test stays the reference.
+constexpr int CHQ_MAXV = 32;   // vectors per block and chirality
+constexpr int CHQ_CH = 64;     // indices staged per step of the Gram kernel
+constexpr int CHQ_R = 2;       // Gram entries per work-item in each direction (16 x 16 work-items)
+
+// partial Gram matrices: grid (2 Nc, parts); part z sums the indices of its
+// contiguous range, Gp[(ah * parts + z)][j][k] = sum_i conj(V_j[i]) V_k[i]
+__global__ void __launch_bounds__(CWG) chq_gram_kernel(CoarseGeom c, const double2* __restrict__ b64,
+                                                       double2* __restrict__ Gp) {
+    __shared__ double2 S[CHQ_MAXV][CHQ_CH + 1];
+    const int ah = blockIdx.x, n = c.nvec, nh = c.nhalf;
+    const double2* V = b64 + (size_t)ah * n * nh;
+    const int nchunk = (nh + CHQ_CH - 1) / CHQ_CH;
+    const int cb = (int)(((long long)nchunk * blockIdx.y) / gridDim.y);
+    const int ce = (int)(((long long)nchunk * (blockIdx.y + 1)) / gridDim.y);
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    double2 acc[CHQ_R][CHQ_R];
+#pragma unroll
+    for (int r = 0; r < CHQ_R; ++r)
+#pragma unroll
+        for (int q = 0; q < CHQ_R; ++q) acc[r][q] = make_double2(0, 0);
+    for (int ch = cb; ch < ce; ++ch) {
+        const int i0 = ch * CHQ_CH;
+        __syncthreads();  // the previous chunk has been read
+        for (int e = threadIdx.x; e < CHQ_MAXV * CHQ_CH; e += CWG) {
+            const int j = e / CHQ_CH, ii = e - j * CHQ_CH;
+            S[j][ii] = (j < n && i0 + ii < nh) ? V[(size_t)j * nh + i0 + ii] : make_double2(0, 0);
+        }
+        __syncthreads();
+        for (int ii = 0; ii < CHQ_CH; ++ii) {
+            double2 a[CHQ_R], b[CHQ_R];
+#pragma unroll
+            for (int r = 0; r < CHQ_R; ++r) {
+                a[r] = S[ty * CHQ_R + r][ii];
+                b[r] = S[tx * CHQ_R + r][ii];
+            }
+#pragma unroll
+            for (int r = 0; r < CHQ_R; ++r)
+#pragma unroll
+                for (int q = 0; q < CHQ_R; ++q) acc[r][q] = cjfma<double>(a[r], b[q], acc[r][q]);
+        }
+    }
+    double2* G = Gp + ((size_t)ah * gridDim.y + blockIdx.y) * n * n;
+#pragma unroll
+    for (int r = 0; r < CHQ_R; ++r)
+#pragma unroll
+        for (int q = 0; q < CHQ_R; ++q) {
+            const int j = ty * CHQ_R + r, k = tx * CHQ_R + q;
+            if (j < n && k < n) G[j * n + k] = acc[r][q];
+        }
+}
+
+// one wavefront per block and chirality: G = sum of the partials in part
+// order, its Cholesky factor R and Rinv = R^-1 (upper triangular; zeros below
+// the diagonal).  round 0: a pivot d_k <= 1e-8 G_kk sets flag[1] (Cholesky QR
+// out of reach: use Gram-Schmidt); round 1: a pivot <= G_kk / 4, impossible for
+// the nearly orthonormal output of round 0, sets flag[2].
+__global__ void __launch_bounds__(64) chq_chol_kernel(CoarseGeom c, const double2* __restrict__ Gp, int parts,
+                                                      int round, double2* __restrict__ Rinv, int* __restrict__ flag) {
+    __shared__ double2 G[CHQ_MAXV][CHQ_MAXV + 1];
+    __shared__ double2 Rm[CHQ_MAXV][CHQ_MAXV + 1];
+    __shared__ double2 X[CHQ_MAXV][CHQ_MAXV + 1];
+    const int ah = blockIdx.x, n = c.nvec, l = threadIdx.x;
+    for (int e = l; e < n * n; e += 64) {
+        double2 g = make_double2(0, 0);
+        for (int z = 0; z < parts; ++z) g = cadd<double>(g, Gp[((size_t)ah * parts + z) * n * n + e]);
+        G[e / n][e % n] = g;
+    }
+    __syncthreads();
+    const double thr = (round == 0) ? 1e-8 : 0.25;
+    for (int k = 0; k < n; ++k) {
+        if (l == k) {
+            double d = G[k][k].x;
+            for (int j = 0; j < k; ++j) d -= Rm[j][k].x * Rm[j][k].x + Rm[j][k].y * Rm[j][k].y;
+            if (!(d > thr * G[k][k].x)) {
+                flag[round == 0 ? 1 : 2] = 1;
+                d = 1.0;  // keep the factor finite; the caller discards it
+            }
+            Rm[k][k] = make_double2(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        if (l > k && l < n) {
+            double2 sacc = G[k][l];
+            for (int j = 0; j < k; ++j) sacc = cjfma<double>(cneg<double>(Rm[j][k]), Rm[j][l], sacc);
+            const double inv = 1.0 / Rm[k][k].x;
+            Rm[k][l] = make_double2(sacc.x * inv, sacc.y * inv);
+        }
+        __syncthreads();
+    }
+    // column l of R^-1 by back substitution
+    if (l < n) {
+        X[l][l] = make_double2(1.0 / Rm[l][l].x, 0.0);
+        for (int k = l - 1; k >= 0; --k) {
+            double2 sacc = make_double2(0, 0);
+            for (int j = k + 1; j <= l; ++j) sacc = cfma<double>(Rm[k][j], X[j][l], sacc);
+            const double inv = -1.0 / Rm[k][k].x;
+            X[k][l] = make_double2(sacc.x * inv, sacc.y * inv);
+        }
+    }
+    __syncthreads();
+    for (int e = l; e < n * n; e += 64) {
+        const int k = e / n, q = e % n;
+        Rinv[(size_t)ah * n * n + e] = (k <= q) ? X[k][q] : make_double2(0, 0);
+    }
+}
+
+// V <- V Rinv in place: grid (2 Nc, parts); a workgroup stages 64 indices of
+// all nvec vectors in LDS, then work-item (i, g) forms columns 8 g .. 8 g + 7 of
+// index i (column q sums rows k <= q) and writes them back
+constexpr int CHQ_TI = 64;
+__global__ void __launch_bounds__(CWG) chq_apply_kernel(CoarseGeom c, double2* __restrict__ b64,
+                                                        const double2* __restrict__ Rinv) {
+    __shared__ double2 Ri[CHQ_MAXV * CHQ_MAXV];
+    __shared__ double2 S[CHQ_MAXV][CHQ_TI + 1];
+    const int ah = blockIdx.x, n = c.nvec, nh = c.nhalf;
+    for (int e = threadIdx.x; e < n * n; e += CWG) Ri[e] = Rinv[(size_t)ah * n * n + e];
+    double2* V = b64 + (size_t)ah * n * nh;
+    const int ii = threadIdx.x % CHQ_TI, g = threadIdx.x / CHQ_TI;  // 4 groups of 8 columns
+    const int ntile = (nh + CHQ_TI - 1) / CHQ_TI;
+    for (int t = blockIdx.y; t < ntile; t += gridDim.y) {
+        const int i0 = t * CHQ_TI;
+        __syncthreads();  // Ri staged; the previous tile has been read
+        for (int e = threadIdx.x; e < n * CHQ_TI; e += CWG) {
+            const int k = e / CHQ_TI, x = e - k * CHQ_TI;
+            S[k][x] = (i0 + x < nh) ? V[(size_t)k * nh + i0 + x] : make_double2(0, 0);
+        }
+        __syncthreads();
+        double2 w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = make_double2(0, 0);
+        const int q0 = 8 * g;
+        const int kmax = min(n, q0 + 8);
+        for (int k = 0; k < kmax; ++k) {
+            const double2 v = S[k][ii];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (k <= q0 + q) w[q] = cfma<double>(v, Ri[k * n + min(q0 + q, n - 1)], w[q]);
+        }
+        if (i0 + ii < nh) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q0 + q < n) V[(size_t)(q0 + q) * nh + i0 + ii] = w[q];
         }
     }
 }
@@ -1175,6 +1330,29 @@ void launch_basis_fold(const CoarseGeom& c, const double2* vecs, double2* b64, h
 
 void launch_block_orth(const CoarseGeom& c, double2* b64, int* rank_flag, hipStream_t s) {
     hipLaunchKernelGGL(block_orth_kernel, dim3(c.Nc * 2), dim3(CWG), 0, s, c, b64, rank_flag);
+}
+
+bool chq_ok(const CoarseGeom& c) { return c.nvec <= CHQ_MAXV; }
+int chq_parts(const CoarseGeom& c) {
+    const int want = (2048 + 2 * c.Nc - 1) / (2 * c.Nc);  // about 2048 workgroups in all
+    const int chunks = (c.nhalf + CHQ_CH - 1) / CHQ_CH;
+    return std::max(1, std::min(std::min(want, 16), chunks));
+}
+size_t chq_scratch_elems(const CoarseGeom& c) {
+    return chq_ok(c) ? (size_t)2 * c.Nc * (chq_parts(c) + 1) * c.nvec * c.nvec : 0;
+}
+void launch_chq_round(const CoarseGeom& c, double2* b64, double2* scratch, int round, int* flag, hipStream_t s) {
+    const int parts = chq_parts(c);
+    double2* Gp = scratch;
+    double2* Rinv = scratch + (size_t)2 * c.Nc * parts * c.nvec * c.nvec;
+    hipLaunchKernelGGL(chq_gram_kernel, dim3(c.Nc * 2, parts), dim3(CWG), 0, s, c, b64, Gp);
+    hipLaunchKernelGGL(chq_chol_kernel, dim3(c.Nc * 2), dim3(64), 0, s, c, Gp, parts, round, Rinv, flag);
+}
+void launch_chq_apply(const CoarseGeom& c, double2* b64, const double2* scratch, hipStream_t s) {
+    const int parts = chq_parts(c);
+    const double2* Rinv = scratch + (size_t)2 * c.Nc * parts * c.nvec * c.nvec;
+    const int ap = std::max(1, std::min(16, (c.nhalf + CHQ_TI - 1) / CHQ_TI));
+    hipLaunchKernelGGL(chq_apply_kernel, dim3(c.Nc * 2, ap), dim3(CWG), 0, s, c, b64, Rinv);
 }
 
 void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, hipStream_t s) {

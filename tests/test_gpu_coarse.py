@@ -244,6 +244,30 @@ def test_rank_deficient_vectors():
     assert code == hd._abi.HDCR_ERANK
 
 
+@pytest.mark.parametrize("eps,tol", [(1e-3, 1e-9), (1e-6, 1e-8)])
+def test_basis_nearly_dependent_vectors(eps, tol):
+    """Block orthonormalisation of a set with v2 = v0 + eps w.  With eps = 1e-3 the second
+    vector's part outside the first is 1e-3 of its norm: Cholesky QR twice applies (its
+    first-round pivot ratio, about 1e-6, is above 1e-8).  With eps = 1e-6 the ratio is
+    about 1e-12: the build falls back to Gram-Schmidt, whose rank test (1e-24) passes.
+    Both against the oracle's Gram-Schmidt and with an orthonormal result."""
+    torch = torch_dev()
+    L, Ls, block, nvec = (4, 4, 4, 4), 4, (2, 2, 2, 2), 4
+    log(f"coarse basis, nearly dependent vectors, eps={eps}")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    vecs[2] = vecs[0] + eps * vecs[3]
+    vecs[3] = hi.gaussian_fermion(L, Ls, seed=77)
+    basis_ref, st = oracle.block_basis(vecs, cs)
+    assert st == 0
+    basis, _ = hd.build_coarse(lat, to_dev(hd.pack_gauge(U)), _dev_vecs(vecs), hd.C128)
+    got = np.stack([hd.unpack_fermion(f, L, Ls) for f in to_host(hd.export_basis(lat, basis))])
+    assert max_rel_elem(got, basis_ref) <= tol
+    # each exported field holds one basis vector of every block: Phi^dag Phi = Nc I
+    F = got.reshape(got.shape[0], -1)
+    G = F.conj() @ F.T
+    assert np.abs(G / cs.nc - np.eye(F.shape[0])).max() <= 1e-12
+
+
 def test_coarse_build_cfg2_scale():
     """16^4 x 16, 4^4 blocks, 24 vectors (Nb = 48): the GPU little Dirac operator satisfies
     the Galerkin identity A v = P^dag H P v (GPU kernels, FP64) and matches the oracle on
