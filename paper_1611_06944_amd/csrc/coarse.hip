@@ -3,6 +3,7 @@
 // prolongation P, the little Dirac operator A = P^dag H P and its 9-point
 // coarse apply.  Layouts are described in coarse.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include <cstdlib>
@@ -1948,11 +1949,15 @@ template <int TERMS, int NP>
 void rs_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
     constexpr int NB = RS_NB;
     const size_t lds = (size_t)NB * (NB + 4) * 4 + (size_t)TERMS * 16 * NP * (NB + 4) * 4;
-    static bool attr = false;  // per instantiation: raise the dynamic LDS limit once
-    if (!attr) {
+    // per instantiation and device: raise the dynamic LDS limit once (setting
+    // it twice from racing threads is harmless)
+    static std::atomic<unsigned long long> attr_devices{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!((attr_devices.load(std::memory_order_relaxed) >> dev) & 1ull)) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(coarse_mfma_rs_kernel<NB, TERMS, NP>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
+        attr_devices.fetch_or(1ull << dev, std::memory_order_relaxed);
     }
     hipLaunchKernelGGL((coarse_mfma_rs_kernel<NB, TERMS, NP>), dim3(c.Nc), dim3(8 * NB), lds, s, c, A, v, out, nrhs);
 }
