@@ -185,14 +185,28 @@ def test_hdcr_solve_mixed_precision(coarse):
     assert st["coarse_iters"] > 0 and st["fine_applies_inner"] > 0
 
 
+def _sampled_residual(U, b_aos, x, p, lat, L, Ls, seed):
+    """(N5 / n) sum over a uniform sample of n = 20000 5d sites of |b - H x|^2, square-rooted."""
+    x_aos = hd.unpack_fermion(to_host(x), L, Ls)
+    rng = np.random.default_rng(seed)
+    n = 20000
+    sel = rng.choice(lat.N5, size=n, replace=False)
+    hx = oracle.apply_h_sites(U, x_aos, p, sel)
+    t, z, y, xx = np.unravel_index(sel // Ls, (L[3], L[2], L[1], L[0]))
+    r = b_aos[t, z, y, xx, sel % Ls] - hx
+    return np.sqrt(lat.N5 / n * float(np.sum(np.abs(r) ** 2)))
+
+
 def test_hdcr_solve_full_size_sampled_residual():
-    """The benchmark's HDCR solve at 24^4 x 16 (32 subspace vectors filtered with FP16 storage,
+    """The benchmark's HDCR solves at 24^4 x 16 (32 subspace vectors filtered with FP16 storage,
     4^4 blocks, Nb = 64, FP32 cycle with the FP16 basis copy, BF16 coarse operator, FGCR(8) in
-    FP64) reaches 1e-8, and the oracle's H confirms it on a uniform sample of n = 20000 of the N5
-    5d sites: (N5 / n) sum_sample |r_i|^2 estimates |b - H x|^2 without bias, with a relative
-    standard deviation of about sqrt(2 / (24 n)) ~ 0.2% for a residual spread over the lattice
-    (24 real entries per site).  The estimate must lie below (1.5e-8 |b|)^2 and within a factor
-    1.5 of the library's own FP64 true residual."""
+    FP64) reach 1e-8: the plain configuration, and the one with both extensions (FP16-storage
+    smoother, coarse deflation with k = 48 from a block of 64, filter degree 60, 5 passes).  The
+    oracle's H confirms each on a uniform sample of n = 20000 of the N5 5d sites:
+    (N5 / n) sum_sample |r_i|^2 estimates |b - H x|^2 without bias, with a relative standard
+    deviation of about sqrt(2 / (24 n)) ~ 0.2% for a residual spread over the lattice (24 real
+    entries per site).  The estimate must lie below (1.5e-8 |b|)^2 and within a factor 1.5 of
+    the library's own FP64 true residual."""
     torch = torch_dev()
     L, Ls, nvec = (24, 24, 24, 24), 16, 32
     log(f"HDCR solve at L={L} Ls={Ls} nvec={nvec}")
@@ -210,26 +224,28 @@ def test_hdcr_solve_full_size_sampled_residual():
     basis, A = hd.build_coarse(lat, Ud, vecs, hd.BF16C)
     del vecs
     torch.cuda.empty_cache()
-    prm = hd.default_params(precond=hd.PRECOND_TWO_LEVEL, inner_dtype=hd.C64, coarse_dtype=hd.BF16C, coarse_tol=0.2,
-                            coarse_maxiter=500, restart=8, tol=1e-8, maxiter=500, cheb_order=10, cheb_lo=0.5,
-                            cheb_hi=64.0, basis_dtype=hd.F16C)
-    x, st, _ = hd.solve(lat, Ud, bd, params=prm, basis=basis, A=A)
+    kw = dict(precond=hd.PRECOND_TWO_LEVEL, coarse_dtype=hd.BF16C, coarse_tol=0.2, coarse_maxiter=500, restart=8,
+              tol=1e-8, maxiter=500, cheb_order=10, cheb_lo=0.5, cheb_hi=64.0, basis_dtype=hd.F16C)
+    x, st, _ = hd.solve(lat, Ud, bd, params=hd.default_params(inner_dtype=hd.C64, **kw), basis=basis, A=A)
     log(f"  outer {st['outer_iters']} coarse {st['coarse_iters']} true residual {st['true_rel_residual']:.2e}")
     assert st["status"] == 0 and st["true_rel_residual"] <= 1e-8
-    del basis, A
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(31)
+    v0 = torch.randn((64, lat.nc, lat.nb), dtype=torch.complex128, device="cuda:0", generator=g)
+    d = hd.build_deflation(lat, A, hd.BF16C, v0, 48, degree=60, iters=5)
+    x2, st2, _ = hd.solve(lat, Ud, bd, params=hd.default_params(inner_dtype=hd.F16C, **kw), basis=basis, A=A, defl=d)
+    log(f"  FP16 smoother + deflation: outer {st2['outer_iters']} coarse {st2['coarse_iters']} "
+        f"true residual {st2['true_rel_residual']:.2e}")
+    assert st2["status"] == 0 and st2["true_rel_residual"] <= 1e-8
+    assert st2["coarse_iters"] < st["coarse_iters"]
+    del basis, A, d, v0
     torch.cuda.empty_cache()
-    x_aos = hd.unpack_fermion(to_host(x), L, Ls)
-    rng = np.random.default_rng(6)
-    n = 20000
-    sel = rng.choice(lat.N5, size=n, replace=False)
-    hx = oracle.apply_h_sites(U, x_aos, p, sel)
-    t, z, y, xx = np.unravel_index(sel // Ls, (L[3], L[2], L[1], L[0]))
-    r = b_aos[t, z, y, xx, sel % Ls] - hx
-    est = np.sqrt(lat.N5 / n * float(np.sum(np.abs(r) ** 2)))
     bn = np.linalg.norm(b_aos)
-    log(f"  sampled |b - Hx|/|b| = {est / bn:.3e}, library {st['true_rel_residual']:.3e}")
-    assert est <= 1.5e-8 * bn
-    assert 1 / 1.5 <= est / (st["true_rel_residual"] * bn) <= 1.5
+    for xs, s_, seed in ((x, st, 6), (x2, st2, 7)):
+        est = _sampled_residual(U, b_aos, xs, p, lat, L, Ls, seed)
+        log(f"  sampled |b - Hx|/|b| = {est / bn:.3e}, library {s_['true_rel_residual']:.3e}")
+        assert est <= 1.5e-8 * bn
+        assert 1 / 1.5 <= est / (s_["true_rel_residual"] * bn) <= 1.5
 
 
 def test_hdcr_solve_resume_from_nonzero_x0():
