@@ -147,20 +147,20 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     double2* chq = w.take<double2>(chq_scratch_elems(c));
     double2* b64 = basis64(basis);
     // chiral split and block orthonormalisation: Cholesky QR twice where its
-    // first round's pivots are in reach (flag[1] clear), else Gram-Schmidt with
+    // first pass's pivots are in reach (flag[1] clear), else Gram-Schmidt with
     // its rank test (flag[0])
     HDCR_HIP_CHECK(hipMemsetAsync(flag, 0, 3 * sizeof(int), stream));
     launch_basis_fold(c, static_cast<const double2*>(vecs), b64, stream);
     bool gs = !chq_ok(c);
     if (!gs) {
-        launch_chq_round(c, b64, chq, 0, flag, stream);
+        launch_chq_pass(c, b64, chq, 0, flag, stream);
         int hf[2] = {0, 0};
         HDCR_HIP_CHECK(hipMemcpyAsync(hf, flag + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
         HDCR_HIP_CHECK(hipStreamSynchronize(stream));
         gs = hf[0] != 0;
         if (!gs) {
             launch_chq_apply(c, b64, chq, stream);
-            launch_chq_round(c, b64, chq, 1, flag, stream);
+            launch_chq_pass(c, b64, chq, 1, flag, stream);
             launch_chq_apply(c, b64, chq, stream);
         }
     }
@@ -186,7 +186,7 @@ int hdcr_build_coarse(const hdcr_coarse_desc* desc, const void* U, const void* v
     HDCR_HIP_CHECK(hipStreamSynchronize(stream));
     if (hflag[0]) return fail(HDCR_ERANK, "hdcr_build_coarse: a block's subspace vectors are numerically dependent");
     if (hflag[2])
-        return fail(HDCR_ERANK, "hdcr_build_coarse: the second Cholesky QR round lost positive definiteness");
+        return fail(HDCR_ERANK, "hdcr_build_coarse: the second Cholesky QR pass lost positive definiteness");
     return HDCR_OK;
 }
 

@@ -66,13 +66,13 @@ void launch_basis_fold(const CoarseGeom& c, const double2* vecs, double2* b64, h
 // per block and chirality: classical Gram-Schmidt applied twice, in index
 // order; rank_flag[0] is set to 1 if a vector is dependent (|w| <= 1e-12 |w0|)
 void launch_block_orth(const CoarseGeom& c, double2* b64, int* rank_flag, hipStream_t s);
-// Cholesky QR form of the same orthonormalisation (nvec <= 32): one round of
-// Gram matrices and factors (flag[1]: a first-round pivot out of reach, use
-// launch_block_orth on the unchanged vectors; flag[2]: a second-round failure),
+// Cholesky QR form of the same orthonormalisation (nvec <= 32): one pass of
+// Gram matrices and factors (flag[1]: a first-pass pivot out of reach, use
+// launch_block_orth on the unchanged vectors; flag[2]: a second-pass failure),
 // then V <- V R^-1 with launch_chq_apply.  scratch: chq_scratch_elems entries.
 bool chq_ok(const CoarseGeom& c);
 size_t chq_scratch_elems(const CoarseGeom& c);
-void launch_chq_round(const CoarseGeom& c, double2* b64, double2* scratch, int round, int* flag, hipStream_t s);
+void launch_chq_pass(const CoarseGeom& c, double2* b64, double2* scratch, int pass, int* flag, hipStream_t s);
 void launch_chq_apply(const CoarseGeom& c, double2* b64, const double2* scratch, hipStream_t s);
 void launch_basis_to_f32(const CoarseGeom& c, const double2* b64, float2* b32, hipStream_t s);
 void launch_basis_to_f16(const CoarseGeom& c, const double2* b64, uint32_t* b16, hipStream_t s);

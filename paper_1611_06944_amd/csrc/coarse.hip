@@ -271,11 +271,12 @@ __global__ void __launch_bounds__(CWG) chq_gram_kernel(CoarseGeom c, const doubl
 
 // one wavefront per block and chirality: G = sum of the partials in part
 // order, its Cholesky factor R and Rinv = R^-1 (upper triangular; zeros below
-// the diagonal).  round 0: a pivot d_k <= 1e-8 G_kk sets flag[1] (Cholesky QR
-// out of reach: use Gram-Schmidt); round 1: a pivot <= G_kk / 4, impossible for
-// the nearly orthonormal output of round 0, sets flag[2].
+// the diagonal).  First pass (pass = 0): a pivot d_k <= 1e-8 G_kk sets flag[1]
+// (Cholesky QR out of reach: use Gram-Schmidt); second pass (pass = 1): a pivot
+// <= G_kk / 4, impossible for the nearly orthonormal output of the first, sets
+// flag[2].
 __global__ void __launch_bounds__(64) chq_chol_kernel(CoarseGeom c, const double2* __restrict__ Gp, int parts,
-                                                      int round, double2* __restrict__ Rinv, int* __restrict__ flag) {
+                                                      int pass, double2* __restrict__ Rinv, int* __restrict__ flag) {
     __shared__ double2 G[CHQ_MAXV][CHQ_MAXV + 1];
     __shared__ double2 Rm[CHQ_MAXV][CHQ_MAXV + 1];
     __shared__ double2 X[CHQ_MAXV][CHQ_MAXV + 1];
@@ -286,13 +287,13 @@ __global__ void __launch_bounds__(64) chq_chol_kernel(CoarseGeom c, const double
         G[e / n][e % n] = g;
     }
     __syncthreads();
-    const double thr = (round == 0) ? 1e-8 : 0.25;
+    const double thr = (pass == 0) ? 1e-8 : 0.25;
     for (int k = 0; k < n; ++k) {
         if (l == k) {
             double d = G[k][k].x;
             for (int j = 0; j < k; ++j) d -= Rm[j][k].x * Rm[j][k].x + Rm[j][k].y * Rm[j][k].y;
             if (!(d > thr * G[k][k].x)) {
-                flag[round == 0 ? 1 : 2] = 1;
+                flag[pass == 0 ? 1 : 2] = 1;
                 d = 1.0;  // keep the factor finite; the caller discards it
             }
             Rm[k][k] = make_double2(sqrt(d), 0.0);
@@ -1342,12 +1343,12 @@ int chq_parts(const CoarseGeom& c) {
 size_t chq_scratch_elems(const CoarseGeom& c) {
     return chq_ok(c) ? (size_t)2 * c.Nc * (chq_parts(c) + 1) * c.nvec * c.nvec : 0;
 }
-void launch_chq_round(const CoarseGeom& c, double2* b64, double2* scratch, int round, int* flag, hipStream_t s) {
+void launch_chq_pass(const CoarseGeom& c, double2* b64, double2* scratch, int pass, int* flag, hipStream_t s) {
     const int parts = chq_parts(c);
     double2* Gp = scratch;
     double2* Rinv = scratch + (size_t)2 * c.Nc * parts * c.nvec * c.nvec;
     hipLaunchKernelGGL(chq_gram_kernel, dim3(c.Nc * 2, parts), dim3(CWG), 0, s, c, b64, Gp);
-    hipLaunchKernelGGL(chq_chol_kernel, dim3(c.Nc * 2), dim3(64), 0, s, c, Gp, parts, round, Rinv, flag);
+    hipLaunchKernelGGL(chq_chol_kernel, dim3(c.Nc * 2), dim3(64), 0, s, c, Gp, parts, pass, Rinv, flag);
 }
 void launch_chq_apply(const CoarseGeom& c, double2* b64, const double2* scratch, hipStream_t s) {
     const int parts = chq_parts(c);
