@@ -556,7 +556,7 @@ def main():
         # eigenpair residuals |A v - theta v| (|v| = 1) of the stored operator
         res = (d.W - d.theta.to(d.V.real.dtype)[:, None, None] * d.V).reshape(d.k, -1).norm(dim=1)
         defl_space["d"] = d
-        return {"k": args.defl_k, "m": args.defl_m, "degree": args.defl_degree, "passes": args.defl_iters,
+        return {"k": args.defl_k, "k_found": d.k, "m": args.defl_m, "degree": args.defl_degree, "passes": args.defl_iters,
                 "setup_s": round(t_setup, 3), "ritz_abs_min_max": [round(abs(d.theta_host[0]), 5),
                                                                   round(abs(d.theta_host[-1]), 5)],
                 "ritz_residual_max": float(res.max()),

@@ -428,19 +428,26 @@ HDCR_API int hdcr_coarse_solve_static(const hdcr_coarse_desc* desc, hdcr_dtype A
  * orthonormal (Gram-Schmidt in index order, twice) and rotates it to the Ritz
  * vectors of A^2; lo = cut * hi in the first pass and the largest Ritz value
  * of A^2 in the block (at most 0.99 hi) afterwards.  A final Rayleigh-Ritz on A
- * gives theta and V; the k of smallest |theta| are written to theta (device,
- * k doubles), V and W = A V (device, [k][site_c][Nb] in C128 for C128 storage
- * of A, C64 otherwise: the vector precision of the coarse solve that uses
- * them), and to theta_host (may be NULL) in ascending |theta|.  Computed in
- * that vector precision with FP64 inner products; the small dense eigenproblems
- * are solved on the host.  v0: m C128 coarse vectors.  work:
- * hdcr_deflation_workspace_bytes().  Synchronous; HDCR_ENAN if the spectrum
- * estimate or a Ritz value is not finite. */
+ * gives the pairs (theta, y), |y| = 1.  A pair is found when its residual
+ * |A y - theta y| is at most 1e-2 |theta|: a block that is not yet an
+ * invariant subspace of A can mix eigenvectors of opposite sign into a Ritz
+ * vector whose theta lies anywhere between them, near zero included.  The
+ * found pairs of smallest |theta|, at most k of them, are written to theta
+ * (device doubles), V and W = A V (device, [.][site_c][Nb] in C128 for C128
+ * storage of A, C64 otherwise: the vector precision of the coarse solve that
+ * uses them), and to theta_host (may be NULL) in ascending |theta|; *k_found
+ * (may be NULL) gets their number, and only that many entries are written
+ * (buffers sized for k).  Computed in that vector precision with FP64 inner
+ * products; the small dense eigenproblems are solved on the host.  v0: m C128
+ * coarse vectors.  work: hdcr_deflation_workspace_bytes().  Synchronous;
+ * HDCR_ENOTCONV if no pair was found (raise iters, degree or m), HDCR_ENAN if
+ * the spectrum estimate or a Ritz problem is not finite. */
 HDCR_API size_t hdcr_deflation_workspace_bytes(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype,
                                                const hdcr_deflation_params* params);
 HDCR_API int hdcr_build_deflation(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
                                   const hdcr_deflation_params* params, const void* v0, double* theta, void* V, void* W,
-                                  double* theta_host, void* work, size_t work_bytes, hipStream_t stream);
+                                  double* theta_host, int32_t* k_found, void* work, size_t work_bytes,
+                                  hipStream_t stream);
 
 /* Subspace generation (Sec. 4, Fig. 1): vecs[k] = T_degree(yhat) noise[k] / |.|
  * with yhat = (2 H^2 - hi - lo)/(hi - lo): the Chebyshev low-pass filter that

@@ -640,6 +640,9 @@ def coarse_cr(A, v, cdims, tol=1e-2, maxiter=500, defl=None):
     return cr(lambda u: coarse_apply(A, u, cdims), v, tol=tol, maxiter=maxiter, x0=x0, check_true=False)
 
 
+DEFL_RES_TOL = 1e-2  # largest residual |A y - theta y| / |theta| of a deflated eigenpair (|y| = 1)
+
+
 def coarse_deflation(A, cdims, V0, k, degree=40, iters=4, cut=0.05, power_iters=30):
     """Low eigenpairs of the little Dirac operator A for deflating the coarse solve (Sec. 5
     names coarse-space eigenvector deflation as the open option for the coarse cost).
@@ -651,8 +654,12 @@ def coarse_deflation(A, cdims, V0, k, degree=40, iters=4, cut=0.05, power_iters=
     uses lo = cut * hi, later ones lo = the largest Ritz value of A^2 in the block, which
     bounds the part of the spectrum the block does not hold (A^2 is positive definite, so its
     Ritz values never fall below its spectrum, unlike those of the indefinite A).  A final
-    Rayleigh-Ritz on A (theta, Y = eig(V^dag A V)) gives the pairs; the k of smallest |theta|
-    are returned as (theta[k], V[k], W[k] = A V[k]).
+    Rayleigh-Ritz on A (theta, Y = eig(V^dag A V)) gives the pairs.  A pair counts as found when
+    its residual |A y - theta y| (|y| = 1) is at most DEFL_RES_TOL |theta|: a block that is not yet
+    an invariant subspace of A can mix eigenvectors of A of opposite sign into a Ritz vector whose
+    Rayleigh quotient lies anywhere between them, near zero included, and deflating such a pair
+    would divide by that spurious value.  The k found pairs of smallest |theta| (fewer if fewer
+    were found) are returned as (theta, V, W = A V).
     """
     apply = lambda u: coarse_apply(A, u, cdims)
     hi = 1.1 * power_max(apply, V0[0], power_iters)
@@ -674,10 +681,11 @@ def coarse_deflation(A, cdims, V0, k, degree=40, iters=4, cut=0.05, power_iters=
     W = [apply(v) for v in V]
     G = np.array([[vdot(V[i], W[j]) for j in range(m)] for i in range(m)])
     theta, Y = np.linalg.eigh(0.5 * (G + G.conj().T))
-    order = np.argsort(np.abs(theta))[:k]
-    Vk = [sum(Y[i, q] * V[i] for i in range(m)) for q in order]
-    Wk = [sum(Y[i, q] * W[i] for i in range(m)) for q in order]
-    return theta[order], Vk, Wk
+    Vy = [sum(Y[i, q] * V[i] for i in range(m)) for q in range(m)]
+    Wy = [sum(Y[i, q] * W[i] for i in range(m)) for q in range(m)]
+    found = [q for q in range(m) if norm(Wy[q] - theta[q] * Vy[q]) <= DEFL_RES_TOL * abs(theta[q])]
+    order = sorted(found, key=lambda q: abs(theta[q]))[:k]
+    return theta[order], [Vy[q] for q in order], [Wy[q] for q in order]
 
 
 def vcycle(apply, A, basis, cs: Coarse, r, order=10, lo=1.0, hi=64.0, ctol=1e-2, cmaxiter=500,

@@ -604,10 +604,13 @@ def build_deflation(lat: Lattice, A, A_dtype: int, v0, k: int, degree: int = 40,
     V = torch.empty((int(k), lat.nc, lat.nb), dtype=vdt, device=v0.device)
     W = torch.empty_like(V)
     th = (ctypes.c_double * int(k))()
-    _abi.check(lib.hdcr_build_deflation(ctypes.byref(cd), int(A_dtype), _ptr(A), ctypes.byref(prm), _ptr(v0),
-                                        _ptr(theta), _ptr(V), _ptr(W), th, _ptr(work), work.numel(),
-                                        _stream(stream)), "hdcr_build_deflation")
-    return Deflation(theta, V, W, [float(t) for t in th])
+    kf = ctypes.c_int32(0)
+    code = lib.hdcr_build_deflation(ctypes.byref(cd), int(A_dtype), _ptr(A), ctypes.byref(prm), _ptr(v0), _ptr(theta),
+                                    _ptr(V), _ptr(W), th, ctypes.byref(kf), _ptr(work), work.numel(), _stream(stream))
+    if code != 0:
+        raise _abi.HDCRError(code, "hdcr_build_deflation")
+    n = int(kf.value)
+    return Deflation(theta[:n], V[:n], W[:n], [float(t) for t in th[:n]])
 
 
 def coarse_solve(lat: Lattice, A, A_dtype: int, b, maxiter: int = 500, tol: float = 1e-2, defl: Deflation | None = None,

@@ -99,7 +99,7 @@ PROTOTYPES = {
                                                 _vp, _vp, _i32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32), _vp]),
     "hdcr_deflation_workspace_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32, ctypes.POINTER(DeflationParams)]),
     "hdcr_build_deflation": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _i32, _vp, ctypes.POINTER(DeflationParams),
-                                            _vp, _vp, _vp, _vp, _dbl_p, _vp, _sz, _vp]),
+                                            _vp, _vp, _vp, _vp, _dbl_p, ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp]),
     "hdcr_basis_bytes": (_sz, [ctypes.POINTER(CoarseDesc)]),
     "hdcr_coarse_bytes": (_sz, [ctypes.POINTER(CoarseDesc), _i32]),
     "hdcr_build_coarse": (ctypes.c_int, [ctypes.POINTER(CoarseDesc), _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),

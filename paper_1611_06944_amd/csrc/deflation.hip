@@ -298,10 +298,14 @@ template <typename T> class DeflBuilder {
     hipStream_t s_;
 };
 
+// largest residual |A y - theta y| / |theta| of a kept eigenpair (|y| = 1)
+constexpr double DEFL_RES_TOL = 1e-2;
+
 template <typename T>
 int build_deflation(const CoarseGeom& c, hdcr_dtype dt, const void* A, const hdcr_deflation_params* p,
-                    const double2* v0, double* theta, C2<T>* Vout, C2<T>* Wout, double* theta_host, void* work,
-                    size_t work_bytes, hipStream_t s) {
+                    const double2* v0, double* theta, C2<T>* Vout, C2<T>* Wout, double* theta_host, int32_t* k_found,
+                    void* work, size_t work_bytes, hipStream_t s) {
+    if (k_found) *k_found = 0;
     const int m = p->m, k = p->k;
     const int64_t n = (int64_t)c.Nc * c.Nb;
     Carver cw(work, work_bytes);
@@ -359,23 +363,44 @@ int build_deflation(const CoarseGeom& c, hdcr_dtype dt, const void* A, const hdc
     Y.assign((size_t)m * m, cd(0.0, 0.0));
     if (herm_eig(m, G.data(), ev.data(), Y.data()) < 0)
         return fail(HDCR_ENAN, "hdcr_build_deflation: Ritz problem of A did not converge");
-    std::vector<int> order(m);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::fabs(ev[a]) < std::fabs(ev[b]); });
-    std::vector<cd> Ysel((size_t)m * k);
-    std::vector<double> th(k);
-    for (int q = 0; q < k; ++q) {
-        th[q] = ev[order[q]];
-        if (!std::isfinite(th[q]) || th[q] == 0.0)
-            return fail(HDCR_ENAN, "hdcr_build_deflation: a kept Ritz value of A is zero or not finite");
-        for (int pp = 0; pp < m; ++pp) Ysel[(size_t)pp * k + q] = Y[(size_t)pp * m + order[q]];
+    // residual of Ritz pair q, y = V Y_q (|y| = 1, A y = W Y_q):
+    // |A y - theta y|^2 = Y_q^dag (W^dag W) Y_q - theta^2, since V^dag W Y_q = theta Y_q
+    std::vector<cd> G2;
+    if ((e = db.gram(Wb, Wb, G2))) return e;
+    std::vector<double> res2(m);
+    for (int q = 0; q < m; ++q) {
+        cd acc(0.0, 0.0);
+        for (int i = 0; i < m; ++i) {
+            cd row(0.0, 0.0);
+            for (int j = 0; j < m; ++j) row += G2[(size_t)i * m + j] * Y[(size_t)j * m + q];
+            acc += std::conj(Y[(size_t)i * m + q]) * row;
+        }
+        res2[q] = acc.real() - ev[q] * ev[q];
     }
-    if ((e = db.rotate(V, Ysel, k, Vout))) return e;
-    if ((e = db.rotate(Wb, Ysel, k, Wout))) return e;
-    HDCR_HIP_CHECK(hipMemcpyAsync(theta, th.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    // the found pairs (residual at most DEFL_RES_TOL |theta|) in ascending |theta|, at most k
+    std::vector<int> order;
+    for (int q = 0; q < m; ++q)
+        if (std::isfinite(ev[q]) && ev[q] != 0.0 && std::isfinite(res2[q]) &&
+            res2[q] <= DEFL_RES_TOL * DEFL_RES_TOL * ev[q] * ev[q])
+            order.push_back(q);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::fabs(ev[a]) < std::fabs(ev[b]); });
+    const int kf = std::min<int>(k, (int)order.size());
+    if (kf == 0)
+        return fail(HDCR_ENOTCONV, "hdcr_build_deflation: no Ritz pair of A reached a residual of " +
+                                       std::to_string(DEFL_RES_TOL) + " |theta| (raise iters, degree or m)");
+    std::vector<cd> Ysel((size_t)m * kf);
+    std::vector<double> th(kf);
+    for (int q = 0; q < kf; ++q) {
+        th[q] = ev[order[q]];
+        for (int pp = 0; pp < m; ++pp) Ysel[(size_t)pp * kf + q] = Y[(size_t)pp * m + order[q]];
+    }
+    if ((e = db.rotate(V, Ysel, kf, Vout))) return e;
+    if ((e = db.rotate(Wb, Ysel, kf, Wout))) return e;
+    HDCR_HIP_CHECK(hipMemcpyAsync(theta, th.data(), kf * sizeof(double), hipMemcpyHostToDevice, s));
     HDCR_HIP_CHECK(hipStreamSynchronize(s));
     if (theta_host)
-        for (int q = 0; q < k; ++q) theta_host[q] = th[q];
+        for (int q = 0; q < kf; ++q) theta_host[q] = th[q];
+    if (k_found) *k_found = kf;
     return HDCR_OK;
 }
 
@@ -471,7 +496,8 @@ size_t hdcr_deflation_workspace_bytes(const hdcr_coarse_desc* desc, hdcr_dtype A
 
 int hdcr_build_deflation(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,
                          const hdcr_deflation_params* params, const void* v0, double* theta, void* V, void* W,
-                         double* theta_host, void* work, size_t work_bytes, hipStream_t stream) {
+                         double* theta_host, int32_t* k_found, void* work, size_t work_bytes, hipStream_t stream) {
+    if (k_found) *k_found = 0;
     if (!desc || !params) return fail(HDCR_EINVAL, "hdcr_build_deflation: null descriptor or params");
     int e = check_coarse_desc(desc);
     if (e) return e;
@@ -491,9 +517,9 @@ int hdcr_build_deflation(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const
         return fail(HDCR_ENOMEM, "hdcr_build_deflation: workspace too small");
     if (A_dtype == HDCR_C128)
         return build_deflation<double>(c, A_dtype, A, params, (const double2*)v0, theta, (double2*)V, (double2*)W,
-                                       theta_host, work, work_bytes, stream);
+                                       theta_host, k_found, work, work_bytes, stream);
     return build_deflation<float>(c, A_dtype, A, params, (const double2*)v0, theta, (float2*)V, (float2*)W, theta_host,
-                                  work, work_bytes, stream);
+                                  k_found, work, work_bytes, stream);
 }
 
 int hdcr_coarse_solve(const hdcr_coarse_desc* desc, hdcr_dtype A_dtype, const void* A,

@@ -86,6 +86,7 @@ def test_deflation_fp64_matches_oracle_and_dense(L, Ls, block, nvec, m, k):
     _, A = _gpu_coarse(lat, U, vecs, hd.C128)
     d = hd.build_deflation(lat, A, hd.C128, to_dev(np.stack(V0)), k, degree=DEG, iters=ITERS, cut=CUT,
                            power_iters=PITERS)
+    assert d.k == k
     th = to_host(d.theta)
     np.testing.assert_array_equal(th, np.array(d.theta_host))
     # ascending |theta|, the k eigenvalues of smallest |lambda|, the oracle's Ritz values
@@ -98,6 +99,34 @@ def test_deflation_fp64_matches_oracle_and_dense(L, Ls, block, nvec, m, k):
         np.testing.assert_allclose(W[i], D @ V[i], atol=1e-12 * anorm)
         assert np.linalg.norm(D @ V[i] - th[i] * V[i]) <= 1e-8 * anorm
         assert abs(abs(np.vdot(V_ref[i].ravel(), V[i])) - 1.0) <= 1e-8
+
+
+def test_deflation_keeps_only_converged_pairs():
+    """A block filtered too little (degree 40, 2 passes, k = m = 12) leaves Ritz pairs of A that
+    are not eigenpairs; the set-up returns only those with |A y - theta y| <= 1e-2 |theta|, fewer
+    than asked for, each within its residual of an eigenvalue of the dense operator, in
+    ascending |theta| (FP64 storage; the oracle applies the same rule)."""
+    torch = torch_dev()
+    L, Ls, block, nvec, m, _ = CASES[0]
+    log(f"deflation, unconverged block L={L} m={m}")
+    p, cs, lat, U, vecs, basis_ref, A_ref = _problem(L, Ls, block, nvec)
+    _, A = _gpu_coarse(lat, U, vecs, hd.C128)
+    D = oracle.coarse_dense(A_ref, cs.cdims)
+    ev = np.linalg.eigvalsh(D)
+    V0 = _v0(cs, m)
+    d = hd.build_deflation(lat, A, hd.C128, to_dev(np.stack(V0)), m, degree=40, iters=2, cut=CUT, power_iters=PITERS)
+    th_ref, _, _ = oracle.coarse_deflation(A_ref, cs.cdims, V0, m, degree=40, iters=2, cut=CUT, power_iters=PITERS)
+    log(f"  found {d.k} of {m} (oracle {len(th_ref)})")
+    assert 0 < d.k < m and abs(d.k - len(th_ref)) <= 1
+    th = np.array(d.theta_host)
+    assert np.all(np.diff(np.abs(th)) >= 0)
+    V = to_host(d.V).reshape(d.k, -1)
+    W = to_host(d.W).reshape(d.k, -1)
+    for q in range(d.k):
+        r = np.linalg.norm(D @ V[q] - th[q] * V[q])
+        assert np.linalg.norm(W[q] - D @ V[q]) <= 1e-12 * np.abs(ev).max()
+        assert r <= 1e-2 * abs(th[q]) * (1 + 1e-6)
+        assert np.min(np.abs(ev - th[q])) <= r * (1 + 1e-9) + 1e-12
 
 
 @pytest.mark.parametrize("L,Ls,block,nvec,m,k", CASES)
@@ -163,7 +192,7 @@ def test_deflation_fp32_storage(dt, case):
     anorm = np.abs(ev).max()
     d = hd.build_deflation(lat, A, code, to_dev(np.stack(_v0(cs, m))), k, degree=DEG, iters=ITERS, cut=CUT,
                            power_iters=PITERS)
-    assert d.V.dtype == torch.complex64
+    assert d.V.dtype == torch.complex64 and d.k == k
     th = to_host(d.theta)
     np.testing.assert_allclose(np.sort(th), np.sort(ev[np.argsort(np.abs(ev))[:k]]), atol=1e-4 * anorm)
     V = to_host(d.V).reshape(k, -1).astype(np.complex128)

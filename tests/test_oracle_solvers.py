@@ -242,6 +242,30 @@ def test_coarse_deflation_matches_dense_eigenpairs():
         assert oracle.norm(w - th * v) <= 1e-7 * anorm
 
 
+def test_coarse_deflation_keeps_only_converged_pairs():
+    """A block filtered too little to be an invariant subspace of A yields Ritz pairs of A that
+    are not eigenpairs; only pairs with residual |A y - theta y| <= 1e-2 |theta| are returned.
+    For a Hermitian matrix every such theta lies within its residual of an eigenvalue (checked
+    against the dense matrix), and more passes find more pairs."""
+    cs, A = _small_coarse()
+    m = 12
+    V0 = [hi.gaussian_coarse(cs.nc, cs.nb, seed=40 + i) for i in range(m)]
+    D = oracle.coarse_dense(A, cs.cdims)
+    ev = np.linalg.eigvalsh(D)
+    found = []
+    for iters in (2, 3):
+        theta, V, W = oracle.coarse_deflation(A, cs.cdims, V0, m, degree=40, iters=iters, cut=0.05)
+        found.append(len(theta))
+        assert np.all(np.diff(np.abs(theta)) >= 0)
+        for th, v, w in zip(theta, V, W):
+            y = v.reshape(-1)
+            r = np.linalg.norm(D @ y - th * y)
+            assert abs(np.linalg.norm(y) - 1.0) <= 1e-12
+            assert r <= oracle.DEFL_RES_TOL * abs(th) * (1 + 1e-9)
+            assert np.min(np.abs(ev - th)) <= r * (1 + 1e-9) + 1e-12
+    assert 0 < found[0] < found[1] < m
+
+
 def test_deflated_coarse_cr():
     """The Galerkin start leaves a residual orthogonal to the deflation space; the deflated
     solve reaches the same solution in no more iterations."""
