@@ -184,7 +184,7 @@ def test_deflation_argument_validation_before_launch(lib):
     b = lib.hdcr_build_deflation
 
     def call(dt=_abi.C128, prm=p, V_=V, W_=W, nbytes=ws):
-        return b(ctypes.byref(cd), dt, A, ctypes.byref(prm), v0, th, V_, W_, None, work, nbytes, None)
+        return b(ctypes.byref(cd), dt, A, ctypes.byref(prm), v0, th, V_, W_, None, None, work, nbytes, None)
 
     for bad in [_abi.DeflationParams(9, 8, 10, 2, 10, 0, 0.05),   # k > m
                 _abi.DeflationParams(4, 65, 10, 2, 10, 0, 0.05),  # m above the maximum
