@@ -1841,8 +1841,10 @@ __device__ __forceinline__ void split_bf16c(float2 x, uint32_t (&w)[T]) {
 // passes of 16 right-hand sides, so each block goes through LDS and into the
 // A-operand registers once per chunk of 16 NP right-hand sides (NP <= 4; one
 // FP32 accumulator tile per pass), instead of once per pass; the blocks stay in
-// registers across chunks.  The vectors of direction d + 1 are requested before
-// the products of direction d.  Every load and store is a raw buffer access
+// registers across chunks.  With three or four passes per chunk the vectors
+// are requested three (chunk, direction) steps ahead of their use, across chunk
+// boundaries, so that the products of three directions cover their latency;
+// with fewer, one direction ahead.  Every load and store is a raw buffer access
 // whose range ends at the chunk's last right-hand side, so the rows of a
 // partial last pass read zero and their results are dropped, with no test in
 // the kernel.  TERMS
@@ -1871,31 +1873,49 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
 #pragma unroll
     for (int d = 0; d < 9; ++d) nbr[d] = coarse_nbr(c, a, d);
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (size_t)a * 9 * NB * NB, 9u * NB * NB * 4u);
+    // work-item's vector pair: row 16 p + vr of pass p, complex entries 2 kp, 2 kp + 1
+    const int vr = threadIdx.x / (NB / 2), kp = threadIdx.x % (NB / 2);
+    // with three or four passes per chunk the vectors of the (chunk, direction)
+    // steps are requested AH = 3 steps ahead, across chunk boundaries, into a
+    // ring of AH register sets (AH divides 9, so a direction always uses the
+    // same set); with fewer passes, where the blocks' stream dominates, one
+    // direction ahead within the chunk
+    constexpr int AH = NP >= 3 ? 3 : 1;
+    const int nch = (nrhs + RPC - 1) / RPC;
+    auto vrsrc = [&](int ch) {
+        const size_t chunk = (size_t)ch * RPC * c.Nc * NB;
+        return make_rsrc(v + chunk, (uint32_t)((size_t)min(RPC, nrhs - ch * RPC) * c.Nc * NB * 8));
+    };
+    float4 vx[AH][NP];
+    auto load_dir = [&](__amdgpu_buffer_rsrc_t rv, int slot, int nd) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            vx[slot][p] = __builtin_bit_cast(
+                    float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                rv, (((uint32_t)(16 * p + vr) * c.Nc + nd) * NB + 2 * kp) * 8u, 0, 0));
+    };
     u32x4 pre[9][NA4];
 #pragma unroll
     for (int d = 0; d < 9; ++d)
 #pragma unroll
         for (int u = 0; u < NA4; ++u)
             pre[d][u] = __builtin_amdgcn_raw_buffer_load_b128(ra, (d * NB * NB + 4 * (threadIdx.x + u * NT)) * 4u, 0, 0);
-    // work-item's vector pair: row 16 p + vr of pass p, complex entries 2 kp, 2 kp + 1
-    const int vr = threadIdx.x / (NB / 2), kp = threadIdx.x % (NB / 2);
-    for (int r0 = 0; r0 < nrhs; r0 += RPC) {
-        const int nr = min(RPC, nrhs - r0);
-        const size_t chunk = (size_t)r0 * c.Nc * NB;
-        const uint32_t bytes = (uint32_t)((size_t)nr * c.Nc * NB * 8);
-        const __amdgpu_buffer_rsrc_t rv = make_rsrc(v + chunk, bytes), ro = make_rsrc(out + chunk, bytes);
-        float4 vx[NP];
-        auto load_dir = [&](int nd) {
+    if constexpr (AH > 1) {
+        const __amdgpu_buffer_rsrc_t rv0 = vrsrc(0);
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
-                vx[p] = __builtin_bit_cast(
-                        float4, __builtin_amdgcn_raw_buffer_load_b128(
-                                    rv, (((uint32_t)(16 * p + vr) * c.Nc + nd) * NB + 2 * kp) * 8u, 0, 0));
-        };
+        for (int d = 0; d < AH; ++d) load_dir(rv0, d, nbr[d]);
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+        const int r0 = ch * RPC;
+        const size_t chunk = (size_t)r0 * c.Nc * NB;
+        const __amdgpu_buffer_rsrc_t rv = vrsrc(ch);
+        const __amdgpu_buffer_rsrc_t rvn = ch + 1 < nch ? vrsrc(ch + 1) : rv;
+        const __amdgpu_buffer_rsrc_t ro =
+                make_rsrc(out + chunk, (uint32_t)((size_t)min(RPC, nrhs - r0) * c.Nc * NB * 8));
         f32x4 acc[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) acc[p] = f32x4{0, 0, 0, 0};
-        load_dir(nbr[0]);
+        if constexpr (AH == 1) load_dir(rv, 0, nbr[0]);
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
             __syncthreads();  // the previous direction's operands have been read
@@ -1907,13 +1927,17 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 uint32_t w0[TERMS], w1[TERMS];
-                split_bf16c<TERMS>(make_float2(vx[p].x, vx[p].y), w0);
-                split_bf16c<TERMS>(make_float2(vx[p].z, vx[p].w), w1);
+                split_bf16c<TERMS>(make_float2(vx[d % AH][p].x, vx[d % AH][p].y), w0);
+                split_bf16c<TERMS>(make_float2(vx[d % AH][p].z, vx[d % AH][p].w), w1);
 #pragma unroll
                 for (int t = 0; t < TERMS; ++t)
                     *reinterpret_cast<uint2*>(vb + (t * RPC + 16 * p + vr) * VST + 2 * kp) = make_uint2(w0[t], w1[t]);
             }
-            if (d < 8) load_dir(nbr[d < 8 ? d + 1 : 0]);  // in flight during this direction's products
+            // in flight during the next AH directions' products
+            if (d + AH < 9)
+                load_dir(rv, d % AH, nbr[d + AH < 9 ? d + AH : 0]);
+            else if (AH > 1 && ch + 1 < nch)
+                load_dir(rvn, d % AH, nbr[d + AH >= 9 ? d + AH - 9 : 0]);
             __syncthreads();
             u32x4 aw[NB / 16];
 #pragma unroll
