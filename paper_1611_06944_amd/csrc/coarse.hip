@@ -1841,10 +1841,12 @@ __device__ __forceinline__ void split_bf16c(float2 x, uint32_t (&w)[T]) {
 // passes of 16 right-hand sides, so each block goes through LDS and into the
 // A-operand registers once per chunk of 16 NP right-hand sides (NP <= 4; one
 // FP32 accumulator tile per pass), instead of once per pass; the blocks stay in
-// registers across chunks.  With three or four passes per chunk the vectors
-// are requested three (chunk, direction) steps ahead of their use, across chunk
-// boundaries, so that the products of three directions cover their latency;
-// with fewer, one direction ahead.  Every load and store is a raw buffer access
+// registers across chunks.  With three or four passes per chunk the staging
+// is double-buffered (the next step is written while the current one is read,
+// one barrier per step) and the vectors are requested three (chunk, direction)
+// steps ahead, across chunk boundaries; with fewer passes, where the stream of
+// the blocks dominates, one buffer and one direction ahead.  Every load and
+// store is a raw buffer access
 // whose range ends at the chunk's last right-hand side, so the rows of a
 // partial last pass read zero and their results are dropped, with no test in
 // the kernel.  TERMS
@@ -1858,10 +1860,13 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
                                                                 float2* __restrict__ out, int nrhs) {
     constexpr int NT = 8 * NB, VST = NB + 4, RPC = 16 * NP;  // work-items, LDS row stride, rows per chunk
     constexpr int NA4 = NB * NB / 4 / NT;                     // 16-byte block loads per work-item and block
+    constexpr int ABW = NB * VST, BUFW = ABW + TERMS * RPC * VST;  // words: one block; one staging buffer
     static_assert(NA4 * 4 * NT == NB * NB, "block loads must tile the block");
+    // staging buffers [block NB x VST][TERMS][RPC][VST] (two at three or more
+    // passes: step g (chunk, direction) is read from buffer g & 1 while step
+    // g + 1 is written to the other)
     extern __shared__ unsigned char smem_raw[];
-    uint32_t* ab = reinterpret_cast<uint32_t*>(smem_raw);  // [NB][VST] one block
-    uint32_t* vb = ab + NB * VST;                           // [TERMS][RPC][VST] bf16 terms of one direction's vectors
+    uint32_t* const sbuf = reinterpret_cast<uint32_t*>(smem_raw);
     const int a = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1875,12 +1880,14 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (size_t)a * 9 * NB * NB, 9u * NB * NB * 4u);
     // work-item's vector pair: row 16 p + vr of pass p, complex entries 2 kp, 2 kp + 1
     const int vr = threadIdx.x / (NB / 2), kp = threadIdx.x % (NB / 2);
-    // with three or four passes per chunk the vectors of the (chunk, direction)
-    // steps are requested AH = 3 steps ahead, across chunk boundaries, into a
-    // ring of AH register sets (AH divides 9, so a direction always uses the
-    // same set); with fewer passes, where the blocks' stream dominates, one
-    // direction ahead within the chunk
-    constexpr int AH = NP >= 3 ? 3 : 1;
+    // DB (three or four passes per chunk): two staging buffers, one barrier per
+    // step; the vectors of step g are requested AH = 3 steps before it is
+    // staged, across chunk boundaries, into a ring of AH register sets (AH
+    // divides 9, so a direction always uses the same set).  Otherwise (the
+    // stream of the blocks dominates): one buffer, staged and then read, the
+    // vectors one direction ahead within the chunk.
+    constexpr bool DB = NP >= 3;
+    constexpr int AH = DB ? 3 : 1;
     const int nch = (nrhs + RPC - 1) / RPC;
     auto vrsrc = [&](int ch) {
         const size_t chunk = (size_t)ch * RPC * c.Nc * NB;
@@ -1900,65 +1907,96 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
 #pragma unroll
         for (int u = 0; u < NA4; ++u)
             pre[d][u] = __builtin_amdgcn_raw_buffer_load_b128(ra, (d * NB * NB + 4 * (threadIdx.x + u * NT)) * 4u, 0, 0);
-    if constexpr (AH > 1) {
+    // block d and the bf16 terms of ring set d % AH into staging buffer b
+    auto stage = [&](int b, const u32x4 (&blk)[NA4], const float4 (&x)[NP]) {
+        uint32_t* const ab = sbuf + b * BUFW;
+        uint32_t* const vb = ab + ABW;
+#pragma unroll
+        for (int u = 0; u < NA4; ++u) {
+            const int e = 4 * (threadIdx.x + u * NT);
+            *reinterpret_cast<u32x4*>(ab + (e / NB) * VST + e % NB) = blk[u];
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            uint32_t w0[TERMS], w1[TERMS];
+            split_bf16c<TERMS>(make_float2(x[p].x, x[p].y), w0);
+            split_bf16c<TERMS>(make_float2(x[p].z, x[p].w), w1);
+#pragma unroll
+            for (int t = 0; t < TERMS; ++t)
+                *reinterpret_cast<uint2*>(vb + (t * RPC + 16 * p + vr) * VST + 2 * kp) = make_uint2(w0[t], w1[t]);
+        }
+    };
+    // products of one step from staging buffer b into acc
+    auto products = [&](int b, f32x4 (&acc)[NP]) {
+        const uint32_t* const ab = sbuf + b * BUFW;
+        const uint32_t* const vb = ab + ABW;
+        u32x4 aw[NB / 16];
+#pragma unroll
+        for (int ks = 0; ks < NB / 16; ++ks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t w = ab[(16 * ks + 4 * kq + q) * VST + j];
+                aw[ks][q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+            }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int ks = 0; ks < NB / 16; ++ks)
+#pragma unroll
+                for (int t = 0; t < TERMS; ++t) {
+                    const u32x4 bw =
+                        *reinterpret_cast<const u32x4*>(vb + (t * RPC + 16 * p + col) * VST + 16 * ks + 4 * kq);
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aw[ks]),
+                                                                     __builtin_bit_cast(bf16x8, bw), acc[p], 0, 0, 0);
+                }
+    };
+    if constexpr (DB) {
         const __amdgpu_buffer_rsrc_t rv0 = vrsrc(0);
 #pragma unroll
         for (int d = 0; d < AH; ++d) load_dir(rv0, d, nbr[d]);
+        stage(0, pre[0], vx[0]);
+        load_dir(rv0, 0, nbr[AH]);  // step AH, into the set just staged
+        __syncthreads();
     }
     for (int ch = 0; ch < nch; ++ch) {
         const int r0 = ch * RPC;
         const size_t chunk = (size_t)r0 * c.Nc * NB;
         const __amdgpu_buffer_rsrc_t rv = vrsrc(ch);
-        const __amdgpu_buffer_rsrc_t rvn = ch + 1 < nch ? vrsrc(ch + 1) : rv;
+        const bool more = ch + 1 < nch;
+        const __amdgpu_buffer_rsrc_t rvn = more ? vrsrc(ch + 1) : rv;
         const __amdgpu_buffer_rsrc_t ro =
                 make_rsrc(out + chunk, (uint32_t)((size_t)min(RPC, nrhs - r0) * c.Nc * NB * 8));
         f32x4 acc[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) acc[p] = f32x4{0, 0, 0, 0};
-        if constexpr (AH == 1) load_dir(rv, 0, nbr[0]);
+        if constexpr (!DB) load_dir(rv, 0, nbr[0]);
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
-            __syncthreads();  // the previous direction's operands have been read
-#pragma unroll
-            for (int u = 0; u < NA4; ++u) {
-                const int e = 4 * (threadIdx.x + u * NT);
-                *reinterpret_cast<u32x4*>(ab + (e / NB) * VST + e % NB) = pre[d][u];
-            }
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                uint32_t w0[TERMS], w1[TERMS];
-                split_bf16c<TERMS>(make_float2(vx[d % AH][p].x, vx[d % AH][p].y), w0);
-                split_bf16c<TERMS>(make_float2(vx[d % AH][p].z, vx[d % AH][p].w), w1);
-#pragma unroll
-                for (int t = 0; t < TERMS; ++t)
-                    *reinterpret_cast<uint2*>(vb + (t * RPC + 16 * p + vr) * VST + 2 * kp) = make_uint2(w0[t], w1[t]);
-            }
-            // in flight during the next AH directions' products
-            if (d + AH < 9)
-                load_dir(rv, d % AH, nbr[d + AH < 9 ? d + AH : 0]);
-            else if (AH > 1 && ch + 1 < nch)
-                load_dir(rvn, d % AH, nbr[d + AH >= 9 ? d + AH - 9 : 0]);
-            __syncthreads();
-            u32x4 aw[NB / 16];
-#pragma unroll
-            for (int ks = 0; ks < NB / 16; ++ks)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t w = ab[(16 * ks + 4 * kq + q) * VST + j];
-                    aw[ks][q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+            if constexpr (DB) {
+                const int cur = (ch + d) & 1;  // buffer of step 9 ch + d
+                // stage step g + 1 into the other buffer, then request the
+                // vectors of step g + 1 + AH into the ring set it used
+                const int dn = d < 8 ? d + 1 : 0;  // direction of step g + 1
+                const int dl = dn + AH;            // direction of step g + 1 + AH, counted from step g + 1's chunk
+                if (d < 8) {
+                    stage(cur ^ 1, pre[dn], vx[dn % AH]);
+                    if (dl < 9)
+                        load_dir(rv, dn % AH, nbr[dl < 9 ? dl : 0]);
+                    else if (more)
+                        load_dir(rvn, dn % AH, nbr[dl >= 9 ? dl - 9 : 0]);
+                } else if (more) {
+                    stage(cur ^ 1, pre[0], vx[0]);
+                    load_dir(rvn, 0, nbr[AH]);  // step g + 1 + AH: direction AH of chunk ch + 1
                 }
-#pragma unroll
-            for (int p = 0; p < NP; ++p)
-#pragma unroll
-                for (int ks = 0; ks < NB / 16; ++ks)
-#pragma unroll
-                    for (int t = 0; t < TERMS; ++t) {
-                        const u32x4 bw =
-                            *reinterpret_cast<const u32x4*>(vb + (t * RPC + 16 * p + col) * VST + 16 * ks + 4 * kq);
-                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aw[ks]),
-                                                                         __builtin_bit_cast(bf16x8, bw), acc[p], 0, 0,
-                                                                         0);
-                    }
+                products(cur, acc);
+                __syncthreads();  // step g read; step g + 1 staged
+            } else {
+                __syncthreads();  // the previous direction's operands have been read
+                stage(0, pre[d], vx[0]);
+                if (d < 8) load_dir(rv, 0, nbr[d < 8 ? d + 1 : 0]);  // in flight during this direction's products
+                __syncthreads();
+                products(0, acc);
+            }
         }
         // lane holds complex rows j0, j0 + 1 of right-hand side 16 p + col; rows
         // past the chunk's last right-hand side fall outside ro and are dropped
@@ -1973,7 +2011,7 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
 template <int TERMS, int NP>
 void rs_launch(const CoarseGeom& c, const uint32_t* A, const float2* v, float2* out, int nrhs, hipStream_t s) {
     constexpr int NB = RS_NB;
-    const size_t lds = (size_t)NB * (NB + 4) * 4 + (size_t)TERMS * 16 * NP * (NB + 4) * 4;
+    const size_t lds = (NP >= 3 ? 2 : 1) * ((size_t)NB * (NB + 4) * 4 + (size_t)TERMS * 16 * NP * (NB + 4) * 4);
     // per instantiation and device: raise the dynamic LDS limit once (setting
     // it twice from racing threads is harmless)
     static std::atomic<unsigned long long> attr_devices{0};
