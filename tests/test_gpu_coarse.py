@@ -167,7 +167,7 @@ def test_batched_coarse_apply_mfma(L, block, nvec, nrhs):
     assert np.array_equal(to_host(hd.apply_coarse_batched(lat, Ab, vd)), outs[0])
 
 
-@pytest.mark.parametrize("nrhs", [1, 12, 40, 96, 101])
+@pytest.mark.parametrize("nrhs", [1, 12, 40, 96, 101, 150])
 def test_batched_coarse_apply_split_terms(nrhs):
     """The batched apply at the 16^4 x 16 multi-RHS shape (coarse 4^4 from 4^4 blocks,
     Nb = 64, BF16 A) with complex64 right-hand sides carried as 3 bf16 terms: every
@@ -178,8 +178,9 @@ def test_batched_coarse_apply_split_terms(nrhs):
     the oracle's FP64 apply of the stored bf16 A to the complex64 vectors.  In norm it
     must meet the FP32 target 1e-5 and beat the one-term (bf16-rounded) result by
     100x; two terms carry each component to within 2^-16 of its value.  Chunks of
-    48 or 64 right-hand sides with a partial last pass (40, 101) and the one-term
-    identity with variant 8 are covered."""
+    48 or 64 right-hand sides with a partial last pass (40, 101), one to three
+    chunks (150: 64 + 64 + 22, the double-buffered staging across two chunk
+    boundaries) and the one-term identity with variant 8 are covered."""
     torch = torch_dev()
     L, block, nvec = (16, 16, 16, 16), (4, 4, 4, 4), 32
     log(f"batched coarse apply, split terms, L={L} nvec={nvec} nrhs={nrhs}")
