@@ -1881,13 +1881,14 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
     // work-item's vector pair: row 16 p + vr of pass p, complex entries 2 kp, 2 kp + 1
     const int vr = threadIdx.x / (NB / 2), kp = threadIdx.x % (NB / 2);
     // DB (three or four passes per chunk): two staging buffers, one barrier per
-    // step; the vectors of step g are requested AH = 3 steps before it is
-    // staged, across chunk boundaries, into a ring of AH register sets (AH
-    // divides 9, so a direction always uses the same set).  Otherwise (the
+    // step; the vectors of step g are requested AH = 3 steps (1 with B22) before
+    // it is staged, across chunk boundaries, into a ring of AH register sets
+    // (AH divides 9, so a direction always uses the same set).  Otherwise (the
     // stream of the blocks dominates): one buffer, staged and then read, the
     // vectors one direction ahead within the chunk.
     constexpr bool DB = NP >= 3;
-    constexpr int AH = DB ? 3 : 1;
+    constexpr bool B22 = NP == 4 && TERMS > 1;  // 2 x 2 tile blocks per wave (products below)
+    constexpr int AH = DB && !B22 ? 3 : 1;
     const int nch = (nrhs + RPC - 1) / RPC;
     auto vrsrc = [&](int ch) {
         const size_t chunk = (size_t)ch * RPC * c.Nc * NB;
@@ -1926,10 +1927,47 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
                 *reinterpret_cast<uint2*>(vb + (t * RPC + 16 * p + vr) * VST + 2 * kp) = make_uint2(w0[t], w1[t]);
         }
     };
-    // products of one step from staging buffer b into acc
+    // products of one step from staging buffer b into acc.  B22 (four passes of
+    // split vectors): each wave takes a 2 x 2 block of (row tile, pass) tiles,
+    // rows 2 rp, 2 rp + 1 and passes 2 pp, 2 pp + 1 (acc[2 r + i]), so that it
+    // reads half the staged vectors and two row slices of the block (a fifth
+    // less LDS reading than one row tile by four passes; the vectors then go
+    // one step ahead, for registers); otherwise row tile `wave` by every pass.
+    // Either way each output takes the same products in the same order.
     auto products = [&](int b, f32x4 (&acc)[NP]) {
         const uint32_t* const ab = sbuf + b * BUFW;
         const uint32_t* const vb = ab + ABW;
+        if constexpr (B22) {
+            const int rp = wave & 3, pp = wave >> 2;
+            // one k-slice at a time, so that only its operands are live
+#pragma unroll
+            for (int ks = 0; ks < NB / 16; ++ks) {
+                u32x4 aw2[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int jr = (16 * (2 * rp + r) + col) >> 1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t w = ab[(16 * ks + 4 * kq + q) * VST + jr];
+                        aw2[r][q] = __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int t = 0; t < TERMS; ++t) {
+                        const u32x4 bw = *reinterpret_cast<const u32x4*>(
+                                vb + (t * RPC + 16 * (2 * pp + i) + col) * VST + 16 * ks + 4 * kq);
+#pragma unroll
+                        for (int r = 0; r < 2; ++r)
+                            acc[2 * r + i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    __builtin_bit_cast(bf16x8, aw2[r]), __builtin_bit_cast(bf16x8, bw),
+                                    acc[2 * r + i], 0, 0, 0);
+                    }
+                __builtin_amdgcn_sched_barrier(0);  // keeps the next slice's reads from being hoisted (spills)
+            }
+            return;
+        }
         u32x4 aw[NB / 16];
 #pragma unroll
         for (int ks = 0; ks < NB / 16; ++ks)
@@ -2000,11 +2038,14 @@ __global__ void __launch_bounds__(8 * NB) coarse_mfma_rs_kernel(CoarseGeom c, co
         }
         // lane holds complex rows j0, j0 + 1 of right-hand side 16 p + col; rows
         // past the chunk's last right-hand side fall outside ro and are dropped
-        const int j0 = 8 * wave + 2 * kq;
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-            store_b128<0>(__builtin_bit_cast(u32x4, acc[p]), ro, (((uint32_t)(16 * p + col) * c.Nc + a) * NB + j0) * 8u,
+        for (int e = 0; e < NP; ++e) {
+            const int rt = B22 ? 2 * (wave & 3) + e / 2 : wave;  // row tile
+            const int p = B22 ? 2 * (wave >> 2) + e % 2 : e;      // pass
+            const int j0 = 8 * rt + 2 * kq;
+            store_b128<0>(__builtin_bit_cast(u32x4, acc[e]), ro, (((uint32_t)(16 * p + col) * c.Nc + a) * NB + j0) * 8u,
                           0u);
+        }
     }
 }
 
