@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
     wg_sum<T, RKG>(acc, sh);
 #pragma unroll
     for (int q = 0; q < RKG; ++q)
-        if (threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
+        if ((int)threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
 // psi = y + P v for coarse site a (one workgroup).  A work-item handles NI
@@ -625,7 +625,6 @@ __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __r
 // ---------------------------------------------------------------------------
 
 template <typename T, typename S> __device__ __forceinline__ C2<T> ldA(const S* A, size_t idx);
-template <> __device__ __forceinline__ double2 ldA<double, double2>(const double2* A, size_t idx) { return A[idx]; }
 template <> __device__ __forceinline__ float2 ldA<float, float2>(const float2* A, size_t idx) { return A[idx]; }
 template <> __device__ __forceinline__ float2 ldA<float, uint32_t>(const uint32_t* A, size_t idx) {
     const uint32_t w = A[idx];  // (bf16 re, bf16 im)
@@ -933,7 +932,8 @@ template <typename T, typename S, int E, bool FIRST>
 __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* __restrict__ A,
                                                         const C2<T>* __restrict__ r, C2<T>* __restrict__ Ar,
                                                         C2<T>* __restrict__ p, C2<T>* __restrict__ Ap, double* part,
-                                                        double* cs, int* flags) {
+                                                        double* /* cs: the scalars are read by the update kernels */,
+                                                        int* flags) {
     if (flags[0]) return;
     extern __shared__ unsigned char smem_raw[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
