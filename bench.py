@@ -24,7 +24,8 @@ The printed value is the achieved algorithmic bandwidth of the FP32 fine apply
 (the dominant kernel of the HDCR solve): bytes = (2 * 12 * N5 spinor entries +
 36 * V4 link entries) * 8, i.e. psi read once, written once, links once.
 Further sections: the project's copy-kernel ceiling, the deflated and
-FP16-smoother solves, the continued-fraction overlap operator, the batched
+FP16-smoother solves, restriction, prolongation and the single-RHS coarse apply
+at the solve's shape, the continued-fraction overlap operator, the batched
 coarse apply on the matrix cores, the fermion force and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -77,6 +78,9 @@ def parse():
     ap.add_argument("--coarse-multi-only", action="store_true",
                     help="only the batched coarse apply sweep (profiling runs)")
     ap.add_argument("--cf-only", action="store_true", help="only the continued-fraction operator (profiling runs)")
+    ap.add_argument("--basis-only", action="store_true",
+                    help="only restriction, prolongation and the single-RHS coarse apply at the solve's shape, on "
+                         "a constant-filled basis and a random A (profiling runs)")
     ap.add_argument("--defl-k", type=int, default=48, help="coarse deflation: eigenpairs kept (0: skip)")
     ap.add_argument("--defl-m", type=int, default=64, help="coarse deflation: block size of the set-up")
     ap.add_argument("--defl-degree", type=int, default=60)
@@ -260,6 +264,37 @@ def timed_launches(torch, fn, n=20):
     return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
 
 
+def basis_section(hd, torch, lat, basis, A):
+    """Restriction and prolongation of the two-level cycle (the whole basis streamed per call) and
+    the single-RHS BF16 coarse apply of the coarse CR, at the solve's shape, each timed with HIP
+    events over 20 launches: P^dag psi with the FP16 basis copy (the solve's choice) and with the
+    FP32 one, P v with the FP16 copy, and A v.  Algorithmic bytes: the basis copy read once, psi
+    read (restriction) or written (prolongation) once; A read once for the coarse apply."""
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(51)
+    psi = torch.randn(lat.fshape, dtype=torch.complex64, device=dev, generator=gen)
+    vc = torch.randn((lat.nc, lat.nb), dtype=torch.complex64, device=dev, generator=gen)
+    outc = torch.empty_like(vc)
+    outf = torch.empty_like(psi)
+    f32 = 12 * lat.N5 * 8
+    b16, b32 = lat.nvec * 12 * lat.N5 * 4, lat.nvec * 12 * lat.N5 * 8
+    a_bytes = hd.coarse_bytes(lat, hd.BF16C)
+    res = {"workload": f"{'x'.join(map(str, lat.L))}x{lat.Ls}, blocks {'x'.join(map(str, lat.block))}, "
+                       f"Nb={lat.nb}, coarse {lat.nc} sites"}
+    cases = (("restrict_f16_basis", lambda: hd.restrict(lat, basis, psi, out=outc, half_basis=True), b16 + f32),
+             ("restrict_f32_basis", lambda: hd.restrict(lat, basis, psi, out=outc), b32 + f32),
+             ("prolong_f16_basis", lambda: hd.prolong(lat, basis, vc, out=outf, half_basis=True), b16 + f32),
+             ("coarse_apply_bf16", lambda: hd.apply_coarse(lat, A, hd.BF16C, vc, outc), a_bytes))
+    for name, fn, nbytes in cases:
+        ms = timed_launches(torch, fn)
+        res[name] = {"us": round(ms * 1e3, 1), "bytes_per_launch": nbytes,
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del psi, vc, outc, outf
+    return res
+
+
 def cf_section(hd, hi, torch):
     """The continued-fraction overlap operator (Sec. 3) at 24^4 with 8 pole slices (Ls = 9) and
     with 15 (Ls = 16): the seeded links, Gaussian field, beta_i spaced evenly in [0.5, 2], R = 0.3.
@@ -415,6 +450,16 @@ def main():
         return
     if args.cf_only:
         print(json.dumps({"cf_overlap": cf_section(hd, hi, torch)}), flush=True)
+        return
+    if args.basis_only:
+        latb = hd.Lattice(tuple(args.L), args.Ls, M5=1.8, mf=0.01, block=tuple(args.block), nvec=args.nvec)
+        bas = torch.full((hd.basis_bytes(latb),), 60, dtype=torch.uint8, device="cuda:0")  # 0x3c3c: small finite values
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(52)
+        raw = torch.randn(hd.coarse_bytes(latb, hd.C128) // 8, dtype=torch.float64, device="cuda:0", generator=gen)
+        Ab = hd.convert_coarse(latb, raw, hd.BF16C)
+        del raw
+        print(json.dumps({"basis_transfer": basis_section(hd, torch, latb, bas, Ab)}), flush=True)
         return
 
     L, Ls = tuple(args.L), args.Ls
@@ -652,6 +697,8 @@ def main():
         out["hdcr_f16_smoother"] = fsec
         progress("HDCR with the FP16-storage smoother measured")
     if not args.fine_only:
+        out["basis_transfer"] = basis_section(hd, torch, lat, basis, A)
+        progress("restriction, prolongation and single-RHS coarse apply measured")
         del basis, A, work_hdcr, work_cr
         defl_space.clear()
         torch.cuda.empty_cache()

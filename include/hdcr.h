@@ -94,8 +94,8 @@ typedef enum {
  *                   fifth-dimension slices per load (1, 2: FP32, even Ls), cross-lane
  *                   sums by DPP (1) or through LDS (2); an unsupported split is
  *                   rejected with HDCR_EINVAL
- *   restrict_w, restrict_rkg  restriction: s slots per work-item (1, 2, 4), vectors
- *                   per workgroup (16, 32)
+ *   restrict_w, restrict_rkg  restriction: s slots per work-item (1, 2, 4, 8; 0: 8
+ *                   with the FP16 basis copy, else 4), vectors per workgroup (16, 32)
  *   prolong_ni      prolongation with the FP16 basis: indices per work-item (2, 4)
  *   wg_per_cu       at most this many workgroups of the parity-tile stencil kernels
  *                   resident per compute unit (enforced through their LDS size; 0 or a

@@ -3,6 +3,7 @@
 // prolongation P, the little Dirac operator A = P^dag H P and its 9-point
 // coarse apply.  Layouts are described in coarse.h.
 #include <algorithm>
+#include <type_traits>
 #include <atomic>
 #include <cmath>
 
@@ -450,12 +451,13 @@ __device__ __forceinline__ float2 dec_h(uint32_t w) {
     return make_float2(re * inv, im * inv);
 }
 template <typename T, int W> __device__ __forceinline__ void ld_basis(const C2<T>* p, C2<T> (&o)[W]) {
-    if constexpr (W == 4) {
-        const Pair<T> q0 = ld_pair<T>(p), q1 = ld_pair<T>(p + 2);
-        o[0] = q0.a;
-        o[1] = q0.b;
-        o[2] = q1.a;
-        o[3] = q1.b;
+    if constexpr (W >= 4) {
+#pragma unroll
+        for (int u = 0; u < W / 2; ++u) {
+            const Pair<T> q = ld_pair<T>(p + 2 * u);
+            o[2 * u] = q.a;
+            o[2 * u + 1] = q.b;
+        }
     } else if constexpr (W == 2) {
         const Pair<T> q = ld_pair<T>(p);
         o[0] = q.a;
@@ -465,12 +467,15 @@ template <typename T, int W> __device__ __forceinline__ void ld_basis(const C2<T
     }
 }
 template <typename T, int W> __device__ __forceinline__ void ld_basis(const uint32_t* p, float2 (&o)[W]) {
-    if constexpr (W == 4) {
-        const uint4 q = *reinterpret_cast<const uint4*>(p);
-        o[0] = dec_h(q.x);
-        o[1] = dec_h(q.y);
-        o[2] = dec_h(q.z);
-        o[3] = dec_h(q.w);
+    if constexpr (W >= 4) {
+#pragma unroll
+        for (int u = 0; u < W / 4; ++u) {
+            const uint4 q = *reinterpret_cast<const uint4*>(p + 4 * u);
+            o[4 * u] = dec_h(q.x);
+            o[4 * u + 1] = dec_h(q.y);
+            o[4 * u + 2] = dec_h(q.z);
+            o[4 * u + 3] = dec_h(q.w);
+        }
     } else if constexpr (W == 2) {
         const uint2 q = *reinterpret_cast<const uint2*>(p);
         o[0] = dec_h(q.x);
@@ -519,17 +524,17 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
             const size_t fb = ((size_t)comp * c.f.V4 + block_site(c, a, sl)) * c.f.Ls;
             // slot s + w pairs with the mirrored Ls-1-s-w
             C2<T> p1[W], p2[W];
-            if constexpr (W == 4) {
-                const Pair<T> a0 = ld_pair<T>(psi + fb + s), a1 = ld_pair<T>(psi + fb + s + 2);
-                const Pair<T> b1 = ld_pair<T>(psi + fb + c.f.Ls - 4 - s), b0 = ld_pair<T>(psi + fb + c.f.Ls - 2 - s);
-                p1[0] = a0.a;
-                p1[1] = a0.b;
-                p1[2] = a1.a;
-                p1[3] = a1.b;
-                p2[0] = b0.b;
-                p2[1] = b0.a;
-                p2[2] = b1.b;
-                p2[3] = b1.a;
+            if constexpr (W >= 4) {
+                // pairs from both ends: slot s + w and its mirror Ls-1-s-w
+#pragma unroll
+                for (int u = 0; u < W / 2; ++u) {
+                    const Pair<T> lo = ld_pair<T>(psi + fb + s + 2 * u);
+                    const Pair<T> hi = ld_pair<T>(psi + fb + c.f.Ls - 2 - s - 2 * u);
+                    p1[2 * u] = lo.a;
+                    p1[2 * u + 1] = lo.b;
+                    p2[2 * u] = hi.b;
+                    p2[2 * u + 1] = hi.a;
+                }
             } else if constexpr (W == 2) {
                 const Pair<T> lo = ld_pair<T>(psi + fb + s), hi = ld_pair<T>(psi + fb + c.f.Ls - 2 - s);
                 p1[0] = lo.a;
@@ -1385,10 +1390,12 @@ void restrict_launch_w(const CoarseGeom& c, const B* basis, const C2<T>* psi, co
 template <typename T, typename B, int RKG>
 void restrict_launch_r(const CoarseGeom& c, int wmax, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v,
                        hipStream_t s) {
-    // W consecutive s slots per work-item: 4 when Ls/2 is a multiple of 4 (16-byte
-    // basis loads in FP16, 16-byte psi pairs in FP32), 2 when it is even, and a
-    // row must fit the workgroup
-    if (wmax >= 4 && c.Lh % 4 == 0 && c.Lh / 4 <= CWG)
+    // W consecutive s slots per work-item: 8 (on request) or 4 when Ls/2 is a
+    // multiple of it (16-byte basis loads in FP16, 16-byte psi pairs in FP32), 2
+    // when it is even, and a row must fit the workgroup
+    if (wmax >= 8 && c.Lh % 8 == 0 && c.Lh / 8 <= CWG)
+        restrict_launch_w<T, B, 8, RKG>(c, basis, psi, psi2, v, s);
+    else if (wmax >= 4 && c.Lh % 4 == 0 && c.Lh / 4 <= CWG)
         restrict_launch_w<T, B, 4, RKG>(c, basis, psi, psi2, v, s);
     else if (wmax >= 2 && c.Lh % 2 == 0 && c.Lh / 2 <= CWG)
         restrict_launch_w<T, B, 2, RKG>(c, basis, psi, psi2, v, s);
@@ -1399,8 +1406,11 @@ void restrict_launch_r(const CoarseGeom& c, int wmax, const B* basis, const C2<T
 template <typename T, typename B>
 void restrict_launch(const CoarseGeom& c, const B* basis, const C2<T>* psi, const C2<T>* psi2, C2<T>* v, hipStream_t s) {
     if (c.Lh > CWG) return;  // not reachable: Ls <= 512 is enforced by the descriptor checks
-    // the caller's shape (tune.restrict_w / restrict_rkg; 0 = 4 slots, 16 vectors)
-    const int wmax = c.f.tune.restrict_w > 0 ? c.f.tune.restrict_w : 4;
+    // the caller's shape (tune.restrict_w / restrict_rkg; 0 = 16 vectors and 8
+    // slots with the FP16 basis copy, 4 with the FP32 and FP64 ones: measured at
+    // 24^4 x 16, Nb = 64, 1.45 against 1.93 ms with the FP16 copy, 2.77 against
+    // 2.69 ms with the FP32 one)
+    const int wmax = c.f.tune.restrict_w > 0 ? c.f.tune.restrict_w : (std::is_same<B, uint32_t>::value ? 8 : 4);
     const int rkg = c.f.tune.restrict_rkg > 0 ? c.f.tune.restrict_rkg : 16;
     if (rkg >= RKG_MAX && c.nvec >= RKG_MAX)
         restrict_launch_r<T, B, RKG_MAX>(c, wmax, basis, psi, psi2, v, s);
