@@ -330,15 +330,17 @@ int vcycle(const CoarseGeom& c, const hdcr_solve_params* prm, const C2<T>* U, co
         cheb_smoother<T>(g, U, in, out, acc, w.sm, order, prm->cheb_lo, prm->cheb_hi, s);
     };
     smooth(r, e, false);
-    launch_dslash<T>(g, U, e, w.t, s);
+    // t = r - H e1 (fused into the stencil's epilogue; the same single rounding
+    // as subtracting H e1 inside the restriction), then P^dag t
+    launch_dslash_epi<T>(g, U, e, w.t, Epi<T>{{r, nullptr, nullptr, nullptr}, {(T)1, 0, 0, 0}, (T)-1, 1}, s);
     tm.begin(PhaseTimer::COARSE);
     if constexpr (sizeof(T) == 4) {
         if (bh)
-            launch_restrict_h(c, bh, r, w.t, w.vc, s);
+            launch_restrict_h(c, bh, w.t, nullptr, w.vc, s);
         else
-            launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+            launch_restrict<T>(c, basis, w.t, nullptr, w.vc, s);
     } else {
-        launch_restrict<T>(c, basis, r, w.t, w.vc, s);
+        launch_restrict<T>(c, basis, w.t, nullptr, w.vc, s);
     }
     int it = 0, reason = 0;
     int st = coarse_cr<T>(c, (hdcr_dtype)prm->coarse_dtype, A, w.vc, w.cx, prm->coarse_maxiter, prm->coarse_tol, w.ccr,
