@@ -477,6 +477,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
     }
     typedef std::complex<double> cd;
     bool true_res = true;  // r is the true residual of x
+    bool rin_ok = false;   // r_in holds r rounded to FP32 (written by the last r update)
     while (status == HDCR_ENOTCONV && it < prm->maxiter) {
         true_res = false;
         // coefficient of the normalised directions zhat_i over the raw Z_j
@@ -489,7 +490,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             int e;
             if constexpr (sizeof(T) == 4) {
                 tm.begin(PhaseTimer::OUTER);
-                launch_convert<double2, float2>(n, w.r, w.r_in, s);
+                if (!rin_ok) launch_convert<double2, float2>(n, w.r, w.r_in, s);
                 e = vcycle<T>(c, prm, Uin, bas, bh, A, defl, w.r_in, w.Z[i], w.cyc, tm, cnt, s);
             } else {
                 e = vcycle<T>(c, prm, Uin, bas, bh, A, defl, w.r, w.Z[i], w.cyc, tm, cnt, s);
@@ -513,7 +514,12 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             PtrList Rl{};
             Rl.p[0] = w.r;
             launch_multidot<double, T>(n, Rl, 1, w.W[i], w.part, w.S + SD3, s);
-            launch_r_update<T>(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
+            if constexpr (sizeof(T) == 4) {
+                launch_r_update<T>(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s, w.r_in);
+                rin_ok = true;  // the next cycle's input, rounded as the conversion would
+            } else {
+                launch_r_update<T>(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
+            }
             launch_finalize_real(w.part, 1, w.S, SRR, -1, -1, -1, s);
             launch_scale_inv_sqrt<T>(n, w.W[i], w.S, SD3 + 2 * MAXV, s);
             tm.end();
@@ -566,6 +572,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
         }
         if (stop) break;
         // true residual at every restart (r then holds b - H x for the current x)
+        rin_ok = false;
         tm.begin(PhaseTimer::OUTER);
         launch_dslash<double>(g, U, x, w.tmp, s);
         ++n64;

@@ -36,10 +36,11 @@ void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const doubl
 // x <- x + sum_j g[j] Z[j]   (g on the host, x FP64)
 template <typename TV>
 void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2* g, double2* x, hipStream_t s);
-// r <- r - ((S[ic] - i S[ic+1]) / S[inn]) w, partial |r|^2 in part[0..REDUCE_BLOCKS)  (r FP64)
+// r <- r - ((S[ic] - i S[ic+1]) / S[inn]) w, partial |r|^2 in part[0..REDUCE_BLOCKS)  (r FP64);
+// r32, if not null, receives r rounded to FP32
 template <typename TV>
 void launch_r_update(int64_t n, const double* S, int ic, int inn, const C2<TV>* w, double2* r, double* part,
-                     hipStream_t s);
+                     hipStream_t s, float2* r32 = nullptr);
 
 // FP16 field storage, (fp16 re, fp16 im) per complex entry: y = fp16(f x) with
 // f = sqrt(n / S[idx]), so that y has unit RMS per entry (f = 0 when S[idx] = 0;

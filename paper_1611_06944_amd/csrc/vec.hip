@@ -188,11 +188,13 @@ __global__ void __launch_bounds__(VWG) multi_update_kernel(int64_t n, PtrListT<T
 }
 
 // r <- r - (conj(c) / nn) w with c = (S[ic], S[ic+1]) = <r, w> and nn = S[inn] = |w|^2
-// (so the step is <w, r>/|w|^2); partial |r|^2.  r FP64, w FP64 or FP32.
+// (so the step is <w, r>/|w|^2); partial |r|^2.  r FP64, w FP64 or FP32; r32, if
+// not null, receives r rounded to FP32 (the inner cycle's copy).
 template <typename TV>
 __global__ void __launch_bounds__(REDUCE_THREADS) r_update_kernel(int64_t n, const double* __restrict__ S, int ic,
                                                                   int inn, const C2<TV>* __restrict__ w,
-                                                                  double2* __restrict__ r, double* __restrict__ part) {
+                                                                  double2* __restrict__ r, double* __restrict__ part,
+                                                                  float2* __restrict__ r32) {
     const double nn = S[inn];
     const double2 a = make_double2(S[ic] / nn, -S[ic + 1] / nn);
     double v[1] = {0.0};
@@ -201,6 +203,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) r_update_kernel(int64_t n, con
         const C2<TV> wt = w[i];
         double2 rv = cfma<double>(cneg<double>(a), make_double2(wt.x, wt.y), r[i]);
         r[i] = rv;
+        if (r32) r32[i] = make_float2((float)rv.x, (float)rv.y);
         v[0] += rv.x * rv.x + rv.y * rv.y;
     }
     block_reduce<1>(v);
@@ -440,9 +443,9 @@ void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2
 
 template <typename TV>
 void launch_r_update(int64_t n, const double* S, int ic, int inn, const C2<TV>* w, double2* r, double* part,
-                     hipStream_t s) {
+                     hipStream_t s, float2* r32) {
     hipLaunchKernelGGL(r_update_kernel<TV>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, S, ic, inn, w, r,
-                       part);
+                       part, r32);
 }
 
 template void launch_multidot<double, double>(int64_t, const PtrListT<double>&, int, const double2*, double*, double*,
@@ -461,7 +464,8 @@ template void launch_multi_update<double>(int64_t, const PtrListT<double>&, int,
                                           hipStream_t);
 template void launch_multi_update<float>(int64_t, const PtrListT<float>&, int, const double2*, double2*, hipStream_t);
 template void launch_r_update<double>(int64_t, const double*, int, int, const double2*, double2*, double*,
-                                      hipStream_t);
-template void launch_r_update<float>(int64_t, const double*, int, int, const float2*, double2*, double*, hipStream_t);
+                                      hipStream_t, float2*);
+template void launch_r_update<float>(int64_t, const double*, int, int, const float2*, double2*, double*, hipStream_t,
+                                     float2*);
 
 }  // namespace hdcr
