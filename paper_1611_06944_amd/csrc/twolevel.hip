@@ -379,13 +379,13 @@ template <typename T> struct FgcrWork {
     double2* r;
     double2* tmp;
     double* part;
-    double* S;        // device scalars: D1 [0,17), D2 [17,34), D3 [34,51), rr 51, bb 52
+    double* S;        // device scalars: D1 [0,17), D2 [17,34), D3 [34,51), rr 51, bb 52, 1/|W_j|^2 [53,61)
     C2<T>* U_in;      // inner-precision links (FP32 copy, or null for FP64)
     C2<T>* r_in;      // r in the inner precision (FP32 cycle only)
     CycleWork<T> cyc;
 };
 constexpr int SD1 = 0, SD2 = 2 * MAXV + 1, SD3 = 2 * (2 * MAXV + 1), SRR = 3 * (2 * MAXV + 1), SBB = SRR + 1,
-              SCOUNT = SBB + 8;
+              SINV = SBB + 1, SCOUNT = SINV + MAXV;
 
 template <typename T> FgcrWork<T> fgcr_carve(Carver& w, const CoarseGeom& c, int m) {
     const size_t n = (size_t)12 * c.f.N5;
@@ -483,6 +483,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
         // coefficient of the normalised directions zhat_i over the raw Z_j
         std::vector<std::vector<cd>> coef;
         std::vector<cd> alpha;
+        std::vector<double> wnorm;  // |W_j| of the stored, unnormalised W_j
         int i = 0;
         bool stop = false;
         for (; i < m && it < prm->maxiter; ++i) {
@@ -497,7 +498,10 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             }
             if (e) return e;
             tm.begin(PhaseTimer::OUTER);
-            // w_i = H z_i, orthogonalised twice against the previous (normalised) w_j
+            // w_i = H z_i, orthogonalised twice against the previous w_j.  The W_j are
+            // kept unnormalised: the projections take the coefficients <W_j, w>
+            // times 1 / |W_j|^2 (S[SINV + j]), and the host divides the same inner
+            // products by |W_j| for the normalised directions of its bookkeeping.
             launch_dslash<T>(g, Uin, w.Z[i], w.W[i], s);
             if (sizeof(T) == 8)
                 ++n64;
@@ -507,10 +511,10 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             for (int j = 0; j < i; ++j) Wl.p[j] = w.W[j];
             if (i > 0) {  // the second pass's inner products ride on the first pass's update
                 launch_multidot<T, T>(n, Wl, i, w.W[i], w.part, w.S + SD1, s);
-                launch_multi_axpy_dot<T>(n, Wl, i, w.S + SD1, w.W[i], w.part, w.S + SD2, s);
-                launch_multi_axpy<T>(n, Wl, i, w.S + SD2, w.W[i], s);
+                launch_multi_axpy_dot<T>(n, Wl, i, w.S + SD1, w.W[i], w.part, w.S + SD2, s, w.S + SINV);
+                launch_multi_axpy<T>(n, Wl, i, w.S + SD2, w.W[i], s, w.S + SINV);
             }
-            // <r, w>, |w|^2; r -= (<w, r>/|w|^2) w; normalise w
+            // <r, w>, |w|^2; r -= (<w, r>/|w|^2) w; 1 / |w|^2 for the later projections
             PtrList Rl{};
             Rl.p[0] = w.r;
             launch_multidot<double, T>(n, Rl, 1, w.W[i], w.part, w.S + SD3, s);
@@ -521,7 +525,7 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
                 launch_r_update<T>(n, w.S, SD3, SD3 + 2 * MAXV, w.W[i], w.r, w.part, s);
             }
             launch_finalize_real(w.part, 1, w.S, SRR, -1, -1, -1, s);
-            launch_scale_inv_sqrt<T>(n, w.W[i], w.S, SD3 + 2 * MAXV, s);
+            launch_inv_copy(w.S, SD3 + 2 * MAXV, SINV + i, s);
             tm.end();
             HDCR_HIP_CHECK(readS());
             ++it;
@@ -543,11 +547,14 @@ int fgcr_solve(const CoarseGeom& c, const hdcr_solve_params* prm, const double2*
             std::vector<cd> ci(m, cd(0, 0));
             ci[i] = cd(1, 0);
             for (int j = 0; j < i; ++j) {
-                const cd beta = cd(hS[SD1 + 2 * j], hS[SD1 + 2 * j + 1]) + cd(hS[SD2 + 2 * j], hS[SD2 + 2 * j + 1]);
+                // <what_j, w> over both passes, what_j = W_j / |W_j|
+                const cd beta =
+                        (cd(hS[SD1 + 2 * j], hS[SD1 + 2 * j + 1]) + cd(hS[SD2 + 2 * j], hS[SD2 + 2 * j + 1])) / wnorm[j];
                 for (int q = 0; q < m; ++q) ci[q] -= beta * coef[j][q];
             }
             for (auto& v : ci) v /= nw;
             coef.push_back(ci);
+            wnorm.push_back(nw);
             // step along zhat_i: <what_i, r> = conj(<r, w_i>) / |w_i|
             alpha.push_back(std::conj(cd(hS[SD3], hS[SD3 + 1])) / nw);
             if (history && hl < hcap) history[hl++] = std::sqrt(rr / bb);

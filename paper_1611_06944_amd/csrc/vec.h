@@ -25,14 +25,15 @@ template <typename T> void launch_scale(int64_t n, T a, const C2<T>* x, C2<T>* o
 template <typename TV, typename TY>
 void launch_multidot(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y, double* part, double* out,
                      hipStream_t s);
-// y <- y - sum_j (coef[2j] + i coef[2j+1]) V[j]
+// y <- y - sum_j (coef[2j] + i coef[2j+1]) sc[j] V[j]   (sc: real scales, null for 1)
 template <typename TV>
-void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s);
-// y <- y - sum_j (coef[2j] + i coef[2j+1]) V[j], then out as launch_multidot(V, y) of the stored
-// result (bitwise the same sums), in one pass over V and y
+void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s,
+                       const double* sc = nullptr);
+// y <- y - sum_j (coef[2j] + i coef[2j+1]) sc[j] V[j], then out as launch_multidot(V, y) of the
+// stored result (bitwise the same sums), in one pass over V and y
 template <typename TV>
 void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, double* part,
-                           double* out, hipStream_t s);
+                           double* out, hipStream_t s, const double* sc = nullptr);
 // x <- x + sum_j g[j] Z[j]   (g on the host, x FP64)
 template <typename TV>
 void launch_multi_update(int64_t n, const PtrListT<TV>& Z, int nz, const double2* g, double2* x, hipStream_t s);
@@ -66,5 +67,7 @@ void launch_h16_to_c128(int64_t n, const void* x, double2* out, hipStream_t s);
 template <typename T> void launch_norm2(int64_t n, const C2<T>* x, double* part, double* S, int idx, hipStream_t s);
 // x <- x / sqrt(S[idx])
 template <typename T> void launch_scale_inv_sqrt(int64_t n, C2<T>* x, const double* S, int idx, hipStream_t s);
+// S[dst] = 1 / S[src] (one work-item)
+void launch_inv_copy(double* S, int src, int dst, hipStream_t s);
 
 }  // namespace hdcr

@@ -103,10 +103,14 @@ __global__ void __launch_bounds__(REDUCE_THREADS) multidot_finalize_kernel(const
 // y <- y - sum_j coef[j] V[j]   (coef: complex, device memory; FP64 arithmetic, one rounding to TV)
 template <typename TV>
 __global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrListT<TV> V, int nv,
-                                                         const double* __restrict__ coef, C2<TV>* __restrict__ y) {
+                                                         const double* __restrict__ coef, C2<TV>* __restrict__ y,
+                                                         const double* __restrict__ sc) {
     double2 cf[MAXV];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j) cf[j] = (j < nv) ? make_double2(coef[2 * j], coef[2 * j + 1]) : make_double2(0, 0);
+    for (int j = 0; j < MAXV; ++j) {
+        const double f = (j < nv && sc) ? sc[j] : 1.0;
+        cf[j] = (j < nv) ? make_double2(f * coef[2 * j], f * coef[2 * j + 1]) : make_double2(0, 0);
+    }
     for (int64_t i = (int64_t)blockIdx.x * VWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * VWG) {
         const C2<TV> yt = y[i];
         double2 yv = make_double2(yt.x, yt.y);
@@ -121,7 +125,7 @@ __global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrListT<TV>
     }
 }
 
-// y <- y - sum_j coef[j] V[j] as multi_axpy_kernel, and the partial sums of
+// y <- y - sum_j coef[j] sc[j] V[j] as multi_axpy_kernel, and the partial sums of
 // <V[j], y> and |y|^2 of the stored result as multidot_kernel: same grid, same
 // index per work-item and same reduction, so the sums are bitwise those of a
 // separate multidot pass over the updated y
@@ -129,10 +133,14 @@ template <typename TV>
 __global__ void __launch_bounds__(REDUCE_THREADS) multi_axpy_dot_kernel(int64_t n, PtrListT<TV> V, int nv,
                                                                         const double* __restrict__ coef,
                                                                         C2<TV>* __restrict__ y,
-                                                                        double* __restrict__ part) {
+                                                                        double* __restrict__ part,
+                                                                        const double* __restrict__ sc) {
     double2 cf[MAXV];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j) cf[j] = (j < nv) ? make_double2(coef[2 * j], coef[2 * j + 1]) : make_double2(0, 0);
+    for (int j = 0; j < MAXV; ++j) {
+        const double f = (j < nv && sc) ? sc[j] : 1.0;
+        cf[j] = (j < nv) ? make_double2(f * coef[2 * j], f * coef[2 * j + 1]) : make_double2(0, 0);
+    }
     double acc[2 * MAXV + 1];
 #pragma unroll
     for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
@@ -421,15 +429,16 @@ void launch_multidot(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y, 
 }
 
 template <typename TV>
-void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s) {
-    hipLaunchKernelGGL(multi_axpy_kernel<TV>, dim3(vgrid(n)), dim3(VWG), 0, s, n, V, nv, coef, y);
+void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, hipStream_t s,
+                       const double* sc) {
+    hipLaunchKernelGGL(multi_axpy_kernel<TV>, dim3(vgrid(n)), dim3(VWG), 0, s, n, V, nv, coef, y, sc);
 }
 
 template <typename TV>
 void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, double* part,
-                           double* out, hipStream_t s) {
+                           double* out, hipStream_t s, const double* sc) {
     hipLaunchKernelGGL(multi_axpy_dot_kernel<TV>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, coef, y,
-                       part);
+                       part, sc);
     hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
                        out);
 }
@@ -448,18 +457,27 @@ void launch_r_update(int64_t n, const double* S, int ic, int inn, const C2<TV>* 
                        part, r32);
 }
 
+__global__ void inv_copy_kernel(double* S, int src, int dst) {
+    if (threadIdx.x == 0) S[dst] = 1.0 / S[src];
+}
+void launch_inv_copy(double* S, int src, int dst, hipStream_t s) {
+    hipLaunchKernelGGL(inv_copy_kernel, dim3(1), dim3(64), 0, s, S, src, dst);
+}
+
 template void launch_multidot<double, double>(int64_t, const PtrListT<double>&, int, const double2*, double*, double*,
                                               hipStream_t);
 template void launch_multidot<float, float>(int64_t, const PtrListT<float>&, int, const float2*, double*, double*,
                                             hipStream_t);
 template void launch_multidot<double, float>(int64_t, const PtrListT<double>&, int, const float2*, double*, double*,
                                              hipStream_t);
-template void launch_multi_axpy<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, hipStream_t);
-template void launch_multi_axpy<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, hipStream_t);
+template void launch_multi_axpy<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, hipStream_t,
+                                        const double*);
+template void launch_multi_axpy<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, hipStream_t,
+                                       const double*);
 template void launch_multi_axpy_dot<double>(int64_t, const PtrListT<double>&, int, const double*, double2*, double*,
-                                            double*, hipStream_t);
+                                            double*, hipStream_t, const double*);
 template void launch_multi_axpy_dot<float>(int64_t, const PtrListT<float>&, int, const double*, float2*, double*,
-                                           double*, hipStream_t);
+                                           double*, hipStream_t, const double*);
 template void launch_multi_update<double>(int64_t, const PtrListT<double>&, int, const double2*, double2*,
                                           hipStream_t);
 template void launch_multi_update<float>(int64_t, const PtrListT<float>&, int, const double2*, double2*, hipStream_t);
