@@ -119,9 +119,10 @@ template <typename T> struct CoarseCRWork {
     C2<T>* p;
     C2<T>* Ar;
     C2<T>* Ap;
-    double* part;   // partial sums: [2][Nc] of the apply, then [2][DEFL_INIT_BLOCKS] of the update and init kernels
-    double* cs;     // scalars: 0 <r,Ar>, 1 <r,Ar> new, 2 |Ap|^2, 3 |r|^2, 4 |b|^2, 5 tol^2
-    int* flags;     // 0 done, 1 iterations, 2 first-apply sums pending, 3 maxiter,
+    double* part;   // partial sums: [3][Nc] of the apply, [2][work-groups] of the start kernels,
+                    // then two halves of [2][CCR_UPDATE_MAX] of the update kernel (even / odd steps)
+    double* cs;     // scalars: 3 |r|^2 of the start, 4 |b|^2, 5 tol^2, 6 / 7 <r,Ar> of the even / odd steps
+    int* flags;     // 0 done, 1 iterations, 2 (unused), 3 maxiter,
                     // 4 stop reason (0 none, 2 near-breakdown, 3 not finite);
                     // CCR_COUNTERS.. arrival counters (CCR_FLAGS ints)
     double* dpart;  // partial sums of the deflated start: [2 * DEFL_KMAX][DEFL_BLOCKS]
@@ -138,7 +139,8 @@ template <typename T> struct DeflView {
     const C2<T>* V;
     const C2<T>* W;
 };
-constexpr int CCR_BLOCKS = 64;
+constexpr int CCR_BLOCKS = 64;        // work-groups of the start kernel
+constexpr int CCR_UPDATE_MAX = 512;   // most work-groups of the update kernel (one element per work-item below it)
 constexpr int ARRIVE_GROUPS = 16;   // group counters of the last-arrival test
 constexpr int ARRIVE_STRIDE = 64;   // ints between counters (each counter on its own 256-byte line)
 constexpr int CCR_COUNTERS = 64;    // first arrival counter in flags
@@ -155,11 +157,11 @@ void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const Coarse
 template <typename T>
 void launch_ccr_init_defl(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const CoarseCRWork<T>& w,
                           const DeflView<T>& d, int maxiter, double tol, hipStream_t s);
-// one CR iteration (x, r update; Ar = A r; p, Ap update); first = true issues
-// the start-up step (p = r, Ap = A r) instead
+// CR step `step` (1, 2, ...: the p, x and r updates of step `step`, then
+// Ar = A r for the next one); step 0 issues the first apply Ar = A r instead
 template <typename T>
 void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
-                     bool first, hipStream_t s);
+                     int step, hipStream_t s);
 
 // little Dirac operator build: A64[a][d][k][j] for basis vectors in [k0, k0+nk),
 // nk <= 4, given the class-split fine fields Y[(kk*9 + d)] = H^(d) Phi_{k0+kk}

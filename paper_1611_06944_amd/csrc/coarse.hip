@@ -792,6 +792,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int np, double 
     double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v[q] += part[(size_t)q * np + i];
@@ -835,7 +836,6 @@ __global__ void __launch_bounds__(CWG) ccr_init_kernel(int n, const C2<T>* __res
             cs[3] = s[0];
             cs[5] = tol2;
             flags[3] = maxiter;
-            flags[2] = 1;  // the sums of the first apply are still to be reduced
             flags[1] = 0;
             flags[4] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0])) ? 1 : 0;
@@ -923,7 +923,6 @@ __global__ void __launch_bounds__(CWG) ccr_init_defl_kernel(int n, const C2<T>* 
             cs[3] = s[1];
             cs[5] = tol2;
             flags[3] = maxiter;
-            flags[2] = 1;
             flags[1] = 0;
             flags[4] = 0;
             flags[0] = (s[0] == 0.0 || maxiter <= 0 || !isfinite(s[0]) || !isfinite(s[1])) ? 1 : 0;
@@ -931,14 +930,13 @@ __global__ void __launch_bounds__(CWG) ccr_init_defl_kernel(int n, const C2<T>* 
     }
 }
 
-// Ar = A r for coarse site a (one workgroup); FIRST: also p = r, Ap = Ar.
-// Partial sums of <r,Ar> and |Ar|^2 per coarse site go to part[a], part[Nc+a].
+// Ar = A r for coarse site a (one workgroup).  Partial sums per coarse site:
+// <r,Ar> to part[a], |Ar|^2 to part[Nc+a] and Re<Ap,Ar> (Ap of the previous
+// step; 0 on the first apply, FIRST) to part[2Nc+a].
 template <typename T, typename S, int E, bool FIRST>
 __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* __restrict__ A,
                                                         const C2<T>* __restrict__ r, C2<T>* __restrict__ Ar,
-                                                        C2<T>* __restrict__ p, C2<T>* __restrict__ Ap, double* part,
-                                                        double* /* cs: the scalars are read by the update kernels */,
-                                                        int* flags) {
+                                                        const C2<T>* __restrict__ Ap, double* part, int* flags) {
     if (flags[0]) return;
     extern __shared__ unsigned char smem_raw[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(smem_raw);   // [9][Nb]
@@ -951,125 +949,112 @@ __global__ void __launch_bounds__(CWG) ccr_apply_kernel(CoarseGeom c, const S* _
     }
     __syncthreads();
     site_gemv<T, S, E>(c, A, a, vs, red, res);
-    double sums[2] = {0.0, 0.0};
+    double sums[3] = {0.0, 0.0, 0.0};
     for (int j = threadIdx.x; j < c.Nb; j += CWG) {
         const C2<T> o = res[j];
         const size_t idx = (size_t)a * c.Nb + j;
         Ar[idx] = o;
         const C2<T> rv = vs[j];  // d = 0 slot holds r(a)
-        if (FIRST) {
-            p[idx] = rv;
-            Ap[idx] = o;
-        }
         sums[0] += (double)rv.x * o.x + (double)rv.y * o.y;
         sums[1] += (double)o.x * o.x + (double)o.y * o.y;
+        if (!FIRST) {
+            const C2<T> q = Ap[idx];
+            sums[2] += (double)q.x * o.x + (double)q.y * o.y;
+        }
     }
-    block_reduce<2>(sums);
-    // partial sums only: the next update kernel reduces them in every one of
-    // its workgroups (no device-scope fence and atomic per coarse site here)
+    block_reduce<3>(sums);
+    // partial sums only: the update kernel reduces them in every one of its
+    // workgroups (no device-scope fence and atomic per coarse site here)
     if (threadIdx.x == 0) {
         part[a] = sums[0];
         part[c.Nc + a] = sums[1];
+        part[2 * c.Nc + a] = sums[2];
     }
 }
 
-// x += alpha p; r -= alpha Ap with alpha = <r,Ar>/|Ap|^2; |r|^2, convergence test
-// (right after the first apply: alpha = <r,Ar>/|Ar|^2 from the apply's partials)
+// CR step k (k >= 1) after the apply of r_k, in a single pass:
+//   beta = <r,Ar>_k / <r,Ar>_{k-1}, p = r + beta p, Ap = Ar + beta Ap
+//   (step 1: p = r, Ap = Ar),
+//   alpha = <r,Ar>_k / |Ap|^2,  x += alpha p,  r -= alpha Ap,
+// with |Ap|^2 = |Ar|^2 + 2 beta Re<Ap_old,Ar> + beta^2 |Ap_old|^2 from the
+// apply's partials, so no reduction separates the p update from the x, r update.
+// The step needs no grid-wide arrival either: it stores its per-work-group
+// partials of |r_{k+1}|^2 and |Ap_k|^2 (uout), and step k+1 reduces them
+// (uin, the other half of a ping-pong pair) in each of its work-groups, ordered
+// by the kernel boundary.  So the convergence test of r_k runs at the start of
+// step k (from step 2 on; step 1 runs unconditionally, as the start kernel only
+// stops on a zero or non-finite b), and a converged r_k costs one apply that is
+// not used.  All work-groups reduce the same partials in the same order and so
+// take the same decisions; work-group 0 records them.
 template <typename T>
-__global__ void __launch_bounds__(CWG) ccr_update_xr_kernel(int n, C2<T>* __restrict__ x, C2<T>* __restrict__ r,
-                                                            const C2<T>* __restrict__ p, const C2<T>* __restrict__ Ap,
-                                                            const double* apart, int nc, double* part, double* cs,
-                                                            int* flags) {
+__global__ void __launch_bounds__(CWG) ccr_update_kernel(int n, C2<T>* __restrict__ x, C2<T>* __restrict__ r,
+                                                         C2<T>* __restrict__ p, const C2<T>* __restrict__ Ar,
+                                                         C2<T>* __restrict__ Ap, const double* apart, int nc,
+                                                         const double* uin, double* uout, double* cs, int* flags,
+                                                         int step) {
     if (flags[0]) return;
-    const bool first = flags[2] != 0;
-    double rar = cs[0], apap = cs[2];
-    if (first) {
-        double t[2];
-        sum_partials<2>(apart, nc, t);
-        rar = t[0];
-        apap = t[1];  // |Ap|^2 = |Ar|^2 on the first step
-        const int bd = ccr_breakdown<T>(rar, cs[3], apap);
-        if (bd) {  // (near-)breakdown ends the coarse solve; every workgroup takes the same decision
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                flags[4] = bd;
-                flags[0] = 1;
-            }
+    const bool first = step == 1;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    double rr = cs[3], apold = 0.0;
+    if (!first) {
+        double u[2];
+        sum_partials<2>(uin, (int)gridDim.x, u);
+        rr = u[0];
+        apold = u[1];
+        if (rr <= cs[5] * cs[4] || !isfinite(rr)) {  // r_k converged (or not finite): x_k is the result
+            if (lead) flags[0] = 1;
             return;
         }
     }
-    const T alpha = (T)(rar / apap);
-    double v[1] = {0.0};
-    for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
-        C2<T> xv = x[i], rv = r[i];
-        const C2<T> pv = p[i], apv = Ap[i];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * apv.x;
-        rv.y -= alpha * apv.y;
-        x[i] = xv;
-        r[i] = rv;
-        v[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
-    }
-    block_reduce<1>(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_arrival(flags + CCR_COUNTERS)) {
-        double s[1];
-        reduce_partials<1>(part, gridDim.x, s);
-        if (threadIdx.x == 0) {
-            if (first) {
-                cs[0] = rar;
-                cs[2] = apap;
-                flags[2] = 0;
-            }
-            cs[3] = s[0];
-            const int it = flags[1] + 1;
-            flags[1] = it;
-            if (s[0] <= cs[5] * cs[4] || it >= flags[3] || !isfinite(s[0])) flags[0] = 1;
-        }
-    }
-}
-
-// p = r + beta p; Ap = Ar + beta Ap with beta = <r,Ar>_new/<r,Ar>; |Ap|^2
-// (<r,Ar>_new reduced from the apply's partials in every workgroup)
-template <typename T>
-__global__ void __launch_bounds__(CWG) ccr_update_p_kernel(int n, const C2<T>* __restrict__ r, C2<T>* __restrict__ p,
-                                                           const C2<T>* __restrict__ Ar, C2<T>* __restrict__ Ap,
-                                                           const double* apart, int nc, double* part, double* cs,
-                                                           int* flags) {
-    if (flags[0]) return;
-    double t[2];
-    sum_partials<2>(apart, nc, t);
-    const double rar_new = t[0];
-    const int bd = ccr_breakdown<T>(rar_new, cs[3], t[1]);
-    if (bd) {  // (near-)breakdown ends the coarse solve; every workgroup takes the same decision
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            flags[4] = bd;
+    double t[3];
+    sum_partials<3>(apart, nc, t);
+    const double rar = t[0];
+    const int bd = ccr_breakdown<T>(rar, rr, t[1]);
+    const double beta = first ? 0.0 : rar / cs[6 + ((step - 1) & 1)];
+    const double apap = first ? t[1] : t[1] + 2.0 * beta * t[2] + beta * beta * apold;
+    if (bd || !(apap > 0.0)) {  // (near-)breakdown ends the coarse solve
+        if (lead) {
+            flags[4] = bd ? bd : 2;
             flags[0] = 1;
         }
         return;
     }
-    const T beta = (T)(rar_new / cs[0]);
-    double v[1] = {0.0};
+    const T bt = (T)beta, alpha = (T)(rar / apap);
+    double v[2] = {0.0, 0.0};
     for (int i = blockIdx.x * CWG + threadIdx.x; i < n; i += gridDim.x * CWG) {
-        C2<T> pv = p[i], apv = Ap[i];
-        const C2<T> rv = r[i], arv = Ar[i];
-        pv.x = rv.x + beta * pv.x;
-        pv.y = rv.y + beta * pv.y;
-        apv.x = arv.x + beta * apv.x;
-        apv.y = arv.y + beta * apv.y;
+        C2<T> rv = r[i], pv, apv;
+        const C2<T> arv = Ar[i];
+        if (first) {
+            pv = rv;
+            apv = arv;
+        } else {
+            pv = p[i];
+            apv = Ap[i];
+            pv.x = rv.x + bt * pv.x;
+            pv.y = rv.y + bt * pv.y;
+            apv.x = arv.x + bt * apv.x;
+            apv.y = arv.y + bt * apv.y;
+        }
+        C2<T> xv = x[i];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        rv.x -= alpha * apv.x;
+        rv.y -= alpha * apv.y;
         p[i] = pv;
         Ap[i] = apv;
-        v[0] += (double)apv.x * apv.x + (double)apv.y * apv.y;
+        x[i] = xv;
+        r[i] = rv;
+        v[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
+        v[1] += (double)apv.x * apv.x + (double)apv.y * apv.y;
     }
-    block_reduce<1>(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-    if (last_arrival(flags + CCR_COUNTERS)) {
-        double s[1];
-        reduce_partials<1>(part, gridDim.x, s);
-        if (threadIdx.x == 0) {
-            cs[2] = s[0];
-            cs[0] = rar_new;
-        }
+    block_reduce<2>(v);
+    if (threadIdx.x == 0) {
+        uout[blockIdx.x] = v[0];
+        uout[gridDim.x + blockIdx.x] = v[1];
+    }
+    if (lead) {
+        cs[6 + (step & 1)] = rar;
+        flags[1] = step;
     }
 }
 
@@ -1079,10 +1064,10 @@ void ccr_apply_launch(const CoarseGeom& c, const S* A, const CoarseCRWork<T>& w,
     constexpr int E = wide_entries<S>();
     if (c.Nb % E == 0)
         hipLaunchKernelGGL((ccr_apply_kernel<T, S, E, FIRST>), dim3(c.Nc), dim3(CWG), (apply_lds<T, E>(c)), s, c, A,
-                           w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+                           w.r, w.Ar, w.Ap, w.part, w.flags);
     else
         hipLaunchKernelGGL((ccr_apply_kernel<T, S, 1, FIRST>), dim3(c.Nc), dim3(CWG), (apply_lds<T, 1>(c)), s, c, A,
-                           w.r, w.Ar, w.p, w.Ap, w.part, w.cs, w.flags);
+                           w.r, w.Ar, w.Ap, w.part, w.flags);
 }
 
 template <typename T, bool FIRST>
@@ -1283,7 +1268,7 @@ void launch_ccr_init(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const Coarse
                      hipStream_t s) {
     const double tol2 = tol > 0 ? tol * tol : 0.0;
     hipLaunchKernelGGL(ccr_init_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, c.Nc * c.Nb, b, x, w.r,
-                       w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
+                       w.part + 3 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
 }
 
 template <typename T>
@@ -1294,23 +1279,28 @@ void launch_ccr_init_defl(const CoarseGeom& c, const C2<T>* b, C2<T>* x, const C
     hipLaunchKernelGGL(defl_dot_kernel<T>, dim3(DEFL_BLOCKS, (d.k + 7) / 8), dim3(CWG), 0, s, n, d, b, w.dpart);
     hipLaunchKernelGGL(defl_coef_kernel<T>, dim3(2 * d.k), dim3(CWG), 0, s, d, (const double*)w.dpart, w.dcoef);
     hipLaunchKernelGGL(ccr_init_defl_kernel<T>, dim3(DEFL_INIT_BLOCKS), dim3(CWG), 0, s, n, b, x, w.r, d,
-                       (const double*)w.dcoef, w.part + 2 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
+                       (const double*)w.dcoef, w.part + 3 * (size_t)c.Nc, w.cs, w.flags, maxiter, tol2);
+}
+
+static int ccr_update_blocks(int n) {
+    const int b = (n + CWG - 1) / CWG;
+    return b < 1 ? 1 : (b > CCR_UPDATE_MAX ? CCR_UPDATE_MAX : b);
 }
 
 template <typename T>
 void launch_ccr_step(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, C2<T>* x, const CoarseCRWork<T>& w,
-                     bool first, hipStream_t s) {
+                     int step, hipStream_t s) {
     const int n = c.Nc * c.Nb;
-    if (first) {
+    if (step == 0) {
         ccr_apply_dispatch<T, true>(c, A_dtype, A, w, s);
         return;
     }
-    double* upart = w.part + 2 * (size_t)c.Nc;  // partials of the update kernels
-    hipLaunchKernelGGL(ccr_update_xr_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, x, w.r, w.p, w.Ap,
-                       (const double*)w.part, c.Nc, upart, w.cs, w.flags);
+    double* upart = w.part + 3 * (size_t)c.Nc + 2 * (size_t)std::max(CCR_BLOCKS, DEFL_INIT_BLOCKS);
+    const size_t half = 2 * (size_t)CCR_UPDATE_MAX;
+    hipLaunchKernelGGL(ccr_update_kernel<T>, dim3(ccr_update_blocks(n)), dim3(CWG), 0, s, n, x, w.r, w.p, w.Ar, w.Ap,
+                       (const double*)w.part, c.Nc, (const double*)(upart + ((step - 1) & 1) * half),
+                       upart + (step & 1) * half, w.cs, w.flags, step);
     ccr_apply_dispatch<T, false>(c, A_dtype, A, w, s);
-    hipLaunchKernelGGL(ccr_update_p_kernel<T>, dim3(CCR_BLOCKS), dim3(CWG), 0, s, n, w.r, w.p, w.Ar, w.Ap,
-                       (const double*)w.part, c.Nc, upart, w.cs, w.flags);
 }
 
 template void launch_ccr_init<double>(const CoarseGeom&, const double2*, double2*, const CoarseCRWork<double>&, int,
@@ -1322,9 +1312,9 @@ template void launch_ccr_init_defl<double>(const CoarseGeom&, const double2*, do
 template void launch_ccr_init_defl<float>(const CoarseGeom&, const float2*, float2*, const CoarseCRWork<float>&,
                                           const DeflView<float>&, int, double, hipStream_t);
 template void launch_ccr_step<double>(const CoarseGeom&, hdcr_dtype, const void*, double2*,
-                                      const CoarseCRWork<double>&, bool, hipStream_t);
+                                      const CoarseCRWork<double>&, int, hipStream_t);
 template void launch_ccr_step<float>(const CoarseGeom&, hdcr_dtype, const void*, float2*, const CoarseCRWork<float>&,
-                                     bool, hipStream_t);
+                                     int, hipStream_t);
 
 size_t coarse_bytes(const CoarseGeom& c, hdcr_dtype dt) {
     return coarse_elems(c) * (dt == HDCR_C128 ? 16 : dt == HDCR_C64 ? 8 : 4);

@@ -73,7 +73,8 @@ template <typename T> CoarseCRWork<T> coarse_cr_carve(Carver& w, const CoarseGeo
     k.p = w.take<C2<T>>(n);
     k.Ar = w.take<C2<T>>(n);
     k.Ap = w.take<C2<T>>(n);
-    k.part = w.take<double>(2 * (size_t)c.Nc + 2 * std::max(CCR_BLOCKS, DEFL_INIT_BLOCKS));
+    k.part = w.take<double>(3 * (size_t)c.Nc + 2 * (size_t)std::max(CCR_BLOCKS, DEFL_INIT_BLOCKS) +
+                            4 * (size_t)CCR_UPDATE_MAX);
     k.cs = w.take<double>(8);
     k.flags = w.take<int>(CCR_FLAGS);
     k.dpart = w.take<double>((size_t)2 * DEFL_KMAX * DEFL_BLOCKS);
@@ -95,9 +96,9 @@ int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T
         launch_ccr_init_defl<T>(c, b, x, w, *defl, maxiter, tol, s);
     else
         launch_ccr_init<T>(c, b, x, w, maxiter, tol, s);
-    launch_ccr_step<T>(c, A_dtype, A, x, w, true, s);
+    launch_ccr_step<T>(c, A_dtype, A, x, w, 0, s);
     if (tol <= 0) {
-        for (int i = 0; i < maxiter; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
+        for (int i = 1; i <= maxiter; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, i, s);
         if (iters) *iters = maxiter;
         HDCR_HIP_CHECK(hipGetLastError());
         return HDCR_OK;
@@ -108,7 +109,7 @@ int coarse_cr(const CoarseGeom& c, hdcr_dtype A_dtype, const void* A, const C2<T
     int hf[5] = {0, 0, 0, 0, 0};
     while (enq < maxiter) {
         const int nb = std::min(batch, maxiter - enq);
-        for (int i = 0; i < nb; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, false, s);
+        for (int i = 1; i <= nb; ++i) launch_ccr_step<T>(c, A_dtype, A, x, w, enq + i, s);
         enq += nb;
         HDCR_HIP_CHECK(hipMemcpyAsync(hf, w.flags, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
         HDCR_HIP_CHECK(hipStreamSynchronize(s));
