@@ -97,6 +97,8 @@ typedef enum {
  *   restrict_w, restrict_rkg  restriction: s slots per work-item (1, 2, 4, 8; 0: 8
  *                   with the FP16 basis copy, else 4), vectors per workgroup (16, 32)
  *   prolong_ni      prolongation with the FP16 basis: indices per work-item (2, 4)
+ *   prolong_split   prolongation: workgroups per coarse site (1 .. 16; 0: about
+ *                   7800 workgroups in all, each part at least one sweep long)
  *   wg_per_cu       at most this many workgroups of the parity-tile stencil kernels
  *                   resident per compute unit (enforced through their LDS size; 0 or a
  *                   value above what fits: no cap) */
@@ -106,6 +108,7 @@ typedef struct hdcr_tuning {
     int32_t force_r, force_ms, force_p, force_sum;
     int32_t restrict_w, restrict_rkg, prolong_ni;
     int32_t wg_per_cu;
+    int32_t prolong_split;
 } hdcr_tuning;
 
 /* Fine lattice: L = (Lx, Ly, Lz, Lt), Ls, bc per direction (+1 periodic, -1

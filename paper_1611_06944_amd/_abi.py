@@ -26,7 +26,7 @@ COARSE_STATIC_BYTES = 8 << 20
 
 
 TUNE_FIELDS = ("dslash_variant", "tslab", "ysplit", "xsplit", "force_r", "force_ms", "force_p", "force_sum",
-               "restrict_w", "restrict_rkg", "prolong_ni", "wg_per_cu")
+               "restrict_w", "restrict_rkg", "prolong_ni", "wg_per_cu", "prolong_split")
 
 
 class Tuning(ctypes.Structure):

@@ -574,10 +574,12 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
         if ((int)threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
-// psi = y + P v for coarse site a (one workgroup).  A work-item handles NI
-// consecutive compressed indices (4 when nhalf is a multiple of 4, else 2; nhalf
-// is even), so the basis loads are 16-byte (FP16 at NI = 4, FP32 at NI = 2) or
-// 8-byte runs; each index yields the pair of outputs at s and its mirror Ls-1-s.
+// psi = y + P v for coarse site a (workgroups blockIdx.y = 0 .. gridDim.y - 1
+// take consecutive parts of its compressed indices, each part a multiple of NI
+// long).  A work-item handles NI consecutive compressed indices (4 when nhalf is
+// a multiple of 4, else 2; nhalf is even), so the basis loads are 16-byte (FP16
+// at NI = 4, FP32 at NI = 2) or 8-byte runs; each index yields the pair of
+// outputs at s and its mirror Ls-1-s.
 template <typename T, typename B, int NI>
 __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                       const C2<T>* __restrict__ v, const C2<T>* __restrict__ y,
@@ -590,7 +592,10 @@ __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __r
     const B* bp = basis + ((size_t)a * 2 + 0) * c.nvec * c.nhalf;
     const B* bm = basis + ((size_t)a * 2 + 1) * c.nvec * c.nhalf;
     const T r2 = (T)RSQRT2;
-    for (int i0 = NI * threadIdx.x; i0 < c.nhalf; i0 += NI * CWG) {
+    const int part = NI * ((c.nhalf / NI + (int)gridDim.y - 1) / (int)gridDim.y);
+    const int beg = (int)blockIdx.y * part;
+    const int end = min(c.nhalf, beg + part);
+    for (int i0 = beg + NI * threadIdx.x; i0 < end; i0 += NI * CWG) {
         C2<T> tp[NI], tm[NI];
 #pragma unroll
         for (int q = 0; q < NI; ++q) tp[q] = tm[q] = mk<T>(0, 0);
@@ -1419,11 +1424,27 @@ void launch_restrict_h(const CoarseGeom& c, const uint32_t* basis, const float2*
     restrict_launch<float, uint32_t>(c, basis, psi, psi2, v, s);
 }
 
+// Workgroups per coarse site of the prolongation: tune.prolong_split, else about
+// 7800 workgroups in all (six per site at 6^4 coarse sites, the fastest of 1 to
+// 8 measured at 24^4 x 16 with Nb = 64: 1.74 ms against 1.86 ms for one), with
+// parts of at least one sweep of the workgroup over its indices.  One workgroup
+// per site left the grid at 1296 workgroups, about five waves per SIMD with one
+// basis load pair in flight per work-item.
+static int prolong_parts(const CoarseGeom& c) {
+    int p = c.f.tune.prolong_split;
+    if (p <= 0) {
+        p = (7800 + c.Nc / 2) / c.Nc;
+        const int sweeps = c.nhalf / (2 * CWG);
+        if (p > sweeps) p = sweeps;
+    }
+    return p < 1 ? 1 : (p > 16 ? 16 : p);
+}
+
 template <typename T>
 void launch_prolong(const CoarseGeom& c, const C2<T>* basis, const C2<T>* v, const C2<T>* y, C2<T>* psi,
                     hipStream_t s) {
-    hipLaunchKernelGGL((prolong_kernel<T, C2<T>, 2>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(C2<T>), s, c, basis, v,
-                       y, psi);
+    hipLaunchKernelGGL((prolong_kernel<T, C2<T>, 2>), dim3(c.Nc, prolong_parts(c)), dim3(CWG), c.Nb * sizeof(C2<T>), s,
+                       c, basis, v, y, psi);
 }
 
 void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* v, const float2* y, float2* psi,
@@ -1431,12 +1452,13 @@ void launch_prolong_h(const CoarseGeom& c, const uint32_t* basis, const float2* 
     // two indices per work-item (measured faster at 24^4 x 16 than four with
     // 16-byte FP16 loads: 1.88 against 1.94 ms); tune.prolong_ni = 4 selects four
     const int ni = c.f.tune.prolong_ni > 0 ? c.f.tune.prolong_ni : 2;
+    const dim3 grid(c.Nc, prolong_parts(c));
     if (ni >= 4 && c.nhalf % 4 == 0)
-        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 4>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c,
-                           basis, v, y, psi);
+        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 4>), grid, dim3(CWG), c.Nb * sizeof(float2), s, c, basis,
+                           v, y, psi);
     else
-        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 2>), dim3(c.Nc), dim3(CWG), c.Nb * sizeof(float2), s, c,
-                           basis, v, y, psi);
+        hipLaunchKernelGGL((prolong_kernel<float, uint32_t, 2>), grid, dim3(CWG), c.Nb * sizeof(float2), s, c, basis,
+                           v, y, psi);
 }
 
 namespace {

@@ -55,6 +55,7 @@ int main(void) {
   printf("%zu %zu\n", offsetof(hdcr_solve_stats, true_rel_residual), offsetof(hdcr_solve_stats, history_len));
   printf("%zu %zu %zu %zu\n", offsetof(hdcr_fine_desc, cayley_b), offsetof(hdcr_fine_desc, tune),
          offsetof(hdcr_tuning, prolong_ni), offsetof(hdcr_solve_stats, coarse_breakdowns));
+  printf("%zu %zu\n", offsetof(hdcr_tuning, wg_per_cu), offsetof(hdcr_tuning, prolong_split));
   printf("%zu %zu %zu %zu %zu\n", sizeof(hdcr_coarse_deflation), offsetof(hdcr_coarse_deflation, theta),
          offsetof(hdcr_coarse_deflation, W), sizeof(hdcr_deflation_params), offsetof(hdcr_deflation_params, cut));
   return 0;
@@ -70,6 +71,7 @@ int main(void) {
           _abi.SolveStats.true_rel_residual.offset,
           _abi.SolveStats.history_len.offset, _abi.FineDesc.cayley_b.offset, _abi.FineDesc.tune.offset,
           _abi.Tuning.prolong_ni.offset, _abi.SolveStats.coarse_breakdowns.offset,
+          _abi.Tuning.wg_per_cu.offset, _abi.Tuning.prolong_split.offset,
           ctypes.sizeof(_abi.CoarseDeflation), _abi.CoarseDeflation.theta.offset, _abi.CoarseDeflation.W.offset,
           ctypes.sizeof(_abi.DeflationParams), _abi.DeflationParams.cut.offset]
     assert vals == py

@@ -159,11 +159,12 @@ def test_bf16_coarse_apply_24x24x24x24_coarse_shape():
 
 @pytest.mark.parametrize("tune", [dict(restrict_rkg=32), dict(restrict_w=4), dict(restrict_w=2),
                                   dict(restrict_w=1, restrict_rkg=32), dict(restrict_w=8, restrict_rkg=32),
-                                  dict(prolong_ni=4)])
+                                  dict(prolong_ni=4), dict(prolong_split=5), dict(prolong_ni=4, prolong_split=7)])
 def test_restrict_prolong_shapes_bench_shape(space, tune):
     """Every restriction shape (32 vectors per workgroup: one group per chirality; 1, 2, 4 or 8
-    s slots per work-item, 8 being the FP16 default) and the four-index FP16 prolongation against
-    the oracle at Nb = 64:
+    s slots per work-item, 8 being the FP16 default), the four-index FP16 prolongation and the
+    prolongation split over 5 and 7 workgroups per coarse site (ragged last parts) against the
+    oracle at Nb = 64:
     FP64 at 1e-10, FP32 at 1e-5, FP16 basis within the derived bound."""
     torch = torch_dev()
     log(f"bench-shape restrict / prolong shape {tune}")
