@@ -1025,19 +1025,31 @@ __global__ void __launch_bounds__(CWG) ccr_update_kernel(int n, C2<T>* __restric
     if (flags[0]) return;
     const bool first = step == 1;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // the apply's partials (t[0..2]) and the previous step's (t[3..4]) in one
+    // pass and one workgroup reduction, each sum in the order of sum_partials
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int i = threadIdx.x; i < nc; i += CWG) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) t[q] += apart[(size_t)q * nc + i];
+    }
+    if (!first) {
+        const int nu = (int)gridDim.x;
+        for (int i = threadIdx.x; i < nu; i += CWG) {
+            t[3] += uin[i];
+            t[4] += uin[nu + i];
+        }
+    }
+    block_reduce<5>(t);
     double rr = cs[3], apold = 0.0;
     if (!first) {
-        double u[2];
-        sum_partials<2>(uin, (int)gridDim.x, u);
-        rr = u[0];
-        apold = u[1];
+        rr = t[3];
+        apold = t[4];
         if (rr <= cs[5] * cs[4] || !isfinite(rr)) {  // r_k converged (or not finite): x_k is the result
             if (lead) flags[0] = 1;
             return;
         }
     }
-    double t[3];
-    sum_partials<3>(apart, nc, t);
     const double rar = t[0];
     const int bd = ccr_breakdown<T>(rar, rr, t[1]);
     const double beta = first ? 0.0 : rar / cs[6 + ((step - 1) & 1)];

@@ -349,3 +349,47 @@ def test_coarse_cr_near_breakdown():
         gd = to_dev(g) if dt == hd.C128 else to_dev(g, torch.complex64)
         x, it, code = hd.coarse_solve(lat, store, dt, gd, maxiter=50, tol=1e-2, return_status=True)
         assert code == 0 and 0 < it <= 50, (dt, code, it)
+
+
+def test_coarse_cr_stopping_matches_oracle():
+    """The coarse CR's stopping rules against the oracle's CR on the same FP64 operator: for
+    tolerances 1e-1 .. 1e-8 the same iteration count and iterate (1e-9); capped one iteration
+    short of convergence, exactly maxiter iterations with the oracle's fixed-work iterate; and 30
+    fixed iterations (the device forms |Ap|^2 from the apply's partial sums, |Ar|^2 +
+    2 beta Re<Ap_old, Ar> + beta^2 |Ap_old|^2, where the oracle sums |Ap|^2 directly) at 1e-8.
+    FP32 vectors (C64 storage; tolerances down to 1e-4): the iteration count within one of the
+    FP64 count, and the true residual under the stored operator within the tolerance plus 1e-5
+    (the drift of the recursive FP32 residual)."""
+    torch = torch_dev()
+    L, Ls, block, nvec = CASES[3]
+    log("coarse CR stopping rules")
+    p, cs, lat, U, vecs = _setup(L, Ls, block, nvec)
+    _, A = hd.build_coarse(lat, to_dev(hd.pack_gauge(U)), _dev_vecs(vecs), hd.C128)
+    A_ref = to_host(hd.export_coarse(lat, A, hd.C128))
+    b = hi.gaussian_coarse(cs.nc, cs.nb, seed=33)
+    bd = to_dev(b)
+    M64 = oracle.coarse_dense(to_host(hd.export_coarse(lat, hd.convert_coarse(lat, A, hd.C64), hd.C64)), cs.cdims)
+    for tol in (1e-1, 1e-2, 1e-4, 1e-8):
+        ref = oracle.coarse_cr(A_ref, b, cs.cdims, tol=tol, maxiter=500)
+        x, it, code = hd.coarse_solve(lat, A, hd.C128, bd, maxiter=500, tol=tol, return_status=True)
+        log(f"  tol {tol:g}: {it} iterations (oracle {ref.iters})")
+        assert code == 0 and ref.status == 0
+        assert it == ref.iters, (tol, it, ref.iters)
+        assert max_rel_elem(to_host(x), ref.x) <= 1e-9, tol
+        if ref.iters >= 2:
+            cap = ref.iters - 1
+            x, it = hd.coarse_solve(lat, A, hd.C128, bd, maxiter=cap, tol=tol)
+            fixed = oracle.coarse_cr(A_ref, b, cs.cdims, tol=0.0, maxiter=cap)
+            assert it == cap
+            assert max_rel_elem(to_host(x), fixed.x) <= 1e-9, tol
+        A32 = hd.convert_coarse(lat, A, hd.C64)
+        x32, it32 = hd.coarse_solve(lat, A32, hd.C64, to_dev(b, torch.complex64), maxiter=500, tol=tol)
+        if tol >= 1e-4:
+            assert abs(it32 - ref.iters) <= 1, (tol, it32, ref.iters)
+            res = b.ravel() - M64 @ to_host(x32).ravel().astype(np.complex128)
+            # the recursive FP32 residual drifts from the true one by FP32 rounding
+            assert np.linalg.norm(res) <= (tol + 1e-5) * np.linalg.norm(b), tol
+    x, it = hd.coarse_solve(lat, A, hd.C128, bd, maxiter=30, tol=0.0)
+    ref = oracle.coarse_cr(A_ref, b, cs.cdims, tol=0.0, maxiter=30)
+    assert it == 30 and ref.iters == 30
+    assert max_rel_elem(to_host(x), ref.x) <= 1e-8
