@@ -59,9 +59,48 @@ __global__ void __launch_bounds__(VWG) scale_kernel(int64_t n, T a, const C2<T>*
     }
 }
 
+// Entries 2k and 2k+1 of an array of complex values: one 16-byte load for FP32
+// storage, two for FP64.
+template <typename T>
+__device__ __forceinline__ void ld_two(const C2<T>* p, int64_t k, C2<T>& a, C2<T>& b) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = reinterpret_cast<const float4*>(p)[k];
+        a = make_float2(q.x, q.y);
+        b = make_float2(q.z, q.w);
+    } else {
+        a = p[2 * k];
+        b = p[2 * k + 1];
+    }
+}
+template <typename T> __device__ __forceinline__ void st_two(C2<T>* p, int64_t k, C2<T> a, C2<T> b) {
+    if constexpr (sizeof(T) == 4) {
+        reinterpret_cast<float4*>(p)[k] = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+        p[2 * k] = a;
+        p[2 * k + 1] = b;
+    }
+}
+
+// acc[2j], acc[2j+1] += <v_j, y> (re, im) for j < nv; acc[2 MAXV] += |y|^2
+template <typename TV>
+__device__ __forceinline__ void dot_terms(const C2<TV> (&vt)[MAXV], int nv, double2 yv, double (&acc)[2 * MAXV + 1]) {
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j) {
+        if (j < nv) {
+            const double2 v = make_double2(vt[j].x, vt[j].y);
+            acc[2 * j] += v.x * yv.x + v.y * yv.y;
+            acc[2 * j + 1] += v.x * yv.y - v.y * yv.x;
+        }
+    }
+    acc[2 * MAXV] += yv.x * yv.x + yv.y * yv.y;
+}
+
 // partial sums of <V[j], y> for j < nv and |y|^2 into part[q * REDUCE_BLOCKS + blk]
-// (V and y in FP64 or FP32 storage, FP64 accumulation)
-template <typename TV, typename TY>
+// (V and y in FP64 or FP32 storage, FP64 accumulation).  PAIR (FP32 y, n even,
+// 16-byte aligned arrays): a work-item takes entries 2k and 2k+1 per step, so
+// FP32 storage is read in 16-byte runs, twice the bytes per load of one entry at
+// a time (which kept the kernel below 4 TB/s at 4 waves per SIMD).
+template <typename TV, typename TY, bool PAIR>
 __global__ void __launch_bounds__(REDUCE_THREADS) multidot_kernel(int64_t n, PtrListT<TV> V, int nv,
                                                                   const C2<TY>* __restrict__ y,
                                                                   double* __restrict__ part) {
@@ -69,19 +108,26 @@ __global__ void __launch_bounds__(REDUCE_THREADS) multidot_kernel(int64_t n, Ptr
 #pragma unroll
     for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const C2<TY> yt = y[i];
-        const double2 yv = make_double2(yt.x, yt.y);
+    if constexpr (PAIR) {
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n / 2; k += stride) {
+            C2<TY> y0, y1;
+            ld_two<TY>(y, k, y0, y1);
+            C2<TV> v0[MAXV], v1[MAXV];
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j) {
-            if (j < nv) {
-                const C2<TV> vt = V.p[j][i];
-                const double2 v = make_double2(vt.x, vt.y);
-                acc[2 * j] += v.x * yv.x + v.y * yv.y;
-                acc[2 * j + 1] += v.x * yv.y - v.y * yv.x;
-            }
+            for (int j = 0; j < MAXV; ++j)
+                if (j < nv) ld_two<TV>(V.p[j], k, v0[j], v1[j]);
+            dot_terms<TV>(v0, nv, make_double2(y0.x, y0.y), acc);
+            dot_terms<TV>(v1, nv, make_double2(y1.x, y1.y), acc);
         }
-        acc[2 * MAXV] += yv.x * yv.x + yv.y * yv.y;
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const C2<TY> yt = y[i];
+            C2<TV> vt[MAXV];
+#pragma unroll
+            for (int j = 0; j < MAXV; ++j)
+                if (j < nv) vt[j] = V.p[j][i];
+            dot_terms<TV>(vt, nv, make_double2(yt.x, yt.y), acc);
+        }
     }
     block_reduce<2 * MAXV + 1>(acc);
     if (threadIdx.x == 0) {
@@ -127,9 +173,9 @@ __global__ void __launch_bounds__(VWG) multi_axpy_kernel(int64_t n, PtrListT<TV>
 
 // y <- y - sum_j coef[j] sc[j] V[j] as multi_axpy_kernel, and the partial sums of
 // <V[j], y> and |y|^2 of the stored result as multidot_kernel: same grid, same
-// index per work-item and same reduction, so the sums are bitwise those of a
-// separate multidot pass over the updated y
-template <typename TV>
+// entries per work-item (PAIR as there) and same reduction, so the sums are
+// bitwise those of a separate multidot pass over the updated y
+template <typename TV, bool PAIR>
 __global__ void __launch_bounds__(REDUCE_THREADS) multi_axpy_dot_kernel(int64_t n, PtrListT<TV> V, int nv,
                                                                         const double* __restrict__ coef,
                                                                         C2<TV>* __restrict__ y,
@@ -141,33 +187,40 @@ __global__ void __launch_bounds__(REDUCE_THREADS) multi_axpy_dot_kernel(int64_t 
         const double f = (j < nv && sc) ? sc[j] : 1.0;
         cf[j] = (j < nv) ? make_double2(f * coef[2 * j], f * coef[2 * j + 1]) : make_double2(0, 0);
     }
+    auto update = [&](C2<TV> yt, const C2<TV> (&vt)[MAXV]) {
+        double2 yv = make_double2(yt.x, yt.y);
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+            if (j < nv) yv = cfma<double>(cneg<double>(cf[j]), make_double2(vt[j].x, vt[j].y), yv);
+        return mk<TV>((TV)yv.x, (TV)yv.y);
+    };
     double acc[2 * MAXV + 1];
 #pragma unroll
     for (int q = 0; q < 2 * MAXV + 1; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const C2<TV> yt = y[i];
-        double2 yv = make_double2(yt.x, yt.y);
-        C2<TV> vt[MAXV];
+    if constexpr (PAIR) {
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n / 2; k += stride) {
+            C2<TV> y0, y1;
+            ld_two<TV>(y, k, y0, y1);
+            C2<TV> v0[MAXV], v1[MAXV];
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j) {
-            if (j < nv) {
-                vt[j] = V.p[j][i];
-                yv = cfma<double>(cneg<double>(cf[j]), make_double2(vt[j].x, vt[j].y), yv);
-            }
+            for (int j = 0; j < MAXV; ++j)
+                if (j < nv) ld_two<TV>(V.p[j], k, v0[j], v1[j]);
+            const C2<TV> o0 = update(y0, v0), o1 = update(y1, v1);
+            st_two<TV>(y, k, o0, o1);
+            dot_terms<TV>(v0, nv, make_double2(o0.x, o0.y), acc);
+            dot_terms<TV>(v1, nv, make_double2(o1.x, o1.y), acc);
         }
-        const C2<TV> yo = mk<TV>((TV)yv.x, (TV)yv.y);
-        y[i] = yo;
-        const double2 ys = make_double2(yo.x, yo.y);
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            C2<TV> vt[MAXV];
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j) {
-            if (j < nv) {
-                const double2 v = make_double2(vt[j].x, vt[j].y);
-                acc[2 * j] += v.x * ys.x + v.y * ys.y;
-                acc[2 * j + 1] += v.x * ys.y - v.y * ys.x;
-            }
+            for (int j = 0; j < MAXV; ++j)
+                if (j < nv) vt[j] = V.p[j][i];
+            const C2<TV> yo = update(y[i], vt);
+            y[i] = yo;
+            dot_terms<TV>(vt, nv, make_double2(yo.x, yo.y), acc);
         }
-        acc[2 * MAXV] += ys.x * ys.x + ys.y * ys.y;
     }
     block_reduce<2 * MAXV + 1>(acc);
     if (threadIdx.x == 0) {
@@ -420,10 +473,25 @@ HDCR_VEC_INST(double)
 HDCR_VEC_INST(float)
 #undef HDCR_VEC_INST
 
+// entries taken two at a time: FP32 y (FP64 entries are 16 bytes already), n
+// even and every array 16-byte aligned
+template <typename TV, typename TY>
+static bool pair_ok(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y) {
+    if (sizeof(TY) != 4 || n % 2 || reinterpret_cast<uintptr_t>(y) % 16) return false;
+    for (int j = 0; j < nv; ++j)
+        if (reinterpret_cast<uintptr_t>(V.p[j]) % 16) return false;
+    return true;
+}
+
 template <typename TV, typename TY>
 void launch_multidot(int64_t n, const PtrListT<TV>& V, int nv, const C2<TY>* y, double* part, double* out,
                      hipStream_t s) {
-    hipLaunchKernelGGL((multidot_kernel<TV, TY>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, y, part);
+    if (pair_ok<TV, TY>(n, V, nv, y))
+        hipLaunchKernelGGL((multidot_kernel<TV, TY, true>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv,
+                           y, part);
+    else
+        hipLaunchKernelGGL((multidot_kernel<TV, TY, false>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V,
+                           nv, y, part);
     hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
                        out);
 }
@@ -437,8 +505,12 @@ void launch_multi_axpy(int64_t n, const PtrListT<TV>& V, int nv, const double* c
 template <typename TV>
 void launch_multi_axpy_dot(int64_t n, const PtrListT<TV>& V, int nv, const double* coef, C2<TV>* y, double* part,
                            double* out, hipStream_t s, const double* sc) {
-    hipLaunchKernelGGL(multi_axpy_dot_kernel<TV>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V, nv, coef, y,
-                       part, sc);
+    if (pair_ok<TV, TV>(n, V, nv, y))
+        hipLaunchKernelGGL((multi_axpy_dot_kernel<TV, true>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V,
+                           nv, coef, y, part, sc);
+    else
+        hipLaunchKernelGGL((multi_axpy_dot_kernel<TV, false>), dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, s, n, V,
+                           nv, coef, y, part, sc);
     hipLaunchKernelGGL(multidot_finalize_kernel, dim3(2 * MAXV + 1), dim3(REDUCE_THREADS), 0, s, part, 2 * MAXV + 1,
                        out);
 }
