@@ -574,16 +574,17 @@ __global__ void __launch_bounds__(CWG) restrict_kernel(CoarseGeom c, const B* __
         if ((int)threadIdx.x == q && q < kn) v[(size_t)a * c.Nb + h * c.nvec + k0 + q] = acc[q];
 }
 
+// Vectors whose basis entries a prolongation work-item requests together: 8
+// (108 VGPRs, 4 waves per SIMD) took 1.73 ms at 24^4 x 16 against 1.87 ms for
+// one vector at a time, timed in one process (2 and 4 lay in between).
+constexpr int PKU = 8;
+
 // psi = y + P v for coarse site a (workgroups blockIdx.y = 0 .. gridDim.y - 1
 // take consecutive parts of its compressed indices, each part a multiple of NI
 // long).  A work-item handles NI consecutive compressed indices (4 when nhalf is
 // a multiple of 4, else 2; nhalf is even), so the basis loads are 16-byte (FP16
 // at NI = 4, FP32 at NI = 2) or 8-byte runs; each index yields the pair of
 // outputs at s and its mirror Ls-1-s.
-// Vectors whose basis entries a prolongation work-item requests together: 8
-// (108 VGPRs, 4 waves per SIMD) took 1.73 ms at 24^4 x 16 against 1.87 ms for
-// one vector at a time, timed in one process (2 and 4 lay in between).
-constexpr int PKU = 8;
 template <typename T, typename B, int NI>
 __global__ void __launch_bounds__(CWG) prolong_kernel(CoarseGeom c, const B* __restrict__ basis,
                                                       const C2<T>* __restrict__ v, const C2<T>* __restrict__ y,
